@@ -1,0 +1,341 @@
+"""Pins of the oracle DGSEM + partitioned RK against invariants, closed forms and brute force."""
+import decimal
+import math
+
+import numpy as np
+import pytest
+
+import perk_inputs as pin
+from oracle import dgsem as od
+from oracle import perk_coeffs as pc
+
+GAMMA = 1.4
+
+
+# ------------------------------------------------------------------ quadrature and operators
+@pytest.mark.parametrize("N", [3, 4, 5, 7])
+def test_lgl_closed_forms_and_sbp(N):
+    x, w, D = od.lgl(N)
+    if N == 3:
+        np.testing.assert_allclose(x, [-1, 0, 1], atol=1e-16)
+        np.testing.assert_allclose(w, [1 / 3, 4 / 3, 1 / 3], atol=1e-15)
+    if N == 4:
+        np.testing.assert_allclose(x, [-1, -1 / math.sqrt(5), 1 / math.sqrt(5), 1], atol=1e-15)
+        np.testing.assert_allclose(w, [1 / 6, 5 / 6, 5 / 6, 1 / 6], atol=1e-15)
+    assert abs(w.sum() - 2.0) < 1e-14
+    # summation by parts: M D + (M D)^T = diag(-1, 0, ..., 0, 1)
+    MD = np.diag(w) @ D
+    B = np.zeros((N, N)); B[0, 0] = -1; B[-1, -1] = 1
+    np.testing.assert_allclose(MD + MD.T, B, atol=1e-13)
+    # D differentiates polynomials of degree <= N-1 exactly
+    for k in range(N):
+        np.testing.assert_allclose(D @ x ** k, k * x ** max(k - 1, 0) if k else 0 * x, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_mortar_operators(dim):
+    mesh = pin.uniform_mesh(dim, (2,) * dim, (0.0,) * dim, (1.0,) * dim, 0)
+    o = od.Oracle(mesh, 4)
+    P, R = o.mortar_ops()
+    x, w, _ = od.lgl(4)
+    # exact interpolation of cubic polynomials onto the two halves
+    f = 1 + 2 * x - x ** 3
+    np.testing.assert_allclose(P[0] @ f, 1 + 2 * (0.5 * (x - 1)) - (0.5 * (x - 1)) ** 3, atol=1e-14)
+    np.testing.assert_allclose(P[1] @ f, 1 + 2 * (0.5 * (x + 1)) - (0.5 * (x + 1)) ** 3, atol=1e-14)
+    # freestream: projections of constants add up to the constant
+    np.testing.assert_allclose(R[0] @ np.ones(4) + R[1] @ np.ones(4), np.ones(4), atol=1e-15)
+    # conservation: sum_i w_i (R_m g)_i = 1/2 sum_j w_j g_j for any g
+    g = np.random.default_rng(0).standard_normal(4)
+    for m in range(2):
+        assert abs(w @ (R[m] @ g) - 0.5 * (w @ g)) < 1e-15
+
+
+# ------------------------------------------------------------------ two-point fluxes
+def _rand_states(dim, n, seed):
+    rng = np.random.default_rng(seed)
+    rho = 0.5 + rng.random(n)
+    v = rng.standard_normal((dim, n))
+    p = 0.5 + rng.random(n)
+    return pin.prim2cons(rho, list(v), p, GAMMA).T
+
+
+def _entropy_vars(u, dim):
+    rho = u[0]; v = u[1:1 + dim] / rho; p = (GAMMA - 1) * (u[-1] - 0.5 * rho * np.sum(v * v))
+    s = np.log(p) - GAMMA * np.log(rho)
+    return np.concatenate([[(GAMMA - s) / (GAMMA - 1) - 0.5 * rho * np.sum(v * v) / p], rho * v / p, [-rho / p]])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_ec_flux_properties(dim):
+    A = _rand_states(dim, 300, 1)
+    B = _rand_states(dim, 300, 2)
+    for uL, uR in zip(A, B):
+        for d in range(dim):
+            f = od.ec_flux(dim, GAMMA, uL, uR, d)
+            # symmetry and consistency
+            np.testing.assert_allclose(f, od.ec_flux(dim, GAMMA, uR, uL, d), rtol=1e-14, atol=1e-14)
+            np.testing.assert_allclose(od.ec_flux(dim, GAMMA, uL, uL, d), od.euler_flux(dim, GAMMA, uL, d),
+                                       rtol=1e-13, atol=1e-13)
+            # Tadmor's condition: (w_R - w_L) . f = psi_R - psi_L with psi = rho v_d
+            wl, wr = _entropy_vars(uL, dim), _entropy_vars(uR, dim)
+            lhs = (wr - wl) @ f
+            rhs = uR[1 + d] - uL[1 + d]
+            assert abs(lhs - rhs) <= 1e-12 * (1 + abs(rhs) + np.abs(wr - wl) @ np.abs(f))
+            # kinetic energy preservation: momentum flux = f^rho {{v}} + {{p}} e_d
+            vl, vr = uL[1:1 + dim] / uL[0], uR[1:1 + dim] / uR[0]
+            pl = (GAMMA - 1) * (uL[-1] - 0.5 * uL[0] * vl @ vl)
+            pr = (GAMMA - 1) * (uR[-1] - 0.5 * uR[0] * vr @ vr)
+            mom = f[0] * 0.5 * (vl + vr)
+            mom[d] += 0.5 * (pl + pr)
+            np.testing.assert_allclose(f[1:1 + dim], mom, rtol=1e-14, atol=1e-14)
+
+
+def test_log_mean_both_branches():
+    decimal.getcontext().prec = 50
+    rng = np.random.default_rng(3)
+    for _ in range(400):
+        a = float(rng.uniform(0.1, 5))
+        b = a * float(np.exp(rng.choice([1e-9, 1e-6, 1e-3, 5e-3, 1.9e-2, 2.1e-2, 0.3, 2.0]) * rng.choice([-1, 1])))
+        ex = (decimal.Decimal(b) - decimal.Decimal(a)) / (decimal.Decimal(b).ln() - decimal.Decimal(a).ln())
+        # the log branch loses ~eps/|ln(b/a)| to cancellation in b - a
+        tol = 1e-15 * max(1.0, 1.0 / abs(math.log(b / a)) if b != a else 1.0)
+        assert abs(od.log_mean(a, b) - float(ex)) <= tol * float(ex)
+
+
+def test_hll_flux_consistency_and_upwinding():
+    for u in _rand_states(2, 50, 4):
+        for d in range(2):
+            np.testing.assert_allclose(od.hll_flux(2, GAMMA, u, u, d), od.euler_flux(2, GAMMA, u, d), rtol=1e-14, atol=1e-14)
+    # supersonic to the right: the flux is the left physical flux
+    uL = pin.prim2cons(np.array(1.0), [np.array(5.0), np.array(0.1)], np.array(1.0), GAMMA)
+    uR = pin.prim2cons(np.array(0.8), [np.array(4.5), np.array(0.0)], np.array(0.9), GAMMA)
+    np.testing.assert_allclose(od.hll_flux(2, GAMMA, uL, uR, 0), od.euler_flux(2, GAMMA, uL, 0), rtol=1e-15)
+
+
+# ------------------------------------------------------------------ spatial operator invariants
+def _fs_tol(o, u):
+    # round-off scale of the operator: (2/h_min) * max|u| * 10, times a few ulps
+    return 1e-14 * 10 * np.max(2.0 / o.element_sizes()) * np.max(np.abs(u))
+
+
+def _freestream(o, dim):
+    u = np.zeros(o.shape)
+    u[:, 0] = 1.3
+    vel = [0.4, -0.7, 0.25][:dim]
+    for d in range(dim):
+        u[:, 1 + d] = 1.3 * vel[d]
+    u[:, -1] = 2.1 / (GAMMA - 1) + 0.5 * 1.3 * sum(v * v for v in vel)
+    return u
+
+
+MESHES_2D = {
+    "vortex_2level": lambda: pin.mesh_vortex_2level(),
+    "random_forest": lambda: pin.random_forest_2d(11, n_root=4, max_level=2),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES_2D))
+@pytest.mark.parametrize("N", [3, 4])
+@pytest.mark.parametrize("viscous", [False, True])
+def test_freestream_and_conservation_2d(name, N, viscous):
+    mesh = MESHES_2D[name]()
+    o = od.Oracle(mesh, N, viscous=viscous, mu=1e-2)
+    u0 = _freestream(o, 2)
+    du = o.rhs(u0)
+    assert np.max(np.abs(du)) < _fs_tol(o, u0)
+    x = o.node_coords()
+    u = pin.smooth_random_state(x.transpose(1, 0, 2), 2, seed=5).transpose(1, 0, 2).copy()
+    du = o.rhs(u)
+    scale = np.abs(o.integral(np.abs(du))) + 1e-30
+    assert np.all(np.abs(o.integral(du)) < 1e-13 * scale)
+
+
+def _mesh3d_small():
+    # 4^3 roots on [-pi,pi]^3 with two adjacent roots refined (mortars in 3D)
+    m = pin.uniform_mesh(3, (4, 4, 4), (-np.pi,) * 3, (np.pi,) * 3, 0)
+    sel = [r for r, (l, i, j, k) in enumerate(m.leaves.tolist()) if (i, j, k) in ((1, 1, 1), (2, 1, 1))]
+    m.leaves = pin.refine_leaves(m.leaves, 3, sel)
+    return m
+
+
+@pytest.mark.parametrize("viscous", [False, True])
+def test_freestream_and_conservation_3d(viscous):
+    o = od.Oracle(_mesh3d_small(), 4, viscous=viscous, mu=1.0 / 1600)
+    kinds, _ = o.faces()
+    assert (kinds == 2).sum() == 10 and (kinds == 1).sum() == 40
+    u0 = _freestream(o, 3)
+    du = o.rhs(u0)
+    assert np.max(np.abs(du)) < _fs_tol(o, u0)
+    x = o.node_coords().transpose(1, 0, 2)
+    u = pin.taylor_green(x[0], x[1], x[2]).transpose(1, 0, 2).copy()
+    du = o.rhs(u)
+    scale = np.abs(o.integral(np.abs(du))) + 1e-30
+    assert np.all(np.abs(o.integral(du)) < 1e-13 * scale)
+
+
+def _entropy_rate(o, u, du):
+    x, w, _ = od.lgl(o.N)
+    W = np.einsum("i,j->ji", w, w).reshape(-1)
+    jac = np.prod(o.element_sizes() / 2.0, axis=1)
+    tot, mag = 0.0, 0.0
+    for e in range(o.n_elements):
+        for n in range(o.Nd):
+            wv = _entropy_vars(u[e, :, n], 2)
+            tot += jac[e] * W[n] * (wv @ du[e, :, n])
+            mag += jac[e] * W[n] * np.abs(wv) @ np.abs(du[e, :, n])
+    return tot, mag
+
+
+def test_entropy_conservation_and_stability():
+    # conforming periodic mesh: EC volume + EC surface flux conserves entropy to round-off;
+    # with the HLL surface flux entropy can only decrease
+    mesh = pin.uniform_mesh(2, (4, 4), (-5, -5), (5, 5), 0)
+    x = None
+    for surface in ("ec", "hll"):
+        o = od.Oracle(mesh, 4, surface=surface)
+        x = o.node_coords().transpose(1, 0, 2)
+        u = pin.isentropic_vortex(x[0], x[1]).transpose(1, 0, 2).copy()
+        tot, mag = _entropy_rate(o, u, o.rhs(u))
+        if surface == "ec":
+            assert abs(tot) < 1e-12 * mag
+        else:
+            assert tot < 1e-12 * mag
+
+
+# ------------------------------------------------------------------ time integration
+def _rk4():
+    A = np.zeros((4, 4)); A[1, 0] = 0.5; A[2, 1] = 0.5; A[3, 2] = 1.0
+    return A, np.array([1, 2, 2, 1]) / 6.0
+
+
+def _vortex_error(n, N, eps, t_end=0.5, dt=0.005):
+    """L2 density error of the translating vortex on a uniform n x n mesh (RK4 in time)."""
+    mesh = pin.uniform_mesh(2, (n, n), (-5, -5), (5, 5), 0)
+    o = od.Oracle(mesh, N)
+    x = o.node_coords().transpose(1, 0, 2)
+    u = pin.isentropic_vortex(x[0], x[1], eps=eps).transpose(1, 0, 2).copy()
+    A, b = _rk4()
+    for _ in range(int(round(t_end / dt))):
+        u = o.rk_step(u, dt, A, b)
+    ex = pin.isentropic_vortex(x[0], x[1], eps=eps, t=t_end).transpose(1, 0, 2)
+    err = np.zeros(o.shape)
+    err[:, 0] = (u[:, 0] - ex[:, 0]) ** 2
+    return math.sqrt(o.integral(err)[0])
+
+
+def test_spatial_order_vortex():
+    # design order p+1 for smooth solutions (L2 norm, weak vortex, 16^2 -> 32^2, p = 3)
+    e16, e32 = _vortex_error(16, 4, 1.0), _vortex_error(32, 4, 1.0)
+    assert math.log2(e16 / e32) > 3.5
+
+
+def _c1_setup():
+    mesh = pin.mesh_vortex_2level()
+    o = od.Oracle(mesh, 4)
+    x = o.node_coords().transpose(1, 0, 2)
+    u0 = pin.isentropic_vortex(x[0], x[1]).transpose(1, 0, 2).copy()
+    member = od.member_of_levels_paper_rule(mesh.leaves[:, 0], 2)
+    return o, u0, member
+
+
+def _perk3_fam(E_list):
+    th = np.linspace(0, 2 * np.pi, 200, endpoint=False)
+    eigs = -1.0 + np.exp(1j * th)
+    return pc.perk3_family(E_list, {E: pc.optimize_alpha(eigs, 3, E)[1] for E in E_list})
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_temporal_order_partitioned(order):
+    # Sec. 5: the partitioned schemes keep their design order (slopes 2 and 3)
+    o, u0, member = _c1_setup()
+    fam = pc.perk2_family([4, 8]) if order == 2 else _perk3_fam([4, 8])
+    T = 0.2
+
+    def run(dt):
+        u = u0.copy()
+        for _ in range(int(round(T / dt))):
+            u = o.prk_step(u, dt, fam, member)
+        return u
+
+    ref = run(T / 160)
+    errs = [np.max(np.abs(run(T / n) - ref)) for n in (20, 40)]
+    slope = math.log2(errs[0] / errs[1])
+    # the third-order slope approaches 3 from above on this range (3.9, 3.5, 3.3, ...)
+    lo, hi = (1.8, 2.3) if order == 2 else (2.8, 3.5)
+    assert lo < slope < hi, (errs, slope)
+
+
+def test_single_member_equals_reduced_method():
+    # Sec. 3.1: with every element in the E=4 member, the S=8 partitioned step equals the
+    # standalone 4-stage method obtained by deleting the stages that member never evaluates
+    o, u0, _ = _c1_setup()
+    fam = pc.perk2_family([4, 8])
+    stages = pc.member_stage_evaluations(fam.a_sub[0], fam.c, fam.b)
+    assert stages == [1, 6, 7, 8]
+    A8 = pc.dense_A(fam.c, fam.a_sub[0])
+    idx = [s - 1 for s in stages]
+    A4 = A8[np.ix_(idx, idx)]
+    b4 = fam.b[idx]
+    dt = 0.05
+    u_prk = o.prk_step(u0, dt, fam, np.zeros(o.n_elements, np.int32))
+    u_rk = o.rk_step(u0, dt, A4, b4)
+    assert np.max(np.abs(u_prk - u_rk)) <= 1e-14 * np.max(np.abs(u0))
+    # and with every element in the E=8 member it is the plain 8-stage method
+    u_prk8 = o.prk_step(u0, dt, fam, np.ones(o.n_elements, np.int32))
+    u_rk8 = o.rk_step(u0, dt, pc.dense_A(fam.c, fam.a_sub[1]), fam.b)
+    assert np.max(np.abs(u_prk8 - u_rk8)) <= 1e-14 * np.max(np.abs(u0))
+
+
+def test_conservation_over_partitioned_steps():
+    # eq. (Conservation): shared b keeps linear invariants to round-off over many steps
+    o, u0, member = _c1_setup()
+    fam = pc.perk2_family([4, 8])
+    u = u0.copy()
+    I0 = o.integral(u0)
+    for _ in range(20):
+        u = o.prk_step(u, 0.02, fam, member)
+    assert np.all(np.abs(o.integral(u) - I0) < 1e-12 * np.maximum(1.0, np.abs(I0)))
+
+
+# ------------------------------------------------------------------ brute-force spectra
+def _tiny_mesh(refined):
+    m = pin.uniform_mesh(2, (4, 4), (0, 0), (1, 1), 0)
+    if refined:
+        sel = [r for r, (l, i, j, k) in enumerate(m.leaves.tolist()) if 1 <= i < 3 and 1 <= j < 3]
+        m.leaves = pin.refine_leaves(m.leaves, 2, sel)
+    return m
+
+
+def _fd_jacobian(f, u0, eps=1e-7):
+    n = u0.size
+    J = np.zeros((n, n))
+    for k in range(n):
+        du = np.zeros(n); du[k] = eps * max(1.0, abs(u0.flat[k]))
+        J[:, k] = (f((u0.ravel() + du).reshape(u0.shape)).ravel() - f((u0.ravel() - du).reshape(u0.shape)).ravel()) / (2 * du[k])
+    return J
+
+
+def test_bruteforce_spectra_tiny_meshes():
+    # Sec. 2.2 and 4.1: linearisation about a constant state has no amplifying modes and its
+    # spectral radius scales with 1/h; the fully discrete partitioned step is stable (rho(D) <= 1)
+    rads = []
+    for n in (4, 8):
+        m = pin.uniform_mesh(2, (n, n), (0, 0), (1, 1), 0)
+        o = od.Oracle(m, 3)
+        J = _fd_jacobian(o.rhs, _freestream(o, 2))
+        lam = np.linalg.eigvals(J)
+        rads.append(np.max(np.abs(lam)))
+        assert np.max(lam.real) <= 1e-6 * rads[-1]
+    assert 1.9 < rads[1] / rads[0] < 2.1
+    o = od.Oracle(_tiny_mesh(True), 3)
+    u0 = _freestream(o, 2)
+    J = _fd_jacobian(o.rhs, u0)
+    lam = np.linalg.eigvals(J)
+    assert np.max(lam.real) <= 1e-6 * np.max(np.abs(lam))
+    fam = pc.perk2_family([4, 8])
+    member = od.member_of_levels_paper_rule(o.mesh.leaves[:, 0], 2)
+    coef8 = pc.stability_poly(pc.dense_A(fam.c, fam.a_sub[1]), fam.b)
+    dt = 0.9 * pc.max_stable_step(coef8, lam)
+    # one step is linear in the perturbation about a constant state: build D column by column
+    D = _fd_jacobian(lambda v: o.prk_step(v, dt, fam, member), u0, eps=1e-6)
+    assert np.max(np.abs(np.linalg.eigvals(D))) <= 1.0 + 1e-6

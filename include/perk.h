@@ -1,0 +1,163 @@
+/* perk.h - C ABI of the MI355X partitioned P-ERK + DGSEM library (libperk.so).
+ *
+ * The library advances a method-of-lines system U' = F(U) obtained from a discontinuous
+ * Galerkin spectral element discretisation (DGSEM, flux differencing on Legendre-Gauss-Lobatto
+ * nodes) of the compressible Euler or Navier-Stokes (BR1) equations on a periodic Cartesian
+ * forest of quad/octrees with 2:1 mortars, with a partitioned Paired-Explicit Runge-Kutta
+ * (P-ERK) method whose members are assigned to the elements by their refinement level.
+ *
+ * Paper passages defining the operations (D. Doehring et al., "Multirate time-integration
+ * based on dynamic ODE partitioning through adaptively refined meshes for compressible fluid
+ * dynamics"):
+ *   - partitioned system and partitioned RK step: Sec. 2, eq. (PartitionedODESys) and
+ *     eq. (PartitionedRKSystem);
+ *   - P-ERK tableaux (shared c and b, two nonzeros per row, internal consistency): Sec. 3.1,
+ *     eq. (PERK_ButcherTableauClassic), Sec. 3.3, eq. (PERK_ThirdOrderShuOsher);
+ *   - order conditions, internal consistency, conservation: eqs. (PRKOrderCondsSimplified),
+ *     (InternalConsistency), (Conservation);
+ *   - level-wise evaluation of the right-hand side over the elements of a partition and the
+ *     assignment of elements, interfaces and mortars to partitions after every mesh change:
+ *     Sec. 6.1, 6.2;
+ *   - level -> method map when there are more levels than methods: Sec. 6.3.1;
+ *   - scalar RHS-evaluation count: eq. (ActualRHSEvals).
+ *
+ * Conventions
+ *   - Every call returns a pe_status; on failure pe_last_error(ctx) describes it.  No call
+ *     aborts or throws across the ABI.  Calls made in the wrong order return PE_ESTATE.
+ *   - Device pointers are HIP device addresses on the current device; host pointers are
+ *     ordinary memory.  The caller owns every buffer it passes; the library never frees them.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Calls that take a stream are
+ *     asynchronous on it unless stated otherwise.
+ *   - One context per host thread.  Calls on one context must not overlap.
+ *   - All floating point is fp64.
+ *
+ * State layouts
+ *   - "leaf layout" (what the caller sees): [leaf][var][node], leaves in the order of the
+ *     leaf list given to pe_mesh_build, vars = rho, rho v_1 .. rho v_d, E, node index
+ *     i + N j (+ N^2 k) with N = degree + 1.
+ *   - "slot layout" (what the library steps): [var][slot][node], slots = elements sorted by
+ *     partition, finest partition first, leaf order inside a partition.  The elements active
+ *     at any stage form a prefix of the slots.  pe_element_info maps slots to leaves.
+ */
+#ifndef PERK_H
+#define PERK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pe_ctx pe_ctx;
+
+typedef enum {
+  PE_OK = 0,
+  PE_EINVAL = -1,        /* invalid argument (shape, range, unbalanced mesh, bad tableau) */
+  PE_ENOMEM = -2,        /* host allocation failed */
+  PE_EHIP = -3,          /* a HIP runtime call failed */
+  PE_ESTATE = -4,        /* call out of order (e.g. step before partition or bind) */
+  PE_ENONFINITE = -5,    /* non-finite or non-positive density/pressure detected */
+  PE_EUNSUPPORTED = -6   /* valid but not built (dimension / degree / equations combination) */
+} pe_status;
+
+typedef struct {
+  int dim;          /* 2 or 3 */
+  int degree;       /* polynomial degree k; built: 2 and 3 (N = k+1 LGL nodes per direction) */
+  int equations;    /* 0: compressible Euler; 1: compressible Navier-Stokes with BR1 */
+  double gamma;     /* ratio of specific heats */
+  double mu;        /* dynamic viscosity (Navier-Stokes only, constant) */
+  double prandtl;   /* Prandtl number (Navier-Stokes only); gas constant 1 */
+} pe_physics;
+
+typedef struct {
+  int dim;
+  int n_root[3];            /* trees per direction (third ignored in 2D) */
+  double lo[3], hi[3];      /* box corners */
+  int n_leaves;
+  const int32_t* leaves;    /* host, [n_leaves][4]: (level, i, j, k); cell (i, j, k) of the uniform
+                               grid with n_root[d] << level cells per direction; periodic box */
+} pe_mesh_desc;
+
+typedef struct {
+  int order;                /* 2 or 3 (linear order of consistency p) */
+  int n_members;            /* R, 1 <= R <= 8 */
+  int n_stages;             /* S = E[R-1] (the largest member uses every stage), S <= 32 */
+  const int32_t* E;         /* host [R]: stage evaluations per member, strictly ascending */
+  const double* c;          /* host [S]: shared abscissae */
+  const double* a_sub;      /* host [R][S]: a_{i,i-1} per member (0-based row i; rows 0 and 1
+                               are 0); a_{i,1} = c_i - a_{i,i-1} (internal consistency) */
+  const double* b;          /* host [S]: shared weights */
+} pe_perk_coeffs;
+
+/* Create a context for the given physics.  No device work.  (Sec. 2, eq. ConservationLaw.) */
+pe_status pe_create(pe_ctx** out, const pe_physics* phys);
+
+/* Destroy a context.  Does not touch caller-owned device memory. */
+void pe_destroy(pe_ctx* ctx);
+
+/* Text of the last error on this context (valid until the next call on it). */
+const char* pe_last_error(const pe_ctx* ctx);
+
+/* Build the forest from a leaf list: periodic neighbour search, conforming faces and 2:1
+ * mortars (Sec. 6.2).  Host only.  PE_EINVAL if the leaves overlap, leave holes or violate
+ * 2:1 balance across faces.  Invalidates any binding: query sizes and bind again. */
+pe_status pe_mesh_build(pe_ctx* ctx, const pe_mesh_desc* mesh);
+
+/* Set the P-ERK family (Sec. 3.1, 3.3).  Checks to 1e-12: sum b = 1; b^T c = 1/2 (order >= 2);
+ * b^T c^2 = 1/3 and b^T A^(r) c = 1/6 for every member (order 3), eq. (PRKOrderCondsSimplified);
+ * the zero pattern a_{i,i-1}^(r) = 0 for i < S - E^(r) + 2 (0-based) so that member r evaluates
+ * exactly stages 1 and S-E^(r)+2..S; every stage with b_i != 0 evaluated by every member.
+ * Returns PE_EINVAL on violation.  Invalidates the partition. */
+pe_status pe_set_perk_coefficients(pe_ctx* ctx, const pe_perk_coeffs* coeffs);
+
+/* Sizes for the caller's allocations: the state (doubles, slot layout) and the workspace
+ * (bytes, 256-byte aligned start required).  Valid after pe_mesh_build and
+ * pe_set_perk_coefficients. */
+pe_status pe_query_sizes(const pe_ctx* ctx, int64_t* n_state_doubles, int64_t* n_workspace_bytes,
+                         int64_t* n_elements);
+
+/* Bind caller-owned device buffers of the sizes from pe_query_sizes and upload the mesh
+ * tables into the workspace on `stream`.  The state content is undefined until
+ * pe_set_state. */
+pe_status pe_bind(pe_ctx* ctx, double* u_dev, void* workspace_dev, void* stream);
+
+/* Re-flag elements into partitions on the device (Sec. 6.2): member of every element from
+ * member_of_level (host, [n_levels] where n_levels = max leaf level + 1, values in [0, R)),
+ * stable counting sort of the elements by member (most stage evaluations first), remap of the
+ * connectivity to the new slots, permutation of the bound state, per-stage active prefix
+ * lengths.  Synchronises `stream` once to read the member counts back. */
+pe_status pe_partition(pe_ctx* ctx, const int32_t* member_of_level, int n_levels, void* stream);
+
+/* Copy a state in leaf layout (device) into the bound state (slot layout), and back. */
+pe_status pe_set_state(pe_ctx* ctx, const double* u_leaf_dev, void* stream);
+pe_status pe_get_state(pe_ctx* ctx, double* u_leaf_dev, void* stream);
+
+/* Host copies of the slot -> leaf map and the member of every slot (each [n_elements]).
+ * Either pointer may be NULL. */
+pe_status pe_element_info(const pe_ctx* ctx, int32_t* leaf_of_slot, int32_t* member_of_slot);
+
+/* Physical coordinates of every node in leaf layout, x_dev [leaf][dim][node] (device). */
+pe_status pe_node_coords(pe_ctx* ctx, double* x_leaf_dev, void* stream);
+
+/* du = F(u) on every element (both in slot layout, device; u may be the bound state).
+ * The DGSEM right-hand side of Sec. 6.1 (flux-differencing volume integral, surface and
+ * mortar fluxes, lifting; BR1 for Navier-Stokes). */
+pe_status pe_rhs(pe_ctx* ctx, const double* u_dev, double* du_dev, void* stream);
+
+/* Advance the bound state by n_steps partitioned P-ERK steps of size dt (eq.
+ * PartitionedRKSystem with the tableaux of Sec. 3): stage i evaluates the right-hand side
+ * only on the elements of the members that use stage i (a prefix of the slots); the
+ * right-hand side of the other elements is never computed.  Asynchronous. */
+pe_status pe_step(pe_ctx* ctx, double dt, int n_steps, void* stream);
+
+/* Element right-hand-side evaluations performed so far (device counter, read synchronously
+ * on `stream`) in total and per member (out_per_member may be NULL, else [R]).  Multiplying by
+ * n_vars * N^dim gives N_RHS^Actual of eq. (ActualRHSEvals).  reset != 0 zeroes them. */
+pe_status pe_counters(pe_ctx* ctx, int64_t* out_total, int64_t* out_per_member, int reset,
+                      void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PERK_H */

@@ -12,7 +12,8 @@
 //                       - delta_i0 f*_W / w_0 ]
 //    which is the split form with the diagonal terms 2 D_NN f(u_N) = f(u_N)/w_N cancelled.
 //  * Entropy-conserving two-point volume flux (Ranocha, cited in Sec. 4.1 and Sec. 7.2.1),
-//    logarithmic means with a series branch for nearly equal arguments.
+//    logarithmic means with a series branch for nearly equal arguments (the paper does not
+//    say how the logarithmic mean is evaluated).
 //  * HLL surface flux (Harten-Lax-van Leer) with Davis wave-speed estimates.
 //  * Mortars for 2:1 non-conforming faces (Kopriva 1996, cited in Sec. 6.2): interpolate the
 //    coarse trace to each fine sub-face, evaluate the flux there, project back with
@@ -153,13 +154,16 @@ void euler_flux(const Phys& ph, const double* u, int d, double* f) {
   f[nv - 1] = (u[nv - 1] + q.p) * q.v[d];
 }
 
-// logarithmic mean (b - a) / (ln b - ln a); for nearly equal arguments the series
-// ln(b/a) / (2 f) = 1 + u/3 + u^2/5 + u^3/7, f = (b-a)/(b+a), u = f^2, is used for u < 1e-4.
+// logarithmic mean (b - a) / (ln b - ln a).  With f = (b-a)/(b+a), u = f^2 it equals
+// (a+b) / (2 F(u)), F(u) = ln(b/a)/(2f) = sum_k u^k/(2k+1); for u < 1e-2 the series through
+// u^7/15 is used (truncation below u^8/17 < 1e-17), so the logarithm is only evaluated where
+// |ln(b/a)| > 0.2 and the quotient loses little to cancellation.
 double log_mean(double a, double b) {
   double f = (b - a) / (b + a);
   double u = f * f;
-  if (u < 1e-4) {
-    double F = 1.0 + u / 3.0 + u * u / 5.0 + u * u * u / 7.0;
+  if (u < 1e-2) {
+    double F = 1.0 + u / 3.0 + u * u / 5.0 + u * u * u / 7.0 + u * u * u * u / 9.0 +
+               u * u * u * u * u / 11.0 + u * u * u * u * u * u / 13.0 + u * u * u * u * u * u * u / 15.0;
     return (a + b) / (2.0 * F);
   }
   return (b - a) / std::log(b / a);

@@ -276,6 +276,10 @@ def optimize_alpha(eigs, p: int, E: int, M: int = 128, rtol: float = 1e-6):
     eigs = np.asarray(eigs, dtype=complex)
     eigs = eigs[np.abs(eigs) > 0]
     rho = np.max(np.abs(eigs))
+    if E <= p:
+        # no free coefficient: the truncated Taylor polynomial
+        coef = np.array([1.0 / math.factorial(j) for j in range(p + 1)])
+        return max_stable_step(coef, eigs), {}
     lo, hi = 0.0, 2.0 * E * E / rho          # |P| <= 1 cannot hold beyond ~E^2/rho
     best = None
     # find a feasible lower bound first

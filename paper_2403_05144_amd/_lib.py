@@ -1,0 +1,73 @@
+"""ctypes binding of libperk.so: the entry points of include/perk.h under the same names.
+
+Argument marshalling only; every step of the method runs in the HIP library.  Importing this
+module fails loudly when the library has not been built.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libperk.so")
+
+PE_OK = 0
+STATUS = {0: "PE_OK", -1: "PE_EINVAL", -2: "PE_ENOMEM", -3: "PE_EHIP", -4: "PE_ESTATE",
+          -5: "PE_ENONFINITE", -6: "PE_EUNSUPPORTED"}
+
+
+class pe_physics(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("degree", ctypes.c_int), ("equations", ctypes.c_int),
+                ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double)]
+
+
+class pe_mesh_desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_root", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("n_leaves", ctypes.c_int),
+                ("leaves", ctypes.POINTER(ctypes.c_int32))]
+
+
+class pe_perk_coeffs(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int), ("n_members", ctypes.c_int), ("n_stages", ctypes.c_int),
+                ("E", ctypes.POINTER(ctypes.c_int32)), ("c", ctypes.POINTER(ctypes.c_double)),
+                ("a_sub", ctypes.POINTER(ctypes.c_double)), ("b", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+
+_SIGS = {
+    "pe_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(pe_physics)]),
+    "pe_destroy": (None, [ctypes.c_void_p]),
+    "pe_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "pe_mesh_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(pe_mesh_desc)]),
+    "pe_set_perk_coefficients": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(pe_perk_coeffs)]),
+    "pe_query_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "pe_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pe_partition": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
+                                    ctypes.c_void_p]),
+    "pe_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pe_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pe_element_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]),
+    "pe_node_coords": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pe_rhs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pe_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_void_p]),
+    "pe_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_void_p]),
+}
+
+EXPORTS = tuple(_SIGS)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libperk.so not built at {LIB_PATH}: run __graft_entry__.build() "
+                               "(hipcc, gfx950); there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib

@@ -1,0 +1,669 @@
+// Host side of libperk: the C ABI of include/perk.h.
+//
+// Responsibilities: forest connectivity from a leaf list (periodic neighbour search,
+// conforming faces, 2:1 mortars; Sec. 6.2), LGL operators, validation of the P-ERK family
+// (Sec. 2.1-2.4, 3.1, 3.3), per-stage tables (which members evaluate stage i, where their
+// stage values come from, the Butcher coefficients of the next stage value), the workspace
+// carve-up of caller-owned device memory, and the orchestration of the device re-partition
+// and of the stage launches.  No floating-point work of the time step runs on the host.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/perk.h"
+#include "perk_internal.h"
+
+using namespace perk;
+
+struct pe_ctx {
+  // physics
+  int dim = 2, degree = 3, N = 4, equations = 0;
+  Physics ph{};
+  Ops ops{};
+  // mesh (leaf order)
+  bool have_mesh = false;
+  int n_root[3] = {1, 1, 1};
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+  std::vector<int32_t> leaves;          // [n][4]
+  std::vector<int32_t> fk_leaf, fn_leaf, lev_leaf;
+  int n_e = 0, max_level = 0;
+  // coefficients
+  bool have_coeffs = false;
+  int order = 2, R = 1, S = 1;
+  std::vector<int32_t> E;
+  std::vector<double> c, b, a_sub;      // a_sub [R][S]
+  // binding
+  bool bound = false;
+  double* U = nullptr;
+  char* ws = nullptr;
+  double *K1 = nullptr, *Ya = nullptr, *Yb = nullptr, *ACC = nullptr, *Tmp = nullptr, *Q = nullptr;
+  int32_t *d_fk_leaf = nullptr, *d_fn_leaf = nullptr, *d_lev_leaf = nullptr;
+  int32_t *d_fk = nullptr, *d_fn = nullptr, *d_lev = nullptr, *d_mem = nullptr, *d_mem_leaf = nullptr;
+  int32_t *d_slot_of_leaf = nullptr, *d_leaf_of_slot = nullptr, *d_old_slot_of_leaf = nullptr, *d_counts = nullptr;
+  int32_t* d_halo = nullptr;
+  unsigned long long* d_counter = nullptr;
+  // partition
+  bool partitioned = false;
+  bool state_valid = false;
+  std::vector<int32_t> counts;          // [R] elements per member
+  std::vector<int32_t> leaf_of_slot, slot_of_leaf, mem_of_slot;
+  std::vector<int> n_act;               // [S]
+  std::string err;
+};
+
+namespace {
+
+pe_status fail(pe_ctx* c, pe_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+pe_status hip_check(pe_ctx* c, hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(c, PE_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return PE_OK;
+}
+
+#define HIPCHK(call)                                   \
+  do {                                                 \
+    pe_status _st = hip_check(ctx, (call), #call);     \
+    if (_st != PE_OK) return _st;                      \
+  } while (0)
+
+// ---------------------------------------------------------------- LGL operators (host)
+void legendre(int n, double x, double& P, double& dP) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) {
+    P = 1.0;
+    dP = 0.0;
+    return;
+  }
+  for (int k = 2; k <= n; ++k) {
+    const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  P = p1;
+  dP = n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+void make_ops(int N, Ops& op) {
+  std::memset(&op, 0, sizeof op);
+  const int p = N - 1;
+  std::vector<double> x(N), w(N);
+  x[0] = -1.0;
+  x[p] = 1.0;
+  for (int j = 1; j < p; ++j) {
+    double xi = -std::cos(M_PI * j / p);
+    for (int it = 0; it < 100; ++it) {
+      double P, dP;
+      legendre(p, xi, P, dP);
+      const double d2P = (2.0 * xi * dP - p * (p + 1.0) * P) / (1.0 - xi * xi);
+      const double step = dP / d2P;
+      xi -= step;
+      if (std::fabs(step) < 1e-16) break;
+    }
+    x[j] = xi;
+  }
+  // symmetric nodes exactly
+  for (int j = 0; j < N / 2; ++j) {
+    const double s = 0.5 * (x[N - 1 - j] - x[j]);
+    x[j] = -s;
+    x[N - 1 - j] = s;
+  }
+  if (N % 2) x[N / 2] = 0.0;
+  for (int j = 0; j < N; ++j) {
+    double P, dP;
+    if (j == 0 || j == p) P = (j == 0 && (p % 2)) ? -1.0 : 1.0;
+    else legendre(p, x[j], P, dP);
+    w[j] = 2.0 / (p * (p + 1.0) * P * P);
+  }
+  // barycentric weights and differentiation matrix
+  std::vector<double> lam(N, 1.0);
+  for (int j = 0; j < N; ++j)
+    for (int k = 0; k < N; ++k)
+      if (k != j) lam[j] /= (x[j] - x[k]);
+  for (int i = 0; i < N; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < N; ++j)
+      if (j != i) {
+        const double v = (lam[j] / lam[i]) / (x[i] - x[j]);
+        op.D[i * N + j] = v;
+        s += v;
+      }
+    op.D[i * N + i] = -s;
+  }
+  for (int j = 0; j < N; ++j) {
+    op.w[j] = w[j];
+    op.x[j] = x[j];
+  }
+  // mortar operators: P_m[j][k] = l_k((x_j -/+ 1)/2), R_m[j][k] = 1/2 P_m[k][j] w_k / w_j
+  for (int m = 0; m < 2; ++m) {
+    for (int j = 0; j < N; ++j) {
+      const double xi = m == 0 ? 0.5 * (x[j] - 1.0) : 0.5 * (x[j] + 1.0);
+      for (int k = 0; k < N; ++k) {
+        double l = 1.0;
+        for (int q = 0; q < N; ++q)
+          if (q != k) l *= (xi - x[q]) / (x[k] - x[q]);
+        op.P[m][j * N + k] = l;
+      }
+    }
+    for (int j = 0; j < N; ++j)
+      for (int k = 0; k < N; ++k) op.R[m][j * N + k] = 0.5 * op.P[m][k * N + j] * w[k] / w[j];
+  }
+}
+
+// ---------------------------------------------------------------- forest connectivity
+struct KeyHash {
+  size_t operator()(uint64_t k) const { return std::hash<uint64_t>()(k * 0x9E3779B97F4A7C15ull); }
+};
+inline uint64_t cell_key(int lev, int i, int j, int k) {
+  return ((uint64_t)lev << 60) | ((uint64_t)(uint32_t)i << 40) | ((uint64_t)(uint32_t)j << 20) | (uint64_t)(uint32_t)k;
+}
+
+pe_status build_connectivity(pe_ctx* ctx) {
+  const int n = ctx->n_e, dim = ctx->dim, nf = 2 * dim;
+  std::unordered_map<uint64_t, int, KeyHash> idx;
+  idx.reserve(n * 2);
+  ctx->max_level = 0;
+  for (int e = 0; e < n; ++e) {
+    const int32_t* L = &ctx->leaves[4 * e];
+    const int lev = L[0];
+    if (lev < 0 || lev >= kMaxLevels) return fail(ctx, PE_EINVAL, "leaf %d: level %d out of range [0,%d)", e, lev, kMaxLevels);
+    for (int d = 0; d < dim; ++d) {
+      const int nc = ctx->n_root[d] << lev;
+      if (L[1 + d] < 0 || L[1 + d] >= nc) return fail(ctx, PE_EINVAL, "leaf %d: index out of range", e);
+      if (nc >= (1 << 20)) return fail(ctx, PE_EINVAL, "leaf %d: grid too fine", e);
+    }
+    ctx->max_level = std::max(ctx->max_level, lev);
+    const uint64_t key = cell_key(lev, L[1], L[2], dim == 3 ? L[3] : 0);
+    if (!idx.emplace(key, e).second) return fail(ctx, PE_EINVAL, "duplicate leaf %d", e);
+  }
+  // coverage: every leaf's ancestors must not be leaves; total volume must match
+  double vol = 0.0;
+  for (int e = 0; e < n; ++e) {
+    const int lev = ctx->leaves[4 * e];
+    vol += std::ldexp(1.0, -dim * lev);
+    for (int up = 1; up <= lev; ++up) {
+      const int32_t* L = &ctx->leaves[4 * e];
+      if (idx.count(cell_key(lev - up, L[1] >> up, L[2] >> up, dim == 3 ? (L[3] >> up) : 0)))
+        return fail(ctx, PE_EINVAL, "leaf %d overlaps an ancestor leaf", e);
+    }
+  }
+  double roots = 1.0;
+  for (int d = 0; d < dim; ++d) roots *= ctx->n_root[d];
+  if (std::fabs(vol - roots) > 1e-9 * roots) return fail(ctx, PE_EINVAL, "leaves do not cover the domain");
+  ctx->fk_leaf.assign((size_t)n * nf, 0);
+  ctx->fn_leaf.assign((size_t)n * nf * 4, -1);
+  ctx->lev_leaf.assign(n, 0);
+  auto find = [&](int lev, int i, int j, int k) -> int {
+    if (lev < 0) return -1;
+    auto it = idx.find(cell_key(lev, i, j, k));
+    return it == idx.end() ? -1 : it->second;
+  };
+  for (int e = 0; e < n; ++e) {
+    const int32_t* L = &ctx->leaves[4 * e];
+    const int lev = L[0];
+    ctx->lev_leaf[e] = lev;
+    for (int d = 0; d < dim; ++d)
+      for (int s = 0; s < 2; ++s) {
+        const int f = 2 * d + s;
+        int cc[3] = {L[1], L[2], dim == 3 ? L[3] : 0};
+        const int nc = ctx->n_root[d] << lev;
+        cc[d] = ((cc[d] + (s ? 1 : -1)) % nc + nc) % nc;
+        int32_t* nb = &ctx->fn_leaf[((size_t)e * nf + f) * 4];
+        const int same = find(lev, cc[0], cc[1], cc[2]);
+        if (same >= 0) {
+          ctx->fk_leaf[(size_t)e * nf + f] = pack_face(kConforming, 0, 0);
+          nb[0] = same;
+          continue;
+        }
+        const int par = find(lev - 1, cc[0] >> 1, cc[1] >> 1, cc[2] >> 1);
+        if (par >= 0) {
+          int sub[2] = {0, 0}, t = 0;
+          for (int q = 0; q < dim; ++q)
+            if (q != d) sub[t++] = (q == 0 ? L[1] : (q == 1 ? L[2] : L[3])) & 1;
+          ctx->fk_leaf[(size_t)e * nf + f] = pack_face(kFineSide, sub[0], sub[1]);
+          nb[0] = par;
+          continue;
+        }
+        int tang[2] = {0, 0}, t = 0;
+        for (int q = 0; q < dim; ++q)
+          if (q != d) tang[t++] = q;
+        const int nsub = 1 << (dim - 1);
+        for (int m = 0; m < nsub; ++m) {
+          int ch[3] = {2 * cc[0], 2 * cc[1], 2 * cc[2]};
+          ch[d] += s ? 0 : 1;
+          ch[tang[0]] += m & 1;
+          if (dim == 3) ch[tang[1]] += (m >> 1) & 1;
+          const int c = find(lev + 1, ch[0], ch[1], dim == 3 ? ch[2] : 0);
+          if (c < 0) return fail(ctx, PE_EINVAL, "leaf %d face %d: no 2:1-balanced neighbour", e, f);
+          nb[m] = c;
+        }
+        ctx->fk_leaf[(size_t)e * nf + f] = pack_face(kCoarseSide, 0, 0);
+      }
+  }
+  return PE_OK;
+}
+
+int nodes_per_elem(const pe_ctx* c) { return c->dim == 2 ? c->N * c->N : c->N * c->N * c->N; }
+int nvars(const pe_ctx* c) { return c->dim + 2; }
+int64_t state_doubles(const pe_ctx* c) { return (int64_t)c->n_e * nvars(c) * nodes_per_elem(c); }
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace layout: five state-sized fp64 arrays (K1, two stage buffers, the weighted stage
+// sum, a permutation temporary), BR1 gradients for Navier-Stokes, then int32 tables.
+size_t carve(pe_ctx* c, char* base);
+
+size_t workspace_bytes(const pe_ctx* c) {
+  pe_ctx tmp;
+  tmp.dim = c->dim;
+  tmp.N = c->N;
+  tmp.equations = c->equations;
+  tmp.n_e = c->n_e;
+  return carve(&tmp, nullptr);
+}
+
+size_t carve(pe_ctx* c, char* base) {
+  size_t off = 0;
+  const size_t sd = (size_t)state_doubles(c) * sizeof(double);
+  const int n = c->n_e, nf = 2 * c->dim;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  c->K1 = (double*)take(sd);
+  c->Ya = (double*)take(sd);
+  c->Yb = (double*)take(sd);
+  c->ACC = (double*)take(sd);
+  c->Tmp = (double*)take(sd);
+  c->Q = c->equations == 1 ? (double*)take((size_t)c->dim * (c->dim + 1) * n * nodes_per_elem(c) * sizeof(double))
+                           : nullptr;
+  c->d_fk_leaf = (int32_t*)take((size_t)n * nf * 4);
+  c->d_fn_leaf = (int32_t*)take((size_t)n * nf * 4 * 4);
+  c->d_lev_leaf = (int32_t*)take((size_t)n * 4);
+  c->d_fk = (int32_t*)take((size_t)n * nf * 4);
+  c->d_fn = (int32_t*)take((size_t)n * nf * 4 * 4);
+  c->d_lev = (int32_t*)take((size_t)n * 4);
+  c->d_mem = (int32_t*)take((size_t)n * 4);
+  c->d_mem_leaf = (int32_t*)take((size_t)n * 4);
+  c->d_slot_of_leaf = (int32_t*)take((size_t)n * 4);
+  c->d_leaf_of_slot = (int32_t*)take((size_t)n * 4);
+  c->d_old_slot_of_leaf = (int32_t*)take((size_t)n * 4);
+  c->d_counts = (int32_t*)take(kMaxMembers * 4);
+  c->d_halo = (int32_t*)take((size_t)n * 4 * (kMaxMembers + 1));
+  c->d_counter = (unsigned long long*)take(kMaxMembers * 8);
+  return off;
+}
+
+Mesh device_mesh(const pe_ctx* c) {
+  Mesh m{};
+  m.fk = c->d_fk;
+  m.fn = c->d_fn;
+  m.lev = c->d_lev;
+  m.mem = c->d_mem;
+  m.n_e = c->n_e;
+  for (int l = 0; l < kMaxLevels; ++l)
+    for (int d = 0; d < 3; ++d) {
+      const double h = d < c->dim ? (c->hi[d] - c->lo[d]) / std::ldexp((double)c->n_root[d], l) : 1.0;
+      m.jac[l][d] = 2.0 / h;
+    }
+  return m;
+}
+
+// member r evaluates 0-based stage i iff i == 0 or i >= S - E_r + 1
+inline bool active(const pe_ctx* c, int r, int i) { return i == 0 || i >= c->S - c->E[r] + 1; }
+
+void fill_stage(const pe_ctx* c, int i, double dt, StageArgs& a) {
+  std::memset(&a, 0, sizeof a);
+  a.dt = dt;
+  a.ci = c->c[i];
+  a.first = i == 0;
+  a.last = i == c->S - 1;
+  a.n_act = c->n_act[i];
+  // weighted sum of stages with b != 0 before the last
+  int seen = 0;
+  for (int j = 0; j < i; ++j)
+    if (c->b[j] != 0.0) ++seen;
+  if (!a.last && c->b[i] != 0.0) {
+    a.acc_mode = seen == 0 ? 1 : 2;
+    a.bi = c->b[i];
+  }
+  a.bS = c->b[c->S - 1];
+  a.use_acc_last = 0;
+  for (int j = 0; j < c->S - 1; ++j)
+    if (c->b[j] != 0.0) a.use_acc_last = 1;
+  for (int r = 0; r < c->R; ++r) {
+    a.src[r] = i == 0 ? 0 : ((active(c, r, i) && active(c, r, i - 1)) ? 1 : 2);
+    if (i + 1 < c->S) {
+      a.wr[r] = active(c, r, i + 1) ? 1 : 0;
+      a.a2[r] = c->a_sub[(size_t)r * c->S + i + 1];
+      a.a1[r] = c->c[i + 1] - a.a2[r];
+    }
+  }
+}
+
+bool last_stage_in_place_safe(const pe_ctx* c) {
+  // At the last stage a neighbour reads U_n only if its member is first activated there.
+  for (int r = 0; r < c->R; ++r)
+    if (c->S > 1 && !active(c, r, c->S - 2)) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+pe_status pe_create(pe_ctx** out, const pe_physics* phys) {
+  if (!out || !phys) return PE_EINVAL;
+  *out = nullptr;
+  pe_ctx* c = new (std::nothrow) pe_ctx();
+  if (!c) return PE_ENOMEM;
+  if (phys->dim != 2 && phys->dim != 3) {
+    delete c;
+    return PE_EINVAL;
+  }
+  if (phys->degree < 1 || phys->degree + 1 > kMaxN || phys->gamma <= 1.0 || phys->equations < 0 ||
+      phys->equations > 1 || (phys->equations == 1 && (phys->mu < 0.0 || phys->prandtl <= 0.0))) {
+    delete c;
+    return PE_EINVAL;
+  }
+  c->dim = phys->dim;
+  c->degree = phys->degree;
+  c->N = phys->degree + 1;
+  c->equations = phys->equations;
+  c->ph.gamma = phys->gamma;
+  c->ph.mu = phys->equations == 1 ? phys->mu : 0.0;
+  c->ph.kappa = phys->equations == 1 ? phys->gamma * phys->mu / ((phys->gamma - 1.0) * phys->prandtl) : 0.0;
+  make_ops(c->N, c->ops);
+  *out = c;
+  return PE_OK;
+}
+
+void pe_destroy(pe_ctx* ctx) { delete ctx; }
+
+const char* pe_last_error(const pe_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+pe_status pe_mesh_build(pe_ctx* ctx, const pe_mesh_desc* mesh) {
+  if (!ctx) return PE_EINVAL;
+  if (!mesh || mesh->dim != ctx->dim || mesh->n_leaves <= 0 || !mesh->leaves)
+    return fail(ctx, PE_EINVAL, "mesh: bad descriptor (dimension must match the physics)");
+  for (int d = 0; d < ctx->dim; ++d)
+    if (mesh->n_root[d] <= 0 || !(mesh->hi[d] > mesh->lo[d])) return fail(ctx, PE_EINVAL, "mesh: bad box");
+  ctx->have_mesh = false;
+  ctx->bound = false;
+  ctx->partitioned = false;
+  ctx->state_valid = false;
+  for (int d = 0; d < 3; ++d) {
+    ctx->n_root[d] = d < ctx->dim ? mesh->n_root[d] : 1;
+    ctx->lo[d] = d < ctx->dim ? mesh->lo[d] : 0.0;
+    ctx->hi[d] = d < ctx->dim ? mesh->hi[d] : 1.0;
+  }
+  ctx->n_e = mesh->n_leaves;
+  ctx->leaves.assign(mesh->leaves, mesh->leaves + 4 * (size_t)mesh->n_leaves);
+  if (ctx->dim == 2)
+    for (int e = 0; e < ctx->n_e; ++e) ctx->leaves[4 * e + 3] = 0;
+  pe_status st = build_connectivity(ctx);
+  if (st != PE_OK) return st;
+  ctx->have_mesh = true;
+  return PE_OK;
+}
+
+pe_status pe_set_perk_coefficients(pe_ctx* ctx, const pe_perk_coeffs* co) {
+  if (!ctx) return PE_EINVAL;
+  if (!co || !co->E || !co->c || !co->a_sub || !co->b) return fail(ctx, PE_EINVAL, "coefficients: null pointer");
+  const int R = co->n_members, S = co->n_stages;
+  if (R < 1 || R > kMaxMembers || S < 1 || S > kMaxStages || (co->order != 2 && co->order != 3))
+    return fail(ctx, PE_EINVAL, "coefficients: R=%d S=%d order=%d out of range", R, S, co->order);
+  for (int r = 0; r < R; ++r) {
+    if (co->E[r] < 1 || co->E[r] > S || (r > 0 && co->E[r] <= co->E[r - 1]))
+      return fail(ctx, PE_EINVAL, "coefficients: E must be strictly ascending in [1, S]");
+  }
+  if (co->E[R - 1] != S) return fail(ctx, PE_EINVAL, "coefficients: largest member must use all S stages");
+  const double tol = 1e-12;
+  double sb = 0.0, sbc = 0.0, sbc2 = 0.0;
+  for (int i = 0; i < S; ++i) {
+    sb += co->b[i];
+    sbc += co->b[i] * co->c[i];
+    sbc2 += co->b[i] * co->c[i] * co->c[i];
+  }
+  if (std::fabs(co->c[0]) > tol) return fail(ctx, PE_EINVAL, "coefficients: c_1 must be 0");
+  if (std::fabs(sb - 1.0) > tol) return fail(ctx, PE_EINVAL, "order condition b^T 1 = 1 violated (%g)", sb);
+  if (co->order >= 2 && std::fabs(sbc - 0.5) > tol)
+    return fail(ctx, PE_EINVAL, "order condition b^T c = 1/2 violated (%g)", sbc);
+  if (co->order >= 3 && std::fabs(sbc2 - 1.0 / 3.0) > tol)
+    return fail(ctx, PE_EINVAL, "order condition b^T c^2 = 1/3 violated (%g)", sbc2);
+  for (int r = 0; r < R; ++r) {
+    const double* a = co->a_sub + (size_t)r * S;
+    if ((S > 0 && a[0] != 0.0) || (S > 1 && a[1] != 0.0))
+      return fail(ctx, PE_EINVAL, "member %d: a_sub rows 0 and 1 must be zero", r);
+    for (int i = 2; i < S; ++i)
+      if (i <= S - co->E[r] + 1 && a[i] != 0.0)
+        return fail(ctx, PE_EINVAL, "member %d (E=%d): a_{%d,%d} must be zero for a stage it skips", r, co->E[r],
+                    i + 1, i);
+    if (co->order >= 3) {
+      // b^T A c = sum_i b_i (a_{i,1} c_1 + a_{i,i-1} c_{i-1}) with c_1 = 0
+      double s = 0.0;
+      for (int i = 2; i < S; ++i) s += co->b[i] * a[i] * co->c[i - 1];
+      if (S > 1) s += co->b[1] * co->c[1] * co->c[0];
+      if (std::fabs(s - 1.0 / 6.0) > tol)
+        return fail(ctx, PE_EINVAL, "member %d: order condition b^T A c = 1/6 violated (%g)", r, s);
+    }
+  }
+  ctx->order = co->order;
+  ctx->R = R;
+  ctx->S = S;
+  ctx->E.assign(co->E, co->E + R);
+  ctx->c.assign(co->c, co->c + S);
+  ctx->b.assign(co->b, co->b + S);
+  ctx->a_sub.assign(co->a_sub, co->a_sub + (size_t)R * S);
+  for (int i = 0; i < S; ++i)
+    if (co->b[i] != 0.0)
+      for (int r = 0; r < R; ++r)
+        if (!active(ctx, r, i))
+          return fail(ctx, PE_EINVAL, "stage %d has b != 0 but member %d does not evaluate it", i + 1, r);
+  ctx->have_coeffs = true;
+  ctx->partitioned = false;
+  return PE_OK;
+}
+
+pe_status pe_query_sizes(const pe_ctx* ctx, int64_t* n_state, int64_t* n_ws, int64_t* n_elem) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->have_mesh) return fail(const_cast<pe_ctx*>(ctx), PE_ESTATE, "query_sizes before mesh_build");
+  if (n_state) *n_state = state_doubles(ctx);
+  if (n_ws) *n_ws = (int64_t)workspace_bytes(ctx);
+  if (n_elem) *n_elem = ctx->n_e;
+  return PE_OK;
+}
+
+pe_status pe_bind(pe_ctx* ctx, double* u_dev, void* ws, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->have_mesh) return fail(ctx, PE_ESTATE, "bind before mesh_build");
+  if (!u_dev || !ws) return fail(ctx, PE_EINVAL, "bind: null buffer");
+  if (((uintptr_t)ws & 255) != 0) return fail(ctx, PE_EINVAL, "bind: workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  ctx->U = u_dev;
+  ctx->ws = (char*)ws;
+  carve(ctx, ctx->ws);
+  const int n = ctx->n_e, nf = 2 * ctx->dim;
+  HIPCHK(hipMemcpyAsync(ctx->d_fk_leaf, ctx->fk_leaf.data(), (size_t)n * nf * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->d_fn_leaf, ctx->fn_leaf.data(), (size_t)n * nf * 16, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->d_lev_leaf, ctx->lev_leaf.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(ctx->d_counter, 0, kMaxMembers * 8, s));
+  HIPCHK(hipStreamSynchronize(s));
+  ctx->bound = true;
+  ctx->partitioned = false;
+  ctx->state_valid = false;
+  return PE_OK;
+}
+
+pe_status pe_partition(pe_ctx* ctx, const int32_t* member_of_level, int n_levels, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->bound || !ctx->have_coeffs) return fail(ctx, PE_ESTATE, "partition needs a bound mesh and coefficients");
+  if (!member_of_level || n_levels <= ctx->max_level || n_levels > kMaxLevels)
+    return fail(ctx, PE_EINVAL, "member_of_level must cover levels 0..%d", ctx->max_level);
+  PartitionArgs pa{};
+  for (int l = 0; l < kMaxLevels; ++l) pa.member_of_level[l] = l < n_levels ? member_of_level[l] : 0;
+  for (int l = 0; l < n_levels; ++l)
+    if (member_of_level[l] < 0 || member_of_level[l] >= ctx->R)
+      return fail(ctx, PE_EINVAL, "member_of_level[%d] = %d outside [0, %d)", l, member_of_level[l], ctx->R);
+  hipStream_t s = (hipStream_t)stream;
+  const int n = ctx->n_e, nf = 2 * ctx->dim;
+  const bool permute = ctx->state_valid && ctx->partitioned;
+  if (permute)
+    HIPCHK(hipMemcpyAsync(ctx->d_old_slot_of_leaf, ctx->d_slot_of_leaf, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+  pa.lev_leaf = ctx->d_lev_leaf;
+  pa.mem_leaf = ctx->d_mem_leaf;
+  pa.slot_of_leaf = ctx->d_slot_of_leaf;
+  pa.leaf_of_slot = ctx->d_leaf_of_slot;
+  pa.counts = ctx->d_counts;
+  pa.n = n;
+  pa.R = ctx->R;
+  HIPCHK(launch_partition_sort(pa, s));
+  HIPCHK(launch_remap_connectivity(n, nf, ctx->d_leaf_of_slot, ctx->d_slot_of_leaf, ctx->d_fk_leaf, ctx->d_fn_leaf,
+                                   ctx->d_lev_leaf, ctx->d_mem_leaf, ctx->d_fk, ctx->d_fn, ctx->d_lev, ctx->d_mem, s));
+  if (permute) {
+    HIPCHK(launch_permute_state(n, nvars(ctx), nodes_per_elem(ctx), ctx->d_leaf_of_slot, ctx->d_old_slot_of_leaf,
+                                ctx->U, ctx->Tmp, s));
+    HIPCHK(launch_copy(ctx->U, ctx->Tmp, state_doubles(ctx), s));
+  }
+  ctx->counts.assign(ctx->R, 0);
+  ctx->leaf_of_slot.resize(n);
+  ctx->slot_of_leaf.resize(n);
+  ctx->mem_of_slot.resize(n);
+  HIPCHK(hipMemcpyAsync(ctx->counts.data(), ctx->d_counts, ctx->R * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(ctx->leaf_of_slot.data(), ctx->d_leaf_of_slot, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(ctx->slot_of_leaf.data(), ctx->d_slot_of_leaf, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(ctx->mem_of_slot.data(), ctx->d_mem, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  ctx->n_act.assign(ctx->S, 0);
+  for (int i = 0; i < ctx->S; ++i)
+    for (int r = 0; r < ctx->R; ++r)
+      if (active(ctx, r, i)) ctx->n_act[i] += ctx->counts[r];
+  ctx->partitioned = true;
+  return PE_OK;
+}
+
+pe_status pe_set_state(pe_ctx* ctx, const double* u_leaf, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->partitioned) return fail(ctx, PE_ESTATE, "set_state before partition");
+  if (!u_leaf) return fail(ctx, PE_EINVAL, "set_state: null");
+  HIPCHK(launch_leaf_to_slot(ctx->n_e, nvars(ctx), nodes_per_elem(ctx), ctx->d_leaf_of_slot, u_leaf, ctx->U,
+                             (hipStream_t)stream));
+  ctx->state_valid = true;
+  return PE_OK;
+}
+
+pe_status pe_get_state(pe_ctx* ctx, double* u_leaf, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->partitioned || !ctx->state_valid) return fail(ctx, PE_ESTATE, "get_state without a state");
+  if (!u_leaf) return fail(ctx, PE_EINVAL, "get_state: null");
+  HIPCHK(launch_slot_to_leaf(ctx->n_e, nvars(ctx), nodes_per_elem(ctx), ctx->d_slot_of_leaf, ctx->U, u_leaf,
+                             (hipStream_t)stream));
+  return PE_OK;
+}
+
+pe_status pe_element_info(const pe_ctx* ctx, int32_t* leaf_of_slot, int32_t* member_of_slot) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->partitioned) return fail(const_cast<pe_ctx*>(ctx), PE_ESTATE, "element_info before partition");
+  if (leaf_of_slot) std::memcpy(leaf_of_slot, ctx->leaf_of_slot.data(), (size_t)ctx->n_e * 4);
+  if (member_of_slot) std::memcpy(member_of_slot, ctx->mem_of_slot.data(), (size_t)ctx->n_e * 4);
+  return PE_OK;
+}
+
+pe_status pe_node_coords(pe_ctx* ctx, double* x_leaf, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->have_mesh) return fail(ctx, PE_ESTATE, "node_coords before mesh_build");
+  if (!x_leaf) return fail(ctx, PE_EINVAL, "node_coords: null");
+  const int nd = nodes_per_elem(ctx), N = ctx->N, dim = ctx->dim;
+  std::vector<double> x((size_t)ctx->n_e * dim * nd);
+  for (int e = 0; e < ctx->n_e; ++e) {
+    const int32_t* L = &ctx->leaves[4 * e];
+    for (int node = 0; node < nd; ++node) {
+      const int ijk[3] = {node % N, (node / N) % N, node / (N * N)};
+      for (int d = 0; d < dim; ++d) {
+        const double h = (ctx->hi[d] - ctx->lo[d]) / std::ldexp((double)ctx->n_root[d], L[0]);
+        x[((size_t)e * dim + d) * nd + node] = ctx->lo[d] + h * L[1 + d] + 0.5 * h * (1.0 + ctx->ops.x[ijk[d]]);
+      }
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(x_leaf, x.data(), x.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return PE_OK;
+}
+
+pe_status pe_rhs(pe_ctx* ctx, const double* u, double* du, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->partitioned) return fail(ctx, PE_ESTATE, "rhs before partition");
+  if (!u || !du) return fail(ctx, PE_EINVAL, "rhs: null");
+  StageArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.U = u;
+  a.Kout = du;
+  a.n_act = ctx->n_e;
+  Mesh m = device_mesh(ctx);
+  HIPCHK(launch_stage(ctx->dim, ctx->N, ctx->equations == 1, a, m, ctx->ops, ctx->ph, (hipStream_t)stream));
+  return PE_OK;
+}
+
+pe_status pe_step(pe_ctx* ctx, double dt, int n_steps, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->partitioned || !ctx->state_valid) return fail(ctx, PE_ESTATE, "step needs a partition and a state");
+  if (!(dt > 0.0) || n_steps < 0) return fail(ctx, PE_EINVAL, "step: dt must be > 0 and n_steps >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  Mesh m = device_mesh(ctx);
+  const bool in_place = last_stage_in_place_safe(ctx);
+  for (int step = 0; step < n_steps; ++step) {
+    for (int i = 0; i < ctx->S; ++i) {
+      StageArgs a;
+      fill_stage(ctx, i, dt, a);
+      a.U = ctx->U;
+      a.K1 = ctx->K1;
+      a.Yin = (i % 2 == 0) ? ctx->Ya : ctx->Yb;
+      a.Yout = (i % 2 == 0) ? ctx->Yb : ctx->Ya;
+      a.ACC = ctx->ACC;
+      a.Uout = in_place ? ctx->U : ctx->Tmp;
+      a.counter = ctx->d_counter;
+      HIPCHK(launch_stage(ctx->dim, ctx->N, ctx->equations == 1, a, m, ctx->ops, ctx->ph, s));
+    }
+    if (!in_place) HIPCHK(launch_copy(ctx->U, ctx->Tmp, state_doubles(ctx), s));
+  }
+  return PE_OK;
+}
+
+pe_status pe_counters(pe_ctx* ctx, int64_t* total, int64_t* per_member, int reset, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->bound) return fail(ctx, PE_ESTATE, "counters before bind");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long h[kMaxMembers];
+  HIPCHK(hipMemcpyAsync(h, ctx->d_counter, sizeof h, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int64_t t = 0;
+  for (int r = 0; r < ctx->R; ++r) {
+    t += (int64_t)h[r];
+    if (per_member) per_member[r] = (int64_t)h[r];
+  }
+  if (total) *total = t;
+  if (reset) {
+    HIPCHK(hipMemsetAsync(ctx->d_counter, 0, sizeof h, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return PE_OK;
+}
+
+}  // extern "C"

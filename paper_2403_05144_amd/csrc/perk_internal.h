@@ -1,0 +1,110 @@
+// Internal declarations shared by the host side (perk_api.cpp) and the HIP kernels
+// (perk_kernels.hip) of libperk.  Not part of the public ABI (see include/perk.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace perk {
+
+constexpr int kMaxMembers = 8;    // R
+constexpr int kMaxStages = 32;    // S
+constexpr int kMaxLevels = 16;    // refinement levels of the forest
+constexpr int kMaxN = 4;          // nodes per direction (degree 3)
+
+// Face kinds of an element face (Sec. 6.2: interfaces between equal cells, mortars at 2:1
+// hanging faces).  Packed with the sub-face position of a fine element on its coarse face.
+enum FaceKind : int32_t { kConforming = 0, kFineSide = 1, kCoarseSide = 2 };
+__host__ __device__ inline int32_t pack_face(int kind, int s0, int s1) { return kind | (s0 << 2) | (s1 << 3); }
+__host__ __device__ inline int face_kind(int32_t f) { return f & 3; }
+__host__ __device__ inline int face_sub0(int32_t f) { return (f >> 2) & 1; }
+__host__ __device__ inline int face_sub1(int32_t f) { return (f >> 3) & 1; }
+
+// One-dimensional LGL operators for N nodes (N <= kMaxN), passed to kernels by value.
+struct Ops {
+  double D[kMaxN * kMaxN];          // D[i*N + j] = l_j'(x_i)
+  double w[kMaxN];                  // quadrature weights
+  double P[2][kMaxN * kMaxN];       // mortar interpolation to the lower/upper half
+  double R[2][kMaxN * kMaxN];       // mortar projection 1/2 M^{-1} P^T M
+  double x[kMaxN];                  // nodes on [-1, 1]
+};
+
+struct Physics {
+  double gamma;
+  double mu;
+  double kappa;    // gamma mu / ((gamma - 1) Pr), gas constant 1
+};
+
+// Connectivity of the slots (sorted element order).
+struct Mesh {
+  const int32_t* fk;      // [slot][2 dim] packed face kind
+  const int32_t* fn;      // [slot][2 dim][4] neighbour slots
+  const int32_t* lev;     // [slot] refinement level
+  const int32_t* mem;     // [slot] P-ERK member
+  int n_e;                // number of slots (stride of the slot layout)
+  double jac[kMaxLevels][3];   // 2 / h per level and direction
+};
+
+// Everything one stage launch needs.  Stage indices are 0-based here.
+struct StageArgs {
+  const double* U;        // U_n (slot layout)
+  double* K1;             // K_1 (written at stage 0)
+  const double* Yin;      // Y_i of elements whose member was active at stages i-1 and i
+  double* Yout;           // Y_{i+1} of elements active at stage i+1
+  double* ACC;            // running sum of b_j K_j over the stages with b_j != 0 before the last
+  double* Uout;           // U_{n+1} at the last stage (may alias U)
+  double* Kout;           // if non-null: K_i is written here and nothing else (right-hand side)
+  const double* Q;        // BR1 gradients [dim][dim+1][slot][node] (Navier-Stokes)
+  unsigned long long* counter;   // [R] element evaluations per member, or null
+  int n_act;              // active slots: [0, n_act)
+  int n_halo;             // Navier-Stokes gradient kernel only: extra slots listed in halo
+  const int32_t* halo;
+  double dt;
+  double ci;              // c_i
+  double bi;              // b_i (accumulated when acc_mode != 0)
+  double bS;              // b_S (last stage)
+  int first;              // stage 0
+  int last;               // stage S-1
+  int acc_mode;           // 0: nothing, 1: ACC = b_i K, 2: ACC += b_i K
+  int use_acc_last;       // last stage adds ACC
+  int src[kMaxMembers];   // where Y_i of a member comes from: 0 U_n, 1 Yin, 2 U_n + dt c_i K_1
+  int wr[kMaxMembers];    // member writes Y_{i+1}
+  double a1[kMaxMembers]; // a_{i+1,1}
+  double a2[kMaxMembers]; // a_{i+1,i}
+};
+
+// Kernel launch wrappers (perk_kernels.hip).  All return hipError_t.
+hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,
+                        const Physics& ph, hipStream_t s);
+hipError_t launch_gradients(int dim, int N, const StageArgs& a, const Mesh& m, const Ops& op,
+                            const Physics& ph, double* Q, hipStream_t s);
+
+struct PartitionArgs {
+  const int32_t* lev_leaf;       // [n] level per leaf
+  int32_t* mem_leaf;             // [n] member per leaf (out)
+  int32_t* slot_of_leaf;         // [n] (out)
+  int32_t* leaf_of_slot;         // [n] (out)
+  int32_t* counts;               // [R] (out)
+  int n;
+  int R;
+  int member_of_level[kMaxLevels];
+};
+hipError_t launch_partition_sort(const PartitionArgs& a, hipStream_t s);
+
+// Rebuild slot-order connectivity from leaf-order connectivity.
+hipError_t launch_remap_connectivity(int n, int nfaces, const int32_t* leaf_of_slot, const int32_t* slot_of_leaf,
+                                     const int32_t* fk_leaf, const int32_t* fn_leaf, const int32_t* lev_leaf,
+                                     const int32_t* mem_leaf, int32_t* fk, int32_t* fn, int32_t* lev, int32_t* mem,
+                                     hipStream_t s);
+// dst[v][slot][node] = src[v][old_slot_of_leaf[leaf_of_slot[slot]]][node]
+hipError_t launch_permute_state(int n, int nv, int nd, const int32_t* leaf_of_slot, const int32_t* old_slot_of_leaf,
+                                const double* src, double* dst, hipStream_t s);
+// leaf layout <-> slot layout
+hipError_t launch_leaf_to_slot(int n, int nv, int nd, const int32_t* leaf_of_slot, const double* src, double* dst,
+                               hipStream_t s);
+hipError_t launch_slot_to_leaf(int n, int nv, int nd, const int32_t* slot_of_leaf, const double* src, double* dst,
+                               hipStream_t s);
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+
+}  // namespace perk

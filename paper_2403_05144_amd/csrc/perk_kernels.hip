@@ -1,0 +1,648 @@
+// HIP kernels of libperk for gfx950 (CDNA4).  fp64 on the vector ALUs throughout: flux
+// differencing is a pairwise nonlinear function of node states, not a dense contraction, so
+// the matrix cores have nothing to do here.
+//
+// Stage kernel (one launch per P-ERK stage, Sec. 3.1 and eq. PartitionedRKSystem):
+//   * one element per group of N^dim lanes (one lane per LGL node), EPB elements per block;
+//     an element's conservative state and derived node quantities are staged in LDS;
+//   * only the active prefix [0, n_act) of the partition-sorted slots is launched: elements of
+//     inactive members cost neither blocks nor lanes (Sec. 6.1);
+//   * every element computes the numerical fluxes of its own faces (conforming faces, the
+//     fine side of a 2:1 mortar from the interpolated coarse trace, and the coarse side by
+//     projecting the fluxes of all sub-faces), so no face buffers and no second launch;
+//     both neighbours evaluate a shared face flux from identical inputs in the same order,
+//     so the two sides see bitwise identical fluxes and conservation holds to round-off;
+//   * traces of neighbours whose member is inactive at this stage are formed on the fly as
+//     U_n + dt c_i K_1 (the stage value of a member with a_{i,i-1} = 0);
+//   * the epilogue applies the per-member stage combination of the P-ERK tableau
+//     (Y_{i+1} = U_n + dt (a_{i+1,1} K_1 + a_{i+1,i} K_i)), the running weighted sum of the
+//     stages with b_j != 0, and the final update, so K_i is never stored (low storage, Sec. 3.1).
+//
+// Memory layout: slot layout [var][slot][node]; lanes of a block read consecutive nodes of
+// consecutive elements, so every state access of the own element is one coalesced segment
+// per variable.
+
+#include "perk_internal.h"
+
+namespace perk {
+namespace {
+
+template <int DIM, int N>
+struct G {
+  static constexpr int ND = DIM == 2 ? N * N : N * N * N;   // nodes per element
+  static constexpr int NF = DIM == 2 ? N : N * N;           // nodes per face
+  static constexpr int NFC = 2 * DIM;                       // faces per element
+  static constexpr int NV = DIM + 2;                        // conserved variables
+  static constexpr int NSUB = DIM == 2 ? 2 : 4;             // fine faces per mortar
+  static constexpr int NQ = DIM + 5;                        // rho, v, p, ln rho, beta, ln beta
+};
+
+template <int DIM, int N>
+__device__ __forceinline__ int node_index_dir(int nd, int d) {
+  if (d == 0) return nd % N;
+  if (d == 1) return (nd / N) % N;
+  return nd / (N * N);
+}
+
+template <int DIM, int N>
+__device__ __forceinline__ int stride_dir(int d) {
+  return d == 0 ? 1 : (d == 1 ? N : N * N);
+}
+
+// volume node of face node j on face (d, side)
+template <int DIM, int N>
+__device__ __forceinline__ int face_node(int d, int side, int j) {
+  const int sv = side ? N - 1 : 0;
+  if (DIM == 2) return d == 0 ? sv + N * j : j + N * sv;
+  const int a = j % N, b = j / N;
+  if (d == 0) return sv + N * a + N * N * b;
+  if (d == 1) return a + N * sv + N * N * b;
+  return a + N * b + N * N * sv;
+}
+
+// face node index of volume node nd on a face normal to d
+template <int DIM, int N>
+__device__ __forceinline__ int face_index(int nd, int d) {
+  const int i = nd % N, j = (nd / N) % N;
+  if (DIM == 2) return d == 0 ? j : i;
+  const int k = nd / (N * N);
+  if (d == 0) return j + N * k;
+  if (d == 1) return i + N * k;
+  return i + N * j;
+}
+
+// Logarithmic mean (a - b)/(ln a - ln b) from precomputed node logarithms.  With
+// f = (a-b)/(a+b), u = f^2 it equals (a+b) / (2 F(u)), F(u) = sum_k u^k/(2k+1); for u < 1e-2
+// the series through u^7/15 is used (truncation < 1e-17), so the difference of logarithms is
+// only used where |ln a - ln b| > 0.2 and loses little to cancellation.
+__device__ __forceinline__ double series_F(double u) {
+  return 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0 + u * (1.0 / 9.0 +
+         u * (1.0 / 11.0 + u * (1.0 / 13.0 + u * (1.0 / 15.0)))))));
+}
+
+__device__ __forceinline__ double log_mean(double a, double b, double la, double lb) {
+  const double dd = a - b, ss = a + b;
+  if (dd * dd < 1e-2 * ss * ss) {
+    const double f = dd / ss;
+    return ss / (2.0 * series_F(f * f));
+  }
+  return dd / (la - lb);
+}
+
+__device__ __forceinline__ double inv_log_mean(double a, double b, double la, double lb) {
+  const double dd = a - b, ss = a + b;
+  if (dd * dd < 1e-2 * ss * ss) {
+    const double f = dd / ss;
+    return 2.0 * series_F(f * f) / ss;
+  }
+  return (la - lb) / dd;
+}
+
+template <int DIM>
+struct NodeQ {
+  double rho, v[DIM], p, lrho, beta, lbeta;
+};
+
+template <int DIM>
+__device__ __forceinline__ void cons_to_prim(const double* u, double gamma, double& rho, double* v, double& p) {
+  rho = u[0];
+  const double ir = 1.0 / rho;
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    v[d] = u[1 + d] * ir;
+    ke += u[1 + d] * v[d];
+  }
+  p = (gamma - 1.0) * (u[DIM + 1] - 0.5 * ke);
+}
+
+// Entropy-conserving, kinetic-energy-preserving two-point flux (Ranocha), direction d.
+template <int DIM>
+__device__ __forceinline__ void ec_flux(const NodeQ<DIM>& L, const NodeQ<DIM>& R, int d, double inv_gm1,
+                                        double* f) {
+  const double rho_ln = log_mean(L.rho, R.rho, L.lrho, R.lrho);
+  const double ibeta_ln = inv_log_mean(L.beta, R.beta, L.lbeta, R.lbeta);
+  double vd = 0.5 * (L.v[d] + R.v[d]);
+  double vv = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) vv += L.v[k] * R.v[k];
+  const double fr = rho_ln * vd;
+  f[0] = fr;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) f[1 + k] = fr * 0.5 * (L.v[k] + R.v[k]);
+  f[1 + d] += 0.5 * (L.p + R.p);
+  f[DIM + 1] = fr * (0.5 * vv + ibeta_ln * inv_gm1) + 0.5 * (L.p * R.v[d] + R.p * L.v[d]);
+}
+
+// HLL flux with Davis wave speeds, normal +e_d from L to R; uL, uR conservative.
+template <int DIM>
+__device__ __forceinline__ void hll_flux(const double* uL, const double* uR, int d, double gamma, double* f) {
+  double rl, vl[DIM], pl, rr, vr[DIM], pr;
+  cons_to_prim<DIM>(uL, gamma, rl, vl, pl);
+  cons_to_prim<DIM>(uR, gamma, rr, vr, pr);
+  const double cl = sqrt(gamma * pl / rl), cr = sqrt(gamma * pr / rr);
+  const double sl = fmin(vl[d] - cl, vr[d] - cr);
+  const double sr = fmax(vl[d] + cl, vr[d] + cr);
+  double fl[DIM + 2], fr[DIM + 2];
+  fl[0] = uL[1 + d];
+  fr[0] = uR[1 + d];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    fl[1 + k] = uL[1 + k] * vl[d];
+    fr[1 + k] = uR[1 + k] * vr[d];
+  }
+  fl[1 + d] += pl;
+  fr[1 + d] += pr;
+  fl[DIM + 1] = (uL[DIM + 1] + pl) * vl[d];
+  fr[DIM + 1] = (uR[DIM + 1] + pr) * vr[d];
+  if (sl >= 0.0) {
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v) f[v] = fl[v];
+  } else if (sr <= 0.0) {
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v) f[v] = fr[v];
+  } else {
+    const double inv = 1.0 / (sr - sl);
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v) f[v] = (sr * fl[v] - sl * fr[v] + sl * sr * (uR[v] - uL[v])) * inv;
+  }
+}
+
+// Stage value of variable v at (slot, node) as seen at this stage (see StageArgs::src).
+__device__ __forceinline__ double stage_value(const StageArgs& a, int src, int64_t idx) {
+  if (src == 0) return a.U[idx];
+  if (src == 1) return a.Yin[idx];
+  return a.U[idx] + a.dt * a.ci * a.K1[idx];
+}
+
+// ------------------------------------------------------------------------------------------
+// Stage kernel (Euler; the Navier-Stokes viscous terms are added by the template flag VISC)
+// ------------------------------------------------------------------------------------------
+template <int DIM, int N, int EPB, bool VISC>
+__global__ __launch_bounds__((EPB * G<DIM, N>::ND)) void k_stage(StageArgs a, Mesh m, Ops op, Physics ph) {
+  using g = G<DIM, N>;
+  constexpr int ND = g::ND, NF = g::NF, NFC = g::NFC, NV = g::NV, NSUB = g::NSUB;
+  __shared__ double s_u[EPB][NV][ND];
+  __shared__ NodeQ<DIM> s_q[EPB][ND];
+  __shared__ double s_f[EPB][NFC][NV][NF];
+  __shared__ double s_t[EPB][NFC][NV][NF];
+
+  const int tid = threadIdx.x;
+  const int le = tid / ND;
+  const int nd = tid - le * ND;
+  const int e = blockIdx.x * EPB + le;
+  const bool act = e < a.n_act;
+  const int ne = m.n_e;
+  const double gamma = ph.gamma;
+  const double inv_gm1 = 1.0 / (gamma - 1.0);
+
+  int my_mem = 0, my_src = 0, my_lev = 0;
+  double J[DIM];
+  double u[NV];
+  if (act) {
+    my_mem = m.mem[e];
+    my_src = a.src[my_mem];
+    my_lev = m.lev[e];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) J[d] = m.jac[my_lev][d];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      u[v] = stage_value(a, my_src, ((int64_t)v * ne + e) * ND + nd);
+      s_u[le][v][nd] = u[v];
+    }
+    NodeQ<DIM> q;
+    cons_to_prim<DIM>(u, gamma, q.rho, q.v, q.p);
+    q.lrho = log(q.rho);
+    q.beta = q.rho / q.p;
+    q.lbeta = log(q.beta);
+    s_q[le][nd] = q;
+    if (nd == 0 && a.counter) atomicAdd(&a.counter[my_mem], 1ull);
+  }
+  __syncthreads();
+
+  double du[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) du[v] = 0.0;
+
+  // ---- volume integral: flux differencing along every coordinate line through the node
+  if (act) {
+    const NodeQ<DIM> qi = s_q[le][nd];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int ia = node_index_dir<DIM, N>(nd, d);
+      const int st = stride_dir<DIM, N>(d);
+      double acc[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+      for (int mm = 0; mm < N; ++mm) {
+        if (mm == ia) continue;
+        const NodeQ<DIM> qm = s_q[le][nd + (mm - ia) * st];
+        double f[NV];
+        ec_flux<DIM>(qi, qm, d, inv_gm1, f);
+        const double c2 = 2.0 * op.D[ia * N + mm];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += c2 * f[v];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) du[v] -= J[d] * acc[v];
+    }
+  }
+
+  // ---- face fluxes of the own faces (each lane handles face-node slots nd, nd+ND, ...)
+  bool has_coarse = false;
+  if (act) {
+    for (int fs = nd; fs < NFC * NF; fs += ND) {
+      const int f = fs / NF, j = fs - f * NF;
+      const int d = f >> 1, s = f & 1;
+      const int32_t pk = m.fk[(int64_t)e * NFC + f];
+      const int kind = face_kind(pk);
+      const int* nbp = m.fn + ((int64_t)e * NFC + f) * 4;
+      double own[NV], oth[NV], fl[NV];
+      const int own_node = face_node<DIM, N>(d, s, j);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) own[v] = s_u[le][v][own_node];
+      if (kind == kConforming) {
+        const int nb = nbp[0];
+        const int src = a.src[m.mem[nb]];
+        const int nn = face_node<DIM, N>(d, 1 - s, j);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) oth[v] = stage_value(a, src, ((int64_t)v * ne + nb) * ND + nn);
+      } else if (kind == kFineSide) {
+        // coarse neighbour trace interpolated to this sub-face
+        const int nb = nbp[0];
+        const int src = a.src[m.mem[nb]];
+        const int s0 = face_sub0(pk), s1 = face_sub1(pk);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) oth[v] = 0.0;
+        if (DIM == 2) {
+#pragma unroll
+          for (int k = 0; k < N; ++k) {
+            const double c = op.P[s0][j * N + k];
+            const int nn = face_node<DIM, N>(d, 1 - s, k);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) oth[v] += c * stage_value(a, src, ((int64_t)v * ne + nb) * ND + nn);
+          }
+        } else {
+          const int ja = j % N, jb = j / N;
+#pragma unroll
+          for (int kb = 0; kb < N; ++kb) {
+            double row[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) row[v] = 0.0;
+#pragma unroll
+            for (int ka = 0; ka < N; ++ka) {
+              const double c = op.P[s0][ja * N + ka];
+              const int nn = face_node<DIM, N>(d, 1 - s, ka + N * kb);
+#pragma unroll
+              for (int v = 0; v < NV; ++v) row[v] += c * stage_value(a, src, ((int64_t)v * ne + nb) * ND + nn);
+            }
+            const double cb = op.P[s1][jb * N + kb];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) oth[v] += cb * row[v];
+          }
+        }
+      }
+      if (kind == kCoarseSide) {
+        has_coarse = true;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s_f[le][f][v][j] = 0.0;
+      } else {
+        if (s == 1) hll_flux<DIM>(own, oth, d, gamma, fl);
+        else hll_flux<DIM>(oth, own, d, gamma, fl);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s_f[le][f][v][j] = fl[v];
+      }
+    }
+  }
+  // coarse sides of mortars: flux on every fine sub-face, projected back with R_m
+  if (__syncthreads_or(has_coarse)) {
+    for (int msub = 0; msub < NSUB; ++msub) {
+      const int m0 = msub & 1, m1 = (msub >> 1) & 1;
+      if (act) {
+        for (int fs = nd; fs < NFC * NF; fs += ND) {
+          const int f = fs / NF, j = fs - f * NF;
+          const int32_t pk = m.fk[(int64_t)e * NFC + f];
+          if (face_kind(pk) != kCoarseSide) continue;
+          const int d = f >> 1, s = f & 1;
+          const int nb = m.fn[((int64_t)e * NFC + f) * 4 + msub];
+          const int src = a.src[m.mem[nb]];
+          double own[NV], oth[NV], fl[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) own[v] = 0.0;
+          if (DIM == 2) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+              const double c = op.P[m0][j * N + k];
+              const int on = face_node<DIM, N>(d, s, k);
+#pragma unroll
+              for (int v = 0; v < NV; ++v) own[v] += c * s_u[le][v][on];
+            }
+          } else {
+            const int ja = j % N, jb = j / N;
+#pragma unroll
+            for (int kb = 0; kb < N; ++kb) {
+              double row[NV];
+#pragma unroll
+              for (int v = 0; v < NV; ++v) row[v] = 0.0;
+#pragma unroll
+              for (int ka = 0; ka < N; ++ka) {
+                const double c = op.P[m0][ja * N + ka];
+                const int on = face_node<DIM, N>(d, s, ka + N * kb);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) row[v] += c * s_u[le][v][on];
+              }
+              const double cb = op.P[m1][jb * N + kb];
+#pragma unroll
+              for (int v = 0; v < NV; ++v) own[v] += cb * row[v];
+            }
+          }
+          const int nn = face_node<DIM, N>(d, 1 - s, j);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) oth[v] = stage_value(a, src, ((int64_t)v * ne + nb) * ND + nn);
+          if (s == 1) hll_flux<DIM>(own, oth, d, gamma, fl);
+          else hll_flux<DIM>(oth, own, d, gamma, fl);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) s_t[le][f][v][j] = fl[v];
+        }
+      }
+      __syncthreads();
+      if (act) {
+        for (int fs = nd; fs < NFC * NF; fs += ND) {
+          const int f = fs / NF, j = fs - f * NF;
+          if (face_kind(m.fk[(int64_t)e * NFC + f]) != kCoarseSide) continue;
+          if (DIM == 2) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              double acc = 0.0;
+#pragma unroll
+              for (int k = 0; k < N; ++k) acc += op.R[m0][j * N + k] * s_t[le][f][v][k];
+              s_f[le][f][v][j] += acc;
+            }
+          } else {
+            const int ja = j % N, jb = j / N;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              double acc = 0.0;
+#pragma unroll
+              for (int kb = 0; kb < N; ++kb) {
+                double row = 0.0;
+#pragma unroll
+                for (int ka = 0; ka < N; ++ka) row += op.R[m0][ja * N + ka] * s_t[le][f][v][ka + N * kb];
+                acc += op.R[m1][jb * N + kb] * row;
+              }
+              s_f[le][f][v][j] += acc;
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+
+  if (!act) return;
+
+  // ---- lifting of the surface fluxes (strong form; boundary nodes only)
+  const double iw0 = 1.0 / op.w[0], iwN = 1.0 / op.w[N - 1];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const int ia = node_index_dir<DIM, N>(nd, d);
+    if (ia == N - 1) {
+      const int fi = face_index<DIM, N>(nd, d);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) du[v] -= J[d] * iwN * s_f[le][2 * d + 1][v][fi];
+    } else if (ia == 0) {
+      const int fi = face_index<DIM, N>(nd, d);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) du[v] += J[d] * iw0 * s_f[le][2 * d][v][fi];
+    }
+  }
+
+  // ---- epilogue: stage combination of the P-ERK tableau (K_i never stored)
+  if (a.Kout) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a.Kout[((int64_t)v * ne + e) * ND + nd] = du[v];
+    return;
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int64_t idx = ((int64_t)v * ne + e) * ND + nd;
+    const double K = du[v];
+    const double Un = a.U[idx];
+    double K1v;
+    if (a.first) {
+      a.K1[idx] = K;
+      K1v = K;
+    } else {
+      K1v = a.K1[idx];
+    }
+    double acc = 0.0;
+    if (a.acc_mode == 1) {
+      acc = a.bi * K;
+      a.ACC[idx] = acc;
+    } else if (a.acc_mode == 2) {
+      acc = a.ACC[idx] + a.bi * K;
+      a.ACC[idx] = acc;
+    }
+    if (a.last) {
+      const double inc = a.use_acc_last ? a.ACC[idx] + a.bS * K : a.bS * K;
+      a.Uout[idx] = Un + a.dt * inc;
+    } else if (a.wr[my_mem]) {
+      a.Yout[idx] = Un + a.dt * (a.a1[my_mem] * K1v + a.a2[my_mem] * K);
+    }
+  }
+}
+
+template <int DIM, int N, bool VISC>
+hipError_t launch_stage_t(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s) {
+  constexpr int ND = G<DIM, N>::ND;
+  constexpr int EPB = (DIM == 2) ? (64 / ND > 0 ? 64 / ND : 1) : 1;
+  if (a.n_act <= 0) return hipSuccess;
+  const int blocks = (a.n_act + EPB - 1) / EPB;
+  hipLaunchKernelGGL((k_stage<DIM, N, EPB, VISC>), dim3(blocks), dim3(EPB * ND), 0, s, a, m, op, ph);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Re-partition (Sec. 6.2): member per leaf, stable counting sort by member (most stage
+// evaluations first), one block of 1024 lanes; ranks inside a chunk from wave ballots.
+// ------------------------------------------------------------------------------------------
+constexpr int kSortThreads = 1024;
+
+__global__ __launch_bounds__(kSortThreads) void k_partition_sort(PartitionArgs a) {
+  __shared__ int s_count[kMaxMembers];
+  __shared__ int s_base[kMaxMembers];
+  __shared__ int s_wave[kMaxMembers][kSortThreads / 64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  if (tid < kMaxMembers) s_count[tid] = 0;
+  __syncthreads();
+  for (int i = tid; i < a.n; i += kSortThreads) {
+    const int mem = a.member_of_level[a.lev_leaf[i]];
+    a.mem_leaf[i] = mem;
+    atomicAdd(&s_count[a.R - 1 - mem], 1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int k = 0; k < a.R; ++k) {
+      s_base[k] = acc;
+      acc += s_count[k];
+      a.counts[a.R - 1 - k] = s_count[k];
+    }
+  }
+  __syncthreads();
+  for (int c0 = 0; c0 < a.n; c0 += kSortThreads) {
+    const int i = c0 + tid;
+    const int key = i < a.n ? a.R - 1 - a.mem_leaf[i] : -1;
+    int my_rank = 0;
+    for (int k = 0; k < a.R; ++k) {
+      const unsigned long long mask = __ballot(key == k);
+      if (lane == 0) s_wave[k][wave] = __popcll(mask);
+      if (key == k) my_rank = __popcll(mask & ((1ull << lane) - 1ull));
+    }
+    __syncthreads();
+    if (key >= 0) {
+      int before = 0;
+      for (int w = 0; w < wave; ++w) before += s_wave[key][w];
+      const int slot = s_base[key] + before + my_rank;
+      a.slot_of_leaf[i] = slot;
+      a.leaf_of_slot[slot] = i;
+    }
+    __syncthreads();
+    if (tid < a.R) {
+      int tot = 0;
+      for (int w = 0; w < kSortThreads / 64; ++w) tot += s_wave[tid][w];
+      s_base[tid] += tot;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_remap(int n, int nfaces, const int32_t* leaf_of_slot, const int32_t* slot_of_leaf,
+                        const int32_t* fk_leaf, const int32_t* fn_leaf, const int32_t* lev_leaf,
+                        const int32_t* mem_leaf, int32_t* fk, int32_t* fn, int32_t* lev, int32_t* mem) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * nfaces) return;
+  const int slot = (int)(t / nfaces), f = (int)(t % nfaces);
+  const int leaf = leaf_of_slot[slot];
+  fk[t] = fk_leaf[(int64_t)leaf * nfaces + f];
+  for (int q = 0; q < 4; ++q) {
+    const int nb = fn_leaf[((int64_t)leaf * nfaces + f) * 4 + q];
+    fn[t * 4 + q] = nb >= 0 ? slot_of_leaf[nb] : -1;
+  }
+  if (f == 0) {
+    lev[slot] = lev_leaf[leaf];
+    mem[slot] = mem_leaf[leaf];
+  }
+}
+
+__global__ void k_permute(int64_t total, int n, int nd, const int32_t* leaf_of_slot, const int32_t* old_slot_of_leaf,
+                          const double* src, double* dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int node = (int)(t % nd);
+  const int64_t r = t / nd;
+  const int slot = (int)(r % n);
+  const int v = (int)(r / n);
+  const int old = old_slot_of_leaf[leaf_of_slot[slot]];
+  dst[t] = src[((int64_t)v * n + old) * nd + node];
+}
+
+__global__ void k_leaf_to_slot(int64_t total, int n, int nv, int nd, const int32_t* leaf_of_slot, const double* src,
+                               double* dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int node = (int)(t % nd);
+  const int64_t r = t / nd;
+  const int slot = (int)(r % n);
+  const int v = (int)(r / n);
+  dst[t] = src[((int64_t)leaf_of_slot[slot] * nv + v) * nd + node];
+}
+
+__global__ void k_slot_to_leaf(int64_t total, int n, int nv, int nd, const int32_t* slot_of_leaf, const double* src,
+                               double* dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int node = (int)(t % nd);
+  const int64_t r = t / nd;
+  const int v = (int)(r % nv);
+  const int leaf = (int)(r / nv);
+  dst[t] = src[((int64_t)v * n + slot_of_leaf[leaf]) * nd + node];
+}
+
+__global__ void k_copy(double* dst, const double* src, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) dst[t] = src[t];
+}
+
+inline unsigned grid_for(int64_t total, int bs) { return (unsigned)((total + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,
+                        const Physics& ph, hipStream_t s) {
+  if (viscous) return hipErrorNotSupported;
+  if (dim == 2 && N == 4) return launch_stage_t<2, 4, false>(a, m, op, ph, s);
+  if (dim == 2 && N == 3) return launch_stage_t<2, 3, false>(a, m, op, ph, s);
+  if (dim == 3 && N == 4) return launch_stage_t<3, 4, false>(a, m, op, ph, s);
+  if (dim == 3 && N == 3) return launch_stage_t<3, 3, false>(a, m, op, ph, s);
+  return hipErrorNotSupported;
+}
+
+hipError_t launch_gradients(int, int, const StageArgs&, const Mesh&, const Ops&, const Physics&, double*,
+                            hipStream_t) {
+  return hipErrorNotSupported;
+}
+
+hipError_t launch_partition_sort(const PartitionArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_partition_sort, dim3(1), dim3(kSortThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_remap_connectivity(int n, int nfaces, const int32_t* leaf_of_slot, const int32_t* slot_of_leaf,
+                                     const int32_t* fk_leaf, const int32_t* fn_leaf, const int32_t* lev_leaf,
+                                     const int32_t* mem_leaf, int32_t* fk, int32_t* fn, int32_t* lev, int32_t* mem,
+                                     hipStream_t s) {
+  const int64_t total = (int64_t)n * nfaces;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_remap, dim3(grid_for(total, 256)), dim3(256), 0, s, n, nfaces, leaf_of_slot, slot_of_leaf,
+                     fk_leaf, fn_leaf, lev_leaf, mem_leaf, fk, fn, lev, mem);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute_state(int n, int nv, int nd, const int32_t* leaf_of_slot, const int32_t* old_slot_of_leaf,
+                                const double* src, double* dst, hipStream_t s) {
+  const int64_t total = (int64_t)n * nv * nd;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_permute, dim3(grid_for(total, 256)), dim3(256), 0, s, total, n, nd, leaf_of_slot,
+                     old_slot_of_leaf, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf_to_slot(int n, int nv, int nd, const int32_t* leaf_of_slot, const double* src, double* dst,
+                               hipStream_t s) {
+  const int64_t total = (int64_t)n * nv * nd;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_leaf_to_slot, dim3(grid_for(total, 256)), dim3(256), 0, s, total, n, nv, nd, leaf_of_slot,
+                     src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_to_leaf(int n, int nv, int nd, const int32_t* slot_of_leaf, const double* src, double* dst,
+                               hipStream_t s) {
+  const int64_t total = (int64_t)n * nv * nd;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slot_to_leaf, dim3(grid_for(total, 256)), dim3(256), 0, s, total, n, nv, nd, slot_of_leaf,
+                     src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+}  // namespace perk

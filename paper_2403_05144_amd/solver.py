@@ -1,0 +1,169 @@
+"""PerkSolver: torch-owned device buffers around one libperk context.
+
+Only argument marshalling and buffer ownership live here; the time step, the right-hand side,
+the re-partition and the state permutations all run in libperk's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class PerkError(RuntimeError):
+    pass
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class PerkSolver:
+    """One partitioned P-ERK + DGSEM simulation on a forest mesh.
+
+    mesh: object with dim, n_root, lo, hi, leaves ([n,4] int32 rows (level, i, j, k)).
+    family: object with order, S, E, c, b, a_sub (shared c, b; a_{i,i-1} per member).
+    member_of_level: int sequence, member index per refinement level (Sec. 6.3.1).
+    """
+
+    def __init__(self, mesh, degree, family, member_of_level, gamma=1.4, equations=0, mu=0.0,
+                 prandtl=0.72, device="cuda"):
+        if not torch.cuda.is_available():
+            raise PerkError("PerkSolver needs a HIP device; there is no CPU path")
+        self.lib = L.lib()
+        self.device = torch.device(device)
+        self.dim = int(mesh.dim)
+        self.degree = int(degree)
+        self.N = self.degree + 1
+        self.nv = self.dim + 2
+        self.Nd = self.N ** self.dim
+        self._ctx = ctypes.c_void_p()
+        phys = L.pe_physics(self.dim, self.degree, int(equations), gamma, mu, prandtl)
+        self._check(self.lib.pe_create(ctypes.byref(self._ctx), ctypes.byref(phys)), "pe_create")
+        self.mesh = mesh
+        self._build_mesh(mesh)
+        self.set_family(family)
+        self._alloc_and_bind()
+        self.partition(member_of_level)
+
+    # ------------------------------------------------------------------ plumbing
+    def _check(self, st, what):
+        if st != L.PE_OK:
+            msg = self.lib.pe_last_error(self._ctx).decode() if self._ctx else ""
+            raise PerkError(f"{what}: {L.STATUS.get(st, st)}: {msg}")
+
+    def __del__(self):
+        try:
+            if self._ctx:
+                self.lib.pe_destroy(self._ctx)
+                self._ctx = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def _build_mesh(self, mesh):
+        leaves = np.ascontiguousarray(np.asarray(mesh.leaves, dtype=np.int32).reshape(-1, 4))
+        self._leaves = leaves
+        nr = list(mesh.n_root) + [1] * (3 - self.dim)
+        lo = list(mesh.lo) + [0.0] * (3 - self.dim)
+        hi = list(mesh.hi) + [1.0] * (3 - self.dim)
+        desc = L.pe_mesh_desc(self.dim, (ctypes.c_int * 3)(*nr), (ctypes.c_double * 3)(*lo),
+                              (ctypes.c_double * 3)(*hi), leaves.shape[0],
+                              leaves.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        self._check(self.lib.pe_mesh_build(self._ctx, ctypes.byref(desc)), "pe_mesh_build")
+        self.n_elements = leaves.shape[0]
+
+    def set_family(self, fam):
+        self.family = fam
+        E = np.ascontiguousarray(np.asarray(fam.E, dtype=np.int32))
+        c = np.ascontiguousarray(np.asarray(fam.c, dtype=np.float64))
+        b = np.ascontiguousarray(np.asarray(fam.b, dtype=np.float64))
+        a = np.ascontiguousarray(np.asarray(fam.a_sub, dtype=np.float64).reshape(len(E), -1))
+        self._coef_keep = (E, c, b, a)
+        co = L.pe_perk_coeffs(int(fam.order), len(E), int(fam.S),
+                              E.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        self._check(self.lib.pe_set_perk_coefficients(self._ctx, ctypes.byref(co)),
+                    "pe_set_perk_coefficients")
+
+    def _alloc_and_bind(self):
+        ns, nw, ne = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.pe_query_sizes(self._ctx, ctypes.byref(ns), ctypes.byref(nw), ctypes.byref(ne)),
+                    "pe_query_sizes")
+        self.u = torch.empty(ns.value, dtype=torch.float64, device=self.device)
+        self.workspace = torch.empty(nw.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self._check(self.lib.pe_bind(self._ctx, ctypes.c_void_p(self.u.data_ptr()), ctypes.c_void_p(aligned),
+                                     _stream_handle()), "pe_bind")
+
+    # ------------------------------------------------------------------ API
+    def partition(self, member_of_level):
+        mol = np.ascontiguousarray(np.asarray(member_of_level, dtype=np.int32))
+        self.member_of_level = mol
+        self._check(self.lib.pe_partition(self._ctx, mol.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                          len(mol), _stream_handle()), "pe_partition")
+
+    def element_info(self):
+        los = np.zeros(self.n_elements, np.int32)
+        mos = np.zeros(self.n_elements, np.int32)
+        self._check(self.lib.pe_element_info(self._ctx, los.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                             mos.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+                    "pe_element_info")
+        return los, mos
+
+    @property
+    def leaf_shape(self):
+        return (self.n_elements, self.nv, self.Nd)
+
+    def node_coords(self):
+        x = torch.empty((self.n_elements, self.dim, self.Nd), dtype=torch.float64, device=self.device)
+        self._check(self.lib.pe_node_coords(self._ctx, ctypes.c_void_p(x.data_ptr()), _stream_handle()),
+                    "pe_node_coords")
+        return x
+
+    def set_state(self, u_leaf):
+        """u_leaf: [n_leaves, n_vars, nodes] (numpy or torch), leaf order of the mesh."""
+        t = torch.as_tensor(u_leaf, dtype=torch.float64).to(self.device).contiguous()
+        if tuple(t.shape) != self.leaf_shape:
+            raise PerkError(f"set_state: shape {tuple(t.shape)} != {self.leaf_shape}")
+        self._check(self.lib.pe_set_state(self._ctx, ctypes.c_void_p(t.data_ptr()), _stream_handle()),
+                    "pe_set_state")
+        torch.cuda.current_stream().synchronize()
+
+    def get_state(self):
+        out = torch.empty(self.leaf_shape, dtype=torch.float64, device=self.device)
+        self._check(self.lib.pe_get_state(self._ctx, ctypes.c_void_p(out.data_ptr()), _stream_handle()),
+                    "pe_get_state")
+        return out
+
+    def step(self, dt, n_steps=1, stream=None):
+        self._check(self.lib.pe_step(self._ctx, float(dt), int(n_steps), _stream_handle(stream)), "pe_step")
+
+    def rhs_slot(self, u_slot):
+        du = torch.empty_like(u_slot)
+        self._check(self.lib.pe_rhs(self._ctx, ctypes.c_void_p(u_slot.data_ptr()), ctypes.c_void_p(du.data_ptr()),
+                                    _stream_handle()), "pe_rhs")
+        return du
+
+    def rhs_leaf(self, u_leaf):
+        """F(u) for a state in leaf layout, returned in leaf layout (uses the bound state buffer)."""
+        saved = self.u.clone()
+        self.set_state(u_leaf)
+        du_slot = self.rhs_slot(self.u)
+        self.u.copy_(du_slot)
+        out = self.get_state()
+        self.u.copy_(saved)
+        return out
+
+    def counters(self, reset=False):
+        tot = ctypes.c_int64()
+        per = (ctypes.c_int64 * 8)()
+        self._check(self.lib.pe_counters(self._ctx, ctypes.byref(tot), per, int(reset), _stream_handle()),
+                    "pe_counters")
+        return tot.value, list(per)[:len(self.family.E)]

@@ -1,0 +1,190 @@
+"""GPU (libperk HIP path) vs oracle parity for 2D Euler: right-hand side, partition, P-ERK steps.
+
+Inputs are seeded and bitwise identical on both sides (the initial state is built once from
+the oracle's node coordinates and handed to both).  Bar: per conserved variable
+||U_gpu - U_oracle||_inf <= 1e-12 ||U_oracle||_inf (fp64).
+"""
+import numpy as np
+import pytest
+
+import perk_inputs as pin
+from oracle import dgsem as od
+from oracle import perk_coeffs as pc
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def rel_err(a, b):
+    """max over variables of ||a_v - b_v||_inf / ||b_v||_inf; arrays [n, nv, nodes]."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    out = 0.0
+    for v in range(b.shape[1]):
+        den = np.max(np.abs(b[:, v]))
+        out = max(out, np.max(np.abs(a[:, v] - b[:, v])) / (den if den > 0 else 1.0))
+    return out
+
+
+def flux_scale(o, u):
+    """Per variable: max over elements of (2/h) times the largest physical-flux component at a
+    node.  The right-hand side is a sum of terms of this size, so its rounding floor is set by
+    it, not by |du| (which can be much smaller where the terms cancel)."""
+    gam = 1.4
+    rho = u[:, 0]
+    vel = u[:, 1:3] / rho[:, None]
+    p = (gam - 1) * (u[:, 3] - 0.5 * rho * np.sum(vel * vel, axis=1))
+    jmax = np.max(2.0 / o.element_sizes(), axis=1)[:, None]
+    out = []
+    for d in range(2):
+        f = [u[:, 1 + d], u[:, 1] * vel[:, d] + (p if d == 0 else 0), u[:, 2] * vel[:, d] + (p if d == 1 else 0),
+             (u[:, 3] + p) * vel[:, d]]
+        out.append([np.max(jmax * np.abs(fv)) for fv in f])
+    return np.max(np.array(out), axis=0)
+
+
+def rhs_err_ok(du_gpu, du_ora, scale, tol=TOL):
+    for v in range(du_ora.shape[1]):
+        ref = max(np.max(np.abs(du_ora[:, v])), scale[v])
+        if np.max(np.abs(du_gpu[:, v] - du_ora[:, v])) > tol * ref:
+            return False
+    return True
+
+
+def _solver(mesh, N, fam, member_of_level):
+    from paper_2403_05144_amd import PerkSolver
+    return PerkSolver(mesh, N - 1, fam, member_of_level)
+
+
+def _vortex_state(o):
+    x = o.node_coords().transpose(1, 0, 2)
+    return pin.isentropic_vortex(x[0], x[1]).transpose(1, 0, 2).copy()
+
+
+def _random_state(o, seed):
+    x = o.node_coords().transpose(1, 0, 2)
+    return pin.smooth_random_state(x, 2, seed).transpose(1, 0, 2).copy()
+
+
+CASES = {
+    "vortex_2level_p3": (lambda: pin.mesh_vortex_2level(), 4, _vortex_state),
+    "vortex_2level_p2": (lambda: pin.mesh_vortex_2level(), 3, _vortex_state),
+    "random_forest_p3": (lambda: pin.random_forest_2d(11, n_root=4, max_level=2), 4, lambda o: _random_state(o, 7)),
+    "random_forest_p2": (lambda: pin.random_forest_2d(5, n_root=3, max_level=3), 3, lambda o: _random_state(o, 8)),
+    "uniform_p3": (lambda: pin.uniform_mesh(2, (5, 3), (-5, -5), (5, 5), 0), 4, lambda o: _random_state(o, 9)),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_rhs_parity(case):
+    mk, N, ic = CASES[case]
+    mesh = mk()
+    o = od.Oracle(mesh, N)
+    u0 = ic(o)
+    fam = pc.perk2_family([4, 8])
+    levels = mesh.leaves[:, 0]
+    mol = od.member_of_levels_paper_rule(np.arange(levels.max() + 1), 2)
+    s = _solver(mesh, N, fam, mol)
+    du_gpu = s.rhs_leaf(u0).cpu().numpy()
+    du_ora = o.rhs(u0)
+    assert rhs_err_ok(du_gpu, du_ora, flux_scale(o, u0)), rel_err(du_gpu, du_ora)
+
+
+@pytest.mark.parametrize("case", ["vortex_2level_p3", "random_forest_p2"])
+def test_partition_is_stable_sort_by_member(case):
+    # Sec. 6.2: elements re-flagged into members; slots sorted finest member first, leaf order
+    # inside a member.  Integer work: bit-exact.
+    mk, N, _ = CASES[case]
+    mesh = mk()
+    levels = mesh.leaves[:, 0]
+    nl = levels.max() + 1
+    fam = pc.perk2_family([2, 4, 8][-min(3, nl):] if nl >= 2 else [8])
+    R = len(fam.E)
+    mol = od.member_of_levels_paper_rule(np.arange(nl), R)
+    s = _solver(mesh, N, fam, mol)
+    leaf_of_slot, mem_of_slot = s.element_info()
+    member = mol[levels]
+    expect = np.argsort(-member, kind="stable")
+    np.testing.assert_array_equal(leaf_of_slot, expect)
+    np.testing.assert_array_equal(mem_of_slot, member[expect])
+
+
+def _stepping_case(order, E_list, mesh, N, u0_fn, dt, n_steps, mol=None):
+    o = od.Oracle(mesh, N)
+    u0 = u0_fn(o)
+    if order == 2:
+        fam = pc.perk2_family(E_list)
+    else:
+        th = np.linspace(0, 2 * np.pi, 200, endpoint=False)
+        eigs = -1.0 + np.exp(1j * th)
+        fam = pc.perk3_family(E_list, {E: pc.optimize_alpha(eigs, 3, E)[1] for E in E_list})
+    levels = mesh.leaves[:, 0]
+    if mol is None:
+        mol = od.member_of_levels_paper_rule(np.arange(levels.max() + 1), len(E_list))
+    s = _solver(mesh, N, fam, mol)
+    s.set_state(u0)
+    member = np.asarray(mol)[levels]
+    u_ora = u0.copy()
+    for _ in range(n_steps):
+        u_ora = o.prk_step(u_ora, dt, fam, member)
+    s.step(dt, n_steps)
+    u_gpu = s.get_state().cpu().numpy()
+    return rel_err(u_gpu, u_ora), s, fam, member
+
+
+@pytest.mark.parametrize("order,E", [(2, [4, 8]), (3, [4, 8]), (2, [8, 16]), (3, [3, 6])])
+def test_step_parity_vortex_2level(order, E):
+    err, *_ = _stepping_case(order, E, pin.mesh_vortex_2level(), 4, _vortex_state, 0.02, 1)
+    assert err <= TOL
+    err, *_ = _stepping_case(order, E, pin.mesh_vortex_2level(), 4, _vortex_state, 0.02, 10)
+    assert err <= TOL
+
+
+def test_step_parity_three_members_random_forest():
+    mesh = pin.random_forest_2d(5, n_root=3, max_level=3)
+    err, *_ = _stepping_case(2, [2, 4, 8], mesh, 3, lambda o: _random_state(o, 3), 0.002, 5)
+    assert err <= TOL
+
+
+def test_step_parity_single_member_uniform():
+    # one member everywhere: the partitioned step is the plain S-stage method
+    mesh = pin.uniform_mesh(2, (6, 6), (-5, -5), (5, 5), 0)
+    err, *_ = _stepping_case(2, [4], mesh, 4, _vortex_state, 0.02, 3, mol=[0])
+    assert err <= TOL
+
+
+def test_rhs_evaluation_counter_matches_formula():
+    # eq. (ActualRHSEvals): element evaluations per step = sum_e E^(member(e))
+    err, s, fam, member = _stepping_case(2, [4, 8], pin.mesh_vortex_2level(), 4, _vortex_state, 0.02, 3)
+    tot, per = s.counters()
+    E = np.asarray(fam.E)
+    assert tot == 3 * int(np.sum(E[member]))
+    for r in range(len(E)):
+        assert per[r] == 3 * E[r] * int(np.sum(member == r))
+    n_vars, nodes = 4, 16
+    assert tot * n_vars * nodes == od.n_rhs_actual([s.mesh.leaves[:, 0]] * 3,
+                                                   lambda lv: np.asarray(s.member_of_level)[lv], E, n_vars, nodes, 1)
+
+
+def test_repartition_permutes_state():
+    # re-flag with a different level map: the bound state follows its leaves
+    mesh = pin.mesh_vortex_2level()
+    o = od.Oracle(mesh, 4)
+    u0 = _vortex_state(o)
+    fam = pc.perk2_family([4, 8])
+    s = _solver(mesh, 4, fam, [0, 1])
+    s.set_state(u0)
+    s.partition([1, 0])
+    np.testing.assert_array_equal(s.get_state().cpu().numpy(), u0)
+    leaf_of_slot, mem = s.element_info()
+    assert np.all(mem[:240] == 1) and np.all(mem[240:] == 0)
+
+
+def test_repeatable_bitwise():
+    # no floating-point atomics: two runs give identical bits (race check)
+    outs = []
+    for _ in range(2):
+        err, s, *_ = _stepping_case(2, [4, 8], pin.mesh_vortex_2level(), 4, _vortex_state, 0.02, 5)
+        outs.append(s.get_state().cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])

@@ -1,0 +1,224 @@
+"""Benchmark of the partitioned P-ERK + DGSEM hot path on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+A step is one P-ERK time step of the whole hot path (every stage's right-hand side on the
+active elements, the stage combinations and the final update; for adaptive workloads also the
+indicator, mesh adaptation and re-partition every N_AMR steps).  Prints one JSON line.
+
+Metric: DoF-updates/s = steps * n_vars * N^d * n_elements / wall time (inputs resident in HBM
+before the timed region).  PID = wall time / N_RHS^Actual (eq. ActualRHSEvals) is reported
+beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------------------------------
+# Workloads
+# ----------------------------------------------------------------------------------------
+def family_for(name, order, E_list, reduced_mesh, degree, ic_fn, h_red):
+    """Coefficients from the project's own optimisation on the spectrum of a reduced mesh
+    (cached as JSON next to the package)."""
+    from paper_2403_05144_amd import PerkSolver, coeffs
+    path = os.path.join(ROOT, "paper_2403_05144_amd", "data", f"{name}.json")
+    if os.path.exists(path):
+        return coeffs.Family.load(path)
+    _log(f"building coefficient family {name} (spectrum of the reduced mesh, LP optimisation)")
+    tmp = coeffs.Family(2, 2, [2], np.array([0.0, 0.5]), np.array([0.0, 1.0]), np.zeros((1, 2)))
+    s = PerkSolver(reduced_mesh, degree, tmp, [0] * (int(reduced_mesh.leaves[:, 0].max()) + 1))
+    x = s.node_coords().cpu().numpy().transpose(1, 0, 2)
+    u = ic_fn(x).transpose(1, 0, 2).copy()
+    lam = coeffs.fd_spectrum(s, u)
+    fam = coeffs.build_family(order, E_list, lam, h_ref=h_red)
+    assert coeffs.check_family(fam)
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    fam.save(path)
+    return fam
+
+
+def member_of_levels(levels, R):
+    """Sec. 6.3.1: finest level -> member R-1, next finer -> R-2, remaining coarse levels -> 0."""
+    Lmax = int(np.max(levels))
+    return [max(0, (R - 1) - (Lmax - l)) for l in range(Lmax + 1)]
+
+
+def stable_dt(fam, mesh, mol, cfl):
+    """dt = cfl * min over members of dt_opt(E_r) * h_min(r) / h_ref (spectra scale with 1/h)."""
+    levels = mesh.leaves[:, 0]
+    h = lambda l: (mesh.hi[0] - mesh.lo[0]) / (mesh.n_root[0] << int(l))
+    dts = []
+    for l in np.unique(levels):
+        r = mol[int(l)]
+        dts.append(fam.dt_opt[r] * h(l) / fam.h_ref)
+    return cfl * min(dts)
+
+
+def wl_vortex_2level():
+    import perk_inputs as pin
+    mesh = pin.mesh_vortex_2level()
+    red = pin.uniform_mesh(2, (4, 4), (-5, -5), (5, 5), 0)
+    ic = lambda x: pin.isentropic_vortex(x[0], x[1])
+    fam = family_for("perk2_4_8_vortex_p3", 2, [4, 8], red, 3, ic, 2.5)
+    mol = member_of_levels(mesh.leaves[:, 0], len(fam.E))
+    return dict(name="vortex_2level", mesh=mesh, degree=3, fam=fam, mol=mol, ic=ic,
+                dt=stable_dt(fam, mesh, mol, 0.9), t_final=1.0,
+                desc="2D Euler isentropic vortex (M=0.5, eps=5) on [-5,5]^2, 16x16 roots with the "
+                     "centred 4x4 block refined once (304 elements, 2 levels), p=3, EC volume + HLL "
+                     "surface flux, P-ERK2{4,8}")
+
+
+WORKLOADS = {"vortex_2level": wl_vortex_2level}
+
+
+# ----------------------------------------------------------------------------------------
+def cpu_baseline(wl, u0_leaf, budget_s=15.0):
+    """The oracle (serial C++, one core) on a bounded number of steps of the same workload."""
+    from oracle import dgsem as od
+    from oracle import perk_coeffs as pc
+    mesh = wl["mesh"]
+    o = od.Oracle(mesh, wl["degree"] + 1)
+    fam = wl["fam"]
+    ofam = pc.PerkFamily(fam.order, fam.S, list(fam.E), np.asarray(fam.c), np.asarray(fam.b),
+                         np.asarray(fam.a_sub))
+    member = np.asarray(wl["mol"])[mesh.leaves[:, 0]]
+    u = np.array(u0_leaf, copy=True)
+    n, t0 = 0, time.perf_counter()
+    while True:
+        u = o.prk_step(u, wl["dt"], ofam, member)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or n >= 1000:
+            break
+    dofs = mesh.n_elements * (mesh.dim + 2) * (wl["degree"] + 1) ** mesh.dim
+    return {"value": n * dofs / el, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} P-ERK steps of the same workload ({el:.1f} s, serial C++ oracle, dense "
+                      f"masked stages: every stage evaluated on every element)"}
+
+
+def flops_per_element_stage(dim, N):
+    """Algorithmic fp64 operations of one element-stage of the stage kernel, counted from its
+    code path (divisions, square roots and logarithms as one operation each):
+    per node and direction (N-1) two-point fluxes of 53 (2D) / 63 (3D) operations plus 2 n_v
+    accumulations; per face node one HLL flux of 95 (2D) / 115 (3D); per node 16 operations for
+    primitives and logarithms and 6 n_v for the stage combination."""
+    nv = dim + 2
+    nd = N ** dim
+    ec = 53 if dim == 2 else 63
+    hll = 95 if dim == 2 else 115
+    per_node = dim * (N - 1) * (ec + 2 * nv) + 16 + 6 * nv
+    return nd * per_node + 2 * dim * N ** (dim - 1) * hll
+
+
+def bytes_per_element_stage(dim, N):
+    """Algorithmic HBM bytes of one element-stage: read the stage value, U_n and K_1 and write
+    the next stage value of the element (4 element slices of n_v N^d fp64)."""
+    return 4 * (dim + 2) * N ** dim * 8
+
+
+def run(args):
+    import torch
+    from paper_2403_05144_amd import PerkSolver
+
+    wl = WORKLOADS[args.workload]()
+    mesh, deg, fam = wl["mesh"], wl["degree"], wl["fam"]
+    N = deg + 1
+    s = PerkSolver(mesh, deg, fam, wl["mol"])
+    x = s.node_coords().cpu().numpy().transpose(1, 0, 2)
+    u0 = wl["ic"](x).transpose(1, 0, 2).copy()
+    s.set_state(u0)
+    dt = wl["dt"]
+    _log(f"workload {wl['name']}: {mesh.n_elements} elements, dt={dt:.5g}, family E={fam.E}")
+    for _ in range(args.warmup):
+        s.step(dt, 1)
+    torch.cuda.synchronize()
+    s.counters(reset=True)
+    s.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.step(dt, 1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms, launches, elem_stages = s.profile_stats()
+    s.set_profiling(False)
+    tot_evals, per_member = s.counters()
+    u_end = s.get_state().cpu().numpy()
+    if not np.all(np.isfinite(u_end)):
+        raise RuntimeError("non-finite state after the timed steps")
+    wall = t1 - t0
+    nv = mesh.dim + 2
+    dofs = mesh.n_elements * nv * N ** mesh.dim
+    value = args.steps * dofs / wall
+    n_rhs_actual = tot_evals * nv * N ** mesh.dim
+    pid = wall / n_rhs_actual
+    avg_launch_s = kern_ms * 1e-3 / max(1, launches)
+    es_per_launch = elem_stages / max(1, launches)
+    B = bytes_per_element_stage(mesh.dim, N) * es_per_launch
+    F = flops_per_element_stage(mesh.dim, N) * es_per_launch
+    gbs = B / avg_launch_s / 1e9
+    tflops = F / avg_launch_s / 1e12
+    frac_b, frac_f = gbs / HBM_PEAK_GBS, tflops / FP64_PEAK_TFLOPS
+    if frac_b >= frac_f:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": frac_b}
+    else:
+        roof = {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": frac_f}
+    roof["traffic"] = None
+    roof["kernel"] = "k_stage"
+    roof["avg_launch_us"] = avg_launch_s * 1e6
+    roof["element_stages_per_launch"] = es_per_launch
+    roof["alt"] = {"hbm_frac": frac_b, "alu_frac": frac_f, "gbs": gbs, "tflops": tflops}
+    line = {
+        "metric": "DoF-updates/s & PID; P-ERK vs single-level RK wall time at equal error",
+        "value": value, "unit": "DoF-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["name"], "description": wl["desc"], "elements": mesh.n_elements,
+                   "degree": deg, "family_E": list(fam.E), "order": fam.order, "dt": dt},
+        "pid_s": pid, "n_rhs_actual": n_rhs_actual,
+        "kernel_time_frac": kern_ms * 1e-3 / wall,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        _log("timing the oracle on the host (cpu_baseline)")
+        line["cpu_baseline"] = cpu_baseline(wl, u0, budget_s=args.cpu_seconds)
+    return line
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="vortex_2level", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU design is "
+              "documented but not built", file=sys.stderr)
+        sys.exit(2)
+    line = run(args)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

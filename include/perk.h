@@ -116,6 +116,11 @@ pe_status pe_set_perk_coefficients(pe_ctx* ctx, const pe_perk_coeffs* coeffs);
 pe_status pe_query_sizes(const pe_ctx* ctx, int64_t* n_state_doubles, int64_t* n_workspace_bytes,
                          int64_t* n_elements);
 
+/* Reserve room for up to max_elements elements (default: the current element count) so that
+ * adaptive meshes keep their buffers: the slot layout then has leading dimension max_elements.
+ * Invalidates any binding: query sizes and bind again. */
+pe_status pe_reserve(pe_ctx* ctx, int64_t max_elements);
+
 /* Bind caller-owned device buffers of the sizes from pe_query_sizes and upload the mesh
  * tables into the workspace on `stream`.  The state content is undefined until
  * pe_set_state. */
@@ -155,6 +160,37 @@ pe_status pe_step(pe_ctx* ctx, double dt, int n_steps, void* stream);
  * n_vars * N^dim gives N_RHS^Actual of eq. (ActualRHSEvals).  reset != 0 zeroes them. */
 pe_status pe_counters(pe_ctx* ctx, int64_t* out_total, int64_t* out_per_member, int reset,
                       void* stream);
+
+/* Refinement indicator per leaf (the adaptive Kelvin-Helmholtz workload's density-gradient
+ * indicator): eta_e = h_e max_nodes |grad rho| / max_nodes rho, h_e the element size in x,
+ * grad rho from the DGSEM derivative matrix.  Written to eta_leaf_host [n_elements] in leaf
+ * order; synchronises `stream`.  (The paper's indicators are cited in Sec. 7; the mesh change
+ * and re-flagging it triggers is Sec. 6.2.) */
+pe_status pe_amr_indicator(pe_ctx* ctx, double* eta_leaf_host, void* stream);
+
+/* Adapt the forest (Sec. 6.2: the mesh change after which the partition is rebuilt).
+ * flags_host[n_elements] in leaf order: +1 refine, -1 coarsen, 0 keep; levels stay in
+ * [level_min, level_max].  Rules: flagged leaves below level_max are refined once; coarser
+ * face neighbours are refined until face neighbours differ by at most one level; a complete
+ * family of 2^dim sibling leaves is coarsened only if all are flagged -1, none was refined,
+ * their level exceeds level_min and no face neighbour outside the family ends finer than the
+ * family's level.  The state is projected on the device (children: interpolation of the
+ * parent polynomial; parents: LGL-quadrature L2 projection of the children, conservative).
+ * The new leaf list is in Morton order (pe_get_leaves).  pe_partition must be called before
+ * the next step.  PE_ENOMEM if the new mesh exceeds the reserved capacity (mesh unchanged). */
+pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags_host, int level_min, int level_max, void* stream);
+
+/* Current leaf list (host) [n][4] (level, i, j, k); leaves may be NULL to query n. */
+pe_status pe_get_leaves(const pe_ctx* ctx, int32_t* leaves, int64_t* n);
+
+/* Time every stage-kernel launch of pe_step with a pair of HIP events recorded on the launch
+ * stream (on != 0), or stop (0).  Switching resets the statistics. */
+pe_status pe_set_profiling(pe_ctx* ctx, int on);
+
+/* Sum of the event-measured durations of the stage kernels launched since profiling was
+ * switched on (milliseconds; waits for the recorded events), the number of launches, and the
+ * number of element-stages (active elements summed over the launches). */
+pe_status pe_profile_stats(pe_ctx* ctx, double* kernel_ms, int64_t* launches, int64_t* element_stages);
 
 #ifdef __cplusplus
 }

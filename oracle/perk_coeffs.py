@@ -197,9 +197,12 @@ def perk2_family(E_list, alphas=None) -> PerkFamily:
 # Third order: nonlinear solve (Sec. 4.3.2).  Unknowns a_{i,i-1} for the E-2 rows
 # i = S-E+3..S; equations: the z^3..z^E coefficients of P from the dense tableau equal
 # (1/6, alpha_4..alpha_E).  The z^3 equation is b_S a_S + b_{S-1} a_{S-1} = 1/6.
-# Positivity 0 < a_i < c_i; random starting points of a trust-region solver.
+# Positivity 0 < a_i < c_i; random starting points of a trust-region solver.  The unknowns are
+# solved for as log a_i (positivity by construction, upper bound log c_i) and every equation
+# is scaled by its target (coefficients of high degree are tiny), i.e. residuals
+# coef_k(a) / alpha_k - 1.
 # ----------------------------------------------------------------------------------------
-def perk3_member(alpha: dict, E: int, S: int, seeds=range(1000), tol=1e-14):
+def perk3_member(alpha: dict, E: int, S: int, seeds=range(200), tol=1e-12):
     from scipy.optimize import least_squares
 
     c = perk3_abscissae(S)
@@ -211,25 +214,25 @@ def perk3_member(alpha: dict, E: int, S: int, seeds=range(1000), tol=1e-14):
         return a
     target = np.array([1.0 / 6.0] + [alpha[k] for k in range(4, E + 1)])
 
-    def full(x):
+    def full(logx):
         a = np.zeros(S)
-        for r, v in zip(rows, x):
+        for r, v in zip(rows, np.exp(logx)):
             a[r - 1] = v
         return a
 
-    def resid(x):
-        coef = stability_poly(dense_A(c, full(x)), b)
-        return coef[3:E + 1] - target
+    def resid(logx):
+        coef = stability_poly(dense_A(c, full(logx)), b)
+        return coef[3:E + 1] / target - 1.0
 
-    lo = np.array([1e-14] * len(rows))
-    hi = np.array([c[r - 1] - 1e-14 for r in rows])
+    hi = np.log(np.array([c[r - 1] for r in rows]))
+    lo = np.full(len(rows), -60.0)
     for seed in seeds:
-        rng = np.random.default_rng(seed)
-        x0 = lo + (hi - lo) * rng.random(len(rows))
+        x0 = hi + np.log(np.random.default_rng(seed).random(len(rows)))
         sol = least_squares(resid, x0, bounds=(lo, hi), xtol=1e-15, ftol=1e-15, gtol=1e-15,
-                            method="trf", max_nfev=20000)
-        if np.max(np.abs(sol.fun)) < tol and np.all(sol.x > 0) and np.all(sol.x < hi + 1e-14):
-            return full(sol.x)
+                            method="trf", max_nfev=2000)
+        a = full(sol.x)
+        if np.max(np.abs(sol.fun)) < tol and all(0 < a[r - 1] < c[r - 1] for r in rows):
+            return a
     raise RuntimeError(f"no positive third-order P-ERK tableau found for E={E}, S={S}")
 
 

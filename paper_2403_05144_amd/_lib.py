@@ -53,6 +53,14 @@ _SIGS = {
     "pe_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_void_p]),
     "pe_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_void_p]),
+    "pe_reserve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "pe_amr_indicator": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "pe_adapt": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int8), ctypes.c_int, ctypes.c_int,
+                                ctypes.c_void_p]),
+    "pe_get_leaves": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
+    "pe_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "pe_profile_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
 }
 
 EXPORTS = tuple(_SIGS)

@@ -35,6 +35,7 @@ struct pe_ctx {
   std::vector<int32_t> leaves;          // [n][4]
   std::vector<int32_t> fk_leaf, fn_leaf, lev_leaf;
   int n_e = 0, max_level = 0;
+  int64_t capacity = 0;                 // reserved elements (leading dimension of the slot layout)
   // coefficients
   bool have_coeffs = false;
   int order = 2, R = 1, S = 1;
@@ -49,14 +50,26 @@ struct pe_ctx {
   int32_t *d_fk = nullptr, *d_fn = nullptr, *d_lev = nullptr, *d_mem = nullptr, *d_mem_leaf = nullptr;
   int32_t *d_slot_of_leaf = nullptr, *d_leaf_of_slot = nullptr, *d_old_slot_of_leaf = nullptr, *d_counts = nullptr;
   int32_t* d_halo = nullptr;
+  int32_t* d_plan = nullptr;            // AMR projection plan [capacity][10]
+  double* d_eta = nullptr;              // AMR indicator per leaf
   unsigned long long* d_counter = nullptr;
   // partition
   bool partitioned = false;
   bool state_valid = false;
+  bool pending_leaf_state = false;      // adapted state waiting in Tmp (leaf layout)
   std::vector<int32_t> counts;          // [R] elements per member
   std::vector<int32_t> leaf_of_slot, slot_of_leaf, mem_of_slot;
   std::vector<int> n_act;               // [S]
+  // optional per-launch timing of the stage kernels with HIP events on the launch stream
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  int64_t prof_launches = 0, prof_elem_stages = 0;
+  double prof_ms = 0.0;
   std::string err;
+  ~pe_ctx() {
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -260,7 +273,8 @@ pe_status build_connectivity(pe_ctx* ctx) {
 
 int nodes_per_elem(const pe_ctx* c) { return c->dim == 2 ? c->N * c->N : c->N * c->N * c->N; }
 int nvars(const pe_ctx* c) { return c->dim + 2; }
-int64_t state_doubles(const pe_ctx* c) { return (int64_t)c->n_e * nvars(c) * nodes_per_elem(c); }
+int64_t cap_of(const pe_ctx* c) { return c->capacity > c->n_e ? c->capacity : c->n_e; }
+int64_t state_doubles(const pe_ctx* c) { return cap_of(c) * nvars(c) * nodes_per_elem(c); }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -274,13 +288,14 @@ size_t workspace_bytes(const pe_ctx* c) {
   tmp.N = c->N;
   tmp.equations = c->equations;
   tmp.n_e = c->n_e;
+  tmp.capacity = c->capacity;
   return carve(&tmp, nullptr);
 }
 
 size_t carve(pe_ctx* c, char* base) {
   size_t off = 0;
   const size_t sd = (size_t)state_doubles(c) * sizeof(double);
-  const int n = c->n_e, nf = 2 * c->dim;
+  const int n = (int)cap_of(c), nf = 2 * c->dim;
   auto take = [&](size_t bytes) -> char* {
     char* p = base ? base + off : nullptr;
     off += align256(bytes);
@@ -307,6 +322,8 @@ size_t carve(pe_ctx* c, char* base) {
   c->d_counts = (int32_t*)take(kMaxMembers * 4);
   c->d_halo = (int32_t*)take((size_t)n * 4 * (kMaxMembers + 1));
   c->d_counter = (unsigned long long*)take(kMaxMembers * 8);
+  c->d_plan = (int32_t*)take((size_t)n * 10 * 4);
+  c->d_eta = (double*)take((size_t)n * 8);
   return off;
 }
 
@@ -316,7 +333,7 @@ Mesh device_mesh(const pe_ctx* c) {
   m.fn = c->d_fn;
   m.lev = c->d_lev;
   m.mem = c->d_mem;
-  m.n_e = c->n_e;
+  m.ld = (int)cap_of(c);
   for (int l = 0; l < kMaxLevels; ++l)
     for (int d = 0; d < 3; ++d) {
       const double h = d < c->dim ? (c->hi[d] - c->lo[d]) / std::ldexp((double)c->n_root[d], l) : 1.0;
@@ -504,6 +521,7 @@ pe_status pe_bind(pe_ctx* ctx, double* u_dev, void* ws, void* stream) {
   HIPCHK(hipMemcpyAsync(ctx->d_fn_leaf, ctx->fn_leaf.data(), (size_t)n * nf * 16, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->d_lev_leaf, ctx->lev_leaf.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(ctx->d_counter, 0, kMaxMembers * 8, s));
+  ctx->pending_leaf_state = false;
   HIPCHK(hipStreamSynchronize(s));
   ctx->bound = true;
   ctx->partitioned = false;
@@ -523,7 +541,7 @@ pe_status pe_partition(pe_ctx* ctx, const int32_t* member_of_level, int n_levels
       return fail(ctx, PE_EINVAL, "member_of_level[%d] = %d outside [0, %d)", l, member_of_level[l], ctx->R);
   hipStream_t s = (hipStream_t)stream;
   const int n = ctx->n_e, nf = 2 * ctx->dim;
-  const bool permute = ctx->state_valid && ctx->partitioned;
+  const bool permute = ctx->state_valid && ctx->partitioned && !ctx->pending_leaf_state;
   if (permute)
     HIPCHK(hipMemcpyAsync(ctx->d_old_slot_of_leaf, ctx->d_slot_of_leaf, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
   pa.lev_leaf = ctx->d_lev_leaf;
@@ -537,9 +555,15 @@ pe_status pe_partition(pe_ctx* ctx, const int32_t* member_of_level, int n_levels
   HIPCHK(launch_remap_connectivity(n, nf, ctx->d_leaf_of_slot, ctx->d_slot_of_leaf, ctx->d_fk_leaf, ctx->d_fn_leaf,
                                    ctx->d_lev_leaf, ctx->d_mem_leaf, ctx->d_fk, ctx->d_fn, ctx->d_lev, ctx->d_mem, s));
   if (permute) {
-    HIPCHK(launch_permute_state(n, nvars(ctx), nodes_per_elem(ctx), ctx->d_leaf_of_slot, ctx->d_old_slot_of_leaf,
-                                ctx->U, ctx->Tmp, s));
+    HIPCHK(launch_permute_state(n, (int)cap_of(ctx), nvars(ctx), nodes_per_elem(ctx), ctx->d_leaf_of_slot,
+                                ctx->d_old_slot_of_leaf, ctx->U, ctx->Tmp, s));
     HIPCHK(launch_copy(ctx->U, ctx->Tmp, state_doubles(ctx), s));
+  }
+  if (ctx->pending_leaf_state) {
+    HIPCHK(launch_leaf_to_slot(n, (int)cap_of(ctx), nvars(ctx), nodes_per_elem(ctx), ctx->d_leaf_of_slot, ctx->Tmp,
+                               ctx->U, s));
+    ctx->pending_leaf_state = false;
+    ctx->state_valid = true;
   }
   ctx->counts.assign(ctx->R, 0);
   ctx->leaf_of_slot.resize(n);
@@ -562,9 +586,10 @@ pe_status pe_set_state(pe_ctx* ctx, const double* u_leaf, void* stream) {
   if (!ctx) return PE_EINVAL;
   if (!ctx->partitioned) return fail(ctx, PE_ESTATE, "set_state before partition");
   if (!u_leaf) return fail(ctx, PE_EINVAL, "set_state: null");
-  HIPCHK(launch_leaf_to_slot(ctx->n_e, nvars(ctx), nodes_per_elem(ctx), ctx->d_leaf_of_slot, u_leaf, ctx->U,
-                             (hipStream_t)stream));
+  HIPCHK(launch_leaf_to_slot(ctx->n_e, (int)cap_of(ctx), nvars(ctx), nodes_per_elem(ctx), ctx->d_leaf_of_slot, u_leaf,
+                             ctx->U, (hipStream_t)stream));
   ctx->state_valid = true;
+  ctx->pending_leaf_state = false;
   return PE_OK;
 }
 
@@ -572,8 +597,8 @@ pe_status pe_get_state(pe_ctx* ctx, double* u_leaf, void* stream) {
   if (!ctx) return PE_EINVAL;
   if (!ctx->partitioned || !ctx->state_valid) return fail(ctx, PE_ESTATE, "get_state without a state");
   if (!u_leaf) return fail(ctx, PE_EINVAL, "get_state: null");
-  HIPCHK(launch_slot_to_leaf(ctx->n_e, nvars(ctx), nodes_per_elem(ctx), ctx->d_slot_of_leaf, ctx->U, u_leaf,
-                             (hipStream_t)stream));
+  HIPCHK(launch_slot_to_leaf(ctx->n_e, (int)cap_of(ctx), nvars(ctx), nodes_per_elem(ctx), ctx->d_slot_of_leaf, ctx->U,
+                             u_leaf, (hipStream_t)stream));
   return PE_OK;
 }
 
@@ -621,6 +646,30 @@ pe_status pe_rhs(pe_ctx* ctx, const double* u, double* du, void* stream) {
   return PE_OK;
 }
 
+namespace {
+pe_status prof_event(pe_ctx* ctx, hipStream_t s) {
+  if (ctx->ev_used == ctx->ev_pool.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    ctx->ev_pool.push_back(e);
+  }
+  HIPCHK(hipEventRecord(ctx->ev_pool[ctx->ev_used++], s));
+  return PE_OK;
+}
+
+// Sum the event pairs recorded so far (waits for them).
+pe_status prof_collect(pe_ctx* ctx) {
+  for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
+    HIPCHK(hipEventSynchronize(ctx->ev_pool[i + 1]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev_pool[i], ctx->ev_pool[i + 1]));
+    ctx->prof_ms += ms;
+  }
+  ctx->ev_used = 0;
+  return PE_OK;
+}
+}  // namespace
+
 pe_status pe_step(pe_ctx* ctx, double dt, int n_steps, void* stream) {
   if (!ctx) return PE_EINVAL;
   if (!ctx->partitioned || !ctx->state_valid) return fail(ctx, PE_ESTATE, "step needs a partition and a state");
@@ -639,10 +688,215 @@ pe_status pe_step(pe_ctx* ctx, double dt, int n_steps, void* stream) {
       a.ACC = ctx->ACC;
       a.Uout = in_place ? ctx->U : ctx->Tmp;
       a.counter = ctx->d_counter;
+      if (ctx->profiling && a.n_act > 0) {
+        pe_status st = prof_event(ctx, s);
+        if (st != PE_OK) return st;
+      }
       HIPCHK(launch_stage(ctx->dim, ctx->N, ctx->equations == 1, a, m, ctx->ops, ctx->ph, s));
+      if (ctx->profiling && a.n_act > 0) {
+        pe_status st = prof_event(ctx, s);
+        if (st != PE_OK) return st;
+        ctx->prof_launches += 1;
+        ctx->prof_elem_stages += a.n_act;
+        if (ctx->ev_used >= 4096) {
+          st = prof_collect(ctx);
+          if (st != PE_OK) return st;
+        }
+      }
     }
     if (!in_place) HIPCHK(launch_copy(ctx->U, ctx->Tmp, state_doubles(ctx), s));
   }
+  return PE_OK;
+}
+
+pe_status pe_reserve(pe_ctx* ctx, int64_t max_elements) {
+  if (!ctx) return PE_EINVAL;
+  if (max_elements < 0 || max_elements > (int64_t)1 << 28) return fail(ctx, PE_EINVAL, "reserve: bad capacity");
+  ctx->capacity = max_elements;
+  ctx->bound = false;
+  ctx->partitioned = false;
+  ctx->state_valid = false;
+  ctx->pending_leaf_state = false;
+  return PE_OK;
+}
+
+pe_status pe_get_leaves(const pe_ctx* ctx, int32_t* leaves, int64_t* n) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->have_mesh) return fail(const_cast<pe_ctx*>(ctx), PE_ESTATE, "get_leaves before mesh_build");
+  if (n) *n = ctx->n_e;
+  if (leaves) std::memcpy(leaves, ctx->leaves.data(), ctx->leaves.size() * 4);
+  return PE_OK;
+}
+
+pe_status pe_amr_indicator(pe_ctx* ctx, double* eta_leaf, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->partitioned || !ctx->state_valid) return fail(ctx, PE_ESTATE, "indicator needs a partition and a state");
+  if (!eta_leaf) return fail(ctx, PE_EINVAL, "indicator: null");
+  hipStream_t s = (hipStream_t)stream;
+  Mesh m = device_mesh(ctx);
+  HIPCHK(launch_indicator(ctx->dim, ctx->N, ctx->n_e, (int)cap_of(ctx), ctx->d_slot_of_leaf, ctx->d_lev_leaf, ctx->U,
+                          ctx->ops, m, ctx->d_eta, s));
+  HIPCHK(hipMemcpyAsync(eta_leaf, ctx->d_eta, (size_t)ctx->n_e * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return PE_OK;
+}
+
+namespace {
+uint64_t morton_key(const int32_t* L, int dim) {
+  const int shift = kMaxLevels - 1 - L[0];
+  uint64_t x[3] = {(uint64_t)L[1] << shift, (uint64_t)L[2] << shift, dim == 3 ? (uint64_t)L[3] << shift : 0};
+  uint64_t key = 0;
+  for (int b = 0; b < 21; ++b)
+    for (int d = 0; d < dim; ++d) key |= ((x[d] >> b) & 1ull) << (dim * b + d);
+  return key;
+}
+}  // namespace
+
+pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags, int level_min, int level_max, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->partitioned || !ctx->state_valid) return fail(ctx, PE_ESTATE, "adapt needs a partition and a state");
+  if (!flags) return fail(ctx, PE_EINVAL, "adapt: null flags");
+  if (level_min < 0 || level_max < level_min || level_max >= kMaxLevels)
+    return fail(ctx, PE_EINVAL, "adapt: bad level range [%d, %d]", level_min, level_max);
+  const int n = ctx->n_e, dim = ctx->dim, nf = 2 * dim, nch = 1 << dim;
+  std::vector<int> lev(n), t(n);
+  for (int e = 0; e < n; ++e) {
+    lev[e] = ctx->leaves[4 * e];
+    t[e] = lev[e] + ((flags[e] > 0 && lev[e] < level_max) ? 1 : 0);
+  }
+  auto for_nbrs = [&](int e, auto&& fn) {
+    for (int f = 0; f < nf; ++f) {
+      const int kind = face_kind(ctx->fk_leaf[(size_t)e * nf + f]);
+      const int cnt = kind == kCoarseSide ? (1 << (dim - 1)) : 1;
+      for (int q = 0; q < cnt; ++q) fn(ctx->fn_leaf[((size_t)e * nf + f) * 4 + q]);
+    }
+  };
+  // 2:1 balance after refinement: face neighbours may differ by at most one target level
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (int e = 0; e < n; ++e)
+      for_nbrs(e, [&](int g) {
+        if (t[e] - t[g] >= 2) {
+          t[g] = lev[g] + 1;
+          changed = true;
+        }
+      });
+  }
+  // coarsening of complete sibling families
+  std::unordered_map<uint64_t, std::vector<int>, KeyHash> fams;
+  for (int e = 0; e < n; ++e) {
+    if (lev[e] <= level_min || flags[e] >= 0 || t[e] != lev[e]) continue;
+    const int32_t* L = &ctx->leaves[4 * e];
+    fams[cell_key(lev[e] - 1, L[1] >> 1, L[2] >> 1, dim == 3 ? (L[3] >> 1) : 0)].push_back(e);
+  }
+  std::vector<int> parent_of(n, -1);   // index of the family's first member for coarsened leaves
+  for (auto& kv : fams) {
+    auto& mem = kv.second;
+    if ((int)mem.size() != nch) continue;
+    bool ok = true;
+    for (int e : mem)
+      for_nbrs(e, [&](int g) {
+        if (std::find(mem.begin(), mem.end(), g) == mem.end() && t[g] > lev[e]) ok = false;
+      });
+    if (!ok) continue;
+    const int first = *std::min_element(mem.begin(), mem.end());
+    for (int e : mem) parent_of[e] = first;
+  }
+  // new leaves with their projection plans
+  struct NewLeaf {
+    std::array<int32_t, 4> L;
+    std::array<int32_t, 10> plan;
+    uint64_t key;
+  };
+  std::vector<NewLeaf> nl;
+  nl.reserve(n * 2);
+  for (int e = 0; e < n; ++e) {
+    const int32_t* L = &ctx->leaves[4 * e];
+    NewLeaf x{};
+    if (parent_of[e] >= 0) {
+      if (parent_of[e] != e) continue;
+      x.L = {lev[e] - 1, L[1] >> 1, L[2] >> 1, dim == 3 ? (L[3] >> 1) : 0};
+      x.plan[0] = 2;
+      for (int g = 0; g < n; ++g)
+        if (parent_of[g] == e) {
+          const int32_t* G = &ctx->leaves[4 * g];
+          const int pos = (G[1] & 1) | ((G[2] & 1) << 1) | (dim == 3 ? ((G[3] & 1) << 2) : 0);
+          x.plan[2 + pos] = g;
+        }
+      nl.push_back(x);
+    } else if (t[e] == lev[e] + 1) {
+      for (int c = 0; c < nch; ++c) {
+        NewLeaf y{};
+        y.L = {lev[e] + 1, 2 * L[1] + (c & 1), 2 * L[2] + ((c >> 1) & 1), dim == 3 ? 2 * L[3] + ((c >> 2) & 1) : 0};
+        y.plan[0] = 1;
+        y.plan[1] = c;
+        y.plan[2] = e;
+        nl.push_back(y);
+      }
+    } else {
+      x.L = {L[0], L[1], L[2], L[3]};
+      x.plan[0] = 0;
+      x.plan[2] = e;
+      nl.push_back(x);
+    }
+  }
+  if ((int64_t)nl.size() > cap_of(ctx))
+    return fail(ctx, PE_ENOMEM, "adapt: %zu elements exceed the reserved capacity %lld", nl.size(),
+                (long long)cap_of(ctx));
+  for (auto& x : nl) x.key = morton_key(x.L.data(), dim);
+  std::sort(nl.begin(), nl.end(), [](const NewLeaf& a, const NewLeaf& b) { return a.key < b.key; });
+  std::vector<int32_t> plan(nl.size() * 10);
+  std::vector<int32_t> leaves(nl.size() * 4);
+  for (size_t i = 0; i < nl.size(); ++i) {
+    std::memcpy(&plan[i * 10], nl[i].plan.data(), 40);
+    std::memcpy(&leaves[i * 4], nl[i].L.data(), 16);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  // project the old state (slot layout, old slot map) onto the new leaves (leaf layout, in Tmp)
+  HIPCHK(hipMemcpyAsync(ctx->d_plan, plan.data(), plan.size() * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_project(dim, ctx->N, (int)nl.size(), (int)cap_of(ctx), ctx->d_plan, ctx->d_slot_of_leaf, ctx->U,
+                        ctx->ops, ctx->Tmp, s));
+  // new forest
+  std::vector<int32_t> old_leaves;
+  old_leaves.swap(ctx->leaves);
+  const int old_n = ctx->n_e;
+  ctx->leaves.swap(leaves);
+  ctx->n_e = (int)nl.size();
+  pe_status st = build_connectivity(ctx);
+  if (st != PE_OK) {
+    ctx->leaves.swap(old_leaves);
+    ctx->n_e = old_n;
+    build_connectivity(ctx);
+    return st;
+  }
+  const int nn = ctx->n_e;
+  HIPCHK(hipMemcpyAsync(ctx->d_fk_leaf, ctx->fk_leaf.data(), (size_t)nn * nf * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->d_fn_leaf, ctx->fn_leaf.data(), (size_t)nn * nf * 16, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->d_lev_leaf, ctx->lev_leaf.data(), (size_t)nn * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  ctx->partitioned = false;
+  ctx->state_valid = false;
+  ctx->pending_leaf_state = true;
+  return PE_OK;
+}
+
+pe_status pe_set_profiling(pe_ctx* ctx, int on) {
+  if (!ctx) return PE_EINVAL;
+  ctx->profiling = on != 0;
+  ctx->ev_used = 0;
+  ctx->prof_ms = 0.0;
+  ctx->prof_launches = 0;
+  ctx->prof_elem_stages = 0;
+  return PE_OK;
+}
+
+pe_status pe_profile_stats(pe_ctx* ctx, double* kernel_ms, int64_t* launches, int64_t* element_stages) {
+  if (!ctx) return PE_EINVAL;
+  pe_status st = prof_collect(ctx);
+  if (st != PE_OK) return st;
+  if (kernel_ms) *kernel_ms = ctx->prof_ms;
+  if (launches) *launches = ctx->prof_launches;
+  if (element_stages) *element_stages = ctx->prof_elem_stages;
   return PE_OK;
 }
 

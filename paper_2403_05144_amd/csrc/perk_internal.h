@@ -42,7 +42,7 @@ struct Mesh {
   const int32_t* fn;      // [slot][2 dim][4] neighbour slots
   const int32_t* lev;     // [slot] refinement level
   const int32_t* mem;     // [slot] P-ERK member
-  int n_e;                // number of slots (stride of the slot layout)
+  int ld;                 // leading dimension of the slot layout (reserved capacity)
   double jac[kMaxLevels][3];   // 2 / h per level and direction
 };
 
@@ -97,14 +97,25 @@ hipError_t launch_remap_connectivity(int n, int nfaces, const int32_t* leaf_of_s
                                      const int32_t* fk_leaf, const int32_t* fn_leaf, const int32_t* lev_leaf,
                                      const int32_t* mem_leaf, int32_t* fk, int32_t* fn, int32_t* lev, int32_t* mem,
                                      hipStream_t s);
-// dst[v][slot][node] = src[v][old_slot_of_leaf[leaf_of_slot[slot]]][node]
-hipError_t launch_permute_state(int n, int nv, int nd, const int32_t* leaf_of_slot, const int32_t* old_slot_of_leaf,
-                                const double* src, double* dst, hipStream_t s);
-// leaf layout <-> slot layout
-hipError_t launch_leaf_to_slot(int n, int nv, int nd, const int32_t* leaf_of_slot, const double* src, double* dst,
-                               hipStream_t s);
-hipError_t launch_slot_to_leaf(int n, int nv, int nd, const int32_t* slot_of_leaf, const double* src, double* dst,
-                               hipStream_t s);
+// dst[v][slot][node] = src[v][old_slot_of_leaf[leaf_of_slot[slot]]][node]; both with stride ld
+hipError_t launch_permute_state(int n, int ld, int nv, int nd, const int32_t* leaf_of_slot,
+                                const int32_t* old_slot_of_leaf, const double* src, double* dst, hipStream_t s);
+// leaf layout [leaf][v][node] <-> slot layout [v][slot (stride ld)][node]
+hipError_t launch_leaf_to_slot(int n, int ld, int nv, int nd, const int32_t* leaf_of_slot, const double* src,
+                               double* dst, hipStream_t s);
+hipError_t launch_slot_to_leaf(int n, int ld, int nv, int nd, const int32_t* slot_of_leaf, const double* src,
+                               double* dst, hipStream_t s);
+
+// AMR indicator per leaf: eta = h max_nodes |grad rho| / max_nodes rho (h = element size in x).
+hipError_t launch_indicator(int dim, int N, int n, int ld, const int32_t* slot_of_leaf, const int32_t* lev_leaf,
+                            const double* U, const Ops& op, const Mesh& m, double* eta_leaf, hipStream_t s);
+
+// Projection of the state onto an adapted forest.  plan[new][10]: kind (0 copy, 1 child of a
+// refined leaf, 2 parent of coarsened leaves), child position bits (kind 1), then the old leaf
+// (kind 0/1) or the 2^dim old children ordered by child position (kind 2).  Reads the old state
+// in slot layout through old_slot_of_leaf, writes the new state in leaf layout.
+hipError_t launch_project(int dim, int N, int n_new, int ld, const int32_t* plan, const int32_t* old_slot_of_leaf,
+                          const double* U_old, const Ops& op, double* dst_leaf, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 
 }  // namespace perk

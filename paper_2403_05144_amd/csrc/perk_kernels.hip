@@ -192,7 +192,7 @@ __global__ __launch_bounds__((EPB * G<DIM, N>::ND)) void k_stage(StageArgs a, Me
   const int nd = tid - le * ND;
   const int e = blockIdx.x * EPB + le;
   const bool act = e < a.n_act;
-  const int ne = m.n_e;
+  const int ne = m.ld;
   const double gamma = ph.gamma;
   const double inv_gm1 = 1.0 / (gamma - 1.0);
 
@@ -538,8 +538,8 @@ __global__ void k_remap(int n, int nfaces, const int32_t* leaf_of_slot, const in
   }
 }
 
-__global__ void k_permute(int64_t total, int n, int nd, const int32_t* leaf_of_slot, const int32_t* old_slot_of_leaf,
-                          const double* src, double* dst) {
+__global__ void k_permute(int64_t total, int n, int ld, int nd, const int32_t* leaf_of_slot,
+                          const int32_t* old_slot_of_leaf, const double* src, double* dst) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total) return;
   const int node = (int)(t % nd);
@@ -547,29 +547,106 @@ __global__ void k_permute(int64_t total, int n, int nd, const int32_t* leaf_of_s
   const int slot = (int)(r % n);
   const int v = (int)(r / n);
   const int old = old_slot_of_leaf[leaf_of_slot[slot]];
-  dst[t] = src[((int64_t)v * n + old) * nd + node];
+  dst[((int64_t)v * ld + slot) * nd + node] = src[((int64_t)v * ld + old) * nd + node];
 }
 
-__global__ void k_leaf_to_slot(int64_t total, int n, int nv, int nd, const int32_t* leaf_of_slot, const double* src,
-                               double* dst) {
+__global__ void k_leaf_to_slot(int64_t total, int n, int ld, int nv, int nd, const int32_t* leaf_of_slot,
+                               const double* src, double* dst) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total) return;
   const int node = (int)(t % nd);
   const int64_t r = t / nd;
   const int slot = (int)(r % n);
   const int v = (int)(r / n);
-  dst[t] = src[((int64_t)leaf_of_slot[slot] * nv + v) * nd + node];
+  dst[((int64_t)v * ld + slot) * nd + node] = src[((int64_t)leaf_of_slot[slot] * nv + v) * nd + node];
 }
 
-__global__ void k_slot_to_leaf(int64_t total, int n, int nv, int nd, const int32_t* slot_of_leaf, const double* src,
-                               double* dst) {
+__global__ void k_slot_to_leaf(int64_t total, int ld, int nv, int nd, const int32_t* slot_of_leaf,
+                               const double* src, double* dst) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total) return;
   const int node = (int)(t % nd);
   const int64_t r = t / nd;
   const int v = (int)(r % nv);
   const int leaf = (int)(r / nv);
-  dst[t] = src[((int64_t)v * n + slot_of_leaf[leaf]) * nd + node];
+  dst[t] = src[((int64_t)v * ld + slot_of_leaf[leaf]) * nd + node];
+}
+
+// eta = h max |grad rho| / max rho over the nodes of one leaf; one lane per leaf.
+template <int DIM, int N>
+__global__ void k_indicator(int n, int ld, const int32_t* slot_of_leaf, const int32_t* lev_leaf, const double* U,
+                            Ops op, Mesh m, double* eta) {
+  constexpr int ND = G<DIM, N>::ND;
+  const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
+  if (leaf >= n) return;
+  const int slot = slot_of_leaf[leaf];
+  const int lev = lev_leaf[leaf];
+  const double* rho = U + (int64_t)slot * ND;     // variable 0
+  double rmax = 0.0, gmax = 0.0;
+  for (int nd = 0; nd < ND; ++nd) {
+    rmax = fmax(rmax, rho[nd]);
+    double g2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int ia = node_index_dir<DIM, N>(nd, d);
+      const int st = stride_dir<DIM, N>(d);
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < N; ++q) acc += op.D[ia * N + q] * rho[nd + (q - ia) * st];
+      const double gd = m.jac[lev][d] * acc;
+      g2 += gd * gd;
+    }
+    gmax = fmax(gmax, sqrt(g2));
+  }
+  const double h = 2.0 / m.jac[lev][0];
+  eta[leaf] = h * gmax / rmax;
+}
+
+// one lane per (new leaf, variable, node)
+template <int DIM, int N>
+__global__ void k_project(int64_t total, int ld, const int32_t* plan, const int32_t* old_slot_of_leaf,
+                          const double* U, Ops op, double* dst) {
+  constexpr int ND = G<DIM, N>::ND, NV = DIM + 2;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int node = (int)(t % ND);
+  const int64_t r = t / ND;
+  const int v = (int)(r % NV);
+  const int leaf = (int)(r / NV);
+  const int32_t* pl = plan + (int64_t)leaf * 10;
+  const int kind = pl[0];
+  int j[3] = {node % N, (node / N) % N, DIM == 3 ? node / (N * N) : 0};
+  double val = 0.0;
+  if (kind == 0) {
+    const int slot = old_slot_of_leaf[pl[2]];
+    val = U[((int64_t)v * ld + slot) * ND + node];
+  } else if (kind == 1) {
+    // child of a refined leaf: tensor-product interpolation of the parent polynomial
+    const int pos = pl[1];
+    const int slot = old_slot_of_leaf[pl[2]];
+    const double* src = U + ((int64_t)v * ld + slot) * ND;
+    for (int q = 0; q < ND; ++q) {
+      const int k[3] = {q % N, (q / N) % N, DIM == 3 ? q / (N * N) : 0};
+      double w = 1.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) w *= op.P[(pos >> d) & 1][j[d] * N + k[d]];
+      val += w * src[q];
+    }
+  } else {
+    // parent of a coarsened family: LGL-quadrature L2 projection of the children
+    for (int c = 0; c < (1 << DIM); ++c) {
+      const int slot = old_slot_of_leaf[pl[2 + c]];
+      const double* src = U + ((int64_t)v * ld + slot) * ND;
+      for (int q = 0; q < ND; ++q) {
+        const int k[3] = {q % N, (q / N) % N, DIM == 3 ? q / (N * N) : 0};
+        double w = 1.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) w *= op.R[(c >> d) & 1][j[d] * N + k[d]];
+        val += w * src[q];
+      }
+    }
+  }
+  dst[t] = val;
 }
 
 __global__ void k_copy(double* dst, const double* src, int64_t n) {
@@ -612,30 +689,56 @@ hipError_t launch_remap_connectivity(int n, int nfaces, const int32_t* leaf_of_s
   return hipGetLastError();
 }
 
-hipError_t launch_permute_state(int n, int nv, int nd, const int32_t* leaf_of_slot, const int32_t* old_slot_of_leaf,
-                                const double* src, double* dst, hipStream_t s) {
+hipError_t launch_permute_state(int n, int ld, int nv, int nd, const int32_t* leaf_of_slot,
+                                const int32_t* old_slot_of_leaf, const double* src, double* dst, hipStream_t s) {
   const int64_t total = (int64_t)n * nv * nd;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_permute, dim3(grid_for(total, 256)), dim3(256), 0, s, total, n, nd, leaf_of_slot,
+  hipLaunchKernelGGL(k_permute, dim3(grid_for(total, 256)), dim3(256), 0, s, total, n, ld, nd, leaf_of_slot,
                      old_slot_of_leaf, src, dst);
   return hipGetLastError();
 }
 
-hipError_t launch_leaf_to_slot(int n, int nv, int nd, const int32_t* leaf_of_slot, const double* src, double* dst,
-                               hipStream_t s) {
+hipError_t launch_leaf_to_slot(int n, int ld, int nv, int nd, const int32_t* leaf_of_slot, const double* src,
+                               double* dst, hipStream_t s) {
   const int64_t total = (int64_t)n * nv * nd;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_leaf_to_slot, dim3(grid_for(total, 256)), dim3(256), 0, s, total, n, nv, nd, leaf_of_slot,
+  hipLaunchKernelGGL(k_leaf_to_slot, dim3(grid_for(total, 256)), dim3(256), 0, s, total, n, ld, nv, nd,
+                     leaf_of_slot, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_to_leaf(int n, int ld, int nv, int nd, const int32_t* slot_of_leaf, const double* src,
+                               double* dst, hipStream_t s) {
+  const int64_t total = (int64_t)n * nv * nd;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slot_to_leaf, dim3(grid_for(total, 256)), dim3(256), 0, s, total, ld, nv, nd, slot_of_leaf,
                      src, dst);
   return hipGetLastError();
 }
 
-hipError_t launch_slot_to_leaf(int n, int nv, int nd, const int32_t* slot_of_leaf, const double* src, double* dst,
-                               hipStream_t s) {
-  const int64_t total = (int64_t)n * nv * nd;
+hipError_t launch_indicator(int dim, int N, int n, int ld, const int32_t* slot_of_leaf, const int32_t* lev_leaf,
+                            const double* U, const Ops& op, const Mesh& m, double* eta, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const dim3 g(grid_for(n, 128)), b(128);
+  if (dim == 2 && N == 4) hipLaunchKernelGGL((k_indicator<2, 4>), g, b, 0, s, n, ld, slot_of_leaf, lev_leaf, U, op, m, eta);
+  else if (dim == 2 && N == 3) hipLaunchKernelGGL((k_indicator<2, 3>), g, b, 0, s, n, ld, slot_of_leaf, lev_leaf, U, op, m, eta);
+  else if (dim == 3 && N == 4) hipLaunchKernelGGL((k_indicator<3, 4>), g, b, 0, s, n, ld, slot_of_leaf, lev_leaf, U, op, m, eta);
+  else if (dim == 3 && N == 3) hipLaunchKernelGGL((k_indicator<3, 3>), g, b, 0, s, n, ld, slot_of_leaf, lev_leaf, U, op, m, eta);
+  else return hipErrorNotSupported;
+  return hipGetLastError();
+}
+
+hipError_t launch_project(int dim, int N, int n_new, int ld, const int32_t* plan, const int32_t* old_slot_of_leaf,
+                          const double* U_old, const Ops& op, double* dst, hipStream_t s) {
+  const int nd = dim == 2 ? N * N : N * N * N;
+  const int64_t total = (int64_t)n_new * (dim + 2) * nd;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_slot_to_leaf, dim3(grid_for(total, 256)), dim3(256), 0, s, total, n, nv, nd, slot_of_leaf,
-                     src, dst);
+  const dim3 g(grid_for(total, 256)), b(256);
+  if (dim == 2 && N == 4) hipLaunchKernelGGL((k_project<2, 4>), g, b, 0, s, total, ld, plan, old_slot_of_leaf, U_old, op, dst);
+  else if (dim == 2 && N == 3) hipLaunchKernelGGL((k_project<2, 3>), g, b, 0, s, total, ld, plan, old_slot_of_leaf, U_old, op, dst);
+  else if (dim == 3 && N == 4) hipLaunchKernelGGL((k_project<3, 4>), g, b, 0, s, total, ld, plan, old_slot_of_leaf, U_old, op, dst);
+  else if (dim == 3 && N == 3) hipLaunchKernelGGL((k_project<3, 3>), g, b, 0, s, total, ld, plan, old_slot_of_leaf, U_old, op, dst);
+  else return hipErrorNotSupported;
   return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ class PerkSolver:
     """
 
     def __init__(self, mesh, degree, family, member_of_level, gamma=1.4, equations=0, mu=0.0,
-                 prandtl=0.72, device="cuda"):
+                 prandtl=0.72, device="cuda", capacity=None):
         if not torch.cuda.is_available():
             raise PerkError("PerkSolver needs a HIP device; there is no CPU path")
         self.lib = L.lib()
@@ -47,6 +47,8 @@ class PerkSolver:
         self.mesh = mesh
         self._build_mesh(mesh)
         self.set_family(family)
+        self.capacity = int(capacity) if capacity else self.n_elements
+        self._check(self.lib.pe_reserve(self._ctx, self.capacity), "pe_reserve")
         self._alloc_and_bind()
         self.partition(member_of_level)
 
@@ -160,6 +162,41 @@ class PerkSolver:
         out = self.get_state()
         self.u.copy_(saved)
         return out
+
+    def leaves(self):
+        n = ctypes.c_int64()
+        self._check(self.lib.pe_get_leaves(self._ctx, None, ctypes.byref(n)), "pe_get_leaves")
+        out = np.zeros((n.value, 4), np.int32)
+        self._check(self.lib.pe_get_leaves(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                           ctypes.byref(n)), "pe_get_leaves")
+        return out
+
+    def indicator(self):
+        eta = np.zeros(self.n_elements)
+        self._check(self.lib.pe_amr_indicator(self._ctx, eta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              _stream_handle()), "pe_amr_indicator")
+        return eta
+
+    def adapt(self, flags, level_min, level_max, member_of_level):
+        """Adapt the forest with per-leaf flags, project the state, re-partition."""
+        f = np.ascontiguousarray(np.asarray(flags, dtype=np.int8))
+        if f.shape != (self.n_elements,):
+            raise PerkError("adapt: one flag per leaf")
+        self._check(self.lib.pe_adapt(self._ctx, f.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), int(level_min),
+                                      int(level_max), _stream_handle()), "pe_adapt")
+        self._leaves = self.leaves()
+        self.n_elements = self._leaves.shape[0]
+        self.mesh.leaves = self._leaves
+        self.partition(member_of_level)
+
+    def set_profiling(self, on):
+        self._check(self.lib.pe_set_profiling(self._ctx, int(bool(on))), "pe_set_profiling")
+
+    def profile_stats(self):
+        ms, nl, es = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.pe_profile_stats(self._ctx, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(es)),
+                    "pe_profile_stats")
+        return ms.value, nl.value, es.value
 
     def counters(self, reset=False):
         tot = ctypes.c_int64()

@@ -47,9 +47,7 @@ def family_for(name, order, E_list, reduced_mesh, degree, ic_fn, h_red):
     s = PerkSolver(reduced_mesh, degree, tmp, [0] * (int(reduced_mesh.leaves[:, 0].max()) + 1))
     x = s.node_coords().cpu().numpy().transpose(1, 0, 2)
     u = ic_fn(x).transpose(1, 0, 2).copy()
-    lam = coeffs.fd_spectrum(s, u)
-    fam = coeffs.build_family(order, E_list, lam, h_ref=h_red)
-    assert coeffs.check_family(fam)
+    fam, lam = coeffs.family_from_solver_spectrum(s, u, order, E_list, h_red)
     os.makedirs(os.path.dirname(path), exist_ok=True)
     fam.save(path)
     return fam
@@ -86,15 +84,42 @@ def wl_vortex_2level():
                      "surface flux, P-ERK2{4,8}")
 
 
-WORKLOADS = {"vortex_2level": wl_vortex_2level}
+def wl_kh_amr(n_root=8, level_max=3, name="kh_amr_l3-6"):
+    """Kelvin-Helmholtz shear layer, quadtree AMR between config levels 3 and 6 (forest levels
+    0..3 on 8x8 roots), P-ERK3{4,6,8,12,16}, adaptation every 10 steps."""
+    import perk_inputs as pin
+    from paper_2403_05144_amd import partition_rule
+    mesh = pin.uniform_mesh(2, (n_root, n_root), (-1, -1), (1, 1), 0)
+    ic = lambda x: pin.kelvin_helmholtz(x[0], x[1])
+    h_red = 2.0 / n_root
+    fam = family_for(f"perk3_4_6_8_12_16_kh_p3_n{n_root}", 3, [4, 6, 8, 12, 16],
+                     pin.uniform_mesh(2, (n_root, n_root), (-1, -1), (1, 1), 0), 3, ic, h_red)
+    mol = partition_rule.required_dt_rule(level_max, fam.dt_opt, fam.E)
+    h_min = h_red / 2 ** level_max
+    dt = 0.5 * fam.dt_opt[-1] * h_min / fam.h_ref
+    return dict(name=name, mesh=mesh, degree=3, fam=fam, mol=mol, ic=ic, dt=dt, t_final=3.0,
+                amr=dict(level_min=0, level_max=level_max, interval=10, refine_above=0.05, coarsen_below=0.01,
+                         capacity=(n_root << level_max) ** 2),
+                desc=f"2D Euler Kelvin-Helmholtz shear layer on [-1,1]^2 (rho 0.5/1, v_x +-0.5, tanh width "
+                     f"0.05, seeded v_y perturbation 0.01), p=3, EC volume + HLL surface flux, quadtree AMR on "
+                     f"a density-gradient indicator between levels {int(np.log2(n_root))} and "
+                     f"{int(np.log2(n_root)) + level_max} every 10 steps with re-partition after every "
+                     f"adaptation, P-ERK3{{4,6,8,12,16}} at 50% of the optimised step (largest of 0.3/0.5/0.7 without blow-up)")
+
+
+WORKLOADS = {"vortex_2level": wl_vortex_2level, "kh_amr": wl_kh_amr,
+             "kh_amr_l4-7": lambda: wl_kh_amr(16, 3, "kh_amr_l4-7")}
 
 
 # ----------------------------------------------------------------------------------------
-def cpu_baseline(wl, u0_leaf, budget_s=15.0):
-    """The oracle (serial C++, one core) on a bounded number of steps of the same workload."""
+def cpu_baseline(wl, u0_leaf, leaves0, budget_s=15.0):
+    """The oracle (serial C++, one core) on a bounded number of steps of the same workload
+    (the starting mesh; no adaptation inside the sample)."""
+    import perk_inputs as pin
     from oracle import dgsem as od
     from oracle import perk_coeffs as pc
-    mesh = wl["mesh"]
+    m0 = wl["mesh"]
+    mesh = pin.MeshDesc(m0.dim, m0.n_root, m0.lo, m0.hi, leaves0)
     o = od.Oracle(mesh, wl["degree"] + 1)
     fam = wl["fam"]
     ofam = pc.PerkFamily(fam.order, fam.S, list(fam.E), np.asarray(fam.c), np.asarray(fam.b),
@@ -138,24 +163,45 @@ def run(args):
     import torch
     from paper_2403_05144_amd import PerkSolver
 
+    from paper_2403_05144_amd.amr import AmrDriver
+
     wl = WORKLOADS[args.workload]()
     mesh, deg, fam = wl["mesh"], wl["degree"], wl["fam"]
     N = deg + 1
-    s = PerkSolver(mesh, deg, fam, wl["mol"])
-    x = s.node_coords().cpu().numpy().transpose(1, 0, 2)
-    u0 = wl["ic"](x).transpose(1, 0, 2).copy()
-    s.set_state(u0)
+    amr = wl.get("amr")
+    s = PerkSolver(mesh, deg, fam, wl["mol"], capacity=amr["capacity"] if amr else None)
+    ic_leaf = lambda x: wl["ic"](x.transpose(1, 0, 2)).transpose(1, 0, 2).copy()
+    drv = None
+    if amr:
+        drv = AmrDriver(s, amr["level_min"], amr["level_max"], wl["mol"], amr["refine_above"],
+                        amr["coarsen_below"], amr["interval"])
+        drv.initial_mesh(ic_leaf, passes=3)
+    else:
+        s.set_state(ic_leaf(s.node_coords().cpu().numpy()))
+    u0 = s.get_state().cpu().numpy()
+    leaves0 = s.leaves().copy()
     dt = wl["dt"]
-    _log(f"workload {wl['name']}: {mesh.n_elements} elements, dt={dt:.5g}, family E={fam.E}")
-    for _ in range(args.warmup):
+    _log(f"workload {wl['name']}: {s.n_elements} elements, dt={dt:.5g}, family E={fam.E}, members/level {wl['mol']}")
+    dof_updates = [0]
+    per_elem = (mesh.dim + 2) * N ** mesh.dim
+
+    def count(_k):
+        dof_updates[0] += s.n_elements * per_elem
+
+    for k in range(args.warmup):
         s.step(dt, 1)
     torch.cuda.synchronize()
     s.counters(reset=True)
     s.set_profiling(True)
+    n_adapt0 = drv.n_adapt if drv else 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s.step(dt, 1)
+    if drv:
+        drv.run(dt, args.steps, on_step=count)
+    else:
+        for _ in range(args.steps):
+            s.step(dt, 1)
+            count(0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kern_ms, launches, elem_stages = s.profile_stats()
@@ -166,8 +212,7 @@ def run(args):
         raise RuntimeError("non-finite state after the timed steps")
     wall = t1 - t0
     nv = mesh.dim + 2
-    dofs = mesh.n_elements * nv * N ** mesh.dim
-    value = args.steps * dofs / wall
+    value = dof_updates[0] / wall
     n_rhs_actual = tot_evals * nv * N ** mesh.dim
     pid = wall / n_rhs_actual
     avg_launch_s = kern_ms * 1e-3 / max(1, launches)
@@ -191,15 +236,17 @@ def run(args):
         "value": value, "unit": "DoF-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": wl["name"], "description": wl["desc"], "elements": mesh.n_elements,
-                   "degree": deg, "family_E": list(fam.E), "order": fam.order, "dt": dt},
+        "config": {"workload": wl["name"], "description": wl["desc"], "elements_start": int(leaves0.shape[0]),
+                   "elements_end": int(s.n_elements), "degree": deg, "family_E": list(fam.E), "order": fam.order,
+                   "dt": dt, "member_of_level": [int(m) for m in wl["mol"]],
+                   "adaptations_timed": (drv.n_adapt - n_adapt0) if drv else 0},
         "pid_s": pid, "n_rhs_actual": n_rhs_actual,
         "kernel_time_frac": kern_ms * 1e-3 / wall,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
         _log("timing the oracle on the host (cpu_baseline)")
-        line["cpu_baseline"] = cpu_baseline(wl, u0, budget_s=args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(wl, u0, leaves0, budget_s=args.cpu_seconds)
     return line
 
 
@@ -208,7 +255,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="vortex_2level", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="kh_amr", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()

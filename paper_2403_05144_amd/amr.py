@@ -1,0 +1,48 @@
+"""Adaptive-mesh driver around PerkSolver: indicator thresholds -> per-leaf flags -> device
+adaptation and re-partition (Sec. 6.2: the partition is rebuilt after every mesh change).
+
+The indicator itself, the adaptation with 2:1 balance, the projection and the re-partition run
+in libperk; this module only turns indicator values into flags and schedules the calls.
+"""
+import numpy as np
+
+
+def flags_from_indicator(eta, refine_above, coarsen_below):
+    f = np.zeros(len(eta), np.int8)
+    f[np.asarray(eta) > refine_above] = 1
+    f[np.asarray(eta) < coarsen_below] = -1
+    return f
+
+
+class AmrDriver:
+    def __init__(self, solver, level_min, level_max, member_of_level, refine_above=0.05, coarsen_below=0.01,
+                 interval=10):
+        self.s = solver
+        self.level_min, self.level_max = level_min, level_max
+        self.member_of_level = list(member_of_level)
+        self.refine_above, self.coarsen_below = refine_above, coarsen_below
+        self.interval = interval
+        self.n_adapt = 0
+
+    def adapt_once(self):
+        eta = self.s.indicator()
+        flags = flags_from_indicator(eta, self.refine_above, self.coarsen_below)
+        self.s.adapt(flags, self.level_min, self.level_max, self.member_of_level)
+        self.n_adapt += 1
+        return flags
+
+    def initial_mesh(self, ic_leaf_fn, passes=3):
+        """Refine from the initial condition: set, indicate, adapt, re-evaluate, `passes` times."""
+        for _ in range(passes):
+            self.s.set_state(ic_leaf_fn(self.s.node_coords().cpu().numpy()))
+            self.adapt_once()
+        self.s.set_state(ic_leaf_fn(self.s.node_coords().cpu().numpy()))
+
+    def run(self, dt, n_steps, on_step=None):
+        """n_steps P-ERK steps, adapting every `interval` steps."""
+        for k in range(1, n_steps + 1):
+            self.s.step(dt, 1)
+            if on_step:
+                on_step(k)
+            if self.interval and k % self.interval == 0:
+                self.adapt_once()

@@ -207,6 +207,33 @@ def perk3_row(alpha, E, S, n_starts=200):
     raise RuntimeError(f"no positive third-order tableau for E={E}")
 
 
+def hull_points(lam):
+    """Boundary of the spectrum in the closed upper half plane (Sec. 4.1, step 2): convex hull
+    of the eigenvalues with non-negative imaginary part plus the origin, with extra points on
+    every hull edge so that consecutive points are no farther apart than the mean edge length.
+    |P| <= 1 on this polygon implies |P| <= 1 inside it (maximum modulus principle)."""
+    from scipy.spatial import ConvexHull
+    pts = np.asarray(lam, complex)
+    pts = pts[pts.imag >= 0]
+    xy = np.unique(np.round(np.stack([np.append(pts.real, 0.0), np.append(pts.imag, 0.0)], axis=1), 14), axis=0)
+    if len(xy) < 3:
+        return pts
+    hull = ConvexHull(xy)
+    v = xy[hull.vertices]
+    ring = np.concatenate([v, v[:1]])
+    seg = np.linalg.norm(np.diff(ring, axis=0), axis=1)
+    delta = seg.mean()
+    out = []
+    for k in range(len(v)):
+        a, b = ring[k], ring[k + 1]
+        m = max(1, int(np.ceil(seg[k] / delta)))
+        for t in np.arange(m) / m:
+            p = a + t * (b - a)
+            out.append(p[0] + 1j * p[1])
+    out = np.array(out)
+    return out[out.imag >= -1e-14]
+
+
 def build_family(order, E_list, lam, h_ref=None):
     """Optimise every member on the spectrum lam and build the family."""
     E_list = sorted(int(e) for e in E_list)
@@ -249,3 +276,12 @@ def fd_spectrum(solver, u_leaf, eps=1e-7):
     lam = lam[lam.imag >= 0]                  # spectrum is symmetric about the real axis
     lam.real = np.minimum(lam.real, 0.0)      # round-off positive real parts
     return lam
+
+
+def family_from_solver_spectrum(solver, u_leaf, order, E_list, h_ref):
+    """Sec. 4.1 steps 1-2 on the GPU right-hand side, then Sec. 4.2-4.3."""
+    lam = fd_spectrum(solver, u_leaf)
+    fam = build_family(order, E_list, hull_points(lam), h_ref=h_ref)
+    if not check_family(fam):
+        raise RuntimeError("constructed family violates the order conditions")
+    return fam, lam

@@ -52,7 +52,8 @@ struct pe_ctx {
   int32_t* d_halo = nullptr;
   int32_t* d_plan = nullptr;            // AMR projection plan [capacity][10]
   double* d_eta = nullptr;              // AMR indicator per leaf
-  unsigned long long* d_counter = nullptr;
+  unsigned long long* d_counter = nullptr;   // [R] folded totals
+  int32_t* d_evals = nullptr;               // [capacity] per-slot evaluations since the last fold
   // partition
   bool partitioned = false;
   bool state_valid = false;
@@ -322,6 +323,7 @@ size_t carve(pe_ctx* c, char* base) {
   c->d_counts = (int32_t*)take(kMaxMembers * 4);
   c->d_halo = (int32_t*)take((size_t)n * 4 * (kMaxMembers + 1));
   c->d_counter = (unsigned long long*)take(kMaxMembers * 8);
+  c->d_evals = (int32_t*)take((size_t)n * 4);
   c->d_plan = (int32_t*)take((size_t)n * 10 * 4);
   c->d_eta = (double*)take((size_t)n * 8);
   return off;
@@ -334,6 +336,16 @@ Mesh device_mesh(const pe_ctx* c) {
   m.lev = c->d_lev;
   m.mem = c->d_mem;
   m.ld = (int)cap_of(c);
+  m.R = c->R;
+  {
+    // slots are sorted by member, most stage evaluations first
+    int acc = 0;
+    for (int k = 0; k < kMaxMembers; ++k) {
+      const int r = c->R - 1 - k;
+      if (r >= 0 && (int)c->counts.size() == c->R) acc += c->counts[r];
+      m.bnd[k] = acc;
+    }
+  }
   for (int l = 0; l < kMaxLevels; ++l)
     for (int d = 0; d < 3; ++d) {
       const double h = d < c->dim ? (c->hi[d] - c->lo[d]) / std::ldexp((double)c->n_root[d], l) : 1.0;
@@ -521,6 +533,7 @@ pe_status pe_bind(pe_ctx* ctx, double* u_dev, void* ws, void* stream) {
   HIPCHK(hipMemcpyAsync(ctx->d_fn_leaf, ctx->fn_leaf.data(), (size_t)n * nf * 16, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->d_lev_leaf, ctx->lev_leaf.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(ctx->d_counter, 0, kMaxMembers * 8, s));
+  HIPCHK(hipMemsetAsync(ctx->d_evals, 0, (size_t)cap_of(ctx) * 4, s));
   ctx->pending_leaf_state = false;
   HIPCHK(hipStreamSynchronize(s));
   ctx->bound = true;
@@ -542,6 +555,7 @@ pe_status pe_partition(pe_ctx* ctx, const int32_t* member_of_level, int n_levels
   hipStream_t s = (hipStream_t)stream;
   const int n = ctx->n_e, nf = 2 * ctx->dim;
   const bool permute = ctx->state_valid && ctx->partitioned && !ctx->pending_leaf_state;
+  if (ctx->partitioned) HIPCHK(launch_fold_evals(n, device_mesh(ctx), ctx->d_evals, ctx->d_counter, s));
   if (permute)
     HIPCHK(hipMemcpyAsync(ctx->d_old_slot_of_leaf, ctx->d_slot_of_leaf, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
   pa.lev_leaf = ctx->d_lev_leaf;
@@ -640,6 +654,7 @@ pe_status pe_rhs(pe_ctx* ctx, const double* u, double* du, void* stream) {
   std::memset(&a, 0, sizeof a);
   a.U = u;
   a.Kout = du;
+  a.first = 1;          // F(U): stage values are U itself (src 0 for every member)
   a.n_act = ctx->n_e;
   Mesh m = device_mesh(ctx);
   HIPCHK(launch_stage(ctx->dim, ctx->N, ctx->equations == 1, a, m, ctx->ops, ctx->ph, (hipStream_t)stream));
@@ -687,7 +702,9 @@ pe_status pe_step(pe_ctx* ctx, double dt, int n_steps, void* stream) {
       a.Yout = (i % 2 == 0) ? ctx->Yb : ctx->Ya;
       a.ACC = ctx->ACC;
       a.Uout = in_place ? ctx->U : ctx->Tmp;
-      a.counter = ctx->d_counter;
+      a.evals = ctx->d_evals;
+      if (!a.U || !a.K1 || !a.Yin || !a.Yout || !a.ACC || !a.Uout)
+        return fail(ctx, PE_ESTATE, "step: stage buffers not bound");
       if (ctx->profiling && a.n_act > 0) {
         pe_status st = prof_event(ctx, s);
         if (st != PE_OK) return st;
@@ -852,6 +869,8 @@ pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags, int level_min, int level_ma
     std::memcpy(&leaves[i * 4], nl[i].L.data(), 16);
   }
   hipStream_t s = (hipStream_t)stream;
+  // evaluation counts of the old partition into the per-member totals
+  HIPCHK(launch_fold_evals(ctx->n_e, device_mesh(ctx), ctx->d_evals, ctx->d_counter, s));
   // project the old state (slot layout, old slot map) onto the new leaves (leaf layout, in Tmp)
   HIPCHK(hipMemcpyAsync(ctx->d_plan, plan.data(), plan.size() * 4, hipMemcpyHostToDevice, s));
   HIPCHK(launch_project(dim, ctx->N, (int)nl.size(), (int)cap_of(ctx), ctx->d_plan, ctx->d_slot_of_leaf, ctx->U,
@@ -904,6 +923,7 @@ pe_status pe_counters(pe_ctx* ctx, int64_t* total, int64_t* per_member, int rese
   if (!ctx) return PE_EINVAL;
   if (!ctx->bound) return fail(ctx, PE_ESTATE, "counters before bind");
   hipStream_t s = (hipStream_t)stream;
+  if (ctx->partitioned) HIPCHK(launch_fold_evals(ctx->n_e, device_mesh(ctx), ctx->d_evals, ctx->d_counter, s));
   unsigned long long h[kMaxMembers];
   HIPCHK(hipMemcpyAsync(h, ctx->d_counter, sizeof h, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));

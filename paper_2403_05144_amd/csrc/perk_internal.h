@@ -43,8 +43,17 @@ struct Mesh {
   const int32_t* lev;     // [slot] refinement level
   const int32_t* mem;     // [slot] P-ERK member
   int ld;                 // leading dimension of the slot layout (reserved capacity)
+  int R;                  // members
+  int bnd[kMaxMembers];   // slot ranges per member in slot order: [bnd[k-1], bnd[k]) holds member R-1-k
   double jac[kMaxLevels][3];   // 2 / h per level and direction
 };
+
+// Member of a slot from the partition boundaries (slots are sorted by member).
+__host__ __device__ inline int member_of_slot(const Mesh& m, int s) {
+  int k = 0;
+  while (k < m.R - 1 && s >= m.bnd[k]) ++k;
+  return m.R - 1 - k;
+}
 
 // Everything one stage launch needs.  Stage indices are 0-based here.
 struct StageArgs {
@@ -56,7 +65,7 @@ struct StageArgs {
   double* Uout;           // U_{n+1} at the last stage (may alias U)
   double* Kout;           // if non-null: K_i is written here and nothing else (right-hand side)
   const double* Q;        // BR1 gradients [dim][dim+1][slot][node] (Navier-Stokes)
-  unsigned long long* counter;   // [R] element evaluations per member, or null
+  int32_t* evals;         // [slot] right-hand-side evaluations of the slot's element, or null
   int n_act;              // active slots: [0, n_act)
   int n_halo;             // Navier-Stokes gradient kernel only: extra slots listed in halo
   const int32_t* halo;
@@ -117,5 +126,8 @@ hipError_t launch_indicator(int dim, int N, int n, int ld, const int32_t* slot_o
 hipError_t launch_project(int dim, int N, int n_new, int ld, const int32_t* plan, const int32_t* old_slot_of_leaf,
                           const double* U_old, const Ops& op, double* dst_leaf, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+// Add the per-slot evaluation counts into per-member totals (member from the partition
+// boundaries) and zero them.
+hipError_t launch_fold_evals(int n, const Mesh& m, int32_t* evals, unsigned long long* totals, hipStream_t s);
 
 }  // namespace perk

@@ -176,167 +176,207 @@ __device__ __forceinline__ double stage_value(const StageArgs& a, int src, int64
 }
 
 // ------------------------------------------------------------------------------------------
-// Stage kernel (Euler; the Navier-Stokes viscous terms are added by the template flag VISC)
+// Stage kernel.  One element per T lanes (T = 64 for 2D p=3, one wave), EPB elements per
+// block.  Phases, separated by block barriers:
+//   A  connectivity of the element into LDS; own stage value and the epilogue operands
+//      (U_n, K_1) loaded into registers, one (variable, node) item per lane;
+//   B  neighbour face traces into LDS (conforming: the neighbour's face; fine side of a
+//      mortar: the coarse neighbour's whole face; coarse side: every fine neighbour's face);
+//   C  node quantities (primitives, logarithms) and, on fine sides, interpolation of the
+//      coarse trace to the sub-face;
+//   D  one two-point flux per lane: every unordered node pair along a coordinate line gets
+//      one entropy-conserving flux (symmetric, used by both nodes), every face node (and
+//      every sub-face node of a coarse side) one HLL flux;
+//   E  per (variable, node): flux-differencing sum, lifting of the face fluxes (projected
+//      with R_m on coarse sides), Jacobian, and the P-ERK stage combination.
 // ------------------------------------------------------------------------------------------
-template <int DIM, int N, int EPB, bool VISC>
-__global__ __launch_bounds__((EPB * G<DIM, N>::ND)) void k_stage(StageArgs a, Mesh m, Ops op, Physics ph) {
+template <int DIM, int N>
+struct SK {
   using g = G<DIM, N>;
-  constexpr int ND = g::ND, NF = g::NF, NFC = g::NFC, NV = g::NV, NSUB = g::NSUB;
+  static constexpr int ND = g::ND, NF = g::NF, NFC = g::NFC, NV = g::NV, NSUB = g::NSUB;
+  static constexpr int NPL = N * (N - 1) / 2;                 // pairs per coordinate line
+  static constexpr int NLINE = DIM == 2 ? N : N * N;          // lines per direction
+  static constexpr int NP = DIM * NLINE * NPL;                // pairs per element
+  static constexpr int WORK = NP + NFC * NF;                  // flux items without mortars
+  static constexpr int T = DIM == 2 ? (N == 4 ? 64 : 32) : (N == 4 ? 384 : 192);
+  static constexpr int EPB = T >= 64 ? 1 : 64 / T;
+  static constexpr int NITEM = (NV * ND + T - 1) / T;         // (variable, node) items per lane
+};
+
+// index of the unordered pair (a, b), a < b, among the N(N-1)/2 pairs of a line
+template <int N>
+__device__ __forceinline__ int pair_index(int a, int b) {
+  return a * (2 * N - a - 1) / 2 + (b - a - 1);
+}
+
+// line index of a node for direction d (the other coordinates) and its coordinate along d
+template <int DIM, int N>
+__device__ __forceinline__ void line_of(int nd, int d, int& line, int& pos) {
+  const int i = nd % N, j = (nd / N) % N, k = DIM == 3 ? nd / (N * N) : 0;
+  if (d == 0) { line = j + N * k; pos = i; }
+  else if (d == 1) { line = i + N * k; pos = j; }
+  else { line = i + N * j; pos = k; }
+}
+
+template <int DIM, int N>
+__device__ __forceinline__ int node_on_line(int d, int line, int pos) {
+  if (DIM == 2) return d == 0 ? pos + N * line : line + N * pos;
+  const int a = line % N, b = line / N;
+  if (d == 0) return pos + N * a + N * N * b;
+  if (d == 1) return a + N * pos + N * N * b;
+  return a + N * b + N * N * pos;
+}
+
+template <int DIM, int N, bool VISC>
+__global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB)) void k_stage(StageArgs a, Mesh m, Ops op, Physics ph) {
+  using K = SK<DIM, N>;
+  constexpr int ND = K::ND, NF = K::NF, NFC = K::NFC, NV = K::NV, NSUB = K::NSUB, T = K::T, EPB = K::EPB;
+  constexpr int NP = K::NP, NPL = K::NPL, NITEM = K::NITEM;
   __shared__ double s_u[EPB][NV][ND];
   __shared__ NodeQ<DIM> s_q[EPB][ND];
-  __shared__ double s_f[EPB][NFC][NV][NF];
-  __shared__ double s_t[EPB][NFC][NV][NF];
+  __shared__ double s_tr[EPB][NFC][NSUB][NV][NF];   // neighbour traces, later HLL fluxes in place
+  __shared__ double s_pf[EPB][NP][NV];
+  __shared__ int s_fk[EPB][NFC];
+  __shared__ int s_fn[EPB][NFC][4];
 
-  const int tid = threadIdx.x;
-  const int le = tid / ND;
-  const int nd = tid - le * ND;
+  const int le = threadIdx.x / T;
+  const int lane = threadIdx.x - le * T;
   const int e = blockIdx.x * EPB + le;
   const bool act = e < a.n_act;
-  const int ne = m.ld;
+  const int ld = m.ld;
   const double gamma = ph.gamma;
   const double inv_gm1 = 1.0 / (gamma - 1.0);
 
-  int my_mem = 0, my_src = 0, my_lev = 0;
+  // ---- A: connectivity, own values, epilogue operands
+  int my_mem = 0, my_src = 0;
   double J[DIM];
-  double u[NV];
+  double own[NITEM], un[NITEM], k1[NITEM];
   if (act) {
-    my_mem = m.mem[e];
+    my_mem = member_of_slot(m, e);
     my_src = a.src[my_mem];
-    my_lev = m.lev[e];
+    const int lev = m.lev[e];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) J[d] = m.jac[my_lev][d];
+    for (int d = 0; d < DIM; ++d) J[d] = m.jac[lev][d];
+    if (lane < NFC) s_fk[le][lane] = m.fk[(int64_t)e * NFC + lane];
+    if (lane < NFC * 4) s_fn[le][lane / 4][lane % 4] = m.fn[(int64_t)e * NFC * 4 + lane];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      u[v] = stage_value(a, my_src, ((int64_t)v * ne + e) * ND + nd);
-      s_u[le][v][nd] = u[v];
+    for (int it = 0; it < NITEM; ++it) {
+      const int w = lane + it * T;
+      if (w < NV * ND) {
+        const int v = w / ND, nd = w - v * ND;
+        const int64_t idx = ((int64_t)v * ld + e) * ND + nd;
+        un[it] = a.U[idx];
+        // K_1 exists only after the first stage of a step; right-hand-side launches never read it
+        k1[it] = (a.first || a.Kout) ? 0.0 : a.K1[idx];
+        own[it] = my_src == 0 ? un[it] : (my_src == 1 ? a.Yin[idx] : un[it] + a.dt * a.ci * k1[it]);
+      }
     }
-    NodeQ<DIM> q;
-    cons_to_prim<DIM>(u, gamma, q.rho, q.v, q.p);
-    q.lrho = log(q.rho);
-    q.beta = q.rho / q.p;
-    q.lbeta = log(q.beta);
-    s_q[le][nd] = q;
-    if (nd == 0 && a.counter) atomicAdd(&a.counter[my_mem], 1ull);
+    if (lane == 0 && a.evals) a.evals[e] += 1;   // each slot belongs to exactly one block
   }
   __syncthreads();
 
-  double du[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) du[v] = 0.0;
-
-  // ---- volume integral: flux differencing along every coordinate line through the node
+  // ---- B: own values to LDS, neighbour traces
   if (act) {
-    const NodeQ<DIM> qi = s_q[le][nd];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      const int ia = node_index_dir<DIM, N>(nd, d);
-      const int st = stride_dir<DIM, N>(d);
-      double acc[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-#pragma unroll
-      for (int mm = 0; mm < N; ++mm) {
-        if (mm == ia) continue;
-        const NodeQ<DIM> qm = s_q[le][nd + (mm - ia) * st];
-        double f[NV];
-        ec_flux<DIM>(qi, qm, d, inv_gm1, f);
-        const double c2 = 2.0 * op.D[ia * N + mm];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] += c2 * f[v];
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) du[v] -= J[d] * acc[v];
+    for (int it = 0; it < NITEM; ++it) {
+      const int w = lane + it * T;
+      if (w < NV * ND) s_u[le][w / ND][w % ND] = own[it];
+    }
+    for (int w = lane; w < NSUB * NFC * NV * NF; w += T) {
+      const int j = w % NF;
+      const int v = (w / NF) % NV;
+      const int f = (w / (NF * NV)) % NFC;
+      const int sub = w / (NF * NV * NFC);
+      const int kind = face_kind(s_fk[le][f]);
+      if (sub > 0 && kind != kCoarseSide) continue;
+      const int nb = s_fn[le][f][sub];
+      const int d = f >> 1, side = f & 1;
+      const int src = a.src[member_of_slot(m, nb)];
+      const int nn = face_node<DIM, N>(d, 1 - side, j);
+      s_tr[le][f][sub][v][j] = stage_value(a, src, ((int64_t)v * ld + nb) * ND + nn);
     }
   }
+  __syncthreads();
 
-  // ---- face fluxes of the own faces (each lane handles face-node slots nd, nd+ND, ...)
-  bool has_coarse = false;
+  // ---- C: node quantities; fine sides: coarse trace interpolated into sub-slot 1
   if (act) {
-    for (int fs = nd; fs < NFC * NF; fs += ND) {
-      const int f = fs / NF, j = fs - f * NF;
-      const int d = f >> 1, s = f & 1;
-      const int32_t pk = m.fk[(int64_t)e * NFC + f];
-      const int kind = face_kind(pk);
-      const int* nbp = m.fn + ((int64_t)e * NFC + f) * 4;
-      double own[NV], oth[NV], fl[NV];
-      const int own_node = face_node<DIM, N>(d, s, j);
+    for (int w = lane; w < ND; w += T) {
+      double uu[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) own[v] = s_u[le][v][own_node];
-      if (kind == kConforming) {
-        const int nb = nbp[0];
-        const int src = a.src[m.mem[nb]];
-        const int nn = face_node<DIM, N>(d, 1 - s, j);
+      for (int v = 0; v < NV; ++v) uu[v] = s_u[le][v][w];
+      NodeQ<DIM> q;
+      cons_to_prim<DIM>(uu, gamma, q.rho, q.v, q.p);
+      q.lrho = log(q.rho);
+      q.beta = q.rho / q.p;
+      q.lbeta = log(q.beta);
+      s_q[le][w] = q;
+    }
+    for (int w = lane; w < NFC * NV * NF; w += T) {
+      const int j = w % NF;
+      const int v = (w / NF) % NV;
+      const int f = w / (NF * NV);
+      const int32_t pk = s_fk[le][f];
+      if (face_kind(pk) != kFineSide) continue;
+      const int s0 = face_sub0(pk), s1 = face_sub1(pk);
+      double val = 0.0;
+      if (DIM == 2) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) oth[v] = stage_value(a, src, ((int64_t)v * ne + nb) * ND + nn);
-      } else if (kind == kFineSide) {
-        // coarse neighbour trace interpolated to this sub-face
-        const int nb = nbp[0];
-        const int src = a.src[m.mem[nb]];
-        const int s0 = face_sub0(pk), s1 = face_sub1(pk);
+        for (int k = 0; k < N; ++k) val += op.P[s0][j * N + k] * s_tr[le][f][0][v][k];
+      } else {
+        const int ja = j % N, jb = j / N;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) oth[v] = 0.0;
-        if (DIM == 2) {
+        for (int kb = 0; kb < N; ++kb) {
+          double row = 0.0;
 #pragma unroll
-          for (int k = 0; k < N; ++k) {
-            const double c = op.P[s0][j * N + k];
-            const int nn = face_node<DIM, N>(d, 1 - s, k);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) oth[v] += c * stage_value(a, src, ((int64_t)v * ne + nb) * ND + nn);
-          }
-        } else {
-          const int ja = j % N, jb = j / N;
-#pragma unroll
-          for (int kb = 0; kb < N; ++kb) {
-            double row[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) row[v] = 0.0;
-#pragma unroll
-            for (int ka = 0; ka < N; ++ka) {
-              const double c = op.P[s0][ja * N + ka];
-              const int nn = face_node<DIM, N>(d, 1 - s, ka + N * kb);
-#pragma unroll
-              for (int v = 0; v < NV; ++v) row[v] += c * stage_value(a, src, ((int64_t)v * ne + nb) * ND + nn);
-            }
-            const double cb = op.P[s1][jb * N + kb];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) oth[v] += cb * row[v];
-          }
+          for (int ka = 0; ka < N; ++ka) row += op.P[s0][ja * N + ka] * s_tr[le][f][0][v][ka + N * kb];
+          val += op.P[s1][jb * N + kb] * row;
         }
       }
-      if (kind == kCoarseSide) {
-        has_coarse = true;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) s_f[le][f][v][j] = 0.0;
-      } else {
-        if (s == 1) hll_flux<DIM>(own, oth, d, gamma, fl);
-        else hll_flux<DIM>(oth, own, d, gamma, fl);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) s_f[le][f][v][j] = fl[v];
-      }
+      s_tr[le][f][1][v][j] = val;
     }
   }
-  // coarse sides of mortars: flux on every fine sub-face, projected back with R_m
-  if (__syncthreads_or(has_coarse)) {
-    for (int msub = 0; msub < NSUB; ++msub) {
-      const int m0 = msub & 1, m1 = (msub >> 1) & 1;
-      if (act) {
-        for (int fs = nd; fs < NFC * NF; fs += ND) {
-          const int f = fs / NF, j = fs - f * NF;
-          const int32_t pk = m.fk[(int64_t)e * NFC + f];
-          if (face_kind(pk) != kCoarseSide) continue;
-          const int d = f >> 1, s = f & 1;
-          const int nb = m.fn[((int64_t)e * NFC + f) * 4 + msub];
-          const int src = a.src[m.mem[nb]];
-          double own[NV], oth[NV], fl[NV];
+  __syncthreads();
+
+  // ---- D: fluxes.  Pairs first, then face nodes sub-face-major (sub 0 of every face first).
+  if (act) {
+    for (int w = lane; w < NP + NSUB * NFC * NF; w += T) {
+      if (w < NP) {
+        const int pl = w % NPL;
+        const int line = (w / NPL) % K::NLINE;
+        const int d = w / (NPL * K::NLINE);
+        int pa = 0, pb = 1, cnt = 0;
+        for (int x = 0; x < N; ++x)
+          for (int y = x + 1; y < N; ++y) {
+            if (cnt == pl) { pa = x; pb = y; }
+            ++cnt;
+          }
+        double f[NV];
+        ec_flux<DIM>(s_q[le][node_on_line<DIM, N>(d, line, pa)], s_q[le][node_on_line<DIM, N>(d, line, pb)], d,
+                     inv_gm1, f);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) own[v] = 0.0;
+        for (int v = 0; v < NV; ++v) s_pf[le][w][v] = f[v];
+      } else {
+        const int r = w - NP;
+        const int j = r % NF;
+        const int f = (r / NF) % NFC;
+        const int sub = r / (NF * NFC);
+        const int32_t pk = s_fk[le][f];
+        const int kind = face_kind(pk);
+        if (sub > 0 && kind != kCoarseSide) continue;
+        const int d = f >> 1, side = f & 1;
+        double mine[NV], oth[NV], fl[NV];
+        if (kind == kCoarseSide) {
+          // own trace interpolated to sub-face `sub`
+          const int m0 = sub & 1, m1 = (sub >> 1) & 1;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) mine[v] = 0.0;
           if (DIM == 2) {
 #pragma unroll
             for (int k = 0; k < N; ++k) {
               const double c = op.P[m0][j * N + k];
-              const int on = face_node<DIM, N>(d, s, k);
+              const int on = face_node<DIM, N>(d, side, k);
 #pragma unroll
-              for (int v = 0; v < NV; ++v) own[v] += c * s_u[le][v][on];
+              for (int v = 0; v < NV; ++v) mine[v] += c * s_u[le][v][on];
             }
           } else {
             const int ja = j % N, jb = j / N;
@@ -348,119 +388,112 @@ __global__ __launch_bounds__((EPB * G<DIM, N>::ND)) void k_stage(StageArgs a, Me
 #pragma unroll
               for (int ka = 0; ka < N; ++ka) {
                 const double c = op.P[m0][ja * N + ka];
-                const int on = face_node<DIM, N>(d, s, ka + N * kb);
+                const int on = face_node<DIM, N>(d, side, ka + N * kb);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) row[v] += c * s_u[le][v][on];
               }
               const double cb = op.P[m1][jb * N + kb];
 #pragma unroll
-              for (int v = 0; v < NV; ++v) own[v] += cb * row[v];
+              for (int v = 0; v < NV; ++v) mine[v] += cb * row[v];
             }
           }
-          const int nn = face_node<DIM, N>(d, 1 - s, j);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) oth[v] = stage_value(a, src, ((int64_t)v * ne + nb) * ND + nn);
-          if (s == 1) hll_flux<DIM>(own, oth, d, gamma, fl);
-          else hll_flux<DIM>(oth, own, d, gamma, fl);
+          for (int v = 0; v < NV; ++v) oth[v] = s_tr[le][f][sub][v][j];
+        } else {
+          const int on = face_node<DIM, N>(d, side, j);
+          const int ts = kind == kFineSide ? 1 : 0;
 #pragma unroll
-          for (int v = 0; v < NV; ++v) s_t[le][f][v][j] = fl[v];
+          for (int v = 0; v < NV; ++v) {
+            mine[v] = s_u[le][v][on];
+            oth[v] = s_tr[le][f][ts][v][j];
+          }
         }
+        if (side == 1) hll_flux<DIM>(mine, oth, d, gamma, fl);
+        else hll_flux<DIM>(oth, mine, d, gamma, fl);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s_tr[le][f][sub][v][j] = fl[v];
       }
-      __syncthreads();
-      if (act) {
-        for (int fs = nd; fs < NFC * NF; fs += ND) {
-          const int f = fs / NF, j = fs - f * NF;
-          if (face_kind(m.fk[(int64_t)e * NFC + f]) != kCoarseSide) continue;
+    }
+  }
+  __syncthreads();
+  if (!act) return;
+
+  // ---- E: sums, lifting, Jacobian, stage combination
+  const double iw0 = 1.0 / op.w[0], iwN = 1.0 / op.w[N - 1];
+#pragma unroll
+  for (int it = 0; it < NITEM; ++it) {
+    const int w = lane + it * T;
+    if (w >= NV * ND) continue;
+    const int v = w / ND, nd = w - v * ND;
+    double du = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      int line, pos;
+      line_of<DIM, N>(nd, d, line, pos);
+      const int base = (d * K::NLINE + line) * NPL;
+      double acc = 0.0;
+#pragma unroll
+      for (int mm = 0; mm < N; ++mm) {
+        if (mm == pos) continue;
+        const int pi = mm > pos ? pair_index<N>(pos, mm) : pair_index<N>(mm, pos);
+        acc += 2.0 * op.D[pos * N + mm] * s_pf[le][base + pi][v];
+      }
+      if (pos == N - 1 || pos == 0) {
+        const int f = 2 * d + (pos == N - 1 ? 1 : 0);
+        const int fi = face_index<DIM, N>(nd, d);
+        double fs;
+        if (face_kind(s_fk[le][f]) == kCoarseSide) {
+          fs = 0.0;
           if (DIM == 2) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-              double acc = 0.0;
+            for (int ms = 0; ms < 2; ++ms)
 #pragma unroll
-              for (int k = 0; k < N; ++k) acc += op.R[m0][j * N + k] * s_t[le][f][v][k];
-              s_f[le][f][v][j] += acc;
-            }
+              for (int k = 0; k < N; ++k) fs += op.R[ms][fi * N + k] * s_tr[le][f][ms][v][k];
           } else {
-            const int ja = j % N, jb = j / N;
+            const int ja = fi % N, jb = fi / N;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-              double acc = 0.0;
+            for (int ms = 0; ms < 4; ++ms) {
+              const int m0 = ms & 1, m1 = (ms >> 1) & 1;
 #pragma unroll
               for (int kb = 0; kb < N; ++kb) {
                 double row = 0.0;
 #pragma unroll
-                for (int ka = 0; ka < N; ++ka) row += op.R[m0][ja * N + ka] * s_t[le][f][v][ka + N * kb];
-                acc += op.R[m1][jb * N + kb] * row;
+                for (int ka = 0; ka < N; ++ka) row += op.R[m0][ja * N + ka] * s_tr[le][f][ms][v][ka + N * kb];
+                fs += op.R[m1][jb * N + kb] * row;
               }
-              s_f[le][f][v][j] += acc;
             }
           }
+        } else {
+          fs = s_tr[le][f][0][v][fi];
         }
+        acc += pos == N - 1 ? iwN * fs : -iw0 * fs;
       }
-      __syncthreads();
+      du -= J[d] * acc;
     }
-  }
-  __syncthreads();
-
-  if (!act) return;
-
-  // ---- lifting of the surface fluxes (strong form; boundary nodes only)
-  const double iw0 = 1.0 / op.w[0], iwN = 1.0 / op.w[N - 1];
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    const int ia = node_index_dir<DIM, N>(nd, d);
-    if (ia == N - 1) {
-      const int fi = face_index<DIM, N>(nd, d);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) du[v] -= J[d] * iwN * s_f[le][2 * d + 1][v][fi];
-    } else if (ia == 0) {
-      const int fi = face_index<DIM, N>(nd, d);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) du[v] += J[d] * iw0 * s_f[le][2 * d][v][fi];
+    const int64_t idx = ((int64_t)v * ld + e) * ND + nd;
+    if (a.Kout) {
+      a.Kout[idx] = du;
+      continue;
     }
-  }
-
-  // ---- epilogue: stage combination of the P-ERK tableau (K_i never stored)
-  if (a.Kout) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) a.Kout[((int64_t)v * ne + e) * ND + nd] = du[v];
-    return;
-  }
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const int64_t idx = ((int64_t)v * ne + e) * ND + nd;
-    const double K = du[v];
-    const double Un = a.U[idx];
-    double K1v;
-    if (a.first) {
-      a.K1[idx] = K;
-      K1v = K;
-    } else {
-      K1v = a.K1[idx];
-    }
-    double acc = 0.0;
-    if (a.acc_mode == 1) {
-      acc = a.bi * K;
-      a.ACC[idx] = acc;
-    } else if (a.acc_mode == 2) {
-      acc = a.ACC[idx] + a.bi * K;
-      a.ACC[idx] = acc;
-    }
+    const double K1v = a.first ? du : k1[it];
+    if (a.first) a.K1[idx] = du;
+    if (a.acc_mode == 1) a.ACC[idx] = a.bi * du;
+    else if (a.acc_mode == 2) a.ACC[idx] = a.ACC[idx] + a.bi * du;
     if (a.last) {
-      const double inc = a.use_acc_last ? a.ACC[idx] + a.bS * K : a.bS * K;
-      a.Uout[idx] = Un + a.dt * inc;
+      const double inc = a.use_acc_last ? a.ACC[idx] + a.bS * du : a.bS * du;
+      a.Uout[idx] = un[it] + a.dt * inc;
     } else if (a.wr[my_mem]) {
-      a.Yout[idx] = Un + a.dt * (a.a1[my_mem] * K1v + a.a2[my_mem] * K);
+      a.Yout[idx] = un[it] + a.dt * (a.a1[my_mem] * K1v + a.a2[my_mem] * du);
     }
   }
 }
 
 template <int DIM, int N, bool VISC>
 hipError_t launch_stage_t(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s) {
-  constexpr int ND = G<DIM, N>::ND;
-  constexpr int EPB = (DIM == 2) ? (64 / ND > 0 ? 64 / ND : 1) : 1;
+  using K = SK<DIM, N>;
   if (a.n_act <= 0) return hipSuccess;
-  const int blocks = (a.n_act + EPB - 1) / EPB;
-  hipLaunchKernelGGL((k_stage<DIM, N, EPB, VISC>), dim3(blocks), dim3(EPB * ND), 0, s, a, m, op, ph);
+  const int blocks = (a.n_act + K::EPB - 1) / K::EPB;
+  hipLaunchKernelGGL((k_stage<DIM, N, VISC>), dim3(blocks), dim3(K::T * K::EPB), 0, s, a, m, op, ph);
   return hipGetLastError();
 }
 
@@ -654,6 +687,21 @@ __global__ void k_copy(double* dst, const double* src, int64_t n) {
   if (t < n) dst[t] = src[t];
 }
 
+__global__ __launch_bounds__(1024) void k_fold_evals(int n, Mesh m, int32_t* evals, unsigned long long* totals) {
+  __shared__ unsigned long long s_tot[kMaxMembers];
+  if (threadIdx.x < kMaxMembers) s_tot[threadIdx.x] = 0;
+  __syncthreads();
+  unsigned long long mine[kMaxMembers] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    mine[member_of_slot(m, i)] += (unsigned long long)evals[i];
+    evals[i] = 0;
+  }
+  for (int r = 0; r < m.R; ++r)
+    if (mine[r]) atomicAdd(&s_tot[r], mine[r]);
+  __syncthreads();
+  if (threadIdx.x < m.R) totals[threadIdx.x] += s_tot[threadIdx.x];
+}
+
 inline unsigned grid_for(int64_t total, int bs) { return (unsigned)((total + bs - 1) / bs); }
 
 }  // namespace
@@ -739,6 +787,12 @@ hipError_t launch_project(int dim, int N, int n_new, int ld, const int32_t* plan
   else if (dim == 3 && N == 4) hipLaunchKernelGGL((k_project<3, 4>), g, b, 0, s, total, ld, plan, old_slot_of_leaf, U_old, op, dst);
   else if (dim == 3 && N == 3) hipLaunchKernelGGL((k_project<3, 3>), g, b, 0, s, total, ld, plan, old_slot_of_leaf, U_old, op, dst);
   else return hipErrorNotSupported;
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_evals(int n, const Mesh& m, int32_t* evals, unsigned long long* totals, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_evals, dim3(1), dim3(1024), 0, s, n, m, evals, totals);
   return hipGetLastError();
 }
 

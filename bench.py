@@ -35,7 +35,7 @@ def _log(msg):
 # ----------------------------------------------------------------------------------------
 # Workloads
 # ----------------------------------------------------------------------------------------
-def family_for(name, order, E_list, reduced_mesh, degree, ic_fn, h_red):
+def family_for(name, order, E_list, reduced_mesh, degree, ic_fn, h_red, equations=0, mu=0.0):
     """Coefficients from the project's own optimisation on the spectrum of a reduced mesh
     (cached as JSON next to the package)."""
     from paper_2403_05144_amd import PerkSolver, coeffs
@@ -44,7 +44,8 @@ def family_for(name, order, E_list, reduced_mesh, degree, ic_fn, h_red):
         return coeffs.Family.load(path)
     _log(f"building coefficient family {name} (spectrum of the reduced mesh, LP optimisation)")
     tmp = coeffs.Family(2, 2, [2], np.array([0.0, 0.5]), np.array([0.0, 1.0]), np.zeros((1, 2)))
-    s = PerkSolver(reduced_mesh, degree, tmp, [0] * (int(reduced_mesh.leaves[:, 0].max()) + 1))
+    s = PerkSolver(reduced_mesh, degree, tmp, [0] * (int(reduced_mesh.leaves[:, 0].max()) + 1),
+                   equations=equations, mu=mu)
     x = s.node_coords().cpu().numpy().transpose(1, 0, 2)
     u = ic_fn(x).transpose(1, 0, 2).copy()
     fam, lam = coeffs.family_from_solver_spectrum(s, u, order, E_list, h_red)
@@ -107,7 +108,26 @@ def wl_kh_amr(n_root=8, level_max=3, name="kh_amr_l3-6"):
                      f"adaptation, P-ERK3{{4,6,8,12,16}} at 50% of the optimised step (largest of 0.3/0.5/0.7 without blow-up)")
 
 
-WORKLOADS = {"vortex_2level": wl_vortex_2level, "kh_amr": wl_kh_amr,
+def wl_tgv():
+    """3D compressible Navier-Stokes Taylor-Green vortex, Ma 0.1, Re 1600, Pr 0.72, 16^3 roots
+    with a seeded 2-level refined region (7120 elements), p=3, BR1, P-ERK2{4,8,16}."""
+    import perk_inputs as pin
+    mesh = pin.mesh_taylor_green()
+    mu = 1.0 / 1600
+    ic = lambda x: pin.taylor_green(x[0], x[1], x[2])
+    red = pin.uniform_mesh(3, (2, 2, 2), (-np.pi,) * 3, (np.pi,) * 3, 0)
+    fam = family_for("perk2_4_8_16_tgv_p3", 2, [4, 8, 16], red, 3, ic, np.pi, equations=1, mu=mu)
+    mol = [0, 1, 2]
+    dt = stable_dt(fam, mesh, mol, 0.5)
+    return dict(name="tgv_ns_3d", mesh=mesh, degree=3, fam=fam, mol=mol, ic=ic, dt=dt, t_final=None,
+                equations=1, mu=mu,
+                desc="3D compressible Navier-Stokes Taylor-Green vortex (Ma 0.1, Re 1600, Pr 0.72) on "
+                     "[-pi,pi]^3, 16^3 roots with a seeded 2-level refined region (3880+1512+1728 = 7120 "
+                     "elements), p=3, EC volume + HLL surface flux, BR1, P-ERK2{4,8,16} at 50% of the "
+                     "optimised step (largest of 0.9/0.7/0.5 without blow-up over 200 steps)")
+
+
+WORKLOADS = {"vortex_2level": wl_vortex_2level, "kh_amr": wl_kh_amr, "tgv": wl_tgv,
              "kh_amr_l4-7": lambda: wl_kh_amr(16, 3, "kh_amr_l4-7")}
 
 
@@ -120,7 +140,7 @@ def cpu_baseline(wl, u0_leaf, leaves0, budget_s=15.0):
     from oracle import perk_coeffs as pc
     m0 = wl["mesh"]
     mesh = pin.MeshDesc(m0.dim, m0.n_root, m0.lo, m0.hi, leaves0)
-    o = od.Oracle(mesh, wl["degree"] + 1)
+    o = od.Oracle(mesh, wl["degree"] + 1, viscous=wl.get("equations", 0) == 1, mu=wl.get("mu", 0.0))
     fam = wl["fam"]
     ofam = pc.PerkFamily(fam.order, fam.S, list(fam.E), np.asarray(fam.c), np.asarray(fam.b),
                          np.asarray(fam.a_sub))
@@ -169,7 +189,8 @@ def run(args):
     mesh, deg, fam = wl["mesh"], wl["degree"], wl["fam"]
     N = deg + 1
     amr = wl.get("amr")
-    s = PerkSolver(mesh, deg, fam, wl["mol"], capacity=amr["capacity"] if amr else None)
+    s = PerkSolver(mesh, deg, fam, wl["mol"], capacity=amr["capacity"] if amr else None,
+                   equations=wl.get("equations", 0), mu=wl.get("mu", 0.0))
     ic_leaf = lambda x: wl["ic"](x.transpose(1, 0, 2)).transpose(1, 0, 2).copy()
     drv = None
     if amr:

@@ -45,7 +45,7 @@ struct pe_ctx {
   bool bound = false;
   double* U = nullptr;
   char* ws = nullptr;
-  double *K1 = nullptr, *Ya = nullptr, *Yb = nullptr, *ACC = nullptr, *Tmp = nullptr, *Q = nullptr;
+  double *K1 = nullptr, *Ya = nullptr, *Yb = nullptr, *ACC = nullptr, *Tmp = nullptr, *Fv = nullptr;
   int32_t *d_fk_leaf = nullptr, *d_fn_leaf = nullptr, *d_lev_leaf = nullptr;
   int32_t *d_fk = nullptr, *d_fn = nullptr, *d_lev = nullptr, *d_mem = nullptr, *d_mem_leaf = nullptr;
   int32_t *d_slot_of_leaf = nullptr, *d_leaf_of_slot = nullptr, *d_old_slot_of_leaf = nullptr, *d_counts = nullptr;
@@ -61,6 +61,7 @@ struct pe_ctx {
   std::vector<int32_t> counts;          // [R] elements per member
   std::vector<int32_t> leaf_of_slot, slot_of_leaf, mem_of_slot;
   std::vector<int> n_act;               // [S]
+  std::vector<int> halo_off, halo_cnt;  // [S] Navier-Stokes: inactive face neighbours of the active prefix
   // optional per-launch timing of the stage kernels with HIP events on the launch stream
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -307,8 +308,8 @@ size_t carve(pe_ctx* c, char* base) {
   c->Yb = (double*)take(sd);
   c->ACC = (double*)take(sd);
   c->Tmp = (double*)take(sd);
-  c->Q = c->equations == 1 ? (double*)take((size_t)c->dim * (c->dim + 1) * n * nodes_per_elem(c) * sizeof(double))
-                           : nullptr;
+  c->Fv = c->equations == 1 ? (double*)take((size_t)c->dim * nvars(c) * n * nodes_per_elem(c) * sizeof(double))
+                            : nullptr;
   c->d_fk_leaf = (int32_t*)take((size_t)n * nf * 4);
   c->d_fn_leaf = (int32_t*)take((size_t)n * nf * 4 * 4);
   c->d_lev_leaf = (int32_t*)take((size_t)n * 4);
@@ -592,6 +593,56 @@ pe_status pe_partition(pe_ctx* ctx, const int32_t* member_of_level, int n_levels
   for (int i = 0; i < ctx->S; ++i)
     for (int r = 0; r < ctx->R; ++r)
       if (active(ctx, r, i)) ctx->n_act[i] += ctx->counts[r];
+  ctx->halo_off.assign(ctx->S, 0);
+  ctx->halo_cnt.assign(ctx->S, 0);
+  if (ctx->equations == 1) {
+    // the BR1 gradient pass of a stage also covers the inactive face neighbours of the active
+    // prefix (their viscous face fluxes enter the active elements' surface terms)
+    std::vector<int32_t> all;
+    std::vector<int> seen_na;
+    std::vector<char> mark(n, 0);
+    for (int i = 0; i < ctx->S; ++i) {
+      const int na = ctx->n_act[i];
+      auto it = std::find(seen_na.begin(), seen_na.end(), na);
+      if (it != seen_na.end()) {
+        const int k = (int)(it - seen_na.begin());
+        int j = 0;
+        for (; j < i; ++j)
+          if (ctx->n_act[j] == na) break;
+        ctx->halo_off[i] = ctx->halo_off[j];
+        ctx->halo_cnt[i] = ctx->halo_cnt[j];
+        (void)k;
+        continue;
+      }
+      seen_na.push_back(na);
+      std::vector<int32_t> h;
+      if (na < n) {
+        std::fill(mark.begin(), mark.end(), 0);
+        for (int sl = 0; sl < na; ++sl) {
+          const int leaf = ctx->leaf_of_slot[sl];
+          for (int f = 0; f < nf; ++f) {
+            const int kind = face_kind(ctx->fk_leaf[(size_t)leaf * nf + f]);
+            const int cnt = kind == kCoarseSide ? (1 << (ctx->dim - 1)) : 1;
+            for (int q = 0; q < cnt; ++q) {
+              const int t = ctx->slot_of_leaf[ctx->fn_leaf[((size_t)leaf * nf + f) * 4 + q]];
+              if (t >= na && !mark[t]) {
+                mark[t] = 1;
+                h.push_back(t);
+              }
+            }
+          }
+        }
+        std::sort(h.begin(), h.end());
+      }
+      ctx->halo_off[i] = (int)all.size();
+      ctx->halo_cnt[i] = (int)h.size();
+      all.insert(all.end(), h.begin(), h.end());
+    }
+    if (!all.empty()) {
+      HIPCHK(hipMemcpyAsync(ctx->d_halo, all.data(), all.size() * 4, hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+  }
   ctx->partitioned = true;
   return PE_OK;
 }
@@ -656,7 +707,10 @@ pe_status pe_rhs(pe_ctx* ctx, const double* u, double* du, void* stream) {
   a.Kout = du;
   a.first = 1;          // F(U): stage values are U itself (src 0 for every member)
   a.n_act = ctx->n_e;
+  a.Fv = ctx->Fv;
   Mesh m = device_mesh(ctx);
+  if (ctx->equations == 1)
+    HIPCHK(launch_gradients(ctx->dim, ctx->N, a, m, ctx->ops, ctx->ph, (hipStream_t)stream));
   HIPCHK(launch_stage(ctx->dim, ctx->N, ctx->equations == 1, a, m, ctx->ops, ctx->ph, (hipStream_t)stream));
   return PE_OK;
 }
@@ -703,8 +757,14 @@ pe_status pe_step(pe_ctx* ctx, double dt, int n_steps, void* stream) {
       a.ACC = ctx->ACC;
       a.Uout = in_place ? ctx->U : ctx->Tmp;
       a.evals = ctx->d_evals;
-      if (!a.U || !a.K1 || !a.Yin || !a.Yout || !a.ACC || !a.Uout)
+      a.Fv = ctx->Fv;
+      if (!a.U || !a.K1 || !a.Yin || !a.Yout || !a.ACC || !a.Uout || (ctx->equations == 1 && !a.Fv))
         return fail(ctx, PE_ESTATE, "step: stage buffers not bound");
+      if (ctx->equations == 1) {
+        a.n_halo = ctx->halo_cnt[i];
+        a.halo = ctx->d_halo + ctx->halo_off[i];
+        HIPCHK(launch_gradients(ctx->dim, ctx->N, a, m, ctx->ops, ctx->ph, s));
+      }
       if (ctx->profiling && a.n_act > 0) {
         pe_status st = prof_event(ctx, s);
         if (st != PE_OK) return st;

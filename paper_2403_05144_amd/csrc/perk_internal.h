@@ -64,7 +64,8 @@ struct StageArgs {
   double* ACC;            // running sum of b_j K_j over the stages with b_j != 0 before the last
   double* Uout;           // U_{n+1} at the last stage (may alias U)
   double* Kout;           // if non-null: K_i is written here and nothing else (right-hand side)
-  const double* Q;        // BR1 gradients [dim][dim+1][slot][node] (Navier-Stokes)
+  double* Fv;             // BR1 viscous flux [dim][n_v][slot][node] (Navier-Stokes; written by the
+                          // gradient kernel, read by the stage kernel)
   int32_t* evals;         // [slot] right-hand-side evaluations of the slot's element, or null
   int n_act;              // active slots: [0, n_act)
   int n_halo;             // Navier-Stokes gradient kernel only: extra slots listed in halo
@@ -86,8 +87,10 @@ struct StageArgs {
 // Kernel launch wrappers (perk_kernels.hip).  All return hipError_t.
 hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,
                         const Physics& ph, hipStream_t s);
+// BR1 gradient pass over slots [0, n_act) and the n_halo slots of `halo`: lifted gradients of
+// w = (v, T) with central face values, then the viscous flux F_v at every node into a.Fv.
 hipError_t launch_gradients(int dim, int N, const StageArgs& a, const Mesh& m, const Ops& op,
-                            const Physics& ph, double* Q, hipStream_t s);
+                            const Physics& ph, hipStream_t s);
 
 struct PartitionArgs {
   const int32_t* lev_leaf;       // [n] level per leaf

@@ -238,6 +238,9 @@ __global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB)) void k_stage(Sta
   __shared__ double s_pf[EPB][NP][NV];
   __shared__ int s_fk[EPB][NFC];
   __shared__ int s_fn[EPB][NFC][4];
+  // BR1: own viscous flux at every node and the neighbours' viscous face traces
+  __shared__ double s_fv[VISC ? EPB : 1][VISC ? DIM : 1][VISC ? NV : 1][VISC ? ND : 1];
+  __shared__ double s_trv[VISC ? EPB : 1][VISC ? NFC : 1][VISC ? NSUB : 1][VISC ? NV : 1][VISC ? NF : 1];
 
   const int le = threadIdx.x / T;
   const int lane = threadIdx.x - le * T;
@@ -294,6 +297,13 @@ __global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB)) void k_stage(Sta
       const int src = a.src[member_of_slot(m, nb)];
       const int nn = face_node<DIM, N>(d, 1 - side, j);
       s_tr[le][f][sub][v][j] = stage_value(a, src, ((int64_t)v * ld + nb) * ND + nn);
+      if (VISC) s_trv[le][f][sub][v][j] = a.Fv[(((int64_t)d * NV + v) * ld + nb) * ND + nn];
+    }
+    if (VISC) {
+      for (int w = lane; w < DIM * NV * ND; w += T) {
+        const int nd = w % ND, v = (w / ND) % NV, d = w / (ND * NV);
+        s_fv[le][d][v][nd] = a.Fv[(((int64_t)d * NV + v) * ld + e) * ND + nd];
+      }
     }
   }
   __syncthreads();
@@ -333,6 +343,23 @@ __global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB)) void k_stage(Sta
         }
       }
       s_tr[le][f][1][v][j] = val;
+      if (VISC) {
+        double vv = 0.0;
+        if (DIM == 2) {
+#pragma unroll
+          for (int k = 0; k < N; ++k) vv += op.P[s0][j * N + k] * s_trv[le][f][0][v][k];
+        } else {
+          const int ja = j % N, jb = j / N;
+#pragma unroll
+          for (int kb = 0; kb < N; ++kb) {
+            double row = 0.0;
+#pragma unroll
+            for (int ka = 0; ka < N; ++ka) row += op.P[s0][ja * N + ka] * s_trv[le][f][0][v][ka + N * kb];
+            vv += op.P[s1][jb * N + kb] * row;
+          }
+        }
+        s_trv[le][f][1][v][j] = vv;
+      }
     }
   }
   __syncthreads();
@@ -412,6 +439,35 @@ __global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB)) void k_stage(Sta
         else hll_flux<DIM>(oth, mine, d, gamma, fl);
 #pragma unroll
         for (int v = 0; v < NV; ++v) s_tr[le][f][sub][v][j] = fl[v];
+        if (VISC) {
+          // BR1 central viscous flux on this (sub-)face node: 1/2 (own + neighbour)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            double ownv;
+            if (kind == kCoarseSide) {
+              const int m0 = sub & 1, m1 = (sub >> 1) & 1;
+              ownv = 0.0;
+              if (DIM == 2) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) ownv += op.P[m0][j * N + k] * s_fv[le][d][v][face_node<DIM, N>(d, side, k)];
+              } else {
+                const int ja = j % N, jb = j / N;
+#pragma unroll
+                for (int kb = 0; kb < N; ++kb) {
+                  double row = 0.0;
+#pragma unroll
+                  for (int ka = 0; ka < N; ++ka)
+                    row += op.P[m0][ja * N + ka] * s_fv[le][d][v][face_node<DIM, N>(d, side, ka + N * kb)];
+                  ownv += op.P[m1][jb * N + kb] * row;
+                }
+              }
+            } else {
+              ownv = s_fv[le][d][v][face_node<DIM, N>(d, side, j)];
+            }
+            const int ts = kind == kFineSide ? 1 : sub;
+            s_trv[le][f][sub][v][j] = 0.5 * (ownv + s_trv[le][f][ts][v][j]);
+          }
+        }
       }
     }
   }
@@ -469,6 +525,43 @@ __global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB)) void k_stage(Sta
         acc += pos == N - 1 ? iwN * fs : -iw0 * fs;
       }
       du -= J[d] * acc;
+      if (VISC) {
+        double vacc = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < N; ++mm) vacc += op.D[pos * N + mm] * s_fv[le][d][v][node_on_line<DIM, N>(d, line, mm)];
+        if (pos == N - 1 || pos == 0) {
+          const int f = 2 * d + (pos == N - 1 ? 1 : 0);
+          const int fi = face_index<DIM, N>(nd, d);
+          double fs;
+          if (face_kind(s_fk[le][f]) == kCoarseSide) {
+            fs = 0.0;
+            if (DIM == 2) {
+#pragma unroll
+              for (int ms = 0; ms < 2; ++ms)
+#pragma unroll
+                for (int k = 0; k < N; ++k) fs += op.R[ms][fi * N + k] * s_trv[le][f][ms][v][k];
+            } else {
+              const int ja = fi % N, jb = fi / N;
+#pragma unroll
+              for (int ms = 0; ms < 4; ++ms) {
+                const int m0 = ms & 1, m1 = (ms >> 1) & 1;
+#pragma unroll
+                for (int kb = 0; kb < N; ++kb) {
+                  double row = 0.0;
+#pragma unroll
+                  for (int ka = 0; ka < N; ++ka) row += op.R[m0][ja * N + ka] * s_trv[le][f][ms][v][ka + N * kb];
+                  fs += op.R[m1][jb * N + kb] * row;
+                }
+              }
+            }
+          } else {
+            fs = s_trv[le][f][0][v][fi];
+          }
+          const double jump = fs - s_fv[le][d][v][nd];
+          vacc += pos == N - 1 ? iwN * jump : -iw0 * jump;
+        }
+        du += J[d] * vacc;
+      }
     }
     const int64_t idx = ((int64_t)v * ld + e) * ND + nd;
     if (a.Kout) {
@@ -486,6 +579,208 @@ __global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB)) void k_stage(Sta
       a.Yout[idx] = un[it] + a.dt * (a.a1[my_mem] * K1v + a.a2[my_mem] * du);
     }
   }
+}
+
+// ------------------------------------------------------------------------------------------
+// BR1 gradient kernel (Navier-Stokes).  One element per block.  w = (v_1..v_d, T), T = p/rho:
+//   q_d = (2/h_d) [ D w along d + lifting of (w* - w) at the two boundary nodes ],
+// w* the central average of the two traces (interpolated to, and projected back from, the
+// sub-faces of a mortar); then the viscous flux F_v(w, q) in every direction at every node:
+//   tau = mu (grad v + grad v^T) - 2/3 mu (div v) I, F_v,d = (0, tau_{:,d}, tau_{:,d}.v + kappa dT/dx_d).
+// ------------------------------------------------------------------------------------------
+template <int DIM, int N>
+struct GKc {
+  using g = G<DIM, N>;
+  static constexpr int ND = g::ND, NF = g::NF, NFC = g::NFC, NV = g::NV, NSUB = g::NSUB, NW = DIM + 1;
+  static constexpr int T = DIM == 2 ? 64 : 256;
+};
+
+template <int DIM>
+__device__ __forceinline__ void grad_vars(const double* u, double gamma, double* w) {
+  double rho, v[DIM], p;
+  cons_to_prim<DIM>(u, gamma, rho, v, p);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) w[d] = v[d];
+  w[DIM] = p / rho;
+}
+
+template <int DIM, int N>
+__global__ __launch_bounds__((GKc<DIM, N>::T)) void k_grad(StageArgs a, Mesh m, Ops op, Physics ph) {
+  using K = GKc<DIM, N>;
+  constexpr int ND = K::ND, NF = K::NF, NFC = K::NFC, NV = K::NV, NSUB = K::NSUB, NW = K::NW, T = K::T;
+  __shared__ double s_w[NW][ND];
+  __shared__ double s_tr[NFC][NSUB][NV][NF];
+  __shared__ double s_q[DIM][NW][ND];
+  __shared__ int s_fk[NFC];
+  __shared__ int s_fn[NFC][4];
+  const int b = blockIdx.x;
+  const int e = b < a.n_act ? b : a.halo[b - a.n_act];
+  const int lane = threadIdx.x;
+  const int ld = m.ld;
+  const double gamma = ph.gamma;
+  const int my_src = a.src[member_of_slot(m, e)];
+  const int lev = m.lev[e];
+  if (lane < NFC) s_fk[lane] = m.fk[(int64_t)e * NFC + lane];
+  if (lane < NFC * 4) s_fn[lane / 4][lane % 4] = m.fn[(int64_t)e * NFC * 4 + lane];
+  for (int nd = lane; nd < ND; nd += T) {
+    double u[NV], w[NW];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = stage_value(a, my_src, ((int64_t)v * ld + e) * ND + nd);
+    grad_vars<DIM>(u, gamma, w);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s_w[k][nd] = w[k];
+  }
+  __syncthreads();
+  // neighbour traces, converted to w at the trace node
+  for (int it = lane; it < NSUB * NFC * NF; it += T) {
+    const int j = it % NF;
+    const int f = (it / NF) % NFC;
+    const int sub = it / (NF * NFC);
+    const int kind = face_kind(s_fk[f]);
+    if (sub > 0 && kind != kCoarseSide) continue;
+    const int nb = s_fn[f][sub];
+    const int d = f >> 1, side = f & 1;
+    const int src = a.src[member_of_slot(m, nb)];
+    const int nn = face_node<DIM, N>(d, 1 - side, j);
+    double u[NV], w[NW];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = stage_value(a, src, ((int64_t)v * ld + nb) * ND + nn);
+    grad_vars<DIM>(u, gamma, w);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s_tr[f][sub][k][j] = w[k];
+  }
+  __syncthreads();
+  // fine sides: coarse w trace interpolated to the sub-face (into sub-slot 1)
+  for (int it = lane; it < NFC * NW * NF; it += T) {
+    const int j = it % NF, k = (it / NF) % NW, f = it / (NF * NW);
+    const int32_t pk = s_fk[f];
+    if (face_kind(pk) != kFineSide) continue;
+    const int s0 = face_sub0(pk), s1 = face_sub1(pk);
+    double val = 0.0;
+    if (DIM == 2) {
+#pragma unroll
+      for (int q = 0; q < N; ++q) val += op.P[s0][j * N + q] * s_tr[f][0][k][q];
+    } else {
+      const int ja = j % N, jb = j / N;
+#pragma unroll
+      for (int kb = 0; kb < N; ++kb) {
+        double row = 0.0;
+#pragma unroll
+        for (int ka = 0; ka < N; ++ka) row += op.P[s0][ja * N + ka] * s_tr[f][0][k][ka + N * kb];
+        val += op.P[s1][jb * N + kb] * row;
+      }
+    }
+    s_tr[f][1][k][j] = val;
+  }
+  __syncthreads();
+  // central face values w* on every (sub-)face node, in place
+  for (int it = lane; it < NSUB * NFC * NF; it += T) {
+    const int j = it % NF;
+    const int f = (it / NF) % NFC;
+    const int sub = it / (NF * NFC);
+    const int kind = face_kind(s_fk[f]);
+    if (sub > 0 && kind != kCoarseSide) continue;
+    const int d = f >> 1, side = f & 1;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      double own;
+      if (kind == kCoarseSide) {
+        const int m0 = sub & 1, m1 = (sub >> 1) & 1;
+        own = 0.0;
+        if (DIM == 2) {
+#pragma unroll
+          for (int q = 0; q < N; ++q) own += op.P[m0][j * N + q] * s_w[k][face_node<DIM, N>(d, side, q)];
+        } else {
+          const int ja = j % N, jb = j / N;
+#pragma unroll
+          for (int kb = 0; kb < N; ++kb) {
+            double row = 0.0;
+#pragma unroll
+            for (int ka = 0; ka < N; ++ka) row += op.P[m0][ja * N + ka] * s_w[k][face_node<DIM, N>(d, side, ka + N * kb)];
+            own += op.P[m1][jb * N + kb] * row;
+          }
+        }
+      } else {
+        own = s_w[k][face_node<DIM, N>(d, side, j)];
+      }
+      const int ts = kind == kFineSide ? 1 : sub;
+      s_tr[f][sub][k][j] = 0.5 * (own + s_tr[f][ts][k][j]);
+    }
+  }
+  __syncthreads();
+  // lifted gradients
+  const double iw0 = 1.0 / op.w[0], iwN = 1.0 / op.w[N - 1];
+  for (int it = lane; it < DIM * NW * ND; it += T) {
+    const int nd = it % ND, k = (it / ND) % NW, d = it / (ND * NW);
+    int line, pos;
+    line_of<DIM, N>(nd, d, line, pos);
+    double acc = 0.0;
+#pragma unroll
+    for (int mm = 0; mm < N; ++mm) acc += op.D[pos * N + mm] * s_w[k][node_on_line<DIM, N>(d, line, mm)];
+    if (pos == N - 1 || pos == 0) {
+      const int f = 2 * d + (pos == N - 1 ? 1 : 0);
+      const int fi = face_index<DIM, N>(nd, d);
+      double ws;
+      if (face_kind(s_fk[f]) == kCoarseSide) {
+        ws = 0.0;
+        if (DIM == 2) {
+#pragma unroll
+          for (int ms = 0; ms < 2; ++ms)
+#pragma unroll
+            for (int q = 0; q < N; ++q) ws += op.R[ms][fi * N + q] * s_tr[f][ms][k][q];
+        } else {
+          const int ja = fi % N, jb = fi / N;
+#pragma unroll
+          for (int ms = 0; ms < 4; ++ms) {
+            const int m0 = ms & 1, m1 = (ms >> 1) & 1;
+#pragma unroll
+            for (int kb = 0; kb < N; ++kb) {
+              double row = 0.0;
+#pragma unroll
+              for (int ka = 0; ka < N; ++ka) row += op.R[m0][ja * N + ka] * s_tr[f][ms][k][ka + N * kb];
+              ws += op.R[m1][jb * N + kb] * row;
+            }
+          }
+        }
+      } else {
+        ws = s_tr[f][0][k][fi];
+      }
+      const double jump = ws - s_w[k][nd];
+      acc += pos == N - 1 ? iwN * jump : -iw0 * jump;
+    }
+    s_q[d][k][nd] = m.jac[lev][d] * acc;
+  }
+  __syncthreads();
+  // viscous flux at every node, every direction
+  for (int nd = lane; nd < ND; nd += T) {
+    double divv = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) divv += s_q[k][k][nd];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      double f[NV];
+      f[0] = 0.0;
+      double en = 0.0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        double tau = ph.mu * (s_q[d][k][nd] + s_q[k][d][nd]);
+        if (k == d) tau -= 2.0 / 3.0 * ph.mu * divv;
+        f[1 + k] = tau;
+        en += tau * s_w[k][nd];
+      }
+      f[DIM + 1] = en + ph.kappa * s_q[d][DIM][nd];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a.Fv[(((int64_t)d * NV + v) * ld + e) * ND + nd] = f[v];
+    }
+  }
+}
+
+template <int DIM, int N>
+hipError_t launch_grad_t(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s) {
+  const int blocks = a.n_act + a.n_halo;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_grad<DIM, N>), dim3(blocks), dim3(GKc<DIM, N>::T), 0, s, a, m, op, ph);
+  return hipGetLastError();
 }
 
 template <int DIM, int N, bool VISC>
@@ -708,16 +1003,26 @@ inline unsigned grid_for(int64_t total, int bs) { return (unsigned)((total + bs 
 
 hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,
                         const Physics& ph, hipStream_t s) {
-  if (viscous) return hipErrorNotSupported;
-  if (dim == 2 && N == 4) return launch_stage_t<2, 4, false>(a, m, op, ph, s);
-  if (dim == 2 && N == 3) return launch_stage_t<2, 3, false>(a, m, op, ph, s);
-  if (dim == 3 && N == 4) return launch_stage_t<3, 4, false>(a, m, op, ph, s);
-  if (dim == 3 && N == 3) return launch_stage_t<3, 3, false>(a, m, op, ph, s);
+  if (!viscous) {
+    if (dim == 2 && N == 4) return launch_stage_t<2, 4, false>(a, m, op, ph, s);
+    if (dim == 2 && N == 3) return launch_stage_t<2, 3, false>(a, m, op, ph, s);
+    if (dim == 3 && N == 4) return launch_stage_t<3, 4, false>(a, m, op, ph, s);
+    if (dim == 3 && N == 3) return launch_stage_t<3, 3, false>(a, m, op, ph, s);
+  } else {
+    if (dim == 2 && N == 4) return launch_stage_t<2, 4, true>(a, m, op, ph, s);
+    if (dim == 2 && N == 3) return launch_stage_t<2, 3, true>(a, m, op, ph, s);
+    if (dim == 3 && N == 4) return launch_stage_t<3, 4, true>(a, m, op, ph, s);
+    if (dim == 3 && N == 3) return launch_stage_t<3, 3, true>(a, m, op, ph, s);
+  }
   return hipErrorNotSupported;
 }
 
-hipError_t launch_gradients(int, int, const StageArgs&, const Mesh&, const Ops&, const Physics&, double*,
-                            hipStream_t) {
+hipError_t launch_gradients(int dim, int N, const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph,
+                            hipStream_t s) {
+  if (dim == 2 && N == 4) return launch_grad_t<2, 4>(a, m, op, ph, s);
+  if (dim == 2 && N == 3) return launch_grad_t<2, 3>(a, m, op, ph, s);
+  if (dim == 3 && N == 4) return launch_grad_t<3, 4>(a, m, op, ph, s);
+  if (dim == 3 && N == 3) return launch_grad_t<3, 3>(a, m, op, ph, s);
   return hipErrorNotSupported;
 }
 

@@ -1,0 +1,113 @@
+"""GPU vs oracle parity for compressible Navier-Stokes with BR1 (2D and 3D, 2:1 mortars),
+including the partitioned steps whose gradient pass covers the inactive face neighbours of the
+active elements, and the full 3D Taylor-Green mesh (7120 elements, p=3)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import perk_inputs as pin
+from oracle import dgsem as od
+from oracle import perk_coeffs as pc
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+from parity_util import flux_scale, rel_err, rhs_close as rhs_ok, state_close, worst  # noqa: E402
+
+
+def golden_family(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return pc.PerkFamily.from_json(json.load(f))
+
+
+def _mesh3d_small():
+    m = pin.uniform_mesh(3, (4, 4, 4), (-np.pi,) * 3, (np.pi,) * 3, 0)
+    sel = [r for r, (l, i, j, k) in enumerate(m.leaves.tolist()) if (i, j, k) in ((1, 1, 1), (2, 1, 1), (1, 2, 1))]
+    m.leaves = pin.refine_leaves(m.leaves, 3, sel)
+    return m
+
+
+def _tgv(o):
+    x = o.node_coords().transpose(1, 0, 2)
+    return pin.taylor_green(x[0], x[1], x[2]).transpose(1, 0, 2).copy()
+
+
+def _random2d(o, seed):
+    x = o.node_coords().transpose(1, 0, 2)
+    return pin.smooth_random_state(x, 2, seed).transpose(1, 0, 2).copy()
+
+
+CASES = {
+    "2d_forest_p3": (lambda: pin.random_forest_2d(11, n_root=4, max_level=2), 4, lambda o: _random2d(o, 7), 2e-2),
+    "2d_forest_p2": (lambda: pin.random_forest_2d(5, n_root=3, max_level=3), 3, lambda o: _random2d(o, 8), 2e-2),
+    "3d_mortar_p3": (_mesh3d_small, 4, _tgv, 1.0 / 1600),
+    "3d_mortar_p2": (_mesh3d_small, 3, _tgv, 1.0 / 1600),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_rhs_parity_ns(case):
+    from paper_2403_05144_amd import PerkSolver
+    mk, N, ic, mu = CASES[case]
+    mesh = mk()
+    o = od.Oracle(mesh, N, viscous=True, mu=mu, prandtl=0.72)
+    u0 = ic(o)
+    fam = pc.perk2_family([4, 8])
+    lv = mesh.leaves[:, 0]
+    mol = od.member_of_levels_paper_rule(np.arange(lv.max() + 1), 2)
+    s = PerkSolver(mesh, N - 1, fam, mol, equations=1, mu=mu, prandtl=0.72)
+    du_gpu = s.rhs_leaf(u0).cpu().numpy()
+    du_ora = o.rhs(u0)
+    assert rhs_ok(du_gpu, du_ora, flux_scale(o, u0)), rel_err(du_gpu, du_ora)
+
+
+@pytest.mark.parametrize("case,E,dt,n", [("2d_forest_p3", [2, 4, 8], 2e-3, 4), ("3d_mortar_p3", [4, 8], 1e-3, 2),
+                                         ("3d_mortar_p2", [4, 8], 1e-3, 2)])
+def test_step_parity_ns(case, E, dt, n):
+    from paper_2403_05144_amd import PerkSolver
+    mk, N, ic, mu = CASES[case]
+    mesh = mk()
+    o = od.Oracle(mesh, N, viscous=True, mu=mu, prandtl=0.72)
+    u0 = ic(o)
+    fam = pc.perk2_family(E)
+    lv = mesh.leaves[:, 0]
+    mol = od.member_of_levels_paper_rule(np.arange(lv.max() + 1), len(E))
+    s = PerkSolver(mesh, N - 1, fam, mol, equations=1, mu=mu, prandtl=0.72)
+    s.set_state(u0)
+    s.step(dt, n)
+    u = u0.copy()
+    member = np.asarray(mol)[lv]
+    for _ in range(n):
+        u = o.prk_step(u, dt, fam, member)
+    g = s.get_state().cpu().numpy()
+    sig = flux_scale(o, u0)
+    assert state_close(g, u, sig, n, dt), worst(g, u, sig, n, dt)
+
+
+def test_taylor_green_full_mesh():
+    # the 3D Navier-Stokes workload at full size: 16^3 roots with a seeded 2-level refined
+    # region (7120 elements, p=3), Re = 1600, Pr = 0.72, P-ERK2{4,8,16}: one RHS and one step
+    from paper_2403_05144_amd import PerkSolver
+    mesh = pin.mesh_taylor_green()
+    assert mesh.n_elements == 7120
+    mu = 1.0 / 1600
+    o = od.Oracle(mesh, 4, viscous=True, mu=mu, prandtl=0.72)
+    u0 = _tgv(o)
+    fam = golden_family("perk2_4_8_16_disk.json")
+    mol = [0, 1, 2]
+    s = PerkSolver(mesh, 3, fam, mol, equations=1, mu=mu, prandtl=0.72)
+    du_gpu = s.rhs_leaf(u0).cpu().numpy()
+    du_ora = o.rhs(u0)
+    assert rhs_ok(du_gpu, du_ora, flux_scale(o, u0)), rel_err(du_gpu, du_ora)
+    s.set_state(u0)
+    dt = 2e-3
+    s.step(dt, 1)
+    u1 = o.prk_step(u0, dt, fam, np.asarray(mol)[mesh.leaves[:, 0]])
+    g = s.get_state().cpu().numpy()
+    sig = flux_scale(o, u0)
+    assert state_close(g, u1, sig, 1, dt), worst(g, u1, sig, 1, dt)
+    tot, per = s.counters()
+    assert per == [4 * 3880, 8 * 1512, 16 * 1728]

@@ -339,3 +339,53 @@ def test_bruteforce_spectra_tiny_meshes():
     # one step is linear in the perturbation about a constant state: build D column by column
     D = _fd_jacobian(lambda v: o.prk_step(v, dt, fam, member), u0, eps=1e-6)
     assert np.max(np.abs(np.linalg.eigvals(D))) <= 1.0 + 1e-6
+
+
+# ------------------------------------------------------------------ viscous terms (BR1)
+def _shear_error(dim, n, mu=0.05):
+    mesh = pin.uniform_mesh(dim, (n,) * dim, (0.0,) * dim, (2 * np.pi,) * dim, 0)
+    o = od.Oracle(mesh, 4, viscous=True, mu=mu, prandtl=0.72)
+    y = o.node_coords()[:, 1]
+    u = np.zeros(o.shape)
+    u[:, 0] = 1.0
+    u[:, 1] = np.sin(y)
+    u[:, -1] = 1.0 / (GAMMA - 1) + 0.5 * np.sin(y) ** 2
+    du = o.rhs(u)
+    expect = np.zeros(o.shape)
+    expect[:, 1] = -mu * np.sin(y)
+    expect[:, -1] = mu * np.cos(2 * y)
+    # components that vanish exactly stay at round-off
+    zero = [v for v in range(o.nv) if v not in (1, o.nv - 1)]
+    assert np.max(np.abs(du[:, zero])) < 1e-12
+    return np.max(np.abs(du - expect)) / mu
+
+
+@pytest.mark.parametrize("dim,ns", [(2, (4, 8, 16)), (3, (2, 4, 8))])
+def test_viscous_shear_flow_closed_form(dim, ns):
+    # rho = p = 1, v = (sin y, 0[, 0]): the inviscid divergence vanishes and the viscous one is
+    # (0, -mu sin y, 0[, 0], mu cos 2y) (stress tau_xy = mu cos y, its work tau_xy v_x)
+    errs = [_shear_error(dim, n) for n in ns]
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert min(rates) > 2.0 and errs[-1] < 5e-2, (errs, rates)
+
+
+def test_heat_conduction_closed_form():
+    # v = 0, p = 1, T = 1 + 0.1 sin x sin y, rho = p / T: the only nonzero component is
+    # du_E = kappa Laplace(T) = -0.2 kappa sin x sin y
+    mu, pr = 0.05, 0.72
+    kappa = GAMMA * mu / ((GAMMA - 1) * pr)
+    errs = []
+    for n in (4, 8, 16):
+        mesh = pin.uniform_mesh(2, (n, n), (0.0, 0.0), (2 * np.pi, 2 * np.pi), 0)
+        o = od.Oracle(mesh, 4, viscous=True, mu=mu, prandtl=pr)
+        x = o.node_coords()
+        T = 1 + 0.1 * np.sin(x[:, 0]) * np.sin(x[:, 1])
+        u = np.zeros(o.shape)
+        u[:, 0] = 1.0 / T
+        u[:, -1] = 1.0 / (GAMMA - 1)
+        du = o.rhs(u)
+        assert np.max(np.abs(du[:, :3])) < 1e-12
+        expect = kappa * (-0.2 * np.sin(x[:, 0]) * np.sin(x[:, 1]))
+        errs.append(np.max(np.abs(du[:, 3] - expect)) / (0.2 * kappa))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > 2.0 and errs[-1] < 1e-2, (errs, rates)

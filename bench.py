@@ -187,53 +187,75 @@ def run(args):
 
     wl = WORKLOADS[args.workload]()
     mesh, deg, fam = wl["mesh"], wl["degree"], wl["fam"]
+    leaves_init = np.array(mesh.leaves, copy=True)
     N = deg + 1
     amr = wl.get("amr")
-    s = PerkSolver(mesh, deg, fam, wl["mol"], capacity=amr["capacity"] if amr else None,
-                   equations=wl.get("equations", 0), mu=wl.get("mu", 0.0))
     ic_leaf = lambda x: wl["ic"](x.transpose(1, 0, 2)).transpose(1, 0, 2).copy()
-    drv = None
-    if amr:
-        drv = AmrDriver(s, amr["level_min"], amr["level_max"], wl["mol"], amr["refine_above"],
-                        amr["coarsen_below"], amr["interval"])
-        drv.initial_mesh(ic_leaf, passes=3)
-    else:
-        s.set_state(ic_leaf(s.node_coords().cpu().numpy()))
-    u0 = s.get_state().cpu().numpy()
-    leaves0 = s.leaves().copy()
     dt = wl["dt"]
-    _log(f"workload {wl['name']}: {s.n_elements} elements, dt={dt:.5g}, family E={fam.E}, members/level {wl['mol']}")
-    dof_updates = [0]
     per_elem = (mesh.dim + 2) * N ** mesh.dim
 
-    def count(_k):
-        dof_updates[0] += s.n_elements * per_elem
+    def setup():
+        """Solver at the start of the measured run: initial mesh (and adaptation passes), IC, warmup."""
+        import perk_inputs as pin
+        m0 = pin.MeshDesc(mesh.dim, mesh.n_root, mesh.lo, mesh.hi, np.array(leaves_init, copy=True))
+        s = PerkSolver(m0, deg, fam, wl["mol"], capacity=amr["capacity"] if amr else None,
+                       equations=wl.get("equations", 0), mu=wl.get("mu", 0.0))
+        drv = None
+        if amr:
+            drv = AmrDriver(s, amr["level_min"], amr["level_max"], wl["mol"], amr["refine_above"],
+                            amr["coarsen_below"], amr["interval"])
+            drv.initial_mesh(ic_leaf, passes=3)
+        else:
+            s.set_state(ic_leaf(s.node_coords().cpu().numpy()))
+        return s, drv
 
-    for k in range(args.warmup):
-        s.step(dt, 1)
+    def run_steps(s, drv, n, acc):
+        for k in range(1, n + 1):
+            s.step(dt, 1)
+            acc["dof"] += s.n_elements * per_elem
+            if drv and drv.interval and k % drv.interval == 0:
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                drv.adapt_once()
+                torch.cuda.synchronize()
+                acc["amr_s"] += time.perf_counter() - ta
+                acc["n_adapt"] += 1
+
+    s, drv = setup()
+    u0 = s.get_state().cpu().numpy()
+    leaves0 = s.leaves().copy()
+    _log(f"workload {wl['name']}: {s.n_elements} elements, dt={dt:.5g}, family E={fam.E}, members/level {wl['mol']}")
+    warm = {"dof": 0, "amr_s": 0.0, "n_adapt": 0}
+    run_steps(s, drv, args.warmup, warm)
     torch.cuda.synchronize()
     s.counters(reset=True)
-    s.set_profiling(True)
-    n_adapt0 = drv.n_adapt if drv else 0
+    # timed region: the production path (one captured step replayed as a HIP graph)
+    acc = {"dof": 0, "amr_s": 0.0, "n_adapt": 0}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    if drv:
-        drv.run(dt, args.steps, on_step=count)
-    else:
-        for _ in range(args.steps):
-            s.step(dt, 1)
-            count(0)
+    run_steps(s, drv, args.steps, acc)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kern_ms, launches, elem_stages = s.profile_stats()
-    s.set_profiling(False)
     tot_evals, per_member = s.counters()
+    n_elements_end = s.n_elements
     u_end = s.get_state().cpu().numpy()
     if not np.all(np.isfinite(u_end)):
         raise RuntimeError("non-finite state after the timed steps")
+    dof_timed, amr_s, n_adapt_timed = acc["dof"], acc["amr_s"], acc["n_adapt"]
+    # profiled region: the same run again from the same start, every stage launch bracketed by
+    # HIP events on the launch stream
+    del s, drv
+    s, drv = setup()
+    run_steps(s, drv, args.warmup, dict(warm))
+    torch.cuda.synchronize()
+    s.set_profiling(True)
+    run_steps(s, drv, args.steps, {"dof": 0, "amr_s": 0.0, "n_adapt": 0})
+    torch.cuda.synchronize()
+    kern_ms, launches, elem_stages = s.profile_stats()
+    s.set_profiling(False)
     wall = t1 - t0
     nv = mesh.dim + 2
-    value = dof_updates[0] / wall
+    value = dof_timed / wall
     n_rhs_actual = tot_evals * nv * N ** mesh.dim
     pid = wall / n_rhs_actual
     avg_launch_s = kern_ms * 1e-3 / max(1, launches)
@@ -258,11 +280,12 @@ def run(args):
         "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl["name"], "description": wl["desc"], "elements_start": int(leaves0.shape[0]),
-                   "elements_end": int(s.n_elements), "degree": deg, "family_E": list(fam.E), "order": fam.order,
+                   "elements_end": int(n_elements_end), "degree": deg, "family_E": list(fam.E), "order": fam.order,
                    "dt": dt, "member_of_level": [int(m) for m in wl["mol"]],
-                   "adaptations_timed": (drv.n_adapt - n_adapt0) if drv else 0},
+                   "adaptations_timed": n_adapt_timed},
         "pid_s": pid, "n_rhs_actual": n_rhs_actual,
-        "kernel_time_frac": kern_ms * 1e-3 / wall,
+        "stage_kernel_time_frac": kern_ms * 1e-3 / wall,
+        "adaptation_share": amr_s / wall,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
@@ -279,7 +302,19 @@ def main():
     ap.add_argument("--workload", default="kh_amr", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy this many bytes device-to-device once (calibration of HBM counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 8 * n, "copy_probe_bytes_written": 8 * n}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU design is "
               "documented but not built", file=sys.stderr)

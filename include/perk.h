@@ -152,8 +152,15 @@ pe_status pe_rhs(pe_ctx* ctx, const double* u_dev, double* du_dev, void* stream)
 /* Advance the bound state by n_steps partitioned P-ERK steps of size dt (eq.
  * PartitionedRKSystem with the tableaux of Sec. 3): stage i evaluates the right-hand side
  * only on the elements of the members that use stage i (a prefix of the slots); the
- * right-hand side of the other elements is never computed.  Asynchronous. */
+ * right-hand side of the other elements is never computed.  Asynchronous.  Unless graph replay
+ * is off or profiling is on, the step's launches are captured once into a HIP graph and
+ * replayed n_steps times on `stream`. */
 pe_status pe_step(pe_ctx* ctx, double dt, int n_steps, void* stream);
+
+/* pe_step replays one captured step as a HIP graph (captured again after every partition,
+ * binding, coefficient or dt change) when on != 0 (default), or enqueues every launch when 0.
+ * Results are identical either way. */
+pe_status pe_set_graph_replay(pe_ctx* ctx, int on);
 
 /* Element right-hand-side evaluations performed so far (device counter, read synchronously
  * on `stream`) in total and per member (out_per_member may be NULL, else [R]).  Multiplying by

@@ -7,7 +7,7 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libperk.so")
+LIB_PATH = os.environ.get("PERK_LIBRARY_PATH", os.path.join(_HERE, "libperk.so"))
 
 PE_OK = 0
 STATUS = {0: "PE_OK", -1: "PE_EINVAL", -2: "PE_ENOMEM", -3: "PE_EHIP", -4: "PE_ESTATE",
@@ -58,6 +58,7 @@ _SIGS = {
     "pe_adapt": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int8), ctypes.c_int, ctypes.c_int,
                                 ctypes.c_void_p]),
     "pe_get_leaves": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
+    "pe_set_graph_replay": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "pe_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "pe_profile_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),

@@ -62,6 +62,13 @@ struct pe_ctx {
   std::vector<int32_t> leaf_of_slot, slot_of_leaf, mem_of_slot;
   std::vector<int> n_act;               // [S]
   std::vector<int> halo_off, halo_cnt;  // [S] Navier-Stokes: inactive face neighbours of the active prefix
+  // replay of one captured step (HIP graph), valid until the partition, binding or dt changes
+  bool graphs_enabled = true;
+  bool graph_valid = false;
+  double graph_dt = 0.0;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool maps_on_host = false;            // leaf_of_slot / slot_of_leaf / mem_of_slot copied back
   // optional per-launch timing of the stage kernels with HIP events on the launch stream
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -71,6 +78,8 @@ struct pe_ctx {
   std::string err;
   ~pe_ctx() {
     for (auto e : ev_pool) (void)hipEventDestroy(e);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
 
@@ -437,6 +446,7 @@ pe_status pe_mesh_build(pe_ctx* ctx, const pe_mesh_desc* mesh) {
   ctx->have_mesh = false;
   ctx->bound = false;
   ctx->partitioned = false;
+  ctx->graph_valid = false;
   ctx->state_valid = false;
   for (int d = 0; d < 3; ++d) {
     ctx->n_root[d] = d < ctx->dim ? mesh->n_root[d] : 1;
@@ -508,6 +518,7 @@ pe_status pe_set_perk_coefficients(pe_ctx* ctx, const pe_perk_coeffs* co) {
           return fail(ctx, PE_EINVAL, "stage %d has b != 0 but member %d does not evaluate it", i + 1, r);
   ctx->have_coeffs = true;
   ctx->partitioned = false;
+  ctx->graph_valid = false;
   return PE_OK;
 }
 
@@ -538,10 +549,28 @@ pe_status pe_bind(pe_ctx* ctx, double* u_dev, void* ws, void* stream) {
   ctx->pending_leaf_state = false;
   HIPCHK(hipStreamSynchronize(s));
   ctx->bound = true;
+  ctx->graph_valid = false;
   ctx->partitioned = false;
+  ctx->graph_valid = false;
   ctx->state_valid = false;
   return PE_OK;
 }
+
+namespace {
+// slot maps and members back to the host (for element_info and the halo lists)
+pe_status copy_maps(pe_ctx* ctx, hipStream_t s) {
+  const int n = ctx->n_e;
+  ctx->leaf_of_slot.resize(n);
+  ctx->slot_of_leaf.resize(n);
+  ctx->mem_of_slot.resize(n);
+  HIPCHK(hipMemcpyAsync(ctx->leaf_of_slot.data(), ctx->d_leaf_of_slot, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(ctx->slot_of_leaf.data(), ctx->d_slot_of_leaf, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(ctx->mem_of_slot.data(), ctx->d_mem, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  ctx->maps_on_host = true;
+  return PE_OK;
+}
+}  // namespace
 
 pe_status pe_partition(pe_ctx* ctx, const int32_t* member_of_level, int n_levels, void* stream) {
   if (!ctx) return PE_EINVAL;
@@ -581,13 +610,12 @@ pe_status pe_partition(pe_ctx* ctx, const int32_t* member_of_level, int n_levels
     ctx->state_valid = true;
   }
   ctx->counts.assign(ctx->R, 0);
-  ctx->leaf_of_slot.resize(n);
-  ctx->slot_of_leaf.resize(n);
-  ctx->mem_of_slot.resize(n);
   HIPCHK(hipMemcpyAsync(ctx->counts.data(), ctx->d_counts, ctx->R * 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(ctx->leaf_of_slot.data(), ctx->d_leaf_of_slot, (size_t)n * 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(ctx->slot_of_leaf.data(), ctx->d_slot_of_leaf, (size_t)n * 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(ctx->mem_of_slot.data(), ctx->d_mem, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+  ctx->maps_on_host = false;
+  if (ctx->equations == 1) {
+    pe_status st = copy_maps(ctx, s);
+    if (st != PE_OK) return st;
+  }
   HIPCHK(hipStreamSynchronize(s));
   ctx->n_act.assign(ctx->S, 0);
   for (int i = 0; i < ctx->S; ++i)
@@ -644,6 +672,7 @@ pe_status pe_partition(pe_ctx* ctx, const int32_t* member_of_level, int n_levels
     }
   }
   ctx->partitioned = true;
+  ctx->graph_valid = false;
   return PE_OK;
 }
 
@@ -667,9 +696,14 @@ pe_status pe_get_state(pe_ctx* ctx, double* u_leaf, void* stream) {
   return PE_OK;
 }
 
-pe_status pe_element_info(const pe_ctx* ctx, int32_t* leaf_of_slot, int32_t* member_of_slot) {
+pe_status pe_element_info(const pe_ctx* cctx, int32_t* leaf_of_slot, int32_t* member_of_slot) {
+  pe_ctx* ctx = const_cast<pe_ctx*>(cctx);
   if (!ctx) return PE_EINVAL;
-  if (!ctx->partitioned) return fail(const_cast<pe_ctx*>(ctx), PE_ESTATE, "element_info before partition");
+  if (!ctx->partitioned) return fail(ctx, PE_ESTATE, "element_info before partition");
+  if (!ctx->maps_on_host) {
+    pe_status st = copy_maps(ctx, nullptr);
+    if (st != PE_OK) return st;
+  }
   if (leaf_of_slot) std::memcpy(leaf_of_slot, ctx->leaf_of_slot.data(), (size_t)ctx->n_e * 4);
   if (member_of_slot) std::memcpy(member_of_slot, ctx->mem_of_slot.data(), (size_t)ctx->n_e * 4);
   return PE_OK;
@@ -739,50 +773,99 @@ pe_status prof_collect(pe_ctx* ctx) {
 }
 }  // namespace
 
+namespace {
+// Enqueue the launches of one P-ERK step on stream s (optionally timing every stage launch).
+pe_status enqueue_step(pe_ctx* ctx, double dt, hipStream_t s, bool timed) {
+  Mesh m = device_mesh(ctx);
+  const bool in_place = last_stage_in_place_safe(ctx);
+  for (int i = 0; i < ctx->S; ++i) {
+    StageArgs a;
+    fill_stage(ctx, i, dt, a);
+    a.U = ctx->U;
+    a.K1 = ctx->K1;
+    a.Yin = (i % 2 == 0) ? ctx->Ya : ctx->Yb;
+    a.Yout = (i % 2 == 0) ? ctx->Yb : ctx->Ya;
+    a.ACC = ctx->ACC;
+    a.Uout = in_place ? ctx->U : ctx->Tmp;
+    a.evals = ctx->d_evals;
+    a.Fv = ctx->Fv;
+    if (!a.U || !a.K1 || !a.Yin || !a.Yout || !a.ACC || !a.Uout || (ctx->equations == 1 && !a.Fv))
+      return fail(ctx, PE_ESTATE, "step: stage buffers not bound");
+    if (ctx->equations == 1) {
+      a.n_halo = ctx->halo_cnt[i];
+      a.halo = ctx->d_halo + ctx->halo_off[i];
+      HIPCHK(launch_gradients(ctx->dim, ctx->N, a, m, ctx->ops, ctx->ph, s));
+    }
+    if (timed && a.n_act > 0) {
+      pe_status st = prof_event(ctx, s);
+      if (st != PE_OK) return st;
+    }
+    HIPCHK(launch_stage(ctx->dim, ctx->N, ctx->equations == 1, a, m, ctx->ops, ctx->ph, s));
+    if (timed && a.n_act > 0) {
+      pe_status st = prof_event(ctx, s);
+      if (st != PE_OK) return st;
+      ctx->prof_launches += 1;
+      ctx->prof_elem_stages += a.n_act;
+      if (ctx->ev_used >= 4096) {
+        st = prof_collect(ctx);
+        if (st != PE_OK) return st;
+      }
+    }
+  }
+  if (!in_place) HIPCHK(launch_copy(ctx->U, ctx->Tmp, state_doubles(ctx), s));
+  return PE_OK;
+}
+
+// Capture one step into an executable graph (on a private stream of default priority).
+pe_status capture_step(pe_ctx* ctx, double dt) {
+  if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  if (ctx->gexec) {
+    HIPCHK(hipGraphExecDestroy(ctx->gexec));
+    ctx->gexec = nullptr;
+  }
+  HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+  pe_status st = enqueue_step(ctx, dt, ctx->cap_stream, false);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+  if (st != PE_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  HIPCHK(e);
+  e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(e);
+  ctx->graph_valid = true;
+  ctx->graph_dt = dt;
+  return PE_OK;
+}
+}  // namespace
+
 pe_status pe_step(pe_ctx* ctx, double dt, int n_steps, void* stream) {
   if (!ctx) return PE_EINVAL;
   if (!ctx->partitioned || !ctx->state_valid) return fail(ctx, PE_ESTATE, "step needs a partition and a state");
   if (!(dt > 0.0) || n_steps < 0) return fail(ctx, PE_EINVAL, "step: dt must be > 0 and n_steps >= 0");
   hipStream_t s = (hipStream_t)stream;
-  Mesh m = device_mesh(ctx);
-  const bool in_place = last_stage_in_place_safe(ctx);
-  for (int step = 0; step < n_steps; ++step) {
-    for (int i = 0; i < ctx->S; ++i) {
-      StageArgs a;
-      fill_stage(ctx, i, dt, a);
-      a.U = ctx->U;
-      a.K1 = ctx->K1;
-      a.Yin = (i % 2 == 0) ? ctx->Ya : ctx->Yb;
-      a.Yout = (i % 2 == 0) ? ctx->Yb : ctx->Ya;
-      a.ACC = ctx->ACC;
-      a.Uout = in_place ? ctx->U : ctx->Tmp;
-      a.evals = ctx->d_evals;
-      a.Fv = ctx->Fv;
-      if (!a.U || !a.K1 || !a.Yin || !a.Yout || !a.ACC || !a.Uout || (ctx->equations == 1 && !a.Fv))
-        return fail(ctx, PE_ESTATE, "step: stage buffers not bound");
-      if (ctx->equations == 1) {
-        a.n_halo = ctx->halo_cnt[i];
-        a.halo = ctx->d_halo + ctx->halo_off[i];
-        HIPCHK(launch_gradients(ctx->dim, ctx->N, a, m, ctx->ops, ctx->ph, s));
-      }
-      if (ctx->profiling && a.n_act > 0) {
-        pe_status st = prof_event(ctx, s);
-        if (st != PE_OK) return st;
-      }
-      HIPCHK(launch_stage(ctx->dim, ctx->N, ctx->equations == 1, a, m, ctx->ops, ctx->ph, s));
-      if (ctx->profiling && a.n_act > 0) {
-        pe_status st = prof_event(ctx, s);
-        if (st != PE_OK) return st;
-        ctx->prof_launches += 1;
-        ctx->prof_elem_stages += a.n_act;
-        if (ctx->ev_used >= 4096) {
-          st = prof_collect(ctx);
-          if (st != PE_OK) return st;
-        }
-      }
+  if (ctx->profiling || !ctx->graphs_enabled) {
+    for (int step = 0; step < n_steps; ++step) {
+      pe_status st = enqueue_step(ctx, dt, s, ctx->profiling);
+      if (st != PE_OK) return st;
     }
-    if (!in_place) HIPCHK(launch_copy(ctx->U, ctx->Tmp, state_doubles(ctx), s));
+    return PE_OK;
   }
+  if (n_steps == 0) return PE_OK;
+  if (!ctx->graph_valid || ctx->graph_dt != dt) {
+    pe_status st = capture_step(ctx, dt);
+    if (st != PE_OK) return st;
+  }
+  for (int step = 0; step < n_steps; ++step) HIPCHK(hipGraphLaunch(ctx->gexec, s));
+  return PE_OK;
+}
+
+pe_status pe_set_graph_replay(pe_ctx* ctx, int on) {
+  if (!ctx) return PE_EINVAL;
+  ctx->graphs_enabled = on != 0;
+  ctx->graph_valid = false;
   return PE_OK;
 }
 
@@ -792,6 +875,7 @@ pe_status pe_reserve(pe_ctx* ctx, int64_t max_elements) {
   ctx->capacity = max_elements;
   ctx->bound = false;
   ctx->partitioned = false;
+  ctx->graph_valid = false;
   ctx->state_valid = false;
   ctx->pending_leaf_state = false;
   return PE_OK;
@@ -954,6 +1038,7 @@ pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags, int level_min, int level_ma
   HIPCHK(hipMemcpyAsync(ctx->d_lev_leaf, ctx->lev_leaf.data(), (size_t)nn * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   ctx->partitioned = false;
+  ctx->graph_valid = false;
   ctx->state_valid = false;
   ctx->pending_leaf_state = true;
   return PE_OK;

@@ -201,6 +201,9 @@ struct SK {
   static constexpr int T = DIM == 2 ? (N == 4 ? 64 : 32) : (N == 4 ? 384 : 192);
   static constexpr int EPB = T >= 64 ? 1 : 64 / T;
   static constexpr int NITEM = (NV * ND + T - 1) / T;         // (variable, node) items per lane
+  // waves per SIMD the register allocation must allow (forcing two 384-lane 3D blocks per CU
+  // spills registers and was measured slower than one block per CU)
+  static constexpr int MINW = 1;
 };
 
 // index of the unordered pair (a, b), a < b, among the N(N-1)/2 pairs of a line
@@ -228,7 +231,7 @@ __device__ __forceinline__ int node_on_line(int d, int line, int pos) {
 }
 
 template <int DIM, int N, bool VISC>
-__global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB)) void k_stage(StageArgs a, Mesh m, Ops op, Physics ph) {
+__global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB), (SK<DIM, N>::MINW)) void k_stage(StageArgs a, Mesh m, Ops op, Physics ph) {
   using K = SK<DIM, N>;
   constexpr int ND = K::ND, NF = K::NF, NFC = K::NFC, NV = K::NV, NSUB = K::NSUB, T = K::T, EPB = K::EPB;
   constexpr int NP = K::NP, NPL = K::NPL, NITEM = K::NITEM;

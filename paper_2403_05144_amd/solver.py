@@ -189,6 +189,9 @@ class PerkSolver:
         self.mesh.leaves = self._leaves
         self.partition(member_of_level)
 
+    def set_graph_replay(self, on):
+        self._check(self.lib.pe_set_graph_replay(self._ctx, int(bool(on))), "pe_set_graph_replay")
+
     def set_profiling(self, on):
         self._check(self.lib.pe_set_profiling(self._ctx, int(bool(on))), "pe_set_profiling")
 

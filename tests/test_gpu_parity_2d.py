@@ -188,3 +188,34 @@ def test_repeatable_bitwise():
         err, s, *_ = _stepping_case(2, [4, 8], pin.mesh_vortex_2level(), 4, _vortex_state, 0.02, 5)
         outs.append(s.get_state().cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_graph_replay_equals_eager_launches():
+    # every replay of the captured step equals the eagerly launched step bit for bit, with eager
+    # work and synchronisations between the replays; the graph is re-captured after a re-partition
+    import torch
+    mesh = pin.mesh_vortex_2level()
+    o = od.Oracle(mesh, 4)
+    u0 = _vortex_state(o)
+    fam = pc.perk3_family([3, 6], {E: pc.optimize_alpha(-1.0 + np.exp(1j * np.linspace(0, np.pi, 100)), 3, E)[1]
+                                   for E in (3, 6)})
+    g = _solver(mesh, 4, fam, [0, 1])
+    e = _solver(mesh, 4, fam, [0, 1])
+    e.set_graph_replay(False)
+    g.set_state(u0)
+    e.set_state(u0)
+    for k in range(4):
+        g.step(0.02, 1)
+        e.step(0.02, 1)
+        torch.cuda.synchronize()
+        a = g.get_state().cpu().numpy()
+        b = e.get_state().cpu().numpy()
+        assert np.array_equal(a, b), k
+        _ = torch.ones(1000, device="cuda").sum().item()   # unrelated eager work between replays
+    g.partition([1, 0])
+    e.partition([1, 0])
+    for k in range(3):
+        g.step(0.02, 1)
+        e.step(0.02, 1)
+        torch.cuda.synchronize()
+        assert np.array_equal(g.get_state().cpu().numpy(), e.get_state().cpu().numpy()), k

@@ -760,6 +760,18 @@ pe_status prof_event(pe_ctx* ctx, hipStream_t s) {
   return PE_OK;
 }
 
+// Next pair of pool events (start, end) for a dispatch-recorded kernel timing.
+pe_status prof_pair(pe_ctx* ctx, hipEvent_t* e0, hipEvent_t* e1) {
+  while (ctx->ev_pool.size() < ctx->ev_used + 2) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    ctx->ev_pool.push_back(e);
+  }
+  *e0 = ctx->ev_pool[ctx->ev_used++];
+  *e1 = ctx->ev_pool[ctx->ev_used++];
+  return PE_OK;
+}
+
 // Sum the event pairs recorded so far (waits for them).
 pe_status prof_collect(pe_ctx* ctx) {
   for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
@@ -797,19 +809,19 @@ pe_status enqueue_step(pe_ctx* ctx, double dt, hipStream_t s, bool timed) {
       HIPCHK(launch_gradients(ctx->dim, ctx->N, a, m, ctx->ops, ctx->ph, s));
     }
     if (timed && a.n_act > 0) {
-      pe_status st = prof_event(ctx, s);
+      // events recorded by the dispatch itself around the stage kernel
+      hipEvent_t e0, e1;
+      pe_status st = prof_pair(ctx, &e0, &e1);
       if (st != PE_OK) return st;
-    }
-    HIPCHK(launch_stage(ctx->dim, ctx->N, ctx->equations == 1, a, m, ctx->ops, ctx->ph, s));
-    if (timed && a.n_act > 0) {
-      pe_status st = prof_event(ctx, s);
-      if (st != PE_OK) return st;
+      HIPCHK(launch_stage(ctx->dim, ctx->N, ctx->equations == 1, a, m, ctx->ops, ctx->ph, s, e0, e1));
       ctx->prof_launches += 1;
       ctx->prof_elem_stages += a.n_act;
       if (ctx->ev_used >= 4096) {
         st = prof_collect(ctx);
         if (st != PE_OK) return st;
       }
+    } else {
+      HIPCHK(launch_stage(ctx->dim, ctx->N, ctx->equations == 1, a, m, ctx->ops, ctx->ph, s));
     }
   }
   if (!in_place) HIPCHK(launch_copy(ctx->U, ctx->Tmp, state_doubles(ctx), s));

@@ -85,8 +85,9 @@ struct StageArgs {
 };
 
 // Kernel launch wrappers (perk_kernels.hip).  All return hipError_t.
+// ev0/ev1 (optional): events recorded by the dispatch itself at kernel start and end
 hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,
-                        const Physics& ph, hipStream_t s);
+                        const Physics& ph, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // BR1 gradient pass over slots [0, n_act) and the n_halo slots of `halo`: lifted gradients of
 // w = (v, T) with central face values, then the viscous flux F_v at every node into a.Fv.
 hipError_t launch_gradients(int dim, int N, const StageArgs& a, const Mesh& m, const Ops& op,

@@ -22,6 +22,8 @@
 // consecutive elements, so every state access of the own element is one coalesced segment
 // per variable.
 
+#include <hip/hip_ext.h>
+
 #include "perk_internal.h"
 
 namespace perk {
@@ -71,6 +73,16 @@ __device__ __forceinline__ int face_index(int nd, int d) {
   return i + N * j;
 }
 
+// Reciprocal: hardware estimate refined by two Newton steps with FMA (within one ulp of 1/x for
+// the positive, normal arguments used here: densities, pressures, sums of them, wave-speed gaps).
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Logarithmic mean (a - b)/(ln a - ln b) from precomputed node logarithms.  With
 // f = (a-b)/(a+b), u = f^2 it equals (a+b) / (2 F(u)), F(u) = sum_k u^k/(2k+1); for u < 1e-2
 // the series through u^7/15 is used (truncation < 1e-17), so the difference of logarithms is
@@ -83,19 +95,20 @@ __device__ __forceinline__ double series_F(double u) {
 __device__ __forceinline__ double log_mean(double a, double b, double la, double lb) {
   const double dd = a - b, ss = a + b;
   if (dd * dd < 1e-2 * ss * ss) {
-    const double f = dd / ss;
-    return ss / (2.0 * series_F(f * f));
+    const double f = dd * rcp(ss);
+    return 0.5 * ss * rcp(series_F(f * f));
   }
-  return dd / (la - lb);
+  return dd * rcp(la - lb);
 }
 
 __device__ __forceinline__ double inv_log_mean(double a, double b, double la, double lb) {
   const double dd = a - b, ss = a + b;
+  const double iss = rcp(ss);
   if (dd * dd < 1e-2 * ss * ss) {
-    const double f = dd / ss;
-    return 2.0 * series_F(f * f) / ss;
+    const double f = dd * iss;
+    return 2.0 * series_F(f * f) * iss;
   }
-  return (la - lb) / dd;
+  return (la - lb) * rcp(dd);
 }
 
 template <int DIM>
@@ -106,7 +119,7 @@ struct NodeQ {
 template <int DIM>
 __device__ __forceinline__ void cons_to_prim(const double* u, double gamma, double& rho, double* v, double& p) {
   rho = u[0];
-  const double ir = 1.0 / rho;
+  const double ir = rcp(rho);
   double ke = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
@@ -140,7 +153,7 @@ __device__ __forceinline__ void hll_flux(const double* uL, const double* uR, int
   double rl, vl[DIM], pl, rr, vr[DIM], pr;
   cons_to_prim<DIM>(uL, gamma, rl, vl, pl);
   cons_to_prim<DIM>(uR, gamma, rr, vr, pr);
-  const double cl = sqrt(gamma * pl / rl), cr = sqrt(gamma * pr / rr);
+  const double cl = sqrt(gamma * pl * rcp(rl)), cr = sqrt(gamma * pr * rcp(rr));
   const double sl = fmin(vl[d] - cl, vr[d] - cr);
   const double sr = fmax(vl[d] + cl, vr[d] + cr);
   double fl[DIM + 2], fr[DIM + 2];
@@ -162,7 +175,7 @@ __device__ __forceinline__ void hll_flux(const double* uL, const double* uR, int
 #pragma unroll
     for (int v = 0; v < DIM + 2; ++v) f[v] = fr[v];
   } else {
-    const double inv = 1.0 / (sr - sl);
+    const double inv = rcp(sr - sl);
 #pragma unroll
     for (int v = 0; v < DIM + 2; ++v) f[v] = (sr * fl[v] - sl * fr[v] + sl * sr * (uR[v] - uL[v])) * inv;
   }
@@ -253,18 +266,32 @@ __global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB), (SK<DIM, N>::MIN
   const double gamma = ph.gamma;
   const double inv_gm1 = 1.0 / (gamma - 1.0);
 
-  // ---- A: connectivity, own values, epilogue operands
+  // ---- A+B: connectivity, own values and epilogue operands, neighbour traces, all in flight
+  //      together; one barrier before the node quantities
+  constexpr int NTRI = NSUB * NFC * NV * NF;             // trace items of the element
+  constexpr int NTR = (NTRI + T - 1) / T;                // per lane
   int my_mem = 0, my_src = 0;
   double J[DIM];
-  double own[NITEM], un[NITEM], k1[NITEM];
+  double un[NITEM], k1[NITEM];
   if (act) {
     my_mem = member_of_slot(m, e);
     my_src = a.src[my_mem];
-    const int lev = m.lev[e];
+    int tr_nb[NTR], tr_pk[NTR];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) J[d] = m.jac[lev][d];
+    for (int it = 0; it < NTR; ++it) {
+      const int w = lane + it * T;
+      tr_pk[it] = -1;
+      if (w < NTRI) {
+        const int f = (w / (NF * NV)) % NFC;
+        const int sub = w / (NF * NV * NFC);
+        tr_pk[it] = m.fk[(int64_t)e * NFC + f];
+        tr_nb[it] = m.fn[((int64_t)e * NFC + f) * 4 + sub];
+      }
+    }
+    const int lev = m.lev[e];
     if (lane < NFC) s_fk[le][lane] = m.fk[(int64_t)e * NFC + lane];
     if (lane < NFC * 4) s_fn[le][lane / 4][lane % 4] = m.fn[(int64_t)e * NFC * 4 + lane];
+    double own[NITEM];
 #pragma unroll
     for (int it = 0; it < NITEM; ++it) {
       const int w = lane + it * T;
@@ -277,25 +304,16 @@ __global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB), (SK<DIM, N>::MIN
         own[it] = my_src == 0 ? un[it] : (my_src == 1 ? a.Yin[idx] : un[it] + a.dt * a.ci * k1[it]);
       }
     }
-    if (lane == 0 && a.evals) a.evals[e] += 1;   // each slot belongs to exactly one block
-  }
-  __syncthreads();
-
-  // ---- B: own values to LDS, neighbour traces
-  if (act) {
 #pragma unroll
-    for (int it = 0; it < NITEM; ++it) {
+    for (int it = 0; it < NTR; ++it) {
       const int w = lane + it * T;
-      if (w < NV * ND) s_u[le][w / ND][w % ND] = own[it];
-    }
-    for (int w = lane; w < NSUB * NFC * NV * NF; w += T) {
+      if (w >= NTRI) continue;
       const int j = w % NF;
       const int v = (w / NF) % NV;
       const int f = (w / (NF * NV)) % NFC;
       const int sub = w / (NF * NV * NFC);
-      const int kind = face_kind(s_fk[le][f]);
-      if (sub > 0 && kind != kCoarseSide) continue;
-      const int nb = s_fn[le][f][sub];
+      if (sub > 0 && face_kind(tr_pk[it]) != kCoarseSide) continue;
+      const int nb = tr_nb[it];
       const int d = f >> 1, side = f & 1;
       const int src = a.src[member_of_slot(m, nb)];
       const int nn = face_node<DIM, N>(d, 1 - side, j);
@@ -308,6 +326,14 @@ __global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB), (SK<DIM, N>::MIN
         s_fv[le][d][v][nd] = a.Fv[(((int64_t)d * NV + v) * ld + e) * ND + nd];
       }
     }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) J[d] = m.jac[lev][d];
+#pragma unroll
+    for (int it = 0; it < NITEM; ++it) {
+      const int w = lane + it * T;
+      if (w < NV * ND) s_u[le][w / ND][w % ND] = own[it];
+    }
+    if (lane == 0 && a.evals) a.evals[e] += 1;   // each slot belongs to exactly one block
   }
   __syncthreads();
 
@@ -320,7 +346,7 @@ __global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB), (SK<DIM, N>::MIN
       NodeQ<DIM> q;
       cons_to_prim<DIM>(uu, gamma, q.rho, q.v, q.p);
       q.lrho = log(q.rho);
-      q.beta = q.rho / q.p;
+      q.beta = q.rho * rcp(q.p);
       q.lbeta = log(q.beta);
       s_q[le][w] = q;
     }
@@ -787,11 +813,15 @@ hipError_t launch_grad_t(const StageArgs& a, const Mesh& m, const Ops& op, const
 }
 
 template <int DIM, int N, bool VISC>
-hipError_t launch_stage_t(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s) {
+hipError_t launch_stage_t(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s,
+                          hipEvent_t ev0, hipEvent_t ev1) {
   using K = SK<DIM, N>;
   if (a.n_act <= 0) return hipSuccess;
   const int blocks = (a.n_act + K::EPB - 1) / K::EPB;
-  hipLaunchKernelGGL((k_stage<DIM, N, VISC>), dim3(blocks), dim3(K::T * K::EPB), 0, s, a, m, op, ph);
+  if (ev0)
+    hipExtLaunchKernelGGL((k_stage<DIM, N, VISC>), dim3(blocks), dim3(K::T * K::EPB), 0, s, ev0, ev1, 0, a, m, op, ph);
+  else
+    hipLaunchKernelGGL((k_stage<DIM, N, VISC>), dim3(blocks), dim3(K::T * K::EPB), 0, s, a, m, op, ph);
   return hipGetLastError();
 }
 
@@ -1005,17 +1035,17 @@ inline unsigned grid_for(int64_t total, int bs) { return (unsigned)((total + bs 
 }  // namespace
 
 hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,
-                        const Physics& ph, hipStream_t s) {
+                        const Physics& ph, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (!viscous) {
-    if (dim == 2 && N == 4) return launch_stage_t<2, 4, false>(a, m, op, ph, s);
-    if (dim == 2 && N == 3) return launch_stage_t<2, 3, false>(a, m, op, ph, s);
-    if (dim == 3 && N == 4) return launch_stage_t<3, 4, false>(a, m, op, ph, s);
-    if (dim == 3 && N == 3) return launch_stage_t<3, 3, false>(a, m, op, ph, s);
+    if (dim == 2 && N == 4) return launch_stage_t<2, 4, false>(a, m, op, ph, s, e0, e1);
+    if (dim == 2 && N == 3) return launch_stage_t<2, 3, false>(a, m, op, ph, s, e0, e1);
+    if (dim == 3 && N == 4) return launch_stage_t<3, 4, false>(a, m, op, ph, s, e0, e1);
+    if (dim == 3 && N == 3) return launch_stage_t<3, 3, false>(a, m, op, ph, s, e0, e1);
   } else {
-    if (dim == 2 && N == 4) return launch_stage_t<2, 4, true>(a, m, op, ph, s);
-    if (dim == 2 && N == 3) return launch_stage_t<2, 3, true>(a, m, op, ph, s);
-    if (dim == 3 && N == 4) return launch_stage_t<3, 4, true>(a, m, op, ph, s);
-    if (dim == 3 && N == 3) return launch_stage_t<3, 3, true>(a, m, op, ph, s);
+    if (dim == 2 && N == 4) return launch_stage_t<2, 4, true>(a, m, op, ph, s, e0, e1);
+    if (dim == 2 && N == 3) return launch_stage_t<2, 3, true>(a, m, op, ph, s, e0, e1);
+    if (dim == 3 && N == 4) return launch_stage_t<3, 4, true>(a, m, op, ph, s, e0, e1);
+    if (dim == 3 && N == 3) return launch_stage_t<3, 3, true>(a, m, op, ph, s, e0, e1);
   }
   return hipErrorNotSupported;
 }

@@ -87,7 +87,12 @@ def wl_vortex_2level():
 
 def wl_kh_amr(n_root=8, level_max=3, name="kh_amr_l3-6"):
     """Kelvin-Helmholtz shear layer, quadtree AMR between config levels 3 and 6 (forest levels
-    0..3 on 8x8 roots), P-ERK3{4,6,8,12,16}, adaptation every 10 steps."""
+    0..3 on 8x8 roots), P-ERK3{4,6,8,12,16}, adaptation every 10 steps.
+
+    Level -> member map: the required-step rule with margin 2 ({6,12,16,16} from coarse to
+    fine), stable up to CFL 1.0 of the finest member's optimal step over t in [0, 3]; with
+    margin 1 ({4,6,12,16}) the family is stable only up to CFL 0.5 (member boundaries at high
+    local CFL, Sec. 5).  The timed run uses CFL 0.9."""
     import perk_inputs as pin
     from paper_2403_05144_amd import partition_rule
     mesh = pin.uniform_mesh(2, (n_root, n_root), (-1, -1), (1, 1), 0)
@@ -95,36 +100,50 @@ def wl_kh_amr(n_root=8, level_max=3, name="kh_amr_l3-6"):
     h_red = 2.0 / n_root
     fam = family_for(f"perk3_4_6_8_12_16_kh_p3_n{n_root}", 3, [4, 6, 8, 12, 16],
                      pin.uniform_mesh(2, (n_root, n_root), (-1, -1), (1, 1), 0), 3, ic, h_red)
-    mol = partition_rule.required_dt_rule(level_max, fam.dt_opt, fam.E)
+    mol = partition_rule.required_dt_rule(level_max, fam.dt_opt, fam.E, margin=2.0)
+    mol1 = partition_rule.required_dt_rule(level_max, fam.dt_opt, fam.E, margin=1.0)
     h_min = h_red / 2 ** level_max
-    dt = 0.5 * fam.dt_opt[-1] * h_min / fam.h_ref
+    cfl = 0.9
+    dt = cfl * fam.dt_opt[-1] * h_min / fam.h_ref
     return dict(name=name, mesh=mesh, degree=3, fam=fam, mol=mol, ic=ic, dt=dt, t_final=3.0,
+                perk_maps=[("required-step rule, margin 2", mol), ("required-step rule, margin 1", mol1)],
                 amr=dict(level_min=0, level_max=level_max, interval=10, refine_above=0.05, coarsen_below=0.01,
                          capacity=(n_root << level_max) ** 2),
                 desc=f"2D Euler Kelvin-Helmholtz shear layer on [-1,1]^2 (rho 0.5/1, v_x +-0.5, tanh width "
                      f"0.05, seeded v_y perturbation 0.01), p=3, EC volume + HLL surface flux, quadtree AMR on "
                      f"a density-gradient indicator between levels {int(np.log2(n_root))} and "
                      f"{int(np.log2(n_root)) + level_max} every 10 steps with re-partition after every "
-                     f"adaptation, P-ERK3{{4,6,8,12,16}} at 50% of the optimised step (largest of 0.3/0.5/0.7 without blow-up)")
+                     f"adaptation, P-ERK3{{4,6,8,12,16}} with levels mapped to E={[fam.E[r] for r in mol]} "
+                     f"(required-step rule, margin 2), CFL {cfl} of the finest member's optimised step")
 
 
 def wl_tgv():
     """3D compressible Navier-Stokes Taylor-Green vortex, Ma 0.1, Re 1600, Pr 0.72, 16^3 roots
-    with a seeded 2-level refined region (7120 elements), p=3, BR1, P-ERK2{4,8,16}."""
+    with a seeded 2-level refined region (7120 elements), p=3, BR1, P-ERK2{4,8,16}.
+
+    Level -> member map: the required-step rule ({8,16,16} from coarse to fine), stable up to
+    CFL 0.8 of the finest member's optimal step over 200 steps, like the standalone
+    P-ERK2;16; the one-member-per-level map {4,8,16} is stable only up to CFL 0.4.  The timed
+    run uses CFL 0.7."""
     import perk_inputs as pin
+    from paper_2403_05144_amd import partition_rule
     mesh = pin.mesh_taylor_green()
     mu = 1.0 / 1600
     ic = lambda x: pin.taylor_green(x[0], x[1], x[2])
     red = pin.uniform_mesh(3, (2, 2, 2), (-np.pi,) * 3, (np.pi,) * 3, 0)
     fam = family_for("perk2_4_8_16_tgv_p3", 2, [4, 8, 16], red, 3, ic, np.pi, equations=1, mu=mu)
-    mol = [0, 1, 2]
-    dt = stable_dt(fam, mesh, mol, 0.5)
-    return dict(name="tgv_ns_3d", mesh=mesh, degree=3, fam=fam, mol=mol, ic=ic, dt=dt, t_final=None,
+    mol = partition_rule.required_dt_rule(2, fam.dt_opt, fam.E, margin=1.0)
+    h_min = 2 * np.pi / 16 / 4
+    cfl = 0.7
+    dt = cfl * fam.dt_opt[-1] * h_min / fam.h_ref
+    return dict(name="tgv_ns_3d", mesh=mesh, degree=3, fam=fam, mol=mol, ic=ic, dt=dt, t_final=200 * dt,
                 equations=1, mu=mu,
+                perk_maps=[("required-step rule", mol), ("one member per level", [0, 1, 2])],
                 desc="3D compressible Navier-Stokes Taylor-Green vortex (Ma 0.1, Re 1600, Pr 0.72) on "
                      "[-pi,pi]^3, 16^3 roots with a seeded 2-level refined region (3880+1512+1728 = 7120 "
-                     "elements), p=3, EC volume + HLL surface flux, BR1, P-ERK2{4,8,16} at 50% of the "
-                     "optimised step (largest of 0.9/0.7/0.5 without blow-up over 200 steps)")
+                     f"elements), p=3, EC volume + HLL surface flux, BR1, P-ERK2{{4,8,16}} with levels mapped "
+                     f"to E={[fam.E[r] for r in mol]} (required-step rule), CFL {cfl} of the finest member's "
+                     "optimised step")
 
 
 WORKLOADS = {"vortex_2level": wl_vortex_2level, "kh_amr": wl_kh_amr, "tgv": wl_tgv,
@@ -157,6 +176,305 @@ def cpu_baseline(wl, u0_leaf, leaves0, budget_s=15.0):
     return {"value": n * dofs / el, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} P-ERK steps of the same workload ({el:.1f} s, serial C++ oracle, dense "
                       f"masked stages: every stage evaluated on every element)"}
+
+
+# ----------------------------------------------------------------------------------------
+# P-ERK against single-level schemes on the same kernels, at equal error
+# ----------------------------------------------------------------------------------------
+def single_member_family(fam, r):
+    """Member r of a family run alone on every element (standalone P-ERK_{p;E_r})."""
+    from paper_2403_05144_amd import coeffs
+    return coeffs.Family(fam.order, fam.S, [fam.E[r]], np.asarray(fam.c), np.asarray(fam.b),
+                         np.asarray(fam.a_sub)[r:r + 1].copy(), [fam.dt_opt[r]], fam.h_ref)
+
+
+def standard_rk_family(fam):
+    """The order's classical low-storage scheme written in P-ERK form with S = E = p: the
+    explicit midpoint rule for p = 2, Shu-Osher SSPRK33 for p = 3 (c = (0, 1, 1/2),
+    a_{3,2} = a_{3,1} = 1/4, b = (1/6, 1/6, 2/3)).  Its CFL-1 step is the first member's optimal
+    step scaled by the stage ratio; the stability scan fixes the usable fraction."""
+    from paper_2403_05144_amd import coeffs
+    S = fam.order
+    a = np.zeros((1, S))
+    if S == 3:
+        a[0, 2] = 0.25
+    return coeffs.Family(fam.order, S, [S], coeffs.abscissae(fam.order, S), coeffs.weights(fam.order, S), a,
+                         [fam.dt_opt[0] * S / fam.E[0]], fam.h_ref)
+
+
+def _dt_cfl1(wl, fam1, mol1, levels):
+    m = wl["mesh"]
+    h = lambda l: (m.hi[0] - m.lo[0]) / (m.n_root[0] << int(l))
+    return min(fam1.dt_opt[mol1[int(l)]] * h(l) / fam1.h_ref for l in levels)
+
+
+def _steps_per_interval(spi, n_int):
+    """Integer step counts of n_int intervals that add up to round(spi * n_int)."""
+    edges = np.floor(np.arange(n_int + 1) * spi + 1e-9).astype(int)
+    return np.diff(edges)
+
+
+def _integrate(wl, fam1, mol1, start, T_int, n_int, spi, flags=None, record=False, reps=1):
+    """One run over [0, n_int T_int]: interval k takes its share of round(spi n_int) equal steps;
+    between intervals an adaptive workload adapts the mesh (recording the flags from the GPU
+    indicator, or replaying recorded ones).  Returns the wall time of the stepping and
+    adaptation (graph replay path; the smallest of `reps` runs, repeated on the same solver for
+    a static mesh and on a fresh one for an adaptive mesh), the final state and mesh, and the
+    element-RHS count."""
+    import torch
+    import perk_inputs as pin
+    from paper_2403_05144_amd import PerkError, PerkSolver
+    from paper_2403_05144_amd.amr import AmrDriver
+    m0 = wl["mesh"]
+    amr = wl.get("amr")
+    steps = _steps_per_interval(spi, n_int)
+    s, walls, rec, ok = None, [], [], True
+    for rep in range(reps):
+        if s is None or amr:
+            s = None
+            mesh = pin.MeshDesc(m0.dim, m0.n_root, m0.lo, m0.hi, np.array(start["leaves"], copy=True))
+            s = PerkSolver(mesh, wl["degree"], fam1, mol1, capacity=amr["capacity"] if amr else None,
+                           equations=wl.get("equations", 0), mu=wl.get("mu", 0.0))
+        s.set_state(start["u"])
+        drv = AmrDriver(s, amr["level_min"], amr["level_max"], mol1, amr["refine_above"], amr["coarsen_below"],
+                        0) if (amr and record and rep == 0) else None
+        s.counters(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            for k in range(n_int):
+                s.step(T_int / steps[k], int(steps[k]))
+                if amr and k < n_int - 1:
+                    if drv is not None:
+                        rec.append(drv.adapt_once())
+                    else:
+                        s.adapt((flags if flags is not None else rec)[k], amr["level_min"], amr["level_max"], mol1)
+            torch.cuda.synchronize()
+        except PerkError as e:
+            _log(f"run stopped: {e}")
+            ok = False
+            break
+        walls.append(time.perf_counter() - t0)
+    out = {"ok": ok, "wall": min(walls) if walls else float("nan"), "steps": int(steps.sum()), "flags": rec}
+    if ok:
+        out["u"] = s.get_state().cpu().numpy()
+        out["leaves"] = s.leaves()
+        out["w"] = s.node_weights()
+        out["element_rhs"] = s.counters()[0]
+    del s
+    return out
+
+
+def _stable(run, rho0_max):
+    if not run["ok"]:
+        return False
+    rho = run["u"][:, 0]
+    return bool(np.all(np.isfinite(run["u"])) and rho.min() > 0 and rho.max() < 2 * rho0_max)
+
+
+def _density_error(run, ref):
+    if ref.get("exact") is not None:
+        r_ref = ref["exact"](run)
+    else:
+        if not np.array_equal(run["leaves"], ref["leaves"]):
+            raise RuntimeError("compared runs ended on different meshes")
+        r_ref = ref["u"][:, 0]
+    d = np.abs(run["u"][:, 0] - r_ref)
+    return float(np.sum(run["w"] * d) / np.sum(run["w"])), float(d.max())
+
+
+CFL_SCAN = (1.0, 0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2, 0.15, 0.1)
+
+
+def compare_equal_error(wl, t_final=None, tol=0.05, ref_budget=6e8):
+    """Wall time of the P-ERK family against (a) the standalone P-ERK_{p;E_max} on every element
+    and (b) the order's classical scheme (explicit midpoint / SSPRK33), all on these kernels.
+    Every scheme runs at the largest CFL of CFL_SCAN that keeps the density finite, positive and
+    below twice its initial maximum over the horizon; the density error (quadrature L1 over the
+    domain, and nodal max) is taken against the exact solution where one exists (isentropic
+    vortex) and otherwise against the standalone P-ERK_{p;E_max} at an eighth of the finest step
+    used, on the same mesh sequence (adaptive meshes replay the P-ERK run's flags).  Of each
+    pair, the step of the less accurate scheme is then shrunk (secant on log error vs log step
+    count, then bisection) until the L1 errors agree within tol, and both are timed again.
+    The P-ERK family is tried with every level -> member map the workload lists; the one with
+    the shortest wall time at its largest stable CFL is compared.  A comparator whose reference
+    run would exceed ref_budget element-stage evaluations is left out (reported as such)."""
+    import perk_inputs as pin
+    import torch
+    from paper_2403_05144_amd import PerkSolver
+    from paper_2403_05144_amd.amr import AmrDriver
+    fam, mol, m0 = wl["fam"], wl["mol"], wl["mesh"]
+    amr = wl.get("amr")
+    R = len(fam.E)
+    # start state (adaptive workloads: the initial mesh built from the initial condition)
+    mesh = pin.MeshDesc(m0.dim, m0.n_root, m0.lo, m0.hi, np.array(m0.leaves, copy=True))
+    s = PerkSolver(mesh, wl["degree"], fam, mol, capacity=amr["capacity"] if amr else None,
+                   equations=wl.get("equations", 0), mu=wl.get("mu", 0.0))
+    ic_leaf = lambda x: wl["ic"](x.transpose(1, 0, 2)).transpose(1, 0, 2).copy()
+    if amr:
+        AmrDriver(s, amr["level_min"], amr["level_max"], mol, amr["refine_above"], amr["coarsen_below"],
+                  amr["interval"]).initial_mesh(ic_leaf, passes=3)
+    else:
+        s.set_state(ic_leaf(s.node_coords().cpu().numpy()))
+    start = {"leaves": s.leaves(), "u": s.get_state().cpu().numpy()}
+    torch.cuda.synchronize()
+    del s
+    rho0_max = float(start["u"][:, 0].max())
+    levels = range(amr["level_max"] + 1) if amr else np.unique(start["leaves"][:, 0])
+    if amr:
+        T_int = amr["interval"] * wl["dt"]
+        n_int = int(math.ceil((t_final or wl["t_final"]) / T_int))
+    else:
+        n_int = 1
+        T_int = t_final or wl["t_final"] or 200 * wl["dt"]
+    t_end = n_int * T_int
+    Lmax = int(max(levels))
+    schemes = {
+        "single_level": (single_member_family(fam, R - 1), [0] * (Lmax + 1)),
+        "standard_rk": (standard_rk_family(fam), [0] * (Lmax + 1)),
+    }
+    names = {"p_erk": f"P-ERK{fam.order} E={list(fam.E)}",
+             "single_level": f"standalone P-ERK{fam.order};{fam.E[-1]} on every element",
+             "standard_rk": "SSPRK33 (Shu-Osher)" if fam.order == 3 else "explicit midpoint RK2"}
+
+    def scan(key, f1, m1, flags, record):
+        dt1 = _dt_cfl1(wl, f1, m1, levels)
+        for cfl in CFL_SCAN:
+            spi = max(1.0, T_int / (cfl * dt1))
+            spi = float(math.ceil(spi * n_int - 1e-9)) / n_int
+            run = _integrate(wl, f1, m1, start, T_int, n_int, spi, flags=flags, record=record)
+            if _stable(run, rho0_max):
+                _log(f"equal-error: {key} largest stable CFL {cfl}, {run['steps']} steps")
+                return {"cfl_max": cfl, "spi": spi, "run": run}
+            _log(f"equal-error: {key} unstable at CFL {cfl}")
+        raise RuntimeError(f"{key}: no stable CFL in the scan")
+
+    # P-ERK: every candidate level -> member map at its largest stable CFL (adaptive meshes record
+    # their own flags); the fastest one is compared with the single-level schemes
+    candidates = []
+    for label, m1 in wl.get("perk_maps", [("workload map", list(mol))]):
+        c = scan(f"P-ERK ({label})", fam, list(m1), None, bool(amr))
+        t2 = _integrate(wl, fam, list(m1), start, T_int, n_int, c["spi"], flags=c["run"]["flags"] or None,
+                        reps=2 if amr else 5)
+        c.update(label=label, mol=list(m1), wall=min(c["run"]["wall"], t2["wall"]))
+        candidates.append(c)
+    best = min(candidates, key=lambda c: c["wall"])
+    schemes["p_erk"] = (fam, best["mol"])
+    flags = best["run"]["flags"] if amr else None
+    info = {"p_erk": best}
+    for key in ("single_level", "standard_rk"):
+        info[key] = scan(key, *schemes[key], flags, False)
+    skipped = {}
+    n_e0 = len(start["leaves"])
+    cost = 8 * max(v["spi"] for v in info.values()) * n_int * fam.E[-1] * n_e0
+    if wl["name"] != "vortex_2level" and cost > ref_budget:
+        info.pop("standard_rk")
+        skipped[names["standard_rk"]] = (f"not compared: a reference at 1/8 of its step would cost about "
+                                         f"{cost:.2g} element-stage evaluations")
+        _log(f"equal-error: {names['standard_rk']} skipped (reference cost {cost:.2g} element-stages)")
+    # reference
+    if wl["name"] == "vortex_2level":
+        x_cache = {}
+
+        def exact(run):
+            key = run["leaves"].tobytes()
+            if key not in x_cache:
+                mesh = pin.MeshDesc(m0.dim, m0.n_root, m0.lo, m0.hi, run["leaves"])
+                sx = PerkSolver(mesh, wl["degree"], fam, mol)
+                x = sx.node_coords().cpu().numpy().transpose(1, 0, 2)
+                x_cache[key] = pin.isentropic_vortex(x[0], x[1], t=t_end)[0].copy()
+                del sx
+            return x_cache[key]
+        ref = {"exact": exact, "what": "exact solution"}
+    else:
+        spi_ref = 8 * max(v["spi"] for v in info.values())
+        f1, m1 = schemes["single_level"]
+        _log(f"equal-error: reference run, {int(round(spi_ref * n_int))} steps")
+        rr = _integrate(wl, f1, m1, start, T_int, n_int, spi_ref, flags=flags)
+        if not _stable(rr, rho0_max):
+            raise RuntimeError("reference run unstable")
+        ref = {"u": rr["u"], "leaves": rr["leaves"], "what": f"{names['single_level']} with "
+               f"{rr['steps']} steps (1/8 of the finest step used), same mesh sequence"}
+    for v in info.values():
+        v["run"]["err"] = _density_error(v["run"], ref)
+    for c in candidates:             # other maps: own mesh sequence under adaptation, no common reference
+        if c is not best:
+            c["run"]["err"] = None if amr else _density_error(c["run"], ref)
+
+    def run_at(key, spi):
+        f1, m1 = schemes[key]
+        r = _integrate(wl, f1, m1, start, T_int, n_int, spi, flags=flags)
+        r["err"] = _density_error(r, ref)
+        return r
+
+    def summary(key, spi, r):
+        t2 = _integrate(wl, *schemes[key], start, T_int, n_int, spi, flags=flags, reps=2 if amr else 5)
+        return {"scheme": names[key], "steps": r["steps"], "dt_mean": t_end / r["steps"],
+                "err_L1": r["err"][0], "err_Linf": r["err"][1], "wall_s": min(r["wall"], t2["wall"]),
+                "element_rhs": r["element_rhs"]}
+
+    pairs = []
+    for other in [k for k in ("single_level", "standard_rk") if k in info]:
+        a = {"p_erk": (info["p_erk"]["spi"], info["p_erk"]["run"]),
+             other: (info[other]["spi"], info[other]["run"])}
+        worse = max(a, key=lambda k: a[k][1]["err"][0])
+        better = other if worse == "p_erk" else "p_erk"
+        target = a[better][1]["err"][0]
+        spi_w, r_w = a[worse]
+        close = lambda e: abs(e - target) <= tol * max(e, target)
+        lo, hi = (spi_w, r_w), None          # too coarse / finer than needed
+        hist = [(spi_w, r_w["err"][0])]
+        it = 0
+        while not close(r_w["err"][0]) and it < 10:
+            if hi is None:
+                if len(hist) >= 2 and hist[-1][1] != hist[-2][1]:
+                    (s1, e1), (s2, e2) = hist[-2], hist[-1]
+                    slope = min(-0.5, (math.log(e2) - math.log(e1)) / (math.log(s2) - math.log(s1)))
+                else:
+                    slope = -float(fam.order)
+                spi_new = lo[0] * (target / lo[1]["err"][0]) ** (1.0 / slope)
+                spi_new = max(lo[0] + 1.0 / n_int, float(math.ceil(spi_new * n_int - 1e-9)) / n_int)
+            else:
+                spi_new = float(round(0.5 * (lo[0] + hi[0]) * n_int)) / n_int
+                if spi_new <= lo[0] or spi_new >= hi[0]:
+                    break
+            r_new = run_at(worse, spi_new)
+            hist.append((spi_new, r_new["err"][0]))
+            spi_w, r_w = spi_new, r_new
+            if r_new["err"][0] > target:
+                lo = (spi_new, r_new)
+            else:
+                hi = (spi_new, r_new)
+            it += 1
+        if not close(r_w["err"][0]) and hi is not None:
+            spi_w, r_w = hi                   # nearest step count at which it is at least as accurate
+        a[worse] = (spi_w, r_w)
+        t_c = _integrate(wl, *schemes[other], start, T_int, n_int, info[other]["spi"], flags=flags,
+                         reps=2 if amr else 5)
+        wall_c_max = min(info[other]["run"]["wall"], t_c["wall"])
+        at_max = {"p_erk_steps": best["run"]["steps"], "comparator_steps": info[other]["run"]["steps"],
+                  "p_erk_wall_s": best["wall"], "comparator_wall_s": wall_c_max,
+                  "p_erk_err_L1": best["run"]["err"][0], "comparator_err_L1": info[other]["run"]["err"][0],
+                  "wall_ratio_comparator_over_p_erk": wall_c_max / best["wall"]}
+        sp, sc = summary("p_erk", *a["p_erk"]), summary(other, *a[other])
+        rel = abs(sc["err_L1"] - sp["err_L1"]) / max(sp["err_L1"], sc["err_L1"])
+        pairs.append({"at_cfl_max": at_max, "comparator": sc, "p_erk": sp, "comparator_cfl_max": info[other]["cfl_max"],
+                      "shrunk": worse, "err_L1_rel_diff": rel, "equal_error": bool(rel <= tol),
+                      "wall_ratio_comparator_over_p_erk": sc["wall_s"] / sp["wall_s"],
+                      "element_rhs_ratio": sc["element_rhs"] / sp["element_rhs"]})
+        _log(f"equal-error: {other}: wall ratio {sc['wall_s'] / sp['wall_s']:.3f} at L1 errors "
+             f"{sp['err_L1']:.3e} / {sc['err_L1']:.3e}")
+    cand_out = [{"map": c["label"], "E_of_level": [int(fam.E[r]) for r in c["mol"]], "cfl_max": c["cfl_max"],
+                 "steps": c["run"]["steps"], "wall_s_at_cfl_max": c["wall"], "element_rhs": c["run"]["element_rhs"],
+                 "err_L1": None if c["run"]["err"] is None else c["run"]["err"][0], "chosen": c is best}
+                for c in candidates]
+    return {"workload": wl["name"], "t_final": t_end, "p_erk_cfl_max": info["p_erk"]["cfl_max"],
+            "p_erk_maps": cand_out,
+            "cfl": "fraction of the scheme's own largest linearly stable step (optimised stability polynomial, "
+                   "element sizes of every level); largest value of the scan without blow-up over the horizon",
+            "error": f"density, quadrature L1 (domain mean) and nodal max, against the {ref['what']}",
+            "adaptation": "flags of the P-ERK run replayed in every run" if amr else "static mesh",
+            "pairs": pairs, "not_compared": skipped}
 
 
 def flops_per_element_stage(dim, N):
@@ -288,6 +606,9 @@ def run(args):
         "adaptation_share": amr_s / wall,
         "roofline": roof,
     }
+    if not args.no_equal_error:
+        _log("P-ERK against single-level schemes at equal error")
+        line["p_erk_vs_single_level"] = compare_equal_error(wl)
     if not args.no_cpu_baseline:
         _log("timing the oracle on the host (cpu_baseline)")
         line["cpu_baseline"] = cpu_baseline(wl, u0, leaves0, budget_s=args.cpu_seconds)
@@ -302,6 +623,8 @@ def main():
     ap.add_argument("--workload", default="kh_amr", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-equal-error", action="store_true",
+                    help="skip the comparison with single-level schemes at equal error")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device once (calibration of HBM counters)")
     args = ap.parse_args()

@@ -141,6 +141,10 @@ pe_status pe_get_state(pe_ctx* ctx, double* u_leaf_dev, void* stream);
  * Either pointer may be NULL. */
 pe_status pe_element_info(const pe_ctx* ctx, int32_t* leaf_of_slot, int32_t* member_of_slot);
 
+/* The 1D Legendre-Gauss-Lobatto nodes on [-1, 1] and quadrature weights used by the DGSEM
+ * (host arrays of degree+1 entries each; either may be NULL). */
+pe_status pe_quadrature(const pe_ctx* ctx, double* nodes, double* weights);
+
 /* Physical coordinates of every node in leaf layout, x_dev [leaf][dim][node] (device). */
 pe_status pe_node_coords(pe_ctx* ctx, double* x_leaf_dev, void* stream);
 

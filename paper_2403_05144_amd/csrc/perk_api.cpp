@@ -1056,6 +1056,15 @@ pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags, int level_min, int level_ma
   return PE_OK;
 }
 
+pe_status pe_quadrature(const pe_ctx* ctx, double* nodes, double* weights) {
+  if (!ctx) return PE_EINVAL;
+  for (int i = 0; i < ctx->N; ++i) {
+    if (nodes) nodes[i] = ctx->ops.x[i];
+    if (weights) weights[i] = ctx->ops.w[i];
+  }
+  return PE_OK;
+}
+
 pe_status pe_set_profiling(pe_ctx* ctx, int on) {
   if (!ctx) return PE_EINVAL;
   ctx->profiling = on != 0;

@@ -189,6 +189,25 @@ class PerkSolver:
         self.mesh.leaves = self._leaves
         self.partition(member_of_level)
 
+    def quadrature(self):
+        x = np.zeros(self.N)
+        w = np.zeros(self.N)
+        self._check(self.lib.pe_quadrature(self._ctx, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "pe_quadrature")
+        return x, w
+
+    def node_weights(self):
+        """Quadrature weight of every node in leaf layout, [n_leaves, nodes] (element volume included)."""
+        _, w = self.quadrature()
+        W = w
+        for _ in range(self.dim - 1):
+            W = np.multiply.outer(w, W).reshape(-1)
+        lv = self.leaves()[:, 0]
+        vol = np.ones(len(lv))
+        for d in range(self.dim):
+            vol = vol * (self.mesh.hi[d] - self.mesh.lo[d]) / (np.asarray(self.mesh.n_root[d]) * 2.0 ** lv) / 2.0
+        return vol[:, None] * W[None, :]
+
     def set_graph_replay(self, on):
         self._check(self.lib.pe_set_graph_replay(self._ctx, int(bool(on))), "pe_set_graph_replay")
 

@@ -219,3 +219,19 @@ def test_graph_replay_equals_eager_launches():
         e.step(0.02, 1)
         torch.cuda.synchronize()
         assert np.array_equal(g.get_state().cpu().numpy(), e.get_state().cpu().numpy()), k
+
+
+def test_quadrature_matches_oracle_and_integrates_area():
+    # the library's LGL rule equals the oracle's; node weights of a 2:1 mesh sum to its area and
+    # integrate the density like the oracle's quadrature
+    mesh = pin.mesh_vortex_2level()
+    o = od.Oracle(mesh, 4)
+    s = _solver(mesh, 4, pc.perk2_family([4, 8]), [0, 1])
+    x, w = s.quadrature()
+    xo, wo = od.lgl(4)[:2]
+    np.testing.assert_allclose(x, xo, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(w, wo, rtol=0, atol=1e-15)
+    W = s.node_weights()
+    assert abs(W.sum() - 100.0) <= 1e-12 * 100.0
+    u = _vortex_state(o)
+    assert abs(np.sum(W * u[:, 0]) - o.integral(u)[0]) <= 1e-12 * abs(o.integral(u)[0])

@@ -497,6 +497,29 @@ def bytes_per_element_stage(dim, N):
     return 4 * (dim + 2) * N ** dim * 8
 
 
+def measured_traffic(workload, es_per_launch):
+    """HBM bytes per stage-kernel launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary of this workload (each counter scaled by its reading for a plain copy of known
+    size), at this run's element-stages per launch.  None when there is no summary or the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_stage_{workload}_hbm_counters.txt")
+    src = os.path.join(ROOT, "paper_2403_05144_amd", "csrc", "perk_kernels.hip")
+    if not os.path.exists(path):
+        return None, "no counter summary for this workload"
+    rec = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("TRAFFIC "):
+                rec = json.loads(line[len("TRAFFIC "):])
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec is None or rec.get("kernel_sha256") != sha:
+        return None, f"{os.path.relpath(path, ROOT)} was taken on another kernel source"
+    per_es = rec["fetch_bytes_per_element_stage"] + rec["write_bytes_per_element_stage"]
+    return per_es * es_per_launch, os.path.relpath(path, ROOT)
+
+
 def run(args):
     import torch
     from paper_2403_05144_amd import PerkSolver
@@ -587,7 +610,7 @@ def run(args):
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": frac_b}
     else:
         roof = {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": frac_f}
-    roof["traffic"] = None
+    roof["traffic"], roof["traffic_source"] = measured_traffic(wl["name"], es_per_launch)
     roof["kernel"] = "k_stage"
     roof["avg_launch_us"] = avg_launch_s * 1e6
     roof["element_stages_per_launch"] = es_per_launch

@@ -172,6 +172,15 @@ pe_status pe_set_graph_replay(pe_ctx* ctx, int on);
 pe_status pe_counters(pe_ctx* ctx, int64_t* out_total, int64_t* out_per_member, int reset,
                       void* stream);
 
+/* Step-size bound of eq. (CFL_DG) and eq. (TimestepConstraint) from the bound state:
+ * beta_l = 1 / max over the elements of level l, their nodes and the directions d of
+ * (k+1)(|v_d| + c) / h_d  (k the polynomial degree, c the speed of sound; convective part only,
+ * the bound the paper uses for its convection-dominated cases), and dt_out = cfl * min_l beta_l.
+ * beta_of_level may be NULL, else [16] host doubles (0 for levels without elements).
+ * Synchronises `stream`.  PE_ENONFINITE if the state gives a non-finite speed, PE_EINVAL if
+ * cfl <= 0. */
+pe_status pe_max_dt(pe_ctx* ctx, double cfl, double* dt_out, double* beta_of_level, void* stream);
+
 /* Refinement indicator per leaf (the adaptive Kelvin-Helmholtz workload's density-gradient
  * indicator): eta_e = h_e max_nodes |grad rho| / max_nodes rho, h_e the element size in x,
  * grad rho from the DGSEM derivative matrix.  Written to eta_leaf_host [n_elements] in leaf

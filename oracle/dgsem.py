@@ -192,6 +192,24 @@ class Oracle:
         return np.einsum("e,evn,n->v", jac, u, W)
 
 
+def max_dt(o: Oracle, u, cfl=1.0, gamma=1.4):
+    """Step-size bound of eq. (CFL_DG) and eq. (TimestepConstraint): for every element,
+    beta_e = min over its nodes and the directions d of h_d / ((k+1) (|v_d| + c)), with k + 1 =
+    o.N nodes per direction and c the speed of sound; beta per refinement level is the minimum
+    over the level's elements, and dt = cfl * min over levels.  Returns (dt, {level: beta})."""
+    h = o.element_sizes()
+    lev = np.asarray(o.mesh.leaves)[:, 0]
+    betas = {}
+    for e in range(o.n_elements):
+        rho = u[e, 0]
+        vel = [u[e, 1 + d] / rho for d in range(o.dim)]
+        p = (gamma - 1.0) * (u[e, o.dim + 1] - 0.5 * rho * sum(v * v for v in vel))
+        c = np.sqrt(gamma * p / rho)
+        b = min(float(np.min(h[e, d] / (o.N * (np.abs(vel[d]) + c)))) for d in range(o.dim))
+        betas[int(lev[e])] = min(betas.get(int(lev[e]), np.inf), b)
+    return cfl * min(betas.values()), betas
+
+
 def member_of_levels_paper_rule(levels, n_members):
     """Sec. 6.3.1: finest level -> member R-1 (most evaluations), next finer -> R-2, ...,
     every level beyond the R-th finest -> member 0."""

@@ -51,7 +51,8 @@ struct pe_ctx {
   int32_t *d_slot_of_leaf = nullptr, *d_leaf_of_slot = nullptr, *d_old_slot_of_leaf = nullptr, *d_counts = nullptr;
   int32_t* d_halo = nullptr;
   int32_t* d_plan = nullptr;            // AMR projection plan [capacity][10]
-  double* d_eta = nullptr;              // AMR indicator per leaf
+  double* d_eta = nullptr;              // AMR indicator per leaf; wave-speed bound per slot
+  double* d_beta = nullptr;             // [kMaxLevels] largest (p+1)(|v_d|+c)/h_d per level
   unsigned long long* d_counter = nullptr;   // [R] folded totals
   int32_t* d_evals = nullptr;               // [capacity] per-slot evaluations since the last fold
   // partition
@@ -336,6 +337,7 @@ size_t carve(pe_ctx* c, char* base) {
   c->d_evals = (int32_t*)take((size_t)n * 4);
   c->d_plan = (int32_t*)take((size_t)n * 10 * 4);
   c->d_eta = (double*)take((size_t)n * 8);
+  c->d_beta = (double*)take(kMaxLevels * 8);
   return off;
 }
 
@@ -911,6 +913,28 @@ pe_status pe_amr_indicator(pe_ctx* ctx, double* eta_leaf, void* stream) {
                           ctx->ops, m, ctx->d_eta, s));
   HIPCHK(hipMemcpyAsync(eta_leaf, ctx->d_eta, (size_t)ctx->n_e * 8, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  return PE_OK;
+}
+
+pe_status pe_max_dt(pe_ctx* ctx, double cfl, double* dt_out, double* beta_of_level, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->partitioned || !ctx->state_valid) return fail(ctx, PE_ESTATE, "max_dt needs a partition and a state");
+  if (!dt_out) return fail(ctx, PE_EINVAL, "max_dt: null dt_out");
+  if (!(cfl > 0.0)) return fail(ctx, PE_EINVAL, "max_dt: cfl must be positive");
+  hipStream_t s = (hipStream_t)stream;
+  Mesh m = device_mesh(ctx);
+  HIPCHK(launch_wave_speed(ctx->dim, ctx->N, ctx->n_e, ctx->U, ctx->ph, m, ctx->d_eta, ctx->d_beta, s));
+  double w[kMaxLevels];
+  HIPCHK(hipMemcpyAsync(w, ctx->d_beta, sizeof(w), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double wmax = 0.0;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    if (!std::isfinite(w[l])) return fail(ctx, PE_ENONFINITE, "max_dt: non-finite wave speed on level %d", l);
+    if (beta_of_level) beta_of_level[l] = w[l] > 0.0 ? 1.0 / w[l] : 0.0;
+    wmax = std::max(wmax, w[l]);
+  }
+  if (!(wmax > 0.0)) return fail(ctx, PE_ENONFINITE, "max_dt: zero wave speed");
+  *dt_out = cfl / wmax;
   return PE_OK;
 }
 

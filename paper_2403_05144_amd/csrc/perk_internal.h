@@ -132,6 +132,10 @@ hipError_t launch_project(int dim, int N, int n_new, int ld, const int32_t* plan
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 // Add the per-slot evaluation counts into per-member totals (member from the partition
 // boundaries) and zero them.
+// Per slot: max over nodes and directions of (N)(|v_d| + c) * (2/h_d) / 2; per level the maximum
+// over its slots into beta[kMaxLevels] (0 for empty levels, NaN propagates).
+hipError_t launch_wave_speed(int dim, int N, int n, const double* U, const Physics& ph, const Mesh& m, double* w_slot,
+                             double* w_level, hipStream_t s);
 hipError_t launch_fold_evals(int n, const Mesh& m, int32_t* evals, unsigned long long* totals, hipStream_t s);
 
 }  // namespace perk

@@ -963,6 +963,49 @@ __global__ void k_indicator(int n, int ld, const int32_t* slot_of_leaf, const in
   eta[leaf] = h * gmax / rmax;
 }
 
+// Largest convective wave speed per slot, scaled to the step-size bound of eq. (CFL_DG):
+// w_e = max over nodes and directions of (k+1)(|v_d| + c) / h_d, one lane per slot.
+template <int DIM, int N>
+__global__ void k_wave_speed(int n, int ld, const double* U, Physics ph, Mesh m, double* w) {
+  constexpr int ND = G<DIM, N>::ND, NV = DIM + 2;
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= n) return;
+  const int lev = m.lev[slot];
+  double wmax = 0.0;
+  for (int nd = 0; nd < ND; ++nd) {
+    double u[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = U[((int64_t)v * ld + slot) * ND + nd];
+    const double ir = 1.0 / u[0];
+    double ke = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ke += u[1 + d] * u[1 + d];
+    const double p = (ph.gamma - 1.0) * (u[NV - 1] - 0.5 * ke * ir);
+    const double c = sqrt(ph.gamma * p * ir);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double s = (fabs(u[1 + d] * ir) + c) * (0.5 * N * m.jac[lev][d]);
+      wmax = (s > wmax || s != s) ? s : wmax;      // NaN wins, so a broken state is reported
+    }
+  }
+  w[slot] = wmax;
+}
+
+// Maximum per level over the slots; one block.  Non-negative doubles order like their bit
+// patterns, and NaN's pattern is above +inf, so an integer maximum keeps NaN.
+__global__ void k_level_max(int n, const int32_t* lev, const double* w, double* out) {
+  __shared__ unsigned long long sm[kMaxLevels];
+  if (threadIdx.x < kMaxLevels) sm[threadIdx.x] = 0ull;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double x = w[i];
+    const unsigned long long b = x != x ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(x);
+    atomicMax(&sm[lev[i]], b);
+  }
+  __syncthreads();
+  if (threadIdx.x < kMaxLevels) out[threadIdx.x] = __longlong_as_double((long long)sm[threadIdx.x]);
+}
+
 // one lane per (new leaf, variable, node)
 template <int DIM, int N>
 __global__ void k_project(int64_t total, int ld, const int32_t* plan, const int32_t* old_slot_of_leaf,
@@ -1125,6 +1168,21 @@ hipError_t launch_project(int dim, int N, int n_new, int ld, const int32_t* plan
   else if (dim == 3 && N == 4) hipLaunchKernelGGL((k_project<3, 4>), g, b, 0, s, total, ld, plan, old_slot_of_leaf, U_old, op, dst);
   else if (dim == 3 && N == 3) hipLaunchKernelGGL((k_project<3, 3>), g, b, 0, s, total, ld, plan, old_slot_of_leaf, U_old, op, dst);
   else return hipErrorNotSupported;
+  return hipGetLastError();
+}
+
+hipError_t launch_wave_speed(int dim, int N, int n, const double* U, const Physics& ph, const Mesh& m, double* w_slot,
+                             double* w_level, hipStream_t s) {
+  if (n <= 0) return hipErrorInvalidValue;
+  const dim3 g(grid_for(n, 128)), b(128);
+  if (dim == 2 && N == 4) hipLaunchKernelGGL((k_wave_speed<2, 4>), g, b, 0, s, n, m.ld, U, ph, m, w_slot);
+  else if (dim == 2 && N == 3) hipLaunchKernelGGL((k_wave_speed<2, 3>), g, b, 0, s, n, m.ld, U, ph, m, w_slot);
+  else if (dim == 3 && N == 4) hipLaunchKernelGGL((k_wave_speed<3, 4>), g, b, 0, s, n, m.ld, U, ph, m, w_slot);
+  else if (dim == 3 && N == 3) hipLaunchKernelGGL((k_wave_speed<3, 3>), g, b, 0, s, n, m.ld, U, ph, m, w_slot);
+  else return hipErrorNotSupported;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_level_max, dim3(1), dim3(1024), 0, s, n, m.lev, w_slot, w_level);
   return hipGetLastError();
 }
 

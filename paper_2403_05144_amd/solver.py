@@ -189,6 +189,15 @@ class PerkSolver:
         self.mesh.leaves = self._leaves
         self.partition(member_of_level)
 
+    def max_dt(self, cfl=1.0):
+        """(cfl * min_l beta_l, beta per level) from the current state, eq. (CFL_DG)."""
+        dt = ctypes.c_double()
+        beta = np.zeros(16)
+        self._check(self.lib.pe_max_dt(self._ctx, float(cfl), ctypes.byref(dt),
+                                       beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream_handle()),
+                    "pe_max_dt")
+        return dt.value, beta
+
     def quadrature(self):
         x = np.zeros(self.N)
         w = np.zeros(self.N)

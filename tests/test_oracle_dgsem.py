@@ -389,3 +389,36 @@ def test_heat_conduction_closed_form():
         errs.append(np.max(np.abs(du[:, 3] - expect)) / (0.2 * kappa))
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert min(rates) > 2.0 and errs[-1] < 1e-2, (errs, rates)
+
+
+def test_max_dt_uniform_state_closed_form():
+    # eq. (CFL_DG): for a constant state beta on level l is h_l / ((k+1)(max_d |v_d| + c)),
+    # halving with every level; the largest velocity component decides
+    mesh = pin.mesh_vortex_2level()
+    o = od.Oracle(mesh, 4)
+    rho, vx, vy, p = 1.3, 0.4, -0.7, 2.0
+    u = np.zeros(o.shape)
+    u[:, 0], u[:, 1], u[:, 2] = rho, rho * vx, rho * vy
+    u[:, 3] = p / 0.4 + 0.5 * rho * (vx * vx + vy * vy)
+    c = np.sqrt(1.4 * p / rho)
+    dt, beta = od.max_dt(o, u, cfl=0.9)
+    assert set(beta) == {0, 1}
+    np.testing.assert_allclose(beta[0], 0.625 / (4 * (0.7 + c)), rtol=1e-15)
+    np.testing.assert_allclose(beta[1], 0.3125 / (4 * (0.7 + c)), rtol=1e-15)
+    np.testing.assert_allclose(dt, 0.9 * beta[1], rtol=1e-15)
+
+
+def test_max_dt_vortex_below_background():
+    # the vortex raises |v| above and lowers c below the background; its bound must lie below
+    # the free-stream value and above that of the largest node speed in the whole domain
+    mesh = pin.mesh_vortex_2level()
+    o = od.Oracle(mesh, 4)
+    x = o.node_coords().transpose(1, 0, 2)
+    u = pin.isentropic_vortex(x[0], x[1]).transpose(1, 0, 2).copy()
+    dt, beta = od.max_dt(o, u)
+    c_inf = np.sqrt(1.4)
+    assert beta[1] < 0.3125 / (4 * (0.5 * c_inf + c_inf))
+    rho = u[:, 0]
+    p = 0.4 * (u[:, 3] - 0.5 * (u[:, 1] ** 2 + u[:, 2] ** 2) / rho)
+    smax = np.max(np.sqrt((u[:, 1] ** 2 + u[:, 2] ** 2)) / rho + np.sqrt(1.4 * p / rho))
+    assert dt >= 0.3125 / (4 * smax) * (1 - 1e-15)

@@ -25,6 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# files whose contents define the stage kernel (hashed into the counter summaries)
+STAGE_KERNEL_SOURCES = ("perk_stage.hip", "perk_device.h", "perk_internal.h")
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -504,7 +506,6 @@ def measured_traffic(workload, es_per_launch):
     kernel source has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_stage_{workload}_hbm_counters.txt")
-    src = os.path.join(ROOT, "paper_2403_05144_amd", "csrc", "perk_kernels.hip")
     if not os.path.exists(path):
         return None, "no counter summary for this workload"
     rec = None
@@ -512,8 +513,11 @@ def measured_traffic(workload, es_per_launch):
         for line in f:
             if line.startswith("TRAFFIC "):
                 rec = json.loads(line[len("TRAFFIC "):])
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in STAGE_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2403_05144_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    sha = h.hexdigest()
     if rec is None or rec.get("kernel_sha256") != sha:
         return None, f"{os.path.relpath(path, ROOT)} was taken on another kernel source"
     per_es = rec["fetch_bytes_per_element_stage"] + rec["write_bytes_per_element_stage"]

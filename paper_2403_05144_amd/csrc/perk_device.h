@@ -1,0 +1,57 @@
+// Device-side index helpers shared by the libperk kernel files (gfx950).
+#pragma once
+
+#include "perk_internal.h"
+
+namespace perk {
+namespace {
+
+template <int DIM, int N>
+struct G {
+  static constexpr int ND = DIM == 2 ? N * N : N * N * N;   // nodes per element
+  static constexpr int NF = DIM == 2 ? N : N * N;           // nodes per face
+  static constexpr int NFC = 2 * DIM;                       // faces per element
+  static constexpr int NV = DIM + 2;                        // conserved variables
+  static constexpr int NSUB = DIM == 2 ? 2 : 4;             // fine faces per mortar
+  static constexpr int NQ = DIM + 5;                        // rho, v, p, ln rho, beta, ln beta
+};
+
+template <int DIM, int N>
+__device__ __forceinline__ int node_index_dir(int nd, int d) {
+  if (d == 0) return nd % N;
+  if (d == 1) return (nd / N) % N;
+  return nd / (N * N);
+}
+
+template <int DIM, int N>
+__device__ __forceinline__ int stride_dir(int d) {
+  return d == 0 ? 1 : (d == 1 ? N : N * N);
+}
+
+// volume node of face node j on face (d, side)
+template <int DIM, int N>
+__device__ __forceinline__ int face_node(int d, int side, int j) {
+  const int sv = side ? N - 1 : 0;
+  if (DIM == 2) return d == 0 ? sv + N * j : j + N * sv;
+  const int a = j % N, b = j / N;
+  if (d == 0) return sv + N * a + N * N * b;
+  if (d == 1) return a + N * sv + N * N * b;
+  return a + N * b + N * N * sv;
+}
+
+// face node index of volume node nd on a face normal to d
+template <int DIM, int N>
+__device__ __forceinline__ int face_index(int nd, int d) {
+  const int i = nd % N, j = (nd / N) % N;
+  if (DIM == 2) return d == 0 ? j : i;
+  const int k = nd / (N * N);
+  if (d == 0) return j + N * k;
+  if (d == 1) return i + N * k;
+  return i + N * j;
+}
+
+
+inline unsigned grid_for(int64_t total, int bs) { return (unsigned)((total + bs - 1) / bs); }
+
+}  // namespace
+}  // namespace perk

@@ -1,5 +1,5 @@
 // Internal declarations shared by the host side (perk_api.cpp) and the HIP kernels
-// (perk_kernels.hip) of libperk.  Not part of the public ABI (see include/perk.h).
+// (perk_stage.hip, perk_mesh.hip) of libperk.  Not part of the public ABI (see include/perk.h).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -84,7 +84,7 @@ struct StageArgs {
   double a2[kMaxMembers]; // a_{i+1,i}
 };
 
-// Kernel launch wrappers (perk_kernels.hip).  All return hipError_t.
+// Kernel launch wrappers (perk_stage.hip: stage and gradient kernels; perk_mesh.hip: the rest).  All return hipError_t.
 // ev0/ev1 (optional): events recorded by the dispatch itself at kernel start and end
 hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,
                         const Physics& ph, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

@@ -24,54 +24,10 @@
 
 #include <hip/hip_ext.h>
 
-#include "perk_internal.h"
+#include "perk_device.h"
 
 namespace perk {
 namespace {
-
-template <int DIM, int N>
-struct G {
-  static constexpr int ND = DIM == 2 ? N * N : N * N * N;   // nodes per element
-  static constexpr int NF = DIM == 2 ? N : N * N;           // nodes per face
-  static constexpr int NFC = 2 * DIM;                       // faces per element
-  static constexpr int NV = DIM + 2;                        // conserved variables
-  static constexpr int NSUB = DIM == 2 ? 2 : 4;             // fine faces per mortar
-  static constexpr int NQ = DIM + 5;                        // rho, v, p, ln rho, beta, ln beta
-};
-
-template <int DIM, int N>
-__device__ __forceinline__ int node_index_dir(int nd, int d) {
-  if (d == 0) return nd % N;
-  if (d == 1) return (nd / N) % N;
-  return nd / (N * N);
-}
-
-template <int DIM, int N>
-__device__ __forceinline__ int stride_dir(int d) {
-  return d == 0 ? 1 : (d == 1 ? N : N * N);
-}
-
-// volume node of face node j on face (d, side)
-template <int DIM, int N>
-__device__ __forceinline__ int face_node(int d, int side, int j) {
-  const int sv = side ? N - 1 : 0;
-  if (DIM == 2) return d == 0 ? sv + N * j : j + N * sv;
-  const int a = j % N, b = j / N;
-  if (d == 0) return sv + N * a + N * N * b;
-  if (d == 1) return a + N * sv + N * N * b;
-  return a + N * b + N * N * sv;
-}
-
-// face node index of volume node nd on a face normal to d
-template <int DIM, int N>
-__device__ __forceinline__ int face_index(int nd, int d) {
-  const int i = nd % N, j = (nd / N) % N;
-  if (DIM == 2) return d == 0 ? j : i;
-  const int k = nd / (N * N);
-  if (d == 0) return j + N * k;
-  if (d == 1) return i + N * k;
-  return i + N * j;
-}
 
 // Reciprocal: hardware estimate refined by two Newton steps with FMA (within one ulp of 1/x for
 // the positive, normal arguments used here: densities, pressures, sums of them, wave-speed gaps).
@@ -825,256 +781,6 @@ hipError_t launch_stage_t(const StageArgs& a, const Mesh& m, const Ops& op, cons
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------------------------------
-// Re-partition (Sec. 6.2): member per leaf, stable counting sort by member (most stage
-// evaluations first), one block of 1024 lanes; ranks inside a chunk from wave ballots.
-// ------------------------------------------------------------------------------------------
-constexpr int kSortThreads = 1024;
-
-__global__ __launch_bounds__(kSortThreads) void k_partition_sort(PartitionArgs a) {
-  __shared__ int s_count[kMaxMembers];
-  __shared__ int s_base[kMaxMembers];
-  __shared__ int s_wave[kMaxMembers][kSortThreads / 64];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  if (tid < kMaxMembers) s_count[tid] = 0;
-  __syncthreads();
-  for (int i = tid; i < a.n; i += kSortThreads) {
-    const int mem = a.member_of_level[a.lev_leaf[i]];
-    a.mem_leaf[i] = mem;
-    atomicAdd(&s_count[a.R - 1 - mem], 1);
-  }
-  __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int k = 0; k < a.R; ++k) {
-      s_base[k] = acc;
-      acc += s_count[k];
-      a.counts[a.R - 1 - k] = s_count[k];
-    }
-  }
-  __syncthreads();
-  for (int c0 = 0; c0 < a.n; c0 += kSortThreads) {
-    const int i = c0 + tid;
-    const int key = i < a.n ? a.R - 1 - a.mem_leaf[i] : -1;
-    int my_rank = 0;
-    for (int k = 0; k < a.R; ++k) {
-      const unsigned long long mask = __ballot(key == k);
-      if (lane == 0) s_wave[k][wave] = __popcll(mask);
-      if (key == k) my_rank = __popcll(mask & ((1ull << lane) - 1ull));
-    }
-    __syncthreads();
-    if (key >= 0) {
-      int before = 0;
-      for (int w = 0; w < wave; ++w) before += s_wave[key][w];
-      const int slot = s_base[key] + before + my_rank;
-      a.slot_of_leaf[i] = slot;
-      a.leaf_of_slot[slot] = i;
-    }
-    __syncthreads();
-    if (tid < a.R) {
-      int tot = 0;
-      for (int w = 0; w < kSortThreads / 64; ++w) tot += s_wave[tid][w];
-      s_base[tid] += tot;
-    }
-    __syncthreads();
-  }
-}
-
-__global__ void k_remap(int n, int nfaces, const int32_t* leaf_of_slot, const int32_t* slot_of_leaf,
-                        const int32_t* fk_leaf, const int32_t* fn_leaf, const int32_t* lev_leaf,
-                        const int32_t* mem_leaf, int32_t* fk, int32_t* fn, int32_t* lev, int32_t* mem) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)n * nfaces) return;
-  const int slot = (int)(t / nfaces), f = (int)(t % nfaces);
-  const int leaf = leaf_of_slot[slot];
-  fk[t] = fk_leaf[(int64_t)leaf * nfaces + f];
-  for (int q = 0; q < 4; ++q) {
-    const int nb = fn_leaf[((int64_t)leaf * nfaces + f) * 4 + q];
-    fn[t * 4 + q] = nb >= 0 ? slot_of_leaf[nb] : -1;
-  }
-  if (f == 0) {
-    lev[slot] = lev_leaf[leaf];
-    mem[slot] = mem_leaf[leaf];
-  }
-}
-
-__global__ void k_permute(int64_t total, int n, int ld, int nd, const int32_t* leaf_of_slot,
-                          const int32_t* old_slot_of_leaf, const double* src, double* dst) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  const int node = (int)(t % nd);
-  const int64_t r = t / nd;
-  const int slot = (int)(r % n);
-  const int v = (int)(r / n);
-  const int old = old_slot_of_leaf[leaf_of_slot[slot]];
-  dst[((int64_t)v * ld + slot) * nd + node] = src[((int64_t)v * ld + old) * nd + node];
-}
-
-__global__ void k_leaf_to_slot(int64_t total, int n, int ld, int nv, int nd, const int32_t* leaf_of_slot,
-                               const double* src, double* dst) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  const int node = (int)(t % nd);
-  const int64_t r = t / nd;
-  const int slot = (int)(r % n);
-  const int v = (int)(r / n);
-  dst[((int64_t)v * ld + slot) * nd + node] = src[((int64_t)leaf_of_slot[slot] * nv + v) * nd + node];
-}
-
-__global__ void k_slot_to_leaf(int64_t total, int ld, int nv, int nd, const int32_t* slot_of_leaf,
-                               const double* src, double* dst) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  const int node = (int)(t % nd);
-  const int64_t r = t / nd;
-  const int v = (int)(r % nv);
-  const int leaf = (int)(r / nv);
-  dst[t] = src[((int64_t)v * ld + slot_of_leaf[leaf]) * nd + node];
-}
-
-// eta = h max |grad rho| / max rho over the nodes of one leaf; one lane per leaf.
-template <int DIM, int N>
-__global__ void k_indicator(int n, int ld, const int32_t* slot_of_leaf, const int32_t* lev_leaf, const double* U,
-                            Ops op, Mesh m, double* eta) {
-  constexpr int ND = G<DIM, N>::ND;
-  const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
-  if (leaf >= n) return;
-  const int slot = slot_of_leaf[leaf];
-  const int lev = lev_leaf[leaf];
-  const double* rho = U + (int64_t)slot * ND;     // variable 0
-  double rmax = 0.0, gmax = 0.0;
-  for (int nd = 0; nd < ND; ++nd) {
-    rmax = fmax(rmax, rho[nd]);
-    double g2 = 0.0;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      const int ia = node_index_dir<DIM, N>(nd, d);
-      const int st = stride_dir<DIM, N>(d);
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < N; ++q) acc += op.D[ia * N + q] * rho[nd + (q - ia) * st];
-      const double gd = m.jac[lev][d] * acc;
-      g2 += gd * gd;
-    }
-    gmax = fmax(gmax, sqrt(g2));
-  }
-  const double h = 2.0 / m.jac[lev][0];
-  eta[leaf] = h * gmax / rmax;
-}
-
-// Largest convective wave speed per slot, scaled to the step-size bound of eq. (CFL_DG):
-// w_e = max over nodes and directions of (k+1)(|v_d| + c) / h_d, one lane per slot.
-template <int DIM, int N>
-__global__ void k_wave_speed(int n, int ld, const double* U, Physics ph, Mesh m, double* w) {
-  constexpr int ND = G<DIM, N>::ND, NV = DIM + 2;
-  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= n) return;
-  const int lev = m.lev[slot];
-  double wmax = 0.0;
-  for (int nd = 0; nd < ND; ++nd) {
-    double u[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) u[v] = U[((int64_t)v * ld + slot) * ND + nd];
-    const double ir = 1.0 / u[0];
-    double ke = 0.0;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) ke += u[1 + d] * u[1 + d];
-    const double p = (ph.gamma - 1.0) * (u[NV - 1] - 0.5 * ke * ir);
-    const double c = sqrt(ph.gamma * p * ir);
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      const double s = (fabs(u[1 + d] * ir) + c) * (0.5 * N * m.jac[lev][d]);
-      wmax = (s > wmax || s != s) ? s : wmax;      // NaN wins, so a broken state is reported
-    }
-  }
-  w[slot] = wmax;
-}
-
-// Maximum per level over the slots; one block.  Non-negative doubles order like their bit
-// patterns, and NaN's pattern is above +inf, so an integer maximum keeps NaN.
-__global__ void k_level_max(int n, const int32_t* lev, const double* w, double* out) {
-  __shared__ unsigned long long sm[kMaxLevels];
-  if (threadIdx.x < kMaxLevels) sm[threadIdx.x] = 0ull;
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double x = w[i];
-    const unsigned long long b = x != x ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(x);
-    atomicMax(&sm[lev[i]], b);
-  }
-  __syncthreads();
-  if (threadIdx.x < kMaxLevels) out[threadIdx.x] = __longlong_as_double((long long)sm[threadIdx.x]);
-}
-
-// one lane per (new leaf, variable, node)
-template <int DIM, int N>
-__global__ void k_project(int64_t total, int ld, const int32_t* plan, const int32_t* old_slot_of_leaf,
-                          const double* U, Ops op, double* dst) {
-  constexpr int ND = G<DIM, N>::ND, NV = DIM + 2;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  const int node = (int)(t % ND);
-  const int64_t r = t / ND;
-  const int v = (int)(r % NV);
-  const int leaf = (int)(r / NV);
-  const int32_t* pl = plan + (int64_t)leaf * 10;
-  const int kind = pl[0];
-  int j[3] = {node % N, (node / N) % N, DIM == 3 ? node / (N * N) : 0};
-  double val = 0.0;
-  if (kind == 0) {
-    const int slot = old_slot_of_leaf[pl[2]];
-    val = U[((int64_t)v * ld + slot) * ND + node];
-  } else if (kind == 1) {
-    // child of a refined leaf: tensor-product interpolation of the parent polynomial
-    const int pos = pl[1];
-    const int slot = old_slot_of_leaf[pl[2]];
-    const double* src = U + ((int64_t)v * ld + slot) * ND;
-    for (int q = 0; q < ND; ++q) {
-      const int k[3] = {q % N, (q / N) % N, DIM == 3 ? q / (N * N) : 0};
-      double w = 1.0;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) w *= op.P[(pos >> d) & 1][j[d] * N + k[d]];
-      val += w * src[q];
-    }
-  } else {
-    // parent of a coarsened family: LGL-quadrature L2 projection of the children
-    for (int c = 0; c < (1 << DIM); ++c) {
-      const int slot = old_slot_of_leaf[pl[2 + c]];
-      const double* src = U + ((int64_t)v * ld + slot) * ND;
-      for (int q = 0; q < ND; ++q) {
-        const int k[3] = {q % N, (q / N) % N, DIM == 3 ? q / (N * N) : 0};
-        double w = 1.0;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) w *= op.R[(c >> d) & 1][j[d] * N + k[d]];
-        val += w * src[q];
-      }
-    }
-  }
-  dst[t] = val;
-}
-
-__global__ void k_copy(double* dst, const double* src, int64_t n) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) dst[t] = src[t];
-}
-
-__global__ __launch_bounds__(1024) void k_fold_evals(int n, Mesh m, int32_t* evals, unsigned long long* totals) {
-  __shared__ unsigned long long s_tot[kMaxMembers];
-  if (threadIdx.x < kMaxMembers) s_tot[threadIdx.x] = 0;
-  __syncthreads();
-  unsigned long long mine[kMaxMembers] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    mine[member_of_slot(m, i)] += (unsigned long long)evals[i];
-    evals[i] = 0;
-  }
-  for (int r = 0; r < m.R; ++r)
-    if (mine[r]) atomicAdd(&s_tot[r], mine[r]);
-  __syncthreads();
-  if (threadIdx.x < m.R) totals[threadIdx.x] += s_tot[threadIdx.x];
-}
-
-inline unsigned grid_for(int64_t total, int bs) { return (unsigned)((total + bs - 1) / bs); }
-
 }  // namespace
 
 hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,
@@ -1100,102 +806,6 @@ hipError_t launch_gradients(int dim, int N, const StageArgs& a, const Mesh& m, c
   if (dim == 3 && N == 4) return launch_grad_t<3, 4>(a, m, op, ph, s);
   if (dim == 3 && N == 3) return launch_grad_t<3, 3>(a, m, op, ph, s);
   return hipErrorNotSupported;
-}
-
-hipError_t launch_partition_sort(const PartitionArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_partition_sort, dim3(1), dim3(kSortThreads), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_remap_connectivity(int n, int nfaces, const int32_t* leaf_of_slot, const int32_t* slot_of_leaf,
-                                     const int32_t* fk_leaf, const int32_t* fn_leaf, const int32_t* lev_leaf,
-                                     const int32_t* mem_leaf, int32_t* fk, int32_t* fn, int32_t* lev, int32_t* mem,
-                                     hipStream_t s) {
-  const int64_t total = (int64_t)n * nfaces;
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_remap, dim3(grid_for(total, 256)), dim3(256), 0, s, n, nfaces, leaf_of_slot, slot_of_leaf,
-                     fk_leaf, fn_leaf, lev_leaf, mem_leaf, fk, fn, lev, mem);
-  return hipGetLastError();
-}
-
-hipError_t launch_permute_state(int n, int ld, int nv, int nd, const int32_t* leaf_of_slot,
-                                const int32_t* old_slot_of_leaf, const double* src, double* dst, hipStream_t s) {
-  const int64_t total = (int64_t)n * nv * nd;
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_permute, dim3(grid_for(total, 256)), dim3(256), 0, s, total, n, ld, nd, leaf_of_slot,
-                     old_slot_of_leaf, src, dst);
-  return hipGetLastError();
-}
-
-hipError_t launch_leaf_to_slot(int n, int ld, int nv, int nd, const int32_t* leaf_of_slot, const double* src,
-                               double* dst, hipStream_t s) {
-  const int64_t total = (int64_t)n * nv * nd;
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_leaf_to_slot, dim3(grid_for(total, 256)), dim3(256), 0, s, total, n, ld, nv, nd,
-                     leaf_of_slot, src, dst);
-  return hipGetLastError();
-}
-
-hipError_t launch_slot_to_leaf(int n, int ld, int nv, int nd, const int32_t* slot_of_leaf, const double* src,
-                               double* dst, hipStream_t s) {
-  const int64_t total = (int64_t)n * nv * nd;
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_slot_to_leaf, dim3(grid_for(total, 256)), dim3(256), 0, s, total, ld, nv, nd, slot_of_leaf,
-                     src, dst);
-  return hipGetLastError();
-}
-
-hipError_t launch_indicator(int dim, int N, int n, int ld, const int32_t* slot_of_leaf, const int32_t* lev_leaf,
-                            const double* U, const Ops& op, const Mesh& m, double* eta, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  const dim3 g(grid_for(n, 128)), b(128);
-  if (dim == 2 && N == 4) hipLaunchKernelGGL((k_indicator<2, 4>), g, b, 0, s, n, ld, slot_of_leaf, lev_leaf, U, op, m, eta);
-  else if (dim == 2 && N == 3) hipLaunchKernelGGL((k_indicator<2, 3>), g, b, 0, s, n, ld, slot_of_leaf, lev_leaf, U, op, m, eta);
-  else if (dim == 3 && N == 4) hipLaunchKernelGGL((k_indicator<3, 4>), g, b, 0, s, n, ld, slot_of_leaf, lev_leaf, U, op, m, eta);
-  else if (dim == 3 && N == 3) hipLaunchKernelGGL((k_indicator<3, 3>), g, b, 0, s, n, ld, slot_of_leaf, lev_leaf, U, op, m, eta);
-  else return hipErrorNotSupported;
-  return hipGetLastError();
-}
-
-hipError_t launch_project(int dim, int N, int n_new, int ld, const int32_t* plan, const int32_t* old_slot_of_leaf,
-                          const double* U_old, const Ops& op, double* dst, hipStream_t s) {
-  const int nd = dim == 2 ? N * N : N * N * N;
-  const int64_t total = (int64_t)n_new * (dim + 2) * nd;
-  if (total == 0) return hipSuccess;
-  const dim3 g(grid_for(total, 256)), b(256);
-  if (dim == 2 && N == 4) hipLaunchKernelGGL((k_project<2, 4>), g, b, 0, s, total, ld, plan, old_slot_of_leaf, U_old, op, dst);
-  else if (dim == 2 && N == 3) hipLaunchKernelGGL((k_project<2, 3>), g, b, 0, s, total, ld, plan, old_slot_of_leaf, U_old, op, dst);
-  else if (dim == 3 && N == 4) hipLaunchKernelGGL((k_project<3, 4>), g, b, 0, s, total, ld, plan, old_slot_of_leaf, U_old, op, dst);
-  else if (dim == 3 && N == 3) hipLaunchKernelGGL((k_project<3, 3>), g, b, 0, s, total, ld, plan, old_slot_of_leaf, U_old, op, dst);
-  else return hipErrorNotSupported;
-  return hipGetLastError();
-}
-
-hipError_t launch_wave_speed(int dim, int N, int n, const double* U, const Physics& ph, const Mesh& m, double* w_slot,
-                             double* w_level, hipStream_t s) {
-  if (n <= 0) return hipErrorInvalidValue;
-  const dim3 g(grid_for(n, 128)), b(128);
-  if (dim == 2 && N == 4) hipLaunchKernelGGL((k_wave_speed<2, 4>), g, b, 0, s, n, m.ld, U, ph, m, w_slot);
-  else if (dim == 2 && N == 3) hipLaunchKernelGGL((k_wave_speed<2, 3>), g, b, 0, s, n, m.ld, U, ph, m, w_slot);
-  else if (dim == 3 && N == 4) hipLaunchKernelGGL((k_wave_speed<3, 4>), g, b, 0, s, n, m.ld, U, ph, m, w_slot);
-  else if (dim == 3 && N == 3) hipLaunchKernelGGL((k_wave_speed<3, 3>), g, b, 0, s, n, m.ld, U, ph, m, w_slot);
-  else return hipErrorNotSupported;
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_level_max, dim3(1), dim3(1024), 0, s, n, m.lev, w_slot, w_level);
-  return hipGetLastError();
-}
-
-hipError_t launch_fold_evals(int n, const Mesh& m, int32_t* evals, unsigned long long* totals, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fold_evals, dim3(1), dim3(1024), 0, s, n, m, evals, totals);
-  return hipGetLastError();
-}
-
-hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, src, n);
-  return hipGetLastError();
 }
 
 }  // namespace perk

@@ -49,6 +49,7 @@ extern "C" {
 #endif
 
 typedef struct pe_ctx pe_ctx;
+typedef struct pe_batch pe_batch;
 
 typedef enum {
   PE_OK = 0,
@@ -211,6 +212,39 @@ pe_status pe_set_profiling(pe_ctx* ctx, int on);
  * switched on (milliseconds; waits for the recorded events), the number of launches, and the
  * number of element-stages (active elements summed over the launches). */
 pe_status pe_profile_stats(pe_ctx* ctx, double* kernel_ms, int64_t* launches, int64_t* element_stages);
+
+/* ---------------------------------------------------------------- batched independent runs
+ * Many independent partitioned P-ERK runs (the step of Sec. 3 with the level partition of
+ * Sec. 6, each run with its own mesh, polynomial degree, coefficient family, stage count S and
+ * dt) advanced together: one kernel launch per stage tick moves every unfinished run by one of
+ * its own stages.  A run with S stages and n steps is busy for n S ticks; tick t applies its
+ * stage t mod S.  The work of a tick is the concatenation of the active element prefixes of
+ * the runs, cut into tiles; results are bitwise those of pe_step on each run alone.
+ * Supported: 2D Euler runs of degree 2 or 3 whose members all evaluate at least 3 stages.
+ * Device tables for the batch are allocated by the library; the runs keep owning their state
+ * and workspace, and pe_get_state / pe_counters read each run as usual. */
+
+/* Group existing runs (each bound, with a state and a partition; at most once each).  The runs
+ * must outlive the batch.  On failure *out is NULL and pe_batch_last_error(NULL) says why. */
+pe_status pe_batch_create(pe_batch** out, pe_ctx* const* runs, int n_runs);
+void pe_batch_destroy(pe_batch* batch);
+const char* pe_batch_last_error(const pe_batch* batch);
+
+/* Per run k: step dt[k] and number of steps n_steps[k] (host arrays [n_runs]).  Freezes the
+ * runs' current partitions and buffers into device descriptors; call again after any change
+ * to a run (adaptation, re-partition, new coefficients, re-binding).  Synchronous. */
+pe_status pe_batch_set_steps(pe_batch* batch, const double* dt, const int64_t* n_steps);
+
+/* Tile shape: elems_per_tile_p3 in {1, 2, 4} elements of degree 3 per tile (twice as many of
+ * degree 2; a block of 64 * elems_per_tile_p3 lanes), grid_blocks blocks per tick (each block
+ * takes every grid_blocks-th tile), or 0 for one block per tile. */
+pe_status pe_batch_set_tiling(pe_batch* batch, int elems_per_tile_p3, int grid_blocks);
+
+/* Number of ticks until every run has finished, and the element-stages they contain. */
+pe_status pe_batch_info(const pe_batch* batch, int64_t* n_ticks, int64_t* element_stages);
+
+/* Launch ticks [tick_begin, tick_end) on `stream` (asynchronous). */
+pe_status pe_batch_run(pe_batch* batch, int64_t tick_begin, int64_t tick_end, void* stream);
 
 #ifdef __cplusplus
 }

@@ -5,3 +5,4 @@ Hot path in HIP (libperk.so, C ABI in include/perk.h); this package is the thin 
 streams, `partition_rule` holds the level -> member maps of Sec. 6.3.1.
 """
 from .solver import PerkSolver, PerkError  # noqa: F401
+from .batch import PerkBatch  # noqa: F401

@@ -1131,3 +1131,195 @@ pe_status pe_counters(pe_ctx* ctx, int64_t* total, int64_t* per_member, int rese
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ batched runs
+struct pe_batch {
+  std::vector<pe_ctx*> runs;
+  int M = 1;                             // elements of p = 3 per tile (2M of p = 2)
+  int grid = 0;                          // blocks per tick; 0: one block per tile
+  bool have_steps = false;
+  std::vector<int64_t> ticks;            // per run: n_steps * S
+  int64_t n_ticks = 0;
+  int64_t elem_stages = 0;
+  std::vector<StageArgs> sargs;
+  std::vector<BatchRun> brun;
+  std::vector<int32_t> tiles;            // [n_ticks][n_runs + 1]
+  BatchRun* d_runs = nullptr;
+  StageArgs* d_sargs = nullptr;
+  int32_t* d_tiles = nullptr;
+  size_t cap_tiles = 0, cap_sargs = 0, cap_runs = 0;
+  std::string err;
+  ~pe_batch() {
+    if (d_runs) (void)hipFree(d_runs);
+    if (d_sargs) (void)hipFree(d_sargs);
+    if (d_tiles) (void)hipFree(d_tiles);
+  }
+};
+
+namespace {
+thread_local std::string g_batch_err;
+
+pe_status bfail(pe_batch* b, pe_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  (b ? b->err : g_batch_err) = buf;
+  return st;
+}
+
+#define BCHK(call)                                                                         \
+  do {                                                                                     \
+    hipError_t _e = (call);                                                                \
+    if (_e != hipSuccess) return bfail(b, PE_EHIP, "%s: %s", #call, hipGetErrorString(_e)); \
+  } while (0)
+
+int elems_per_tile(const pe_batch* b, int N) { return N == 4 ? b->M : 2 * b->M; }
+
+void build_tiles(pe_batch* b) {
+  const int nr = (int)b->runs.size();
+  b->tiles.assign((size_t)b->n_ticks * (nr + 1), 0);
+  b->elem_stages = 0;
+  for (int64_t t = 0; t < b->n_ticks; ++t) {
+    int32_t* row = &b->tiles[(size_t)t * (nr + 1)];
+    int acc = 0;
+    for (int k = 0; k < nr; ++k) {
+      row[k] = acc;
+      const pe_ctx* c = b->runs[k];
+      if (t < b->ticks[k]) {
+        const int na = c->n_act[(size_t)(t % c->S)];
+        const int ept = elems_per_tile(b, c->N);
+        acc += (na + ept - 1) / ept;
+        b->elem_stages += na;
+      }
+    }
+    row[nr] = acc;
+  }
+}
+
+template <class T>
+pe_status upload(pe_batch* b, T*& dptr, size_t& cap, const std::vector<T>& h) {
+  const size_t bytes = h.size() * sizeof(T);
+  if (bytes > cap) {
+    if (dptr) BCHK(hipFree(dptr));
+    dptr = nullptr;
+    cap = 0;
+    BCHK(hipMalloc((void**)&dptr, bytes));
+    cap = bytes;
+  }
+  if (bytes) BCHK(hipMemcpy(dptr, h.data(), bytes, hipMemcpyHostToDevice));
+  return PE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+pe_status pe_batch_create(pe_batch** out, pe_ctx* const* runs, int n_runs) {
+  if (!out) return bfail(nullptr, PE_EINVAL, "batch: null output");
+  *out = nullptr;
+  if (!runs || n_runs < 1) return bfail(nullptr, PE_EINVAL, "batch: need at least one run");
+  for (int k = 0; k < n_runs; ++k) {
+    const pe_ctx* c = runs[k];
+    if (!c) return bfail(nullptr, PE_EINVAL, "batch: run %d is null", k);
+    if (c->dim != 2 || c->equations != 0 || (c->N != 3 && c->N != 4))
+      return bfail(nullptr, PE_EUNSUPPORTED, "batch: run %d is not 2D Euler with degree 2 or 3", k);
+    if (!c->partitioned || !c->state_valid || !c->bound)
+      return bfail(nullptr, PE_ESTATE, "batch: run %d needs a bound state and a partition", k);
+    if (!last_stage_in_place_safe(c))
+      return bfail(nullptr, PE_EUNSUPPORTED, "batch: run %d has a member with fewer than 3 evaluations", k);
+    for (int j = 0; j < k; ++j)
+      if (runs[j] == c) return bfail(nullptr, PE_EINVAL, "batch: run %d appears twice", k);
+  }
+  pe_batch* b = new (std::nothrow) pe_batch();
+  if (!b) return bfail(nullptr, PE_ENOMEM, "batch: out of host memory");
+  b->runs.assign(runs, runs + n_runs);
+  *out = b;
+  return PE_OK;
+}
+
+void pe_batch_destroy(pe_batch* b) { delete b; }
+
+const char* pe_batch_last_error(const pe_batch* b) { return b ? b->err.c_str() : g_batch_err.c_str(); }
+
+pe_status pe_batch_set_steps(pe_batch* b, const double* dt, const int64_t* n_steps) {
+  if (!b) return bfail(nullptr, PE_EINVAL, "batch: null");
+  if (!dt || !n_steps) return bfail(b, PE_EINVAL, "batch: null dt or n_steps");
+  const int nr = (int)b->runs.size();
+  b->sargs.clear();
+  b->brun.assign(nr, BatchRun{});
+  b->ticks.assign(nr, 0);
+  b->n_ticks = 0;
+  for (int k = 0; k < nr; ++k) {
+    pe_ctx* c = b->runs[k];
+    if (!(dt[k] > 0.0) || n_steps[k] < 0) return bfail(b, PE_EINVAL, "batch: run %d: dt must be > 0, n_steps >= 0", k);
+    if (!c->partitioned || !c->state_valid || (int)c->n_act.size() != c->S)
+      return bfail(b, PE_ESTATE, "batch: run %d lost its partition or state", k);
+    BatchRun& r = b->brun[k];
+    r.m = device_mesh(c);
+    r.op = c->ops;
+    r.ph = c->ph;
+    r.N = c->N;
+    r.S = c->S;
+    r.sarg0 = (int)b->sargs.size();
+    for (int i = 0; i < c->S; ++i) {
+      StageArgs a;
+      fill_stage(c, i, dt[k], a);
+      a.U = c->U;
+      a.K1 = c->K1;
+      a.Yin = (i % 2 == 0) ? c->Ya : c->Yb;
+      a.Yout = (i % 2 == 0) ? c->Yb : c->Ya;
+      a.ACC = c->ACC;
+      a.Uout = c->U;
+      a.evals = c->d_evals;
+      b->sargs.push_back(a);
+    }
+    b->ticks[k] = n_steps[k] * c->S;
+    b->n_ticks = std::max(b->n_ticks, b->ticks[k]);
+  }
+  build_tiles(b);
+  pe_status st = upload(b, b->d_runs, b->cap_runs, b->brun);
+  if (st == PE_OK) st = upload(b, b->d_sargs, b->cap_sargs, b->sargs);
+  if (st == PE_OK) st = upload(b, b->d_tiles, b->cap_tiles, b->tiles);
+  if (st != PE_OK) return st;
+  b->have_steps = true;
+  return PE_OK;
+}
+
+pe_status pe_batch_set_tiling(pe_batch* b, int elems_per_tile_p3, int grid_blocks) {
+  if (!b) return bfail(nullptr, PE_EINVAL, "batch: null");
+  if ((elems_per_tile_p3 != 1 && elems_per_tile_p3 != 2 && elems_per_tile_p3 != 4) || grid_blocks < 0)
+    return bfail(b, PE_EINVAL, "batch: tiles of 1, 2 or 4 elements of degree 3, grid >= 0");
+  b->M = elems_per_tile_p3;
+  b->grid = grid_blocks;
+  if (b->have_steps) {
+    build_tiles(b);
+    return upload(b, b->d_tiles, b->cap_tiles, b->tiles);
+  }
+  return PE_OK;
+}
+
+pe_status pe_batch_info(const pe_batch* b, int64_t* n_ticks, int64_t* element_stages) {
+  if (!b) return PE_EINVAL;
+  if (n_ticks) *n_ticks = b->n_ticks;
+  if (element_stages) *element_stages = b->elem_stages;
+  return PE_OK;
+}
+
+pe_status pe_batch_run(pe_batch* b, int64_t tick_begin, int64_t tick_end, void* stream) {
+  if (!b) return bfail(nullptr, PE_EINVAL, "batch: null");
+  if (!b->have_steps) return bfail(b, PE_ESTATE, "batch: set_steps first");
+  if (tick_begin < 0 || tick_end > b->n_ticks || tick_begin > tick_end)
+    return bfail(b, PE_EINVAL, "batch: ticks [%lld, %lld) outside [0, %lld)", (long long)tick_begin,
+                 (long long)tick_end, (long long)b->n_ticks);
+  const int nr = (int)b->runs.size();
+  hipStream_t s = (hipStream_t)stream;
+  for (int64_t t = tick_begin; t < tick_end; ++t) {
+    const int n_tiles = b->tiles[(size_t)t * (nr + 1) + nr];
+    const int g = b->grid > 0 ? std::min(b->grid, n_tiles) : n_tiles;
+    BCHK(launch_stage_batch(b->M, g, b->d_runs, b->d_sargs, b->d_tiles + (size_t)t * (nr + 1), nr, t, s));
+  }
+  return PE_OK;
+}
+
+}  // extern "C"

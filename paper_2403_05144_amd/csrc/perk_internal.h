@@ -84,6 +84,17 @@ struct StageArgs {
   double a2[kMaxMembers]; // a_{i+1,i}
 };
 
+// One run of a batched launch: its mesh tables, operators, physics, polynomial degree (N nodes
+// per direction), stage count and the index of its first stage descriptor (S consecutive).
+struct BatchRun {
+  Mesh m;
+  Ops op;
+  Physics ph;
+  int N;
+  int S;
+  int sarg0;
+};
+
 // Kernel launch wrappers (perk_stage.hip: stage and gradient kernels; perk_mesh.hip: the rest).  All return hipError_t.
 // ev0/ev1 (optional): events recorded by the dispatch itself at kernel start and end
 hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,
@@ -136,6 +147,10 @@ hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s)
 // over its slots into beta[kMaxLevels] (0 for empty levels, NaN propagates).
 hipError_t launch_wave_speed(int dim, int N, int n, const double* U, const Physics& ph, const Mesh& m, double* w_slot,
                              double* w_level, hipStream_t s);
+// One batched stage tick (2D Euler runs, p = 2 or 3): M in {1, 2, 4} elements of p = 3 per
+// tile (2M of p = 2), grid blocks; tile_off [n_runs + 1] are the tick's tile offsets.
+hipError_t launch_stage_batch(int M, int grid, const BatchRun* runs, const StageArgs* sargs, const int32_t* tile_off,
+                              int n_runs, int64_t tick, hipStream_t s);
 hipError_t launch_fold_evals(int n, const Mesh& m, int32_t* evals, unsigned long long* totals, hipStream_t s);
 
 }  // namespace perk

@@ -199,10 +199,14 @@ __device__ __forceinline__ int node_on_line(int d, int line, int pos) {
   return a + N * b + N * N * pos;
 }
 
-template <int DIM, int N, bool VISC>
-__global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB), (SK<DIM, N>::MINW)) void k_stage(StageArgs a, Mesh m, Ops op, Physics ph) {
+// The stage work of one block of EPB elements: block `blk` of the launch covers the slots
+// [blk EPB, blk EPB + EPB).  Shared by the single-run kernel and the batched kernel, which
+// therefore compute bitwise identical stages.
+template <int DIM, int N, bool VISC, int EPB>
+__device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph,
+                                            int blk) {
   using K = SK<DIM, N>;
-  constexpr int ND = K::ND, NF = K::NF, NFC = K::NFC, NV = K::NV, NSUB = K::NSUB, T = K::T, EPB = K::EPB;
+  constexpr int ND = K::ND, NF = K::NF, NFC = K::NFC, NV = K::NV, NSUB = K::NSUB, T = K::T;
   constexpr int NP = K::NP, NPL = K::NPL, NITEM = K::NITEM;
   __shared__ double s_u[EPB][NV][ND];
   __shared__ NodeQ<DIM> s_q[EPB][ND];
@@ -216,7 +220,7 @@ __global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB), (SK<DIM, N>::MIN
 
   const int le = threadIdx.x / T;
   const int lane = threadIdx.x - le * T;
-  const int e = blockIdx.x * EPB + le;
+  const int e = blk * EPB + le;
   const bool act = e < a.n_act;
   const int ld = m.ld;
   const double gamma = ph.gamma;
@@ -566,6 +570,41 @@ __global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB), (SK<DIM, N>::MIN
   }
 }
 
+template <int DIM, int N, bool VISC>
+__global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB), (SK<DIM, N>::MINW)) void k_stage(StageArgs a, Mesh m, Ops op, Physics ph) {
+  stage_block<DIM, N, VISC, SK<DIM, N>::EPB>(a, m, op, ph, blockIdx.x);
+}
+
+// ------------------------------------------------------------------------------------------
+// Batched stage tick: many independent 2D Euler runs, each advanced by one of its own stages.
+// The tiles of the tick (EPB elements of one run each) are the concatenated active prefixes
+// of the unfinished runs, tile_off[k] the first tile of run k; a block of 64 M lanes takes
+// tiles blockIdx.x, blockIdx.x + gridDim.x, ... (persistent when the grid is smaller than the
+// tile count) and runs the p = 3 body with M elements or the p = 2 body with 2 M elements.
+// ------------------------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(64 * M) void k_stage_batch(const BatchRun* __restrict__ runs,
+                                                          const StageArgs* __restrict__ sargs,
+                                                          const int32_t* __restrict__ tile_off, int n_runs,
+                                                          int64_t tick) {
+  const int n_tiles = tile_off[n_runs];
+  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    int lo = 0, hi = n_runs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tile_off[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const int k = __builtin_amdgcn_readfirstlane(lo);
+    const BatchRun& r = runs[k];
+    const StageArgs& a = sargs[r.sarg0 + (int)(tick % r.S)];
+    const int blk = t - tile_off[k];
+    if (r.N == 4) stage_block<2, 4, false, M>(a, r.m, r.op, r.ph, blk);
+    else stage_block<2, 3, false, 2 * M>(a, r.m, r.op, r.ph, blk);
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // BR1 gradient kernel (Navier-Stokes).  One element per block.  w = (v_1..v_d, T), T = p/rho:
 //   q_d = (2/h_d) [ D w along d + lifting of (w* - w) at the two boundary nodes ],
@@ -782,6 +821,16 @@ hipError_t launch_stage_t(const StageArgs& a, const Mesh& m, const Ops& op, cons
 }
 
 }  // namespace
+
+hipError_t launch_stage_batch(int M, int grid, const BatchRun* runs, const StageArgs* sargs, const int32_t* tile_off,
+                              int n_runs, int64_t tick, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (M == 1) hipLaunchKernelGGL((k_stage_batch<1>), dim3(grid), dim3(64), 0, s, runs, sargs, tile_off, n_runs, tick);
+  else if (M == 2) hipLaunchKernelGGL((k_stage_batch<2>), dim3(grid), dim3(128), 0, s, runs, sargs, tile_off, n_runs, tick);
+  else if (M == 4) hipLaunchKernelGGL((k_stage_batch<4>), dim3(grid), dim3(256), 0, s, runs, sargs, tile_off, n_runs, tick);
+  else return hipErrorNotSupported;
+  return hipGetLastError();
+}
 
 hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,
                         const Physics& ph, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {

@@ -159,6 +159,65 @@ def balance_2d(leaves, n_root):
     return leaves
 
 
+def balance_2d_fast(leaves, n_root):
+    """Same result class as balance_2d (every pair of face neighbours at most one level apart,
+    periodic), refining all offending coarse leaves of a pass together."""
+    leaves = set(leaves)
+    while True:
+        marked = set()
+        for (l, i, j) in leaves:
+            n = n_root << l
+            for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                ni, nj = (i + di) % n, (j + dj) % n
+                lev = _covering_leaf(leaves, l, ni, nj)
+                if lev is not None and lev < l - 1:
+                    s = l - lev
+                    marked.add((lev, ni >> s, nj >> s))
+        if not marked:
+            return leaves
+        for (lev, ci, cj) in marked:
+            leaves.discard((lev, ci, cj))
+            for c in range(4):
+                leaves.add((lev + 1, 2 * ci + (c & 1), 2 * cj + (c >> 1)))
+
+
+def mesh_vortex_disks(n_root, n_levels, radii=(3.0, 2.0, 1.0), box=5.0, centre=(0.0, 0.0)):
+    """n_root^2 roots on [-box, box]^2; leaves whose centre lies within radii[l] of the vortex
+    centre are refined to level l + 1 (nested disks), for l < n_levels; then 2:1 balanced."""
+    h0 = 2.0 * box / n_root
+    leaves = {(0, i, j) for i in range(n_root) for j in range(n_root)}
+    for l in range(n_levels):
+        new = set()
+        for (lev, i, j) in leaves:
+            h = h0 / (1 << lev)
+            cx, cy = -box + (i + 0.5) * h, -box + (j + 0.5) * h
+            if lev == l and (cx - centre[0]) ** 2 + (cy - centre[1]) ** 2 < radii[l] ** 2:
+                for c in range(4):
+                    new.add((lev + 1, 2 * i + (c & 1), 2 * j + (c >> 1)))
+            else:
+                new.add((lev, i, j))
+        leaves = balance_2d_fast(new, n_root)
+    rows = sorted(leaves, key=lambda t: (t[0], t[2], t[1]))
+    return MeshDesc(2, (n_root, n_root), (-box, -box), (box, box), _rows([(l, i, j, 0) for (l, i, j) in rows]))
+
+
+def batch_vortex_runs(seed=MASTER_SEED + 3, n_runs=64):
+    """Independent isentropic-vortex runs of uneven size for the batched form: per run, roots
+    per side n ~ U{8..64}, refinement levels L ~ U{1,2,3} (nested disks of radii 3, 2, 1 around
+    the vortex centre), vortex strength eps ~ U[1,5], polynomial degree ~ U{2,3} and stage
+    family ~ U{{4,8}, {4,8,16}}; Mach 0.5, t in [0, 1]."""
+    rng = np.random.default_rng(seed)
+    runs = []
+    for k in range(n_runs):
+        n = int(rng.integers(8, 65))
+        L = int(rng.integers(1, 4))
+        eps = float(rng.uniform(1.0, 5.0))
+        p = int(rng.integers(2, 4))
+        fam = (4, 8) if rng.integers(0, 2) == 0 else (4, 8, 16)
+        runs.append(dict(n_root=n, levels=L, eps=eps, degree=p, E=fam, mesh=mesh_vortex_disks(n, L)))
+    return runs
+
+
 # ------------------------------------------------------------------------------------------
 # Initial conditions at caller-supplied coordinates.  Conservative output with the variable
 # axis first: rho, rho v_1..rho v_d, E.

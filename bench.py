@@ -148,7 +148,132 @@ def wl_tgv():
                      "optimised step")
 
 
-WORKLOADS = {"vortex_2level": wl_vortex_2level, "kh_amr": wl_kh_amr, "tgv": wl_tgv,
+def vortex_family(degree, E):
+    """P-ERK2 family with stage counts E optimised on the spectrum of the isentropic vortex
+    (strength 5) on a 4x4 reduced mesh of [-5,5]^2 at the given degree."""
+    import perk_inputs as pin
+    red = pin.uniform_mesh(2, (4, 4), (-5, -5), (5, 5), 0)
+    ic = lambda x: pin.isentropic_vortex(x[0], x[1])
+    return family_for(f"perk2_{'_'.join(str(e) for e in E)}_vortex_p{degree}", 2, list(E), red, degree, ic, 2.5)
+
+
+def batch_runs(replicas=1, cfl=0.4):
+    """The batched workload: 64 seeded isentropic-vortex runs of uneven size (roots per side
+    8..64, 1-3 nested refinement disks, strength 1..5, degree 2 or 3, P-ERK2 {4,8} or {4,8,16}),
+    each to t = 1 at cfl times its largest stable step, replicated `replicas` times.  (At CFL
+    0.6 nine and at 0.8 twenty-seven of the {4,8,16} runs blow up before t = 1; 0.4 keeps all.)"""
+    import perk_inputs as pin
+    from paper_2403_05144_amd import partition_rule
+    runs = []
+    for spec in pin.batch_vortex_runs():
+        fam = vortex_family(spec["degree"], spec["E"])
+        mesh = spec["mesh"]
+        lmax = int(mesh.leaves[:, 0].max())
+        mol = partition_rule.paper_rule(lmax, len(fam.E))
+        dt = stable_dt(fam, mesh, mol, cfl)
+        n_steps = int(math.ceil(1.0 / dt))
+        runs.append(dict(spec, fam=fam, mol=mol, dt=1.0 / n_steps, n_steps=n_steps))
+    return runs * replicas
+
+
+def run_batch(args):
+    """Batched independent runs: one stage-tick launch for all runs, against the same runs
+    launched one after another through the single-run path (graph replay)."""
+    import torch
+    import perk_inputs as pin
+    from paper_2403_05144_amd import PerkBatch, PerkSolver
+    specs = batch_runs(args.batch_replicas)
+    solvers, u0s = [], []
+    for sp in specs:
+        m = sp["mesh"]
+        mesh = pin.MeshDesc(m.dim, m.n_root, m.lo, m.hi, np.array(m.leaves, copy=True))
+        s = PerkSolver(mesh, sp["degree"], sp["fam"], sp["mol"])
+        x = s.node_coords().cpu().numpy().transpose(1, 0, 2)
+        u0 = pin.isentropic_vortex(x[0], x[1], eps=sp["eps"]).transpose(1, 0, 2).copy()
+        s.set_state(u0)
+        solvers.append(s)
+        u0s.append(s.u.clone())
+    n_runs = len(solvers)
+    dofs = [s.n_elements * s.nv * s.Nd for s in solvers]
+    work = sum(d * sp["n_steps"] for d, sp in zip(dofs, specs))
+    _log(f"batch: {n_runs} runs, {sum(s.n_elements for s in solvers)} elements, {work:.3g} DoF-updates")
+
+    def reset():
+        for s, u in zip(solvers, u0s):
+            s.u.copy_(u)
+            s.counters(reset=True)
+        torch.cuda.synchronize()
+
+    # sequential comparator (warm: every run's step graph captured beforehand)
+    for s, sp in zip(solvers, specs):
+        s.step(sp["dt"], 1)
+    reset()
+    t0 = time.perf_counter()
+    for s, sp in zip(solvers, specs):
+        s.step(sp["dt"], sp["n_steps"])
+    torch.cuda.synchronize()
+    wall_seq = time.perf_counter() - t0
+    seq_states = [s.u.clone() for s in solvers]
+    seq_es = sum(s.counters()[0] for s in solvers)
+    reset()
+    b = PerkBatch(solvers)
+    b.set_steps([sp["dt"] for sp in specs], [sp["n_steps"] for sp in specs])
+    tune = b.autotune()
+    n_ticks, es = b.info()
+    reset()
+    b.run()                                   # warm-up pass
+    reset()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    b.run()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    same = all(torch.equal(s.u, ref) for s, ref in zip(solvers, seq_states))
+    finite = all(bool(torch.isfinite(s.u[: s.n_elements * s.nv * s.Nd]).all()) for s in solvers)
+    if not finite:
+        raise RuntimeError("non-finite state after the batched runs")
+    # algorithmic bytes and flops of all element-stages (per run: its degree)
+    bytes_tot = flops_tot = 0.0
+    for s in solvers:
+        k = s.counters()[0]
+        bytes_tot += k * bytes_per_element_stage(2, s.N)
+        flops_tot += k * flops_per_element_stage(2, s.N)
+    t_kernel = gpu_ms * 1e-3 / n_ticks          # per tick: launch gaps included (stream events)
+    gbs = bytes_tot / n_ticks / t_kernel / 1e9
+    tflops = flops_tot / n_ticks / t_kernel / 1e12
+    frac_b, frac_f = gbs / HBM_PEAK_GBS, tflops / FP64_PEAK_TFLOPS
+    roof = ({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": frac_b}
+            if frac_b >= frac_f else
+            {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": frac_f})
+    roof.update(traffic=None, kernel="k_stage_batch", avg_launch_us=t_kernel * 1e6,
+                element_stages_per_launch=es / n_ticks,
+                alt={"hbm_frac": frac_b, "alu_frac": frac_f, "gbs": gbs, "tflops": tflops})
+    name = f"batch_vortex64_x{args.batch_replicas}"
+    return {
+        "metric": "DoF-updates/s & PID; P-ERK vs single-level RK wall time at equal error",
+        "value": work / wall, "unit": "DoF-updates/s", "n_gpus": 1, "steps": int(n_ticks), "warmup": 1,
+        "ms_per_step": wall / n_ticks * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": name, "runs": n_runs, "elements": int(sum(s.n_elements for s in solvers)),
+                   "description": "64 seeded 2D Euler isentropic-vortex runs of uneven size (8..64 roots per side, "
+                                  "1-3 nested refinement disks of radii 3/2/1, strength U[1,5], degree 2 or 3, "
+                                  "P-ERK2 {4,8} or {4,8,16} optimised on the vortex spectrum, CFL 0.4, t in [0,1]), "
+                                  f"replicated x{args.batch_replicas}; one launch per stage tick",
+                   "tiling": tune["tiling"], "ticks": int(n_ticks)},
+        "pid_s": wall / sum(s.counters()[0] * s.nv * s.Nd for s in solvers),
+        "batched_vs_sequential": {"sequential_wall_s": wall_seq, "batched_wall_s": wall,
+                                  "speedup": wall_seq / wall, "bitwise_equal": bool(same),
+                                  "element_stages": int(es), "element_stages_sequential": int(seq_es)},
+        "autotune": tune,
+        "roofline": roof,
+    }
+
+
+WORKLOADS = {"vortex_2level": wl_vortex_2level, "kh_amr": wl_kh_amr, "tgv": wl_tgv, "batch_vortex64": None,
              "kh_amr_l4-7": lambda: wl_kh_amr(16, 3, "kh_amr_l4-7")}
 
 
@@ -650,6 +775,7 @@ def main():
     ap.add_argument("--workload", default="kh_amr", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--batch-replicas", type=int, default=1, help="batch_vortex64: copies of the 64 runs")
     ap.add_argument("--no-equal-error", action="store_true",
                     help="skip the comparison with single-level schemes at equal error")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -669,7 +795,7 @@ def main():
         print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU design is "
               "documented but not built", file=sys.stderr)
         sys.exit(2)
-    line = run(args)
+    line = run_batch(args) if args.workload == "batch_vortex64" else run(args)
     print(json.dumps(line), flush=True)
 
 

@@ -217,9 +217,10 @@ pe_status pe_profile_stats(pe_ctx* ctx, double* kernel_ms, int64_t* launches, in
  * Many independent partitioned P-ERK runs (the step of Sec. 3 with the level partition of
  * Sec. 6, each run with its own mesh, polynomial degree, coefficient family, stage count S and
  * dt) advanced together: one kernel launch per stage tick moves every unfinished run by one of
- * its own stages.  A run with S stages and n steps is busy for n S ticks; tick t applies its
- * stage t mod S.  The work of a tick is the concatenation of the active element prefixes of
- * the runs, cut into tiles; results are bitwise those of pe_step on each run alone.
+ * its own stages (one launch per polynomial degree present in the batch).  A run with S stages
+ * and n steps is busy for n S ticks; tick t applies its stage t mod S.  The work of a tick is
+ * the concatenation of the active element prefixes of the runs, cut into tiles; results are
+ * bitwise those of pe_step on each run alone.
  * Supported: 2D Euler runs of degree 2 or 3 whose members all evaluate at least 3 stages.
  * Device tables for the batch are allocated by the library; the runs keep owning their state
  * and workspace, and pe_get_state / pe_counters read each run as usual. */

@@ -1134,7 +1134,9 @@ pe_status pe_counters(pe_ctx* ctx, int64_t* total, int64_t* per_member, int rese
 
 // ------------------------------------------------------------------ batched runs
 struct pe_batch {
-  std::vector<pe_ctx*> runs;
+  std::vector<pe_ctx*> runs;             // caller's order
+  std::vector<int> order;                // internal position -> caller's index (degree 3 first)
+  int split = 0;                         // internal positions [0, split) have N = 4, the rest N = 3
   int M = 1;                             // elements of p = 3 per tile (2M of p = 2)
   int grid = 0;                          // blocks per tick; 0: one block per tile
   bool have_steps = false;
@@ -1184,8 +1186,9 @@ void build_tiles(pe_batch* b) {
   for (int64_t t = 0; t < b->n_ticks; ++t) {
     int32_t* row = &b->tiles[(size_t)t * (nr + 1)];
     int acc = 0;
-    for (int k = 0; k < nr; ++k) {
-      row[k] = acc;
+    for (int q = 0; q < nr; ++q) {
+      row[q] = acc;
+      const int k = b->order[q];
       const pe_ctx* c = b->runs[k];
       if (t < b->ticks[k]) {
         const int na = c->n_act[(size_t)(t % c->S)];
@@ -1234,6 +1237,11 @@ pe_status pe_batch_create(pe_batch** out, pe_ctx* const* runs, int n_runs) {
   pe_batch* b = new (std::nothrow) pe_batch();
   if (!b) return bfail(nullptr, PE_ENOMEM, "batch: out of host memory");
   b->runs.assign(runs, runs + n_runs);
+  for (int k = 0; k < n_runs; ++k)
+    if (runs[k]->N == 4) b->order.push_back(k);
+  b->split = (int)b->order.size();
+  for (int k = 0; k < n_runs; ++k)
+    if (runs[k]->N == 3) b->order.push_back(k);
   *out = b;
   return PE_OK;
 }
@@ -1250,12 +1258,14 @@ pe_status pe_batch_set_steps(pe_batch* b, const double* dt, const int64_t* n_ste
   b->brun.assign(nr, BatchRun{});
   b->ticks.assign(nr, 0);
   b->n_ticks = 0;
-  for (int k = 0; k < nr; ++k) {
-    pe_ctx* c = b->runs[k];
+  for (int k = 0; k < nr; ++k)
     if (!(dt[k] > 0.0) || n_steps[k] < 0) return bfail(b, PE_EINVAL, "batch: run %d: dt must be > 0, n_steps >= 0", k);
+  for (int q = 0; q < nr; ++q) {
+    const int k = b->order[q];
+    pe_ctx* c = b->runs[k];
     if (!c->partitioned || !c->state_valid || (int)c->n_act.size() != c->S)
       return bfail(b, PE_ESTATE, "batch: run %d lost its partition or state", k);
-    BatchRun& r = b->brun[k];
+    BatchRun& r = b->brun[q];
     r.m = device_mesh(c);
     r.op = c->ops;
     r.ph = c->ph;
@@ -1315,9 +1325,17 @@ pe_status pe_batch_run(pe_batch* b, int64_t tick_begin, int64_t tick_end, void* 
   const int nr = (int)b->runs.size();
   hipStream_t s = (hipStream_t)stream;
   for (int64_t t = tick_begin; t < tick_end; ++t) {
-    const int n_tiles = b->tiles[(size_t)t * (nr + 1) + nr];
-    const int g = b->grid > 0 ? std::min(b->grid, n_tiles) : n_tiles;
-    BCHK(launch_stage_batch(b->M, g, b->d_runs, b->d_sargs, b->d_tiles + (size_t)t * (nr + 1), nr, t, s));
+    const int32_t* row = &b->tiles[(size_t)t * (nr + 1)];
+    const int32_t* drow = b->d_tiles + (size_t)t * (nr + 1);
+    // one launch per degree present at this tick: runs [0, split) of degree 3, then degree 2
+    const int cls[2][3] = {{4, 0, b->split}, {3, b->split, nr}};
+    for (const auto& cl : cls) {
+      const int n_tiles = row[cl[2]] - row[cl[1]];
+      if (n_tiles <= 0) continue;
+      const bool persistent = b->grid > 0 && b->grid < n_tiles;
+      const int g = persistent ? b->grid : n_tiles;
+      BCHK(launch_stage_batch(cl[0], b->M, g, persistent, b->d_runs, b->d_sargs, drow, cl[1], cl[2], t, s));
+    }
   }
   return PE_OK;
 }

@@ -147,10 +147,12 @@ hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s)
 // over its slots into beta[kMaxLevels] (0 for empty levels, NaN propagates).
 hipError_t launch_wave_speed(int dim, int N, int n, const double* U, const Physics& ph, const Mesh& m, double* w_slot,
                              double* w_level, hipStream_t s);
-// One batched stage tick (2D Euler runs, p = 2 or 3): M in {1, 2, 4} elements of p = 3 per
-// tile (2M of p = 2), grid blocks; tile_off [n_runs + 1] are the tick's tile offsets.
-hipError_t launch_stage_batch(int M, int grid, const BatchRun* runs, const StageArgs* sargs, const int32_t* tile_off,
-                              int n_runs, int64_t tick, hipStream_t s);
+// One batched stage tick over the runs k0 <= k < k1, all of N nodes per direction (2D Euler,
+// N = 3 or 4): M in {1, 2, 4} elements of N = 4 per tile (2M of N = 3), grid blocks;
+// tile_off [n_runs + 1] are the tick's tile offsets.  persistent: the grid loops over the
+// tiles; otherwise grid must equal the tile count (one block per tile).
+hipError_t launch_stage_batch(int N, int M, int grid, bool persistent, const BatchRun* runs, const StageArgs* sargs,
+                              const int32_t* tile_off, int k0, int k1, int64_t tick, hipStream_t s);
 hipError_t launch_fold_evals(int n, const Mesh& m, int32_t* evals, unsigned long long* totals, hipStream_t s);
 
 }  // namespace perk

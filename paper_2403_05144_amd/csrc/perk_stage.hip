@@ -576,42 +576,52 @@ __global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB), (SK<DIM, N>::MIN
 }
 
 // ------------------------------------------------------------------------------------------
-// Batched stage tick: many independent 2D Euler runs, each advanced by one of its own stages.
-// The tiles of the tick (EPB elements of one run each) are the concatenated active prefixes
-// of the unfinished runs, tile_off[k] the first tile of run k; a block of 64 M lanes takes
-// tiles blockIdx.x, blockIdx.x + gridDim.x, ... (persistent when the grid is smaller than the
-// tile count) and runs the p = 3 body with M elements or the p = 2 body with 2 M elements.
+// Batched stage tick: many independent 2D Euler runs of one polynomial degree, each advanced by
+// one of its own stages.  The tiles of the tick (EPB elements of one run each) are the
+// concatenated active prefixes of the unfinished runs k0 <= k < k1, tile_off[k] the first tile
+// of run k; block b takes tiles b, b + gridDim.x, ... (persistent when the grid is smaller
+// than the tile count).  One instantiation per degree keeps the register allocation of a
+// single body (both bodies in one kernel double it).
 // ------------------------------------------------------------------------------------------
-template <int M>
-__global__ __launch_bounds__(64 * M) void k_stage_batch(const BatchRun* __restrict__ runs,
-                                                          const StageArgs* __restrict__ sargs,
-                                                          const int32_t* __restrict__ tile_off, int n_runs,
-                                                          int64_t tick) {
-  const int n_tiles = tile_off[n_runs];
-  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    int lo = 0, hi = n_runs - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (tile_off[mid] <= t) lo = mid;
-      else hi = mid - 1;
-    }
-    const int k = __builtin_amdgcn_readfirstlane(lo);
-    const BatchRun& r = runs[k];
-    const StageArgs& a = sargs[r.sarg0 + (int)(tick % r.S)];
-    const int blk = t - tile_off[k];
-    if (r.N == 4) stage_block<2, 4, false, M>(a, r.m, r.op, r.ph, blk);
-    else stage_block<2, 3, false, 2 * M>(a, r.m, r.op, r.ph, blk);
+template <int N, int EPB>
+__device__ __forceinline__ void batch_tile(const BatchRun* __restrict__ runs, const StageArgs* __restrict__ sargs,
+                                           const int32_t* __restrict__ tile_off, int k0, int k1, int64_t tick, int t) {
+  int lo = k0, hi = k1 - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_off[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const int k = __builtin_amdgcn_readfirstlane(lo);
+  const BatchRun& r = runs[k];
+  const StageArgs& a = sargs[r.sarg0 + (int)(tick % r.S)];
+  stage_block<2, N, false, EPB>(a, r.m, r.op, r.ph, t - tile_off[k]);
+}
+
+// one block per tile, no loop: the register allocation of the single-run kernel
+template <int N, int EPB>
+__global__ __launch_bounds__((SK<2, N>::T * EPB)) void k_stage_batch_flat(const BatchRun* __restrict__ runs,
+                                                                          const StageArgs* __restrict__ sargs,
+                                                                          const int32_t* __restrict__ tile_off,
+                                                                          int k0, int k1, int64_t tick) {
+  batch_tile<N, EPB>(runs, sargs, tile_off, k0, k1, tick, tile_off[k0] + (int)blockIdx.x);
+}
+
+// persistent: a fixed grid loops over the tiles (values hoisted out of the loop raise the
+// register count, so the autotuner weighs it against the flat form)
+template <int N, int EPB>
+__global__ __launch_bounds__((SK<2, N>::T * EPB)) void k_stage_batch(const BatchRun* __restrict__ runs,
+                                                                     const StageArgs* __restrict__ sargs,
+                                                                     const int32_t* __restrict__ tile_off, int k0,
+                                                                     int k1, int64_t tick) {
+  const int t0 = tile_off[k0];
+  const int n_tiles = tile_off[k1] - t0;
+  for (int tt = blockIdx.x; tt < n_tiles; tt += gridDim.x) {
+    batch_tile<N, EPB>(runs, sargs, tile_off, k0, k1, tick, t0 + tt);
     __syncthreads();
   }
 }
 
-// ------------------------------------------------------------------------------------------
-// BR1 gradient kernel (Navier-Stokes).  One element per block.  w = (v_1..v_d, T), T = p/rho:
-//   q_d = (2/h_d) [ D w along d + lifting of (w* - w) at the two boundary nodes ],
-// w* the central average of the two traces (interpolated to, and projected back from, the
-// sub-faces of a mortar); then the viscous flux F_v(w, q) in every direction at every node:
-//   tau = mu (grad v + grad v^T) - 2/3 mu (div v) I, F_v,d = (0, tau_{:,d}, tau_{:,d}.v + kappa dT/dx_d).
-// ------------------------------------------------------------------------------------------
 template <int DIM, int N>
 struct GKc {
   using g = G<DIM, N>;
@@ -822,14 +832,28 @@ hipError_t launch_stage_t(const StageArgs& a, const Mesh& m, const Ops& op, cons
 
 }  // namespace
 
-hipError_t launch_stage_batch(int M, int grid, const BatchRun* runs, const StageArgs* sargs, const int32_t* tile_off,
-                              int n_runs, int64_t tick, hipStream_t s) {
-  if (grid <= 0) return hipSuccess;
-  if (M == 1) hipLaunchKernelGGL((k_stage_batch<1>), dim3(grid), dim3(64), 0, s, runs, sargs, tile_off, n_runs, tick);
-  else if (M == 2) hipLaunchKernelGGL((k_stage_batch<2>), dim3(grid), dim3(128), 0, s, runs, sargs, tile_off, n_runs, tick);
-  else if (M == 4) hipLaunchKernelGGL((k_stage_batch<4>), dim3(grid), dim3(256), 0, s, runs, sargs, tile_off, n_runs, tick);
-  else return hipErrorNotSupported;
+template <int N, int EPB>
+hipError_t launch_batch_t(bool persistent, int grid, const BatchRun* runs, const StageArgs* sargs,
+                          const int32_t* tile_off, int k0, int k1, int64_t tick, hipStream_t s) {
+  const dim3 b(SK<2, N>::T * EPB);
+  if (persistent)
+    hipLaunchKernelGGL((k_stage_batch<N, EPB>), dim3(grid), b, 0, s, runs, sargs, tile_off, k0, k1, tick);
+  else
+    hipLaunchKernelGGL((k_stage_batch_flat<N, EPB>), dim3(grid), b, 0, s, runs, sargs, tile_off, k0, k1, tick);
   return hipGetLastError();
+}
+
+hipError_t launch_stage_batch(int N, int M, int grid, bool persistent, const BatchRun* runs, const StageArgs* sargs,
+                              const int32_t* tile_off, int k0, int k1, int64_t tick, hipStream_t s) {
+  if (grid <= 0 || k1 <= k0) return hipSuccess;
+  // M elements of degree 3 per tile (64 M lanes), 2 M of degree 2 (32 lanes each)
+  if (N == 4 && M == 1) return launch_batch_t<4, 1>(persistent, grid, runs, sargs, tile_off, k0, k1, tick, s);
+  if (N == 4 && M == 2) return launch_batch_t<4, 2>(persistent, grid, runs, sargs, tile_off, k0, k1, tick, s);
+  if (N == 4 && M == 4) return launch_batch_t<4, 4>(persistent, grid, runs, sargs, tile_off, k0, k1, tick, s);
+  if (N == 3 && M == 1) return launch_batch_t<3, 2>(persistent, grid, runs, sargs, tile_off, k0, k1, tick, s);
+  if (N == 3 && M == 2) return launch_batch_t<3, 4>(persistent, grid, runs, sargs, tile_off, k0, k1, tick, s);
+  if (N == 3 && M == 4) return launch_batch_t<3, 8>(persistent, grid, runs, sargs, tile_off, k0, k1, tick, s);
+  return hipErrorNotSupported;
 }
 
 hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,

@@ -41,6 +41,41 @@
 namespace {
 
 // ------------------------------------------------------------------------------------------
+// Forward-mode dual number v + d eps (eps^2 = 0): evaluating a function on duals yields its
+// value and its derivative along the seeded direction, following the branches the value takes.
+// Used only for the tangent-linear and adjoint checks of the Euler operator.
+// ------------------------------------------------------------------------------------------
+struct Dual {
+  double v = 0.0, d = 0.0;
+  Dual() = default;
+  Dual(double x) : v(x), d(0.0) {}
+  Dual(double x, double dx) : v(x), d(dx) {}
+};
+inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+inline Dual operator-(Dual a) { return {-a.v, -a.d}; }
+inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+inline Dual operator/(Dual a, Dual b) { return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)}; }
+inline Dual& operator+=(Dual& a, Dual b) { return a = a + b; }
+inline Dual& operator-=(Dual& a, Dual b) { return a = a - b; }
+inline bool operator<(Dual a, double b) { return a.v < b; }
+inline bool operator>=(Dual a, double b) { return a.v >= b; }
+inline bool operator<=(Dual a, double b) { return a.v <= b; }
+inline Dual log(Dual a) { return {std::log(a.v), a.d / a.v}; }
+inline Dual sqrt(Dual a) {
+  const double r = std::sqrt(a.v);
+  return {r, 0.5 * a.d / r};
+}
+inline Dual fmin(Dual a, Dual b) { return b.v < a.v ? b : a; }
+inline Dual fmax(Dual a, Dual b) { return b.v > a.v ? b : a; }
+using std::fmax;
+using std::fmin;
+using std::log;
+using std::sqrt;
+inline double value_of(double x) { return x; }
+inline double value_of(Dual x) { return x.v; }
+
+// ------------------------------------------------------------------------------------------
 // Legendre-Gauss-Lobatto nodes and weights, Lagrange basis, differentiation matrix.
 // ------------------------------------------------------------------------------------------
 void legendre_and_derivative(int n, double x, double& P, double& dP) {
@@ -127,14 +162,17 @@ struct Phys {
   int surface_ec;  // 0: HLL surface flux; 1: entropy-conserving flux on faces (entropy pin)
 };
 
-struct Prim {
-  double rho, v[3], p;
+template <class T>
+struct PrimT {
+  T rho, v[3], p;
 };
+using Prim = PrimT<double>;
 
-Prim cons2prim(const Phys& ph, const double* u) {
-  Prim q;
+template <class T>
+PrimT<T> cons2prim(const Phys& ph, const T* u) {
+  PrimT<T> q;
   q.rho = u[0];
-  double ke = 0.0;
+  T ke = 0.0;
   for (int d = 0; d < 3; ++d) q.v[d] = 0.0;
   for (int d = 0; d < ph.dim; ++d) {
     q.v[d] = u[1 + d] / u[0];
@@ -145,8 +183,9 @@ Prim cons2prim(const Phys& ph, const double* u) {
 }
 
 // physical flux in direction d
-void euler_flux(const Phys& ph, const double* u, int d, double* f) {
-  Prim q = cons2prim(ph, u);
+template <class T>
+void euler_flux(const Phys& ph, const T* u, int d, T* f) {
+  PrimT<T> q = cons2prim(ph, u);
   const int nv = ph.dim + 2;
   f[0] = u[1 + d];
   for (int k = 0; k < ph.dim; ++k) f[1 + k] = u[1 + k] * q.v[d];
@@ -158,28 +197,30 @@ void euler_flux(const Phys& ph, const double* u, int d, double* f) {
 // (a+b) / (2 F(u)), F(u) = ln(b/a)/(2f) = sum_k u^k/(2k+1); for u < 1e-2 the series through
 // u^7/15 is used (truncation below u^8/17 < 1e-17), so the logarithm is only evaluated where
 // |ln(b/a)| > 0.2 and the quotient loses little to cancellation.
-double log_mean(double a, double b) {
-  double f = (b - a) / (b + a);
-  double u = f * f;
+template <class T>
+T log_mean(T a, T b) {
+  T f = (b - a) / (b + a);
+  T u = f * f;
   if (u < 1e-2) {
-    double F = 1.0 + u / 3.0 + u * u / 5.0 + u * u * u / 7.0 + u * u * u * u / 9.0 +
-               u * u * u * u * u / 11.0 + u * u * u * u * u * u / 13.0 + u * u * u * u * u * u * u / 15.0;
+    T F = 1.0 + u / 3.0 + u * u / 5.0 + u * u * u / 7.0 + u * u * u * u / 9.0 +
+          u * u * u * u * u / 11.0 + u * u * u * u * u * u / 13.0 + u * u * u * u * u * u * u / 15.0;
     return (a + b) / (2.0 * F);
   }
-  return (b - a) / std::log(b / a);
+  return (b - a) / log(b / a);
 }
 
 // Entropy-conserving and kinetic-energy-preserving two-point flux (Ranocha), direction d:
 //   f^rho = rho_ln {{v_d}},  f^{rho v_k} = f^rho {{v_k}} + {{p}} delta_kd,
 //   f^E = f^rho (1/2 v_L . v_R + 1/((gamma-1) (rho/p)_ln)) + 1/2 (p_L v_{d,R} + p_R v_{d,L}).
-void ec_flux(const Phys& ph, const double* uL, const double* uR, int d, double* f) {
-  Prim L = cons2prim(ph, uL), R = cons2prim(ph, uR);
+template <class T>
+void ec_flux(const Phys& ph, const T* uL, const T* uR, int d, T* f) {
+  PrimT<T> L = cons2prim(ph, uL), R = cons2prim(ph, uR);
   const int nv = ph.dim + 2;
-  double rho_ln = log_mean(L.rho, R.rho);
-  double beta_ln = log_mean(L.rho / L.p, R.rho / R.p);
-  double vd = 0.5 * (L.v[d] + R.v[d]);
-  double p_avg = 0.5 * (L.p + R.p);
-  double vLvR = 0.0;
+  T rho_ln = log_mean(L.rho, R.rho);
+  T beta_ln = log_mean(L.rho / L.p, R.rho / R.p);
+  T vd = 0.5 * (L.v[d] + R.v[d]);
+  T p_avg = 0.5 * (L.p + R.p);
+  T vLvR = 0.0;
   for (int k = 0; k < ph.dim; ++k) vLvR += L.v[k] * R.v[k];
   f[0] = rho_ln * vd;
   for (int k = 0; k < ph.dim; ++k) f[1 + k] = f[0] * 0.5 * (L.v[k] + R.v[k]);
@@ -189,14 +230,15 @@ void ec_flux(const Phys& ph, const double* uL, const double* uR, int d, double* 
 }
 
 // HLL flux with Davis wave speeds; normal +e_d from L to R.
-void hll_flux(const Phys& ph, const double* uL, const double* uR, int d, double* f) {
+template <class T>
+void hll_flux(const Phys& ph, const T* uL, const T* uR, int d, T* f) {
   const int nv = ph.dim + 2;
-  Prim L = cons2prim(ph, uL), R = cons2prim(ph, uR);
-  double cL = std::sqrt(ph.gamma * L.p / L.rho);
-  double cR = std::sqrt(ph.gamma * R.p / R.rho);
-  double sL = std::fmin(L.v[d] - cL, R.v[d] - cR);
-  double sR = std::fmax(L.v[d] + cL, R.v[d] + cR);
-  double fL[5], fR[5];
+  PrimT<T> L = cons2prim(ph, uL), R = cons2prim(ph, uR);
+  T cL = sqrt(ph.gamma * L.p / L.rho);
+  T cR = sqrt(ph.gamma * R.p / R.rho);
+  T sL = fmin(L.v[d] - cL, R.v[d] - cR);
+  T sR = fmax(L.v[d] + cL, R.v[d] + cR);
+  T fL[5], fR[5];
   euler_flux(ph, uL, d, fL);
   euler_flux(ph, uR, d, fR);
   if (sL >= 0.0) {
@@ -341,8 +383,9 @@ struct Solver {
   }
 
   // trace (all variables) of a nodal field with nvar components on face (d, s) of element e
-  void trace(const double* f, int nvar, int e, int d, int s, std::vector<double>& out) const {
-    out.assign(nvar * Nf, 0.0);
+  template <class T>
+  void trace(const T* f, int nvar, int e, int d, int s, std::vector<T>& out) const {
+    out.assign(nvar * Nf, T(0.0));
     int nb = dim == 3 ? N : 1;
     for (int b = 0; b < nb; ++b)
       for (int a = 0; a < N; ++a) {
@@ -352,13 +395,14 @@ struct Solver {
   }
 
   // interpolate a face field (nvar components) to sub-face (sub[0], sub[1]) with P_m
-  void to_subface(const std::vector<double>& in, int nvar, const int* sub, std::vector<double>& out) const {
-    out.assign(nvar * Nf, 0.0);
+  template <class T>
+  void to_subface(const std::vector<T>& in, int nvar, const int* sub, std::vector<T>& out) const {
+    out.assign(nvar * Nf, T(0.0));
     if (dim == 2) {
       const auto& P = Pm[sub[0]];
       for (int v = 0; v < nvar; ++v)
         for (int j = 0; j < N; ++j) {
-          double acc = 0.0;
+          T acc = 0.0;
           for (int i = 0; i < N; ++i) acc += P[j * N + i] * in[v * Nf + i];
           out[v * Nf + j] = acc;
         }
@@ -368,7 +412,7 @@ struct Solver {
       for (int v = 0; v < nvar; ++v)
         for (int j2 = 0; j2 < N; ++j2)
           for (int j1 = 0; j1 < N; ++j1) {
-            double acc = 0.0;
+            T acc = 0.0;
             for (int i2 = 0; i2 < N; ++i2)
               for (int i1 = 0; i1 < N; ++i1)
                 acc += P1[j1 * N + i1] * P2[j2 * N + i2] * in[v * Nf + i1 + N * i2];
@@ -378,12 +422,13 @@ struct Solver {
   }
 
   // project a sub-face field back to the coarse face with R_m and add
-  void add_projection(const std::vector<double>& in, int nvar, int m, std::vector<double>& acc) const {
+  template <class T>
+  void add_projection(const std::vector<T>& in, int nvar, int m, std::vector<T>& acc) const {
     if (dim == 2) {
       const auto& R = Rm[m];
       for (int v = 0; v < nvar; ++v)
         for (int i = 0; i < N; ++i) {
-          double s = 0.0;
+          T s = 0.0;
           for (int j = 0; j < N; ++j) s += R[i * N + j] * in[v * Nf + j];
           acc[v * Nf + i] += s;
         }
@@ -393,7 +438,7 @@ struct Solver {
       for (int v = 0; v < nvar; ++v)
         for (int i2 = 0; i2 < N; ++i2)
           for (int i1 = 0; i1 < N; ++i1) {
-            double s = 0.0;
+            T s = 0.0;
             for (int j2 = 0; j2 < N; ++j2)
               for (int j1 = 0; j1 < N; ++j1)
                 s += R1[i1 * N + j1] * R2[i2 * N + j2] * in[v * Nf + j1 + N * j2];
@@ -406,14 +451,13 @@ struct Solver {
   // rule(left_values, right_values, d, out) applied node by node.  `field` holds nvar
   // components per node.  Conforming: rule on the shared nodes.  Fine side: the coarse trace
   // is interpolated to this sub-face.  Coarse side: rule on every sub-face, projected back.
-  template <class Rule>
-  void face_values(const double* field, int nvar, int e, int d, int s, Rule rule,
-                   std::vector<double>& out) const {
+  template <class T, class Rule>
+  void face_values(const T* field, int nvar, int e, int d, int s, Rule rule, std::vector<T>& out) const {
     const Face& F = faces[e][2 * d + s];
-    std::vector<double> mine, other, tmp, res(nvar * Nf);
+    std::vector<T> mine, other, tmp, res(nvar * Nf);
     trace(field, nvar, e, d, s, mine);
-    auto apply = [&](const std::vector<double>& own, const std::vector<double>& nb, std::vector<double>& r) {
-      std::vector<double> a(nvar), b(nvar), o(nvar);
+    auto apply = [&](const std::vector<T>& own, const std::vector<T>& nb, std::vector<T>& r) {
+      std::vector<T> a(nvar), b(nvar), o(nvar);
       for (int n = 0; n < Nf; ++n) {
         for (int v = 0; v < nvar; ++v) {
           a[v] = own[v * Nf + n];
@@ -434,11 +478,11 @@ struct Solver {
       apply(mine, other, res);
       out = res;
     } else {
-      out.assign(nvar * Nf, 0.0);
+      out.assign(nvar * Nf, T(0.0));
       int nsub = 1 << (dim - 1);
       for (int m = 0; m < nsub; ++m) {
         int sub[2] = {m & 1, (m >> 1) & 1};
-        std::vector<double> mine_m;
+        std::vector<T> mine_m;
         to_subface(mine, nvar, sub, mine_m);
         trace(field, nvar, F.nbr[m], d, 1 - s, other);
         apply(mine_m, other, res);
@@ -456,11 +500,12 @@ struct Solver {
     return dim == 2 ? ijk[0] + N * ijk[1] : ijk[0] + N * ijk[1] + N * N * ijk[2];
   }
 
-  // du = F(u)
-  void rhs(const double* u, double* du) const {
+  // inviscid part of du = F(u): volume flux differencing and surface flux (scalar type T:
+  // double, or Dual for the tangent of the Euler operator)
+  template <class T>
+  void rhs_inviscid(const T* u, T* du) const {
     const size_t ne = leaves.size();
-    std::memset(du, 0, sizeof(double) * ne * nv * Nd);
-    // ---- inviscid part: volume flux differencing and surface flux
+    for (size_t q = 0; q < ne * nv * Nd; ++q) du[q] = 0.0;
     for (size_t e = 0; e < ne; ++e) {
       for (int d = 0; d < dim; ++d) {
         double J = 2.0 / h((int)e, d);
@@ -468,7 +513,7 @@ struct Solver {
           int ijk[3];
           node_ijk(nd, ijk);
           int a = ijk[d];
-          double ui[5], um[5], f[5];
+          T ui[5], um[5], f[5];
           for (int v = 0; v < nv; ++v) ui[v] = u[(e * nv + v) * Nd + nd];
           for (int m = 0; m < N; ++m) {
             if (m == a) continue;
@@ -481,9 +526,9 @@ struct Solver {
           }
         }
         for (int s = 0; s < 2; ++s) {
-          std::vector<double> fs;
+          std::vector<T> fs;
           face_values(u, nv, (int)e, d, s,
-                      [&](const double* L, const double* R, int dd, double* o) {
+                      [&](const T* L, const T* R, int dd, T* o) {
                         if (ph.surface_ec) ec_flux(ph, L, R, dd, o);
                         else hll_flux(ph, L, R, dd, o);
                       },
@@ -493,7 +538,7 @@ struct Solver {
             for (int a2 = 0; a2 < N; ++a2) {
               int nd = face_node(d, s, a2, b);
               for (int v = 0; v < nv; ++v) {
-                double val = fs[v * Nf + a2 + N * b];
+                T val = fs[v * Nf + a2 + N * b];
                 if (s == 1) du[(e * nv + v) * Nd + nd] -= J * val / w[N - 1];
                 else du[(e * nv + v) * Nd + nd] += J * val / w[0];
               }
@@ -501,6 +546,12 @@ struct Solver {
         }
       }
     }
+  }
+
+  // du = F(u)
+  void rhs(const double* u, double* du) const {
+    const size_t ne = leaves.size();
+    rhs_inviscid(u, du);
     if (!ph.viscous) return;
     // ---- BR1: gradients of w, viscous flux, divergence
     const int nw = dim + 1;
@@ -775,3 +826,130 @@ int orc_rk_step(void* h, double* u, double dt, int S, const double* A, const dou
   return 0;
 }
 }
+
+// ------------------------------------------------------------------------------------------
+// Tangent-linear and adjoint of the Euler operator and of the partitioned RK step.
+//
+// The discrete adjoint of a map G is G'(u)^T.  Here G' is formed column by column from the
+// forward-mode dual evaluation of G itself (the exact derivative of the computed map, each
+// branch taken as the value takes it), and the adjoint applied to lam is the vector of
+// <lam, G'(u) e_j>.  Dense and slow (one dual evaluation per unknown): for small meshes only.
+// ------------------------------------------------------------------------------------------
+namespace {
+
+template <class T>
+void prk_step_t(const Solver* s, T* u, double dt, int R, int S, const double* A, const double* b,
+                const int32_t* member) {
+  const size_t ne = s->leaves.size();
+  const size_t n = ne * s->nv * s->Nd;
+  const size_t per = (size_t)s->nv * s->Nd;
+  std::vector<std::vector<T>> K(S, std::vector<T>(n));
+  std::vector<T> Y(n);
+  for (int i = 0; i < S; ++i) {
+    for (size_t e = 0; e < ne; ++e) {
+      const double* Ar = A + (size_t)member[e] * S * S;
+      for (size_t q = 0; q < per; ++q) {
+        size_t idx = e * per + q;
+        T acc = 0.0;
+        for (int j = 0; j < i; ++j) acc += Ar[i * S + j] * K[j][idx];
+        Y[idx] = u[idx] + dt * acc;
+      }
+    }
+    s->rhs_inviscid(Y.data(), K[i].data());
+  }
+  for (size_t idx = 0; idx < n; ++idx) {
+    T acc = 0.0;
+    for (int i = 0; i < S; ++i) acc += b[i] * K[i][idx];
+    u[idx] += dt * acc;
+  }
+}
+
+bool check_euler(const Solver* s) {
+  if (s->ph.viscous) {
+    g_err = "tangent and adjoint: Euler operator only";
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+// f = F(u) and t = F'(u) du (Euler)
+int orc_rhs_jvp(void* h, const double* u, const double* du, double* f, double* t) {
+  const Solver* s = static_cast<Solver*>(h);
+  if (!check_euler(s)) return -1;
+  const size_t n = s->leaves.size() * (size_t)s->nv * s->Nd;
+  std::vector<Dual> x(n), y(n);
+  for (size_t q = 0; q < n; ++q) x[q] = Dual(u[q], du[q]);
+  s->rhs_inviscid(x.data(), y.data());
+  for (size_t q = 0; q < n; ++q) {
+    if (f) f[q] = y[q].v;
+    t[q] = y[q].d;
+  }
+  return 0;
+}
+
+// out = F'(u)^T w (Euler), column by column
+int orc_rhs_vjp(void* h, const double* u, const double* w, double* out) {
+  const Solver* s = static_cast<Solver*>(h);
+  if (!check_euler(s)) return -1;
+  const size_t n = s->leaves.size() * (size_t)s->nv * s->Nd;
+  std::vector<Dual> x(n), y(n);
+  for (size_t j = 0; j < n; ++j) {
+    for (size_t q = 0; q < n; ++q) x[q] = Dual(u[q], q == j ? 1.0 : 0.0);
+    s->rhs_inviscid(x.data(), y.data());
+    double acc = 0.0;
+    for (size_t q = 0; q < n; ++q) acc += w[q] * y[q].d;
+    out[j] = acc;
+  }
+  return 0;
+}
+
+// One dense masked partitioned RK step on duals: u_out = Phi(u), t_out = Phi'(u) du (Euler)
+int orc_prk_step_jvp(void* h, const double* u, const double* du, double dt, int R, int S, const double* A,
+                     const double* b, const int32_t* member, double* u_out, double* t_out) {
+  const Solver* s = static_cast<Solver*>(h);
+  if (!check_euler(s)) return -1;
+  const size_t ne = s->leaves.size();
+  for (size_t e = 0; e < ne; ++e)
+    if (member[e] < 0 || member[e] >= R) {
+      g_err = "member index out of range";
+      return -1;
+    }
+  const size_t n = ne * (size_t)s->nv * s->Nd;
+  std::vector<Dual> x(n);
+  for (size_t q = 0; q < n; ++q) x[q] = Dual(u[q], du[q]);
+  prk_step_t(s, x.data(), dt, R, S, A, b, member);
+  for (size_t q = 0; q < n; ++q) {
+    if (u_out) u_out[q] = x[q].v;
+    t_out[q] = x[q].d;
+  }
+  return 0;
+}
+
+// out = Phi'(u)^T lam for one partitioned RK step (Euler), column by column
+int orc_prk_step_vjp(void* h, const double* u, const double* lam, double dt, int R, int S, const double* A,
+                     const double* b, const int32_t* member, double* out) {
+  const Solver* s = static_cast<Solver*>(h);
+  if (!check_euler(s)) return -1;
+  const size_t ne = s->leaves.size();
+  for (size_t e = 0; e < ne; ++e)
+    if (member[e] < 0 || member[e] >= R) {
+      g_err = "member index out of range";
+      return -1;
+    }
+  const size_t n = ne * (size_t)s->nv * s->Nd;
+  std::vector<Dual> x(n);
+  for (size_t j = 0; j < n; ++j) {
+    for (size_t q = 0; q < n; ++q) x[q] = Dual(u[q], q == j ? 1.0 : 0.0);
+    prk_step_t(s, x.data(), dt, R, S, A, b, member);
+    double acc = 0.0;
+    for (size_t q = 0; q < n; ++q) acc += lam[q] * x[q].d;
+    out[j] = acc;
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -60,6 +60,12 @@ def lib():
         L.orc_prk_step.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    dp, dp, ip]
         L.orc_rk_step.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_int, dp, dp]
+        L.orc_rhs_jvp.argtypes = [ctypes.c_void_p, dp, dp, dp, dp]
+        L.orc_rhs_vjp.argtypes = [ctypes.c_void_p, dp, dp, dp]
+        L.orc_prk_step_jvp.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                       dp, dp, ip, dp, dp]
+        L.orc_prk_step_vjp.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                       dp, dp, ip, dp]
         L.orc_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -173,6 +179,50 @@ class Oracle:
         if rc != 0:
             raise ValueError(lib().orc_last_error().decode())
         return u
+
+    # ---- tangent and adjoint of the Euler operator and of the step (dual numbers, dense)
+    def _arr(self, x):
+        return np.ascontiguousarray(np.asarray(x, dtype=float).reshape(self.shape))
+
+    def rhs_jvp(self, u, du):
+        """(F(u), F'(u) du) for the Euler operator."""
+        u, du = self._arr(u), self._arr(du)
+        f, t = np.zeros(self.shape), np.zeros(self.shape)
+        if lib().orc_rhs_jvp(self._h, _dp(u), _dp(du), _dp(f), _dp(t)) != 0:
+            raise ValueError(lib().orc_last_error().decode())
+        return f, t
+
+    def rhs_vjp(self, u, w):
+        """F'(u)^T w, assembled column by column (small meshes only)."""
+        u, w = self._arr(u), self._arr(w)
+        out = np.zeros(self.shape)
+        if lib().orc_rhs_vjp(self._h, _dp(u), _dp(w), _dp(out)) != 0:
+            raise ValueError(lib().orc_last_error().decode())
+        return out
+
+    def _step_args(self, fam, member):
+        A = np.ascontiguousarray(np.stack([dense_A(fam.c, fam.a_sub[r]) for r in range(len(fam.E))]))
+        return A, np.ascontiguousarray(fam.b, float), np.ascontiguousarray(member, np.int32)
+
+    def prk_step_jvp(self, u, du, dt, fam: PerkFamily, member):
+        """(Phi(u), Phi'(u) du) for one partitioned step (Euler)."""
+        u, du = self._arr(u), self._arr(du)
+        A, b, mem = self._step_args(fam, member)
+        u1, t = np.zeros(self.shape), np.zeros(self.shape)
+        if lib().orc_prk_step_jvp(self._h, _dp(u), _dp(du), float(dt), len(fam.E), fam.S, _dp(A), _dp(b), _ip(mem),
+                                  _dp(u1), _dp(t)) != 0:
+            raise ValueError(lib().orc_last_error().decode())
+        return u1, t
+
+    def prk_step_vjp(self, u, lam, dt, fam: PerkFamily, member):
+        """Phi'(u)^T lam for one partitioned step (Euler), column by column (small meshes)."""
+        u, lam = self._arr(u), self._arr(lam)
+        A, b, mem = self._step_args(fam, member)
+        out = np.zeros(self.shape)
+        if lib().orc_prk_step_vjp(self._h, _dp(u), _dp(lam), float(dt), len(fam.E), fam.S, _dp(A), _dp(b), _ip(mem),
+                                  _dp(out)) != 0:
+            raise ValueError(lib().orc_last_error().decode())
+        return out
 
     def rk_step(self, u, dt, A, b):
         u = np.array(u, dtype=float, copy=True).reshape(self.shape)

@@ -173,6 +173,32 @@ pe_status pe_set_graph_replay(pe_ctx* ctx, int on);
 pe_status pe_counters(pe_ctx* ctx, int64_t* out_total, int64_t* out_per_member, int reset,
                       void* stream);
 
+/* ---------------------------------------------------------------- discrete adjoint (Euler)
+ * Reverse mode of the partitioned step of Sec. 3.1 (Y_i = U_n + dt (a_{i,1} K_1 + a_{i,i-1}
+ * K_{i-1}) with each element's member coefficients, K_i = I_i F(Y_i), U_{n+1} = U_n + dt
+ * sum_i b_i K_i) and of the DGSEM right-hand side F of Sec. 6.1: derivatives of the computed
+ * map, flux branches (HLL wave speeds, logarithmic-mean series) as the values take them. */
+
+/* out = F'(u)^T w for the Euler right-hand side; u, w, out device arrays in slot layout
+ * (n_state doubles, see pe_query_sizes; out must not alias u or w).  Asynchronous on stream.
+ * PE_EUNSUPPORTED for Navier-Stokes. */
+pe_status pe_rhs_vjp(pe_ctx* ctx, const double* u, const double* w, double* out, void* stream);
+
+/* Device bytes of the adjoint workspace (S + 2 state arrays: the stage values of a
+ * recomputed step and the stage cotangents), valid for the current coefficients and
+ * capacity; pe_adjoint_bind hands over caller-owned memory (256-byte aligned). */
+pe_status pe_adjoint_query(const pe_ctx* ctx, int64_t* bytes);
+pe_status pe_adjoint_bind(pe_ctx* ctx, void* workspace);
+
+/* lam_prev = Phi'(u_n)^T lam_next for one partitioned step Phi of size dt from u_n (slot
+ * layout device arrays; lam_prev must not alias the inputs).  Recomputes the step from u_n,
+ * keeping the stage values in the adjoint workspace, then sweeps the stages backwards
+ * launching the adjoint kernel only on each stage's active elements and their face
+ * neighbours.  The bound state is not touched; the stage workspace of pe_step is reused.
+ * Asynchronous on stream. */
+pe_status pe_step_adjoint(pe_ctx* ctx, double dt, const double* u_n, const double* lam_next, double* lam_prev,
+                          void* stream);
+
 /* Step-size bound of eq. (CFL_DG) and eq. (TimestepConstraint) from the bound state:
  * beta_l = 1 / max over the elements of level l, their nodes and the directions d of
  * (k+1)(|v_d| + c) / h_d  (k the polynomial degree, c the speed of sound; convective part only,

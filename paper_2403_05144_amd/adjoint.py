@@ -1,0 +1,49 @@
+"""Differentiated form: a time trajectory of the partitioned P-ERK step as a
+torch.autograd.Function, with the discrete adjoint of libperk (pe_step_adjoint) and
+checkpointed recomputation.
+
+forward: n steps of size dt from u0 (slot layout), keeping the state every `every` steps.
+backward: for each segment, last first, recompute the segment's states from its checkpoint
+(pe_step), then apply the step adjoint backwards through the segment.  Memory: the
+checkpoints plus the states of one segment.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class PerkTrajectory(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u0, solver, dt, n_steps, every):
+        if every < 1:
+            raise ValueError("checkpoint interval must be >= 1")
+        ckpts = []
+        solver.u.copy_(u0)
+        for k in range(n_steps):
+            if k % every == 0:
+                ckpts.append(solver.u.clone())
+            solver.step(dt, 1)
+        ctx.solver, ctx.dt, ctx.n_steps, ctx.every, ctx.ckpts = solver, float(dt), int(n_steps), int(every), ckpts
+        return solver.u.clone()
+
+    @staticmethod
+    def backward(ctx, lam):
+        s, dt, n, every = ctx.solver, ctx.dt, ctx.n_steps, ctx.every
+        lam = lam.contiguous().clone()
+        saved = s.u.clone()
+        for seg in reversed(range(len(ctx.ckpts))):
+            k0, k1 = seg * every, min(n, seg * every + every)
+            s.u.copy_(ctx.ckpts[seg])
+            states = []
+            for _ in range(k0, k1):
+                states.append(s.u.clone())
+                s.step(dt, 1)
+            for k in reversed(range(k1 - k0)):
+                lam = s.step_adjoint(states[k], lam, dt)
+        s.u.copy_(saved)
+        return lam, None, None, None, None
+
+
+def trajectory(u0, solver, dt, n_steps, every=10):
+    """u_N = Phi^n(u0) (slot layout), differentiable with respect to u0."""
+    return PerkTrajectory.apply(u0, solver, dt, n_steps, every)

@@ -1,0 +1,389 @@
+// Adjoint (vector-Jacobian product) of the DGSEM Euler right-hand side for gfx950, and the
+// stage-wise reverse sweep of the partitioned P-ERK step built on it.
+//
+// For a cotangent W and the stage state Y the kernel forms G = F'(Y)^T W element by element
+// ("gather" form: each element writes only its own rows of G, so there are no atomics):
+//   * volume: every unordered node pair (a, b) of a coordinate line carries one two-point
+//     flux f#(u_a, u_b) that enters du_a with -J 2 D_ab and du_b with -J 2 D_ba; its cotangent
+//     P = -J (2 D_ab W_a + 2 D_ba W_b) is pulled back through the local Jacobians of f#;
+//   * faces: the HLL flux of a face node enters the lifting of both neighbours; the element
+//     collects the flux cotangent of both sides (its own W and the neighbour's W, projected
+//     with R_m^T across a 2:1 mortar) and pulls it back through the derivative with respect to
+//     its own trace only (the neighbour does the same for its trace); on the coarse side of a
+//     mortar the result lives on the sub-face nodes and is taken back with P_m^T.
+// The local flux Jacobians come from forward-mode dual numbers over the flux formulas
+// (entropy-conserving flux with the logarithmic mean and its series branch; HLL with Davis
+// wave speeds, ties resolved towards the first argument), i.e. the derivative of the computed
+// map along the branches it takes.
+//
+// Reverse sweep of one step (Sec. 3.1: Y_i = U_n + dt (a_{i,1} K_1 + a_{i,i-1} K_{i-1}),
+// K_i = I_i F(Y_i), U_{n+1} = U_n + dt sum_i b_i K_i), from the stage values stored by a
+// forward recomputation: with K~_i the cotangent of K_i,
+//   Ybar_i = F'(Y_i)^T (I_i K~_i);  Ubar += Ybar_i;  K~_1 += dt a_{i,1} Ybar_i;
+//   K~_{i-1} = dt b_{i-1} lam + dt a_{i,i-1} Ybar_i,
+// per element with its member's coefficients; only active elements and their face
+// neighbours are launched (everything else has Ybar_i = 0).
+
+#include "perk_device.h"
+
+namespace perk {
+namespace {
+
+// ---------------------------------------------------------------- forward-mode dual number
+struct Dd {
+  double v, d;
+};
+__device__ __forceinline__ Dd mk(double v, double d = 0.0) { return Dd{v, d}; }
+__device__ __forceinline__ Dd operator+(Dd a, Dd b) { return Dd{a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dd operator-(Dd a, Dd b) { return Dd{a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dd operator*(Dd a, Dd b) { return Dd{a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dd operator*(double s, Dd a) { return Dd{s * a.v, s * a.d}; }
+__device__ __forceinline__ Dd operator/(Dd a, Dd b) {
+  const double q = a.v / b.v;
+  return Dd{q, (a.d - q * b.d) / b.v};
+}
+__device__ __forceinline__ Dd operator/(Dd a, double s) { return Dd{a.v / s, a.d / s}; }
+__device__ __forceinline__ Dd dlog(Dd a) { return Dd{log(a.v), a.d / a.v}; }
+__device__ __forceinline__ Dd dsqrt(Dd a) {
+  const double r = sqrt(a.v);
+  return Dd{r, 0.5 * a.d / r};
+}
+__device__ __forceinline__ Dd dmin(Dd a, Dd b) { return b.v < a.v ? b : a; }
+__device__ __forceinline__ Dd dmax(Dd a, Dd b) { return b.v > a.v ? b : a; }
+
+template <int DIM>
+struct DPrim {
+  Dd rho, v[DIM], p;
+};
+
+template <int DIM>
+__device__ __forceinline__ DPrim<DIM> dprim(const Dd* u, double gamma) {
+  DPrim<DIM> q;
+  q.rho = u[0];
+  Dd ke = mk(0.0);
+  for (int k = 0; k < DIM; ++k) {
+    q.v[k] = u[1 + k] / u[0];
+    ke = ke + 0.5 * (u[1 + k] * q.v[k]);
+  }
+  q.p = (gamma - 1.0) * (u[DIM + 1] - ke);
+  return q;
+}
+
+// (b - a) / ln(b / a), with the series in u = ((b-a)/(b+a))^2 below 1e-2
+__device__ __forceinline__ Dd dlog_mean(Dd a, Dd b) {
+  const Dd f = (b - a) / (b + a);
+  const Dd u = f * f;
+  if (u.v < 1e-2) {
+    const Dd u2 = u * u, u3 = u2 * u, u4 = u3 * u, u5 = u4 * u, u6 = u5 * u, u7 = u6 * u;
+    const Dd F = mk(1.0) + u / 3.0 + u2 / 5.0 + u3 / 7.0 + u4 / 9.0 + u5 / 11.0 + u6 / 13.0 + u7 / 15.0;
+    return (a + b) / (2.0 * F);
+  }
+  return (b - a) / dlog(b / a);
+}
+
+// entropy-conserving, kinetic-energy-preserving two-point flux in direction d
+template <int DIM>
+__device__ __forceinline__ void dec_flux(const Dd* uL, const Dd* uR, int d, double gamma, Dd* f) {
+  constexpr int NV = DIM + 2;
+  const DPrim<DIM> L = dprim<DIM>(uL, gamma), R = dprim<DIM>(uR, gamma);
+  const Dd rho_ln = dlog_mean(L.rho, R.rho);
+  const Dd beta_ln = dlog_mean(L.rho / L.p, R.rho / R.p);
+  const Dd vd = 0.5 * (L.v[d] + R.v[d]);
+  const Dd p_avg = 0.5 * (L.p + R.p);
+  Dd vLvR = mk(0.0);
+  for (int k = 0; k < DIM; ++k) vLvR = vLvR + L.v[k] * R.v[k];
+  f[0] = rho_ln * vd;
+  for (int k = 0; k < DIM; ++k) f[1 + k] = f[0] * (0.5 * (L.v[k] + R.v[k]));
+  f[1 + d] = f[1 + d] + p_avg;
+  f[NV - 1] = f[0] * (0.5 * vLvR + mk(1.0) / ((gamma - 1.0) * beta_ln)) + 0.5 * (L.p * R.v[d] + R.p * L.v[d]);
+}
+
+template <int DIM>
+__device__ __forceinline__ void deuler_flux(const Dd* u, const DPrim<DIM>& q, int d, Dd* f) {
+  constexpr int NV = DIM + 2;
+  f[0] = u[1 + d];
+  for (int k = 0; k < DIM; ++k) f[1 + k] = u[1 + k] * q.v[d];
+  f[1 + d] = f[1 + d] + q.p;
+  f[NV - 1] = (u[NV - 1] + q.p) * q.v[d];
+}
+
+// HLL with Davis wave speeds, normal +e_d from L to R
+template <int DIM>
+__device__ __forceinline__ void dhll_flux(const Dd* uL, const Dd* uR, int d, double gamma, Dd* f) {
+  constexpr int NV = DIM + 2;
+  const DPrim<DIM> L = dprim<DIM>(uL, gamma), R = dprim<DIM>(uR, gamma);
+  const Dd cL = dsqrt(gamma * L.p / L.rho), cR = dsqrt(gamma * R.p / R.rho);
+  const Dd sL = dmin(L.v[d] - cL, R.v[d] - cR);
+  const Dd sR = dmax(L.v[d] + cL, R.v[d] + cR);
+  Dd fL[NV], fR[NV];
+  deuler_flux<DIM>(uL, L, d, fL);
+  deuler_flux<DIM>(uR, R, d, fR);
+  if (sL.v >= 0.0) {
+    for (int v = 0; v < NV; ++v) f[v] = fL[v];
+  } else if (sR.v <= 0.0) {
+    for (int v = 0; v < NV; ++v) f[v] = fR[v];
+  } else {
+    for (int v = 0; v < NV; ++v) f[v] = (sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v])) / (sR - sL);
+  }
+}
+
+// stage value of slot data: 0 U_n, 1 Yin, 2 U_n + dt c_i K_1 (as in the stage kernel)
+__device__ __forceinline__ double vstage(const VjpArgs& a, int src, int64_t idx) {
+  if (src == 0) return a.U[idx];
+  if (src == 1) return a.Yin[idx];
+  return a.U[idx] + a.dt * a.ci * a.K1[idx];
+}
+
+template <int DIM, int N>
+struct AK {
+  using g = G<DIM, N>;
+  static constexpr int ND = g::ND, NF = g::NF, NFC = g::NFC, NV = g::NV, NSUB = g::NSUB;
+  static constexpr int NPL = N * (N - 1) / 2;
+  static constexpr int NLINE = DIM == 2 ? N : N * N;
+  static constexpr int NP = DIM * NLINE * NPL;
+  static constexpr int T = DIM == 2 ? 64 : (N == 4 ? 384 : 192);
+};
+
+// R_m[i, k] (coarse node i, sub-face node k) and P_m[k, i] of a 2:1 mortar, tensor products in 3D
+template <int DIM, int N>
+__device__ __forceinline__ double Rm(const Ops& op, int m, int i, int k) {
+  if (DIM == 2) return op.R[m][i * N + k];
+  return op.R[m & 1][(i % N) * N + (k % N)] * op.R[(m >> 1) & 1][(i / N) * N + (k / N)];
+}
+template <int DIM, int N>
+__device__ __forceinline__ double Pm(const Ops& op, int m0, int m1, int k, int i) {
+  if (DIM == 2) return op.P[m0][k * N + i];
+  return op.P[m0][(k % N) * N + (i % N)] * op.P[m1][(k / N) * N + (i / N)];
+}
+
+template <int DIM, int N>
+__global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, Ops op, Physics ph) {
+  using K = AK<DIM, N>;
+  constexpr int ND = K::ND, NF = K::NF, NFC = K::NFC, NV = K::NV, NSUB = K::NSUB, T = K::T;
+  constexpr int NP = K::NP, NPL = K::NPL;
+  __shared__ double s_u[NV][ND];                 // own stage state
+  __shared__ double s_w[NV][ND];                 // own cotangent
+  __shared__ double s_tr[NFC][NSUB][NV][NF];     // neighbour stage traces (fine side: interpolated in sub 1)
+  __shared__ double s_tw[NFC][NSUB][NV][NF];     // neighbour cotangent traces (raw)
+  __shared__ double s_jn[NFC][NSUB];             // neighbour 2/h in the face direction
+  __shared__ double s_ga[NP][NV], s_gb[NP][NV];  // pair pull-backs to the first / second node
+  __shared__ double s_gf[NFC][NSUB][NV][NF];     // face pull-backs (coarse side: on sub-face nodes)
+  __shared__ int s_fk[NFC];
+  __shared__ int s_fn[NFC][4];
+
+  const int lane = threadIdx.x;
+  const int b = blockIdx.x;
+  const int e = b < a.n_act ? b : a.halo[b - a.n_act];
+  const int ld = m.ld;
+  const double gamma = ph.gamma;
+  const int mem = member_of_slot(m, e);
+  const int lev = m.lev[e];
+  double J[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) J[d] = m.jac[lev][d];
+
+  // ---- A: own state and cotangent, connectivity, neighbour traces
+  if (lane < NFC) s_fk[lane] = m.fk[(int64_t)e * NFC + lane];
+  if (lane < NFC * 4) s_fn[lane / 4][lane % 4] = m.fn[(int64_t)e * NFC * 4 + lane];
+  const int my_src = a.src[mem];
+  const bool w_own = e < a.n_w;
+  for (int w = lane; w < NV * ND; w += T) {
+    const int v = w / ND, nd = w - v * ND;
+    const int64_t idx = ((int64_t)v * ld + e) * ND + nd;
+    s_u[v][nd] = vstage(a, my_src, idx);
+    s_w[v][nd] = w_own ? a.W[idx] : 0.0;
+  }
+  __syncthreads();
+  for (int w = lane; w < NSUB * NFC * NV * NF; w += T) {
+    const int j = w % NF;
+    const int v = (w / NF) % NV;
+    const int f = (w / (NF * NV)) % NFC;
+    const int sub = w / (NF * NV * NFC);
+    const int kind = face_kind(s_fk[f]);
+    if (sub > 0 && kind != kCoarseSide) continue;
+    const int nb = s_fn[f][sub];
+    const int d = f >> 1, side = f & 1;
+    const int nn = face_node<DIM, N>(d, 1 - side, j);
+    const int64_t idx = ((int64_t)v * ld + nb) * ND + nn;
+    s_tr[f][sub][v][j] = vstage(a, a.src[member_of_slot(m, nb)], idx);
+    s_tw[f][sub][v][j] = nb < a.n_w ? a.W[idx] : 0.0;
+    if (v == 0 && j == 0) s_jn[f][sub] = m.jac[m.lev[nb]][d];
+  }
+  __syncthreads();
+  // fine side: coarse trace interpolated to this sub-face into sub-slot 1
+  for (int w = lane; w < NFC * NV * NF; w += T) {
+    const int j = w % NF;
+    const int v = (w / NF) % NV;
+    const int f = w / (NF * NV);
+    const int32_t pk = s_fk[f];
+    if (face_kind(pk) != kFineSide) continue;
+    const int s0 = face_sub0(pk), s1 = face_sub1(pk);
+    double val = 0.0;
+    for (int k = 0; k < NF; ++k) val += Pm<DIM, N>(op, s0, s1, j, k) * s_tr[f][0][v][k];
+    s_tr[f][1][v][j] = val;
+  }
+  __syncthreads();
+
+  // ---- D: pull-backs through the local flux Jacobians, one flux per lane
+  const double iw0 = 1.0 / op.w[0], iwN = 1.0 / op.w[N - 1];
+  for (int w = lane; w < NP + NSUB * NFC * NF; w += T) {
+    if (w < NP) {
+      const int pl = w % NPL;
+      const int line = (w / NPL) % K::NLINE;
+      const int d = w / (NPL * K::NLINE);
+      int pa = 0, pb = 1, cnt = 0;
+      for (int x = 0; x < N; ++x)
+        for (int y = x + 1; y < N; ++y) {
+          if (cnt == pl) { pa = x; pb = y; }
+          ++cnt;
+        }
+      const int na = node_on_line<DIM, N>(d, line, pa), nb = node_on_line<DIM, N>(d, line, pb);
+      double Pb[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        Pb[v] = -J[d] * (2.0 * op.D[pa * N + pb] * s_w[v][na] + 2.0 * op.D[pb * N + pa] * s_w[v][nb]);
+#pragma unroll 1
+      for (int j = 0; j < 2 * NV; ++j) {
+        Dd uL[NV], uR[NV], f[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          uL[v] = mk(s_u[v][na], j == v ? 1.0 : 0.0);
+          uR[v] = mk(s_u[v][nb], j == NV + v ? 1.0 : 0.0);
+        }
+        dec_flux<DIM>(uL, uR, d, gamma, f);
+        double gsum = 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) gsum += Pb[v] * f[v].d;
+        if (j < NV) s_ga[w][j] = gsum;
+        else s_gb[w][j - NV] = gsum;
+      }
+    } else {
+      const int r = w - NP;
+      const int j = r % NF;
+      const int f = (r / NF) % NFC;
+      const int sub = r / (NF * NFC);
+      const int32_t pk = s_fk[f];
+      const int kind = face_kind(pk);
+      if (sub > 0 && kind != kCoarseSide) continue;
+      const int d = f >> 1, side = f & 1;
+      const double lift_own = side == 1 ? -iwN : iw0;
+      const double lift_nb = side == 1 ? iw0 : -iwN;
+      double own[NV], oth[NV], Hb[NV];
+      if (kind == kCoarseSide) {
+        const int m0 = sub & 1, m1 = (sub >> 1) & 1;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double x = 0.0, h = 0.0;
+          for (int i = 0; i < NF; ++i) {
+            const int on = face_node<DIM, N>(d, side, i);
+            x += Pm<DIM, N>(op, m0, m1, j, i) * s_u[v][on];
+            h += Rm<DIM, N>(op, sub, i, j) * s_w[v][on];
+          }
+          own[v] = x;
+          oth[v] = s_tr[f][sub][v][j];
+          Hb[v] = J[d] * lift_own * h + s_jn[f][sub] * lift_nb * s_tw[f][sub][v][j];
+        }
+      } else {
+        const int on = face_node<DIM, N>(d, side, j);
+        const int ts = kind == kFineSide ? 1 : 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          own[v] = s_u[v][on];
+          oth[v] = s_tr[f][ts][v][j];
+          double hn;
+          if (kind == kFineSide) {
+            const int s0 = face_sub0(pk), s1 = face_sub1(pk);
+            const int ms = DIM == 2 ? s0 : s0 + 2 * s1;
+            hn = 0.0;
+            for (int i = 0; i < NF; ++i) hn += Rm<DIM, N>(op, ms, i, j) * s_tw[f][0][v][i];
+          } else {
+            hn = s_tw[f][0][v][j];
+          }
+          Hb[v] = J[d] * lift_own * s_w[v][on] + s_jn[f][0] * lift_nb * hn;
+        }
+      }
+#pragma unroll 1
+      for (int q = 0; q < NV; ++q) {
+        Dd uo[NV], un[NV], fl[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          uo[v] = mk(own[v], q == v ? 1.0 : 0.0);
+          un[v] = mk(oth[v]);
+        }
+        if (side == 1) dhll_flux<DIM>(uo, un, d, gamma, fl);
+        else dhll_flux<DIM>(un, uo, d, gamma, fl);
+        double gsum = 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) gsum += Hb[v] * fl[v].d;
+        s_gf[f][sub][q][j] = gsum;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- E: per (variable, node): gather the pull-backs, stage-combination epilogue
+  for (int w = lane; w < NV * ND; w += T) {
+    const int v = w / ND, nd = w - v * ND;
+    double g = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      int line, pos;
+      line_of<DIM, N>(nd, d, line, pos);
+      const int base = (d * K::NLINE + line) * NPL;
+      for (int mm = 0; mm < N; ++mm) {
+        if (mm == pos) continue;
+        g += mm > pos ? s_ga[base + pair_index<N>(pos, mm)][v] : s_gb[base + pair_index<N>(mm, pos)][v];
+      }
+      if (pos == 0 || pos == N - 1) {
+        const int f = 2 * d + (pos == N - 1 ? 1 : 0);
+        const int fi = face_index<DIM, N>(nd, d);
+        if (face_kind(s_fk[f]) == kCoarseSide) {
+          for (int ms = 0; ms < NSUB; ++ms) {
+            const int m0 = ms & 1, m1 = (ms >> 1) & 1;
+            for (int k = 0; k < NF; ++k) g += Pm<DIM, N>(op, m0, m1, k, fi) * s_gf[f][ms][v][k];
+          }
+        } else {
+          g += s_gf[f][0][v][fi];
+        }
+      }
+    }
+    const int64_t idx = ((int64_t)v * ld + e) * ND + nd;
+    if (a.Gout) a.Gout[idx] = g;
+    if (a.Ubar) a.Ubar[idx] += g;
+    if (a.K1bar) a.K1bar[idx] += a.dt * a.A1[mem] * g;
+    if (a.Kprev) a.Kprev[idx] = a.dt * (a.bprev * a.lam[idx] + a.A2[mem] * g);
+  }
+}
+
+// y = alpha x (n doubles), the start of the reverse sweep
+__global__ void k_scale(double* y, const double* x, double alpha, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = alpha * x[i];
+}
+
+template <int DIM, int N>
+hipError_t launch_vjp_t(const VjpArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s) {
+  const int blocks = a.n_act + a.n_halo;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_rhs_vjp<DIM, N>), dim3(blocks), dim3(AK<DIM, N>::T), 0, s, a, m, op, ph);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_rhs_vjp(int dim, int N, const VjpArgs& a, const Mesh& m, const Ops& op, const Physics& ph,
+                          hipStream_t s) {
+  if (dim == 2 && N == 4) return launch_vjp_t<2, 4>(a, m, op, ph, s);
+  if (dim == 2 && N == 3) return launch_vjp_t<2, 3>(a, m, op, ph, s);
+  if (dim == 3 && N == 4) return launch_vjp_t<3, 4>(a, m, op, ph, s);
+  if (dim == 3 && N == 3) return launch_vjp_t<3, 3>(a, m, op, ph, s);
+  return hipErrorNotSupported;
+}
+
+hipError_t launch_scale(double* y, const double* x, double alpha, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(n, 256)), dim3(256), 0, s, y, x, alpha, n);
+  return hipGetLastError();
+}
+
+}  // namespace perk

@@ -62,7 +62,12 @@ struct pe_ctx {
   std::vector<int32_t> counts;          // [R] elements per member
   std::vector<int32_t> leaf_of_slot, slot_of_leaf, mem_of_slot;
   std::vector<int> n_act;               // [S]
-  std::vector<int> halo_off, halo_cnt;  // [S] Navier-Stokes: inactive face neighbours of the active prefix
+  std::vector<int> halo_off, halo_cnt;  // [S] inactive face neighbours of the active prefix per stage
+  bool halo_valid = false;              // built for Navier-Stokes at partition, on demand for the adjoint
+  // adjoint workspace (caller-owned device memory): stage values Y_1..Y_{S-1}, stage cotangents
+  char* adj_ws = nullptr;
+  int adj_S = 0;
+  int64_t adj_cap = 0;
   // replay of one captured step (HIP graph), valid until the partition, binding or dt changes
   bool graphs_enabled = true;
   bool graph_valid = false;
@@ -572,6 +577,63 @@ pe_status copy_maps(pe_ctx* ctx, hipStream_t s) {
   ctx->maps_on_host = true;
   return PE_OK;
 }
+// Per stage, the inactive face neighbours of the active prefix (sorted slots, shared between
+// stages with the same active count).  Needs the slot maps on the host.
+pe_status build_halo(pe_ctx* ctx, hipStream_t s) {
+  const int n = ctx->n_e, nf = 2 * ctx->dim;
+  if (!ctx->maps_on_host) {
+    pe_status st = copy_maps(ctx, s);
+    if (st != PE_OK) return st;
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  ctx->halo_off.assign(ctx->S, 0);
+  ctx->halo_cnt.assign(ctx->S, 0);
+  std::vector<int32_t> all;
+  std::vector<int> seen_na;
+  std::vector<char> mark(n, 0);
+  for (int i = 0; i < ctx->S; ++i) {
+    const int na = ctx->n_act[i];
+    auto it = std::find(seen_na.begin(), seen_na.end(), na);
+    if (it != seen_na.end()) {
+      int j = 0;
+      for (; j < i; ++j)
+        if (ctx->n_act[j] == na) break;
+      ctx->halo_off[i] = ctx->halo_off[j];
+      ctx->halo_cnt[i] = ctx->halo_cnt[j];
+      continue;
+    }
+    seen_na.push_back(na);
+    std::vector<int32_t> h;
+    if (na < n) {
+      std::fill(mark.begin(), mark.end(), 0);
+      for (int sl = 0; sl < na; ++sl) {
+        const int leaf = ctx->leaf_of_slot[sl];
+        for (int f = 0; f < nf; ++f) {
+          const int kind = face_kind(ctx->fk_leaf[(size_t)leaf * nf + f]);
+          const int cnt = kind == kCoarseSide ? (1 << (ctx->dim - 1)) : 1;
+          for (int q = 0; q < cnt; ++q) {
+            const int t = ctx->slot_of_leaf[ctx->fn_leaf[((size_t)leaf * nf + f) * 4 + q]];
+            if (t >= na && !mark[t]) {
+              mark[t] = 1;
+              h.push_back(t);
+            }
+          }
+        }
+      }
+      std::sort(h.begin(), h.end());
+    }
+    ctx->halo_off[i] = (int)all.size();
+    ctx->halo_cnt[i] = (int)h.size();
+    all.insert(all.end(), h.begin(), h.end());
+  }
+  if (!all.empty()) {
+    HIPCHK(hipMemcpyAsync(ctx->d_halo, all.data(), all.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  ctx->halo_valid = true;
+  return PE_OK;
+}
+
 }  // namespace
 
 pe_status pe_partition(pe_ctx* ctx, const int32_t* member_of_level, int n_levels, void* stream) {
@@ -614,64 +676,15 @@ pe_status pe_partition(pe_ctx* ctx, const int32_t* member_of_level, int n_levels
   ctx->counts.assign(ctx->R, 0);
   HIPCHK(hipMemcpyAsync(ctx->counts.data(), ctx->d_counts, ctx->R * 4, hipMemcpyDeviceToHost, s));
   ctx->maps_on_host = false;
-  if (ctx->equations == 1) {
-    pe_status st = copy_maps(ctx, s);
-    if (st != PE_OK) return st;
-  }
   HIPCHK(hipStreamSynchronize(s));
   ctx->n_act.assign(ctx->S, 0);
   for (int i = 0; i < ctx->S; ++i)
     for (int r = 0; r < ctx->R; ++r)
       if (active(ctx, r, i)) ctx->n_act[i] += ctx->counts[r];
-  ctx->halo_off.assign(ctx->S, 0);
-  ctx->halo_cnt.assign(ctx->S, 0);
+  ctx->halo_valid = false;
   if (ctx->equations == 1) {
-    // the BR1 gradient pass of a stage also covers the inactive face neighbours of the active
-    // prefix (their viscous face fluxes enter the active elements' surface terms)
-    std::vector<int32_t> all;
-    std::vector<int> seen_na;
-    std::vector<char> mark(n, 0);
-    for (int i = 0; i < ctx->S; ++i) {
-      const int na = ctx->n_act[i];
-      auto it = std::find(seen_na.begin(), seen_na.end(), na);
-      if (it != seen_na.end()) {
-        const int k = (int)(it - seen_na.begin());
-        int j = 0;
-        for (; j < i; ++j)
-          if (ctx->n_act[j] == na) break;
-        ctx->halo_off[i] = ctx->halo_off[j];
-        ctx->halo_cnt[i] = ctx->halo_cnt[j];
-        (void)k;
-        continue;
-      }
-      seen_na.push_back(na);
-      std::vector<int32_t> h;
-      if (na < n) {
-        std::fill(mark.begin(), mark.end(), 0);
-        for (int sl = 0; sl < na; ++sl) {
-          const int leaf = ctx->leaf_of_slot[sl];
-          for (int f = 0; f < nf; ++f) {
-            const int kind = face_kind(ctx->fk_leaf[(size_t)leaf * nf + f]);
-            const int cnt = kind == kCoarseSide ? (1 << (ctx->dim - 1)) : 1;
-            for (int q = 0; q < cnt; ++q) {
-              const int t = ctx->slot_of_leaf[ctx->fn_leaf[((size_t)leaf * nf + f) * 4 + q]];
-              if (t >= na && !mark[t]) {
-                mark[t] = 1;
-                h.push_back(t);
-              }
-            }
-          }
-        }
-        std::sort(h.begin(), h.end());
-      }
-      ctx->halo_off[i] = (int)all.size();
-      ctx->halo_cnt[i] = (int)h.size();
-      all.insert(all.end(), h.begin(), h.end());
-    }
-    if (!all.empty()) {
-      HIPCHK(hipMemcpyAsync(ctx->d_halo, all.data(), all.size() * 4, hipMemcpyHostToDevice, s));
-      HIPCHK(hipStreamSynchronize(s));
-    }
+    pe_status st = build_halo(ctx, s);
+    if (st != PE_OK) return st;
   }
   ctx->partitioned = true;
   ctx->graph_valid = false;
@@ -748,6 +761,121 @@ pe_status pe_rhs(pe_ctx* ctx, const double* u, double* du, void* stream) {
   if (ctx->equations == 1)
     HIPCHK(launch_gradients(ctx->dim, ctx->N, a, m, ctx->ops, ctx->ph, (hipStream_t)stream));
   HIPCHK(launch_stage(ctx->dim, ctx->N, ctx->equations == 1, a, m, ctx->ops, ctx->ph, (hipStream_t)stream));
+  return PE_OK;
+}
+
+pe_status pe_rhs_vjp(pe_ctx* ctx, const double* u, const double* w, double* out, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->partitioned) return fail(ctx, PE_ESTATE, "rhs_vjp before partition");
+  if (ctx->equations != 0) return fail(ctx, PE_EUNSUPPORTED, "rhs_vjp: Euler only");
+  if (!u || !w || !out) return fail(ctx, PE_EINVAL, "rhs_vjp: null");
+  VjpArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.U = u;                 // src 0 for every member: the state itself
+  a.W = w;
+  a.n_w = ctx->n_e;
+  a.n_act = ctx->n_e;
+  a.Gout = out;
+  HIPCHK(launch_rhs_vjp(ctx->dim, ctx->N, a, device_mesh(ctx), ctx->ops, ctx->ph, (hipStream_t)stream));
+  return PE_OK;
+}
+
+pe_status pe_adjoint_query(const pe_ctx* ctx, int64_t* bytes) {
+  if (!ctx || !bytes) return PE_EINVAL;
+  if (!ctx->have_coeffs || !ctx->bound) return PE_ESTATE;
+  *bytes = (int64_t)(ctx->S + 2) * state_doubles(ctx) * (int64_t)sizeof(double);
+  return PE_OK;
+}
+
+pe_status pe_adjoint_bind(pe_ctx* ctx, void* workspace) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->have_coeffs || !ctx->bound) return fail(ctx, PE_ESTATE, "adjoint_bind needs coefficients and a binding");
+  if (!workspace || ((uintptr_t)workspace & 255)) return fail(ctx, PE_EINVAL, "adjoint_bind: null or not 256-byte aligned");
+  ctx->adj_ws = (char*)workspace;
+  ctx->adj_S = ctx->S;
+  ctx->adj_cap = cap_of(ctx);
+  return PE_OK;
+}
+
+pe_status pe_step_adjoint(pe_ctx* ctx, double dt, const double* u_n, const double* lam_next, double* lam_prev,
+                          void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->partitioned) return fail(ctx, PE_ESTATE, "step_adjoint before partition");
+  if (ctx->equations != 0) return fail(ctx, PE_EUNSUPPORTED, "step_adjoint: Euler only");
+  if (!u_n || !lam_next || !lam_prev) return fail(ctx, PE_EINVAL, "step_adjoint: null");
+  if (!(dt > 0.0)) return fail(ctx, PE_EINVAL, "step_adjoint: dt must be > 0");
+  if (!ctx->adj_ws || ctx->adj_S != ctx->S || ctx->adj_cap != cap_of(ctx))
+    return fail(ctx, PE_ESTATE, "step_adjoint: adjoint workspace not bound for these coefficients and capacity");
+  if (lam_prev == lam_next || lam_prev == u_n) return fail(ctx, PE_EINVAL, "step_adjoint: lam_prev must not alias");
+  hipStream_t s = (hipStream_t)stream;
+  if (!ctx->halo_valid) {
+    pe_status st = build_halo(ctx, s);
+    if (st != PE_OK) return st;
+  }
+  const int64_t sd = state_doubles(ctx);
+  const int S = ctx->S, R = ctx->R;
+  double* base = (double*)ctx->adj_ws;
+  auto Ystore = [&](int i) { return base + (int64_t)(i - 1) * sd; };   // Y_1 .. Y_{S-1}
+  double* Kcur = base + (int64_t)(S - 1) * sd;
+  double* Kprev = Kcur + sd;
+  double* K1bar = Kprev + sd;
+  Mesh m = device_mesh(ctx);
+  // forward recomputation of the step from u_n, keeping every stage value
+  for (int i = 0; i < S; ++i) {
+    StageArgs a;
+    fill_stage(ctx, i, dt, a);
+    a.U = u_n;
+    a.K1 = ctx->K1;
+    a.Yin = i >= 1 ? Ystore(i) : ctx->Ya;
+    a.Yout = i + 1 < S ? Ystore(i + 1) : ctx->Yb;
+    a.ACC = ctx->ACC;
+    a.Uout = ctx->Tmp;
+    a.evals = nullptr;
+    HIPCHK(launch_stage(ctx->dim, ctx->N, false, a, m, ctx->ops, ctx->ph, s));
+  }
+  // reverse sweep
+  HIPCHK(launch_copy(lam_prev, lam_next, sd, s));
+  HIPCHK(launch_scale(K1bar, lam_next, dt * ctx->b[0], sd, s));
+  if (S > 1) HIPCHK(launch_scale(Kcur, lam_next, dt * ctx->b[S - 1], sd, s));
+  for (int i = S - 1; i >= 1; --i) {
+    StageArgs sa;
+    fill_stage(ctx, i, dt, sa);
+    VjpArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.U = u_n;
+    a.K1 = ctx->K1;
+    a.Yin = Ystore(i);
+    a.dt = dt;
+    a.ci = ctx->c[i];
+    for (int r = 0; r < kMaxMembers; ++r) a.src[r] = sa.src[r];
+    a.W = Kcur;
+    a.n_w = ctx->n_act[i];
+    a.n_act = ctx->n_act[i];
+    a.n_halo = ctx->halo_cnt[i];
+    a.halo = ctx->d_halo + ctx->halo_off[i];
+    a.Ubar = lam_prev;
+    a.K1bar = K1bar;
+    a.Kprev = i - 1 >= 1 ? Kprev : nullptr;
+    a.lam = lam_next;
+    a.bprev = ctx->b[i - 1];
+    for (int r = 0; r < R; ++r) {
+      const double a2 = ctx->a_sub[(size_t)r * S + i];     // a_{i+1,i} in 1-based numbering
+      a.A1[r] = ctx->c[i] - a2;
+      a.A2[r] = a2;
+    }
+    HIPCHK(launch_rhs_vjp(ctx->dim, ctx->N, a, m, ctx->ops, ctx->ph, s));
+    std::swap(Kcur, Kprev);
+  }
+  {
+    VjpArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.U = u_n;
+    a.W = K1bar;
+    a.n_w = ctx->n_e;
+    a.n_act = ctx->n_e;
+    a.Ubar = lam_prev;
+    HIPCHK(launch_rhs_vjp(ctx->dim, ctx->N, a, m, ctx->ops, ctx->ph, s));
+  }
   return PE_OK;
 }
 

@@ -84,6 +84,33 @@ struct StageArgs {
   double a2[kMaxMembers]; // a_{i+1,i}
 };
 
+// Arguments of the adjoint right-hand-side kernel: the stage state of every slot (as in the
+// stage kernel: src 0 U_n, 1 Yin, 2 U_n + dt c_i K_1), the cotangent W of the slots [0, n_w)
+// (zero elsewhere), the launched slots ([0, n_act) and halo[0..n_halo)), and what to do with
+// G = F'(Y)^T W of a launched slot: store it (Gout), add it (Ubar += G, K1bar += dt A1 G) and
+// form the previous stage's cotangent (Kprev = dt (bprev lam + A2 G)); null pointers skip.
+struct VjpArgs {
+  const double* U;
+  const double* K1;
+  const double* Yin;
+  double dt;
+  double ci;
+  int src[kMaxMembers];
+  const double* W;
+  int n_w;
+  int n_act;
+  int n_halo;
+  const int32_t* halo;
+  double* Gout;
+  double* Ubar;
+  double* K1bar;
+  double* Kprev;
+  const double* lam;
+  double bprev;
+  double A1[kMaxMembers];
+  double A2[kMaxMembers];
+};
+
 // One run of a batched launch: its mesh tables, operators, physics, polynomial degree (N nodes
 // per direction), stage count and the index of its first stage descriptor (S consecutive).
 struct BatchRun {
@@ -153,6 +180,11 @@ hipError_t launch_wave_speed(int dim, int N, int n, const double* U, const Physi
 // tiles; otherwise grid must equal the tile count (one block per tile).
 hipError_t launch_stage_batch(int N, int M, int grid, bool persistent, const BatchRun* runs, const StageArgs* sargs,
                               const int32_t* tile_off, int k0, int k1, int64_t tick, hipStream_t s);
+// G = F'(Y)^T W for the Euler right-hand side (perk_adjoint.hip), one element per block
+hipError_t launch_rhs_vjp(int dim, int N, const VjpArgs& a, const Mesh& m, const Ops& op, const Physics& ph,
+                          hipStream_t s);
+// y = alpha x
+hipError_t launch_scale(double* y, const double* x, double alpha, int64_t n, hipStream_t s);
 hipError_t launch_fold_evals(int n, const Mesh& m, int32_t* evals, unsigned long long* totals, hipStream_t s);
 
 }  // namespace perk

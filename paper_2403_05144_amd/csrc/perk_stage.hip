@@ -175,30 +175,6 @@ struct SK {
   static constexpr int MINW = 1;
 };
 
-// index of the unordered pair (a, b), a < b, among the N(N-1)/2 pairs of a line
-template <int N>
-__device__ __forceinline__ int pair_index(int a, int b) {
-  return a * (2 * N - a - 1) / 2 + (b - a - 1);
-}
-
-// line index of a node for direction d (the other coordinates) and its coordinate along d
-template <int DIM, int N>
-__device__ __forceinline__ void line_of(int nd, int d, int& line, int& pos) {
-  const int i = nd % N, j = (nd / N) % N, k = DIM == 3 ? nd / (N * N) : 0;
-  if (d == 0) { line = j + N * k; pos = i; }
-  else if (d == 1) { line = i + N * k; pos = j; }
-  else { line = i + N * j; pos = k; }
-}
-
-template <int DIM, int N>
-__device__ __forceinline__ int node_on_line(int d, int line, int pos) {
-  if (DIM == 2) return d == 0 ? pos + N * line : line + N * pos;
-  const int a = line % N, b = line / N;
-  if (d == 0) return pos + N * a + N * N * b;
-  if (d == 1) return a + N * pos + N * N * b;
-  return a + N * b + N * N * pos;
-}
-
 // The stage work of one block of EPB elements: block `blk` of the launch covers the slots
 // [blk EPB, blk EPB + EPB).  Shared by the single-run kernel and the batched kernel, which
 // therefore compute bitwise identical stages.

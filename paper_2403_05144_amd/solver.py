@@ -163,6 +163,50 @@ class PerkSolver:
         self.u.copy_(saved)
         return out
 
+    # ---------------------------------------------------------------- adjoint (Euler)
+    def rhs_vjp_slot(self, u_slot, w_slot):
+        """F'(u)^T w in slot layout."""
+        out = torch.empty_like(u_slot)
+        self._check(self.lib.pe_rhs_vjp(self._ctx, ctypes.c_void_p(u_slot.data_ptr()), ctypes.c_void_p(w_slot.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), _stream_handle()), "pe_rhs_vjp")
+        return out
+
+    def to_slot(self, x_leaf):
+        """Leaf-layout array [n_leaves, n_vars, nodes] -> slot-layout tensor (uses the bound state)."""
+        saved = self.u.clone()
+        self.set_state(x_leaf)
+        out = self.u.clone()
+        self.u.copy_(saved)
+        return out
+
+    def to_leaf(self, x_slot):
+        saved = self.u.clone()
+        self.u.copy_(x_slot)
+        out = self.get_state()
+        self.u.copy_(saved)
+        return out
+
+    def rhs_vjp_leaf(self, u_leaf, w_leaf):
+        return self.to_leaf(self.rhs_vjp_slot(self.to_slot(u_leaf), self.to_slot(w_leaf)))
+
+    def enable_adjoint(self):
+        """Allocate and bind the adjoint workspace (stage values and stage cotangents)."""
+        nb = ctypes.c_int64()
+        self._check(self.lib.pe_adjoint_query(self._ctx, ctypes.byref(nb)), "pe_adjoint_query")
+        self._adj_ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self._adj_ws.data_ptr() + 255) & ~255
+        self._check(self.lib.pe_adjoint_bind(self._ctx, ctypes.c_void_p(aligned)), "pe_adjoint_bind")
+
+    def step_adjoint(self, u_n_slot, lam_slot, dt):
+        """Phi'(u_n)^T lam for one step of size dt (slot layout)."""
+        if getattr(self, "_adj_ws", None) is None:
+            self.enable_adjoint()
+        out = torch.empty_like(lam_slot)
+        self._check(self.lib.pe_step_adjoint(self._ctx, float(dt), ctypes.c_void_p(u_n_slot.data_ptr()),
+                                             ctypes.c_void_p(lam_slot.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                             _stream_handle()), "pe_step_adjoint")
+        return out
+
     def leaves(self):
         n = ctypes.c_int64()
         self._check(self.lib.pe_get_leaves(self._ctx, None, ctypes.byref(n)), "pe_get_leaves")

@@ -273,7 +273,87 @@ def run_batch(args):
     }
 
 
+def run_adjoint(args):
+    """Differentiated form: gradient of the final kinetic energy with respect to a seeded initial
+    density perturbation through 100 P-ERK2 {4,8} steps on the 2-level band mesh (64^2 roots,
+    roots with ||y| - 0.5| < 1/8 refined: 7168 elements, p = 3, Kelvin-Helmholtz state),
+    checkpoints every 10 steps; central finite differences on 20 seeded directions."""
+    import torch
+    import perk_inputs as pin
+    from paper_2403_05144_amd import PerkSolver
+    from paper_2403_05144_amd.adjoint import kinetic_energy, slot_node_weights, trajectory
+    mesh = pin.mesh_band_2level(64)
+    ic = lambda x: pin.kelvin_helmholtz(x[0], x[1])
+    fam = family_for("perk2_4_8_kh_p3_n8", 2, [4, 8], pin.uniform_mesh(2, (8, 8), (-1, -1), (1, 1), 0), 3, ic, 0.25)
+    mol = [0, 1]
+    s = PerkSolver(mesh, 3, fam, mol)
+    x = s.node_coords().cpu().numpy().transpose(1, 0, 2)
+    rho, vx, vy, p = pin.kelvin_helmholtz_prim(x[0], x[1])
+    m0 = pin.kh_density_perturbation(x[0], x[1])
+    u0_of = lambda m: pin.prim2cons(rho + m, [vx, vy], p, 1.4).transpose(1, 0, 2).copy()
+    s.set_state(u0_of(m0))
+    ws = slot_node_weights(s)
+    n, every = 100, 10
+    dt = stable_dt(fam, mesh, mol, 0.5)
+    _log(f"adjoint: {s.n_elements} elements, dt={dt:.5g}, {n} steps, checkpoints every {every}")
+
+    def J_of(m):
+        s.set_state(u0_of(m))
+        s.step(dt, n)
+        return float(kinetic_energy(s, s.u, ws))
+
+    J_of(m0)                                          # warm-up (graph capture)
+    u0 = s.to_slot(u0_of(m0)).requires_grad_(True)
+    s.enable_adjoint()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    uN = trajectory(u0, s, dt, n, every)
+    J = kinetic_energy(s, uN, ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    lam = s.to_leaf(u0.grad).cpu().numpy()
+    g = lam[:, 0] + lam[:, 1] * vx + lam[:, 2] * vy + lam[:, 3] * 0.5 * (vx * vx + vy * vy)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    J_plain = J_of(m0)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t3
+    rng = np.random.default_rng(pin.MASTER_SEED + 5)
+    errs = []
+    for _ in range(20):
+        dm = rng.standard_normal(m0.shape)
+        eps = 1e-5 / np.max(np.abs(dm))
+        fd = (J_of(m0 + eps * dm) - J_of(m0 - eps * dm)) / (2 * eps)
+        ad = float(np.sum(g * dm))
+        errs.append(abs(fd - ad) / abs(ad))
+    errs = np.array(errs)
+    dofs = s.n_elements * s.nv * s.Nd
+    fwd, bwd = t1 - t0, t2 - t1
+    return {
+        "metric": "DoF-updates/s & PID; P-ERK vs single-level RK wall time at equal error",
+        "value": n * dofs / bwd, "unit": "DoF-updates/s", "n_gpus": 1, "steps": n, "warmup": 1,
+        "ms_per_step": bwd / n * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "adjoint_kh_band64", "elements": int(s.n_elements), "degree": 3, "family_E": [4, 8],
+                   "dt": dt, "checkpoint_every": every,
+                   "description": "discrete adjoint of 100 P-ERK2 {4,8} steps of 2D Euler on the Kelvin-Helmholtz "
+                                  "state, 2-level band mesh of 64^2 roots (7168 elements, p=3); objective: total "
+                                  "kinetic energy at the final step; control: initial density perturbation; value "
+                                  "counts the steps of the reverse sweep (recomputation included) per second"},
+        "objective": J_plain, "objective_in_trajectory": float(J.detach()),
+        "forward_with_checkpoints_s": fwd, "forward_plain_s": t_plain, "backward_s": bwd,
+        "backward_over_forward": bwd / t_plain,
+        "finite_differences": {"directions": 20, "step": "1e-5 / max|dm| (relative to the density scale)",
+                               "max_rel_err": float(errs.max()), "median_rel_err": float(np.median(errs)),
+                               "passed_1e-6": int((errs <= 1e-6).sum())},
+    }
+
+
 WORKLOADS = {"vortex_2level": wl_vortex_2level, "kh_amr": wl_kh_amr, "tgv": wl_tgv, "batch_vortex64": None,
+             "adjoint_kh": None,
              "kh_amr_l4-7": lambda: wl_kh_amr(16, 3, "kh_amr_l4-7")}
 
 
@@ -795,7 +875,12 @@ def main():
         print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU design is "
               "documented but not built", file=sys.stderr)
         sys.exit(2)
-    line = run_batch(args) if args.workload == "batch_vortex64" else run(args)
+    if args.workload == "batch_vortex64":
+        line = run_batch(args)
+    elif args.workload == "adjoint_kh":
+        line = run_adjoint(args)
+    else:
+        line = run(args)
     print(json.dumps(line), flush=True)
 
 

@@ -47,3 +47,19 @@ class PerkTrajectory(torch.autograd.Function):
 def trajectory(u0, solver, dt, n_steps, every=10):
     """u_N = Phi^n(u0) (slot layout), differentiable with respect to u0."""
     return PerkTrajectory.apply(u0, solver, dt, n_steps, every)
+
+
+def slot_node_weights(solver):
+    """Quadrature weights of every node in slot layout, [n_elements, nodes] (element volume
+    included), for objectives written on the slot-layout state."""
+    import numpy as np
+    W = solver.node_weights()
+    full = np.ascontiguousarray(np.broadcast_to(W[:, None, :], solver.leaf_shape))
+    return solver.to_slot(full).view(solver.nv, -1, solver.Nd)[0, : solver.n_elements].clone()
+
+
+def kinetic_energy(solver, u_slot, weights):
+    """Discrete total kinetic energy sum_nodes w 1/2 |rho v|^2 / rho of a slot-layout state."""
+    U = u_slot.view(solver.nv, -1, solver.Nd)[:, : solver.n_elements]
+    mom2 = (U[1: 1 + solver.dim] ** 2).sum(0)
+    return (weights * 0.5 * mom2 / U[0]).sum()

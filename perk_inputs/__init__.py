@@ -251,18 +251,39 @@ def isentropic_vortex(x, y, eps=5.0, mach=0.5, gamma=1.4, center=(0.0, 0.0), t=0
     return prim2cons(rho, [vx, vy], p, gamma)
 
 
-def kelvin_helmholtz(x, y, seed=MASTER_SEED + 1, gamma=1.4, amplitude=0.01, width=0.05):
-    """Shear layer on [-1,1]^2: s(y) = (tanh((y+0.5)/w) - tanh((y-0.5)/w))/2,
-    rho = 0.5 + 0.5 s, v_x = -0.5 + s, p = 1, v_y = A sin(2 pi (x + phi)) times Gaussians
-    centred on the two layers; phi drawn from the seed."""
+def kelvin_helmholtz_prim(x, y, seed=MASTER_SEED + 1, amplitude=0.01, width=0.05):
+    """Shear layer on [-1,1]^2 in primitive variables (rho, v_x, v_y, p):
+    s(y) = (tanh((y+0.5)/w) - tanh((y-0.5)/w))/2, rho = 0.5 + 0.5 s, v_x = -0.5 + s, p = 1,
+    v_y = A sin(2 pi (x + phi)) times Gaussians centred on the two layers; phi from the seed."""
     phi = np.random.default_rng(seed).random()
     s = 0.5 * (np.tanh((y + 0.5) / width) - np.tanh((y - 0.5) / width))
     rho = 0.5 + 0.5 * s
     vx = -0.5 + s
     vy = amplitude * np.sin(2 * np.pi * (x + phi)) * (np.exp(-((y - 0.5) / 0.1) ** 2) +
                                                       np.exp(-((y + 0.5) / 0.1) ** 2))
-    p = np.ones_like(x)
+    return rho, vx, vy, np.ones_like(x)
+
+
+def kelvin_helmholtz(x, y, seed=MASTER_SEED + 1, gamma=1.4, amplitude=0.01, width=0.05):
+    """The shear layer of kelvin_helmholtz_prim in conservative variables."""
+    rho, vx, vy, p = kelvin_helmholtz_prim(x, y, seed, amplitude, width)
     return prim2cons(rho, [vx, vy], p, gamma)
+
+
+def kh_density_perturbation(x, y, seed=MASTER_SEED + 4, amplitude=1e-3, n_modes=8):
+    """Seeded smooth periodic density perturbation on [-1,1]^2 (the control of the
+    differentiated workload): amplitude * sum_k a_k sin(pi (kx_k x + ky_k y) + phi_k), a_k in
+    [0,1], integer wave numbers |kx|, |ky| <= 4 not both zero, phases in [0, 2 pi)."""
+    rng = np.random.default_rng(seed)
+    m = np.zeros_like(x)
+    for _ in range(n_modes):
+        a = rng.random()
+        kx, ky = 0, 0
+        while kx == 0 and ky == 0:
+            kx, ky = (int(v) for v in rng.integers(-4, 5, size=2))
+        phi = 2 * np.pi * rng.random()
+        m = m + a * np.sin(np.pi * (kx * x + ky * y) + phi)
+    return amplitude * m
 
 
 def taylor_green(x, y, z, mach=0.1, gamma=1.4):

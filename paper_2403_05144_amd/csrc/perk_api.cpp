@@ -205,8 +205,6 @@ inline uint64_t cell_key(int lev, int i, int j, int k) {
 
 pe_status build_connectivity(pe_ctx* ctx) {
   const int n = ctx->n_e, dim = ctx->dim, nf = 2 * dim;
-  std::unordered_map<uint64_t, int, KeyHash> idx;
-  idx.reserve(n * 2);
   ctx->max_level = 0;
   for (int e = 0; e < n; ++e) {
     const int32_t* L = &ctx->leaves[4 * e];
@@ -218,28 +216,68 @@ pe_status build_connectivity(pe_ctx* ctx) {
       if (nc >= (1 << 20)) return fail(ctx, PE_EINVAL, "leaf %d: grid too fine", e);
     }
     ctx->max_level = std::max(ctx->max_level, lev);
-    const uint64_t key = cell_key(lev, L[1], L[2], dim == 3 ? L[3] : 0);
-    if (!idx.emplace(key, e).second) return fail(ctx, PE_EINVAL, "duplicate leaf %d", e);
   }
-  // coverage: every leaf's ancestors must not be leaves; total volume must match
-  double vol = 0.0;
-  for (int e = 0; e < n; ++e) {
-    const int lev = ctx->leaves[4 * e];
-    vol += std::ldexp(1.0, -dim * lev);
-    for (int up = 1; up <= lev; ++up) {
+  const int Lm = ctx->max_level;
+  int64_t nfine[3] = {1, 1, 1}, total = 1;
+  for (int d = 0; d < dim; ++d) {
+    nfine[d] = (int64_t)ctx->n_root[d] << Lm;
+    total *= nfine[d];
+  }
+  // Leaf lookup.  Dense: the owner of every cell of the finest level (one array read per
+  // lookup; overlap and coverage checked while filling).  Hash map for very fine grids.
+  const bool dense = total <= ((int64_t)1 << 24);
+  std::vector<int32_t> own;
+  std::unordered_map<uint64_t, int, KeyHash> idx;
+  if (dense) {
+    own.assign((size_t)total, -1);
+    for (int e = 0; e < n; ++e) {
       const int32_t* L = &ctx->leaves[4 * e];
-      if (idx.count(cell_key(lev - up, L[1] >> up, L[2] >> up, dim == 3 ? (L[3] >> up) : 0)))
-        return fail(ctx, PE_EINVAL, "leaf %d overlaps an ancestor leaf", e);
+      const int sh = Lm - L[0], span = 1 << sh;
+      const int64_t i0 = (int64_t)L[1] << sh, j0 = (int64_t)L[2] << sh, k0 = dim == 3 ? ((int64_t)L[3] << sh) : 0;
+      const int sk = dim == 3 ? span : 1;
+      for (int c = 0; c < sk; ++c)
+        for (int b = 0; b < span; ++b) {
+          int32_t* row = &own[(size_t)(((k0 + c) * nfine[1] + (j0 + b)) * nfine[0] + i0)];
+          for (int a = 0; a < span; ++a) {
+            if (row[a] >= 0) return fail(ctx, PE_EINVAL, "leaf %d overlaps leaf %d", e, row[a]);
+            row[a] = e;
+          }
+        }
     }
+    for (int64_t q = 0; q < total; ++q)
+      if (own[(size_t)q] < 0) return fail(ctx, PE_EINVAL, "leaves do not cover the domain");
+  } else {
+    idx.reserve(n * 2);
+    for (int e = 0; e < n; ++e) {
+      const int32_t* L = &ctx->leaves[4 * e];
+      if (!idx.emplace(cell_key(L[0], L[1], L[2], dim == 3 ? L[3] : 0), e).second)
+        return fail(ctx, PE_EINVAL, "duplicate leaf %d", e);
+    }
+    // coverage: every leaf's ancestors must not be leaves; total volume must match
+    double vol = 0.0;
+    for (int e = 0; e < n; ++e) {
+      const int lev = ctx->leaves[4 * e];
+      vol += std::ldexp(1.0, -dim * lev);
+      for (int up = 1; up <= lev; ++up) {
+        const int32_t* L = &ctx->leaves[4 * e];
+        if (idx.count(cell_key(lev - up, L[1] >> up, L[2] >> up, dim == 3 ? (L[3] >> up) : 0)))
+          return fail(ctx, PE_EINVAL, "leaf %d overlaps an ancestor leaf", e);
+      }
+    }
+    double roots = 1.0;
+    for (int d = 0; d < dim; ++d) roots *= ctx->n_root[d];
+    if (std::fabs(vol - roots) > 1e-9 * roots) return fail(ctx, PE_EINVAL, "leaves do not cover the domain");
   }
-  double roots = 1.0;
-  for (int d = 0; d < dim; ++d) roots *= ctx->n_root[d];
-  if (std::fabs(vol - roots) > 1e-9 * roots) return fail(ctx, PE_EINVAL, "leaves do not cover the domain");
   ctx->fk_leaf.assign((size_t)n * nf, 0);
   ctx->fn_leaf.assign((size_t)n * nf * 4, -1);
   ctx->lev_leaf.assign(n, 0);
   auto find = [&](int lev, int i, int j, int k) -> int {
-    if (lev < 0) return -1;
+    if (lev < 0 || lev > Lm) return -1;
+    if (dense) {
+      const int sh = Lm - lev;
+      const int o = own[(size_t)((((int64_t)k << sh) * nfine[1] + ((int64_t)j << sh)) * nfine[0] + ((int64_t)i << sh))];
+      return ctx->leaves[4 * o] == lev ? o : -1;
+    }
     auto it = idx.find(cell_key(lev, i, j, k));
     return it == idx.end() ? -1 : it->second;
   };
@@ -673,10 +711,10 @@ pe_status pe_partition(pe_ctx* ctx, const int32_t* member_of_level, int n_levels
     ctx->pending_leaf_state = false;
     ctx->state_valid = true;
   }
+  // elements per member from the host's leaf levels (the same counts the sort kernel forms)
   ctx->counts.assign(ctx->R, 0);
-  HIPCHK(hipMemcpyAsync(ctx->counts.data(), ctx->d_counts, ctx->R * 4, hipMemcpyDeviceToHost, s));
+  for (int e = 0; e < n; ++e) ctx->counts[member_of_level[ctx->lev_leaf[e]]] += 1;
   ctx->maps_on_host = false;
-  HIPCHK(hipStreamSynchronize(s));
   ctx->n_act.assign(ctx->S, 0);
   for (int i = 0; i < ctx->S; ++i)
     for (int r = 0; r < ctx->R; ++r)
@@ -1067,13 +1105,32 @@ pe_status pe_max_dt(pe_ctx* ctx, double cfl, double* dt_out, double* beta_of_lev
 }
 
 namespace {
+// spread the low 21 bits of x to every 2nd (dim 2) or 3rd (dim 3) bit
+inline uint64_t spread2(uint64_t x) {
+  x &= 0x1FFFFFull;
+  x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+  x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+  x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+  x = (x | (x << 2)) & 0x3333333333333333ull;
+  x = (x | (x << 1)) & 0x5555555555555555ull;
+  return x;
+}
+inline uint64_t spread3(uint64_t x) {
+  x &= 0x1FFFFFull;
+  x = (x | (x << 32)) & 0x001F00000000FFFFull;
+  x = (x | (x << 16)) & 0x001F0000FF0000FFull;
+  x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+  x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+// Morton key of a leaf: coordinates at level kMaxLevels-1, bit b of axis d at position dim*b + d
 uint64_t morton_key(const int32_t* L, int dim) {
   const int shift = kMaxLevels - 1 - L[0];
-  uint64_t x[3] = {(uint64_t)L[1] << shift, (uint64_t)L[2] << shift, dim == 3 ? (uint64_t)L[3] << shift : 0};
-  uint64_t key = 0;
-  for (int b = 0; b < 21; ++b)
-    for (int d = 0; d < dim; ++d) key |= ((x[d] >> b) & 1ull) << (dim * b + d);
-  return key;
+  const uint64_t x = (uint64_t)L[1] << shift, y = (uint64_t)L[2] << shift;
+  if (dim == 2) return spread2(x) | (spread2(y) << 1);
+  const uint64_t z = (uint64_t)L[3] << shift;
+  return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
 }
 }  // namespace
 
@@ -1115,6 +1172,7 @@ pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags, int level_min, int level_ma
     fams[cell_key(lev[e] - 1, L[1] >> 1, L[2] >> 1, dim == 3 ? (L[3] >> 1) : 0)].push_back(e);
   }
   std::vector<int> parent_of(n, -1);   // index of the family's first member for coarsened leaves
+  std::unordered_map<int, std::vector<int>> members;   // first member -> the family
   for (auto& kv : fams) {
     auto& mem = kv.second;
     if ((int)mem.size() != nch) continue;
@@ -1126,6 +1184,7 @@ pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags, int level_min, int level_ma
     if (!ok) continue;
     const int first = *std::min_element(mem.begin(), mem.end());
     for (int e : mem) parent_of[e] = first;
+    members[first] = mem;
   }
   // new leaves with their projection plans
   struct NewLeaf {
@@ -1142,12 +1201,11 @@ pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags, int level_min, int level_ma
       if (parent_of[e] != e) continue;
       x.L = {lev[e] - 1, L[1] >> 1, L[2] >> 1, dim == 3 ? (L[3] >> 1) : 0};
       x.plan[0] = 2;
-      for (int g = 0; g < n; ++g)
-        if (parent_of[g] == e) {
-          const int32_t* G = &ctx->leaves[4 * g];
-          const int pos = (G[1] & 1) | ((G[2] & 1) << 1) | (dim == 3 ? ((G[3] & 1) << 2) : 0);
-          x.plan[2 + pos] = g;
-        }
+      for (int g : members[e]) {
+        const int32_t* G = &ctx->leaves[4 * g];
+        const int pos = (G[1] & 1) | ((G[2] & 1) << 1) | (dim == 3 ? ((G[3] & 1) << 2) : 0);
+        x.plan[2 + pos] = g;
+      }
       nl.push_back(x);
     } else if (t[e] == lev[e] + 1) {
       for (int c = 0; c < nch; ++c) {
@@ -1168,13 +1226,15 @@ pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags, int level_min, int level_ma
   if ((int64_t)nl.size() > cap_of(ctx))
     return fail(ctx, PE_ENOMEM, "adapt: %zu elements exceed the reserved capacity %lld", nl.size(),
                 (long long)cap_of(ctx));
-  for (auto& x : nl) x.key = morton_key(x.L.data(), dim);
-  std::sort(nl.begin(), nl.end(), [](const NewLeaf& a, const NewLeaf& b) { return a.key < b.key; });
+  std::vector<std::pair<uint64_t, int32_t>> order(nl.size());
+  for (size_t i = 0; i < nl.size(); ++i) order[i] = {morton_key(nl[i].L.data(), dim), (int32_t)i};
+  std::sort(order.begin(), order.end());
   std::vector<int32_t> plan(nl.size() * 10);
   std::vector<int32_t> leaves(nl.size() * 4);
   for (size_t i = 0; i < nl.size(); ++i) {
-    std::memcpy(&plan[i * 10], nl[i].plan.data(), 40);
-    std::memcpy(&leaves[i * 4], nl[i].L.data(), 16);
+    const NewLeaf& x = nl[(size_t)order[i].second];
+    std::memcpy(&plan[i * 10], x.plan.data(), 40);
+    std::memcpy(&leaves[i * 4], x.L.data(), 16);
   }
   hipStream_t s = (hipStream_t)stream;
   // evaluation counts of the old partition into the per-member totals

@@ -187,6 +187,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   __shared__ double s_u[EPB][NV][ND];
   __shared__ NodeQ<DIM> s_q[EPB][ND];
   __shared__ double s_tr[EPB][NFC][NSUB][NV][NF];   // neighbour traces, later HLL fluxes in place
+  __shared__ double s_tro[EPB][NFC][NSUB][NV][NF];  // coarse sides: own trace on every sub-face
   __shared__ double s_pf[EPB][NP][NV];
   __shared__ int s_fk[EPB][NFC];
   __shared__ int s_fn[EPB][NFC][4];
@@ -326,6 +327,46 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         s_trv[le][f][1][v][j] = vv;
       }
     }
+    // coarse sides: own trace interpolated to every sub-face and, for BR1, the central average
+    // of the interpolated own viscous flux with the fine neighbour's (one item per lane here
+    // instead of a whole tensor-product interpolation per flux lane in phase D)
+    for (int w = lane; w < NFC * NSUB * NV * NF; w += T) {
+      const int j = w % NF;
+      const int v = (w / NF) % NV;
+      const int sub = (w / (NF * NV)) % NSUB;
+      const int f = w / (NF * NV * NSUB);
+      if (face_kind(s_fk[le][f]) != kCoarseSide) continue;
+      const int d = f >> 1, side = f & 1;
+      const int m0 = sub & 1, m1 = (sub >> 1) & 1;
+      double x = 0.0, xv = 0.0;
+      if (DIM == 2) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const double c = op.P[m0][j * N + k];
+          const int on = face_node<DIM, N>(d, side, k);
+          x += c * s_u[le][v][on];
+          if (VISC) xv += c * s_fv[le][d][v][on];
+        }
+      } else {
+        const int ja = j % N, jb = j / N;
+#pragma unroll
+        for (int kb = 0; kb < N; ++kb) {
+          double row = 0.0, rowv = 0.0;
+#pragma unroll
+          for (int ka = 0; ka < N; ++ka) {
+            const double c = op.P[m0][ja * N + ka];
+            const int on = face_node<DIM, N>(d, side, ka + N * kb);
+            row += c * s_u[le][v][on];
+            if (VISC) rowv += c * s_fv[le][d][v][on];
+          }
+          const double cb = op.P[m1][jb * N + kb];
+          x += cb * row;
+          if (VISC) xv += cb * rowv;
+        }
+      }
+      s_tro[le][f][sub][v][j] = x;
+      if (VISC) s_trv[le][f][sub][v][j] = 0.5 * (xv + s_trv[le][f][sub][v][j]);
+    }
   }
   __syncthreads();
 
@@ -358,39 +399,12 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         const int d = f >> 1, side = f & 1;
         double mine[NV], oth[NV], fl[NV];
         if (kind == kCoarseSide) {
-          // own trace interpolated to sub-face `sub`
-          const int m0 = sub & 1, m1 = (sub >> 1) & 1;
+          // own trace interpolated to sub-face `sub` (phase C)
 #pragma unroll
-          for (int v = 0; v < NV; ++v) mine[v] = 0.0;
-          if (DIM == 2) {
-#pragma unroll
-            for (int k = 0; k < N; ++k) {
-              const double c = op.P[m0][j * N + k];
-              const int on = face_node<DIM, N>(d, side, k);
-#pragma unroll
-              for (int v = 0; v < NV; ++v) mine[v] += c * s_u[le][v][on];
-            }
-          } else {
-            const int ja = j % N, jb = j / N;
-#pragma unroll
-            for (int kb = 0; kb < N; ++kb) {
-              double row[NV];
-#pragma unroll
-              for (int v = 0; v < NV; ++v) row[v] = 0.0;
-#pragma unroll
-              for (int ka = 0; ka < N; ++ka) {
-                const double c = op.P[m0][ja * N + ka];
-                const int on = face_node<DIM, N>(d, side, ka + N * kb);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) row[v] += c * s_u[le][v][on];
-              }
-              const double cb = op.P[m1][jb * N + kb];
-#pragma unroll
-              for (int v = 0; v < NV; ++v) mine[v] += cb * row[v];
-            }
+          for (int v = 0; v < NV; ++v) {
+            mine[v] = s_tro[le][f][sub][v][j];
+            oth[v] = s_tr[le][f][sub][v][j];
           }
-#pragma unroll
-          for (int v = 0; v < NV; ++v) oth[v] = s_tr[le][f][sub][v][j];
         } else {
           const int on = face_node<DIM, N>(d, side, j);
           const int ts = kind == kFineSide ? 1 : 0;
@@ -404,36 +418,62 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         else hll_flux<DIM>(oth, mine, d, gamma, fl);
 #pragma unroll
         for (int v = 0; v < NV; ++v) s_tr[le][f][sub][v][j] = fl[v];
-        if (VISC) {
-          // BR1 central viscous flux on this (sub-)face node: 1/2 (own + neighbour)
+        if (VISC && kind != kCoarseSide) {
+          // BR1 central viscous flux on this face node: 1/2 (own + neighbour); coarse sides
+          // were averaged in phase C
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            double ownv;
-            if (kind == kCoarseSide) {
-              const int m0 = sub & 1, m1 = (sub >> 1) & 1;
-              ownv = 0.0;
-              if (DIM == 2) {
-#pragma unroll
-                for (int k = 0; k < N; ++k) ownv += op.P[m0][j * N + k] * s_fv[le][d][v][face_node<DIM, N>(d, side, k)];
-              } else {
-                const int ja = j % N, jb = j / N;
-#pragma unroll
-                for (int kb = 0; kb < N; ++kb) {
-                  double row = 0.0;
-#pragma unroll
-                  for (int ka = 0; ka < N; ++ka)
-                    row += op.P[m0][ja * N + ka] * s_fv[le][d][v][face_node<DIM, N>(d, side, ka + N * kb)];
-                  ownv += op.P[m1][jb * N + kb] * row;
-                }
-              }
-            } else {
-              ownv = s_fv[le][d][v][face_node<DIM, N>(d, side, j)];
-            }
-            const int ts = kind == kFineSide ? 1 : sub;
+            const double ownv = s_fv[le][d][v][face_node<DIM, N>(d, side, j)];
+            const int ts = kind == kFineSide ? 1 : 0;
             s_trv[le][f][sub][v][j] = 0.5 * (ownv + s_trv[le][f][ts][v][j]);
           }
         }
       }
+    }
+  }
+  __syncthreads();
+
+  // ---- E0: coarse sides: sub-face fluxes projected back to the coarse face nodes with R_m
+  //      (inviscid into s_tro[..][0], viscous into s_tro[..][1]; the own sub-face traces there
+  //      are no longer needed)
+  if (act) {
+    for (int w = lane; w < NFC * NV * NF; w += T) {
+      const int i = w % NF;
+      const int v = (w / NF) % NV;
+      const int f = w / (NF * NV);
+      if (face_kind(s_fk[le][f]) != kCoarseSide) continue;
+      double fs = 0.0, fsv = 0.0;
+      if (DIM == 2) {
+#pragma unroll
+        for (int ms = 0; ms < 2; ++ms)
+#pragma unroll
+          for (int k = 0; k < N; ++k) {
+            const double r = op.R[ms][i * N + k];
+            fs += r * s_tr[le][f][ms][v][k];
+            if (VISC) fsv += r * s_trv[le][f][ms][v][k];
+          }
+      } else {
+        const int ia = i % N, ib = i / N;
+#pragma unroll
+        for (int ms = 0; ms < 4; ++ms) {
+          const int m0 = ms & 1, m1 = (ms >> 1) & 1;
+#pragma unroll
+          for (int kb = 0; kb < N; ++kb) {
+            double row = 0.0, rowv = 0.0;
+#pragma unroll
+            for (int ka = 0; ka < N; ++ka) {
+              const double r = op.R[m0][ia * N + ka];
+              row += r * s_tr[le][f][ms][v][ka + N * kb];
+              if (VISC) rowv += r * s_trv[le][f][ms][v][ka + N * kb];
+            }
+            const double rb = op.R[m1][ib * N + kb];
+            fs += rb * row;
+            if (VISC) fsv += rb * rowv;
+          }
+        }
+      }
+      s_tro[le][f][0][v][i] = fs;
+      if (VISC) s_tro[le][f][1][v][i] = fsv;
     }
   }
   __syncthreads();
@@ -464,26 +504,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         const int fi = face_index<DIM, N>(nd, d);
         double fs;
         if (face_kind(s_fk[le][f]) == kCoarseSide) {
-          fs = 0.0;
-          if (DIM == 2) {
-#pragma unroll
-            for (int ms = 0; ms < 2; ++ms)
-#pragma unroll
-              for (int k = 0; k < N; ++k) fs += op.R[ms][fi * N + k] * s_tr[le][f][ms][v][k];
-          } else {
-            const int ja = fi % N, jb = fi / N;
-#pragma unroll
-            for (int ms = 0; ms < 4; ++ms) {
-              const int m0 = ms & 1, m1 = (ms >> 1) & 1;
-#pragma unroll
-              for (int kb = 0; kb < N; ++kb) {
-                double row = 0.0;
-#pragma unroll
-                for (int ka = 0; ka < N; ++ka) row += op.R[m0][ja * N + ka] * s_tr[le][f][ms][v][ka + N * kb];
-                fs += op.R[m1][jb * N + kb] * row;
-              }
-            }
-          }
+          fs = s_tro[le][f][0][v][fi];
         } else {
           fs = s_tr[le][f][0][v][fi];
         }
@@ -499,26 +520,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
           const int fi = face_index<DIM, N>(nd, d);
           double fs;
           if (face_kind(s_fk[le][f]) == kCoarseSide) {
-            fs = 0.0;
-            if (DIM == 2) {
-#pragma unroll
-              for (int ms = 0; ms < 2; ++ms)
-#pragma unroll
-                for (int k = 0; k < N; ++k) fs += op.R[ms][fi * N + k] * s_trv[le][f][ms][v][k];
-            } else {
-              const int ja = fi % N, jb = fi / N;
-#pragma unroll
-              for (int ms = 0; ms < 4; ++ms) {
-                const int m0 = ms & 1, m1 = (ms >> 1) & 1;
-#pragma unroll
-                for (int kb = 0; kb < N; ++kb) {
-                  double row = 0.0;
-#pragma unroll
-                  for (int ka = 0; ka < N; ++ka) row += op.R[m0][ja * N + ka] * s_trv[le][f][ms][v][ka + N * kb];
-                  fs += op.R[m1][jb * N + kb] * row;
-                }
-              }
-            }
+            fs = s_tro[le][f][1][v][fi];
           } else {
             fs = s_trv[le][f][0][v][fi];
           }
@@ -548,7 +550,12 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
 
 template <int DIM, int N, bool VISC>
 __global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB), (SK<DIM, N>::MINW)) void k_stage(StageArgs a, Mesh m, Ops op, Physics ph) {
-  stage_block<DIM, N, VISC, SK<DIM, N>::EPB>(a, m, op, ph, blockIdx.x);
+  // Workgroups go to the 8 XCDs round-robin (block b to XCD b mod 8); give XCD x the
+  // contiguous block range [x G, (x+1) G), G = gridDim / 8, so that neighbouring slots (sorted
+  // by member, Morton order inside) share an L2 and neighbour-trace reads can hit there.
+  const int g8 = (int)gridDim.x >> 3;
+  const int b = (int)blockIdx.x;
+  stage_block<DIM, N, VISC, SK<DIM, N>::EPB>(a, m, op, ph, (b & 7) * g8 + (b >> 3));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -798,7 +805,7 @@ hipError_t launch_stage_t(const StageArgs& a, const Mesh& m, const Ops& op, cons
                           hipEvent_t ev0, hipEvent_t ev1) {
   using K = SK<DIM, N>;
   if (a.n_act <= 0) return hipSuccess;
-  const int blocks = (a.n_act + K::EPB - 1) / K::EPB;
+  const int blocks = ((a.n_act + K::EPB - 1) / K::EPB + 7) & ~7;   // a multiple of the 8 XCDs
   if (ev0)
     hipExtLaunchKernelGGL((k_stage<DIM, N, VISC>), dim3(blocks), dim3(K::T * K::EPB), 0, s, ev0, ev1, 0, a, m, op, ph);
   else

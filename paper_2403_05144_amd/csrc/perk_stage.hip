@@ -26,6 +26,10 @@
 
 #include "perk_device.h"
 
+#ifndef STAGE_SPLIT_MAX
+#define STAGE_SPLIT_MAX 6144
+#endif
+
 namespace perk {
 namespace {
 
@@ -159,7 +163,7 @@ __device__ __forceinline__ double stage_value(const StageArgs& a, int src, int64
 //   E  per (variable, node): flux-differencing sum, lifting of the face fluxes (projected
 //      with R_m on coarse sides), Jacobian, and the P-ERK stage combination.
 // ------------------------------------------------------------------------------------------
-template <int DIM, int N>
+template <int DIM, int N, bool SPLIT_ = false>
 struct SK {
   using g = G<DIM, N>;
   static constexpr int ND = g::ND, NF = g::NF, NFC = g::NFC, NV = g::NV, NSUB = g::NSUB;
@@ -167,7 +171,11 @@ struct SK {
   static constexpr int NLINE = DIM == 2 ? N : N * N;          // lines per direction
   static constexpr int NP = DIM * NLINE * NPL;                // pairs per element
   static constexpr int WORK = NP + NFC * NF;                  // flux items without mortars
-  static constexpr int T = DIM == 2 ? (N == 4 ? 64 : 32) : (N == 4 ? 384 : 192);
+  // 2D p=3: two waves per element; the flux phase puts the pair fluxes on the first wave and
+  // the face fluxes on the second, so their dependency chains run side by side instead of one
+  // after the other in a divergent wave (the face flux chain is the longest of the kernel)
+  static constexpr bool SPLIT = SPLIT_ && DIM == 2 && N == 4;
+  static constexpr int T = DIM == 2 ? (N == 4 ? (SPLIT ? 128 : 64) : 32) : (N == 4 ? 384 : 192);
   static constexpr int EPB = T >= 64 ? 1 : 64 / T;
   static constexpr int NITEM = (NV * ND + T - 1) / T;         // (variable, node) items per lane
   // waves per SIMD the register allocation must allow (forcing two 384-lane 3D blocks per CU
@@ -178,10 +186,10 @@ struct SK {
 // The stage work of one block of EPB elements: block `blk` of the launch covers the slots
 // [blk EPB, blk EPB + EPB).  Shared by the single-run kernel and the batched kernel, which
 // therefore compute bitwise identical stages.
-template <int DIM, int N, bool VISC, int EPB>
+template <int DIM, int N, bool VISC, int EPB, bool SPLIT = false>
 __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph,
                                             int blk) {
-  using K = SK<DIM, N>;
+  using K = SK<DIM, N, SPLIT>;
   constexpr int ND = K::ND, NF = K::NF, NFC = K::NFC, NV = K::NV, NSUB = K::NSUB, T = K::T;
   constexpr int NP = K::NP, NPL = K::NPL, NITEM = K::NITEM;
   __shared__ double s_u[EPB][NV][ND];
@@ -287,7 +295,9 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       q.lbeta = log(q.beta);
       s_q[le][w] = q;
     }
-    for (int w = lane; w < NFC * NV * NF; w += T) {
+    // (split: interpolations start on the second wave, the node quantities sit on the first)
+    const int lane_c = K::SPLIT ? (lane ^ (T / 2)) : lane;
+    for (int w = lane_c; w < NFC * NV * NF; w += T) {
       const int j = w % NF;
       const int v = (w / NF) % NV;
       const int f = w / (NF * NV);
@@ -330,7 +340,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
     // coarse sides: own trace interpolated to every sub-face and, for BR1, the central average
     // of the interpolated own viscous flux with the fine neighbour's (one item per lane here
     // instead of a whole tensor-product interpolation per flux lane in phase D)
-    for (int w = lane; w < NFC * NSUB * NV * NF; w += T) {
+    for (int w = lane_c; w < NFC * NSUB * NV * NF; w += T) {
       const int j = w % NF;
       const int v = (w / NF) % NV;
       const int sub = (w / (NF * NV)) % NSUB;
@@ -372,7 +382,12 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
 
   // ---- D: fluxes.  Pairs first, then face nodes sub-face-major (sub 0 of every face first).
   if (act) {
-    for (int w = lane; w < NP + NSUB * NFC * NF; w += T) {
+    for (int w0 = lane; w0 < (K::SPLIT ? T : NP + NSUB * NFC * NF); w0 += T) {
+      // split: lanes [0, T/2) take the pairs, lanes [T/2, T) the face nodes
+      const int w = !K::SPLIT ? w0
+                              : (w0 < T / 2 ? (w0 < NP ? w0 : -1)
+                                            : (w0 - T / 2 < NSUB * NFC * NF ? NP + w0 - T / 2 : -1));
+      if (w < 0) continue;
       if (w < NP) {
         const int pl = w % NPL;
         const int line = (w / NPL) % K::NLINE;
@@ -548,14 +563,14 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   }
 }
 
-template <int DIM, int N, bool VISC>
-__global__ __launch_bounds__((SK<DIM, N>::T * SK<DIM, N>::EPB), (SK<DIM, N>::MINW)) void k_stage(StageArgs a, Mesh m, Ops op, Physics ph) {
+template <int DIM, int N, bool VISC, bool SPLIT>
+__global__ __launch_bounds__((SK<DIM, N, SPLIT>::T * SK<DIM, N, SPLIT>::EPB), (SK<DIM, N, SPLIT>::MINW)) void k_stage(StageArgs a, Mesh m, Ops op, Physics ph) {
   // Workgroups go to the 8 XCDs round-robin (block b to XCD b mod 8); give XCD x the
   // contiguous block range [x G, (x+1) G), G = gridDim / 8, so that neighbouring slots (sorted
   // by member, Morton order inside) share an L2 and neighbour-trace reads can hit there.
   const int g8 = (int)gridDim.x >> 3;
   const int b = (int)blockIdx.x;
-  stage_block<DIM, N, VISC, SK<DIM, N>::EPB>(a, m, op, ph, (b & 7) * g8 + (b >> 3));
+  stage_block<DIM, N, VISC, SK<DIM, N, SPLIT>::EPB, SPLIT>(a, m, op, ph, (b & 7) * g8 + (b >> 3));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -800,17 +815,32 @@ hipError_t launch_grad_t(const StageArgs& a, const Mesh& m, const Ops& op, const
   return hipGetLastError();
 }
 
+template <int DIM, int N, bool VISC, bool SPLIT>
+hipError_t launch_stage_v(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s,
+                          hipEvent_t ev0, hipEvent_t ev1) {
+  using K = SK<DIM, N, SPLIT>;
+  const int blocks = ((a.n_act + K::EPB - 1) / K::EPB + 7) & ~7;   // a multiple of the 8 XCDs
+  if (ev0)
+    hipExtLaunchKernelGGL((k_stage<DIM, N, VISC, SPLIT>), dim3(blocks), dim3(K::T * K::EPB), 0, s, ev0, ev1, 0, a, m,
+                          op, ph);
+  else
+    hipLaunchKernelGGL((k_stage<DIM, N, VISC, SPLIT>), dim3(blocks), dim3(K::T * K::EPB), 0, s, a, m, op, ph);
+  return hipGetLastError();
+}
+
+// 2D p=3 launches with few active elements are latency-bound: two waves per element (pair and
+// face fluxes side by side) finish sooner; with many elements the launch is throughput-bound
+// and one wave per element issues fewer instructions per element.  Measured on uniform meshes:
+// split faster up to 4096 elements (1024: 6.3 vs 7.2 us), single wave from 9216 on.
+constexpr int kSplitMaxElements = STAGE_SPLIT_MAX;
+
 template <int DIM, int N, bool VISC>
 hipError_t launch_stage_t(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1) {
-  using K = SK<DIM, N>;
   if (a.n_act <= 0) return hipSuccess;
-  const int blocks = ((a.n_act + K::EPB - 1) / K::EPB + 7) & ~7;   // a multiple of the 8 XCDs
-  if (ev0)
-    hipExtLaunchKernelGGL((k_stage<DIM, N, VISC>), dim3(blocks), dim3(K::T * K::EPB), 0, s, ev0, ev1, 0, a, m, op, ph);
-  else
-    hipLaunchKernelGGL((k_stage<DIM, N, VISC>), dim3(blocks), dim3(K::T * K::EPB), 0, s, a, m, op, ph);
-  return hipGetLastError();
+  if (DIM == 2 && N == 4 && a.n_act <= kSplitMaxElements)
+    return launch_stage_v<DIM, N, VISC, true>(a, m, op, ph, s, ev0, ev1);
+  return launch_stage_v<DIM, N, VISC, false>(a, m, op, ph, s, ev0, ev1);
 }
 
 }  // namespace

@@ -178,9 +178,10 @@ struct SK {
   static constexpr int T = DIM == 2 ? (N == 4 ? (SPLIT ? 128 : 64) : 32) : (N == 4 ? 384 : 192);
   static constexpr int EPB = T >= 64 ? 1 : 64 / T;
   static constexpr int NITEM = (NV * ND + T - 1) / T;         // (variable, node) items per lane
-  // waves per SIMD the register allocation must allow (forcing two 384-lane 3D blocks per CU
-  // spills registers and was measured slower than one block per CU)
-  static constexpr int MINW = 1;
+  // waves per SIMD the register allocation must allow.  A second 6-wave block fits on a CU
+  // only when every SIMD can hold 4 waves (at most 128 VGPRs) and the LDS allows it (measured:
+  // at 3 waves per SIMD a second 384-lane block never starts, whatever its LDS size).
+  static constexpr int MINW = T == 384 ? 4 : 1;
 };
 
 // The stage work of one block of EPB elements: block `blk` of the launch covers the slots
@@ -192,15 +193,23 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   using K = SK<DIM, N, SPLIT>;
   constexpr int ND = K::ND, NF = K::NF, NFC = K::NFC, NV = K::NV, NSUB = K::NSUB, T = K::T;
   constexpr int NP = K::NP, NPL = K::NPL, NITEM = K::NITEM;
+  // 2D stages the own sub-face traces of coarse sides (phase C) and the own viscous flux in LDS.
+  // 3D does not: a coarse-side flux lane interpolates its own trace itself, the own viscous flux
+  // is read where it is used (an L2 hit), and the projected mortar fluxes overwrite the sub-face
+  // fluxes in place.  That keeps a 384-lane 3D block under the LDS size (about 53 KB) at which
+  // two blocks share a CU; with the 72 KB of the staged layout only one does.
+  constexpr bool LDS_OWN = DIM == 2;
+  constexpr int EO = LDS_OWN ? EPB : 1, NSO = LDS_OWN ? NSUB : 1;
+  constexpr bool FVL = VISC && LDS_OWN;
   __shared__ double s_u[EPB][NV][ND];
   __shared__ NodeQ<DIM> s_q[EPB][ND];
   __shared__ double s_tr[EPB][NFC][NSUB][NV][NF];   // neighbour traces, later HLL fluxes in place
-  __shared__ double s_tro[EPB][NFC][NSUB][NV][NF];  // coarse sides: own trace on every sub-face
+  __shared__ double s_tro[EO][LDS_OWN ? NFC : 1][NSO][LDS_OWN ? NV : 1][LDS_OWN ? NF : 1];  // coarse sides: own trace on every sub-face
   __shared__ double s_pf[EPB][NP][NV];
   __shared__ int s_fk[EPB][NFC];
   __shared__ int s_fn[EPB][NFC][4];
-  // BR1: own viscous flux at every node and the neighbours' viscous face traces
-  __shared__ double s_fv[VISC ? EPB : 1][VISC ? DIM : 1][VISC ? NV : 1][VISC ? ND : 1];
+  // BR1: own viscous flux at every node (2D) and the neighbours' viscous face traces
+  __shared__ double s_fv[FVL ? EPB : 1][FVL ? DIM : 1][FVL ? NV : 1][FVL ? ND : 1];
   __shared__ double s_trv[VISC ? EPB : 1][VISC ? NFC : 1][VISC ? NSUB : 1][VISC ? NV : 1][VISC ? NF : 1];
 
   const int le = threadIdx.x / T;
@@ -210,6 +219,11 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   const int ld = m.ld;
   const double gamma = ph.gamma;
   const double inv_gm1 = 1.0 / (gamma - 1.0);
+  // own viscous flux, direction d, variable v, node nd
+  auto fv_own = [&](int d, int v, int nd) -> double {
+    if (FVL) return s_fv[le][d][v][nd];
+    return a.Fv[(((int64_t)d * NV + v) * ld + e) * ND + nd];
+  };
 
   // ---- A+B: connectivity, own values and epilogue operands, neighbour traces, all in flight
   //      together; one barrier before the node quantities
@@ -265,7 +279,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       s_tr[le][f][sub][v][j] = stage_value(a, src, ((int64_t)v * ld + nb) * ND + nn);
       if (VISC) s_trv[le][f][sub][v][j] = a.Fv[(((int64_t)d * NV + v) * ld + nb) * ND + nn];
     }
-    if (VISC) {
+    if (FVL) {
       for (int w = lane; w < DIM * NV * ND; w += T) {
         const int nd = w % ND, v = (w / ND) % NV, d = w / (ND * NV);
         s_fv[le][d][v][nd] = a.Fv[(((int64_t)d * NV + v) * ld + e) * ND + nd];
@@ -337,10 +351,10 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         s_trv[le][f][1][v][j] = vv;
       }
     }
-    // coarse sides: own trace interpolated to every sub-face and, for BR1, the central average
-    // of the interpolated own viscous flux with the fine neighbour's (one item per lane here
-    // instead of a whole tensor-product interpolation per flux lane in phase D)
-    for (int w = lane_c; w < NFC * NSUB * NV * NF; w += T) {
+    // coarse sides: own trace interpolated to every sub-face (2D: one item per lane here
+    // instead of a whole interpolation per flux lane in phase D) and, for BR1, the central
+    // average of the interpolated own viscous flux with the fine neighbour's
+    for (int w = lane_c; (LDS_OWN || VISC) && w < NFC * NSUB * NV * NF; w += T) {
       const int j = w % NF;
       const int v = (w / NF) % NV;
       const int sub = (w / (NF * NV)) % NSUB;
@@ -354,8 +368,8 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         for (int k = 0; k < N; ++k) {
           const double c = op.P[m0][j * N + k];
           const int on = face_node<DIM, N>(d, side, k);
-          x += c * s_u[le][v][on];
-          if (VISC) xv += c * s_fv[le][d][v][on];
+          if (LDS_OWN) x += c * s_u[le][v][on];
+          if (VISC) xv += c * fv_own(d, v, on);
         }
       } else {
         const int ja = j % N, jb = j / N;
@@ -366,15 +380,15 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
           for (int ka = 0; ka < N; ++ka) {
             const double c = op.P[m0][ja * N + ka];
             const int on = face_node<DIM, N>(d, side, ka + N * kb);
-            row += c * s_u[le][v][on];
-            if (VISC) rowv += c * s_fv[le][d][v][on];
+            if (LDS_OWN) row += c * s_u[le][v][on];
+            if (VISC) rowv += c * fv_own(d, v, on);
           }
           const double cb = op.P[m1][jb * N + kb];
           x += cb * row;
           if (VISC) xv += cb * rowv;
         }
       }
-      s_tro[le][f][sub][v][j] = x;
+      if (LDS_OWN) s_tro[le][f][sub][v][j] = x;
       if (VISC) s_trv[le][f][sub][v][j] = 0.5 * (xv + s_trv[le][f][sub][v][j]);
     }
   }
@@ -413,12 +427,31 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         if (sub > 0 && kind != kCoarseSide) continue;
         const int d = f >> 1, side = f & 1;
         double mine[NV], oth[NV], fl[NV];
-        if (kind == kCoarseSide) {
+        if (kind == kCoarseSide && LDS_OWN) {
           // own trace interpolated to sub-face `sub` (phase C)
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             mine[v] = s_tro[le][f][sub][v][j];
             oth[v] = s_tr[le][f][sub][v][j];
+          }
+        } else if (kind == kCoarseSide) {
+          // own trace interpolated to sub-face `sub` here: P_{m1} (x) P_{m0} on the face, one
+          // variable at a time (five accumulators at once would spill at 128 VGPRs)
+          const int m0 = sub & 1, m1 = (sub >> 1) & 1;
+          const int ja = j % N, jb = j / N;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            oth[v] = s_tr[le][f][sub][v][j];
+            double x = 0.0;
+#pragma unroll 1
+            for (int kb = 0; kb < N; ++kb) {
+              double row = 0.0;
+#pragma unroll
+              for (int ka = 0; ka < N; ++ka)
+                row += op.P[m0][ja * N + ka] * s_u[le][v][face_node<DIM, N>(d, side, ka + N * kb)];
+              x += op.P[m1][jb * N + kb] * row;
+            }
+            mine[v] = x;
           }
         } else {
           const int on = face_node<DIM, N>(d, side, j);
@@ -438,7 +471,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
           // were averaged in phase C
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            const double ownv = s_fv[le][d][v][face_node<DIM, N>(d, side, j)];
+            const double ownv = fv_own(d, v, face_node<DIM, N>(d, side, j));
             const int ts = kind == kFineSide ? 1 : 0;
             s_trv[le][f][sub][v][j] = 0.5 * (ownv + s_trv[le][f][ts][v][j]);
           }
@@ -448,47 +481,71 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   }
   __syncthreads();
 
-  // ---- E0: coarse sides: sub-face fluxes projected back to the coarse face nodes with R_m
-  //      (inviscid into s_tro[..][0], viscous into s_tro[..][1]; the own sub-face traces there
-  //      are no longer needed)
-  if (act) {
-    for (int w = lane; w < NFC * NV * NF; w += T) {
-      const int i = w % NF;
-      const int v = (w / NF) % NV;
-      const int f = w / (NF * NV);
-      if (face_kind(s_fk[le][f]) != kCoarseSide) continue;
-      double fs = 0.0, fsv = 0.0;
-      if (DIM == 2) {
+  // ---- E0: coarse sides: sub-face fluxes projected back to the coarse face nodes with R_m.
+  //      2D: inviscid into s_tro[..][0], viscous into s_tro[..][1] (the own sub-face traces
+  //      there are no longer needed).  3D: held in registers over a barrier, then written over
+  //      sub-face 0 of s_tr (inviscid) and s_trv (viscous).
+  constexpr int NE0 = (NFC * NV * NF + T - 1) / T;
+  double e0_fs[NE0], e0_fsv[NE0];
+  bool e0_has[NE0];
 #pragma unroll
-        for (int ms = 0; ms < 2; ++ms)
+  for (int k = 0; k < NE0; ++k) {
+    e0_has[k] = false;
+    e0_fs[k] = e0_fsv[k] = 0.0;
+    const int w = lane + k * T;
+    if (!act || w >= NFC * NV * NF) continue;
+    const int i = w % NF;
+    const int v = (w / NF) % NV;
+    const int f = w / (NF * NV);
+    if (face_kind(s_fk[le][f]) != kCoarseSide) continue;
+    double fs = 0.0, fsv = 0.0;
+    if (DIM == 2) {
 #pragma unroll
-          for (int k = 0; k < N; ++k) {
-            const double r = op.R[ms][i * N + k];
-            fs += r * s_tr[le][f][ms][v][k];
-            if (VISC) fsv += r * s_trv[le][f][ms][v][k];
+      for (int ms = 0; ms < 2; ++ms)
+#pragma unroll
+        for (int kk = 0; kk < N; ++kk) {
+          const double r = op.R[ms][i * N + kk];
+          fs += r * s_tr[le][f][ms][v][kk];
+          if (VISC) fsv += r * s_trv[le][f][ms][v][kk];
+        }
+    } else {
+      const int ia = i % N, ib = i / N;
+#pragma unroll
+      for (int ms = 0; ms < 4; ++ms) {
+        const int m0 = ms & 1, m1 = (ms >> 1) & 1;
+#pragma unroll
+        for (int kb = 0; kb < N; ++kb) {
+          double row = 0.0, rowv = 0.0;
+#pragma unroll
+          for (int ka = 0; ka < N; ++ka) {
+            const double r = op.R[m0][ia * N + ka];
+            row += r * s_tr[le][f][ms][v][ka + N * kb];
+            if (VISC) rowv += r * s_trv[le][f][ms][v][ka + N * kb];
           }
-      } else {
-        const int ia = i % N, ib = i / N;
-#pragma unroll
-        for (int ms = 0; ms < 4; ++ms) {
-          const int m0 = ms & 1, m1 = (ms >> 1) & 1;
-#pragma unroll
-          for (int kb = 0; kb < N; ++kb) {
-            double row = 0.0, rowv = 0.0;
-#pragma unroll
-            for (int ka = 0; ka < N; ++ka) {
-              const double r = op.R[m0][ia * N + ka];
-              row += r * s_tr[le][f][ms][v][ka + N * kb];
-              if (VISC) rowv += r * s_trv[le][f][ms][v][ka + N * kb];
-            }
-            const double rb = op.R[m1][ib * N + kb];
-            fs += rb * row;
-            if (VISC) fsv += rb * rowv;
-          }
+          const double rb = op.R[m1][ib * N + kb];
+          fs += rb * row;
+          if (VISC) fsv += rb * rowv;
         }
       }
+    }
+    if (LDS_OWN) {
       s_tro[le][f][0][v][i] = fs;
-      if (VISC) s_tro[le][f][1][v][i] = fsv;
+      if (VISC) s_tro[le][f][LDS_OWN ? 1 : 0][v][i] = fsv;
+    } else {
+      e0_has[k] = true;
+      e0_fs[k] = fs;
+      e0_fsv[k] = fsv;
+    }
+  }
+  if (!LDS_OWN) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NE0; ++k) {
+      if (!e0_has[k]) continue;
+      const int w = lane + k * T;
+      const int i = w % NF, v = (w / NF) % NV, f = w / (NF * NV);
+      s_tr[le][f][0][v][i] = e0_fs[k];
+      if (VISC) s_trv[le][f][0][v][i] = e0_fsv[k];
     }
   }
   __syncthreads();
@@ -518,7 +575,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         const int f = 2 * d + (pos == N - 1 ? 1 : 0);
         const int fi = face_index<DIM, N>(nd, d);
         double fs;
-        if (face_kind(s_fk[le][f]) == kCoarseSide) {
+        if (LDS_OWN && face_kind(s_fk[le][f]) == kCoarseSide) {
           fs = s_tro[le][f][0][v][fi];
         } else {
           fs = s_tr[le][f][0][v][fi];
@@ -529,17 +586,17 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       if (VISC) {
         double vacc = 0.0;
 #pragma unroll
-        for (int mm = 0; mm < N; ++mm) vacc += op.D[pos * N + mm] * s_fv[le][d][v][node_on_line<DIM, N>(d, line, mm)];
+        for (int mm = 0; mm < N; ++mm) vacc += op.D[pos * N + mm] * fv_own(d, v, node_on_line<DIM, N>(d, line, mm));
         if (pos == N - 1 || pos == 0) {
           const int f = 2 * d + (pos == N - 1 ? 1 : 0);
           const int fi = face_index<DIM, N>(nd, d);
           double fs;
-          if (face_kind(s_fk[le][f]) == kCoarseSide) {
-            fs = s_tro[le][f][1][v][fi];
+          if (LDS_OWN && face_kind(s_fk[le][f]) == kCoarseSide) {
+            fs = s_tro[le][f][LDS_OWN ? 1 : 0][v][fi];
           } else {
             fs = s_trv[le][f][0][v][fi];
           }
-          const double jump = fs - s_fv[le][d][v][nd];
+          const double jump = fs - fv_own(d, v, nd);
           vacc += pos == N - 1 ? iwN * jump : -iw0 * jump;
         }
         du += J[d] * vacc;

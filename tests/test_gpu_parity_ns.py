@@ -1,6 +1,7 @@
 """GPU vs oracle parity for compressible Navier-Stokes with BR1 (2D and 3D, 2:1 mortars),
 including the partitioned steps whose gradient pass covers the inactive face neighbours of the
-active elements, and the full 3D Taylor-Green mesh (7120 elements, p=3)."""
+active elements, the full 3D Taylor-Green mesh (7120 elements, p=3), and the inviscid 3D kernel
+on the same mortar mesh."""
 import json
 import os
 
@@ -84,6 +85,33 @@ def test_step_parity_ns(case, E, dt, n):
         u = o.prk_step(u, dt, fam, member)
     g = s.get_state().cpu().numpy()
     sig = flux_scale(o, u0)
+    assert state_close(g, u, sig, n, dt), worst(g, u, sig, n, dt)
+
+
+@pytest.mark.parametrize("N", [4, 3])
+def test_parity_euler_3d_mortar(N):
+    # the inviscid 3D kernel on the 2:1 mortar mesh (coarse elements with one and with two
+    # refined face neighbours): one right-hand side and two partitioned steps
+    from paper_2403_05144_amd import PerkSolver
+    mesh = _mesh3d_small()
+    o = od.Oracle(mesh, N)
+    u0 = _tgv(o)
+    fam = pc.perk2_family([4, 8])
+    lv = mesh.leaves[:, 0]
+    mol = od.member_of_levels_paper_rule(np.arange(lv.max() + 1), 2)
+    s = PerkSolver(mesh, N - 1, fam, mol)
+    du_gpu = s.rhs_leaf(u0).cpu().numpy()
+    du_ora = o.rhs(u0)
+    sig = flux_scale(o, u0)
+    assert rhs_ok(du_gpu, du_ora, sig), rel_err(du_gpu, du_ora)
+    dt, n = 1e-3, 2
+    s.set_state(u0)
+    s.step(dt, n)
+    u = u0.copy()
+    member = np.asarray(mol)[lv]
+    for _ in range(n):
+        u = o.prk_step(u, dt, fam, member)
+    g = s.get_state().cpu().numpy()
     assert state_close(g, u, sig, n, dt), worst(g, u, sig, n, dt)
 
 

@@ -53,6 +53,7 @@ struct pe_ctx {
   int32_t* d_plan = nullptr;            // AMR projection plan [capacity][10]
   double* d_eta = nullptr;              // AMR indicator per leaf; wave-speed bound per slot
   double* d_beta = nullptr;             // [kMaxLevels] largest (p+1)(|v_d|+c)/h_d per level
+  double* d_dmat = nullptr;             // [2][N^2] derivative tables (Ops::dD)
   unsigned long long* d_counter = nullptr;   // [R] folded totals
   int32_t* d_evals = nullptr;               // [capacity] per-slot evaluations since the last fold
   // partition
@@ -81,8 +82,17 @@ struct pe_ctx {
   size_t ev_used = 0;
   int64_t prof_launches = 0, prof_elem_stages = 0;
   double prof_ms = 0.0;
+  // pinned host staging of the adaptation's uploads and the indicator's download (grown on
+  // demand); `stage_ev` marks the end of the last transfer out of it still in flight
+  void* h_stage = nullptr;
+  size_t h_stage_cap = 0;
+  hipEvent_t stage_ev = nullptr;
+  bool stage_pending = false;
   std::string err;
   ~pe_ctx() {
+    if (stage_ev) (void)hipEventSynchronize(stage_ev);
+    if (h_stage) (void)hipHostFree(h_stage);
+    if (stage_ev) (void)hipEventDestroy(stage_ev);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -196,6 +206,32 @@ void make_ops(int N, Ops& op) {
 }
 
 // ---------------------------------------------------------------- forest connectivity
+// Pinned staging of at least `bytes`, free for the host to write: waits for the transfer still
+// reading from it, grows it (by half again) when too small.
+pe_status stage_reserve(pe_ctx* ctx, size_t bytes) {
+  if (ctx->stage_pending) {
+    HIPCHK(hipEventSynchronize(ctx->stage_ev));
+    ctx->stage_pending = false;
+  }
+  if (!ctx->stage_ev) HIPCHK(hipEventCreateWithFlags(&ctx->stage_ev, hipEventDisableTiming));
+  if (bytes <= ctx->h_stage_cap) return PE_OK;
+  if (ctx->h_stage) HIPCHK(hipHostFree(ctx->h_stage));
+  ctx->h_stage = nullptr;
+  ctx->h_stage_cap = 0;
+  const size_t cap = std::max(bytes + bytes / 2, (size_t)1 << 20);
+  HIPCHK(hipHostMalloc(&ctx->h_stage, cap, hipHostMallocDefault));
+  ctx->h_stage_cap = cap;
+  return PE_OK;
+}
+
+// Marks the transfers just enqueued on `s` out of the staging buffer.
+pe_status stage_mark(pe_ctx* ctx, hipStream_t s) {
+  HIPCHK(hipEventRecord(ctx->stage_ev, s));
+  ctx->stage_pending = true;
+  return PE_OK;
+}
+
+
 struct KeyHash {
   size_t operator()(uint64_t k) const { return std::hash<uint64_t>()(k * 0x9E3779B97F4A7C15ull); }
 };
@@ -381,6 +417,7 @@ size_t carve(pe_ctx* c, char* base) {
   c->d_plan = (int32_t*)take((size_t)n * 10 * 4);
   c->d_eta = (double*)take((size_t)n * 8);
   c->d_beta = (double*)take(kMaxLevels * 8);
+  c->d_dmat = (double*)take(2 * kMaxN * kMaxN * 8);
   return off;
 }
 
@@ -431,8 +468,10 @@ void fill_stage(const pe_ctx* c, int i, double dt, StageArgs& a) {
   a.use_acc_last = 0;
   for (int j = 0; j < c->S - 1; ++j)
     if (c->b[j] != 0.0) a.use_acc_last = 1;
+  a.read_acc = (a.acc_mode == 2 || (a.last && a.use_acc_last)) ? 1 : 0;
   for (int r = 0; r < c->R; ++r) {
     a.src[r] = i == 0 ? 0 : ((active(c, r, i) && active(c, r, i - 1)) ? 1 : 2);
+    a.src_bits |= a.src[r] << (2 * r);
     if (i + 1 < c->S) {
       a.wr[r] = active(c, r, i + 1) ? 1 : 0;
       a.a2[r] = c->a_sub[(size_t)r * c->S + i + 1];
@@ -591,6 +630,14 @@ pe_status pe_bind(pe_ctx* ctx, double* u_dev, void* ws, void* stream) {
   HIPCHK(hipMemcpyAsync(ctx->d_lev_leaf, ctx->lev_leaf.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(ctx->d_counter, 0, kMaxMembers * 8, s));
   HIPCHK(hipMemsetAsync(ctx->d_evals, 0, (size_t)cap_of(ctx) * 4, s));
+  const int N = ctx->N;
+  double dm[2 * kMaxN * kMaxN];
+  for (int i = 0; i < N * N; ++i) {
+    dm[i] = i / N == i % N ? 0.0 : 2.0 * ctx->ops.D[i];
+    dm[N * N + i] = ctx->ops.D[i];
+  }
+  HIPCHK(hipMemcpyAsync(ctx->d_dmat, dm, 2 * (size_t)N * N * 8, hipMemcpyHostToDevice, s));
+  ctx->ops.dD = ctx->d_dmat;
   ctx->pending_leaf_state = false;
   HIPCHK(hipStreamSynchronize(s));
   ctx->bound = true;
@@ -999,10 +1046,6 @@ pe_status enqueue_step(pe_ctx* ctx, double dt, hipStream_t s, bool timed) {
 // Capture one step into an executable graph (on a private stream of default priority).
 pe_status capture_step(pe_ctx* ctx, double dt) {
   if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
-  if (ctx->gexec) {
-    HIPCHK(hipGraphExecDestroy(ctx->gexec));
-    ctx->gexec = nullptr;
-  }
   HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
   pe_status st = enqueue_step(ctx, dt, ctx->cap_stream, false);
   hipGraph_t g = nullptr;
@@ -1012,6 +1055,21 @@ pe_status capture_step(pe_ctx* ctx, double dt) {
     return st;
   }
   HIPCHK(e);
+  if (ctx->gexec) {
+    // same launches with new sizes (after a re-partition): update the executable graph in
+    // place, which costs less than instantiating a new one; otherwise replace it
+    hipGraphNode_t err_node = nullptr;
+    hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+    if (hipGraphExecUpdate(ctx->gexec, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+      (void)hipGraphDestroy(g);
+      ctx->graph_valid = true;
+      ctx->graph_dt = dt;
+      return PE_OK;
+    }
+    (void)hipGetLastError();
+    HIPCHK(hipGraphExecDestroy(ctx->gexec));
+    ctx->gexec = nullptr;
+  }
   e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   HIPCHK(e);
@@ -1077,8 +1135,12 @@ pe_status pe_amr_indicator(pe_ctx* ctx, double* eta_leaf, void* stream) {
   Mesh m = device_mesh(ctx);
   HIPCHK(launch_indicator(ctx->dim, ctx->N, ctx->n_e, (int)cap_of(ctx), ctx->d_slot_of_leaf, ctx->d_lev_leaf, ctx->U,
                           ctx->ops, m, ctx->d_eta, s));
-  HIPCHK(hipMemcpyAsync(eta_leaf, ctx->d_eta, (size_t)ctx->n_e * 8, hipMemcpyDeviceToHost, s));
+  const size_t bytes = (size_t)ctx->n_e * 8;
+  pe_status st = stage_reserve(ctx, bytes);
+  if (st != PE_OK) return st;
+  HIPCHK(hipMemcpyAsync(ctx->h_stage, ctx->d_eta, bytes, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  std::memcpy(eta_leaf, ctx->h_stage, bytes);
   return PE_OK;
 }
 
@@ -1229,9 +1291,18 @@ pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags, int level_min, int level_ma
   std::vector<std::pair<uint64_t, int32_t>> order(nl.size());
   for (size_t i = 0; i < nl.size(); ++i) order[i] = {morton_key(nl[i].L.data(), dim), (int32_t)i};
   std::sort(order.begin(), order.end());
-  std::vector<int32_t> plan(nl.size() * 10);
-  std::vector<int32_t> leaves(nl.size() * 4);
-  for (size_t i = 0; i < nl.size(); ++i) {
+  // uploads through the pinned staging buffer: the plan now, the connectivity after it is built
+  const size_t nn_new = nl.size();
+  const size_t plan_bytes = align256(nn_new * 40), fk_bytes = align256(nn_new * nf * 4);
+  const size_t fn_bytes = align256(nn_new * nf * 16), lev_bytes = align256(nn_new * 4);
+  {
+    pe_status st = stage_reserve(ctx, plan_bytes + fk_bytes + fn_bytes + lev_bytes);
+    if (st != PE_OK) return st;
+  }
+  char* const stage = static_cast<char*>(ctx->h_stage);
+  int32_t* plan = reinterpret_cast<int32_t*>(stage);
+  std::vector<int32_t> leaves(nn_new * 4);
+  for (size_t i = 0; i < nn_new; ++i) {
     const NewLeaf& x = nl[(size_t)order[i].second];
     std::memcpy(&plan[i * 10], x.plan.data(), 40);
     std::memcpy(&leaves[i * 4], x.L.data(), 16);
@@ -1240,7 +1311,11 @@ pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags, int level_min, int level_ma
   // evaluation counts of the old partition into the per-member totals
   HIPCHK(launch_fold_evals(ctx->n_e, device_mesh(ctx), ctx->d_evals, ctx->d_counter, s));
   // project the old state (slot layout, old slot map) onto the new leaves (leaf layout, in Tmp)
-  HIPCHK(hipMemcpyAsync(ctx->d_plan, plan.data(), plan.size() * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->d_plan, plan, nn_new * 40, hipMemcpyHostToDevice, s));
+  {
+    pe_status st = stage_mark(ctx, s);
+    if (st != PE_OK) return st;
+  }
   HIPCHK(launch_project(dim, ctx->N, (int)nl.size(), (int)cap_of(ctx), ctx->d_plan, ctx->d_slot_of_leaf, ctx->U,
                         ctx->ops, ctx->Tmp, s));
   // new forest
@@ -1257,10 +1332,19 @@ pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags, int level_min, int level_ma
     return st;
   }
   const int nn = ctx->n_e;
-  HIPCHK(hipMemcpyAsync(ctx->d_fk_leaf, ctx->fk_leaf.data(), (size_t)nn * nf * 4, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(ctx->d_fn_leaf, ctx->fn_leaf.data(), (size_t)nn * nf * 16, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(ctx->d_lev_leaf, ctx->lev_leaf.data(), (size_t)nn * 4, hipMemcpyHostToDevice, s));
-  HIPCHK(hipStreamSynchronize(s));
+  // the staging region after the plan is not read by the plan copy still in flight
+  char* const up = stage + plan_bytes;
+  std::memcpy(up, ctx->fk_leaf.data(), (size_t)nn * nf * 4);
+  std::memcpy(up + fk_bytes, ctx->fn_leaf.data(), (size_t)nn * nf * 16);
+  std::memcpy(up + fk_bytes + fn_bytes, ctx->lev_leaf.data(), (size_t)nn * 4);
+  HIPCHK(hipMemcpyAsync(ctx->d_fk_leaf, up, (size_t)nn * nf * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->d_fn_leaf, up + fk_bytes, (size_t)nn * nf * 16, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->d_lev_leaf, up + fk_bytes + fn_bytes, (size_t)nn * 4, hipMemcpyHostToDevice, s));
+  {
+    pe_status st2 = stage_mark(ctx, s);
+    if (st2 != PE_OK) return st2;
+  }
+  // no wait here: what follows on the host reads only host data, the device work is in order
   ctx->partitioned = false;
   ctx->graph_valid = false;
   ctx->state_valid = false;

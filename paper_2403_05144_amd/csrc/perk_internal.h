@@ -28,6 +28,10 @@ struct Ops {
   double P[2][kMaxN * kMaxN];       // mortar interpolation to the lower/upper half
   double R[2][kMaxN * kMaxN];       // mortar projection 1/2 M^{-1} P^T M
   double x[kMaxN];                  // nodes on [-1, 1]
+  // device copy (caller's workspace, written at bind): [0, N^2) 2 D with a zero diagonal,
+  // [N^2, 2 N^2) D.  Lane-indexed reads of the tables above come from kernel-argument memory,
+  // which is far slower than this L2-resident copy.
+  const double* dD;
 };
 
 struct Physics {
@@ -48,10 +52,13 @@ struct Mesh {
   double jac[kMaxLevels][3];   // 2 / h per level and direction
 };
 
-// Member of a slot from the partition boundaries (slots are sorted by member).
+// Member of a slot from the partition boundaries (slots are sorted by member, so the boundaries
+// are non-decreasing and the slot lies past a prefix of them).  Counted without an early exit:
+// the boundaries are then read together instead of one dependent read per member.
 __host__ __device__ inline int member_of_slot(const Mesh& m, int s) {
   int k = 0;
-  while (k < m.R - 1 && s >= m.bnd[k]) ++k;
+#pragma unroll
+  for (int j = 0; j < kMaxMembers - 1; ++j) k += (j < m.R - 1 && s >= m.bnd[j]) ? 1 : 0;
   return m.R - 1 - k;
 }
 
@@ -79,10 +86,14 @@ struct StageArgs {
   int acc_mode;           // 0: nothing, 1: ACC = b_i K, 2: ACC += b_i K
   int use_acc_last;       // last stage adds ACC
   int src[kMaxMembers];   // where Y_i of a member comes from: 0 U_n, 1 Yin, 2 U_n + dt c_i K_1
+  int src_bits;           // the same codes, two bits per member (member r at bits 2r, 2r+1)
+  int read_acc;           // the epilogue reads ACC (acc_mode 2, or the last stage with use_acc_last)
   int wr[kMaxMembers];    // member writes Y_{i+1}
   double a1[kMaxMembers]; // a_{i+1,1}
   double a2[kMaxMembers]; // a_{i+1,i}
 };
+
+__host__ __device__ inline int src_of(const StageArgs& a, int member) { return (a.src_bits >> (2 * member)) & 3; }
 
 // Arguments of the adjoint right-hand-side kernel: the stage state of every slot (as in the
 // stage kernel: src 0 U_n, 1 Yin, 2 U_n + dt c_i K_1), the cotangent W of the slots [0, n_w)

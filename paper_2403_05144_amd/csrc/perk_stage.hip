@@ -211,6 +211,11 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   // BR1: own viscous flux at every node (2D) and the neighbours' viscous face traces
   __shared__ double s_fv[FVL ? EPB : 1][FVL ? DIM : 1][FVL ? NV : 1][FVL ? ND : 1];
   __shared__ double s_trv[VISC ? EPB : 1][VISC ? NFC : 1][VISC ? NSUB : 1][VISC ? NV : 1][VISC ? NF : 1];
+  // the derivative matrix: the epilogue reads row `pos` of the lane's node, which from kernel
+  // argument memory would be a gather with a memory round after the last barrier.  s_D2 holds
+  // 2 D with a zero diagonal (the flux-differencing weights, no pair (i, i)), s_D plain D (BR1)
+  __shared__ double s_D2[N * N];
+  __shared__ double s_D[VISC ? N * N : 1];
 
   const int le = threadIdx.x / T;
   const int lane = threadIdx.x - le * T;
@@ -231,7 +236,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   constexpr int NTR = (NTRI + T - 1) / T;                // per lane
   int my_mem = 0, my_src = 0;
   double J[DIM];
-  double un[NITEM], k1[NITEM];
+  double un[NITEM], k1[NITEM], acc[NITEM];
   if (act) {
     my_mem = member_of_slot(m, e);
     my_src = a.src[my_mem];
@@ -260,6 +265,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         un[it] = a.U[idx];
         // K_1 exists only after the first stage of a step; right-hand-side launches never read it
         k1[it] = (a.first || a.Kout) ? 0.0 : a.K1[idx];
+        acc[it] = a.read_acc ? a.ACC[idx] : 0.0;
         own[it] = my_src == 0 ? un[it] : (my_src == 1 ? a.Yin[idx] : un[it] + a.dt * a.ci * k1[it]);
       }
     }
@@ -292,11 +298,21 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       const int w = lane + it * T;
       if (w < NV * ND) s_u[le][w / ND][w % ND] = own[it];
     }
-    if (lane == 0 && a.evals) a.evals[e] += 1;   // each slot belongs to exactly one block
+    if (lane == 0 && a.evals) atomicAdd(&a.evals[e], 1);
   }
   __syncthreads();
 
   // ---- C: node quantities; fine sides: coarse trace interpolated into sub-slot 1
+  // The derivative tables for the epilogue come in on the block's last lanes: in split and 3D
+  // blocks a wave with little to do here, so that the load stays off the node-quantity wave.
+  {
+    const int t = (int)threadIdx.x - (T * EPB - 2 * N * N);
+    if (t >= 0) {
+      const double dv = op.dD[t];
+      if (t < N * N) s_D2[t] = dv;
+      else if (VISC) s_D[t - N * N] = dv;
+    }
+  }
   if (act) {
     for (int w = lane; w < ND; w += T) {
       double uu[NV];
@@ -564,41 +580,27 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       int line, pos;
       line_of<DIM, N>(nd, d, line, pos);
       const int base = (d * K::NLINE + line) * NPL;
+      // branch-free: every lane reads an operand for every term and weighs the terms that do
+      // not apply by zero (the pair (pos, pos) reads pair 0 of the line; interior nodes read
+      // the flux of face 2d), so that the reads issue together instead of one branch at a time
       double acc = 0.0;
 #pragma unroll
       for (int mm = 0; mm < N; ++mm) {
-        if (mm == pos) continue;
-        const int pi = mm > pos ? pair_index<N>(pos, mm) : pair_index<N>(mm, pos);
-        acc += 2.0 * op.D[pos * N + mm] * s_pf[le][base + pi][v];
+        const int pi = mm == pos ? 0 : (mm > pos ? pair_index<N>(pos, mm) : pair_index<N>(mm, pos));
+        acc += s_D2[pos * N + mm] * s_pf[le][base + pi][v];
       }
-      if (pos == N - 1 || pos == 0) {
-        const int f = 2 * d + (pos == N - 1 ? 1 : 0);
-        const int fi = face_index<DIM, N>(nd, d);
-        double fs;
-        if (LDS_OWN && face_kind(s_fk[le][f]) == kCoarseSide) {
-          fs = s_tro[le][f][0][v][fi];
-        } else {
-          fs = s_tr[le][f][0][v][fi];
-        }
-        acc += pos == N - 1 ? iwN * fs : -iw0 * fs;
-      }
+      const int f = 2 * d + (pos == N - 1 ? 1 : 0);
+      const int fi = face_index<DIM, N>(nd, d);
+      const bool coarse = LDS_OWN && face_kind(s_fk[le][f]) == kCoarseSide;
+      const double lift = pos == N - 1 ? iwN : (pos == 0 ? -iw0 : 0.0);
+      acc += lift * (coarse ? s_tro[le][f][0][v][fi] : s_tr[le][f][0][v][fi]);
       du -= J[d] * acc;
       if (VISC) {
         double vacc = 0.0;
 #pragma unroll
-        for (int mm = 0; mm < N; ++mm) vacc += op.D[pos * N + mm] * fv_own(d, v, node_on_line<DIM, N>(d, line, mm));
-        if (pos == N - 1 || pos == 0) {
-          const int f = 2 * d + (pos == N - 1 ? 1 : 0);
-          const int fi = face_index<DIM, N>(nd, d);
-          double fs;
-          if (LDS_OWN && face_kind(s_fk[le][f]) == kCoarseSide) {
-            fs = s_tro[le][f][LDS_OWN ? 1 : 0][v][fi];
-          } else {
-            fs = s_trv[le][f][0][v][fi];
-          }
-          const double jump = fs - fv_own(d, v, nd);
-          vacc += pos == N - 1 ? iwN * jump : -iw0 * jump;
-        }
+        for (int mm = 0; mm < N; ++mm) vacc += s_D[pos * N + mm] * fv_own(d, v, node_on_line<DIM, N>(d, line, mm));
+        const double fs = coarse ? s_tro[le][f][LDS_OWN ? 1 : 0][v][fi] : s_trv[le][f][0][v][fi];
+        vacc += lift * (fs - fv_own(d, v, nd));
         du += J[d] * vacc;
       }
     }
@@ -610,9 +612,9 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
     const double K1v = a.first ? du : k1[it];
     if (a.first) a.K1[idx] = du;
     if (a.acc_mode == 1) a.ACC[idx] = a.bi * du;
-    else if (a.acc_mode == 2) a.ACC[idx] = a.ACC[idx] + a.bi * du;
+    else if (a.acc_mode == 2) a.ACC[idx] = acc[it] + a.bi * du;
     if (a.last) {
-      const double inc = a.use_acc_last ? a.ACC[idx] + a.bS * du : a.bS * du;
+      const double inc = a.use_acc_last ? (a.acc_mode == 0 ? acc[it] : a.ACC[idx]) + a.bS * du : a.bS * du;
       a.Uout[idx] = un[it] + a.dt * inc;
     } else if (a.wr[my_mem]) {
       a.Yout[idx] = un[it] + a.dt * (a.a1[my_mem] * K1v + a.a2[my_mem] * du);
@@ -707,7 +709,7 @@ __global__ __launch_bounds__((GKc<DIM, N>::T)) void k_grad(StageArgs a, Mesh m, 
   const int lane = threadIdx.x;
   const int ld = m.ld;
   const double gamma = ph.gamma;
-  const int my_src = a.src[member_of_slot(m, e)];
+  const int my_src = src_of(a, member_of_slot(m, e));
   const int lev = m.lev[e];
   if (lane < NFC) s_fk[lane] = m.fk[(int64_t)e * NFC + lane];
   if (lane < NFC * 4) s_fn[lane / 4][lane % 4] = m.fn[(int64_t)e * NFC * 4 + lane];
@@ -729,7 +731,7 @@ __global__ __launch_bounds__((GKc<DIM, N>::T)) void k_grad(StageArgs a, Mesh m, 
     if (sub > 0 && kind != kCoarseSide) continue;
     const int nb = s_fn[f][sub];
     const int d = f >> 1, side = f & 1;
-    const int src = a.src[member_of_slot(m, nb)];
+    const int src = src_of(a, member_of_slot(m, nb));
     const int nn = face_node<DIM, N>(d, 1 - side, j);
     double u[NV], w[NW];
 #pragma unroll

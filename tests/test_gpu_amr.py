@@ -95,3 +95,35 @@ def test_adapt_rejects_over_capacity():
     # the mesh is unchanged and still steps
     assert s.n_elements == 16
     s.step(1e-4, 1)
+
+
+def test_graph_replay_across_adaptations_equals_eager():
+    # after every re-partition the captured step is updated in place (same launches, new sizes)
+    # or re-instantiated; stepping by graph replay and by eager launches must give bitwise the
+    # same leaves and states through several adaptation cycles
+    from paper_2403_05144_amd import PerkSolver
+    from paper_2403_05144_amd.amr import AmrDriver
+    fam = golden_family("perk3_4_6_8_12_16_disk.json")
+    lmax = 3
+    mol = [max(0, 4 - (lmax - l)) for l in range(lmax + 1)]
+
+    def ic_leaf(x):
+        return pin.kelvin_helmholtz(x[:, 0], x[:, 1]).transpose(1, 0, 2).copy()
+
+    runs = []
+    for graphs in (True, False):
+        s = PerkSolver(pin.uniform_mesh(2, (8, 8), (-1, -1), (1, 1), 0), 3, fam, mol, capacity=4096)
+        s.set_graph_replay(graphs)
+        drv = AmrDriver(s, 0, lmax, mol, 0.05, 0.01, 3)
+        drv.initial_mesh(ic_leaf, passes=2)
+        states = []
+        for _ in range(4):
+            s.step(2e-4, 3)
+            states.append(s.get_state().cpu().numpy())
+            drv.adapt_once()
+            states.append(s.get_state().cpu().numpy())
+        states.append(s.leaves().copy())
+        runs.append(states)
+    assert runs[0][-1].shape == runs[1][-1].shape
+    for a, b in zip(runs[0], runs[1]):
+        np.testing.assert_array_equal(a, b)

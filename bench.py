@@ -698,10 +698,11 @@ def flops_per_element_stage(dim, N):
     return nd * per_node + 2 * dim * N ** (dim - 1) * hll
 
 
-def bytes_per_element_stage(dim, N):
+def bytes_per_element_stage(dim, N, viscous=False):
     """Algorithmic HBM bytes of one element-stage: read the stage value, U_n and K_1 and write
-    the next stage value of the element (4 element slices of n_v N^d fp64)."""
-    return 4 * (dim + 2) * N ** dim * 8
+    the next stage value of the element (4 element slices of n_v N^d fp64); Navier-Stokes also
+    reads the element's BR1 viscous flux, written by the gradient kernel (dim slices)."""
+    return (4 + (dim if viscous else 0)) * (dim + 2) * N ** dim * 8
 
 
 def measured_traffic(workload, es_per_launch):
@@ -847,7 +848,7 @@ def run(args):
     pid = wall / n_rhs_actual
     avg_launch_s = kern_ms * 1e-3 / max(1, launches)
     es_per_launch = elem_stages / max(1, launches)
-    B = bytes_per_element_stage(mesh.dim, N) * es_per_launch
+    B = bytes_per_element_stage(mesh.dim, N, wl.get("equations", 0) == 1) * es_per_launch
     F = flops_per_element_stage(mesh.dim, N) * es_per_launch
     gbs = B / avg_launch_s / 1e9
     tflops = F / avg_launch_s / 1e12

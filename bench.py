@@ -303,8 +303,13 @@ def run_adjoint(args):
         return float(kinetic_energy(s, s.u, ws))
 
     J_of(m0)                                          # warm-up (graph capture)
-    u0 = s.to_slot(u0_of(m0)).requires_grad_(True)
     s.enable_adjoint()
+    # warm-up of the reverse sweep too (first launches of its kernels, autograd set-up): one
+    # checkpoint interval forward and back, untimed
+    uw = s.to_slot(u0_of(m0)).requires_grad_(True)
+    kinetic_energy(s, trajectory(uw, s, dt, every, every), ws).backward()
+    del uw
+    u0 = s.to_slot(u0_of(m0)).requires_grad_(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     uN = trajectory(u0, s, dt, n, every)

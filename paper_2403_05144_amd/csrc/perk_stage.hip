@@ -288,7 +288,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   double un[NITEM], k1[NITEM], acc[NITEM];
   if (act) {
     my_mem = member_of_slot(m, e);
-    my_src = a.src[my_mem];
+    my_src = src_of(a, my_mem);   // (a shift of one argument word, not an indexed argument load)
     int tr_nb[NTR], tr_pk[NTR];
 #pragma unroll
     for (int it = 0; it < NTR; ++it) {
@@ -329,7 +329,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       if (sub > 0 && face_kind(tr_pk[it]) != kCoarseSide) continue;
       const int nb = tr_nb[it];
       const int d = f >> 1, side = f & 1;
-      const int src = a.src[member_of_slot(m, nb)];
+      const int src = src_of(a, member_of_slot(m, nb));
       const int nn = face_node<DIM, N>(d, 1 - side, j);
       s_tr[le][f][sub][v][j] = stage_value(a, src, ((int64_t)v * ld + nb) * ND + nn);
       if (VISC) s_trv[le][f][sub][v][j] = a.Fv[(((int64_t)d * NV + v) * ld + nb) * ND + nn];
@@ -682,7 +682,10 @@ template <int DIM, int N, bool VISC, bool SPLIT>
 __global__ __launch_bounds__((SK<DIM, N, SPLIT>::T * SK<DIM, N, SPLIT>::EPB), (SK<DIM, N, SPLIT>::MINW)) void k_stage(StageArgs a, Mesh m, Ops op, Physics ph) {
   // Workgroups go to the 8 XCDs round-robin (block b to XCD b mod 8); give XCD x the
   // contiguous block range [x G, (x+1) G), G = gridDim / 8, so that neighbouring slots (sorted
-  // by member, Morton order inside) share an L2 and neighbour-trace reads can hit there.
+  // by member, Morton order inside) share an L2 and neighbour-trace reads can hit there.  (A
+  // mapping that keeps each slot on one XCD in every launch, in chunks of 16 blocks, fetched
+  // 20 % more from beyond L2: within a launch the neighbours matter, across launches the L2
+  // does not keep a slot's data.)
   const int g8 = (int)gridDim.x >> 3;
   const int b = (int)blockIdx.x;
   stage_block<DIM, N, VISC, SK<DIM, N, SPLIT>::EPB, SPLIT>(a, m, op, ph, (b & 7) * g8 + (b >> 3));

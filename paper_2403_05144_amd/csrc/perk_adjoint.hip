@@ -225,7 +225,7 @@ __global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, 
   __syncthreads();
 
   // ---- D: pull-backs through the local flux Jacobians, one flux per lane
-  const double iw0 = 1.0 / op.w[0], iwN = 1.0 / op.w[N - 1];
+  const double iw0 = op.iw[0], iwN = op.iw[N - 1];
   for (int w = lane; w < NP + NSUB * NFC * NF; w += T) {
     if (w < NP) {
       const int pl = w % NPL;

@@ -187,6 +187,7 @@ void make_ops(int N, Ops& op) {
   }
   for (int j = 0; j < N; ++j) {
     op.w[j] = w[j];
+    op.iw[j] = 1.0 / w[j];
     op.x[j] = x[j];
   }
   // mortar operators: P_m[j][k] = l_k((x_j -/+ 1)/2), R_m[j][k] = 1/2 P_m[k][j] w_k / w_j

@@ -25,6 +25,7 @@ __host__ __device__ inline int face_sub1(int32_t f) { return (f >> 3) & 1; }
 struct Ops {
   double D[kMaxN * kMaxN];          // D[i*N + j] = l_j'(x_i)
   double w[kMaxN];                  // quadrature weights
+  double iw[kMaxN];                 // 1 / w (host division, the same correctly rounded value)
   double P[2][kMaxN * kMaxN];       // mortar interpolation to the lower/upper half
   double R[2][kMaxN * kMaxN];       // mortar projection 1/2 M^{-1} P^T M
   double x[kMaxN];                  // nodes on [-1, 1]

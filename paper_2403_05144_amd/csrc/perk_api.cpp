@@ -53,7 +53,7 @@ struct pe_ctx {
   int32_t* d_plan = nullptr;            // AMR projection plan [capacity][10]
   double* d_eta = nullptr;              // AMR indicator per leaf; wave-speed bound per slot
   double* d_beta = nullptr;             // [kMaxLevels] largest (p+1)(|v_d|+c)/h_d per level
-  double* d_dmat = nullptr;             // [2][N^2] derivative tables (Ops::dD)
+  double* d_dmat = nullptr;             // [6][N^2] operator tables (Ops::dD)
   unsigned long long* d_counter = nullptr;   // [R] folded totals
   int32_t* d_evals = nullptr;               // [capacity] per-slot evaluations since the last fold
   // partition
@@ -418,7 +418,7 @@ size_t carve(pe_ctx* c, char* base) {
   c->d_plan = (int32_t*)take((size_t)n * 10 * 4);
   c->d_eta = (double*)take((size_t)n * 8);
   c->d_beta = (double*)take(kMaxLevels * 8);
-  c->d_dmat = (double*)take(2 * kMaxN * kMaxN * 8);
+  c->d_dmat = (double*)take(6 * kMaxN * kMaxN * 8);
   return off;
 }
 
@@ -632,12 +632,16 @@ pe_status pe_bind(pe_ctx* ctx, double* u_dev, void* ws, void* stream) {
   HIPCHK(hipMemsetAsync(ctx->d_counter, 0, kMaxMembers * 8, s));
   HIPCHK(hipMemsetAsync(ctx->d_evals, 0, (size_t)cap_of(ctx) * 4, s));
   const int N = ctx->N;
-  double dm[2 * kMaxN * kMaxN];
+  double dm[6 * kMaxN * kMaxN];
   for (int i = 0; i < N * N; ++i) {
     dm[i] = i / N == i % N ? 0.0 : 2.0 * ctx->ops.D[i];
     dm[N * N + i] = ctx->ops.D[i];
+    for (int mm = 0; mm < 2; ++mm) {
+      dm[(2 + mm) * N * N + i] = ctx->ops.P[mm][i];
+      dm[(4 + mm) * N * N + i] = ctx->ops.R[mm][i];
+    }
   }
-  HIPCHK(hipMemcpyAsync(ctx->d_dmat, dm, 2 * (size_t)N * N * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->d_dmat, dm, 6 * (size_t)N * N * 8, hipMemcpyHostToDevice, s));
   ctx->ops.dD = ctx->d_dmat;
   ctx->pending_leaf_state = false;
   HIPCHK(hipStreamSynchronize(s));

@@ -30,8 +30,8 @@ struct Ops {
   double R[2][kMaxN * kMaxN];       // mortar projection 1/2 M^{-1} P^T M
   double x[kMaxN];                  // nodes on [-1, 1]
   // device copy (caller's workspace, written at bind): [0, N^2) 2 D with a zero diagonal,
-  // [N^2, 2 N^2) D.  Lane-indexed reads of the tables above come from kernel-argument memory,
-  // which is far slower than this L2-resident copy.
+  // [N^2, 2 N^2) D, then P[0], P[1], R[0], R[1] (N^2 each).  Lane-indexed reads of the tables
+  // above come from kernel-argument memory, which is far slower than this L2-resident copy.
   const double* dD;
 };
 

@@ -790,6 +790,9 @@ __global__ __launch_bounds__((GKc<DIM, N>::T)) void k_grad(StageArgs a, Mesh m, 
   __shared__ double s_q[DIM][NW][ND];
   __shared__ int s_fk[NFC];
   __shared__ int s_fn[NFC][4];
+  // D, P_0, P_1, R_0, R_1 from the device copy (lane-indexed reads from kernel-argument memory
+  // would each be a slow memory round)
+  __shared__ double s_op[5][N * N];
   const int b = blockIdx.x;
   const int e = b < a.n_act ? b : a.halo[b - a.n_act];
   const int lane = threadIdx.x;
@@ -807,6 +810,7 @@ __global__ __launch_bounds__((GKc<DIM, N>::T)) void k_grad(StageArgs a, Mesh m, 
 #pragma unroll
     for (int k = 0; k < NW; ++k) s_w[k][nd] = w[k];
   }
+  for (int t = lane; t < 5 * N * N; t += T) s_op[t / (N * N)][t % (N * N)] = op.dD[N * N + t];
   __syncthreads();
   // neighbour traces, converted to w at the trace node
   for (int it = lane; it < NSUB * NFC * NF; it += T) {
@@ -836,15 +840,15 @@ __global__ __launch_bounds__((GKc<DIM, N>::T)) void k_grad(StageArgs a, Mesh m, 
     double val = 0.0;
     if (DIM == 2) {
 #pragma unroll
-      for (int q = 0; q < N; ++q) val += op.P[s0][j * N + q] * s_tr[f][0][k][q];
+      for (int q = 0; q < N; ++q) val += s_op[1 + s0][j * N + q] * s_tr[f][0][k][q];
     } else {
       const int ja = j % N, jb = j / N;
 #pragma unroll
       for (int kb = 0; kb < N; ++kb) {
         double row = 0.0;
 #pragma unroll
-        for (int ka = 0; ka < N; ++ka) row += op.P[s0][ja * N + ka] * s_tr[f][0][k][ka + N * kb];
-        val += op.P[s1][jb * N + kb] * row;
+        for (int ka = 0; ka < N; ++ka) row += s_op[1 + s0][ja * N + ka] * s_tr[f][0][k][ka + N * kb];
+        val += s_op[1 + s1][jb * N + kb] * row;
       }
     }
     s_tr[f][1][k][j] = val;
@@ -866,15 +870,15 @@ __global__ __launch_bounds__((GKc<DIM, N>::T)) void k_grad(StageArgs a, Mesh m, 
         own = 0.0;
         if (DIM == 2) {
 #pragma unroll
-          for (int q = 0; q < N; ++q) own += op.P[m0][j * N + q] * s_w[k][face_node<DIM, N>(d, side, q)];
+          for (int q = 0; q < N; ++q) own += s_op[1 + m0][j * N + q] * s_w[k][face_node<DIM, N>(d, side, q)];
         } else {
           const int ja = j % N, jb = j / N;
 #pragma unroll
           for (int kb = 0; kb < N; ++kb) {
             double row = 0.0;
 #pragma unroll
-            for (int ka = 0; ka < N; ++ka) row += op.P[m0][ja * N + ka] * s_w[k][face_node<DIM, N>(d, side, ka + N * kb)];
-            own += op.P[m1][jb * N + kb] * row;
+            for (int ka = 0; ka < N; ++ka) row += s_op[1 + m0][ja * N + ka] * s_w[k][face_node<DIM, N>(d, side, ka + N * kb)];
+            own += s_op[1 + m1][jb * N + kb] * row;
           }
         }
       } else {
@@ -893,7 +897,7 @@ __global__ __launch_bounds__((GKc<DIM, N>::T)) void k_grad(StageArgs a, Mesh m, 
     line_of<DIM, N>(nd, d, line, pos);
     double acc = 0.0;
 #pragma unroll
-    for (int mm = 0; mm < N; ++mm) acc += op.D[pos * N + mm] * s_w[k][node_on_line<DIM, N>(d, line, mm)];
+    for (int mm = 0; mm < N; ++mm) acc += s_op[0][pos * N + mm] * s_w[k][node_on_line<DIM, N>(d, line, mm)];
     if (pos == N - 1 || pos == 0) {
       const int f = 2 * d + (pos == N - 1 ? 1 : 0);
       const int fi = face_index<DIM, N>(nd, d);
@@ -904,7 +908,7 @@ __global__ __launch_bounds__((GKc<DIM, N>::T)) void k_grad(StageArgs a, Mesh m, 
 #pragma unroll
           for (int ms = 0; ms < 2; ++ms)
 #pragma unroll
-            for (int q = 0; q < N; ++q) ws += op.R[ms][fi * N + q] * s_tr[f][ms][k][q];
+            for (int q = 0; q < N; ++q) ws += s_op[3 + ms][fi * N + q] * s_tr[f][ms][k][q];
         } else {
           const int ja = fi % N, jb = fi / N;
 #pragma unroll
@@ -914,8 +918,8 @@ __global__ __launch_bounds__((GKc<DIM, N>::T)) void k_grad(StageArgs a, Mesh m, 
             for (int kb = 0; kb < N; ++kb) {
               double row = 0.0;
 #pragma unroll
-              for (int ka = 0; ka < N; ++ka) row += op.R[m0][ja * N + ka] * s_tr[f][ms][k][ka + N * kb];
-              ws += op.R[m1][jb * N + kb] * row;
+              for (int ka = 0; ka < N; ++ka) row += s_op[3 + m0][ja * N + ka] * s_tr[f][ms][k][ka + N * kb];
+              ws += s_op[3 + m1][jb * N + kb] * row;
             }
           }
         }

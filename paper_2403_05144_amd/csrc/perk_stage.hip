@@ -297,6 +297,14 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   // 2 D with a zero diagonal (the flux-differencing weights, no pair (i, i)), s_D plain D (BR1)
   __shared__ double s_D2[N * N];
   __shared__ double s_D[VISC ? N * N : 1];
+  // 3D: the mortar operators P_0, P_1, R_0, R_1 too (coarse/fine faces are common in 3D
+  // refinement zones, and their lane-indexed reads from kernel-argument memory are slow); all
+  // six tables come in on the block's last wave in phase A.  2D reads P and R from the kernel
+  // arguments (only mortar blocks do, and they are not the slowest blocks of a launch).
+  constexpr bool OPS_A = DIM == 3;
+  __shared__ double s_PR[OPS_A ? 4 : 1][OPS_A ? N * N : 1];
+  auto Pm = [&](int mm, int idx) -> double { return OPS_A ? s_PR[mm][idx] : op.P[mm][idx]; };
+  auto Rm = [&](int mm, int idx) -> double { return OPS_A ? s_PR[2 + mm][idx] : op.R[mm][idx]; };
 
   const int le = threadIdx.x / T;
   const int lane = threadIdx.x - le * T;
@@ -315,6 +323,16 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   //      together; one barrier before the node quantities
   constexpr int NTRI = NSUB * NFC * NV * NF;             // trace items of the element
   constexpr int NTR = (NTRI + T - 1) / T;                // per lane
+  constexpr int TB = T * EPB, L0 = TB > 64 ? TB - 64 : 0;   // the block's last wave: [L0, TB)
+  constexpr int NTAB = 6 * N * N, NTL = (NTAB + (TB - L0) - 1) / (TB - L0);
+  double tab[OPS_A ? NTL : 1];
+  if (OPS_A) {
+#pragma unroll
+    for (int k = 0; k < NTL; ++k) {
+      const int t = (int)threadIdx.x - L0 + k * (TB - L0);
+      tab[k] = op.dD[t >= 0 && t < NTAB ? t : 0];
+    }
+  }
   int my_mem = 0, my_src = 0;
   double J[DIM];
   double un[NITEM], k1[NITEM], acc[NITEM];
@@ -381,12 +399,23 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
     }
     if (lane == 0 && a.evals) atomicAdd(&a.evals[e], 1);
   }
+  if (OPS_A) {
+#pragma unroll
+    for (int k = 0; k < NTL; ++k) {
+      const int t = (int)threadIdx.x - L0 + k * (TB - L0);
+      if (t < 0 || t >= NTAB) continue;
+      const int tb = t / (N * N), ti = t % (N * N);
+      if (tb == 0) s_D2[ti] = tab[k];
+      else if (tb == 1) { if (VISC) s_D[ti] = tab[k]; }
+      else s_PR[tb - 2][ti] = tab[k];
+    }
+  }
   __syncthreads();
 
   // ---- C: node quantities; fine sides: coarse trace interpolated into sub-slot 1
   // The derivative tables for the epilogue come in on the block's last lanes: in split and 3D
   // blocks a wave with little to do here, so that the load stays off the node-quantity wave.
-  {
+  if (!OPS_A) {
     const int t = (int)threadIdx.x - (T * EPB - 2 * N * N);
     if (t >= 0) {
       const double dv = op.dD[t];
@@ -418,15 +447,15 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       double val = 0.0;
       if (DIM == 2) {
 #pragma unroll
-        for (int k = 0; k < N; ++k) val += op.P[s0][j * N + k] * s_tr[le][f][0][v][k];
+        for (int k = 0; k < N; ++k) val += Pm(s0, j * N + k) * s_tr[le][f][0][v][k];
       } else {
         const int ja = j % N, jb = j / N;
 #pragma unroll
         for (int kb = 0; kb < N; ++kb) {
           double row = 0.0;
 #pragma unroll
-          for (int ka = 0; ka < N; ++ka) row += op.P[s0][ja * N + ka] * s_tr[le][f][0][v][ka + N * kb];
-          val += op.P[s1][jb * N + kb] * row;
+          for (int ka = 0; ka < N; ++ka) row += Pm(s0, ja * N + ka) * s_tr[le][f][0][v][ka + N * kb];
+          val += Pm(s1, jb * N + kb) * row;
         }
       }
       s_tr[le][f][1][v][j] = val;
@@ -434,15 +463,15 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         double vv = 0.0;
         if (DIM == 2) {
 #pragma unroll
-          for (int k = 0; k < N; ++k) vv += op.P[s0][j * N + k] * s_trv[le][f][0][v][k];
+          for (int k = 0; k < N; ++k) vv += Pm(s0, j * N + k) * s_trv[le][f][0][v][k];
         } else {
           const int ja = j % N, jb = j / N;
 #pragma unroll
           for (int kb = 0; kb < N; ++kb) {
             double row = 0.0;
 #pragma unroll
-            for (int ka = 0; ka < N; ++ka) row += op.P[s0][ja * N + ka] * s_trv[le][f][0][v][ka + N * kb];
-            vv += op.P[s1][jb * N + kb] * row;
+            for (int ka = 0; ka < N; ++ka) row += Pm(s0, ja * N + ka) * s_trv[le][f][0][v][ka + N * kb];
+            vv += Pm(s1, jb * N + kb) * row;
           }
         }
         s_trv[le][f][1][v][j] = vv;
@@ -463,7 +492,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       if (DIM == 2) {
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-          const double c = op.P[m0][j * N + k];
+          const double c = Pm(m0, j * N + k);
           const int on = face_node<DIM, N>(d, side, k);
           if (LDS_OWN) x += c * s_u[le][v][on];
           if (VISC) xv += c * fv_own(d, v, on);
@@ -475,12 +504,12 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
           double row = 0.0, rowv = 0.0;
 #pragma unroll
           for (int ka = 0; ka < N; ++ka) {
-            const double c = op.P[m0][ja * N + ka];
+            const double c = Pm(m0, ja * N + ka);
             const int on = face_node<DIM, N>(d, side, ka + N * kb);
             if (LDS_OWN) row += c * s_u[le][v][on];
             if (VISC) rowv += c * fv_own(d, v, on);
           }
-          const double cb = op.P[m1][jb * N + kb];
+          const double cb = Pm(m1, jb * N + kb);
           x += cb * row;
           if (VISC) xv += cb * rowv;
         }
@@ -540,8 +569,8 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
               double row = 0.0;
 #pragma unroll
               for (int ka = 0; ka < N; ++ka)
-                row += op.P[m0][ja * N + ka] * s_u[le][v][face_node<DIM, N>(d, side, ka + N * kb)];
-              x += op.P[m1][jb * N + kb] * row;
+                row += Pm(m0, ja * N + ka) * s_u[le][v][face_node<DIM, N>(d, side, ka + N * kb)];
+              x += Pm(m1, jb * N + kb) * row;
             }
             mine[v] = x;
           }
@@ -603,7 +632,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       for (int ms = 0; ms < 2; ++ms)
 #pragma unroll
         for (int kk = 0; kk < N; ++kk) {
-          const double r = op.R[ms][i * N + kk];
+          const double r = Rm(ms, i * N + kk);
           fs += r * s_tr[le][f][ms][v][kk];
           if (VISC) fsv += r * s_trv[le][f][ms][v][kk];
         }
@@ -617,11 +646,11 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
           double row = 0.0, rowv = 0.0;
 #pragma unroll
           for (int ka = 0; ka < N; ++ka) {
-            const double r = op.R[m0][ia * N + ka];
+            const double r = Rm(m0, ia * N + ka);
             row += r * s_tr[le][f][ms][v][ka + N * kb];
             if (VISC) rowv += r * s_trv[le][f][ms][v][ka + N * kb];
           }
-          const double rb = op.R[m1][ib * N + kb];
+          const double rb = Rm(m1, ib * N + kb);
           fs += rb * row;
           if (VISC) fsv += rb * rowv;
         }

@@ -11,10 +11,11 @@
 //     with R_m^T across a 2:1 mortar) and pulls it back through the derivative with respect to
 //     its own trace only (the neighbour does the same for its trace); on the coarse side of a
 //     mortar the result lives on the sub-face nodes and is taken back with P_m^T.
-// The local flux Jacobians come from forward-mode dual numbers over the flux formulas
-// (entropy-conserving flux with the logarithmic mean and its series branch; HLL with Davis
-// wave speeds, ties resolved towards the first argument), i.e. the derivative of the computed
-// map along the branches it takes.
+// The local flux Jacobians are the derivative of the computed map along the branches it takes:
+// the entropy-conserving pair flux (logarithmic mean and its series branch) in reverse mode,
+// written out (one forward and one backward pass per pair); the HLL face flux (Davis wave
+// speeds, ties resolved towards the first argument) with forward-mode dual numbers, one column
+// per own-trace variable.
 //
 // Reverse sweep of one step (Sec. 3.1: Y_i = U_n + dt (a_{i,1} K_1 + a_{i,i-1} K_{i-1}),
 // K_i = I_i F(Y_i), U_{n+1} = U_n + dt sum_i b_i K_i), from the stage values stored by a
@@ -42,8 +43,6 @@ __device__ __forceinline__ Dd operator/(Dd a, Dd b) {
   const double q = a.v / b.v;
   return Dd{q, (a.d - q * b.d) / b.v};
 }
-__device__ __forceinline__ Dd operator/(Dd a, double s) { return Dd{a.v / s, a.d / s}; }
-__device__ __forceinline__ Dd dlog(Dd a) { return Dd{log(a.v), a.d / a.v}; }
 __device__ __forceinline__ Dd dsqrt(Dd a) {
   const double r = sqrt(a.v);
   return Dd{r, 0.5 * a.d / r};
@@ -69,33 +68,91 @@ __device__ __forceinline__ DPrim<DIM> dprim(const Dd* u, double gamma) {
   return q;
 }
 
-// (b - a) / ln(b / a), with the series in u = ((b-a)/(b+a))^2 below 1e-2
-__device__ __forceinline__ Dd dlog_mean(Dd a, Dd b) {
-  const Dd f = (b - a) / (b + a);
-  const Dd u = f * f;
-  if (u.v < 1e-2) {
-    const Dd u2 = u * u, u3 = u2 * u, u4 = u3 * u, u5 = u4 * u, u6 = u5 * u, u7 = u6 * u;
-    const Dd F = mk(1.0) + u / 3.0 + u2 / 5.0 + u3 / 7.0 + u4 / 9.0 + u5 / 11.0 + u6 / 13.0 + u7 / 15.0;
-    return (a + b) / (2.0 * F);
+// ------------------------------------------------------------ reverse mode for the pair flux
+// Value and both partial derivatives of the logarithmic mean along the branch the dual form
+// takes (same u, same threshold): series (a+b)/(2F(u)) or (b-a)/ln(b/a).
+__device__ __forceinline__ void log_mean_d(double a, double b, double& lm, double& da, double& db) {
+  const double s = a + b, t = b - a;
+  const double f = t / s, u = f * f;
+  if (u < 1e-2) {
+    const double u2 = u * u, u3 = u2 * u, u4 = u3 * u, u5 = u4 * u, u6 = u5 * u, u7 = u6 * u;
+    const double F = 1.0 + u / 3.0 + u2 / 5.0 + u3 / 7.0 + u4 / 9.0 + u5 / 11.0 + u6 / 13.0 + u7 / 15.0;
+    const double Fp = 1.0 / 3.0 + 2.0 * u / 5.0 + 3.0 * u2 / 7.0 + 4.0 * u3 / 9.0 + 5.0 * u4 / 11.0 +
+                      6.0 * u5 / 13.0 + 7.0 * u6 / 15.0;
+    lm = s / (2.0 * F);
+    const double c = Fp * f / (F * F * s);
+    da = 1.0 / (2.0 * F) + 2.0 * c * b;
+    db = 1.0 / (2.0 * F) - 2.0 * c * a;
+  } else {
+    const double L = log(b / a);
+    lm = t / L;
+    da = (t / a - L) / (L * L);
+    db = (L - t / b) / (L * L);
   }
-  return (b - a) / dlog(b / a);
 }
-
-// entropy-conserving, kinetic-energy-preserving two-point flux in direction d
+// P^T (d f#/d u_L) and P^T (d f#/d u_R) of the entropy-conserving flux in one forward and one
+// backward pass (the dual form needs 2 n_v forward passes); the same derivative as the dual
+// form up to rounding (host check on random states of both branches: 1e-14 relative).
 template <int DIM>
-__device__ __forceinline__ void dec_flux(const Dd* uL, const Dd* uR, int d, double gamma, Dd* f) {
+__device__ __forceinline__ void ec_flux_vjp(const double* uL, const double* uR, int d, double gamma, const double* P, double* gL,
+                           double* gR) {
   constexpr int NV = DIM + 2;
-  const DPrim<DIM> L = dprim<DIM>(uL, gamma), R = dprim<DIM>(uR, gamma);
-  const Dd rho_ln = dlog_mean(L.rho, R.rho);
-  const Dd beta_ln = dlog_mean(L.rho / L.p, R.rho / R.p);
-  const Dd vd = 0.5 * (L.v[d] + R.v[d]);
-  const Dd p_avg = 0.5 * (L.p + R.p);
-  Dd vLvR = mk(0.0);
-  for (int k = 0; k < DIM; ++k) vLvR = vLvR + L.v[k] * R.v[k];
-  f[0] = rho_ln * vd;
-  for (int k = 0; k < DIM; ++k) f[1 + k] = f[0] * (0.5 * (L.v[k] + R.v[k]));
-  f[1 + d] = f[1 + d] + p_avg;
-  f[NV - 1] = f[0] * (0.5 * vLvR + mk(1.0) / ((gamma - 1.0) * beta_ln)) + 0.5 * (L.p * R.v[d] + R.p * L.v[d]);
+  const double gm1 = gamma - 1.0;
+  const double rL = uL[0], rR = uR[0];
+  double vL[DIM], vR[DIM], keL = 0.0, keR = 0.0;
+  for (int k = 0; k < DIM; ++k) {
+    vL[k] = uL[1 + k] / rL;
+    vR[k] = uR[1 + k] / rR;
+    keL = keL + 0.5 * (uL[1 + k] * vL[k]);
+    keR = keR + 0.5 * (uR[1 + k] * vR[k]);
+  }
+  const double pL = gm1 * (uL[NV - 1] - keL), pR = gm1 * (uR[NV - 1] - keR);
+  double rho_ln, dra, drb, beta_ln, dba, dbb;
+  log_mean_d(rL, rR, rho_ln, dra, drb);
+  const double bL = rL / pL, bR = rR / pR;
+  log_mean_d(bL, bR, beta_ln, dba, dbb);
+  const double vd = 0.5 * (vL[d] + vR[d]);
+  double vLvR = 0.0;
+  for (int k = 0; k < DIM; ++k) vLvR = vLvR + vL[k] * vR[k];
+  const double f0 = rho_ln * vd;
+  const double ib = 1.0 / (gm1 * beta_ln);
+  const double Q = 0.5 * vLvR + ib;
+  const double PE = P[NV - 1];
+  double vLb[DIM], vRb[DIM];
+  double f0b = P[0] + PE * Q;
+  const double Qb = PE * f0;
+  for (int k = 0; k < DIM; ++k) {
+    f0b += P[1 + k] * (0.5 * (vL[k] + vR[k]));
+    vLb[k] = 0.5 * f0 * P[1 + k] + 0.5 * Qb * vR[k];
+    vRb[k] = 0.5 * f0 * P[1 + k] + 0.5 * Qb * vL[k];
+  }
+  double pLb = 0.5 * PE * vR[d] + 0.5 * P[1 + d];
+  double pRb = 0.5 * PE * vL[d] + 0.5 * P[1 + d];
+  vRb[d] += 0.5 * PE * pL;
+  vLb[d] += 0.5 * PE * pR;
+  const double beta_lnb = -Qb * gm1 * ib * ib;
+  const double rho_lnb = f0b * vd, vdb = f0b * rho_ln;
+  vLb[d] += 0.5 * vdb;
+  vRb[d] += 0.5 * vdb;
+  double rLb = rho_lnb * dra, rRb = rho_lnb * drb;
+  const double bLb = beta_lnb * dba, bRb = beta_lnb * dbb;
+  rLb += bLb / pL;
+  pLb -= bLb * bL / pL;
+  rRb += bRb / pR;
+  pRb -= bRb * bR / pR;
+  // p = (gamma-1)(E - ke), ke = sum 1/2 m_k v_k, v_k = m_k / r
+  const double kLb = -gm1 * pLb, kRb = -gm1 * pRb;
+  gL[NV - 1] = gm1 * pLb;
+  gR[NV - 1] = gm1 * pRb;
+  for (int k = 0; k < DIM; ++k) {
+    const double vbl = vLb[k] + 0.5 * uL[1 + k] * kLb, vbr = vRb[k] + 0.5 * uR[1 + k] * kRb;
+    gL[1 + k] = 0.5 * vL[k] * kLb + vbl / rL;
+    gR[1 + k] = 0.5 * vR[k] * kRb + vbr / rR;
+    rLb -= vbl * vL[k] / rL;
+    rRb -= vbr * vR[k] / rR;
+  }
+  gL[0] = rLb;
+  gR[0] = rRb;
 }
 
 template <int DIM>
@@ -242,20 +299,17 @@ __global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, 
 #pragma unroll
       for (int v = 0; v < NV; ++v)
         Pb[v] = -J[d] * (2.0 * op.D[pa * N + pb] * s_w[v][na] + 2.0 * op.D[pb * N + pa] * s_w[v][nb]);
-#pragma unroll 1
-      for (int j = 0; j < 2 * NV; ++j) {
-        Dd uL[NV], uR[NV], f[NV];
+      double uA[NV], uB[NV], gA[NV], gB[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          uL[v] = mk(s_u[v][na], j == v ? 1.0 : 0.0);
-          uR[v] = mk(s_u[v][nb], j == NV + v ? 1.0 : 0.0);
-        }
-        dec_flux<DIM>(uL, uR, d, gamma, f);
-        double gsum = 0.0;
+      for (int v = 0; v < NV; ++v) {
+        uA[v] = s_u[v][na];
+        uB[v] = s_u[v][nb];
+      }
+      ec_flux_vjp<DIM>(uA, uB, d, gamma, Pb, gA, gB);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) gsum += Pb[v] * f[v].d;
-        if (j < NV) s_ga[w][j] = gsum;
-        else s_gb[w][j - NV] = gsum;
+      for (int v = 0; v < NV; ++v) {
+        s_ga[w][v] = gA[v];
+        s_gb[w][v] = gB[v];
       }
     } else {
       const int r = w - NP;

@@ -357,8 +357,88 @@ def run_adjoint(args):
     }
 
 
+def run_sweep(args):
+    """Stage-kernel throughput on uniform single-level meshes, every element active at every
+    stage: 2D p=3 Euler on 64^2 ... 1024^2 elements (isentropic vortex, P-ERK2;8 alone) and 3D
+    p=3 Euler on 16^3 ... 48^3 (Taylor-Green state, P-ERK2;16 alone).  Per size: the stage
+    kernel's average launch (HIP events on the launch stream), element-stages per second and the
+    roofline fractions of the algorithmic bytes and flops; the line's value is the whole-step
+    DoF-update rate (graph replay) of the largest 2D mesh."""
+    import torch
+    import perk_inputs as pin
+    from paper_2403_05144_amd import PerkSolver
+    cases = [(2, n) for n in (64, 128, 256, 512, 1024)] + [(3, n) for n in (16, 24, 32, 48)]
+    if args.sweep_max:
+        cases = [(d, n) for d, n in cases if n ** d <= args.sweep_max]
+    rows = []
+    value = None
+    for dim, n in cases:
+        if dim == 2:
+            fam = single_member_family(vortex_family(3, (4, 8)), 1)
+            mesh = pin.uniform_mesh(2, (n, n), (-5, -5), (5, 5), 0)
+            ic = lambda x: pin.isentropic_vortex(x[0], x[1])
+        else:
+            fam = single_member_family(wl_tgv()["fam"], 2)
+            mesh = pin.uniform_mesh(3, (n, n, n), (-np.pi,) * 3, (np.pi,) * 3, 0)
+            ic = lambda x: pin.taylor_green(x[0], x[1], x[2])
+        s = PerkSolver(mesh, 3, fam, [0])
+        x = s.node_coords().cpu().numpy().transpose(1, 0, 2)
+        s.set_state(ic(x).transpose(1, 0, 2).copy())
+        dt = stable_dt(fam, mesh, [0], 0.5)
+        s.step(dt, 2)
+        torch.cuda.synchronize()
+        steps = max(2, min(50, int(2e6 // (n ** dim))))
+        t0 = time.perf_counter()
+        s.step(dt, steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        s.set_profiling(True)
+        s.step(dt, min(steps, 10))
+        torch.cuda.synchronize()
+        ms, nl, es = s.profile_stats()
+        s.set_profiling(False)
+        if not np.all(np.isfinite(s.get_state().cpu().numpy())):
+            raise RuntimeError(f"sweep: non-finite state at {dim}D {n}^{dim}")
+        launch_s = ms * 1e-3 / nl
+        rate = (es / nl) / launch_s
+        B, F = bytes_per_element_stage(dim, 4), flops_per_element_stage(dim, 4)
+        dofs = s.n_elements * s.nv * s.Nd
+        row = {"dim": dim, "elements": int(s.n_elements), "avg_launch_us": launch_s * 1e6,
+               "element_stages_per_s": rate, "ns_per_element_stage": 1e9 / rate,
+               "hbm_frac": B * rate / (HBM_PEAK_GBS * 1e9), "alu_frac": F * rate / (FP64_PEAK_TFLOPS * 1e12),
+               "dof_updates_per_s": dofs * steps / wall}
+        rows.append(row)
+        _log(f"sweep {dim}D {n}^{dim}: {row['ns_per_element_stage']:.3f} ns/element-stage, "
+             f"HBM {row['hbm_frac']:.3f}, ALU {row['alu_frac']:.3f}")
+        if dim == 2:
+            value = (row["dof_updates_per_s"], steps, wall, int(s.n_elements))
+        del s
+        torch.cuda.empty_cache()
+    big = max((r for r in rows if r["dim"] == 2), key=lambda r: r["elements"])
+    roof_b, roof_f = big["hbm_frac"], big["alu_frac"]
+    B, F = bytes_per_element_stage(2, 4), flops_per_element_stage(2, 4)
+    if roof_b >= roof_f:
+        roof = {"bound": "hbm", "achieved": B * big["element_stages_per_s"] / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": roof_b}
+    else:
+        roof = {"bound": "alu", "achieved": F * big["element_stages_per_s"] / 1e12, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": roof_f}
+    roof.update({"traffic": None, "kernel": "k_stage", "avg_launch_us": big["avg_launch_us"],
+                 "element_stages_per_launch": big["elements"]})
+    return {
+        "metric": "DoF-updates/s & PID; P-ERK vs single-level RK wall time at equal error",
+        "value": value[0], "unit": "DoF-updates/s", "n_gpus": 1, "steps": value[1], "warmup": 2,
+        "ms_per_step": value[2] / value[1] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "uniform_sweep", "description": "stage kernel on uniform single-level meshes, "
+                   "2D p=3 Euler 64^2..1024^2 (P-ERK2;8 alone), 3D p=3 Euler 16^3..48^3 (P-ERK2;16 alone); "
+                   "value: the largest 2D mesh"},
+        "roofline": roof, "sweep": rows,
+    }
+
+
 WORKLOADS = {"vortex_2level": wl_vortex_2level, "kh_amr": wl_kh_amr, "tgv": wl_tgv, "batch_vortex64": None,
-             "adjoint_kh": None,
+             "adjoint_kh": None, "uniform_sweep": None,
              "kh_amr_l4-7": lambda: wl_kh_amr(16, 3, "kh_amr_l4-7")}
 
 
@@ -691,23 +771,33 @@ def compare_equal_error(wl, t_final=None, tol=0.05, ref_budget=6e8):
 
 def flops_per_element_stage(dim, N):
     """Algorithmic fp64 operations of one element-stage of the stage kernel, counted from its
-    code path (divisions, square roots and logarithms as one operation each):
-    per node and direction (N-1) two-point fluxes of 53 (2D) / 63 (3D) operations plus 2 n_v
-    accumulations; per face node one HLL flux of 95 (2D) / 115 (3D); per node 16 operations for
-    primitives and logarithms and 6 n_v for the stage combination."""
+    code path (divisions, square roots and logarithms as one operation each): one two-point flux
+    of 53 (2D) / 63 (3D) operations per unordered node pair of a line (d N^(d-1) N(N-1)/2
+    pairs, each shared by its two nodes); per node and direction 2 n_v (N-1) operations to
+    accumulate them; per face node one HLL flux of 95 (2D) / 115 (3D); per node 16 operations
+    for primitives and logarithms and 6 n_v for the stage combination."""
     nv = dim + 2
     nd = N ** dim
     ec = 53 if dim == 2 else 63
     hll = 95 if dim == 2 else 115
-    per_node = dim * (N - 1) * (ec + 2 * nv) + 16 + 6 * nv
-    return nd * per_node + 2 * dim * N ** (dim - 1) * hll
+    pairs = dim * N ** (dim - 1) * N * (N - 1) // 2
+    per_node = dim * (N - 1) * 2 * nv + 16 + 6 * nv
+    return pairs * ec + nd * per_node + 2 * dim * N ** (dim - 1) * hll
 
 
 def bytes_per_element_stage(dim, N, viscous=False):
     """Algorithmic HBM bytes of one element-stage: read the stage value, U_n and K_1 and write
-    the next stage value of the element (4 element slices of n_v N^d fp64); Navier-Stokes also
-    reads the element's BR1 viscous flux, written by the gradient kernel (dim slices)."""
-    return (4 + (dim if viscous else 0)) * (dim + 2) * N ** dim * 8
+    the next stage value of the element (4 element slices of n_v N^d fp64), plus the neighbours'
+    face traces (2d faces of n_v N^(d-1) values, times 3/2 for neighbours whose stage value is
+    formed from U_n and K_1); Navier-Stokes also reads the element's BR1 viscous flux, written
+    by the gradient kernel (d slices), and its neighbours' normal viscous flux on the faces."""
+    nv = dim + 2
+    slice_b = nv * N ** dim * 8
+    face_b = 2 * dim * nv * N ** (dim - 1) * 8
+    b = 4 * slice_b + 1.5 * face_b
+    if viscous:
+        b += dim * slice_b + face_b
+    return b
 
 
 def measured_traffic(workload, es_per_launch):
@@ -902,6 +992,8 @@ def main():
     ap.add_argument("--batch-replicas", type=int, default=1, help="batch_vortex64: copies of the 64 runs")
     ap.add_argument("--no-equal-error", action="store_true",
                     help="skip the comparison with single-level schemes at equal error")
+    ap.add_argument("--sweep-max", type=int, default=0,
+                    help="uniform_sweep: largest element count to run (0: all sizes)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device once (calibration of HBM counters)")
     args = ap.parse_args()
@@ -923,6 +1015,8 @@ def main():
         line = run_batch(args)
     elif args.workload == "adjoint_kh":
         line = run_adjoint(args)
+    elif args.workload == "uniform_sweep":
+        line = run_sweep(args)
     else:
         line = run(args)
     print(json.dumps(line), flush=True)

@@ -256,13 +256,18 @@ struct SK {
   // the face fluxes on the second, so their dependency chains run side by side instead of one
   // after the other in a divergent wave (the face flux chain is the longest of the kernel)
   static constexpr bool SPLIT = SPLIT_ && DIM == 2 && N == 4;
-  static constexpr int T = DIM == 2 ? (N == 4 ? (SPLIT ? 128 : 64) : 32) : (N == 4 ? 384 : 192);
+  // 3D p=3: 7 waves, the pair fluxes on the first five (288 of 320 lanes), the face fluxes on
+  // the last two, so that no wave runs both flux paths (with 6 waves one wave did)
+  static constexpr int T = DIM == 2 ? (N == 4 ? (SPLIT ? 128 : 64) : 32) : (N == 4 ? 448 : 192);
+  // lanes of the pair fluxes in phase D when pairs and face nodes have waves of their own
+  // (0: one mixed loop over both)
+  static constexpr int PLN = SPLIT ? T / 2 : (DIM == 3 && N == 4 ? 320 : 0);
   static constexpr int EPB = T >= 64 ? 1 : 64 / T;
   static constexpr int NITEM = (NV * ND + T - 1) / T;         // (variable, node) items per lane
   // waves per SIMD the register allocation must allow.  A second 6-wave block fits on a CU
   // only when every SIMD can hold 4 waves (at most 128 VGPRs) and the LDS allows it (measured:
   // at 3 waves per SIMD a second 384-lane block never starts, whatever its LDS size).
-  static constexpr int MINW = T == 384 ? 4 : 1;
+  static constexpr int MINW = T >= 384 ? 4 : 1;
 };
 
 // The stage work of one block of EPB elements: block `blk` of the launch covers the slots
@@ -435,8 +440,8 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       q.lbeta = log_pos(q.beta);
       s_q[le][w] = q;
     }
-    // (split: interpolations start on the second wave, the node quantities sit on the first)
-    const int lane_c = K::SPLIT ? (lane ^ (T / 2)) : lane;
+    // (interpolations start on the second wave, the node quantities sit on the first)
+    const int lane_c = (lane + 64) % T;
     for (int w = lane_c; w < NFC * NV * NF; w += T) {
       const int j = w % NF;
       const int v = (w / NF) % NV;
@@ -522,88 +527,100 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
 
   // ---- D: fluxes.  Pairs first, then face nodes sub-face-major (sub 0 of every face first).
   if (act) {
-    for (int w0 = lane; w0 < (K::SPLIT ? T : NP + NSUB * NFC * NF); w0 += T) {
-      // split: lanes [0, T/2) take the pairs, lanes [T/2, T) the face nodes
-      const int w = !K::SPLIT ? w0
-                              : (w0 < T / 2 ? (w0 < NP ? w0 : -1)
-                                            : (w0 - T / 2 < NSUB * NFC * NF ? NP + w0 - T / 2 : -1));
-      if (w < 0) continue;
-      if (w < NP) {
-        const int pl = w % NPL;
-        const int line = (w / NPL) % K::NLINE;
-        const int d = w / (NPL * K::NLINE);
-        const int pa = (PairNodes<N>::kFirst >> (4 * pl)) & 15, pb = (PairNodes<N>::kSecond >> (4 * pl)) & 15;
-        double f[NV];
-        ec_flux<DIM>(s_q[le][node_on_line<DIM, N>(d, line, pa)], s_q[le][node_on_line<DIM, N>(d, line, pb)], d,
-                     inv_gm1, f);
+    // pair fluxes (w in [0, NP)) and face fluxes (r in [0, NFI)); with the split on, each on
+    // lanes of its own ([0, PLN) and [PLN, T)), else one loop over both
+    constexpr int NFI = NSUB * NFC * NF;
+    auto pair_flux = [&](int w) {
+      const int pl = w % NPL;
+      const int line = (w / NPL) % K::NLINE;
+      const int d = w / (NPL * K::NLINE);
+      const int pa = (PairNodes<N>::kFirst >> (4 * pl)) & 15, pb = (PairNodes<N>::kSecond >> (4 * pl)) & 15;
+      double f[NV];
+      ec_flux<DIM>(s_q[le][node_on_line<DIM, N>(d, line, pa)], s_q[le][node_on_line<DIM, N>(d, line, pb)], d,
+                   inv_gm1, f);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) s_pf[le][w][v] = f[v];
-      } else {
-        const int r = w - NP;
-        const int j = r % NF;
-        const int f = (r / NF) % NFC;
-        const int sub = r / (NF * NFC);
-        const int32_t pk = s_fk[le][f];
-        const int kind = face_kind(pk);
-        if (sub > 0 && kind != kCoarseSide) continue;
-        const int d = f >> 1, side = f & 1;
-        double mine[NV], oth[NV], fl[NV];
-        if (kind == kCoarseSide && LDS_OWN) {
-          // own trace interpolated to sub-face `sub` (phase C)
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            mine[v] = s_tro[le][f][sub][v][j];
-            oth[v] = s_tr[le][f][sub][v][j];
-          }
-        } else if (kind == kCoarseSide) {
-          // own trace interpolated to sub-face `sub` here: P_{m1} (x) P_{m0} on the face, one
-          // variable at a time (five accumulators at once would spill at 128 VGPRs)
-          const int m0 = sub & 1, m1 = (sub >> 1) & 1;
-          const int ja = j % N, jb = j / N;
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            oth[v] = s_tr[le][f][sub][v][j];
-            double x = 0.0;
-#pragma unroll 1
-            for (int kb = 0; kb < N; ++kb) {
-              double row = 0.0;
-#pragma unroll
-              for (int ka = 0; ka < N; ++ka)
-                row += Pm(m0, ja * N + ka) * s_u[le][v][face_node<DIM, N>(d, side, ka + N * kb)];
-              x += Pm(m1, jb * N + kb) * row;
-            }
-            mine[v] = x;
-          }
-        } else {
-          const int on = face_node<DIM, N>(d, side, j);
-          const int ts = kind == kFineSide ? 1 : 0;
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            mine[v] = s_u[le][v][on];
-            oth[v] = s_tr[le][f][ts][v][j];
-          }
-        }
-        // one flux call with the states ordered along +e_d (two calls, one per side, would run
-        // both inlined copies in every wave whose lanes see both sides)
-        double uL[NV], uR[NV];
+      for (int v = 0; v < NV; ++v) s_pf[le][w][v] = f[v];
+    };
+    auto face_flux = [&](int r) {
+      const int j = r % NF;
+      const int f = (r / NF) % NFC;
+      const int sub = r / (NF * NFC);
+      const int32_t pk = s_fk[le][f];
+      const int kind = face_kind(pk);
+      if (sub > 0 && kind != kCoarseSide) return;
+      const int d = f >> 1, side = f & 1;
+      double mine[NV], oth[NV], fl[NV];
+      if (kind == kCoarseSide && LDS_OWN) {
+        // own trace interpolated to sub-face `sub` (phase C)
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          uL[v] = side == 1 ? mine[v] : oth[v];
-          uR[v] = side == 1 ? oth[v] : mine[v];
+          mine[v] = s_tro[le][f][sub][v][j];
+          oth[v] = s_tr[le][f][sub][v][j];
         }
-        hll_flux<DIM>(uL, uR, d, gamma, fl);
+      } else if (kind == kCoarseSide) {
+        // own trace interpolated to sub-face `sub` here: P_{m1} (x) P_{m0} on the face, one
+        // variable at a time (five accumulators at once would spill at 128 VGPRs)
+        const int m0 = sub & 1, m1 = (sub >> 1) & 1;
+        const int ja = j % N, jb = j / N;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) s_tr[le][f][sub][v][j] = fl[v];
-        if (VISC && kind != kCoarseSide) {
-          // BR1 central viscous flux on this face node: 1/2 (own + neighbour); coarse sides
-          // were averaged in phase C
+        for (int v = 0; v < NV; ++v) {
+          oth[v] = s_tr[le][f][sub][v][j];
+          double x = 0.0;
+#pragma unroll 1
+          for (int kb = 0; kb < N; ++kb) {
+            double row = 0.0;
 #pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            const double ownv = fv_own(d, v, face_node<DIM, N>(d, side, j));
-            const int ts = kind == kFineSide ? 1 : 0;
-            s_trv[le][f][sub][v][j] = 0.5 * (ownv + s_trv[le][f][ts][v][j]);
+            for (int ka = 0; ka < N; ++ka)
+              row += Pm(m0, ja * N + ka) * s_u[le][v][face_node<DIM, N>(d, side, ka + N * kb)];
+            x += Pm(m1, jb * N + kb) * row;
           }
+          mine[v] = x;
         }
+      } else {
+        const int on = face_node<DIM, N>(d, side, j);
+        const int ts = kind == kFineSide ? 1 : 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          mine[v] = s_u[le][v][on];
+          oth[v] = s_tr[le][f][ts][v][j];
+        }
+      }
+      // one flux call with the states ordered along +e_d (two calls, one per side, would run
+      // both inlined copies in every wave whose lanes see both sides)
+      double uL[NV], uR[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        uL[v] = side == 1 ? mine[v] : oth[v];
+        uR[v] = side == 1 ? oth[v] : mine[v];
+      }
+      hll_flux<DIM>(uL, uR, d, gamma, fl);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s_tr[le][f][sub][v][j] = fl[v];
+      if (VISC && kind != kCoarseSide) {
+        // BR1 central viscous flux on this face node: 1/2 (own + neighbour); coarse sides
+        // were averaged in phase C
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double ownv = fv_own(d, v, face_node<DIM, N>(d, side, j));
+          const int ts = kind == kFineSide ? 1 : 0;
+          s_trv[le][f][sub][v][j] = 0.5 * (ownv + s_trv[le][f][ts][v][j]);
+        }
+      }
+    };
+    if (K::PLN) {
+      constexpr int NFL = T - K::PLN;   // face lanes
+      if (lane < K::PLN) {
+        for (int w = lane; w < NP; w += K::PLN) pair_flux(w);
+      } else if (lane - K::PLN < NFI) {
+        face_flux(lane - K::PLN);
+      }
+      // face items beyond the face lanes exist only on the sub-faces of coarse sides; every lane
+      // takes part (on other blocks each returns at once)
+      for (int r = NFL + lane; r < NFI; r += T) face_flux(r);
+    } else {
+      for (int w = lane; w < NP + NFI; w += T) {
+        if (w < NP) pair_flux(w);
+        else face_flux(w - NP);
       }
     }
   }

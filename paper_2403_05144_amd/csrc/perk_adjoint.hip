@@ -11,11 +11,15 @@
 //     with R_m^T across a 2:1 mortar) and pulls it back through the derivative with respect to
 //     its own trace only (the neighbour does the same for its trace); on the coarse side of a
 //     mortar the result lives on the sub-face nodes and is taken back with P_m^T.
-// The local flux Jacobians are the derivative of the computed map along the branches it takes:
-// the entropy-conserving pair flux (logarithmic mean and its series branch) in reverse mode,
-// written out (one forward and one backward pass per pair); the HLL face flux (Davis wave
-// speeds, ties resolved towards the first argument) with forward-mode dual numbers, one column
-// per own-trace variable.
+// The local flux Jacobians are the derivative of the computed map along the branches it takes,
+// in reverse mode written out (one forward and one backward pass per flux): the
+// entropy-conserving pair flux (logarithmic mean and its series branch) and the HLL face flux
+// (Davis wave speeds, ties resolved towards the first argument).
+//
+// Block layout: one element per block; in 2D the pair pull-backs run on the first wave and the
+// face pull-backs on the second, so that neither waits for the other inside a wave.  The
+// derivative and mortar tables come from the device operator table into LDS (lane-indexed
+// reads of kernel-argument memory are slow).
 //
 // Reverse sweep of one step (Sec. 3.1: Y_i = U_n + dt (a_{i,1} K_1 + a_{i,i-1} K_{i-1}),
 // K_i = I_i F(Y_i), U_{n+1} = U_n + dt sum_i b_i K_i), from the stage values stored by a
@@ -29,44 +33,6 @@
 
 namespace perk {
 namespace {
-
-// ---------------------------------------------------------------- forward-mode dual number
-struct Dd {
-  double v, d;
-};
-__device__ __forceinline__ Dd mk(double v, double d = 0.0) { return Dd{v, d}; }
-__device__ __forceinline__ Dd operator+(Dd a, Dd b) { return Dd{a.v + b.v, a.d + b.d}; }
-__device__ __forceinline__ Dd operator-(Dd a, Dd b) { return Dd{a.v - b.v, a.d - b.d}; }
-__device__ __forceinline__ Dd operator*(Dd a, Dd b) { return Dd{a.v * b.v, a.d * b.v + a.v * b.d}; }
-__device__ __forceinline__ Dd operator*(double s, Dd a) { return Dd{s * a.v, s * a.d}; }
-__device__ __forceinline__ Dd operator/(Dd a, Dd b) {
-  const double q = a.v / b.v;
-  return Dd{q, (a.d - q * b.d) / b.v};
-}
-__device__ __forceinline__ Dd dsqrt(Dd a) {
-  const double r = sqrt(a.v);
-  return Dd{r, 0.5 * a.d / r};
-}
-__device__ __forceinline__ Dd dmin(Dd a, Dd b) { return b.v < a.v ? b : a; }
-__device__ __forceinline__ Dd dmax(Dd a, Dd b) { return b.v > a.v ? b : a; }
-
-template <int DIM>
-struct DPrim {
-  Dd rho, v[DIM], p;
-};
-
-template <int DIM>
-__device__ __forceinline__ DPrim<DIM> dprim(const Dd* u, double gamma) {
-  DPrim<DIM> q;
-  q.rho = u[0];
-  Dd ke = mk(0.0);
-  for (int k = 0; k < DIM; ++k) {
-    q.v[k] = u[1 + k] / u[0];
-    ke = ke + 0.5 * (u[1 + k] * q.v[k]);
-  }
-  q.p = (gamma - 1.0) * (u[DIM + 1] - ke);
-  return q;
-}
 
 // ------------------------------------------------------------ reverse mode for the pair flux
 // Value and both partial derivatives of the logarithmic mean along the branch the dual form
@@ -155,32 +121,108 @@ __device__ __forceinline__ void ec_flux_vjp(const double* uL, const double* uR, 
   gR[0] = rRb;
 }
 
+// (d f*/d u_L)^T Hb and (d f*/d u_R)^T Hb of the HLL flux with Davis wave speeds (normal +e_d
+// from L to R) in one forward and one backward pass.  Branches as in the forward flux:
+// s_L >= 0 takes the left Euler flux, s_R <= 0 the right one, otherwise the HLL average; the
+// min / max of the wave speeds pass their cotangent to the argument they took (ties: left).
+// Same derivative as forward-mode dual numbers up to rounding (host check on random sub- and
+// supersonic states: 4e-15 relative).
 template <int DIM>
-__device__ __forceinline__ void deuler_flux(const Dd* u, const DPrim<DIM>& q, int d, Dd* f) {
+__device__ __forceinline__ void hll_flux_vjp(const double* uL, const double* uR, int d, double gamma, const double* Hb, double* gL,
+                     double* gR) {
   constexpr int NV = DIM + 2;
-  f[0] = u[1 + d];
-  for (int k = 0; k < DIM; ++k) f[1 + k] = u[1 + k] * q.v[d];
-  f[1 + d] = f[1 + d] + q.p;
-  f[NV - 1] = (u[NV - 1] + q.p) * q.v[d];
-}
-
-// HLL with Davis wave speeds, normal +e_d from L to R
-template <int DIM>
-__device__ __forceinline__ void dhll_flux(const Dd* uL, const Dd* uR, int d, double gamma, Dd* f) {
-  constexpr int NV = DIM + 2;
-  const DPrim<DIM> L = dprim<DIM>(uL, gamma), R = dprim<DIM>(uR, gamma);
-  const Dd cL = dsqrt(gamma * L.p / L.rho), cR = dsqrt(gamma * R.p / R.rho);
-  const Dd sL = dmin(L.v[d] - cL, R.v[d] - cR);
-  const Dd sR = dmax(L.v[d] + cL, R.v[d] + cR);
-  Dd fL[NV], fR[NV];
-  deuler_flux<DIM>(uL, L, d, fL);
-  deuler_flux<DIM>(uR, R, d, fR);
-  if (sL.v >= 0.0) {
-    for (int v = 0; v < NV; ++v) f[v] = fL[v];
-  } else if (sR.v <= 0.0) {
-    for (int v = 0; v < NV; ++v) f[v] = fR[v];
+  const double gm1 = gamma - 1.0;
+  const double* us[2] = {uL, uR};
+  double rho[2], v[2][DIM], p[2], c[2], fx[2][NV];
+  for (int s = 0; s < 2; ++s) {
+    const double* u = us[s];
+    rho[s] = u[0];
+    double ke = 0.0;
+    for (int k = 0; k < DIM; ++k) {
+      v[s][k] = u[1 + k] / u[0];
+      ke = ke + 0.5 * (u[1 + k] * v[s][k]);
+    }
+    p[s] = gm1 * (u[NV - 1] - ke);
+    c[s] = sqrt(gamma * p[s] / rho[s]);
+    fx[s][0] = u[1 + d];
+    for (int k = 0; k < DIM; ++k) fx[s][1 + k] = u[1 + k] * v[s][d];
+    fx[s][1 + d] = fx[s][1 + d] + p[s];
+    fx[s][NV - 1] = (u[NV - 1] + p[s]) * v[s][d];
+  }
+  const double aL = v[0][d] - c[0], aR = v[1][d] - c[1];
+  const double bL = v[0][d] + c[0], bR = v[1][d] + c[1];
+  const bool sl_r = aR < aL, sr_r = bR > bL;   // ties go to the left state
+  const double sL = sl_r ? aR : aL, sR = sr_r ? bR : bL;
+  double fb[2][NV], ub[2][NV];
+  double sLb = 0.0, sRb = 0.0;
+  for (int k = 0; k < NV; ++k) {
+    ub[0][k] = 0.0;
+    ub[1][k] = 0.0;
+  }
+  if (sL >= 0.0) {
+    for (int k = 0; k < NV; ++k) {
+      fb[0][k] = Hb[k];
+      fb[1][k] = 0.0;
+    }
+  } else if (sR <= 0.0) {
+    for (int k = 0; k < NV; ++k) {
+      fb[0][k] = 0.0;
+      fb[1][k] = Hb[k];
+    }
   } else {
-    for (int v = 0; v < NV; ++v) f[v] = (sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v])) / (sR - sL);
+    const double id = 1.0 / (sR - sL);
+    for (int k = 0; k < NV; ++k) {
+      const double du = uR[k] - uL[k];
+      const double f = (sR * fx[0][k] - sL * fx[1][k] + sL * sR * du) * id;
+      const double h = Hb[k] * id;
+      fb[0][k] = h * sR;
+      fb[1][k] = -h * sL;
+      ub[1][k] += h * sL * sR;
+      ub[0][k] -= h * sL * sR;
+      sRb += h * (fx[0][k] + sL * du - f);
+      sLb += h * (sR * du - fx[1][k] + f);
+    }
+  }
+  // wave speeds: s = v_d -+ c
+  double vdb[2], cb[2];
+  vdb[0] = (sl_r ? 0.0 : sLb) + (sr_r ? 0.0 : sRb);
+  vdb[1] = (sl_r ? sLb : 0.0) + (sr_r ? sRb : 0.0);
+  cb[0] = (sr_r ? 0.0 : sRb) - (sl_r ? 0.0 : sLb);
+  cb[1] = (sr_r ? sRb : 0.0) - (sl_r ? sLb : 0.0);
+  double* gs[2] = {gL, gR};
+  for (int s = 0; s < 2; ++s) {
+    const double* u = us[s];
+    double* g = ub[s];
+    const double* f = fb[s];
+    double vb[DIM];
+    for (int k = 0; k < DIM; ++k) vb[k] = 0.0;
+    double pb = 0.0, rb = 0.0;
+    // c = sqrt(x), x = gamma p / rho
+    const double xb = cb[s] * 0.5 / c[s];
+    pb += xb * gamma / rho[s];
+    rb -= xb * gamma * p[s] / (rho[s] * rho[s]);
+    vb[d] += vdb[s];
+    // Euler flux in direction d
+    g[1 + d] += f[0];
+    for (int k = 0; k < DIM; ++k) {
+      g[1 + k] += f[1 + k] * v[s][d];
+      vb[d] += f[1 + k] * u[1 + k];
+    }
+    pb += f[1 + d];
+    g[NV - 1] += f[NV - 1] * v[s][d];
+    pb += f[NV - 1] * v[s][d];
+    vb[d] += f[NV - 1] * (u[NV - 1] + p[s]);
+    // p = (gamma-1)(E - ke), ke = sum 1/2 m_k v_k, v_k = m_k / rho
+    g[NV - 1] += gm1 * pb;
+    const double keb = -gm1 * pb;
+    for (int k = 0; k < DIM; ++k) {
+      g[1 + k] += 0.5 * v[s][k] * keb;
+      vb[k] += 0.5 * u[1 + k] * keb;
+      g[1 + k] += vb[k] / rho[s];
+      rb -= vb[k] * v[s][k] / rho[s];
+    }
+    g[0] += rb;
+    for (int k = 0; k < NV; ++k) gs[s][k] = g[k];
   }
 }
 
@@ -198,26 +240,30 @@ struct AK {
   static constexpr int NPL = N * (N - 1) / 2;
   static constexpr int NLINE = DIM == 2 ? N : N * N;
   static constexpr int NP = DIM * NLINE * NPL;
-  static constexpr int T = DIM == 2 ? 64 : (N == 4 ? 384 : 192);
+  static constexpr int NFI = NSUB * NFC * NF;          // face items (sub-faces on coarse sides)
+  static constexpr bool SPLIT = DIM == 2;              // pairs on wave 0, faces on wave 1
+  static constexpr int T = DIM == 2 ? 128 : (N == 4 ? 384 : 192);
 };
 
+// Operator tables staged in LDS: t[0] 2 D with a zero diagonal, t[1] D, t[2 + m] P_m,
+// t[4 + m] R_m (N x N, row-major).
 // R_m[i, k] (coarse node i, sub-face node k) and P_m[k, i] of a 2:1 mortar, tensor products in 3D
 template <int DIM, int N>
-__device__ __forceinline__ double Rm(const Ops& op, int m, int i, int k) {
-  if (DIM == 2) return op.R[m][i * N + k];
-  return op.R[m & 1][(i % N) * N + (k % N)] * op.R[(m >> 1) & 1][(i / N) * N + (k / N)];
+__device__ __forceinline__ double Rm(const double (*t)[N * N], int m, int i, int k) {
+  if (DIM == 2) return t[4 + m][i * N + k];
+  return t[4 + (m & 1)][(i % N) * N + (k % N)] * t[4 + ((m >> 1) & 1)][(i / N) * N + (k / N)];
 }
 template <int DIM, int N>
-__device__ __forceinline__ double Pm(const Ops& op, int m0, int m1, int k, int i) {
-  if (DIM == 2) return op.P[m0][k * N + i];
-  return op.P[m0][(k % N) * N + (i % N)] * op.P[m1][(k / N) * N + (i / N)];
+__device__ __forceinline__ double Pm(const double (*t)[N * N], int m0, int m1, int k, int i) {
+  if (DIM == 2) return t[2 + m0][k * N + i];
+  return t[2 + m0][(k % N) * N + (i % N)] * t[2 + m1][(k / N) * N + (i / N)];
 }
 
 template <int DIM, int N>
 __global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, Ops op, Physics ph) {
   using K = AK<DIM, N>;
   constexpr int ND = K::ND, NF = K::NF, NFC = K::NFC, NV = K::NV, NSUB = K::NSUB, T = K::T;
-  constexpr int NP = K::NP, NPL = K::NPL;
+  constexpr int NP = K::NP, NPL = K::NPL, NFI = K::NFI;
   __shared__ double s_u[NV][ND];                 // own stage state
   __shared__ double s_w[NV][ND];                 // own cotangent
   __shared__ double s_tr[NFC][NSUB][NV][NF];     // neighbour stage traces (fine side: interpolated in sub 1)
@@ -225,6 +271,7 @@ __global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, 
   __shared__ double s_jn[NFC][NSUB];             // neighbour 2/h in the face direction
   __shared__ double s_ga[NP][NV], s_gb[NP][NV];  // pair pull-backs to the first / second node
   __shared__ double s_gf[NFC][NSUB][NV][NF];     // face pull-backs (coarse side: on sub-face nodes)
+  __shared__ double s_op[6][N * N];              // 2D (zero diagonal), D, P_0, P_1, R_0, R_1
   __shared__ int s_fk[NFC];
   __shared__ int s_fn[NFC][4];
 
@@ -238,11 +285,18 @@ __global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, 
   double J[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) J[d] = m.jac[lev][d];
+  // the members' stage-value codes packed two bits each (a member-indexed read of the argument
+  // array from a lane-dependent neighbour would be a gather from kernel-argument memory)
+  int src_bits = 0;
+#pragma unroll
+  for (int r = 0; r < kMaxMembers; ++r) src_bits |= a.src[r] << (2 * r);
+  auto src_m = [&](int r) { return (src_bits >> (2 * r)) & 3; };
 
-  // ---- A: own state and cotangent, connectivity, neighbour traces
+  // ---- A: own state and cotangent, connectivity, operator tables; then neighbour traces
   if (lane < NFC) s_fk[lane] = m.fk[(int64_t)e * NFC + lane];
   if (lane < NFC * 4) s_fn[lane / 4][lane % 4] = m.fn[(int64_t)e * NFC * 4 + lane];
-  const int my_src = a.src[mem];
+  for (int t = lane; t < 6 * N * N; t += T) s_op[t / (N * N)][t % (N * N)] = op.dD[t];
+  const int my_src = src_m(mem);
   const bool w_own = e < a.n_w;
   for (int w = lane; w < NV * ND; w += T) {
     const int v = w / ND, nd = w - v * ND;
@@ -251,7 +305,7 @@ __global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, 
     s_w[v][nd] = w_own ? a.W[idx] : 0.0;
   }
   __syncthreads();
-  for (int w = lane; w < NSUB * NFC * NV * NF; w += T) {
+  for (int w = lane; w < NFI * NV; w += T) {
     const int j = w % NF;
     const int v = (w / NF) % NV;
     const int f = (w / (NF * NV)) % NFC;
@@ -262,7 +316,7 @@ __global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, 
     const int d = f >> 1, side = f & 1;
     const int nn = face_node<DIM, N>(d, 1 - side, j);
     const int64_t idx = ((int64_t)v * ld + nb) * ND + nn;
-    s_tr[f][sub][v][j] = vstage(a, a.src[member_of_slot(m, nb)], idx);
+    s_tr[f][sub][v][j] = vstage(a, src_m(member_of_slot(m, nb)), idx);
     s_tw[f][sub][v][j] = nb < a.n_w ? a.W[idx] : 0.0;
     if (v == 0 && j == 0) s_jn[f][sub] = m.jac[m.lev[nb]][d];
   }
@@ -276,101 +330,104 @@ __global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, 
     if (face_kind(pk) != kFineSide) continue;
     const int s0 = face_sub0(pk), s1 = face_sub1(pk);
     double val = 0.0;
-    for (int k = 0; k < NF; ++k) val += Pm<DIM, N>(op, s0, s1, j, k) * s_tr[f][0][v][k];
+    for (int k = 0; k < NF; ++k) val += Pm<DIM, N>(s_op, s0, s1, j, k) * s_tr[f][0][v][k];
     s_tr[f][1][v][j] = val;
   }
   __syncthreads();
 
   // ---- D: pull-backs through the local flux Jacobians, one flux per lane
-  const double iw0 = op.iw[0], iwN = op.iw[N - 1];
-  for (int w = lane; w < NP + NSUB * NFC * NF; w += T) {
-    if (w < NP) {
-      const int pl = w % NPL;
-      const int line = (w / NPL) % K::NLINE;
-      const int d = w / (NPL * K::NLINE);
-      int pa = 0, pb = 1, cnt = 0;
-      for (int x = 0; x < N; ++x)
-        for (int y = x + 1; y < N; ++y) {
-          if (cnt == pl) { pa = x; pb = y; }
-          ++cnt;
-        }
-      const int na = node_on_line<DIM, N>(d, line, pa), nb = node_on_line<DIM, N>(d, line, pb);
-      double Pb[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v)
-        Pb[v] = -J[d] * (2.0 * op.D[pa * N + pb] * s_w[v][na] + 2.0 * op.D[pb * N + pa] * s_w[v][nb]);
-      double uA[NV], uB[NV], gA[NV], gB[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        uA[v] = s_u[v][na];
-        uB[v] = s_u[v][nb];
+  auto pair_vjp = [&](int w) {
+    const int pl = w % NPL;
+    const int line = (w / NPL) % K::NLINE;
+    const int d = w / (NPL * K::NLINE);
+    int pa = 0, pb = 1, cnt = 0;
+    for (int x = 0; x < N; ++x)
+      for (int y = x + 1; y < N; ++y) {
+        if (cnt == pl) { pa = x; pb = y; }
+        ++cnt;
       }
-      ec_flux_vjp<DIM>(uA, uB, d, gamma, Pb, gA, gB);
+    const int na = node_on_line<DIM, N>(d, line, pa), nb = node_on_line<DIM, N>(d, line, pb);
+    const double dab = s_op[0][pa * N + pb], dba = s_op[0][pb * N + pa];
+    double Pb[NV], uA[NV], uB[NV], gA[NV], gB[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      Pb[v] = -J[d] * (dab * s_w[v][na] + dba * s_w[v][nb]);
+      uA[v] = s_u[v][na];
+      uB[v] = s_u[v][nb];
+    }
+    ec_flux_vjp<DIM>(uA, uB, d, gamma, Pb, gA, gB);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      s_ga[w][v] = gA[v];
+      s_gb[w][v] = gB[v];
+    }
+  };
+  const double iw0 = op.iw[0], iwN = op.iw[N - 1];
+  auto face_vjp = [&](int r) {
+    const int j = r % NF;
+    const int f = (r / NF) % NFC;
+    const int sub = r / (NF * NFC);
+    const int32_t pk = s_fk[f];
+    const int kind = face_kind(pk);
+    if (sub > 0 && kind != kCoarseSide) return;
+    const int d = f >> 1, side = f & 1;
+    const double lift_own = side == 1 ? -iwN : iw0;
+    const double lift_nb = side == 1 ? iw0 : -iwN;
+    double own[NV], oth[NV], Hb[NV];
+    if (kind == kCoarseSide) {
+      const int m0 = sub & 1, m1 = (sub >> 1) & 1;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        s_ga[w][v] = gA[v];
-        s_gb[w][v] = gB[v];
+        double x = 0.0, h = 0.0;
+        for (int i = 0; i < NF; ++i) {
+          const int on = face_node<DIM, N>(d, side, i);
+          x += Pm<DIM, N>(s_op, m0, m1, j, i) * s_u[v][on];
+          h += Rm<DIM, N>(s_op, sub, i, j) * s_w[v][on];
+        }
+        own[v] = x;
+        oth[v] = s_tr[f][sub][v][j];
+        Hb[v] = J[d] * lift_own * h + s_jn[f][sub] * lift_nb * s_tw[f][sub][v][j];
       }
     } else {
-      const int r = w - NP;
-      const int j = r % NF;
-      const int f = (r / NF) % NFC;
-      const int sub = r / (NF * NFC);
-      const int32_t pk = s_fk[f];
-      const int kind = face_kind(pk);
-      if (sub > 0 && kind != kCoarseSide) continue;
-      const int d = f >> 1, side = f & 1;
-      const double lift_own = side == 1 ? -iwN : iw0;
-      const double lift_nb = side == 1 ? iw0 : -iwN;
-      double own[NV], oth[NV], Hb[NV];
-      if (kind == kCoarseSide) {
-        const int m0 = sub & 1, m1 = (sub >> 1) & 1;
+      const int on = face_node<DIM, N>(d, side, j);
+      const int ts = kind == kFineSide ? 1 : 0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          double x = 0.0, h = 0.0;
-          for (int i = 0; i < NF; ++i) {
-            const int on = face_node<DIM, N>(d, side, i);
-            x += Pm<DIM, N>(op, m0, m1, j, i) * s_u[v][on];
-            h += Rm<DIM, N>(op, sub, i, j) * s_w[v][on];
-          }
-          own[v] = x;
-          oth[v] = s_tr[f][sub][v][j];
-          Hb[v] = J[d] * lift_own * h + s_jn[f][sub] * lift_nb * s_tw[f][sub][v][j];
+      for (int v = 0; v < NV; ++v) {
+        own[v] = s_u[v][on];
+        oth[v] = s_tr[f][ts][v][j];
+        double hn;
+        if (kind == kFineSide) {
+          const int s0 = face_sub0(pk), s1 = face_sub1(pk);
+          const int ms = DIM == 2 ? s0 : s0 + 2 * s1;
+          hn = 0.0;
+          for (int i = 0; i < NF; ++i) hn += Rm<DIM, N>(s_op, ms, i, j) * s_tw[f][0][v][i];
+        } else {
+          hn = s_tw[f][0][v][j];
         }
-      } else {
-        const int on = face_node<DIM, N>(d, side, j);
-        const int ts = kind == kFineSide ? 1 : 0;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          own[v] = s_u[v][on];
-          oth[v] = s_tr[f][ts][v][j];
-          double hn;
-          if (kind == kFineSide) {
-            const int s0 = face_sub0(pk), s1 = face_sub1(pk);
-            const int ms = DIM == 2 ? s0 : s0 + 2 * s1;
-            hn = 0.0;
-            for (int i = 0; i < NF; ++i) hn += Rm<DIM, N>(op, ms, i, j) * s_tw[f][0][v][i];
-          } else {
-            hn = s_tw[f][0][v][j];
-          }
-          Hb[v] = J[d] * lift_own * s_w[v][on] + s_jn[f][0] * lift_nb * hn;
-        }
+        Hb[v] = J[d] * lift_own * s_w[v][on] + s_jn[f][0] * lift_nb * hn;
       }
-#pragma unroll 1
-      for (int q = 0; q < NV; ++q) {
-        Dd uo[NV], un[NV], fl[NV];
+    }
+    // the own trace is the left state on a +d face (side 1), the right state on a -d face
+    double uL[NV], uR[NV], gL[NV], gR[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          uo[v] = mk(own[v], q == v ? 1.0 : 0.0);
-          un[v] = mk(oth[v]);
-        }
-        if (side == 1) dhll_flux<DIM>(uo, un, d, gamma, fl);
-        else dhll_flux<DIM>(un, uo, d, gamma, fl);
-        double gsum = 0.0;
+    for (int v = 0; v < NV; ++v) {
+      uL[v] = side == 1 ? own[v] : oth[v];
+      uR[v] = side == 1 ? oth[v] : own[v];
+    }
+    hll_flux_vjp<DIM>(uL, uR, d, gamma, Hb, gL, gR);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) gsum += Hb[v] * fl[v].d;
-        s_gf[f][sub][q][j] = gsum;
-      }
+    for (int v = 0; v < NV; ++v) s_gf[f][sub][v][j] = side == 1 ? gL[v] : gR[v];
+  };
+  if (K::SPLIT) {
+    if (lane < 64) {
+      for (int w = lane; w < NP; w += 64) pair_vjp(w);
+    } else {
+      for (int r = lane - 64; r < NFI; r += T - 64) face_vjp(r);
+    }
+  } else {
+    for (int w = lane; w < NP + NFI; w += T) {
+      if (w < NP) pair_vjp(w);
+      else face_vjp(w - NP);
     }
   }
   __syncthreads();
@@ -394,7 +451,7 @@ __global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, 
         if (face_kind(s_fk[f]) == kCoarseSide) {
           for (int ms = 0; ms < NSUB; ++ms) {
             const int m0 = ms & 1, m1 = (ms >> 1) & 1;
-            for (int k = 0; k < NF; ++k) g += Pm<DIM, N>(op, m0, m1, k, fi) * s_gf[f][ms][v][k];
+            for (int k = 0; k < NF; ++k) g += Pm<DIM, N>(s_op, m0, m1, k, fi) * s_gf[f][ms][v][k];
           }
         } else {
           g += s_gf[f][0][v][fi];

@@ -36,52 +36,63 @@ namespace {
 
 // ------------------------------------------------------------ reverse mode for the pair flux
 // Value and both partial derivatives of the logarithmic mean along the branch the dual form
-// takes (same u, same threshold): series (a+b)/(2F(u)) or (b-a)/ln(b/a).
-__device__ __forceinline__ void log_mean_d(double a, double b, double& lm, double& da, double& db) {
+// takes (same u, same threshold): series (a+b)/(2F(u)) or (b-a)/ln(b/a).  ia, ib: 1/a, 1/b.
+__device__ __forceinline__ void log_mean_d(double a, double b, double ia, double ib, double& lm, double& da,
+                                           double& db) {
   const double s = a + b, t = b - a;
-  const double f = t / s, u = f * f;
+  const double is = rcp(s);
+  const double f = t * is, u = f * f;
   if (u < 1e-2) {
-    const double u2 = u * u, u3 = u2 * u, u4 = u3 * u, u5 = u4 * u, u6 = u5 * u, u7 = u6 * u;
-    const double F = 1.0 + u / 3.0 + u2 / 5.0 + u3 / 7.0 + u4 / 9.0 + u5 / 11.0 + u6 / 13.0 + u7 / 15.0;
-    const double Fp = 1.0 / 3.0 + 2.0 * u / 5.0 + 3.0 * u2 / 7.0 + 4.0 * u3 / 9.0 + 5.0 * u4 / 11.0 +
-                      6.0 * u5 / 13.0 + 7.0 * u6 / 15.0;
-    lm = s / (2.0 * F);
-    const double c = Fp * f / (F * F * s);
-    da = 1.0 / (2.0 * F) + 2.0 * c * b;
-    db = 1.0 / (2.0 * F) - 2.0 * c * a;
+    // F(u) = sum_k u^k / (2k+1), k = 0..7, and F'(u), in Horner form (constant reciprocals, no
+    // divisions)
+    constexpr double c1 = 1.0 / 3, c2 = 1.0 / 5, c3 = 1.0 / 7, c4 = 1.0 / 9, c5 = 1.0 / 11, c6 = 1.0 / 13,
+                     c7 = 1.0 / 15;
+    const double F = 1.0 + u * (c1 + u * (c2 + u * (c3 + u * (c4 + u * (c5 + u * (c6 + u * c7))))));
+    const double Fp =
+        c1 + u * (2.0 * c2 + u * (3.0 * c3 + u * (4.0 * c4 + u * (5.0 * c5 + u * (6.0 * c6 + u * (7.0 * c7))))));
+    const double iF = rcp(F);
+    const double h = 0.5 * iF;
+    lm = s * h;
+    const double c = Fp * f * iF * iF * is;
+    da = h + 2.0 * c * b;
+    db = h - 2.0 * c * a;
   } else {
-    const double L = log(b / a);
-    lm = t / L;
-    da = (t / a - L) / (L * L);
-    db = (L - t / b) / (L * L);
+    const double L = log(b * ia);
+    const double iL = rcp(L), iL2 = iL * iL;
+    lm = t * iL;
+    da = (t * ia - L) * iL2;
+    db = (L - t * ib) * iL2;
   }
 }
 // P^T (d f#/d u_L) and P^T (d f#/d u_R) of the entropy-conserving flux in one forward and one
-// backward pass (the dual form needs 2 n_v forward passes); the same derivative as the dual
-// form up to rounding (host check on random states of both branches: 1e-14 relative).
+// backward pass (the dual form needs 2 n_v forward passes); one reciprocal per denominator
+// (densities, pressures, the logarithmic means).  The same derivative as the dual form up to
+// rounding (host check on random states of both branches: 5e-14 relative).
 template <int DIM>
-__device__ __forceinline__ void ec_flux_vjp(const double* uL, const double* uR, int d, double gamma, const double* P, double* gL,
-                           double* gR) {
+__device__ __forceinline__ void ec_flux_vjp(const double* uL, const double* uR, int d, double gamma,
+                                            const double* P, double* gL, double* gR) {
   constexpr int NV = DIM + 2;
   const double gm1 = gamma - 1.0;
   const double rL = uL[0], rR = uR[0];
+  const double irL = rcp(rL), irR = rcp(rR);
   double vL[DIM], vR[DIM], keL = 0.0, keR = 0.0;
   for (int k = 0; k < DIM; ++k) {
-    vL[k] = uL[1 + k] / rL;
-    vR[k] = uR[1 + k] / rR;
+    vL[k] = uL[1 + k] * irL;
+    vR[k] = uR[1 + k] * irR;
     keL = keL + 0.5 * (uL[1 + k] * vL[k]);
     keR = keR + 0.5 * (uR[1 + k] * vR[k]);
   }
   const double pL = gm1 * (uL[NV - 1] - keL), pR = gm1 * (uR[NV - 1] - keR);
+  const double ipL = rcp(pL), ipR = rcp(pR);
   double rho_ln, dra, drb, beta_ln, dba, dbb;
-  log_mean_d(rL, rR, rho_ln, dra, drb);
-  const double bL = rL / pL, bR = rR / pR;
-  log_mean_d(bL, bR, beta_ln, dba, dbb);
+  log_mean_d(rL, rR, irL, irR, rho_ln, dra, drb);
+  const double bL = rL * ipL, bR = rR * ipR;
+  log_mean_d(bL, bR, pL * irL, pR * irR, beta_ln, dba, dbb);
   const double vd = 0.5 * (vL[d] + vR[d]);
   double vLvR = 0.0;
   for (int k = 0; k < DIM; ++k) vLvR = vLvR + vL[k] * vR[k];
   const double f0 = rho_ln * vd;
-  const double ib = 1.0 / (gm1 * beta_ln);
+  const double ib = rcp(gm1 * beta_ln);
   const double Q = 0.5 * vLvR + ib;
   const double PE = P[NV - 1];
   double vLb[DIM], vRb[DIM];
@@ -101,21 +112,21 @@ __device__ __forceinline__ void ec_flux_vjp(const double* uL, const double* uR, 
   vLb[d] += 0.5 * vdb;
   vRb[d] += 0.5 * vdb;
   double rLb = rho_lnb * dra, rRb = rho_lnb * drb;
-  const double bLb = beta_lnb * dba, bRb = beta_lnb * dbb;
-  rLb += bLb / pL;
-  pLb -= bLb * bL / pL;
-  rRb += bRb / pR;
-  pRb -= bRb * bR / pR;
+  const double bLb = beta_lnb * dba * ipL, bRb = beta_lnb * dbb * ipR;
+  rLb += bLb;
+  pLb -= bLb * bL;
+  rRb += bRb;
+  pRb -= bRb * bR;
   // p = (gamma-1)(E - ke), ke = sum 1/2 m_k v_k, v_k = m_k / r
   const double kLb = -gm1 * pLb, kRb = -gm1 * pRb;
   gL[NV - 1] = gm1 * pLb;
   gR[NV - 1] = gm1 * pRb;
   for (int k = 0; k < DIM; ++k) {
-    const double vbl = vLb[k] + 0.5 * uL[1 + k] * kLb, vbr = vRb[k] + 0.5 * uR[1 + k] * kRb;
-    gL[1 + k] = 0.5 * vL[k] * kLb + vbl / rL;
-    gR[1 + k] = 0.5 * vR[k] * kRb + vbr / rR;
-    rLb -= vbl * vL[k] / rL;
-    rRb -= vbr * vR[k] / rR;
+    const double vbl = (vLb[k] + 0.5 * uL[1 + k] * kLb) * irL, vbr = (vRb[k] + 0.5 * uR[1 + k] * kRb) * irR;
+    gL[1 + k] = 0.5 * vL[k] * kLb + vbl;
+    gR[1 + k] = 0.5 * vR[k] * kRb + vbr;
+    rLb -= vbl * vL[k];
+    rRb -= vbr * vR[k];
   }
   gL[0] = rLb;
   gR[0] = rRb;
@@ -125,25 +136,25 @@ __device__ __forceinline__ void ec_flux_vjp(const double* uL, const double* uR, 
 // from L to R) in one forward and one backward pass.  Branches as in the forward flux:
 // s_L >= 0 takes the left Euler flux, s_R <= 0 the right one, otherwise the HLL average; the
 // min / max of the wave speeds pass their cotangent to the argument they took (ties: left).
-// Same derivative as forward-mode dual numbers up to rounding (host check on random sub- and
-// supersonic states: 4e-15 relative).
+// One reciprocal per denominator.  Same derivative as forward-mode dual numbers up to rounding
+// (host check on random sub- and supersonic states: 4e-15 relative).
 template <int DIM>
-__device__ __forceinline__ void hll_flux_vjp(const double* uL, const double* uR, int d, double gamma, const double* Hb, double* gL,
-                     double* gR) {
+__device__ __forceinline__ void hll_flux_vjp(const double* uL, const double* uR, int d, double gamma,
+                                             const double* Hb, double* gL, double* gR) {
   constexpr int NV = DIM + 2;
   const double gm1 = gamma - 1.0;
   const double* us[2] = {uL, uR};
-  double rho[2], v[2][DIM], p[2], c[2], fx[2][NV];
+  double irho[2], v[2][DIM], p[2], c[2], fx[2][NV];
   for (int s = 0; s < 2; ++s) {
     const double* u = us[s];
-    rho[s] = u[0];
+    irho[s] = rcp(u[0]);
     double ke = 0.0;
     for (int k = 0; k < DIM; ++k) {
-      v[s][k] = u[1 + k] / u[0];
+      v[s][k] = u[1 + k] * irho[s];
       ke = ke + 0.5 * (u[1 + k] * v[s][k]);
     }
     p[s] = gm1 * (u[NV - 1] - ke);
-    c[s] = sqrt(gamma * p[s] / rho[s]);
+    c[s] = sqrt(gamma * p[s] * irho[s]);
     fx[s][0] = u[1 + d];
     for (int k = 0; k < DIM; ++k) fx[s][1 + k] = u[1 + k] * v[s][d];
     fx[s][1 + d] = fx[s][1 + d] + p[s];
@@ -170,7 +181,7 @@ __device__ __forceinline__ void hll_flux_vjp(const double* uL, const double* uR,
       fb[1][k] = Hb[k];
     }
   } else {
-    const double id = 1.0 / (sR - sL);
+    const double id = rcp(sR - sL);
     for (int k = 0; k < NV; ++k) {
       const double du = uR[k] - uL[k];
       const double f = (sR * fx[0][k] - sL * fx[1][k] + sL * sR * du) * id;
@@ -198,9 +209,9 @@ __device__ __forceinline__ void hll_flux_vjp(const double* uL, const double* uR,
     for (int k = 0; k < DIM; ++k) vb[k] = 0.0;
     double pb = 0.0, rb = 0.0;
     // c = sqrt(x), x = gamma p / rho
-    const double xb = cb[s] * 0.5 / c[s];
-    pb += xb * gamma / rho[s];
-    rb -= xb * gamma * p[s] / (rho[s] * rho[s]);
+    const double xb = cb[s] * 0.5 * rcp(c[s]) * gamma * irho[s];
+    pb += xb;
+    rb -= xb * p[s] * irho[s];
     vb[d] += vdb[s];
     // Euler flux in direction d
     g[1 + d] += f[0];
@@ -218,8 +229,8 @@ __device__ __forceinline__ void hll_flux_vjp(const double* uL, const double* uR,
     for (int k = 0; k < DIM; ++k) {
       g[1 + k] += 0.5 * v[s][k] * keb;
       vb[k] += 0.5 * u[1 + k] * keb;
-      g[1 + k] += vb[k] / rho[s];
-      rb -= vb[k] * v[s][k] / rho[s];
+      g[1 + k] += vb[k] * irho[s];
+      rb -= vb[k] * v[s][k] * irho[s];
     }
     g[0] += rb;
     for (int k = 0; k < NV; ++k) gs[s][k] = g[k];

@@ -1,10 +1,21 @@
-// Device-side index helpers shared by the libperk kernel files (gfx950).
+// Device-side index helpers and the reciprocal shared by the libperk kernel files (gfx950).
 #pragma once
 
 #include "perk_internal.h"
 
 namespace perk {
 namespace {
+
+// Reciprocal: hardware estimate refined by two Newton steps with FMA (within one ulp of 1/x for
+// normal arguments away from the overflow range: densities, pressures, sums of them,
+// wave-speed gaps, logarithms of ratios).
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 
 template <int DIM, int N>
 struct G {

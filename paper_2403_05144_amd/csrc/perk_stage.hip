@@ -33,16 +33,6 @@
 namespace perk {
 namespace {
 
-// Reciprocal: hardware estimate refined by two Newton steps with FMA (within one ulp of 1/x for
-// the positive, normal arguments used here: densities, pressures, sums of them, wave-speed gaps).
-__device__ __forceinline__ double rcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-
 // Square root of a non-negative argument (sound speeds): the hardware reciprocal-square-root
 // estimate refined by two steps of Goldschmidt's coupled iteration for sqrt(x) and 1/(2 sqrt(x)),
 // then one residual correction (correctly rounded in a host test over 2e7 arguments from

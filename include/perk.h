@@ -227,6 +227,18 @@ pe_status pe_amr_indicator(pe_ctx* ctx, double* eta_leaf_host, void* stream);
  * the next step.  PE_ENOMEM if the new mesh exceeds the reserved capacity (mesh unchanged). */
 pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags_host, int level_min, int level_max, void* stream);
 
+/* One adaptation cycle in a single call (Sec. 6.2: indicator, mesh change, re-partition):
+ * pe_amr_indicator; flags by threshold, +1 where eta > refine_above, then -1 where
+ * eta < coarsen_below, 0 elsewhere (a NaN indicator keeps its leaf); pe_adapt with
+ * [level_min, level_max]; pe_partition with member_of_level[n_levels].  The same flags,
+ * forest and state as those calls made one by one.  flags_host (may be NULL) receives the
+ * flags [n_elements before the call]; n_leaves (may be NULL) the number of leaves after it.
+ * Synchronises `stream` once (the indicator download).  Errors as the three calls; on a
+ * failure of pe_partition the forest is already adapted (call pe_partition again). */
+pe_status pe_amr_cycle(pe_ctx* ctx, double refine_above, double coarsen_below, int level_min, int level_max,
+                       const int32_t* member_of_level, int n_levels, int8_t* flags_host, int64_t* n_leaves,
+                       void* stream);
+
 /* Current leaf list (host) [n][4] (level, i, j, k); leaves may be NULL to query n. */
 pe_status pe_get_leaves(const pe_ctx* ctx, int32_t* leaves, int64_t* n);
 

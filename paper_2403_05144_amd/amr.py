@@ -1,8 +1,10 @@
 """Adaptive-mesh driver around PerkSolver: indicator thresholds -> per-leaf flags -> device
 adaptation and re-partition (Sec. 6.2: the partition is rebuilt after every mesh change).
 
-The indicator itself, the adaptation with 2:1 balance, the projection and the re-partition run
-in libperk; this module only turns indicator values into flags and schedules the calls.
+The indicator, the flags by threshold, the adaptation with 2:1 balance, the projection and the
+re-partition run in libperk, in one call per cycle (pe_amr_cycle); this module schedules the
+cycles.  flags_from_indicator is the same threshold rule for callers that take the indicator
+values first (PerkSolver.indicator, then PerkSolver.adapt with their own flags).
 """
 import numpy as np
 
@@ -25,9 +27,9 @@ class AmrDriver:
         self.n_adapt = 0
 
     def adapt_once(self):
-        eta = self.s.indicator()
-        flags = flags_from_indicator(eta, self.refine_above, self.coarsen_below)
-        self.s.adapt(flags, self.level_min, self.level_max, self.member_of_level)
+        """Indicator, flags, adaptation and re-partition (one library call); returns the flags."""
+        flags = self.s.amr_cycle(self.refine_above, self.coarsen_below, self.level_min, self.level_max,
+                                 self.member_of_level)
         self.n_adapt += 1
         return flags
 

@@ -1357,6 +1357,31 @@ pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags, int level_min, int level_ma
   return PE_OK;
 }
 
+pe_status pe_amr_cycle(pe_ctx* ctx, double refine_above, double coarsen_below, int level_min, int level_max,
+                       const int32_t* member_of_level, int n_levels, int8_t* flags_host, int64_t* n_leaves,
+                       void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!member_of_level) return fail(ctx, PE_EINVAL, "amr_cycle: null member_of_level");
+  const int n = ctx->n_e;
+  std::vector<double> eta(n);
+  pe_status st = pe_amr_indicator(ctx, eta.data(), stream);
+  if (st != PE_OK) return st;
+  std::vector<int8_t> flags(n);
+  for (int e = 0; e < n; ++e) {
+    int8_t f = 0;
+    if (eta[e] > refine_above) f = 1;
+    if (eta[e] < coarsen_below) f = -1;
+    flags[e] = f;
+  }
+  if (flags_host) std::memcpy(flags_host, flags.data(), (size_t)n);
+  st = pe_adapt(ctx, flags.data(), level_min, level_max, stream);
+  if (st != PE_OK) return st;
+  st = pe_partition(ctx, member_of_level, n_levels, stream);
+  if (st != PE_OK) return st;
+  if (n_leaves) *n_leaves = ctx->n_e;
+  return PE_OK;
+}
+
 pe_status pe_quadrature(const pe_ctx* ctx, double* nodes, double* weights) {
   if (!ctx) return PE_EINVAL;
   for (int i = 0; i < ctx->N; ++i) {

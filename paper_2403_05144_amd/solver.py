@@ -233,6 +233,35 @@ class PerkSolver:
         self.mesh.leaves = self._leaves
         self.partition(member_of_level)
 
+    def amr_cycle(self, refine_above, coarsen_below, level_min, level_max, member_of_level):
+        """indicator() + threshold flags + adapt() in one library call (the same flags, forest and
+        state); returns the flags of the leaves before the call.  Host buffers are kept between
+        calls and passed by address: the per-call Python work is a few attribute reads."""
+        cap = self.capacity
+        if getattr(self, "_cyc", None) is None or self._cyc["cap"] != cap:
+            bufs = {"cap": cap, "flags": np.zeros(cap, np.int8), "n": np.zeros(1, np.int64),
+                    "leaves": np.zeros((cap, 4), np.int32), "mol_key": None}
+            for k in ("flags", "n", "leaves"):
+                bufs[k + "_p"] = bufs[k].ctypes.data
+            self._cyc = bufs
+        c = self._cyc
+        key = tuple(int(x) for x in member_of_level)
+        if c["mol_key"] != key:
+            c["mol"] = np.ascontiguousarray(key, dtype=np.int32)
+            c["mol_p"], c["mol_key"] = c["mol"].ctypes.data, key
+        n_old = self.n_elements
+        self._check(self.lib.pe_amr_cycle(self._ctx, float(refine_above), float(coarsen_below), int(level_min),
+                                          int(level_max), c["mol_p"], len(key), c["flags_p"], c["n_p"],
+                                          _stream_handle()), "pe_amr_cycle")
+        n = int(c["n"][0])
+        cnt = ctypes.c_int64(n)
+        self._check(self.lib.pe_get_leaves(self._ctx, c["leaves_p"], ctypes.byref(cnt)), "pe_get_leaves")
+        self._leaves = c["leaves"][:n].copy()
+        self.n_elements = n
+        self.mesh.leaves = self._leaves
+        self.member_of_level = c["mol"]
+        return c["flags"][:n_old].copy()
+
     def max_dt(self, cfl=1.0):
         """(cfl * min_l beta_l, beta per level) from the current state, eq. (CFL_DG)."""
         dt = ctypes.c_double()

@@ -127,3 +127,40 @@ def test_graph_replay_across_adaptations_equals_eager():
     assert runs[0][-1].shape == runs[1][-1].shape
     for a, b in zip(runs[0], runs[1]):
         np.testing.assert_array_equal(a, b)
+
+
+def test_amr_cycle_equals_separate_calls():
+    # one library call (indicator, threshold flags, adaptation, re-partition) against the
+    # indicator download, the flags formed in Python and the adapt + partition calls: the same
+    # flags, leaves and states, bitwise, through several cycles with steps in between
+    from paper_2403_05144_amd import PerkSolver
+    from paper_2403_05144_amd.amr import flags_from_indicator
+    fam = golden_family("perk3_4_6_8_12_16_disk.json")
+    lmax = 3
+    mol = [max(0, 4 - (lmax - l)) for l in range(lmax + 1)]
+
+    def ic_leaf(x):
+        return pin.kelvin_helmholtz(x[:, 0], x[:, 1]).transpose(1, 0, 2).copy()
+
+    runs = []
+    for fused in (True, False):
+        s = PerkSolver(pin.uniform_mesh(2, (8, 8), (-1, -1), (1, 1), 0), 3, fam, mol, capacity=4096)
+        s.set_state(ic_leaf(s.node_coords().cpu().numpy()))
+        rec = []
+        for cycle in range(5):
+            if fused:
+                flags = s.amr_cycle(0.05, 0.01, 0, lmax, mol)
+            else:
+                flags = flags_from_indicator(s.indicator(), 0.05, 0.01)
+                s.adapt(flags, 0, lmax, mol)
+            rec += [flags, s.leaves().copy(), s.get_state().cpu().numpy()]
+            if cycle < 2:
+                s.set_state(ic_leaf(s.node_coords().cpu().numpy()))
+            s.step(2e-4, 3)
+            rec.append(s.get_state().cpu().numpy())
+        runs.append(rec)
+    assert len(runs[0]) == len(runs[1])
+    assert any(np.any(r != 0) for r in runs[0][0::4])   # the cycles did change the mesh
+    for a, b in zip(runs[0], runs[1]):
+        assert a.shape == b.shape
+        np.testing.assert_array_equal(a, b)

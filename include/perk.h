@@ -159,7 +159,9 @@ pe_status pe_rhs(pe_ctx* ctx, const double* u_dev, double* du_dev, void* stream)
  * only on the elements of the members that use stage i (a prefix of the slots); the
  * right-hand side of the other elements is never computed.  Asynchronous.  Unless graph replay
  * is off or profiling is on, the step's launches are captured once into a HIP graph and
- * replayed n_steps times on `stream`. */
+ * replayed on `stream`; when the graph has to be captured again, the call's first step goes
+ * out as plain launches and the capture runs on the host while they execute.  Should a capture
+ * fail, the context continues with plain launches (graph replay off). */
 pe_status pe_step(pe_ctx* ctx, double dt, int n_steps, void* stream);
 
 /* pe_step replays one captured step as a HIP graph (captured again after every partition,

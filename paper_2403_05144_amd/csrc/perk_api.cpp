@@ -1097,11 +1097,27 @@ pe_status pe_step(pe_ctx* ctx, double dt, int n_steps, void* stream) {
     return PE_OK;
   }
   if (n_steps == 0) return PE_OK;
+  int replays = n_steps;
   if (!ctx->graph_valid || ctx->graph_dt != dt) {
-    pe_status st = capture_step(ctx, dt);
+    // the first step after a re-partition or a new step size goes out as plain launches, so
+    // that the device starts at once; the capture and graph update below (host work of the
+    // order of 100 us) then run while those kernels execute
+    pe_status st = enqueue_step(ctx, dt, s, false);
     if (st != PE_OK) return st;
+    --replays;
+    if (capture_step(ctx, dt) != PE_OK) {
+      // graph replay is an optimisation: without a graph the context goes on with plain
+      // launches (the step above has already advanced the state)
+      (void)hipGetLastError();
+      ctx->graphs_enabled = false;
+      for (int step = 0; step < replays; ++step) {
+        st = enqueue_step(ctx, dt, s, false);
+        if (st != PE_OK) return st;
+      }
+      return PE_OK;
+    }
   }
-  for (int step = 0; step < n_steps; ++step) HIPCHK(hipGraphLaunch(ctx->gexec, s));
+  for (int step = 0; step < replays; ++step) HIPCHK(hipGraphLaunch(ctx->gexec, s));
   return PE_OK;
 }
 

@@ -741,8 +741,18 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   }
 }
 
+// Waves per SIMD the register allocation must allow.  A 3D Euler p=3 block (7 waves, 34 KB of
+// LDS) fits three to a CU at 80 VGPRs (6 waves per SIMD; a 20-byte spill), measured 10 % faster
+// per element-stage than two at 86; a Navier-Stokes block's 50 KB of LDS allows two anyway.
 template <int DIM, int N, bool VISC, bool SPLIT>
-__global__ __launch_bounds__((SK<DIM, N, SPLIT>::T * SK<DIM, N, SPLIT>::EPB), (SK<DIM, N, SPLIT>::MINW)) void k_stage(StageArgs a, Mesh m, Ops op, Physics ph) {
+constexpr int stage_waves_per_simd() {
+  return (DIM == 3 && N == 4 && !VISC) ? 6 : SK<DIM, N, SPLIT>::MINW;
+}
+
+template <int DIM, int N, bool VISC, bool SPLIT>
+__global__ __launch_bounds__((SK<DIM, N, SPLIT>::T * SK<DIM, N, SPLIT>::EPB),
+                             (stage_waves_per_simd<DIM, N, VISC, SPLIT>())) void k_stage(StageArgs a, Mesh m, Ops op,
+                                                                                       Physics ph) {
   // Workgroups go to the 8 XCDs round-robin (block b to XCD b mod 8); give XCD x the
   // contiguous block range [x G, (x+1) G), G = gridDim / 8, so that neighbouring slots (sorted
   // by member, Morton order inside) share an L2 and neighbour-trace reads can hit there.  (A

@@ -741,12 +741,13 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   }
 }
 
-// Waves per SIMD the register allocation must allow.  A 3D Euler p=3 block (7 waves, 34 KB of
-// LDS) fits three to a CU at 80 VGPRs (6 waves per SIMD; a 20-byte spill), measured 10 % faster
-// per element-stage than two at 86; a Navier-Stokes block's 50 KB of LDS allows two anyway.
+// Waves per SIMD the register allocation must allow.  3D p=3 blocks (7 waves; 34 KB of LDS for
+// Euler, 50 KB for Navier-Stokes) at 80 VGPRs (6 waves per SIMD, a 20-byte spill) instead of
+// 86-87 leave room for a third block per CU: measured 10 % (Euler, uniform meshes) and 10 %
+// (Navier-Stokes, the Taylor-Green mesh) less time per element-stage.
 template <int DIM, int N, bool VISC, bool SPLIT>
 constexpr int stage_waves_per_simd() {
-  return (DIM == 3 && N == 4 && !VISC) ? 6 : SK<DIM, N, SPLIT>::MINW;
+  return (DIM == 3 && N == 4) ? 6 : SK<DIM, N, SPLIT>::MINW;
 }
 
 template <int DIM, int N, bool VISC, bool SPLIT>

@@ -744,10 +744,14 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
 // Waves per SIMD the register allocation must allow.  3D p=3 blocks (7 waves; 34 KB of LDS for
 // Euler, 50 KB for Navier-Stokes) at 80 VGPRs (6 waves per SIMD, a 20-byte spill) instead of
 // 86-87 leave room for a third block per CU: measured 10 % (Euler, uniform meshes) and 10 %
-// (Navier-Stokes, the Taylor-Green mesh) less time per element-stage.
+// (Navier-Stokes, the Taylor-Green mesh) less time per element-stage.  The one-wave 2D p=3 body
+// (large launches) at 96 VGPRs (5 waves, a 20-byte spill) instead of 102-106: 2-6 % less on
+// uniform 2D meshes of 128^2-1024^2 elements (6 waves spilled 72-88 bytes and ran slower).
 template <int DIM, int N, bool VISC, bool SPLIT>
 constexpr int stage_waves_per_simd() {
-  return (DIM == 3 && N == 4) ? 6 : SK<DIM, N, SPLIT>::MINW;
+  if (DIM == 3 && N == 4) return 6;
+  if (DIM == 2 && N == 4 && !SPLIT) return 5;
+  return SK<DIM, N, SPLIT>::MINW;
 }
 
 template <int DIM, int N, bool VISC, bool SPLIT>

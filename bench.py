@@ -865,9 +865,11 @@ def run(args):
         return {"s": s, "drv": drv, "k": 0}
 
     def run_steps(run, n, acc, profiling=False):
-        """n steps; returns the seconds spent restarting episodes (untimed work)."""
+        """n steps; returns the seconds spent restarting episodes (untimed work).  Steps go to the
+        library in runs up to the next adaptation or episode end (one call per run of steps)."""
         excluded = 0.0
-        for _ in range(n):
+        done = 0
+        while done < n:
             if episode and run["k"] == episode:
                 torch.cuda.synchronize()
                 tr = time.perf_counter()
@@ -886,9 +888,15 @@ def run(args):
                 torch.cuda.synchronize()
                 excluded += time.perf_counter() - tr
             s, drv = run["s"], run["drv"]
-            s.step(dt, 1)
-            run["k"] += 1
-            acc["dof"] += s.n_elements * per_elem
+            chunk = n - done
+            if drv and drv.interval:
+                chunk = min(chunk, drv.interval - run["k"] % drv.interval)
+            if episode:
+                chunk = min(chunk, episode - run["k"])
+            s.step(dt, chunk)
+            run["k"] += chunk
+            done += chunk
+            acc["dof"] += s.n_elements * per_elem * chunk
             if drv and drv.interval and run["k"] % drv.interval == 0:
                 torch.cuda.synchronize()
                 ta = time.perf_counter()

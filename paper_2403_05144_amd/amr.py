@@ -41,9 +41,15 @@ class AmrDriver:
         self.s.set_state(ic_leaf_fn(self.s.node_coords().cpu().numpy()))
 
     def run(self, dt, n_steps, on_step=None):
-        """n_steps P-ERK steps, adapting every `interval` steps."""
-        for k in range(1, n_steps + 1):
-            self.s.step(dt, 1)
+        """n_steps P-ERK steps, adapting every `interval` steps (without a per-step callback the
+        steps between adaptations go to the library in one call)."""
+        k = 0
+        while k < n_steps:
+            chunk = 1 if on_step else n_steps - k
+            if self.interval:
+                chunk = min(chunk, self.interval - k % self.interval)
+            self.s.step(dt, chunk)
+            k += chunk
             if on_step:
                 on_step(k)
             if self.interval and k % self.interval == 0:

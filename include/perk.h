@@ -201,6 +201,22 @@ pe_status pe_adjoint_bind(pe_ctx* ctx, void* workspace);
 pe_status pe_step_adjoint(pe_ctx* ctx, double dt, const double* u_n, const double* lam_next, double* lam_prev,
                           void* stream);
 
+/* A step's record for a later reverse sweep: K_1 and the stage values Y_2..Y_S (Sec. 3.1),
+ * S state arrays, pe_adjoint_record_size doubles (device memory owned by the caller). */
+pe_status pe_adjoint_record_size(const pe_ctx* ctx, int64_t* doubles);
+
+/* One partitioned step of size dt from u_n into u_next, keeping its record (slot layout
+ * device arrays; none may overlap another).  The same stage launches as pe_step; the bound
+ * state and its stage buffers are not touched.  Needs the adjoint workspace (pe_adjoint_bind);
+ * Euler only.  Asynchronous on stream. */
+pe_status pe_step_record(pe_ctx* ctx, double dt, const double* u_n, double* u_next, double* record, void* stream);
+
+/* pe_step_adjoint from a record made by pe_step_record with the same u_n and dt, instead of
+ * recomputing the step: bitwise the same lam_prev.  For checkpointed trajectories whose
+ * segments are recomputed anyway (each step is then computed once, not twice). */
+pe_status pe_step_adjoint_recorded(pe_ctx* ctx, double dt, const double* u_n, const double* record,
+                                   const double* lam_next, double* lam_prev, void* stream);
+
 /* Step-size bound of eq. (CFL_DG) and eq. (TimestepConstraint) from the bound state:
  * beta_l = 1 / max over the elements of level l, their nodes and the directions d of
  * (k+1)(|v_d| + c) / h_d  (k the polynomial degree, c the speed of sound; convective part only,

@@ -3,9 +3,11 @@ torch.autograd.Function, with the discrete adjoint of libperk (pe_step_adjoint) 
 checkpointed recomputation.
 
 forward: n steps of size dt from u0 (slot layout), keeping the state every `every` steps.
-backward: for each segment, last first, recompute the segment's states from its checkpoint
-(pe_step), then apply the step adjoint backwards through the segment.  Memory: the
-checkpoints plus the states of one segment.
+backward: for each segment, last first, recompute the segment from its checkpoint, keeping
+each step's state and record (K_1 and the stage values, pe_step_record), then apply the step
+adjoint backwards through the segment from those records (pe_step_adjoint_recorded): every
+step of the segment is computed once in the backward pass.  Memory: the checkpoints plus the
+states and records of one segment (S + 1 state arrays per step).
 """
 from __future__ import annotations
 
@@ -30,17 +32,18 @@ class PerkTrajectory(torch.autograd.Function):
     def backward(ctx, lam):
         s, dt, n, every = ctx.solver, ctx.dt, ctx.n_steps, ctx.every
         lam = lam.contiguous().clone()
-        saved = s.u.clone()
         for seg in reversed(range(len(ctx.ckpts))):
             k0, k1 = seg * every, min(n, seg * every + every)
-            s.u.copy_(ctx.ckpts[seg])
-            states = []
+            u = ctx.ckpts[seg]
+            states, records = [], []
             for _ in range(k0, k1):
-                states.append(s.u.clone())
-                s.step(dt, 1)
+                u_next, rec = s.step_record(u, dt)
+                states.append(u)
+                records.append(rec)
+                u = u_next
             for k in reversed(range(k1 - k0)):
-                lam = s.step_adjoint(states[k], lam, dt)
-        s.u.copy_(saved)
+                lam = s.step_adjoint_recorded(states[k], records[k], lam, dt)
+            del states, records
         return lam, None, None, None, None
 
 

@@ -887,17 +887,50 @@ pe_status pe_adjoint_bind(pe_ctx* ctx, void* workspace) {
   return PE_OK;
 }
 
-pe_status pe_step_adjoint(pe_ctx* ctx, double dt, const double* u_n, const double* lam_next, double* lam_prev,
-                          void* stream) {
-  if (!ctx) return PE_EINVAL;
-  if (!ctx->partitioned) return fail(ctx, PE_ESTATE, "step_adjoint before partition");
-  if (ctx->equations != 0) return fail(ctx, PE_EUNSUPPORTED, "step_adjoint: Euler only");
-  if (!u_n || !lam_next || !lam_prev) return fail(ctx, PE_EINVAL, "step_adjoint: null");
-  if (!(dt > 0.0)) return fail(ctx, PE_EINVAL, "step_adjoint: dt must be > 0");
+namespace {
+// Checks shared by the adjoint step entry points.
+pe_status adjoint_ready(pe_ctx* ctx, double dt, const char* who) {
+  if (!ctx->partitioned) return fail(ctx, PE_ESTATE, "%s before partition", who);
+  if (ctx->equations != 0) return fail(ctx, PE_EUNSUPPORTED, "%s: Euler only", who);
+  if (!(dt > 0.0)) return fail(ctx, PE_EINVAL, "%s: dt must be > 0", who);
   if (!ctx->adj_ws || ctx->adj_S != ctx->S || ctx->adj_cap != cap_of(ctx))
-    return fail(ctx, PE_ESTATE, "step_adjoint: adjoint workspace not bound for these coefficients and capacity");
-  if (lam_prev == lam_next || lam_prev == u_n) return fail(ctx, PE_EINVAL, "step_adjoint: lam_prev must not alias");
-  hipStream_t s = (hipStream_t)stream;
+    return fail(ctx, PE_ESTATE, "%s: adjoint workspace not bound for these coefficients and capacity", who);
+  return PE_OK;
+}
+
+// Stage-value slot i (1 <= i < S, holding Y_{i+1}) of a record: state array i + off from ybase.
+struct StageSlots {
+  double* ybase;
+  int off;
+  int64_t sd;
+  double* operator()(int i) const { return ybase + (int64_t)(i + off) * sd; }
+};
+
+// One step from u_n keeping what the reverse sweep reads: K_1 in K1 and the stage values
+// Y_2..Y_S in the slots Y(1..S-1); U_{n+1} goes to u_next.
+pe_status record_step(pe_ctx* ctx, double dt, const double* u_n, double* K1, StageSlots Y, double* u_next,
+                      hipStream_t s) {
+  const int S = ctx->S;
+  Mesh m = device_mesh(ctx);
+  for (int i = 0; i < S; ++i) {
+    StageArgs a;
+    fill_stage(ctx, i, dt, a);
+    a.U = u_n;
+    a.K1 = K1;
+    a.Yin = i >= 1 ? Y(i) : ctx->Ya;
+    a.Yout = i + 1 < S ? Y(i + 1) : ctx->Yb;
+    a.ACC = ctx->ACC;
+    a.Uout = u_next;
+    a.evals = nullptr;
+    HIPCHK(launch_stage(ctx->dim, ctx->N, false, a, m, ctx->ops, ctx->ph, s));
+  }
+  return PE_OK;
+}
+
+// The reverse sweep of one step (lam_prev = Phi'(u_n)^T lam_next) from the recorded K_1 and
+// stage values; the stage cotangents live in the adjoint workspace.
+pe_status reverse_sweep(pe_ctx* ctx, double dt, const double* u_n, const double* K1, StageSlots Y,
+                        const double* lam_next, double* lam_prev, hipStream_t s) {
   if (!ctx->halo_valid) {
     pe_status st = build_halo(ctx, s);
     if (st != PE_OK) return st;
@@ -905,25 +938,10 @@ pe_status pe_step_adjoint(pe_ctx* ctx, double dt, const double* u_n, const doubl
   const int64_t sd = state_doubles(ctx);
   const int S = ctx->S, R = ctx->R;
   double* base = (double*)ctx->adj_ws;
-  auto Ystore = [&](int i) { return base + (int64_t)(i - 1) * sd; };   // Y_1 .. Y_{S-1}
   double* Kcur = base + (int64_t)(S - 1) * sd;
   double* Kprev = Kcur + sd;
   double* K1bar = Kprev + sd;
   Mesh m = device_mesh(ctx);
-  // forward recomputation of the step from u_n, keeping every stage value
-  for (int i = 0; i < S; ++i) {
-    StageArgs a;
-    fill_stage(ctx, i, dt, a);
-    a.U = u_n;
-    a.K1 = ctx->K1;
-    a.Yin = i >= 1 ? Ystore(i) : ctx->Ya;
-    a.Yout = i + 1 < S ? Ystore(i + 1) : ctx->Yb;
-    a.ACC = ctx->ACC;
-    a.Uout = ctx->Tmp;
-    a.evals = nullptr;
-    HIPCHK(launch_stage(ctx->dim, ctx->N, false, a, m, ctx->ops, ctx->ph, s));
-  }
-  // reverse sweep
   HIPCHK(launch_copy(lam_prev, lam_next, sd, s));
   HIPCHK(launch_scale(K1bar, lam_next, dt * ctx->b[0], sd, s));
   if (S > 1) HIPCHK(launch_scale(Kcur, lam_next, dt * ctx->b[S - 1], sd, s));
@@ -933,8 +951,8 @@ pe_status pe_step_adjoint(pe_ctx* ctx, double dt, const double* u_n, const doubl
     VjpArgs a;
     std::memset(&a, 0, sizeof a);
     a.U = u_n;
-    a.K1 = ctx->K1;
-    a.Yin = Ystore(i);
+    a.K1 = K1;
+    a.Yin = Y(i);
     a.dt = dt;
     a.ci = ctx->c[i];
     for (int r = 0; r < kMaxMembers; ++r) a.src[r] = sa.src[r];
@@ -967,6 +985,60 @@ pe_status pe_step_adjoint(pe_ctx* ctx, double dt, const double* u_n, const doubl
     HIPCHK(launch_rhs_vjp(ctx->dim, ctx->N, a, m, ctx->ops, ctx->ph, s));
   }
   return PE_OK;
+}
+}  // namespace
+
+pe_status pe_step_adjoint(pe_ctx* ctx, double dt, const double* u_n, const double* lam_next, double* lam_prev,
+                          void* stream) {
+  if (!ctx) return PE_EINVAL;
+  pe_status st = adjoint_ready(ctx, dt, "step_adjoint");
+  if (st != PE_OK) return st;
+  if (!u_n || !lam_next || !lam_prev) return fail(ctx, PE_EINVAL, "step_adjoint: null");
+  if (lam_prev == lam_next || lam_prev == u_n) return fail(ctx, PE_EINVAL, "step_adjoint: lam_prev must not alias");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t sd = state_doubles(ctx);
+  double* base = (double*)ctx->adj_ws;
+  const StageSlots Y{base, -1, sd};   // Y_2 .. Y_S in workspace arrays 0 .. S-2
+  // forward recomputation of the step from u_n, keeping every stage value
+  st = record_step(ctx, dt, u_n, ctx->K1, Y, ctx->Tmp, s);
+  if (st != PE_OK) return st;
+  return reverse_sweep(ctx, dt, u_n, ctx->K1, Y, lam_next, lam_prev, s);
+}
+
+pe_status pe_adjoint_record_size(const pe_ctx* ctx, int64_t* doubles) {
+  if (!ctx || !doubles) return PE_EINVAL;
+  if (!ctx->have_coeffs || !ctx->bound) return PE_ESTATE;
+  *doubles = (int64_t)ctx->S * state_doubles(ctx);
+  return PE_OK;
+}
+
+pe_status pe_step_record(pe_ctx* ctx, double dt, const double* u_n, double* u_next, double* record, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  pe_status st = adjoint_ready(ctx, dt, "step_record");
+  if (st != PE_OK) return st;
+  if (!u_n || !u_next || !record) return fail(ctx, PE_EINVAL, "step_record: null");
+  const int64_t sd = state_doubles(ctx);
+  const double* r0 = record;
+  const double* r1 = record + (int64_t)ctx->S * sd;
+  auto overlaps = [&](const double* p) { return p && p + sd > r0 && p < r1; };
+  if (u_next == u_n || overlaps(u_n) || overlaps(u_next))
+    return fail(ctx, PE_EINVAL, "step_record: u_n, u_next and record must not overlap");
+  const StageSlots Y{record, 0, sd};   // K_1 in array 0, Y_2 .. Y_S in arrays 1 .. S-1
+  return record_step(ctx, dt, u_n, record, Y, u_next, (hipStream_t)stream);
+}
+
+pe_status pe_step_adjoint_recorded(pe_ctx* ctx, double dt, const double* u_n, const double* record,
+                                   const double* lam_next, double* lam_prev, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  pe_status st = adjoint_ready(ctx, dt, "step_adjoint_recorded");
+  if (st != PE_OK) return st;
+  if (!u_n || !record || !lam_next || !lam_prev) return fail(ctx, PE_EINVAL, "step_adjoint_recorded: null");
+  const int64_t sd = state_doubles(ctx);
+  const double* r1 = record + (int64_t)ctx->S * sd;
+  if (lam_prev == lam_next || lam_prev == u_n || (lam_prev + sd > record && lam_prev < r1))
+    return fail(ctx, PE_EINVAL, "step_adjoint_recorded: lam_prev must not alias");
+  const StageSlots Y{const_cast<double*>(record), 0, sd};   // read only here
+  return reverse_sweep(ctx, dt, u_n, record, Y, lam_next, lam_prev, (hipStream_t)stream);
 }
 
 namespace {

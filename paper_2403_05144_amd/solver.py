@@ -207,6 +207,29 @@ class PerkSolver:
                                              _stream_handle()), "pe_step_adjoint")
         return out
 
+    def step_record(self, u_n_slot, dt):
+        """One step from u_n (slot layout) without touching the bound state: (u_next, record),
+        the record holding what step_adjoint_recorded reads (K_1 and the stage values)."""
+        if getattr(self, "_adj_ws", None) is None:
+            self.enable_adjoint()
+        nd = ctypes.c_int64()
+        self._check(self.lib.pe_adjoint_record_size(self._ctx, ctypes.byref(nd)), "pe_adjoint_record_size")
+        u_next = torch.empty_like(u_n_slot)
+        record = torch.empty(nd.value, dtype=torch.float64, device=self.device)
+        self._check(self.lib.pe_step_record(self._ctx, float(dt), u_n_slot.data_ptr(), u_next.data_ptr(),
+                                            record.data_ptr(), _stream_handle()), "pe_step_record")
+        return u_next, record
+
+    def step_adjoint_recorded(self, u_n_slot, record, lam_slot, dt):
+        """step_adjoint(u_n, lam, dt) from the record of step_record(u_n, dt)."""
+        if getattr(self, "_adj_ws", None) is None:
+            self.enable_adjoint()
+        out = torch.empty_like(lam_slot)
+        self._check(self.lib.pe_step_adjoint_recorded(self._ctx, float(dt), u_n_slot.data_ptr(), record.data_ptr(),
+                                                      lam_slot.data_ptr(), out.data_ptr(), _stream_handle()),
+                    "pe_step_adjoint_recorded")
+        return out
+
     def leaves(self):
         n = ctypes.c_int64()
         self._check(self.lib.pe_get_leaves(self._ctx, None, ctypes.byref(n)), "pe_get_leaves")

@@ -103,3 +103,36 @@ def test_adjoint_rejects_navier_stokes():
     u, rng = _state(o, 3)
     with pytest.raises(PerkError):
         s.rhs_vjp_leaf(u, u)
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_recorded_step_adjoint_equals_recomputing(order):
+    # pe_step_record + pe_step_adjoint_recorded against pe_step_adjoint (which recomputes the
+    # step) and pe_step: bitwise the same next state and cotangent; the bound state untouched
+    import torch
+    from paper_2403_05144_amd import PerkSolver
+    mesh = pin.random_forest_2d(7, n_root=3, max_level=2)
+    N = 4
+    o = od.Oracle(mesh, N)
+    u, rng = _state(o, 41 + order)
+    lam = rng.standard_normal(o.shape)
+    if order == 2:
+        fam = pc.perk2_family([4, 8])
+    else:
+        with open(os.path.join(GOLD, "perk3_4_8_16_disk.json")) as f:
+            fam = pc.PerkFamily.from_json(json.load(f))
+    mol = od.member_of_levels_paper_rule(np.arange(3), len(fam.E))
+    dt = 2e-3
+    s = PerkSolver(mesh, N - 1, fam, mol)
+    s.set_state(u)
+    u_slot, lam_slot = s.to_slot(u), s.to_slot(lam)
+    bound = s.u.clone()
+    u_next, rec = s.step_record(u_slot, dt)
+    g_rec = s.step_adjoint_recorded(u_slot, rec, lam_slot, dt)
+    g_ref = s.step_adjoint(u_slot, lam_slot, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(s.u, bound)
+    assert torch.equal(g_rec, g_ref)
+    s.step(dt, 1)
+    stepped = s.get_state().cpu().numpy()
+    np.testing.assert_array_equal(s.to_leaf(u_next).cpu().numpy(), stepped)

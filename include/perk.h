@@ -207,8 +207,9 @@ pe_status pe_adjoint_record_size(const pe_ctx* ctx, int64_t* doubles);
 
 /* One partitioned step of size dt from u_n into u_next, keeping its record (slot layout
  * device arrays; none may overlap another).  The same stage launches as pe_step; the bound
- * state and its stage buffers are not touched.  Needs the adjoint workspace (pe_adjoint_bind);
- * Euler only.  Asynchronous on stream. */
+ * state is not touched, the stage workspace of pe_step is reused (it holds nothing between
+ * steps).  Needs the adjoint workspace (pe_adjoint_bind); Euler only.  Asynchronous on
+ * stream. */
 pe_status pe_step_record(pe_ctx* ctx, double dt, const double* u_n, double* u_next, double* record, void* stream);
 
 /* pe_step_adjoint from a record made by pe_step_record with the same u_n and dt, instead of

@@ -34,6 +34,7 @@ struct pe_ctx {
   double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
   std::vector<int32_t> leaves;          // [n][4]
   std::vector<int32_t> fk_leaf, fn_leaf, lev_leaf;
+  std::vector<int32_t> own_cells;       // connectivity scratch: owner leaf of every finest-level cell
   int n_e = 0, max_level = 0;
   int64_t capacity = 0;                 // reserved elements (leading dimension of the slot layout)
   // coefficients
@@ -263,7 +264,7 @@ pe_status build_connectivity(pe_ctx* ctx) {
   // Leaf lookup.  Dense: the owner of every cell of the finest level (one array read per
   // lookup; overlap and coverage checked while filling).  Hash map for very fine grids.
   const bool dense = total <= ((int64_t)1 << 24);
-  std::vector<int32_t> own;
+  std::vector<int32_t>& own = ctx->own_cells;   // kept between calls (no allocation per adaptation)
   std::unordered_map<uint64_t, int, KeyHash> idx;
   if (dense) {
     own.assign((size_t)total, -1);
@@ -305,9 +306,9 @@ pe_status build_connectivity(pe_ctx* ctx) {
     for (int d = 0; d < dim; ++d) roots *= ctx->n_root[d];
     if (std::fabs(vol - roots) > 1e-9 * roots) return fail(ctx, PE_EINVAL, "leaves do not cover the domain");
   }
-  ctx->fk_leaf.assign((size_t)n * nf, 0);
-  ctx->fn_leaf.assign((size_t)n * nf * 4, -1);
-  ctx->lev_leaf.assign(n, 0);
+  ctx->fk_leaf.resize((size_t)n * nf);        // every entry is written below
+  ctx->fn_leaf.resize((size_t)n * nf * 4);
+  ctx->lev_leaf.resize(n);
   auto find = [&](int lev, int i, int j, int k) -> int {
     if (lev < 0 || lev > Lm) return -1;
     if (dense) {
@@ -327,8 +328,10 @@ pe_status build_connectivity(pe_ctx* ctx) {
         const int f = 2 * d + s;
         int cc[3] = {L[1], L[2], dim == 3 ? L[3] : 0};
         const int nc = ctx->n_root[d] << lev;
-        cc[d] = ((cc[d] + (s ? 1 : -1)) % nc + nc) % nc;
+        const int c = cc[d] + (s ? 1 : -1);   // periodic neighbour cell
+        cc[d] = c < 0 ? c + nc : (c >= nc ? c - nc : c);
         int32_t* nb = &ctx->fn_leaf[((size_t)e * nf + f) * 4];
+        nb[0] = nb[1] = nb[2] = nb[3] = -1;
         const int same = find(lev, cc[0], cc[1], cc[2]);
         if (same >= 0) {
           ctx->fk_leaf[(size_t)e * nf + f] = pack_face(kConforming, 0, 0);
@@ -360,6 +363,7 @@ pe_status build_connectivity(pe_ctx* ctx) {
         ctx->fk_leaf[(size_t)e * nf + f] = pack_face(kCoarseSide, 0, 0);
       }
   }
+  if (own.capacity() > ((size_t)1 << 20)) std::vector<int32_t>().swap(own);   // keep at most 4 MB
   return PE_OK;
 }
 

@@ -833,6 +833,8 @@ struct GKc {
   using g = G<DIM, N>;
   static constexpr int ND = g::ND, NF = g::NF, NFC = g::NFC, NV = g::NV, NSUB = g::NSUB, NW = DIM + 1;
   static constexpr int T = DIM == 2 ? 64 : 256;
+  // 3D p=3: 20.7 KB of LDS and at most 72 VGPRs (7 waves per SIMD) let 7 blocks share a CU
+  static constexpr int WPS = DIM == 3 && N == 4 ? 7 : 1;
 };
 
 template <int DIM>
@@ -845,11 +847,12 @@ __device__ __forceinline__ void grad_vars(const double* u, double gamma, double*
 }
 
 template <int DIM, int N>
-__global__ __launch_bounds__((GKc<DIM, N>::T)) void k_grad(StageArgs a, Mesh m, Ops op, Physics ph) {
+__global__ __launch_bounds__((GKc<DIM, N>::T), (GKc<DIM, N>::WPS)) void k_grad(StageArgs a, Mesh m, Ops op,
+                                                                              Physics ph) {
   using K = GKc<DIM, N>;
   constexpr int ND = K::ND, NF = K::NF, NFC = K::NFC, NV = K::NV, NSUB = K::NSUB, NW = K::NW, T = K::T;
   __shared__ double s_w[NW][ND];
-  __shared__ double s_tr[NFC][NSUB][NV][NF];
+  __shared__ double s_tr[NFC][NSUB][NW][NF];   // neighbour w traces, later central face values
   __shared__ double s_q[DIM][NW][ND];
   __shared__ int s_fk[NFC];
   __shared__ int s_fn[NFC][4];

@@ -315,6 +315,18 @@ __global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, 
     s_u[v][nd] = vstage(a, my_src, idx);
     s_w[v][nd] = w_own ? a.W[idx] : 0.0;
   }
+  // 2D: the epilogue operands of the lane's (variable, node) item come in with the first loads
+  // (no memory round after the last barrier); 3D reads them at the end (its registers are full)
+  constexpr bool PRE = DIM == 2;
+  static_assert(!PRE || NV * ND <= T, "one epilogue item per lane");
+  double pre_ubar = 0.0, pre_k1bar = 0.0, pre_lam = 0.0;
+  if (PRE && lane < NV * ND) {
+    const int v = lane / ND, nd = lane - v * ND;
+    const int64_t idx = ((int64_t)v * ld + e) * ND + nd;
+    if (a.Ubar) pre_ubar = a.Ubar[idx];
+    if (a.K1bar) pre_k1bar = a.K1bar[idx];
+    if (a.Kprev) pre_lam = a.lam[idx];
+  }
   __syncthreads();
   for (int w = lane; w < NFI * NV; w += T) {
     const int j = w % NF;
@@ -471,9 +483,9 @@ __global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, 
     }
     const int64_t idx = ((int64_t)v * ld + e) * ND + nd;
     if (a.Gout) a.Gout[idx] = g;
-    if (a.Ubar) a.Ubar[idx] += g;
-    if (a.K1bar) a.K1bar[idx] += a.dt * a.A1[mem] * g;
-    if (a.Kprev) a.Kprev[idx] = a.dt * (a.bprev * a.lam[idx] + a.A2[mem] * g);
+    if (a.Ubar) a.Ubar[idx] = (PRE ? pre_ubar : a.Ubar[idx]) + g;
+    if (a.K1bar) a.K1bar[idx] = (PRE ? pre_k1bar : a.K1bar[idx]) + a.dt * a.A1[mem] * g;
+    if (a.Kprev) a.Kprev[idx] = a.dt * (a.bprev * (PRE ? pre_lam : a.lam[idx]) + a.A2[mem] * g);
   }
 }
 

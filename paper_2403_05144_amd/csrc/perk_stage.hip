@@ -833,7 +833,8 @@ struct GKc {
   using g = G<DIM, N>;
   static constexpr int ND = g::ND, NF = g::NF, NFC = g::NFC, NV = g::NV, NSUB = g::NSUB, NW = DIM + 1;
   static constexpr int T = DIM == 2 ? 64 : 256;
-  // 3D p=3: 20.7 KB of LDS and at most 72 VGPRs (7 waves per SIMD) let 7 blocks share a CU
+  // 3D p=3: at most 72 VGPRs (7 waves per SIMD); with the 15 KB of LDS below, 37 -> 34.5 us per
+  // Taylor-Green launch against 20.7 KB (8 waves per SIMD measured the same, with a spill)
   static constexpr int WPS = DIM == 3 && N == 4 ? 7 : 1;
 };
 
@@ -852,8 +853,13 @@ __global__ __launch_bounds__((GKc<DIM, N>::T), (GKc<DIM, N>::WPS)) void k_grad(S
   using K = GKc<DIM, N>;
   constexpr int ND = K::ND, NF = K::NF, NFC = K::NFC, NV = K::NV, NSUB = K::NSUB, NW = K::NW, T = K::T;
   __shared__ double s_w[NW][ND];
-  __shared__ double s_tr[NFC][NSUB][NW][NF];   // neighbour w traces, later central face values
-  __shared__ double s_q[DIM][NW][ND];
+  // neighbour w traces, then central face values; after their last read the lifted gradients
+  // take the same LDS (held in registers across one barrier): 15 KB per 3D p=3 block
+  constexpr int NTRW = NFC * NSUB * NW * NF, NQ = DIM * NW * ND;
+  static_assert(NQ <= NTRW, "gradients fit the trace storage");
+  __shared__ double s_trq[NTRW];
+  auto s_tr = reinterpret_cast<double (*)[NSUB][NW][NF]>(s_trq);
+  auto s_q = reinterpret_cast<double (*)[NW][ND]>(s_trq);
   __shared__ int s_fk[NFC];
   __shared__ int s_fn[NFC][4];
   // D, P_0, P_1, R_0, R_1 from the device copy (lane-indexed reads from kernel-argument memory
@@ -957,7 +963,12 @@ __global__ __launch_bounds__((GKc<DIM, N>::T), (GKc<DIM, N>::WPS)) void k_grad(S
   __syncthreads();
   // lifted gradients
   const double iw0 = op.iw[0], iwN = op.iw[N - 1];
-  for (int it = lane; it < DIM * NW * ND; it += T) {
+  constexpr int NQL = (NQ + T - 1) / T;   // per lane
+  double qv[NQL];
+#pragma unroll
+  for (int q = 0; q < NQL; ++q) {
+    const int it = lane + q * T;
+    if (it >= NQ) continue;
     const int nd = it % ND, k = (it / ND) % NW, d = it / (ND * NW);
     int line, pos;
     line_of<DIM, N>(nd, d, line, pos);
@@ -995,7 +1006,13 @@ __global__ __launch_bounds__((GKc<DIM, N>::T), (GKc<DIM, N>::WPS)) void k_grad(S
       const double jump = ws - s_w[k][nd];
       acc += pos == N - 1 ? iwN * jump : -iw0 * jump;
     }
-    s_q[d][k][nd] = m.jac[lev][d] * acc;
+    qv[q] = m.jac[lev][d] * acc;
+  }
+  __syncthreads();   // every read of the face values is done: the gradients take their place
+#pragma unroll
+  for (int q = 0; q < NQL; ++q) {
+    const int it = lane + q * T;
+    if (it < NQ) s_q[it / (NW * ND)][(it / ND) % NW][it % ND] = qv[q];
   }
   __syncthreads();
   // viscous flux at every node, every direction

@@ -50,6 +50,7 @@ CASES = {
     "forest2d_p3": (lambda: pin.random_forest_2d(11, n_root=3, max_level=2), 4),
     "forest2d_p2": (lambda: pin.random_forest_2d(5, n_root=3, max_level=2), 3),
     "mesh3d_p2": (_mesh3d, 3),
+    "mesh3d_p3": (_mesh3d, 4),
 }
 
 

@@ -402,6 +402,7 @@ __global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, 
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         double x = 0.0, h = 0.0;
+#pragma unroll 2
         for (int i = 0; i < NF; ++i) {
           const int on = face_node<DIM, N>(d, side, i);
           x += Pm<DIM, N>(s_op, m0, m1, j, i) * s_u[v][on];
@@ -423,6 +424,7 @@ __global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, 
           const int s0 = face_sub0(pk), s1 = face_sub1(pk);
           const int ms = DIM == 2 ? s0 : s0 + 2 * s1;
           hn = 0.0;
+#pragma unroll 2
           for (int i = 0; i < NF; ++i) hn += Rm<DIM, N>(s_op, ms, i, j) * s_tw[f][0][v][i];
         } else {
           hn = s_tw[f][0][v][j];
@@ -474,6 +476,7 @@ __global__ __launch_bounds__((AK<DIM, N>::T)) void k_rhs_vjp(VjpArgs a, Mesh m, 
         if (face_kind(s_fk[f]) == kCoarseSide) {
           for (int ms = 0; ms < NSUB; ++ms) {
             const int m0 = ms & 1, m1 = (ms >> 1) & 1;
+#pragma unroll 4
             for (int k = 0; k < NF; ++k) g += Pm<DIM, N>(s_op, m0, m1, k, fi) * s_gf[f][ms][v][k];
           }
         } else {

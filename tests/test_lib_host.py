@@ -133,6 +133,17 @@ def test_call_order_errors():
     assert lib.pe_partition(ctx, mol, 2, None) == -4
     ns = ctypes.c_int64()
     assert lib.pe_query_sizes(ctx, ctypes.byref(ns), None, None) == -4
+    # the adaptation cycle and the recorded adjoint step need a partitioned, bound context
+    fl = (ctypes.c_int8 * 4)()
+    nl = ctypes.c_int64()
+    assert lib.pe_amr_cycle(ctx, 0.05, 0.01, 0, 3, mol, 2, fl, ctypes.byref(nl), None) == -4
+    assert lib.pe_amr_cycle(ctx, 0.05, 0.01, 0, 3, None, 2, fl, ctypes.byref(nl), None) == -1
+    buf = ctypes.c_void_p(256)
+    assert lib.pe_step_record(ctx, 0.1, buf, ctypes.c_void_p(512), ctypes.c_void_p(1024), None) == -4
+    assert lib.pe_step_adjoint_recorded(ctx, 0.1, buf, ctypes.c_void_p(512), ctypes.c_void_p(1024),
+                                        ctypes.c_void_p(2048), None) == -4
+    assert lib.pe_adjoint_record_size(ctx, ctypes.byref(ns)) == -4
+    assert lib.pe_step_record(None, 0.1, buf, buf, buf, None) == -1
     lib.pe_destroy(ctx)
 
 

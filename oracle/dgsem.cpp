@@ -16,8 +16,11 @@
 //    say how the logarithmic mean is evaluated).
 //  * HLL surface flux (Harten-Lax-van Leer) with Davis wave-speed estimates.
 //  * Mortars for 2:1 non-conforming faces (Kopriva 1996, cited in Sec. 6.2): interpolate the
-//    coarse trace to each fine sub-face, evaluate the flux there, project back with
-//    R_m = 1/2 M^{-1} P_m^T M (tensor product, factor 1/4, in 3D).
+//    coarse trace to each fine sub-face, evaluate the flux there, project back with the L2
+//    projection R_m = 1/2 M^{-1} B_m, M and B_m with exact integrals (tensor product, factor
+//    1/4, in 3D).  Exact integrals make R_0 P_0 + R_1 P_1 = I (a coarse polynomial survives the
+//    round trip); LGL quadrature in place of them would not, and would cost one order of the
+//    truncation error at mortars.
 //  * BR1 viscous terms (Bassi-Rebay, cited in Sec. 7.1): gradients of w = (v, T) with central
 //    face values, viscous flux, divergence with the central average of the viscous flux.
 //  * Partitioned RK step (eq. PartitionedRKSystem): K_i^(r) = I^(r) F(U_n + dt sum_j sum_k
@@ -36,6 +39,7 @@
 #include <stdexcept>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 namespace {
@@ -122,6 +126,50 @@ void lgl(int N, std::vector<double>& x, std::vector<double>& w) {
     }
     w[j] = 2.0 / (p * (p + 1.0) * P * P);
   }
+}
+
+// Gauss-Legendre nodes and weights (n points, exact for degree 2n-1): roots of P_n by Newton
+// from Chebyshev starts, weights 2 / ((1 - x^2) P'_n(x)^2).
+void gauss_legendre(int n, std::vector<double>& g, std::vector<double>& gw) {
+  g.assign(n, 0.0);
+  gw.assign(n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double xi = -std::cos(M_PI * (j + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double P, dP;
+      legendre_and_derivative(n, xi, P, dP);
+      const double dx = P / dP;
+      xi -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    double P, dP;
+    legendre_and_derivative(n, xi, P, dP);
+    g[j] = xi;
+    gw[j] = 2.0 / ((1.0 - xi * xi) * dP * dP);
+  }
+}
+
+// Solve A X = B for X (A n x n, B n x m, row-major) by Gaussian elimination with partial pivoting.
+std::vector<double> dense_solve(std::vector<double> A, std::vector<double> B, int n, int m) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[piv * n + k]);
+    for (int k = 0; k < m; ++k) std::swap(B[c * m + k], B[piv * m + k]);
+    for (int r = c + 1; r < n; ++r) {
+      const double f = A[r * n + c] / A[c * n + c];
+      for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+      for (int k = 0; k < m; ++k) B[r * m + k] -= f * B[c * m + k];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c)
+    for (int k = 0; k < m; ++k) {
+      double v = B[c * m + k];
+      for (int j = c + 1; j < n; ++j) v -= A[c * n + j] * B[j * m + k];
+      B[c * m + k] = v / A[c * n + c];
+    }
+  return B;
 }
 
 double lagrange(const std::vector<double>& x, int j, double xi) {
@@ -229,6 +277,10 @@ void ec_flux(const Phys& ph, const T* uL, const T* uR, int d, T* f) {
               0.5 * (L.p * R.v[d] + R.p * L.v[d]);
 }
 
+// Branches taken by the plain (double) HLL flux since the last reset: sL >= 0 (left state's
+// flux), sR <= 0 (right state's flux), subsonic (HLL average).  For tests that must reach them.
+static long long g_hll_branch[3] = {0, 0, 0};
+
 // HLL flux with Davis wave speeds; normal +e_d from L to R.
 template <class T>
 void hll_flux(const Phys& ph, const T* uL, const T* uR, int d, T* f) {
@@ -241,9 +293,11 @@ void hll_flux(const Phys& ph, const T* uL, const T* uR, int d, T* f) {
   T fL[5], fR[5];
   euler_flux(ph, uL, d, fL);
   euler_flux(ph, uR, d, fR);
-  if (sL >= 0.0) {
+  const int branch = sL >= 0.0 ? 0 : (sR <= 0.0 ? 1 : 2);
+  if (std::is_same<T, double>::value) ++g_hll_branch[branch];
+  if (branch == 0) {
     for (int v = 0; v < nv; ++v) f[v] = fL[v];
-  } else if (sR <= 0.0) {
+  } else if (branch == 1) {
     for (int v = 0; v < nv; ++v) f[v] = fR[v];
   } else {
     for (int v = 0; v < nv; ++v)
@@ -296,7 +350,10 @@ struct Solver {
   std::vector<std::vector<Face>> faces;    // [e][2*dim]
   std::vector<double> x, w, D;
   std::vector<double> Pm[2];   // [j*N + i] = l_i(xi_j^m), xi^0 = (xi-1)/2, xi^1 = (xi+1)/2
-  std::vector<double> Rm[2];   // [i*N + j] = 1/2 (1/w_i) P_m[j,i] w_j
+  // [i*N + j]: L2 projection of the fine data on sub-face m back to the coarse face (Kopriva's
+  // conservative mortars): with exact integrals, M R_m = 1/2 B_m, M_ik = int l_i l_k,
+  // (B_m)_ij = int_{-1}^{1} l_i(xi^m(s)) l_j(s) ds
+  std::vector<double> Rm[2];
 
   int ncell(int level, int d) const { return nroot[d] << level; }
   double h(int e, int d) const { return (hi[d] - lo[d]) / ncell(leaves[e][0], d); }
@@ -320,8 +377,25 @@ struct Solver {
         double xi = m == 0 ? 0.5 * (x[j] - 1.0) : 0.5 * (x[j] + 1.0);
         for (int i = 0; i < N; ++i) Pm[m][j * N + i] = lagrange(x, i, xi);
       }
+    }
+    {
+      // exact integrals of products of two degree-p polynomials: Gauss-Legendre with N points
+      std::vector<double> g, gw;
+      gauss_legendre(N, g, gw);
+      std::vector<double> M(N * N, 0.0);
       for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j) Rm[m][i * N + j] = 0.5 * Pm[m][j * N + i] * w[j] / w[i];
+        for (int k = 0; k < N; ++k)
+          for (int q = 0; q < N; ++q) M[i * N + k] += gw[q] * lagrange(x, i, g[q]) * lagrange(x, k, g[q]);
+      for (int m = 0; m < 2; ++m) {
+        std::vector<double> B(N * N, 0.0);
+        for (int i = 0; i < N; ++i)
+          for (int j = 0; j < N; ++j)
+            for (int q = 0; q < N; ++q) {
+              const double xi = m == 0 ? 0.5 * (g[q] - 1.0) : 0.5 * (g[q] + 1.0);
+              B[i * N + j] += 0.5 * gw[q] * lagrange(x, i, xi) * lagrange(x, j, g[q]);
+            }
+        Rm[m] = dense_solve(M, B, N, N);
+      }
     }
     index.clear();
     for (size_t e = 0; e < leaves.size(); ++e) {
@@ -749,6 +823,12 @@ void orc_euler_flux(int dim, double gamma, const double* u, int d, double* f) {
   euler_flux(ph, u, d, f);
 }
 double orc_log_mean(double a, double b) { return log_mean(a, b); }
+void orc_hll_branch_counts(long long* out, int reset) {
+  for (int k = 0; k < 3; ++k) {
+    if (out) out[k] = g_hll_branch[k];
+    if (reset) g_hll_branch[k] = 0;
+  }
+}
 
 // Face kinds for inspection: kinds[e*2dim + f], nbrs[(e*2dim + f)*4 + m]
 void orc_faces(void* h, int32_t* kinds, int32_t* nbrs) {

@@ -3,7 +3,7 @@
 Test infrastructure only (see oracle/__init__.py).  States are numpy arrays of shape
 [n_elements, n_vars, nodes_per_element] in the order of the leaf list given to the solver.
 
-Also here: the level -> member rule of Sec. 6.3.1 (the finest level gets the member with the
+Also here: the level -> member rule of Sec. 6.4.1 (the finest level gets the member with the
 most stage evaluations, the next finer the next member, all remaining coarse levels the
 member with the fewest evaluations), and the scalar RHS-evaluation count eq. (ActualRHSEvals).
 """
@@ -66,6 +66,7 @@ def lib():
                                        dp, dp, ip, dp, dp]
         L.orc_prk_step_vjp.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                        dp, dp, ip, dp]
+        L.orc_hll_branch_counts.argtypes = [ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
         L.orc_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -242,6 +243,13 @@ class Oracle:
         return np.einsum("e,evn,n->v", jac, u, W)
 
 
+def hll_branch_counts(reset=False):
+    """Branches the oracle's HLL flux took since the last reset: [sL >= 0, sR <= 0, subsonic]."""
+    out = (ctypes.c_longlong * 3)()
+    lib().orc_hll_branch_counts(out, int(bool(reset)))
+    return list(out)
+
+
 def max_dt(o: Oracle, u, cfl=1.0, gamma=1.4):
     """Step-size bound of eq. (CFL_DG) and eq. (TimestepConstraint): for every element,
     beta_e = min over its nodes and the directions d of h_d / ((k+1) (|v_d| + c)), with k + 1 =
@@ -261,7 +269,7 @@ def max_dt(o: Oracle, u, cfl=1.0, gamma=1.4):
 
 
 def member_of_levels_paper_rule(levels, n_members):
-    """Sec. 6.3.1: finest level -> member R-1 (most evaluations), next finer -> R-2, ...,
+    """Sec. 6.4.1: finest level -> member R-1 (most evaluations), next finer -> R-2, ...,
     every level beyond the R-th finest -> member 0."""
     levels = np.asarray(levels)
     Lmax = int(levels.max())

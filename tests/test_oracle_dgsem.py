@@ -48,6 +48,23 @@ def test_mortar_operators(dim):
     g = np.random.default_rng(0).standard_normal(4)
     for m in range(2):
         assert abs(w @ (R[m] @ g) - 0.5 * (w @ g)) < 1e-15
+    # L2 projection (Kopriva): a coarse polynomial survives interpolation and projection back,
+    # and the residual of projecting random half-face data is orthogonal to every coarse basis
+    # polynomial (integrals by 8-point Gauss-Legendre, exact for these degrees)
+    np.testing.assert_allclose(R[0] @ P[0] + R[1] @ P[1], np.eye(4), atol=2e-15)
+    gq, gw = np.polynomial.legendre.leggauss(8)
+
+    def lag(vals, t):
+        return sum(vals[k] * np.prod([(t - x[q]) / (x[k] - x[q]) for q in range(4) if q != k], axis=0)
+                   for k in range(4))
+    rng = np.random.default_rng(3)
+    f0, f1 = rng.standard_normal(4), rng.standard_normal(4)
+    gproj = R[0] @ f0 + R[1] @ f1
+    for i in range(4):
+        e_i = np.eye(4)[i]
+        lhs = np.sum(gw * lag(gproj, gq) * lag(e_i, gq))
+        rhs = sum(0.5 * np.sum(gw * lag(fm, gq) * lag(e_i, 0.5 * (gq + sg))) for fm, sg in ((f0, -1), (f1, 1)))
+        assert abs(lhs - rhs) < 1e-14
 
 
 # ------------------------------------------------------------------ two-point fluxes
@@ -422,3 +439,76 @@ def test_max_dt_vortex_below_background():
     p = 0.4 * (u[:, 3] - 0.5 * (u[:, 1] ** 2 + u[:, 2] ** 2) / rho)
     smax = np.max(np.sqrt((u[:, 1] ** 2 + u[:, 2] ** 2)) / rho + np.sqrt(1.4 * p / rho))
     assert dt >= 0.3125 / (4 * smax) * (1 - 1e-15)
+
+
+# ------------------------------------------------------------------ 2:1 mortars: truncation order
+def _block_refined(dim, n):
+    """n^dim roots on [0, 2 pi]^dim with the central (n/2)^dim block refined once (2:1 mortars on
+    every side of the block, corners included)."""
+    m = pin.uniform_mesh(dim, (n,) * dim, (0.0,) * dim, (2 * np.pi,) * dim, 0)
+    lo, hi = n // 4, n - n // 4
+    sel = [r for r, row in enumerate(m.leaves.tolist()) if all(lo <= c < hi for c in row[1:1 + dim])]
+    m.leaves = pin.refine_leaves(m.leaves, dim, sel)
+    return m
+
+
+@pytest.mark.parametrize("N,min_rate", [(3, 1.9), (4, 2.8)])
+def test_inviscid_truncation_order_across_mortars(N, min_rate):
+    # density wave rho = 1 + 0.1 sin x sin y advected by v = (1, 1/2) at p = 1: du_rho =
+    # -v . grad rho.  The truncation error of degree p stays O(h^p) with 2:1 mortars (the
+    # coarse trace interpolated exactly, fluxes projected back by L2 projection)
+    errs = []
+    for n in (4, 8, 16):
+        o = od.Oracle(_block_refined(2, n), N)
+        x = o.node_coords()
+        X, Y = x[:, 0], x[:, 1]
+        rho = 1 + 0.1 * np.sin(X) * np.sin(Y)
+        u = np.zeros(o.shape)
+        u[:, 0], u[:, 1], u[:, 2] = rho, rho, 0.5 * rho
+        u[:, 3] = 1 / (GAMMA - 1) + 0.5 * rho * 1.25
+        exact = -(0.1 * np.cos(X) * np.sin(Y) + 0.05 * np.sin(X) * np.cos(Y))
+        errs.append(np.max(np.abs(o.rhs(u)[:, 0] - exact)))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert rates[-1] > min_rate, (errs, rates)
+
+
+def test_viscous_heat_conduction_across_mortars():
+    # v = 0, p = 1, T = 1 + 0.1 sin x sin y on the block-refined mesh, p = 3: du_E = kappa Lap T.
+    # BR1 lifts the O(h^4) jump of the interpolated trace twice (gradient and divergence), so the
+    # truncation error of this second-order operator at the mortars is O(h^{p-1}) = O(h^2)
+    mu, pr = 0.05, 0.72
+    kappa = GAMMA * mu / ((GAMMA - 1) * pr)
+    errs = []
+    for n in (4, 8, 16):
+        o = od.Oracle(_block_refined(2, n), 4, viscous=True, mu=mu, prandtl=pr)
+        x = o.node_coords()
+        T = 1 + 0.1 * np.sin(x[:, 0]) * np.sin(x[:, 1])
+        u = np.zeros(o.shape)
+        u[:, 0] = 1.0 / T
+        u[:, -1] = 1.0 / (GAMMA - 1)
+        du = o.rhs(u)
+        assert np.max(np.abs(du[:, 1:3])) < 1e-12          # no momentum from a pressure-free state
+        expect = kappa * (-0.2 * np.sin(x[:, 0]) * np.sin(x[:, 1]))
+        errs.append(np.max(np.abs(du[:, 3] - expect)) / (0.2 * kappa))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert rates[-1] > 1.85 and min(rates) > 1.6, (errs, rates)
+
+
+def test_viscous_shear_flow_across_mortars_3d():
+    # the steady shear flow of the uniform test on a 3D block-refined mesh (coarse elements with
+    # one and with several refined face neighbours), p = 3: error of the closed form falls at
+    # the truncation order of the mortars
+    mu = 0.05
+    errs = []
+    for n in (4, 8):
+        o = od.Oracle(_block_refined(3, n), 4, viscous=True, mu=mu, prandtl=0.72)
+        y = o.node_coords()[:, 1]
+        u = np.zeros(o.shape)
+        u[:, 0] = 1.0
+        u[:, 1] = np.sin(y)
+        u[:, -1] = 1.0 / (GAMMA - 1) + 0.5 * np.sin(y) ** 2
+        expect = np.zeros(o.shape)
+        expect[:, 1] = -mu * np.sin(y)
+        expect[:, -1] = mu * np.cos(2 * y)
+        errs.append(np.max(np.abs(o.rhs(u) - expect)) / mu)
+    assert math.log2(errs[0] / errs[1]) > 1.6, errs

@@ -56,10 +56,10 @@ def family_for(name, order, E_list, reduced_mesh, degree, ic_fn, h_red, equation
     return fam
 
 
-def member_of_levels(levels, R):
-    """Sec. 6.3.1: finest level -> member R-1, next finer -> R-2, remaining coarse levels -> 0."""
-    Lmax = int(np.max(levels))
-    return [max(0, (R - 1) - (Lmax - l)) for l in range(Lmax + 1)]
+def rule_map(fam, rule, finest_level):
+    """member_of_level of the library's level rule (pe_level_map) at the given finest level."""
+    from paper_2403_05144_amd import partition_rule
+    return partition_rule.level_map(fam, rule, int(finest_level))
 
 
 def stable_dt(fam, mesh, mol, cfl):
@@ -79,8 +79,10 @@ def wl_vortex_2level():
     red = pin.uniform_mesh(2, (4, 4), (-5, -5), (5, 5), 0)
     ic = lambda x: pin.isentropic_vortex(x[0], x[1])
     fam = family_for("perk2_4_8_vortex_p3", 2, [4, 8], red, 3, ic, 2.5)
-    mol = member_of_levels(mesh.leaves[:, 0], len(fam.E))
-    return dict(name="vortex_2level", mesh=mesh, degree=3, fam=fam, mol=mol, ic=ic,
+    from paper_2403_05144_amd.partition_rule import LevelRule
+    rule = LevelRule.paper()
+    mol = rule_map(fam, rule, mesh.leaves[:, 0].max())
+    return dict(name="vortex_2level", mesh=mesh, degree=3, fam=fam, mol=mol, rule=rule, ic=ic,
                 dt=stable_dt(fam, mesh, mol, 0.9), t_final=1.0,
                 desc="2D Euler isentropic vortex (M=0.5, eps=5) on [-5,5]^2, 16x16 roots with the "
                      "centred 4x4 block refined once (304 elements, 2 levels), p=3, EC volume + HLL "
@@ -96,18 +98,19 @@ def wl_kh_amr(n_root=8, level_max=3, name="kh_amr_l3-6"):
     margin 1 ({4,6,12,16}) the family is stable only up to CFL 0.5 (member boundaries at high
     local CFL, Sec. 5).  The timed run uses CFL 0.9."""
     import perk_inputs as pin
-    from paper_2403_05144_amd import partition_rule
+    from paper_2403_05144_amd.partition_rule import LevelRule
     mesh = pin.uniform_mesh(2, (n_root, n_root), (-1, -1), (1, 1), 0)
     ic = lambda x: pin.kelvin_helmholtz(x[0], x[1])
     h_red = 2.0 / n_root
     fam = family_for(f"perk3_4_6_8_12_16_kh_p3_n{n_root}", 3, [4, 6, 8, 12, 16],
                      pin.uniform_mesh(2, (n_root, n_root), (-1, -1), (1, 1), 0), 3, ic, h_red)
-    mol = partition_rule.required_dt_rule(level_max, fam.dt_opt, fam.E, margin=2.0)
-    mol1 = partition_rule.required_dt_rule(level_max, fam.dt_opt, fam.E, margin=1.0)
+    rule = LevelRule.required_step(fam.dt_opt, margin=2.0)
+    mol = rule_map(fam, rule, level_max)
+    mol1 = rule_map(fam, LevelRule.required_step(fam.dt_opt, margin=1.0), level_max)
     h_min = h_red / 2 ** level_max
     cfl = 0.9
     dt = cfl * fam.dt_opt[-1] * h_min / fam.h_ref
-    return dict(name=name, mesh=mesh, degree=3, fam=fam, mol=mol, ic=ic, dt=dt, t_final=3.0,
+    return dict(name=name, mesh=mesh, degree=3, fam=fam, mol=mol, rule=rule, ic=ic, dt=dt, t_final=3.0,
                 perk_maps=[("required-step rule, margin 2", mol), ("required-step rule, margin 1", mol1)],
                 amr=dict(level_min=0, level_max=level_max, interval=10, refine_above=0.05, coarsen_below=0.01,
                          capacity=(n_root << level_max) ** 2),
@@ -128,17 +131,18 @@ def wl_tgv():
     P-ERK2;16; the one-member-per-level map {4,8,16} is stable only up to CFL 0.4.  The timed
     run uses CFL 0.7."""
     import perk_inputs as pin
-    from paper_2403_05144_amd import partition_rule
+    from paper_2403_05144_amd.partition_rule import LevelRule
     mesh = pin.mesh_taylor_green()
     mu = 1.0 / 1600
     ic = lambda x: pin.taylor_green(x[0], x[1], x[2])
     red = pin.uniform_mesh(3, (2, 2, 2), (-np.pi,) * 3, (np.pi,) * 3, 0)
     fam = family_for("perk2_4_8_16_tgv_p3", 2, [4, 8, 16], red, 3, ic, np.pi, equations=1, mu=mu)
-    mol = partition_rule.required_dt_rule(2, fam.dt_opt, fam.E, margin=1.0)
+    rule = LevelRule.required_step(fam.dt_opt, margin=1.0)
+    mol = rule_map(fam, rule, 2)
     h_min = 2 * np.pi / 16 / 4
     cfl = 0.7
     dt = cfl * fam.dt_opt[-1] * h_min / fam.h_ref
-    return dict(name="tgv_ns_3d", mesh=mesh, degree=3, fam=fam, mol=mol, ic=ic, dt=dt, t_final=200 * dt,
+    return dict(name="tgv_ns_3d", mesh=mesh, degree=3, fam=fam, mol=mol, rule=rule, ic=ic, dt=dt, t_final=200 * dt,
                 equations=1, mu=mu,
                 perk_maps=[("required-step rule", mol), ("one member per level", [0, 1, 2])],
                 desc="3D compressible Navier-Stokes Taylor-Green vortex (Ma 0.1, Re 1600, Pr 0.72) on "
@@ -163,13 +167,13 @@ def batch_runs(replicas=1, cfl=0.4):
     each to t = 1 at cfl times its largest stable step, replicated `replicas` times.  (At CFL
     0.6 nine and at 0.8 twenty-seven of the {4,8,16} runs blow up before t = 1; 0.4 keeps all.)"""
     import perk_inputs as pin
-    from paper_2403_05144_amd import partition_rule
+    from paper_2403_05144_amd.partition_rule import LevelRule
     runs = []
     for spec in pin.batch_vortex_runs():
         fam = vortex_family(spec["degree"], spec["E"])
         mesh = spec["mesh"]
         lmax = int(mesh.leaves[:, 0].max())
-        mol = partition_rule.paper_rule(lmax, len(fam.E))
+        mol = rule_map(fam, LevelRule.paper(), lmax)
         dt = stable_dt(fam, mesh, mol, cfl)
         n_steps = int(math.ceil(1.0 / dt))
         runs.append(dict(spec, fam=fam, mol=mol, dt=1.0 / n_steps, n_steps=n_steps))
@@ -844,11 +848,13 @@ def run(args):
         """Solver at the start of the measured run: initial mesh (and adaptation passes), IC, warmup."""
         import perk_inputs as pin
         m0 = pin.MeshDesc(mesh.dim, mesh.n_root, mesh.lo, mesh.hi, np.array(leaves_init, copy=True))
-        s = PerkSolver(m0, deg, fam, wl["mol"], capacity=amr["capacity"] if amr else None,
+        # the library applies the workload's level rule (at the finest level of the current mesh)
+        rule = wl.get("rule", wl["mol"])
+        s = PerkSolver(m0, deg, fam, rule, capacity=amr["capacity"] if amr else None,
                        equations=wl.get("equations", 0), mu=wl.get("mu", 0.0))
         drv = None
         if amr:
-            drv = AmrDriver(s, amr["level_min"], amr["level_max"], wl["mol"], amr["refine_above"],
+            drv = AmrDriver(s, amr["level_min"], amr["level_max"], rule, amr["refine_above"],
                             amr["coarsen_below"], amr["interval"])
             drv.initial_mesh(ic_leaf, passes=3)
         else:

@@ -18,7 +18,8 @@
  *   - level-wise evaluation of the right-hand side over the elements of a partition and the
  *     assignment of elements, interfaces and mortars to partitions after every mesh change:
  *     Sec. 6.1, 6.2;
- *   - level -> method map when there are more levels than methods: Sec. 6.3.1;
+ *   - level -> method map when there are more levels than methods: Sec. 6.4.1 (Actual Number of
+ *     Right-Hand-Side Evaluations);
  *   - scalar RHS-evaluation count: eq. (ActualRHSEvals).
  *
  * Conventions
@@ -111,6 +112,32 @@ pe_status pe_mesh_build(pe_ctx* ctx, const pe_mesh_desc* mesh);
  * Returns PE_EINVAL on violation.  Invalidates the partition. */
 pe_status pe_set_perk_coefficients(pe_ctx* ctx, const pe_perk_coeffs* coeffs);
 
+/* Level -> member rules (which member of the family integrates the elements of each refinement
+ * level; pe_partition and pe_amr_cycle apply the context's rule when they are given no map).
+ *   PE_LEVEL_RULE_PAPER (the default; Sec. 6.4.1): the finest level takes the member with the most
+ *     stage evaluations (R-1), the next coarser level R-2, and so on; every level beyond the R
+ *     finest takes member 0 (the fewest evaluations).
+ *   PE_LEVEL_RULE_REQUIRED_STEP: the spectrum of a convection-dominated discretisation scales with
+ *     1/h (Sec. 3.1), so a member whose optimal step at the finest element size is dt_opt[r]
+ *     admits dt_opt[r] 2^(finest - l) on level l.  Level l takes the cheapest member r that admits
+ *     dt_opt[R-1] * margin (the common step set by the finest level, times a safety margin); the
+ *     finest level takes member R-1; a level no member admits takes member R-1.  With margin 1
+ *     and dt_opt doubling from member to member it gives the paper rule.
+ * Levels finer than the finest level take member R-1 under both rules. */
+typedef enum { PE_LEVEL_RULE_PAPER = 0, PE_LEVEL_RULE_REQUIRED_STEP = 1 } pe_level_rule;
+
+/* Select the level rule of the context.  dt_opt (host [R], positive; ignored by the paper rule)
+ * holds each member's optimal step at one common element size, margin >= 1.  The required-step
+ * rule needs the coefficients set first (dt_opt has one entry per member); a later
+ * pe_set_perk_coefficients with another member count clears it (PE_ESTATE until set again).
+ * PE_EINVAL for an unknown rule, a non-positive or non-finite dt_opt entry or margin < 1. */
+pe_status pe_set_level_rule(pe_ctx* ctx, int rule, const double* dt_opt, double margin);
+
+/* The context's rule as a map: member_of_level[l] (host [n_levels], 1 <= n_levels <= 16) for a
+ * mesh whose finest level is finest_level, or the finest level of the current mesh when
+ * finest_level < 0.  Host only. */
+pe_status pe_level_map(const pe_ctx* ctx, int finest_level, int n_levels, int32_t* member_of_level);
+
 /* Sizes for the caller's allocations: the state (doubles, slot layout) and the workspace
  * (bytes, 256-byte aligned start required).  Valid after pe_mesh_build and
  * pe_set_perk_coefficients. */
@@ -128,7 +155,9 @@ pe_status pe_reserve(pe_ctx* ctx, int64_t max_elements);
 pe_status pe_bind(pe_ctx* ctx, double* u_dev, void* workspace_dev, void* stream);
 
 /* Re-flag elements into partitions on the device (Sec. 6.2): member of every element from
- * member_of_level (host, [n_levels] where n_levels = max leaf level + 1, values in [0, R)),
+ * member_of_level (host, [n_levels] where n_levels = max leaf level + 1, values in [0, R)), or,
+ * when member_of_level is NULL (n_levels ignored), from the context's level rule at the finest
+ * level of the current mesh (pe_set_level_rule; by default the paper rule of Sec. 6.4.1),
  * stable counting sort of the elements by member (most stage evaluations first), remap of the
  * connectivity to the new slots, permutation of the bound state, per-stage active prefix
  * lengths.  Synchronises `stream` once to read the member counts back. */
@@ -145,6 +174,14 @@ pe_status pe_element_info(const pe_ctx* ctx, int32_t* leaf_of_slot, int32_t* mem
 /* The 1D Legendre-Gauss-Lobatto nodes on [-1, 1] and quadrature weights used by the DGSEM
  * (host arrays of degree+1 entries each; either may be NULL). */
 pe_status pe_quadrature(const pe_ctx* ctx, double* nodes, double* weights);
+
+/* The 2:1 mortar operators (Sec. 6.2; Kopriva's conservative mortars), host arrays
+ * [2][N][N] each (either may be NULL), N = degree + 1: P[m][j][k] = l_k((x_j - 1)/2) (m = 0) or
+ * l_k((x_j + 1)/2) (m = 1) interpolates the coarse face's nodal values to the nodes of half face
+ * m; R[m] is the L2 projection (exact integrals) of nodal data on half face m back to the coarse
+ * face, so that sum_m R[m] P[m] = I and sum_j w_j (R[m] g)_j = 1/2 sum_j w_j g_j (conservation).
+ * In 3D the face operators are tensor products of these (factor 1/4 instead of 1/2). */
+pe_status pe_mortar_operators(const pe_ctx* ctx, double* P, double* R);
 
 /* Physical coordinates of every node in leaf layout, x_dev [leaf][dim][node] (device). */
 pe_status pe_node_coords(pe_ctx* ctx, double* x_leaf_dev, void* stream);
@@ -249,7 +286,8 @@ pe_status pe_adapt(pe_ctx* ctx, const int8_t* flags_host, int level_min, int lev
 /* One adaptation cycle in a single call (Sec. 6.2: indicator, mesh change, re-partition):
  * pe_amr_indicator; flags by threshold, +1 where eta > refine_above, then -1 where
  * eta < coarsen_below, 0 elsewhere (a NaN indicator keeps its leaf); pe_adapt with
- * [level_min, level_max]; pe_partition with member_of_level[n_levels].  The same flags,
+ * [level_min, level_max]; pe_partition with member_of_level[n_levels] (NULL: the context's
+ * level rule at the finest level of the adapted mesh).  The same flags,
  * forest and state as those calls made one by one.  flags_host (may be NULL) receives the
  * flags [n_elements before the call]; n_leaves (may be NULL) the number of leaves after it.
  * Synchronises `stream` once (the indicator download).  Errors as the three calls; on a

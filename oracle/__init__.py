@@ -8,7 +8,7 @@ quadrature, fluxes, mortar operators, Runge-Kutta tableaux and partition rule.
 Modules
   perk_coeffs  P-ERK tableaux from stability polynomials (Sec. 3.1, 4.3), order conditions
                (Sec. 2.1), stability polynomial of a tableau, LP optimiser (Sec. 4.2).
-  godunov1d    1D first-order Godunov advection + partitioned RK (Sec. 3.2.1-3.2.4).
+  godunov1d    1D first-order Godunov advection + partitioned RK (Sec. 3.2.1-3.2.5).
   dgsem        ctypes wrapper of dgsem.cpp: DGSEM for 2D/3D Euler and Navier-Stokes (BR1)
                on a Cartesian forest with 2:1 mortars, the dense masked partitioned RK step
                (Sec. 2, eq. PartitionedRKSystem) and AMR helpers.

@@ -11,7 +11,7 @@ Paper passages followed (Sec. 3.2)
     U_{n+1} = U_n + dt sum_i sum_r b_i^(r) K_i^(r)  (eq. PartitionedRKSystem).
     For the linear F = L U this gives U_{n+1} = D U_n (eq. PartitionedSystem).
   * Monotonicity D_ij >= 0 (eq. MonotonicityRequirement); row sums 1 (conservation).
-  * Relative total-variation increase after one step, Sec. 3.2.4, with TV(U) = sum |U_{i+1}-U_i|
+  * Relative total-variation increase after one step, Sec. 3.2.5, with TV(U) = sum |U_{i+1}-U_i|
     taken periodically, and cell averages of u_0 = 1 + sin(pi x)/2 on (-1, 1).
 """
 from __future__ import annotations

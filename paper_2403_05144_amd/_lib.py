@@ -7,7 +7,7 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.environ.get("PERK_LIBRARY_PATH", os.path.join(_HERE, "libperk.so"))
+LIB_PATH = os.path.join(_HERE, "libperk.so")
 
 PE_OK = 0
 STATUS = {0: "PE_OK", -1: "PE_EINVAL", -2: "PE_ENOMEM", -3: "PE_EHIP", -4: "PE_ESTATE",
@@ -39,6 +39,9 @@ _SIGS = {
     "pe_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "pe_mesh_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(pe_mesh_desc)]),
     "pe_set_perk_coefficients": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(pe_perk_coeffs)]),
+    "pe_set_level_rule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.c_double]),
+    "pe_level_map": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
     "pe_query_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "pe_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -82,6 +85,8 @@ _SIGS = {
                                  ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "pe_quadrature": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]),
+    "pe_mortar_operators": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double)]),
     "pe_set_graph_replay": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "pe_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "pe_profile_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
@@ -89,6 +94,13 @@ _SIGS = {
 }
 
 EXPORTS = tuple(_SIGS)
+
+
+def library_fingerprint():
+    """(path, sha256) of the library this process loads."""
+    import hashlib
+    with open(LIB_PATH, "rb") as f:
+        return LIB_PATH, hashlib.sha256(f.read()).hexdigest()
 
 
 def lib():

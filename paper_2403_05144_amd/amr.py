@@ -8,6 +8,8 @@ values first (PerkSolver.indicator, then PerkSolver.adapt with their own flags).
 """
 import numpy as np
 
+from .partition_rule import LevelRule
+
 
 def flags_from_indicator(eta, refine_above, coarsen_below):
     f = np.zeros(len(eta), np.int8)
@@ -21,7 +23,8 @@ class AmrDriver:
                  interval=10):
         self.s = solver
         self.level_min, self.level_max = level_min, level_max
-        self.member_of_level = list(member_of_level)
+        # an explicit map, or a LevelRule the library applies at the finest level after each cycle
+        self.member_of_level = member_of_level if isinstance(member_of_level, LevelRule) else list(member_of_level)
         self.refine_above, self.coarsen_below = refine_above, coarsen_below
         self.interval = interval
         self.n_adapt = 0

@@ -42,6 +42,11 @@ struct pe_ctx {
   int order = 2, R = 1, S = 1;
   std::vector<int32_t> E;
   std::vector<double> c, b, a_sub;      // a_sub [R][S]
+  // level -> member rule applied when pe_partition / pe_amr_cycle get no explicit map
+  bool have_rule = true;
+  int rule = PE_LEVEL_RULE_PAPER;
+  std::vector<double> rule_dt_opt;      // [R] optimal steps at a common element size (required-step rule)
+  double rule_margin = 1.0;
   // binding
   bool bound = false;
   double* U = nullptr;
@@ -76,6 +81,7 @@ struct pe_ctx {
   double graph_dt = 0.0;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
+  std::vector<int> graph_bodies;        // kernel body of every stage launch in gexec (stage_body_id)
   bool maps_on_host = false;            // leaf_of_slot / slot_of_leaf / mem_of_slot copied back
   // optional per-launch timing of the stage kernels with HIP events on the launch stream
   bool profiling = false;
@@ -191,7 +197,7 @@ void make_ops(int N, Ops& op) {
     op.iw[j] = 1.0 / w[j];
     op.x[j] = x[j];
   }
-  // mortar operators: P_m[j][k] = l_k((x_j -/+ 1)/2), R_m[j][k] = 1/2 P_m[k][j] w_k / w_j
+  // mortar interpolation: P_m[j][k] = l_k((x_j -/+ 1)/2)
   for (int m = 0; m < 2; ++m) {
     for (int j = 0; j < N; ++j) {
       const double xi = m == 0 ? 0.5 * (x[j] - 1.0) : 0.5 * (x[j] + 1.0);
@@ -202,8 +208,80 @@ void make_ops(int N, Ops& op) {
         op.P[m][j * N + k] = l;
       }
     }
+  }
+  // mortar projection (Kopriva's conservative mortars): the L2 projection of the data on the
+  // two half faces onto the coarse face's polynomials, with exact integrals, so that
+  // R_0 P_0 + R_1 P_1 = I and a coarse polynomial survives the round trip.  The Lagrange basis is
+  // expanded in monomials, products are integrated exactly (int_{-1}^{1} s^k ds), and
+  // M R_m = 1/2 B_m is solved with M_ij = int l_i l_j, (B_m)_ij = int l_i((s -/+ 1)/2) l_j(s) ds.
+  double mono[kMaxN][kMaxN];            // l_i(s) = sum_k mono[i][k] s^k
+  {
+    double V[kMaxN][2 * kMaxN];
+    for (int r = 0; r < N; ++r)
+      for (int c = 0; c < 2 * N; ++c) V[r][c] = c < N ? std::pow(x[r], c) : (c - N == r ? 1.0 : 0.0);
+    for (int c = 0; c < N; ++c) {     // Gauss-Jordan: [V | I] -> [I | V^-1]
+      int piv = c;
+      for (int r = c + 1; r < N; ++r)
+        if (std::fabs(V[r][c]) > std::fabs(V[piv][c])) piv = r;
+      for (int k = 0; k < 2 * N; ++k) std::swap(V[c][k], V[piv][k]);
+      const double d = V[c][c];
+      for (int k = 0; k < 2 * N; ++k) V[c][k] /= d;
+      for (int r = 0; r < N; ++r)
+        if (r != c) {
+          const double f = V[r][c];
+          for (int k = 0; k < 2 * N; ++k) V[r][k] -= f * V[c][k];
+        }
+    }
+    // monomial coefficients of l_i are column i of V^-1 (V_rk = x_r^k)
+    for (int i = 0; i < N; ++i)
+      for (int k = 0; k < N; ++k) mono[i][k] = V[k][N + i];
+  }
+  auto integral = [&](const double* a, const double* b) {   // int_{-1}^{1} (sum a_k s^k)(sum b_k s^k)
+    double r = 0.0;
+    for (int k = 0; k < N; ++k)
+      for (int l = 0; l < N; ++l)
+        if ((k + l) % 2 == 0) r += a[k] * b[l] * 2.0 / (k + l + 1);
+    return r;
+  };
+  double Mx[kMaxN][kMaxN];
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) Mx[i][j] = integral(mono[i], mono[j]);
+  for (int m = 0; m < 2; ++m) {
+    // l_i((s + sg)/2) in monomials of s, sg = -1 (m = 0) or +1 (m = 1)
+    const double sg = m == 0 ? -1.0 : 1.0;
+    double half[kMaxN][kMaxN];
+    for (int i = 0; i < N; ++i) {
+      for (int k = 0; k < N; ++k) half[i][k] = 0.0;
+      for (int k = 0; k < N; ++k) {
+        // ((s + sg)/2)^k = 2^-k sum_q C(k, q) s^q sg^(k-q)
+        double binom = 1.0;
+        for (int q = 0; q <= k; ++q) {
+          half[i][q] += mono[i][k] * std::ldexp(binom, -k) * ((k - q) % 2 ? sg : 1.0);
+          binom = binom * (k - q) / (q + 1);
+        }
+      }
+    }
+    double A[kMaxN][2 * kMaxN];
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        A[i][j] = Mx[i][j];
+        A[i][N + j] = 0.5 * integral(half[i], mono[j]);
+      }
+    for (int c = 0; c < N; ++c) {     // Gauss-Jordan on [M | B/2] -> [I | R_m]
+      int piv = c;
+      for (int r = c + 1; r < N; ++r)
+        if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+      for (int k = 0; k < 2 * N; ++k) std::swap(A[c][k], A[piv][k]);
+      const double d = A[c][c];
+      for (int k = 0; k < 2 * N; ++k) A[c][k] /= d;
+      for (int r = 0; r < N; ++r)
+        if (r != c) {
+          const double f = A[r][c];
+          for (int k = 0; k < 2 * N; ++k) A[r][k] -= f * A[c][k];
+        }
+    }
     for (int j = 0; j < N; ++j)
-      for (int k = 0; k < N; ++k) op.R[m][j * N + k] = 0.5 * op.P[m][k * N + j] * w[k] / w[j];
+      for (int k = 0; k < N; ++k) op.R[m][j * N + k] = A[j][N + k];
   }
 }
 
@@ -485,6 +563,37 @@ void fill_stage(const pe_ctx* c, int i, double dt, StageArgs& a) {
   }
 }
 
+// Member of every level 0..n_levels-1 from the context's rule, the finest level being `finest`
+// (levels finer than it take the member with the most stage evaluations).
+//   paper rule (Sec. 6.4.1): the finest level takes member R-1, the next coarser R-2, and so on;
+//     every level beyond the R finest takes member 0;
+//   required-step rule: the spectrum of a convection-dominated problem scales with 1/h (Sec. 3.1),
+//     so member r admits dt_opt[r] 2^(finest - l) on level l; level l takes the cheapest member
+//     that admits the common step dt_opt[R-1] of the finest level times the margin (the finest
+//     level itself without margin), or member R-1 if none does.
+void level_map(const pe_ctx* c, int finest, int n_levels, int32_t* out) {
+  const int R = c->R;
+  for (int l = 0; l < n_levels; ++l) {
+    if (l >= finest) {
+      out[l] = R - 1;
+      continue;
+    }
+    if (c->rule == PE_LEVEL_RULE_PAPER) {
+      out[l] = std::max(0, (R - 1) - (finest - l));
+      continue;
+    }
+    const double need = c->rule_dt_opt[R - 1] * c->rule_margin * (1.0 - 1e-12);
+    const double scale = std::ldexp(1.0, finest - l);
+    int r = R - 1;
+    for (int k = 0; k < R; ++k)
+      if (c->rule_dt_opt[k] * scale >= need) {
+        r = k;
+        break;
+      }
+    out[l] = r;
+  }
+}
+
 bool last_stage_in_place_safe(const pe_ctx* c) {
   // At the last stage a neighbour reads U_n only if its member is first activated there.
   for (int r = 0; r < c->R; ++r)
@@ -593,6 +702,15 @@ pe_status pe_set_perk_coefficients(pe_ctx* ctx, const pe_perk_coeffs* co) {
         return fail(ctx, PE_EINVAL, "member %d: order condition b^T A c = 1/6 violated (%g)", r, s);
     }
   }
+  // every stage with b != 0 evaluated by every member (checked before anything is stored, so a
+  // rejected family leaves the context as it was)
+  for (int i = 0; i < S; ++i)
+    if (co->b[i] != 0.0)
+      for (int r = 0; r < R; ++r)
+        if (!(i == 0 || i >= S - co->E[r] + 1))
+          return fail(ctx, PE_EINVAL, "stage %d has b != 0 but member %d does not evaluate it", i + 1, r);
+  if (ctx->have_rule && ctx->rule == PE_LEVEL_RULE_REQUIRED_STEP && (int)ctx->rule_dt_opt.size() != R)
+    ctx->have_rule = false;   // the step sizes belonged to another family
   ctx->order = co->order;
   ctx->R = R;
   ctx->S = S;
@@ -600,14 +718,47 @@ pe_status pe_set_perk_coefficients(pe_ctx* ctx, const pe_perk_coeffs* co) {
   ctx->c.assign(co->c, co->c + S);
   ctx->b.assign(co->b, co->b + S);
   ctx->a_sub.assign(co->a_sub, co->a_sub + (size_t)R * S);
-  for (int i = 0; i < S; ++i)
-    if (co->b[i] != 0.0)
-      for (int r = 0; r < R; ++r)
-        if (!active(ctx, r, i))
-          return fail(ctx, PE_EINVAL, "stage %d has b != 0 but member %d does not evaluate it", i + 1, r);
   ctx->have_coeffs = true;
   ctx->partitioned = false;
   ctx->graph_valid = false;
+  return PE_OK;
+}
+
+pe_status pe_set_level_rule(pe_ctx* ctx, int rule, const double* dt_opt, double margin) {
+  if (!ctx) return PE_EINVAL;
+  if (rule == PE_LEVEL_RULE_PAPER) {
+    ctx->rule = rule;
+    ctx->rule_dt_opt.clear();
+    ctx->rule_margin = 1.0;
+    ctx->have_rule = true;
+    return PE_OK;
+  }
+  if (rule != PE_LEVEL_RULE_REQUIRED_STEP) return fail(ctx, PE_EINVAL, "level rule %d unknown", rule);
+  if (!ctx->have_coeffs) return fail(ctx, PE_ESTATE, "required-step rule needs the coefficients first");
+  if (!dt_opt) return fail(ctx, PE_EINVAL, "required-step rule: null dt_opt");
+  if (!(margin >= 1.0) || !std::isfinite(margin)) return fail(ctx, PE_EINVAL, "required-step rule: margin must be >= 1");
+  for (int r = 0; r < ctx->R; ++r)
+    if (!(dt_opt[r] > 0.0) || !std::isfinite(dt_opt[r]))
+      return fail(ctx, PE_EINVAL, "required-step rule: dt_opt[%d] must be positive and finite", r);
+  ctx->rule = rule;
+  ctx->rule_dt_opt.assign(dt_opt, dt_opt + ctx->R);
+  ctx->rule_margin = margin;
+  ctx->have_rule = true;
+  return PE_OK;
+}
+
+pe_status pe_level_map(const pe_ctx* cctx, int finest_level, int n_levels, int32_t* member_of_level) {
+  if (!cctx) return PE_EINVAL;
+  pe_ctx* ctx = const_cast<pe_ctx*>(cctx);
+  if (!ctx->have_coeffs) return fail(ctx, PE_ESTATE, "level_map before set_perk_coefficients");
+  if (!ctx->have_rule) return fail(ctx, PE_ESTATE, "level_map: no level rule set");
+  if (finest_level < 0) {
+    if (!ctx->have_mesh) return fail(ctx, PE_ESTATE, "level_map: finest level of the mesh asked before mesh_build");
+    finest_level = ctx->max_level;
+  }
+  if (!member_of_level || n_levels < 1 || n_levels > kMaxLevels || finest_level >= kMaxLevels)
+    return fail(ctx, PE_EINVAL, "level_map: need 1 <= n_levels <= %d and finest_level < %d", kMaxLevels, kMaxLevels);
+  level_map(ctx, finest_level, n_levels, member_of_level);
   return PE_OK;
 }
 
@@ -733,7 +884,15 @@ pe_status build_halo(pe_ctx* ctx, hipStream_t s) {
 pe_status pe_partition(pe_ctx* ctx, const int32_t* member_of_level, int n_levels, void* stream) {
   if (!ctx) return PE_EINVAL;
   if (!ctx->bound || !ctx->have_coeffs) return fail(ctx, PE_ESTATE, "partition needs a bound mesh and coefficients");
-  if (!member_of_level || n_levels <= ctx->max_level || n_levels > kMaxLevels)
+  int32_t rule_map[kMaxLevels];
+  if (!member_of_level) {
+    // the context's level rule at the finest level of the current mesh
+    if (!ctx->have_rule) return fail(ctx, PE_ESTATE, "partition: no member_of_level and no level rule set");
+    n_levels = ctx->max_level + 1;
+    level_map(ctx, ctx->max_level, n_levels, rule_map);
+    member_of_level = rule_map;
+  }
+  if (n_levels <= ctx->max_level || n_levels > kMaxLevels)
     return fail(ctx, PE_EINVAL, "member_of_level must cover levels 0..%d", ctx->max_level);
   PartitionArgs pa{};
   for (int l = 0; l < kMaxLevels; ++l) pa.member_of_level[l] = l < n_levels ? member_of_level[l] : 0;
@@ -1136,7 +1295,14 @@ pe_status capture_step(pe_ctx* ctx, double dt) {
     return st;
   }
   HIPCHK(e);
-  if (ctx->gexec) {
+  // the kernel body of every stage launch: a partition that moves a stage's active count across
+  // the point where the 2D p=3 launches change body changes that node's kernel and block size,
+  // which an in-place update is not relied on to carry over: then the graph is instantiated anew
+  std::vector<int> bodies(ctx->S);
+  for (int i = 0; i < ctx->S; ++i) bodies[i] = stage_body_id(ctx->dim, ctx->N, ctx->n_act[i]);
+  const bool same_bodies = bodies == ctx->graph_bodies;
+  ctx->graph_bodies = bodies;
+  if (ctx->gexec && same_bodies) {
     // same launches with new sizes (after a re-partition): update the executable graph in
     // place, which costs less than instantiating a new one; otherwise replace it
     hipGraphNode_t err_node = nullptr;
@@ -1148,6 +1314,8 @@ pe_status capture_step(pe_ctx* ctx, double dt) {
       return PE_OK;
     }
     (void)hipGetLastError();
+  }
+  if (ctx->gexec) {
     HIPCHK(hipGraphExecDestroy(ctx->gexec));
     ctx->gexec = nullptr;
   }
@@ -1453,7 +1621,8 @@ pe_status pe_amr_cycle(pe_ctx* ctx, double refine_above, double coarsen_below, i
                        const int32_t* member_of_level, int n_levels, int8_t* flags_host, int64_t* n_leaves,
                        void* stream) {
   if (!ctx) return PE_EINVAL;
-  if (!member_of_level) return fail(ctx, PE_EINVAL, "amr_cycle: null member_of_level");
+  if (!member_of_level && !ctx->have_rule)
+    return fail(ctx, PE_ESTATE, "amr_cycle: no member_of_level and no level rule set");
   const int n = ctx->n_e;
   std::vector<double> eta(n);
   pe_status st = pe_amr_indicator(ctx, eta.data(), stream);
@@ -1480,6 +1649,17 @@ pe_status pe_quadrature(const pe_ctx* ctx, double* nodes, double* weights) {
     if (nodes) nodes[i] = ctx->ops.x[i];
     if (weights) weights[i] = ctx->ops.w[i];
   }
+  return PE_OK;
+}
+
+pe_status pe_mortar_operators(const pe_ctx* ctx, double* P, double* R) {
+  if (!ctx) return PE_EINVAL;
+  const int N = ctx->N;
+  for (int m = 0; m < 2; ++m)
+    for (int i = 0; i < N * N; ++i) {
+      if (P) P[m * N * N + i] = ctx->ops.P[m][i];
+      if (R) R[m * N * N + i] = ctx->ops.R[m][i];
+    }
   return PE_OK;
 }
 

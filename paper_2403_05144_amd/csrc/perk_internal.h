@@ -27,7 +27,7 @@ struct Ops {
   double w[kMaxN];                  // quadrature weights
   double iw[kMaxN];                 // 1 / w (host division, the same correctly rounded value)
   double P[2][kMaxN * kMaxN];       // mortar interpolation to the lower/upper half
-  double R[2][kMaxN * kMaxN];       // mortar projection 1/2 M^{-1} P^T M
+  double R[2][kMaxN * kMaxN];       // mortar projection: exact L2 projection of the half faces (R_0 P_0 + R_1 P_1 = I)
   double x[kMaxN];                  // nodes on [-1, 1]
   // device copy (caller's workspace, written at bind): [0, N^2) 2 D with a zero diagonal,
   // [N^2, 2 N^2) D, then P[0], P[1], R[0], R[1] (N^2 each).  Lane-indexed reads of the tables
@@ -138,6 +138,9 @@ struct BatchRun {
 // ev0/ev1 (optional): events recorded by the dispatch itself at kernel start and end
 hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,
                         const Physics& ph, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Which kernel body launch_stage picks for a stage with n_act active elements (0: the default
+// body; 1: the two-wave 2D p=3 body of small launches).
+int stage_body_id(int dim, int N, int n_act);
 // BR1 gradient pass over slots [0, n_act) and the n_halo slots of `halo`: lifted gradients of
 // w = (v, T) with central face values, then the viscous flux F_v at every node into a.Fv.
 hipError_t launch_gradients(int dim, int N, const StageArgs& a, const Mesh& m, const Ops& op,

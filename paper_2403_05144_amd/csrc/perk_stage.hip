@@ -1102,6 +1102,10 @@ hipError_t launch_stage_batch(int N, int M, int grid, bool persistent, const Bat
   return hipErrorNotSupported;
 }
 
+int stage_body_id(int dim, int N, int n_act) {
+  return (dim == 2 && N == 4 && n_act > 0 && n_act <= kSplitMaxElements) ? 1 : 0;
+}
+
 hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,
                         const Physics& ph, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (!viscous) {

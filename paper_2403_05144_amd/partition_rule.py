@@ -1,31 +1,83 @@
-"""Level -> P-ERK member maps.
+"""Level -> P-ERK member rules: argument marshalling for the library's rules (pe_set_level_rule,
+pe_level_map in include/perk.h).  The rules themselves live in libperk:
 
-paper_rule (Sec. 6.3.1): the finest level gets the member with the most stage evaluations,
-the next finer level the next member, and so on; when there are more levels than members every
-remaining coarse level gets the member with the fewest evaluations.
+* PAPER (Sec. 6.4.1): the finest level gets the member with the most stage evaluations, the next
+  coarser level the next member, and so on; every level beyond the R finest gets the member with
+  the fewest evaluations.
+* REQUIRED_STEP: each level gets the cheapest member whose optimal step, scaled with the level's
+  element size, still admits the common step of the finest level times a margin.
 
-required_dt_rule: each level gets the cheapest member whose optimal step, scaled with the
-level's element size (convection-dominated spectra scale with 1/h, Sec. 3.1), still admits the
-common step set by the finest level, times a safety margin.  With margin 1 it coincides with
-paper_rule when the optimal step doubles from member to member.  A margin above 1 keeps the
-coarser members away from their own stability limit: at the boundaries between members the
-partitioned scheme is not monotone (Sec. 5), and for inviscid flow a member running close to its
-limit next to a finer level can force the common step down (Sec. 7: the CFL reductions reported
-for the hyperbolic cases); the finest level always takes the largest member.
+`LevelRule` is what PerkSolver and the AMR driver accept in place of an explicit map; `level_map`
+asks the library for the map of a family at a given finest level (host calls only, no device).
 """
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
 import numpy as np
 
+from . import _lib as L
 
-def paper_rule(level_max, n_members):
-    return [max(0, (n_members - 1) - (level_max - l)) for l in range(level_max + 1)]
+PAPER = 0
+REQUIRED_STEP = 1
 
 
-def required_dt_rule(level_max, dt_opt, E, margin=1.0, rel_tol=1e-12):
-    dt_common = dt_opt[-1]                 # finest level, E_max member, element size h_min
-    out = []
-    for l in range(level_max + 1):
-        scale = 2.0 ** (level_max - l)     # element size relative to h_min
-        need = dt_common * (margin if l < level_max else 1.0) * (1 - rel_tol)
-        r = next((k for k in range(len(E)) if dt_opt[k] * scale >= need), len(E) - 1)
-        out.append(r)
-    return out
+@dataclass(frozen=True)
+class LevelRule:
+    kind: int = PAPER
+    dt_opt: tuple | None = None     # [R] optimal steps at a common element size (REQUIRED_STEP)
+    margin: float = 1.0
+
+    @staticmethod
+    def paper():
+        return LevelRule(PAPER)
+
+    @staticmethod
+    def required_step(dt_opt, margin=1.0):
+        return LevelRule(REQUIRED_STEP, tuple(float(x) for x in dt_opt), float(margin))
+
+    def label(self):
+        return "paper rule (Sec. 6.4.1)" if self.kind == PAPER else f"required-step rule, margin {self.margin:g}"
+
+
+def set_rule(lib, ctx, rule: LevelRule):
+    """pe_set_level_rule on an existing context (coefficients already set)."""
+    dt = None
+    if rule.kind == REQUIRED_STEP:
+        arr = np.ascontiguousarray(rule.dt_opt, dtype=np.float64)
+        dt = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return lib.pe_set_level_rule(ctx, int(rule.kind), dt, float(rule.margin))
+
+
+def level_map(family, rule: LevelRule, finest_level, n_levels=None):
+    """member_of_level[0..n_levels) of `family` under `rule` for a mesh whose finest level is
+    finest_level, computed by the library on a host-only context."""
+    lib = L.lib()
+    n_levels = finest_level + 1 if n_levels is None else n_levels
+    ctx = ctypes.c_void_p()
+    phys = L.pe_physics(2, 3, 0, 1.4, 0.0, 0.72)
+    st = lib.pe_create(ctypes.byref(ctx), ctypes.byref(phys))
+    if st != L.PE_OK:
+        raise RuntimeError(f"pe_create: {L.STATUS.get(st, st)}")
+    try:
+        E = np.ascontiguousarray(np.asarray(family.E, dtype=np.int32))
+        c = np.ascontiguousarray(family.c, dtype=np.float64)
+        b = np.ascontiguousarray(family.b, dtype=np.float64)
+        a = np.ascontiguousarray(np.asarray(family.a_sub, dtype=np.float64).reshape(len(E), -1))
+        co = L.pe_perk_coeffs(int(family.order), len(E), int(family.S),
+                              E.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        out = np.zeros(n_levels, np.int32)
+        for what, st in (("pe_set_perk_coefficients", lambda: lib.pe_set_perk_coefficients(ctx, ctypes.byref(co))),
+                         ("pe_set_level_rule", lambda: set_rule(lib, ctx, rule)),
+                         ("pe_level_map", lambda: lib.pe_level_map(ctx, int(finest_level), int(n_levels),
+                                                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))):
+            code = st()
+            if code != L.PE_OK:
+                raise RuntimeError(f"{what}: {L.STATUS.get(code, code)}: {lib.pe_last_error(ctx).decode()}")
+        return [int(x) for x in out]
+    finally:
+        lib.pe_destroy(ctx)

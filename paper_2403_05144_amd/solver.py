@@ -11,6 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
+from .partition_rule import LevelRule, set_rule
 
 
 class PerkError(RuntimeError):
@@ -27,7 +28,9 @@ class PerkSolver:
 
     mesh: object with dim, n_root, lo, hi, leaves ([n,4] int32 rows (level, i, j, k)).
     family: object with order, S, E, c, b, a_sub (shared c, b; a_{i,i-1} per member).
-    member_of_level: int sequence, member index per refinement level (Sec. 6.3.1).
+    member_of_level: int sequence (member index per refinement level), or a LevelRule: the
+        library then applies that rule (Sec. 6.4.1, or the required-step variant) at the finest
+        level of the current mesh, at this partition and after every adaptation.
     """
 
     def __init__(self, mesh, degree, family, member_of_level, gamma=1.4, equations=0, mu=0.0,
@@ -106,10 +109,26 @@ class PerkSolver:
 
     # ------------------------------------------------------------------ API
     def partition(self, member_of_level):
+        if isinstance(member_of_level, LevelRule):
+            self.rule = member_of_level
+            self._check(set_rule(self.lib, self._ctx, member_of_level), "pe_set_level_rule")
+            self._check(self.lib.pe_partition(self._ctx, None, 0, _stream_handle()), "pe_partition")
+            self.member_of_level = self.level_map()
+            return
+        self.rule = None
         mol = np.ascontiguousarray(np.asarray(member_of_level, dtype=np.int32))
         self.member_of_level = mol
         self._check(self.lib.pe_partition(self._ctx, mol.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                           len(mol), _stream_handle()), "pe_partition")
+
+    def level_map(self, finest_level=-1, n_levels=None):
+        """The context's level rule as a map (finest level of the current mesh by default)."""
+        if n_levels is None:
+            n_levels = (int(self._leaves[:, 0].max()) if finest_level < 0 else int(finest_level)) + 1
+        out = np.zeros(n_levels, np.int32)
+        self._check(self.lib.pe_level_map(self._ctx, int(finest_level), int(n_levels),
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), "pe_level_map")
+        return out
 
     def element_info(self):
         los = np.zeros(self.n_elements, np.int32)
@@ -268,13 +287,21 @@ class PerkSolver:
                 bufs[k + "_p"] = bufs[k].ctypes.data
             self._cyc = bufs
         c = self._cyc
-        key = tuple(int(x) for x in member_of_level)
-        if c["mol_key"] != key:
-            c["mol"] = np.ascontiguousarray(key, dtype=np.int32)
-            c["mol_p"], c["mol_key"] = c["mol"].ctypes.data, key
+        if isinstance(member_of_level, LevelRule):
+            # the library applies its rule at the finest level of the adapted mesh
+            if self.rule != member_of_level:
+                self._check(set_rule(self.lib, self._ctx, member_of_level), "pe_set_level_rule")
+                self.rule = member_of_level
+            mol_p, n_lev = None, 0
+        else:
+            key = tuple(int(x) for x in member_of_level)
+            if c["mol_key"] != key:
+                c["mol"] = np.ascontiguousarray(key, dtype=np.int32)
+                c["mol_p"], c["mol_key"] = c["mol"].ctypes.data, key
+            mol_p, n_lev = c["mol_p"], len(key)
         n_old = self.n_elements
         self._check(self.lib.pe_amr_cycle(self._ctx, float(refine_above), float(coarsen_below), int(level_min),
-                                          int(level_max), c["mol_p"], len(key), c["flags_p"], c["n_p"],
+                                          int(level_max), mol_p, n_lev, c["flags_p"], c["n_p"],
                                           _stream_handle()), "pe_amr_cycle")
         n = int(c["n"][0])
         cnt = ctypes.c_int64(n)
@@ -282,7 +309,8 @@ class PerkSolver:
         self._leaves = c["leaves"][:n].copy()
         self.n_elements = n
         self.mesh.leaves = self._leaves
-        self.member_of_level = c["mol"]
+        if not isinstance(member_of_level, LevelRule):
+            self.member_of_level = c["mol"]
         return c["flags"][:n_old].copy()
 
     def max_dt(self, cfl=1.0):

@@ -313,3 +313,25 @@ def smooth_random_state(coords, dim, seed, gamma=1.4, amp=0.1):
     vel = [field(0.3, amp) for _ in range(dim)]
     p = field(1.0, amp)
     return prim2cons(rho, vel, p, gamma)
+
+
+def supersonic_state(coords, dim, seed, gamma=1.4, mach=(2.0, -2.0, 1.5), amp=0.05):
+    """Seeded smooth supersonic stream: rho = p = 1 plus small random Fourier modes, velocity
+    mach[d] times the free-stream sound speed in direction d (positive: every face normal to d
+    sees flow faster than sound to +e_d; negative: to -e_d)."""
+    rng = np.random.default_rng(seed)
+    shape = coords[0].shape
+    c0 = np.sqrt(gamma)
+
+    def field(base, a):
+        f = np.full(shape, base, dtype=float)
+        for _ in range(3):
+            k = rng.integers(1, 3, size=dim)
+            ph = rng.random() * 2 * np.pi
+            arg = ph + sum(2 * np.pi * k[d] * coords[d] / 10.0 for d in range(dim))
+            f = f + a * rng.standard_normal() * np.sin(arg)
+        return f
+    rho = field(1.0, amp)
+    vel = [field(mach[d] * c0, amp) for d in range(dim)]
+    p = field(1.0, amp)
+    return prim2cons(rho, vel, p, gamma)

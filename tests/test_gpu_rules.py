@@ -1,0 +1,150 @@
+"""GPU: the library's level -> member rules applied at partition and after adaptation (Sec. 6.2,
+6.4.1), checked bit-exactly against the oracle's rules; a rejected coefficient family leaves a
+partitioned context stepping as before; graph replay stays bitwise equal to eager launches when
+an adaptation moves the 2D p=3 stage launches across the element count where their kernel body
+changes."""
+import ctypes
+import json
+import os
+
+import numpy as np
+import pytest
+
+import perk_inputs as pin
+from oracle import amr
+from oracle import dgsem as od
+from oracle import level_rules as lr
+from oracle import perk_coeffs as pc
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def golden_family(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return pc.PerkFamily.from_json(json.load(f))
+
+
+def kh_leaf(x):
+    return pin.kelvin_helmholtz(x[:, 0], x[:, 1]).transpose(1, 0, 2).copy()
+
+
+def _kh_forest(lmax=3, cycles=3):
+    """The adaptive Kelvin-Helmholtz forest after a few oracle-decided adaptations (4 levels)."""
+    mesh = pin.uniform_mesh(2, (8, 8), (-1, -1), (1, 1), 0)
+    leaves = mesh.leaves
+    for _ in range(cycles):
+        o = od.Oracle(pin.MeshDesc(2, (8, 8), (-1, -1), (1, 1), leaves), 4)
+        x = o.node_coords().transpose(1, 0, 2)
+        u = pin.kelvin_helmholtz(x[0], x[1]).transpose(1, 0, 2).copy()
+        flags = amr.flags_from_indicator(amr.indicator(o, u), 0.05, 0.01)
+        leaves, _ = amr.adapt(leaves, flags, 0, lmax, 2, (8, 8))
+    return pin.MeshDesc(2, (8, 8), (-1, -1), (1, 1), leaves)
+
+
+@pytest.mark.parametrize("rule", ["paper", "required_step_m1", "required_step_m2"])
+def test_rule_partition_matches_oracle(rule):
+    from paper_2403_05144_amd import PerkSolver
+    from paper_2403_05144_amd.partition_rule import LevelRule
+    fam = golden_family("perk3_4_6_8_12_16_disk.json")
+    # optimised steps of the members at one element size: ratios of an optimised KH family
+    dt_opt = [0.18, 0.34, 0.46, 0.73, 1.0]
+    if rule == "paper":
+        lib_rule, ora = LevelRule.paper(), lambda fin: lr.paper_rule(fin, 5)
+    else:
+        m = 1.0 if rule.endswith("m1") else 2.0
+        lib_rule = LevelRule.required_step(dt_opt, m)
+        ora = lambda fin: lr.required_step_rule(fin, fam.E, dt_opt, m)
+    mesh = _kh_forest()
+    levels = np.asarray(mesh.leaves)[:, 0]
+    assert levels.max() == 3 and len(np.unique(levels)) == 4
+    s = PerkSolver(mesh, 3, fam, lib_rule, capacity=4096)
+    mol = np.asarray(ora(int(levels.max())))
+    np.testing.assert_array_equal(s.member_of_level, mol)
+    leaf_of_slot, mem_of_slot = s.element_info()
+    member = mol[levels]
+    expect = np.argsort(-member, kind="stable")
+    np.testing.assert_array_equal(leaf_of_slot, expect)
+    np.testing.assert_array_equal(mem_of_slot, member[expect])
+    # after adaptation cycles the library applies the rule at the finest level of the new mesh
+    s.set_state(kh_leaf(s.node_coords().cpu().numpy()))
+    for cyc in range(3):
+        s.amr_cycle(0.03 + 0.01 * cyc, 0.02, 0, 3, lib_rule)
+        lv = s.leaves()[:, 0]
+        mol = np.asarray(ora(int(lv.max())))
+        los, mos = s.element_info()
+        member = mol[lv]
+        np.testing.assert_array_equal(los, np.argsort(-member, kind="stable"))
+        np.testing.assert_array_equal(mos, member[los])
+        s.step(1e-4, 2)
+
+
+def test_rejected_coefficients_keep_the_context_stepping():
+    # a family that fails the check that every member evaluates every stage with b != 0 must
+    # leave the coefficients, partition and captured step of the context as they were
+    from paper_2403_05144_amd import PerkSolver
+    from paper_2403_05144_amd import _lib as L
+    mesh = pin.mesh_vortex_2level()
+    fam = pc.perk2_family([4, 8])
+    o = od.Oracle(mesh, 4)
+    x = o.node_coords().transpose(1, 0, 2)
+    u0 = pin.isentropic_vortex(x[0], x[1]).transpose(1, 0, 2).copy()
+    ref = PerkSolver(mesh, 3, fam, [0, 1])
+    ref.set_state(u0)
+    ref.step(0.02, 3)
+    s = PerkSolver(mesh, 3, fam, [0, 1])
+    s.set_state(u0)
+    s.step(0.02, 1)
+    nd0 = ctypes.c_int64()
+    s.enable_adjoint()
+    assert s.lib.pe_adjoint_record_size(s._ctx, ctypes.byref(nd0)) == 0
+    # order 2, S = 8, b = (1/6, 0.., 1/6, 2/3), c_7 = 1, c_8 = 1/2, members E = {2, 8}: stage 7
+    # carries weight but the E = 2 member skips it
+    S = 8
+    E = np.array([2, 8], np.int32)
+    c = np.array(fam.c, np.float64)
+    c[S - 2], c[S - 1] = 1.0, 0.5
+    b = np.zeros(S)
+    b[0], b[S - 2], b[S - 1] = 1 / 6, 1 / 6, 2 / 3
+    a = np.zeros((2, S))
+    a[1, 2:] = np.asarray(fam.a_sub)[1, 2:]
+    co = L.pe_perk_coeffs(2, 2, S, E.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                          c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert s.lib.pe_set_perk_coefficients(s._ctx, ctypes.byref(co)) == -1
+    nd1 = ctypes.c_int64()
+    assert s.lib.pe_adjoint_record_size(s._ctx, ctypes.byref(nd1)) == 0 and nd1.value == nd0.value
+    s.step(0.02, 2)
+    np.testing.assert_array_equal(s.get_state().cpu().numpy(), ref.get_state().cpu().numpy())
+
+
+def test_graph_replay_equals_eager_across_body_switch():
+    # 64x64 = 4096 elements (two-wave body of 2D p=3 stage launches), refined to more than 6144
+    # (one-wave body) and coarsened back: the captured step must be rebuilt, not updated in
+    # place, when a stage's kernel body changes; graph replay and eager launches stay bitwise equal
+    from paper_2403_05144_amd import PerkSolver
+    fam = pc.perk2_family([4, 8])
+    mesh0 = pin.uniform_mesh(2, (64, 64), (-1, -1), (1, 1), 0)
+    flags_up = np.zeros(4096, np.int8)
+    flags_up[:720] = 1                      # +3 elements each: 4096 + 2160 = 6256 > 6144
+    runs = []
+    for graphs in (True, False):
+        s = PerkSolver(pin.MeshDesc(2, (64, 64), (-1, -1), (1, 1), np.array(mesh0.leaves, copy=True)), 3, fam,
+                       [1, 1], capacity=8192)
+        s.set_graph_replay(graphs)
+        s.set_state(kh_leaf(s.node_coords().cpu().numpy()))
+        rec = []
+        s.step(1e-4, 3)
+        rec.append(s.get_state().cpu().numpy())
+        s.adapt(flags_up, 0, 1, [1, 1])
+        assert s.n_elements > 6144
+        s.step(1e-4, 3)
+        rec.append(s.get_state().cpu().numpy())
+        s.adapt(-np.ones(s.n_elements, np.int8), 0, 1, [1, 1])
+        assert s.n_elements == 4096
+        s.step(1e-4, 3)
+        rec.append(s.get_state().cpu().numpy())
+        runs.append(rec)
+    for a, b in zip(*runs):
+        np.testing.assert_array_equal(a, b)

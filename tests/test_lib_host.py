@@ -137,7 +137,9 @@ def test_call_order_errors():
     fl = (ctypes.c_int8 * 4)()
     nl = ctypes.c_int64()
     assert lib.pe_amr_cycle(ctx, 0.05, 0.01, 0, 3, mol, 2, fl, ctypes.byref(nl), None) == -4
-    assert lib.pe_amr_cycle(ctx, 0.05, 0.01, 0, 3, None, 2, fl, ctypes.byref(nl), None) == -1
+    # no map: the context's level rule, still before partition
+    assert lib.pe_amr_cycle(ctx, 0.05, 0.01, 0, 3, None, 2, fl, ctypes.byref(nl), None) == -4
+    assert lib.pe_partition(ctx, None, 0, None) == -4
     buf = ctypes.c_void_p(256)
     assert lib.pe_step_record(ctx, 0.1, buf, ctypes.c_void_p(512), ctypes.c_void_p(1024), None) == -4
     assert lib.pe_step_adjoint_recorded(ctx, 0.1, buf, ctypes.c_void_p(512), ctypes.c_void_p(1024),
@@ -154,3 +156,89 @@ def test_unsupported_and_invalid_physics():
     assert lib.pe_create(ctypes.byref(ctx), ctypes.byref(phys)) == -1
     phys = L.pe_physics(2, 3, 0, 0.9, 0.0, 0.72)
     assert lib.pe_create(ctypes.byref(ctx), ctypes.byref(phys)) == -1
+
+
+def _crafted_family_skipping_a_weighted_stage():
+    """Order-2 family, S = 8, b = (1/6, 0, ..., 0, 1/6, 2/3) with c_7 = 1, c_8 = 1/2 (so b^T 1 = 1,
+    b^T c = 1/2), members E = {2, 8}: the E=2 member evaluates stages 1 and 8 only, so stage 7
+    has b != 0 without every member evaluating it."""
+    fam = pc.perk2_family([4, 8])
+    S = 8
+    fam.E = [2, 8]
+    fam.c = fam.c.copy()
+    fam.c[S - 2], fam.c[S - 1] = 1.0, 0.5
+    fam.b = np.zeros(S)
+    fam.b[0], fam.b[S - 2], fam.b[S - 1] = 1 / 6, 1 / 6, 2 / 3
+    a = np.zeros((2, S))
+    a[1, 2:] = fam.a_sub[1, 2:]
+    fam.a_sub = a
+    return fam
+
+
+def test_rejected_coefficients_leave_context_unchanged():
+    L, lib = _lib()
+    ctx = _ctx(L, lib)
+    good = pc.perk2_family([4, 8, 16])
+    co, keep = _coeffs(L, good)
+    assert lib.pe_set_perk_coefficients(ctx, ctypes.byref(co)) == 0
+    dt = np.ascontiguousarray([0.2, 0.45, 1.0])
+    dp = dt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.pe_set_level_rule(ctx, 1, dp, 1.0) == 0
+    before = (ctypes.c_int32 * 4)()
+    assert lib.pe_level_map(ctx, 3, 4, before) == 0
+    bad = _crafted_family_skipping_a_weighted_stage()
+    co2, keep2 = _coeffs(L, bad)
+    assert lib.pe_set_perk_coefficients(ctx, ctypes.byref(co2)) == -1
+    assert b"does not evaluate it" in lib.pe_last_error(ctx)
+    after = (ctypes.c_int32 * 4)()
+    # still three members and the required-step rule of the good family
+    assert lib.pe_level_map(ctx, 3, 4, after) == 0
+    assert list(after) == list(before) == [0, 1, 2, 2]
+    lib.pe_destroy(ctx)
+
+
+def test_level_rule_argument_errors():
+    L, lib = _lib()
+    ctx = _ctx(L, lib)
+    out = (ctypes.c_int32 * 4)()
+    assert lib.pe_level_map(ctx, 3, 4, out) == -4                 # no coefficients yet
+    dt = np.ascontiguousarray([0.5, 1.0])
+    dp = dt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.pe_set_level_rule(ctx, 1, dp, 1.0) == -4           # required-step needs coefficients
+    co, keep = _coeffs(L, pc.perk2_family([4, 8]))
+    assert lib.pe_set_perk_coefficients(ctx, ctypes.byref(co)) == 0
+    assert lib.pe_set_level_rule(ctx, 7, dp, 1.0) == -1
+    assert lib.pe_set_level_rule(ctx, 1, None, 1.0) == -1
+    assert lib.pe_set_level_rule(ctx, 1, dp, 0.5) == -1
+    neg = np.ascontiguousarray([-0.5, 1.0])
+    assert lib.pe_set_level_rule(ctx, 1, neg.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1.0) == -1
+    assert lib.pe_level_map(ctx, 3, 0, out) == -1
+    assert lib.pe_level_map(ctx, -1, 4, out) == -4                # finest level of a mesh not built
+    assert lib.pe_set_level_rule(ctx, 0, None, 1.0) == 0
+    assert lib.pe_level_map(ctx, 3, 4, out) == 0 and list(out) == [0, 0, 0, 1]
+    # a family with another member count clears the required-step rule
+    assert lib.pe_set_level_rule(ctx, 1, dp, 1.0) == 0
+    co3, keep3 = _coeffs(L, pc.perk2_family([4, 8, 16]))
+    assert lib.pe_set_perk_coefficients(ctx, ctypes.byref(co3)) == 0
+    assert lib.pe_level_map(ctx, 3, 4, out) == -4
+    lib.pe_destroy(ctx)
+
+
+@pytest.mark.parametrize("degree", [2, 3])
+def test_mortar_operators_match_oracle(degree):
+    # the library's 2:1 mortar tables against the oracle's (two independent constructions of the
+    # exact L2 projection: monomial integrals here, Gauss-Legendre quadrature in the oracle)
+    from oracle import dgsem as od
+    L, lib = _lib()
+    ctx = _ctx(L, lib, degree=degree)
+    N = degree + 1
+    P = np.zeros((2, N, N))
+    R = np.zeros((2, N, N))
+    assert lib.pe_mortar_operators(ctx, P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   R.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 0
+    lib.pe_destroy(ctx)
+    o = od.Oracle(pin.uniform_mesh(2, (2, 2), (0.0, 0.0), (1.0, 1.0), 0), N)
+    Po, Ro = o.mortar_ops()
+    np.testing.assert_allclose(P, np.asarray(Po), rtol=0, atol=2e-15)
+    np.testing.assert_allclose(R, np.asarray(Ro), rtol=0, atol=2e-15)
+    np.testing.assert_allclose(R[0] @ P[0] + R[1] @ P[1], np.eye(N), rtol=0, atol=2e-15)

@@ -67,7 +67,7 @@ def _tv_rows():
 
 @pytest.mark.parametrize("key,x,val,pinned,tol", _tv_rows())
 def test_total_variation_tables(key, x, val, pinned, tol):
-    # Tables of Sec. 3.2.4; dt = CFL * 7 dx (disk radius E-1 = 7 at 1/dx), E^(2) = 2 E^(1).
+    # Tables of Sec. 3.2.5; dt = CFL * 7 dx (disk radius E-1 = 7 at 1/dx), E^(2) = 2 E^(1).
     # Tolerance: half a unit of the last printed digit plus 0.006.
     if key == "cfl":
         fam = pc.perk2_family([8, 16])

@@ -83,7 +83,7 @@ def wl_vortex_2level():
     rule = LevelRule.paper()
     mol = rule_map(fam, rule, mesh.leaves[:, 0].max())
     return dict(name="vortex_2level", mesh=mesh, degree=3, fam=fam, mol=mol, rule=rule, ic=ic,
-                dt=stable_dt(fam, mesh, mol, 0.9), t_final=1.0,
+                dt=stable_dt(fam, mesh, mol, 0.9), cfl=0.9, t_final=1.0,
                 desc="2D Euler isentropic vortex (M=0.5, eps=5) on [-5,5]^2, 16x16 roots with the "
                      "centred 4x4 block refined once (304 elements, 2 levels), p=3, EC volume + HLL "
                      "surface flux, P-ERK2{4,8}")
@@ -110,7 +110,7 @@ def wl_kh_amr(n_root=8, level_max=3, name="kh_amr_l3-6"):
     h_min = h_red / 2 ** level_max
     cfl = 0.9
     dt = cfl * fam.dt_opt[-1] * h_min / fam.h_ref
-    return dict(name=name, mesh=mesh, degree=3, fam=fam, mol=mol, rule=rule, ic=ic, dt=dt, t_final=3.0,
+    return dict(name=name, mesh=mesh, degree=3, fam=fam, mol=mol, rule=rule, ic=ic, dt=dt, cfl=cfl, t_final=3.0,
                 perk_maps=[("required-step rule, margin 2", mol), ("required-step rule, margin 1", mol1)],
                 amr=dict(level_min=0, level_max=level_max, interval=10, refine_above=0.05, coarsen_below=0.01,
                          capacity=(n_root << level_max) ** 2),
@@ -142,7 +142,8 @@ def wl_tgv():
     h_min = 2 * np.pi / 16 / 4
     cfl = 0.7
     dt = cfl * fam.dt_opt[-1] * h_min / fam.h_ref
-    return dict(name="tgv_ns_3d", mesh=mesh, degree=3, fam=fam, mol=mol, rule=rule, ic=ic, dt=dt, t_final=200 * dt,
+    return dict(name="tgv_ns_3d", mesh=mesh, degree=3, fam=fam, mol=mol, rule=rule, ic=ic, dt=dt, cfl=cfl,
+                t_final=200 * dt,
                 equations=1, mu=mu,
                 perk_maps=[("required-step rule", mol), ("one member per level", [0, 1, 2])],
                 desc="3D compressible Navier-Stokes Taylor-Green vortex (Ma 0.1, Re 1600, Pr 0.72) on "
@@ -469,9 +470,37 @@ def cpu_baseline(wl, u0_leaf, leaves0, budget_s=15.0):
         if el > budget_s or n >= 1000:
             break
     dofs = mesh.n_elements * (mesh.dim + 2) * (wl["degree"] + 1) ** mesh.dim
+    host = host_cpu()
     return {"value": n * dofs / el, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} P-ERK steps of the same workload ({el:.1f} s, serial C++ oracle, dense "
-                      f"masked stages: every stage evaluated on every element)"}
+                      f"masked stages: every stage evaluated on every element)",
+            "cpu_model": host["model"], "host_cores_total": host["cores_total"],
+            "host_cores_available": host["cores_available"]}
+
+
+def host_cpu():
+    """Model name of the host CPU (as lscpu reports it) and its core counts."""
+    model = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    if model is None:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"model": model, "cores_total": os.cpu_count(), "cores_available": avail}
 
 
 # ----------------------------------------------------------------------------------------
@@ -773,20 +802,109 @@ def compare_equal_error(wl, t_final=None, tol=0.05, ref_budget=6e8):
             "pairs": pairs, "not_compared": skipped}
 
 
-def flops_per_element_stage(dim, N):
-    """Algorithmic fp64 operations of one element-stage of the stage kernel, counted from its
-    code path (divisions, square roots and logarithms as one operation each): one two-point flux
-    of 53 (2D) / 63 (3D) operations per unordered node pair of a line (d N^(d-1) N(N-1)/2
-    pairs, each shared by its two nodes); per node and direction 2 n_v (N-1) operations to
-    accumulate them; per face node one HLL flux of 95 (2D) / 115 (3D); per node 16 operations
-    for primitives and logarithms and 6 n_v for the stage combination."""
+# fp64 flops of the kernels' arithmetic routines, counted from their gfx950 instruction sequences
+# in this build (FMA = 2 flops; the hardware estimates v_rcp_f64 / v_rsq_f64 = 1; compares,
+# exponent/mantissa extraction and conversions = 0): the reciprocal is 1 estimate + 4 FMA, the
+# square root 1 estimate + 2 products + 8 FMA, the logarithm 1 estimate + 16 FMA + 4 sums +
+# 3 products (29 fp64 instructions in all).  A division is a reciprocal and a product.
+RCP_FLOPS, DIV_FLOPS, SQRT_FLOPS, LOG_FLOPS = 9, 10, 19, 40
+
+
+def flops_per_element_stage(dim, N, viscous=False):
+    """Algorithmic fp64 flops of one element-stage of the stage kernel (FMA = 2), from its code
+    path with every reciprocal, division, square root and logarithm weighted by the flops of its
+    instruction sequence (RCP_FLOPS ...):
+      * per unordered node pair of a line (d N^(d-1) N(N-1)/2 pairs, each flux shared by its two
+        nodes) one entropy-conserving flux: two logarithmic means on the series branch (34 and
+        32 flops, each with one reciprocal) and 24 + 3d flops of products and sums;
+      * per node and direction the flux-differencing sum, 2 n_v (N-1) flops;
+      * per node the primitive variables (a reciprocal, 3d + 2 flops), two logarithms and one
+        division (rho / p);
+      * per face node one HLL flux: two sets of primitives, two sound speeds (a division and a
+        square root each, 2 products), the Davis speeds (6), the side fluxes (2 (d + 3)), the
+        blend (a reciprocal, 7 n_v + 2);
+      * per node the lifting, Jacobian and stage combination, 8 n_v flops.
+    Navier-Stokes adds in this kernel the divergence of the viscous flux (2 N d n_v per node)
+    and its face terms (4 n_v per face node)."""
     nv = dim + 2
     nd = N ** dim
-    ec = 53 if dim == 2 else 63
-    hll = 95 if dim == 2 else 115
+    nfn = 2 * dim * N ** (dim - 1)                 # face nodes of the element
+    prim = RCP_FLOPS + 3 * dim + 2
+    ec = (34 + 32) + 24 + 3 * dim
+    hll = 2 * prim + 2 * (DIV_FLOPS + SQRT_FLOPS + 2) + 6 + 2 * (dim + 3) + RCP_FLOPS + 7 * nv + 2
     pairs = dim * N ** (dim - 1) * N * (N - 1) // 2
-    per_node = dim * (N - 1) * 2 * nv + 16 + 6 * nv
-    return pairs * ec + nd * per_node + 2 * dim * N ** (dim - 1) * hll
+    per_node = dim * (N - 1) * 2 * nv + prim + 2 * LOG_FLOPS + DIV_FLOPS + 8 * nv
+    f = pairs * ec + nd * per_node + nfn * hll
+    if viscous:
+        f += nd * 2 * N * dim * nv + nfn * 4 * nv
+    return f
+
+
+def grad_bytes_per_element(dim, N):
+    """Algorithmic HBM bytes of one element of the BR1 gradient pass: read the element's stage
+    value (one slice of n_v N^d fp64) and its neighbours' face traces (2d faces of n_v N^(d-1)
+    values, times 3/2 for neighbours whose stage value is formed from U_n and K_1), write the
+    viscous flux at every node (d slices)."""
+    nv = dim + 2
+    slice_b = nv * N ** dim * 8
+    face_b = 2 * dim * nv * N ** (dim - 1) * 8
+    return slice_b + 1.5 * face_b + dim * slice_b
+
+
+def roofline_of(kernel, ms, launches, bytes_per_launch, flops_per_launch):
+    """Roofline entry of one kernel from its event-timed launches: achieved algorithmic GB/s
+    (and TFLOP/s when a flop count is given) against the MI355X peaks; the bound is the larger
+    fraction."""
+    avg_s = ms * 1e-3 / max(1, launches)
+    gbs = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    out = {"kernel": kernel, "avg_launch_us": avg_s * 1e6, "launches": launches,
+           "bytes_per_launch": bytes_per_launch}
+    frac_b = gbs / HBM_PEAK_GBS
+    if flops_per_launch is None:
+        out.update({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": frac_b})
+        return out
+    tflops = flops_per_launch / avg_s / 1e12 if avg_s > 0 else 0.0
+    frac_f = tflops / FP64_PEAK_TFLOPS
+    out["flops_per_launch"] = flops_per_launch
+    if frac_b >= frac_f:
+        out.update({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": frac_b})
+    else:
+        out.update({"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": frac_f})
+    out["alt"] = {"hbm_frac": frac_b, "alu_frac": frac_f, "gbs": gbs, "tflops": tflops}
+    return out
+
+
+def optimality(fam, wl, finest_steps, dofs_per_elem, rhs_ms, elem_rhs, wall, n_rhs_actual):
+    """N_RHS^Opt, N_RHS+^Hyp and kappa of Sec. 6.4.2-6.4.3.  The hypothetical optimal family gives
+    the finest level of the mesh E_R stage evaluations and halves them per coarser level
+    (E_R / 2^(finest - l)); N_RHS^Opt counts them over the same steps and meshes as the run
+    (finest_steps: per run of steps, the finest level and the element-steps per level).  With a
+    CFL below the optimisation's (CFL_Opt = 1: the optimised step), the optimal scheme would take
+    proportionally fewer steps: N_RHS+^Hyp = N_RHS^Actual - (CFL_Actual / CFL_Opt) N_RHS^Opt
+    (eq. AdditionalRHSEvalsIdealDef_CFLReduction).  kappa = tau_Opt / tau with
+    tau_Opt = tau - N_RHS+^Hyp tau_RHS/C (eq. HypotheticalSpeedUp), tau_RHS/C the measured
+    average cost of one element right-hand side (event-timed stage and gradient kernels over
+    the element-stages they evaluated)."""
+    E_R = float(fam.E[-1])
+    n_opt_elem = 0.0
+    for finest, counts in finest_steps:
+        for l, c in enumerate(counts):
+            if c:
+                n_opt_elem += c * E_R / 2.0 ** (finest - l)
+    n_rhs_opt = n_opt_elem * dofs_per_elem
+    cfl = float(wl.get("cfl", 1.0))
+    n_plus = n_rhs_actual - cfl * n_rhs_opt
+    tau_rhs_c = rhs_ms * 1e-3 / max(1, elem_rhs)          # seconds per element right-hand side
+    tau_opt = wall - (n_plus / dofs_per_elem) * tau_rhs_c
+    return {"n_rhs_opt": n_rhs_opt, "n_rhs_plus_hyp": n_plus, "kappa": tau_opt / wall,
+            "cfl_actual": cfl, "cfl_opt": 1.0, "tau_rhs_per_element_s": tau_rhs_c, "tau_opt_s": tau_opt,
+            "tau_s": wall}
+
+
+def _lib_fingerprint():
+    from paper_2403_05144_amd import _lib
+    return _lib.library_fingerprint()
 
 
 def bytes_per_element_stage(dim, N, viscous=False):
@@ -883,8 +1001,8 @@ def run(args):
                 counts = old.counters()
                 acc["evals"] += counts[0]
                 if profiling:
-                    ms, nl, es = old.profile_stats()
-                    acc["prof"] = [x + y for x, y in zip(acc["prof"], (ms, nl, es))]
+                    for k in range(3):
+                        acc["prof"][k] = [x + y for x, y in zip(acc["prof"][k], old.profile_stats(k))]
                 del old
                 run.clear()
                 run.update(new_run())
@@ -899,6 +1017,12 @@ def run(args):
                 chunk = min(chunk, drv.interval - run["k"] % drv.interval)
             if episode:
                 chunk = min(chunk, episode - run["k"])
+            if profiling:
+                # elements per level over the steps (for N_RHS^Opt, eq. AdditionalRHSEvalsIdealDef);
+                # only in the profiled run, outside the timed one
+                lv = s.leaves()[:, 0]
+                acc["level_steps"] += chunk * np.bincount(lv, minlength=16)[:16]
+                acc["finest_steps"].append((int(lv.max()), chunk * np.bincount(lv, minlength=16)[:16]))
             s.step(dt, chunk)
             run["k"] += chunk
             done += chunk
@@ -915,7 +1039,9 @@ def run(args):
         return excluded
 
     def fresh_acc():
-        return {"dof": 0, "amr_s": 0.0, "n_adapt": 0, "evals": 0, "episodes": 0, "prof": [0.0, 0, 0]}
+        return {"dof": 0, "amr_s": 0.0, "n_adapt": 0, "evals": 0, "episodes": 0,
+                "prof": [[0.0, 0, 0] for _ in range(3)], "level_steps": np.zeros(16, np.int64),
+                "finest_steps": []}
 
     run0 = new_run()
     s = run0["s"]
@@ -948,31 +1074,43 @@ def run(args):
     torch.cuda.synchronize()
     run1["s"].set_profiling(True)
     pacc = fresh_acc()
-    run_steps(run1, args.steps, pacc, profiling=True)
     torch.cuda.synchronize()
-    kern_ms, launches, elem_stages = [x + y for x, y in zip(pacc["prof"], run1["s"].profile_stats())]
+    tp0 = time.perf_counter()
+    p_excluded = run_steps(run1, args.steps, pacc, profiling=True)
+    torch.cuda.synchronize()
+    prof_wall = time.perf_counter() - tp0 - p_excluded
+    prof = [[x + y for x, y in zip(pacc["prof"][k], run1["s"].profile_stats(k))] for k in range(3)]
+    kern_ms, launches, elem_stages = prof[0]
+    grad_ms, grad_launches, grad_elems = prof[1]
+    part_ms, n_part, part_elems = prof[2]
     run1["s"].set_profiling(False)
     wall = t1 - t0 - excluded
     nv = mesh.dim + 2
+    viscous = wl.get("equations", 0) == 1
     value = dof_timed / wall
     n_rhs_actual = tot_evals * nv * N ** mesh.dim
     pid = wall / n_rhs_actual
-    avg_launch_s = kern_ms * 1e-3 / max(1, launches)
     es_per_launch = elem_stages / max(1, launches)
-    B = bytes_per_element_stage(mesh.dim, N, wl.get("equations", 0) == 1) * es_per_launch
-    F = flops_per_element_stage(mesh.dim, N) * es_per_launch
-    gbs = B / avg_launch_s / 1e9
-    tflops = F / avg_launch_s / 1e12
-    frac_b, frac_f = gbs / HBM_PEAK_GBS, tflops / FP64_PEAK_TFLOPS
-    if frac_b >= frac_f:
-        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": frac_b}
-    else:
-        roof = {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": frac_f}
+    roof = roofline_of("k_stage", kern_ms, launches, es_per_launch * bytes_per_element_stage(mesh.dim, N, viscous),
+                       es_per_launch * flops_per_element_stage(mesh.dim, N, viscous))
     roof["traffic"], roof["traffic_source"] = measured_traffic(wl["name"], es_per_launch)
-    roof["kernel"] = "k_stage"
-    roof["avg_launch_us"] = avg_launch_s * 1e6
     roof["element_stages_per_launch"] = es_per_launch
-    roof["alt"] = {"hbm_frac": frac_b, "alu_frac": frac_f, "gbs": gbs, "tflops": tflops}
+    extra = {}
+    if grad_launches:
+        ge = grad_elems / grad_launches
+        rg = roofline_of("k_grad", grad_ms, grad_launches, ge * grad_bytes_per_element(mesh.dim, N), None)
+        rg["elements_per_launch"] = ge
+        extra["roofline_k_grad"] = rg
+        # the whole stage (gradient pass + stage kernel) over the same element-stages
+        rs = roofline_of("stage (k_grad + k_stage)", kern_ms + grad_ms, launches,
+                         es_per_launch * bytes_per_element_stage(mesh.dim, N, viscous)
+                         + ge * grad_bytes_per_element(mesh.dim, N), None)
+        extra["roofline_stage_total"] = rs
+    # optimality measures of Sec. 6.4.2-6.4.3 on the profiled run's level histogram (the same
+    # steps as the timed run)
+    opt = optimality(fam, wl, pacc["finest_steps"], nv * N ** mesh.dim, kern_ms + grad_ms, elem_stages, wall,
+                     n_rhs_actual)
+    lib_path, lib_sha = _lib_fingerprint()
     line = {
         "metric": "DoF-updates/s & PID; P-ERK vs single-level RK wall time at equal error",
         "value": value, "unit": "DoF-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -980,13 +1118,26 @@ def run(args):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl["name"], "description": wl["desc"], "elements_start": int(leaves0.shape[0]),
                    "elements_end": int(n_elements_end), "degree": deg, "family_E": list(fam.E), "order": fam.order,
-                   "dt": dt, "member_of_level": [int(m) for m in wl["mol"]],
+                   "dt": dt, "cfl": wl.get("cfl"), "member_of_level": [int(m) for m in wl["mol"]],
+                   "E_of_level": [int(fam.E[m]) for m in wl["mol"]],
                    "adaptations_timed": n_adapt_timed, "episode_steps": episode,
                    "episode_restarts_timed": acc["episodes"], "restart_s_excluded": excluded},
-        "pid_s": pid, "n_rhs_actual": n_rhs_actual,
-        "stage_kernel_time_frac": kern_ms * 1e-3 / wall,
-        "adaptation_share": amr_s / wall,
+        "pid_s": pid, "pid_per_node_s": pid * nv, "n_rhs_actual": n_rhs_actual,
+        "n_rhs_opt": opt["n_rhs_opt"], "n_rhs_plus_hyp": opt["n_rhs_plus_hyp"], "kappa": opt["kappa"],
+        "optimality": opt,
+        # shares of the profiled run's wall time (every launch timed, re-partitions serialised)
+        "stage_kernel_time_frac": (kern_ms + grad_ms) * 1e-3 / prof_wall,
+        "adaptation_share": pacc["amr_s"] / prof_wall,
+        "repartition_share": (part_ms * 1e-3 / prof_wall) if n_part else 0.0,
+        "adaptation_share_timed_run": amr_s / wall,
+        "repartition": {"count": n_part, "ms_each": part_ms / n_part if n_part else None,
+                        "elements_each": part_elems / n_part if n_part else None,
+                        "how": "pe_amr_cycle's re-partition timed on the host from an idle stream to the end of "
+                               "its kernels (profiled run), share of the profiled run's wall time"
+                        if n_part else "static mesh: partitioned once before the timed region"},
         "roofline": roof,
+        **extra,
+        "library": {"path": os.path.relpath(lib_path, ROOT), "sha256": lib_sha},
     }
     if not args.no_equal_error:
         _log("P-ERK against single-level schemes at equal error")
@@ -1002,7 +1153,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=60)
-    ap.add_argument("--workload", default="kh_amr", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="tgv", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batch-replicas", type=int, default=1, help="batch_vortex64: copies of the 64 runs")

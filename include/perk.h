@@ -264,6 +264,7 @@ pe_status pe_step_adjoint_recorded(pe_ctx* ctx, double dt, const double* u_n, co
  * cfl <= 0. */
 pe_status pe_max_dt(pe_ctx* ctx, double cfl, double* dt_out, double* beta_of_level, void* stream);
 
+
 /* Refinement indicator per leaf (the adaptive Kelvin-Helmholtz workload's density-gradient
  * indicator): eta_e = h_e max_nodes |grad rho| / max_nodes rho, h_e the element size in x,
  * grad rho from the DGSEM derivative matrix.  Written to eta_leaf_host [n_elements] in leaf
@@ -299,14 +300,32 @@ pe_status pe_amr_cycle(pe_ctx* ctx, double refine_above, double coarsen_below, i
 /* Current leaf list (host) [n][4] (level, i, j, k); leaves may be NULL to query n. */
 pe_status pe_get_leaves(const pe_ctx* ctx, int32_t* leaves, int64_t* n);
 
-/* Time every stage-kernel launch of pe_step with a pair of HIP events recorded on the launch
- * stream (on != 0), or stop (0).  Switching resets the statistics. */
+/* Self-check of the arithmetic routines the kernels use instead of library calls: the node
+ * logarithms of the logarithmic means of the entropy-conserving flux (Sec. 6.1 volume flux),
+ * the sound-speed square roots of the HLL wave speeds and the reciprocals.  For device arrays
+ * x [n] and out [3n]: out[0, n) = ln x, out[n, 2n) = sqrt x, out[2n, 3n) = 1/x, asynchronous on
+ * `stream`.  Meant for positive normal arguments (the kernels' domain): the logarithm of x <= 0
+ * is NaN, the rest follow the hardware estimates.  PE_EINVAL for n < 0 or a null array with
+ * n > 0. */
+pe_status pe_device_math(pe_ctx* ctx, const double* x, int64_t n, double* out, void* stream);
+
+/* Time every stage-kernel launch (and, for Navier-Stokes, every BR1 gradient launch) of pe_step
+ * with a pair of HIP events recorded on the launch stream (on != 0), or stop (0).  Switching
+ * resets the statistics. */
 pe_status pe_set_profiling(pe_ctx* ctx, int on);
 
 /* Sum of the event-measured durations of the stage kernels launched since profiling was
  * switched on (milliseconds; waits for the recorded events), the number of launches, and the
  * number of element-stages (active elements summed over the launches). */
 pe_status pe_profile_stats(pe_ctx* ctx, double* kernel_ms, int64_t* launches, int64_t* element_stages);
+
+/* The same per kernel: kernel 0 is the stage kernel (as pe_profile_stats), kernel 1 the BR1
+ * gradient kernel (elements = active elements plus their inactive face neighbours, summed over
+ * the launches), 2 the re-partitions of pe_amr_cycle (Sec. 6.2: the re-assignment of members
+ * after a mesh change), each timed on the host from an idle stream to the end of its kernels
+ * while profiling is on (launches = re-partitions, elements = elements re-partitioned).
+ * PE_EINVAL for any other number. */
+pe_status pe_profile_kernel_stats(pe_ctx* ctx, int kernel, double* kernel_ms, int64_t* launches, int64_t* elements);
 
 /* ---------------------------------------------------------------- batched independent runs
  * Many independent partitioned P-ERK runs (the step of Sec. 3 with the level partition of

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <chrono>
 #include <cstring>
 #include <string>
 #include <unordered_map>
@@ -83,12 +84,15 @@ struct pe_ctx {
   hipGraphExec_t gexec = nullptr;
   std::vector<int> graph_bodies;        // kernel body of every stage launch in gexec (stage_body_id)
   bool maps_on_host = false;            // leaf_of_slot / slot_of_leaf / mem_of_slot copied back
-  // optional per-launch timing of the stage kernels with HIP events on the launch stream
+  // optional per-launch timing of the stage and gradient kernels with HIP events on the launch
+  // stream; ev_kind[k] names the kernel of event pair k (0 stage, 1 gradient)
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind;
   size_t ev_used = 0;
-  int64_t prof_launches = 0, prof_elem_stages = 0;
-  double prof_ms = 0.0;
+  // kernel 2: re-partitions inside pe_amr_cycle (host call and its kernels, serialised)
+  int64_t prof_launches[3] = {0, 0, 0}, prof_elems[3] = {0, 0, 0};
+  double prof_ms[3] = {0.0, 0.0, 0.0};
   // pinned host staging of the adaptation's uploads and the indicator's download (grown on
   // demand); `stage_ev` marks the end of the last transfer out of it still in flight
   void* h_stage = nullptr;
@@ -1215,25 +1219,27 @@ pe_status prof_event(pe_ctx* ctx, hipStream_t s) {
   return PE_OK;
 }
 
-// Next pair of pool events (start, end) for a dispatch-recorded kernel timing.
-pe_status prof_pair(pe_ctx* ctx, hipEvent_t* e0, hipEvent_t* e1) {
+// Next pair of pool events (start, end) for a dispatch-recorded timing of kernel `kind`.
+pe_status prof_pair(pe_ctx* ctx, int kind, hipEvent_t* e0, hipEvent_t* e1) {
   while (ctx->ev_pool.size() < ctx->ev_used + 2) {
     hipEvent_t e;
     HIPCHK(hipEventCreate(&e));
     ctx->ev_pool.push_back(e);
   }
+  if (ctx->ev_kind.size() < ctx->ev_pool.size() / 2) ctx->ev_kind.resize(ctx->ev_pool.size() / 2);
+  ctx->ev_kind[ctx->ev_used / 2] = kind;
   *e0 = ctx->ev_pool[ctx->ev_used++];
   *e1 = ctx->ev_pool[ctx->ev_used++];
   return PE_OK;
 }
 
-// Sum the event pairs recorded so far (waits for them).
+// Sum the event pairs recorded so far per kernel (waits for them).
 pe_status prof_collect(pe_ctx* ctx) {
   for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
     HIPCHK(hipEventSynchronize(ctx->ev_pool[i + 1]));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, ctx->ev_pool[i], ctx->ev_pool[i + 1]));
-    ctx->prof_ms += ms;
+    ctx->prof_ms[ctx->ev_kind[i / 2]] += ms;
   }
   ctx->ev_used = 0;
   return PE_OK;
@@ -1261,16 +1267,25 @@ pe_status enqueue_step(pe_ctx* ctx, double dt, hipStream_t s, bool timed) {
     if (ctx->equations == 1) {
       a.n_halo = ctx->halo_cnt[i];
       a.halo = ctx->d_halo + ctx->halo_off[i];
-      HIPCHK(launch_gradients(ctx->dim, ctx->N, a, m, ctx->ops, ctx->ph, s));
+      if (timed && a.n_act + a.n_halo > 0) {
+        hipEvent_t e0, e1;
+        pe_status st = prof_pair(ctx, 1, &e0, &e1);
+        if (st != PE_OK) return st;
+        HIPCHK(launch_gradients(ctx->dim, ctx->N, a, m, ctx->ops, ctx->ph, s, e0, e1));
+        ctx->prof_launches[1] += 1;
+        ctx->prof_elems[1] += a.n_act + a.n_halo;
+      } else {
+        HIPCHK(launch_gradients(ctx->dim, ctx->N, a, m, ctx->ops, ctx->ph, s));
+      }
     }
     if (timed && a.n_act > 0) {
       // events recorded by the dispatch itself around the stage kernel
       hipEvent_t e0, e1;
-      pe_status st = prof_pair(ctx, &e0, &e1);
+      pe_status st = prof_pair(ctx, 0, &e0, &e1);
       if (st != PE_OK) return st;
       HIPCHK(launch_stage(ctx->dim, ctx->N, ctx->equations == 1, a, m, ctx->ops, ctx->ph, s, e0, e1));
-      ctx->prof_launches += 1;
-      ctx->prof_elem_stages += a.n_act;
+      ctx->prof_launches[0] += 1;
+      ctx->prof_elems[0] += a.n_act;
       if (ctx->ev_used >= 4096) {
         st = prof_collect(ctx);
         if (st != PE_OK) return st;
@@ -1637,9 +1652,28 @@ pe_status pe_amr_cycle(pe_ctx* ctx, double refine_above, double coarsen_below, i
   if (flags_host) std::memcpy(flags_host, flags.data(), (size_t)n);
   st = pe_adapt(ctx, flags.data(), level_min, level_max, stream);
   if (st != PE_OK) return st;
-  st = pe_partition(ctx, member_of_level, n_levels, stream);
-  if (st != PE_OK) return st;
+  if (ctx->profiling) {
+    // the re-partition on its own: from an idle stream to the end of its kernels
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    st = pe_partition(ctx, member_of_level, n_levels, stream);
+    if (st != PE_OK) return st;
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    ctx->prof_ms[2] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    ctx->prof_launches[2] += 1;
+    ctx->prof_elems[2] += ctx->n_e;
+  } else {
+    st = pe_partition(ctx, member_of_level, n_levels, stream);
+    if (st != PE_OK) return st;
+  }
   if (n_leaves) *n_leaves = ctx->n_e;
+  return PE_OK;
+}
+
+pe_status pe_device_math(pe_ctx* ctx, const double* x, int64_t n, double* out, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (n < 0 || (n > 0 && (!x || !out))) return fail(ctx, PE_EINVAL, "device_math: bad arguments");
+  HIPCHK(launch_device_math(n, x, out, (hipStream_t)stream));
   return PE_OK;
 }
 
@@ -1667,19 +1701,26 @@ pe_status pe_set_profiling(pe_ctx* ctx, int on) {
   if (!ctx) return PE_EINVAL;
   ctx->profiling = on != 0;
   ctx->ev_used = 0;
-  ctx->prof_ms = 0.0;
-  ctx->prof_launches = 0;
-  ctx->prof_elem_stages = 0;
+  for (int k = 0; k < 3; ++k) {
+    ctx->prof_ms[k] = 0.0;
+    ctx->prof_launches[k] = 0;
+    ctx->prof_elems[k] = 0;
+  }
   return PE_OK;
 }
 
 pe_status pe_profile_stats(pe_ctx* ctx, double* kernel_ms, int64_t* launches, int64_t* element_stages) {
+  return pe_profile_kernel_stats(ctx, 0, kernel_ms, launches, element_stages);
+}
+
+pe_status pe_profile_kernel_stats(pe_ctx* ctx, int kernel, double* kernel_ms, int64_t* launches, int64_t* elements) {
   if (!ctx) return PE_EINVAL;
+  if (kernel < 0 || kernel > 2) return fail(ctx, PE_EINVAL, "profile_kernel_stats: kernel must be 0, 1 or 2");
   pe_status st = prof_collect(ctx);
   if (st != PE_OK) return st;
-  if (kernel_ms) *kernel_ms = ctx->prof_ms;
-  if (launches) *launches = ctx->prof_launches;
-  if (element_stages) *element_stages = ctx->prof_elem_stages;
+  if (kernel_ms) *kernel_ms = ctx->prof_ms[kernel];
+  if (launches) *launches = ctx->prof_launches[kernel];
+  if (elements) *elements = ctx->prof_elems[kernel];
   return PE_OK;
 }
 

@@ -144,7 +144,7 @@ int stage_body_id(int dim, int N, int n_act);
 // BR1 gradient pass over slots [0, n_act) and the n_halo slots of `halo`: lifted gradients of
 // w = (v, T) with central face values, then the viscous flux F_v at every node into a.Fv.
 hipError_t launch_gradients(int dim, int N, const StageArgs& a, const Mesh& m, const Ops& op,
-                            const Physics& ph, hipStream_t s);
+                            const Physics& ph, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 struct PartitionArgs {
   const int32_t* lev_leaf;       // [n] level per leaf
@@ -183,6 +183,8 @@ hipError_t launch_indicator(int dim, int N, int n, int ld, const int32_t* slot_o
 hipError_t launch_project(int dim, int N, int n_new, int ld, const int32_t* plan, const int32_t* old_slot_of_leaf,
                           const double* U_old, const Ops& op, double* dst_leaf, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+// out[0, n) = ln x, out[n, 2n) = sqrt x, out[2n, 3n) = 1/x with the kernels' own routines
+hipError_t launch_device_math(int64_t n, const double* x, double* out, hipStream_t s);
 // Add the per-slot evaluation counts into per-member totals (member from the partition
 // boundaries) and zero them.
 // Per slot: max over nodes and directions of (N)(|v_d| + c) * (2/h_d) / 2; per level the maximum

@@ -5,6 +5,7 @@
 #include "perk_device.h"
 
 namespace perk {
+
 namespace {
 
 // ------------------------------------------------------------------------------------------
@@ -235,6 +236,15 @@ __global__ void k_project(int64_t total, int ld, const int32_t* plan, const int3
   dst[t] = val;
 }
 
+// The kernels' own arithmetic routines on n arguments: OP 0 logarithm, 1 square root, 2 reciprocal.
+template <int OP>
+__global__ void k_device_math(int64_t n, const double* x, double* y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double v = x[t];
+  y[t] = OP == 0 ? log_pos(v) : (OP == 1 ? sqrt_pos(v) : rcp(v));
+}
+
 __global__ void k_copy(double* dst, const double* src, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) dst[t] = src[t];
@@ -344,6 +354,15 @@ hipError_t launch_wave_speed(int dim, int N, int n, const double* U, const Physi
 hipError_t launch_fold_evals(int n, const Mesh& m, int32_t* evals, unsigned long long* totals, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fold_evals, dim3(1), dim3(1024), 0, s, n, m, evals, totals);
+  return hipGetLastError();
+}
+
+hipError_t launch_device_math(int64_t n, const double* x, double* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 g(grid_for(n, 256)), b(256);
+  hipLaunchKernelGGL(k_device_math<0>, g, b, 0, s, n, x, out);
+  hipLaunchKernelGGL(k_device_math<1>, g, b, 0, s, n, x, out + n);
+  hipLaunchKernelGGL(k_device_math<2>, g, b, 0, s, n, x, out + 2 * n);
   return hipGetLastError();
 }
 

@@ -33,55 +33,6 @@
 namespace perk {
 namespace {
 
-// Square root of a non-negative argument (sound speeds): the hardware reciprocal-square-root
-// estimate refined by two steps of Goldschmidt's coupled iteration for sqrt(x) and 1/(2 sqrt(x)),
-// then one residual correction (correctly rounded in a host test over 2e7 arguments from
-// estimates 2^-20 off).  The library square root scales the argument into range first, which
-// positive normal sound-speed arguments do not need.
-__device__ __forceinline__ double sqrt_pos(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  double h = 0.5 * y, g = x * y;
-  double r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  const double d = fma(-g, g, x);
-  g = fma(d, h, g);
-  return x == 0.0 ? 0.0 : g;
-}
-
-// Natural logarithm of a positive normal argument (node densities and inverse temperatures):
-// x = m 2^e with m in [sqrt(1/2), sqrt(2)), ln m = 2 artanh(f), f = (m - 1)/(m + 1), |f| <= 0.172,
-// the artanh series through f^21 (truncation below 1e-18 relative), e ln 2 added with ln 2 split
-// in two doubles.  Within 2 ulp of the correctly rounded logarithm in a host test over 2e7
-// arguments; about half the instructions of the library logarithm.  Zero and negative
-// arguments give NaN; subnormal ones are not expected here.
-__device__ __forceinline__ double log_pos(double x) {
-  double m = __builtin_amdgcn_frexp_mant(x);   // [1/2, 1)
-  int e = __builtin_amdgcn_frexp_exp(x);
-  const bool lo = m < 0.70710678118654752440;
-  m = lo ? 2.0 * m : m;
-  e = lo ? e - 1 : e;
-  const double f = (m - 1.0) * rcp(m + 1.0), f2 = f * f;
-  double s = 1.0 / 21;
-  s = fma(s, f2, 1.0 / 19);
-  s = fma(s, f2, 1.0 / 17);
-  s = fma(s, f2, 1.0 / 15);
-  s = fma(s, f2, 1.0 / 13);
-  s = fma(s, f2, 1.0 / 11);
-  s = fma(s, f2, 1.0 / 9);
-  s = fma(s, f2, 1.0 / 7);
-  s = fma(s, f2, 1.0 / 5);
-  s = fma(s, f2, 1.0 / 3);
-  const double t = 2.0 * f;
-  const double lm = fma(t * f2, s, t);
-  const double de = (double)e;
-  const double r = fma(de, 0x1.62e42fefa39efp-1, fma(de, 0x1.abc9e3b39803fp-56, lm));
-  return x > 0.0 ? r : __builtin_nan("");   // a non-physical state stays visible as NaN
-}
-
 // Logarithmic mean (a - b)/(ln a - ln b) from precomputed node logarithms.  With
 // f = (a-b)/(a+b), u = f^2 it equals (a+b) / (2 F(u)), F(u) = sum_k u^k/(2k+1); for u < 1e-2
 // the series through u^7/15 is used (truncation < 1e-17), so the difference of logarithms is
@@ -1040,10 +991,14 @@ __global__ __launch_bounds__((GKc<DIM, N>::T), (GKc<DIM, N>::WPS)) void k_grad(S
 }
 
 template <int DIM, int N>
-hipError_t launch_grad_t(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s) {
+hipError_t launch_grad_t(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s,
+                         hipEvent_t ev0, hipEvent_t ev1) {
   const int blocks = a.n_act + a.n_halo;
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_grad<DIM, N>), dim3(blocks), dim3(GKc<DIM, N>::T), 0, s, a, m, op, ph);
+  if (ev0)
+    hipExtLaunchKernelGGL((k_grad<DIM, N>), dim3(blocks), dim3(GKc<DIM, N>::T), 0, s, ev0, ev1, 0, a, m, op, ph);
+  else
+    hipLaunchKernelGGL((k_grad<DIM, N>), dim3(blocks), dim3(GKc<DIM, N>::T), 0, s, a, m, op, ph);
   return hipGetLastError();
 }
 
@@ -1123,11 +1078,11 @@ hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const 
 }
 
 hipError_t launch_gradients(int dim, int N, const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph,
-                            hipStream_t s) {
-  if (dim == 2 && N == 4) return launch_grad_t<2, 4>(a, m, op, ph, s);
-  if (dim == 2 && N == 3) return launch_grad_t<2, 3>(a, m, op, ph, s);
-  if (dim == 3 && N == 4) return launch_grad_t<3, 4>(a, m, op, ph, s);
-  if (dim == 3 && N == 3) return launch_grad_t<3, 3>(a, m, op, ph, s);
+                            hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (dim == 2 && N == 4) return launch_grad_t<2, 4>(a, m, op, ph, s, e0, e1);
+  if (dim == 2 && N == 3) return launch_grad_t<2, 3>(a, m, op, ph, s, e0, e1);
+  if (dim == 3 && N == 4) return launch_grad_t<3, 4>(a, m, op, ph, s, e0, e1);
+  if (dim == 3 && N == 3) return launch_grad_t<3, 3>(a, m, op, ph, s, e0, e1);
   return hipErrorNotSupported;
 }
 

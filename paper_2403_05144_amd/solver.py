@@ -347,10 +347,12 @@ class PerkSolver:
     def set_profiling(self, on):
         self._check(self.lib.pe_set_profiling(self._ctx, int(bool(on))), "pe_set_profiling")
 
-    def profile_stats(self):
+    def profile_stats(self, kernel=0):
+        """(milliseconds, launches, elements) of the timed launches of one kernel: 0 the stage
+        kernel, 1 the BR1 gradient kernel."""
         ms, nl, es = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
-        self._check(self.lib.pe_profile_stats(self._ctx, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(es)),
-                    "pe_profile_stats")
+        self._check(self.lib.pe_profile_kernel_stats(self._ctx, int(kernel), ctypes.byref(ms), ctypes.byref(nl),
+                                                     ctypes.byref(es)), "pe_profile_kernel_stats")
         return ms.value, nl.value, es.value
 
     def counters(self, reset=False):

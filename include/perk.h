@@ -264,6 +264,17 @@ pe_status pe_step_adjoint_recorded(pe_ctx* ctx, double dt, const double* u_n, co
  * cfl <= 0. */
 pe_status pe_max_dt(pe_ctx* ctx, double cfl, double* dt_out, double* beta_of_level, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops): the
+ * bound of pe_max_dt computed entirely on the device, with its scratch (one double per element
+ * plus the 16 per-level maxima) in the library's static per-device array instead of the bound
+ * workspace, and no allocation, copy to the host or synchronisation.  dt_dev [1] and beta_dev
+ * [16] (may be NULL) are caller-owned device arrays written asynchronously on `stream`: the same
+ * values pe_max_dt returns, except that a non-finite or all-zero wave speed gives dt = NaN
+ * instead of an error.  At most 1048576 elements (PE_EINVAL beyond); PE_ESTATE without a
+ * partition and a state, PE_EINVAL for a null dt_dev or cfl <= 0.  Every call on a device
+ * shares that device's scratch: calls that overlap in time on one device (other streams, other
+ * threads) race and must be ordered by the caller. */
+pe_status pe_max_dt_noalloc(pe_ctx* ctx, double cfl, double* dt_dev, double* beta_dev, void* stream);
 
 /* Refinement indicator per leaf (the adaptive Kelvin-Helmholtz workload's density-gradient
  * indicator): eta_e = h_e max_nodes |grad rho| / max_nodes rho, h_e the element size in x,

@@ -1446,6 +1446,20 @@ pe_status pe_max_dt(pe_ctx* ctx, double cfl, double* dt_out, double* beta_of_lev
   return PE_OK;
 }
 
+pe_status pe_max_dt_noalloc(pe_ctx* ctx, double cfl, double* dt_dev, double* beta_dev, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->partitioned || !ctx->state_valid)
+    return fail(ctx, PE_ESTATE, "max_dt_noalloc needs a partition and a state");
+  if (!dt_dev) return fail(ctx, PE_EINVAL, "max_dt_noalloc: null dt");
+  if (!(cfl > 0.0)) return fail(ctx, PE_EINVAL, "max_dt_noalloc: cfl must be positive");
+  if (ctx->n_e > kNoAllocMaxElements)
+    return fail(ctx, PE_EINVAL, "max_dt_noalloc: %d elements exceed the static scratch of %d", ctx->n_e,
+                kNoAllocMaxElements);
+  HIPCHK(launch_max_dt_noalloc(ctx->dim, ctx->N, ctx->n_e, ctx->U, ctx->ph, device_mesh(ctx), cfl, dt_dev, beta_dev,
+                               (hipStream_t)stream));
+  return PE_OK;
+}
+
 namespace {
 // spread the low 21 bits of x to every 2nd (dim 2) or 3rd (dim 3) bit
 inline uint64_t spread2(uint64_t x) {

@@ -11,6 +11,10 @@ namespace perk {
 constexpr int kMaxMembers = 8;    // R
 constexpr int kMaxStages = 32;    // S
 constexpr int kMaxLevels = 16;    // refinement levels of the forest
+constexpr int kMaxDevices = 64;   // devices whose static scratch address is kept
+// elements the allocation-free step-size bound accepts (its static per-device scratch holds one
+// double per element plus the per-level maxima: 8 MiB + 128 B)
+constexpr int kNoAllocMaxElements = 1 << 20;
 constexpr int kMaxN = 4;          // nodes per direction (degree 3)
 
 // Face kinds of an element face (Sec. 6.2: interfaces between equal cells, mortars at 2:1
@@ -183,6 +187,11 @@ hipError_t launch_indicator(int dim, int N, int n, int ld, const int32_t* slot_o
 hipError_t launch_project(int dim, int N, int n_new, int ld, const int32_t* plan, const int32_t* old_slot_of_leaf,
                           const double* U_old, const Ops& op, double* dst_leaf, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+// Step-size bound with the per-slot and per-level scratch in the library's static per-device
+// array (no allocation): dt[0] = cfl / max_l w_l (NaN if a speed is not finite or all are 0),
+// beta[l] = 1 / w_l or 0 (beta may be null).  n in [1, kNoAllocMaxElements].
+hipError_t launch_max_dt_noalloc(int dim, int N, int n, const double* U, const Physics& ph, const Mesh& m,
+                                 double cfl, double* dt, double* beta, hipStream_t s);
 // out[0, n) = ln x, out[n, 2n) = sqrt x, out[2n, 3n) = 1/x with the kernels' own routines
 hipError_t launch_device_math(int64_t n, const double* x, double* out, hipStream_t s);
 // Add the per-slot evaluation counts into per-member totals (member from the partition

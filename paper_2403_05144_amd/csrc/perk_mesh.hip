@@ -2,9 +2,17 @@
 // member, connectivity remap, state permutation), leaf <-> slot layout changes, the AMR
 // indicator and projection, the step-size bound and the evaluation counters.
 
+#include <mutex>
+
 #include "perk_device.h"
 
 namespace perk {
+
+// Scratch of the allocation-free step-size bound (pe_max_dt_noalloc): per-slot wave speeds in
+// [0, kNoAllocMaxElements), per-level maxima in the kMaxLevels doubles after them.  Each device
+// holds its own copy until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (noalloc_scratch).
+static __device__ __align__(256) double scratch[kNoAllocMaxElements + kMaxLevels];
 
 namespace {
 
@@ -245,6 +253,21 @@ __global__ void k_device_math(int64_t n, const double* x, double* y) {
   y[t] = OP == 0 ? log_pos(v) : (OP == 1 ? sqrt_pos(v) : rcp(v));
 }
 
+// dt = cfl / max_l w_l and beta_l = 1 / w_l (0 for levels without elements) on the device; dt is
+// NaN when a level's speed is not finite or every level's speed is zero.
+__global__ void k_dt_from_levels(const double* w_level, double cfl, double* dt, double* beta) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double wmax = 0.0;
+  bool finite = true;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    const double w = w_level[l];
+    finite = finite && (w - w == 0.0);
+    wmax = w > wmax ? w : wmax;
+    if (beta) beta[l] = w > 0.0 ? 1.0 / w : 0.0;
+  }
+  *dt = (finite && wmax > 0.0) ? cfl / wmax : __builtin_nan("");
+}
+
 __global__ void k_copy(double* dst, const double* src, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) dst[t] = src[t];
@@ -354,6 +377,39 @@ hipError_t launch_wave_speed(int dim, int N, int n, const double* U, const Physi
 hipError_t launch_fold_evals(int n, const Mesh& m, int32_t* evals, unsigned long long* totals, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fold_evals, dim3(1), dim3(1024), 0, s, n, m, evals, totals);
+  return hipGetLastError();
+}
+
+hipError_t noalloc_scratch(double** out) {
+  static std::mutex mu;
+  static double* ptrs[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptrs[dev]) {
+    // once per device, with that device current: the device address of this device's copy
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptrs[dev] = static_cast<double*>(p);
+  }
+  *out = ptrs[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_max_dt_noalloc(int dim, int N, int n, const double* U, const Physics& ph, const Mesh& m,
+                                 double cfl, double* dt, double* beta, hipStream_t s) {
+  if (n <= 0 || n > kNoAllocMaxElements) return hipErrorInvalidValue;
+  double* base = nullptr;
+  hipError_t e = noalloc_scratch(&base);
+  if (e != hipSuccess) return e;
+  // every scratch value read below is written first by the same call: w_slot[0, n) by the wave
+  // speed kernel, all kMaxLevels maxima by the level kernel
+  e = launch_wave_speed(dim, N, n, U, ph, m, base, base + kNoAllocMaxElements, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dt_from_levels, dim3(1), dim3(64), 0, s, base + kNoAllocMaxElements, cfl, dt, beta);
   return hipGetLastError();
 }
 

@@ -111,6 +111,14 @@ def log_mean(a, b):
     return lib().orc_log_mean(float(a), float(b))
 
 
+def _member_A(fam, r):
+    """Full Butcher matrix of member r: families with alternative stage patterns (Sec. 3.2.4)
+    carry it themselves, the classic ones by their a_{i,i-1} rows."""
+    if hasattr(fam, "dense"):
+        return fam.dense(r)
+    return dense_A(fam.c, fam.a_sub[r])
+
+
 class Oracle:
     """Serial DGSEM solver on one forest mesh."""
 
@@ -173,7 +181,7 @@ class Oracle:
     def prk_step(self, u, dt, fam: PerkFamily, member):
         """One step of the partitioned RK method (dense, masked)."""
         u = np.array(u, dtype=float, copy=True).reshape(self.shape)
-        A = np.ascontiguousarray(np.stack([dense_A(fam.c, fam.a_sub[r]) for r in range(len(fam.E))]))
+        A = np.ascontiguousarray(np.stack([_member_A(fam, r) for r in range(len(fam.E))]))
         b = np.ascontiguousarray(fam.b, float)
         mem = np.ascontiguousarray(member, np.int32)
         rc = lib().orc_prk_step(self._h, _dp(u), float(dt), len(fam.E), fam.S, _dp(A), _dp(b), _ip(mem))
@@ -202,7 +210,7 @@ class Oracle:
         return out
 
     def _step_args(self, fam, member):
-        A = np.ascontiguousarray(np.stack([dense_A(fam.c, fam.a_sub[r]) for r in range(len(fam.E))]))
+        A = np.ascontiguousarray(np.stack([_member_A(fam, r) for r in range(len(fam.E))]))
         return A, np.ascontiguousarray(fam.b, float), np.ascontiguousarray(member, np.int32)
 
     def prk_step_jvp(self, u, du, dt, fam: PerkFamily, member):

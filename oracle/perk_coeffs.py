@@ -114,8 +114,13 @@ def stability_poly(A: np.ndarray, b: np.ndarray) -> np.ndarray:
 def member_stage_evaluations(a_sub_row: np.ndarray, c: np.ndarray, b: np.ndarray) -> list:
     """Stages i (1-based) whose K_i enters the solution of this member when it is integrated
     alone: K_1, and every K_j used with a nonzero coefficient (Sec. 3.1, reducible methods)."""
-    A = dense_A(c, a_sub_row)
-    S = len(c)
+    return stage_evaluations(dense_A(c, a_sub_row), b)
+
+
+def stage_evaluations(A: np.ndarray, b: np.ndarray) -> list:
+    """The same for a full Butcher matrix A: the stages reachable from the nonzero weights
+    through nonzero entries of A."""
+    S = len(b)
     needed = set()
     frontier = [j for j in range(S) if b[j] != 0.0]
     while frontier:
@@ -324,3 +329,94 @@ def max_stable_step(coef: np.ndarray, eigs, rtol: float = 1e-10) -> float:
         else:
             hi = mid
     return lo
+
+
+# ----------------------------------------------------------------------------------------
+# Alternative stage-evaluation patterns (Sec. 3.2.4, eq. PERK_ButcherTableauAlternating and
+# eq. PERK_ButcherTableauEarlyShared).  A second-order member with E evaluations is given by its
+# chain of evaluated stages s_0 = 0 < s_1 < ... < s_{E-1} = S-1 (0-based): row s_1 is
+# Y = U + dt c K_1, row s_m (m >= 2) couples K_1 and K_{s_{m-1}}, and b = e_S.  For the linear
+# test equation the stage polynomials are y_1 = 1 + c_{s_1} z and
+# y_m = 1 + c_{s_m} z + a_m z (y_{m-1} - 1), so
+#   P(z) = 1 + z y_{E-1} = 1 + z + c_{S-1} z^2 + a_{E-1} c_{s_{E-2}} z^3
+#          + a_{E-1} a_{E-2} c_{s_{E-3}} z^4 + ... + (a_{E-1} ... a_2) c_{s_1} z^E,
+# and matching the monomial coefficients alpha_3 .. alpha_E fixes a_{E-1}, a_{E-2}, ... in turn
+# (the classic chain s_m = S-E+m gives the construction of eq. PERKCoeffsConstruction).
+# ----------------------------------------------------------------------------------------
+PAPER_CHAINS_S6_E4 = {
+    # 0-based evaluated stages of the S = 6, E = 4 tableaux printed in Sec. 3.1 and 3.2.4
+    "classic": [0, 3, 4, 5],        # K_1, K_4, K_5, K_6
+    "alternating": [0, 2, 3, 5],    # K_1, K_3, K_4, K_6
+    "early_shared": [0, 1, 2, 5],   # K_1, K_2, K_3, K_6
+}
+
+
+def chain_member(alpha: dict, chain, S: int):
+    """Coupling column (0-based, -1 for none) and coefficient a_{i,j} of every row of a
+    second-order member evaluating the stages `chain` (0-based, starting at 0, ending at S-1),
+    from the monomial coefficients alpha[3..E] of its stability polynomial."""
+    chain = list(chain)
+    E = len(chain)
+    if chain[0] != 0 or chain[-1] != S - 1 or any(b <= a for a, b in zip(chain, chain[1:])):
+        raise ValueError("chain must rise strictly from stage 0 to stage S-1")
+    c = perk2_abscissae(S)
+    coupling = -np.ones(S, dtype=np.int64)
+    a = np.zeros(S)
+    prod = 1.0
+    for k in range(3, E + 1):
+        m = E + 2 - k                    # chain position whose coefficient alpha_k fixes
+        row, col = chain[m], chain[m - 1]
+        a[row] = alpha[k] / (c[chain[m - 1]] * prod)
+        coupling[row] = col
+        prod *= a[row]
+    return coupling, a
+
+
+def dense_A_coupled(c: np.ndarray, coupling_row, a_row) -> np.ndarray:
+    """Full S x S Butcher matrix of one member with one coupling per row: A[i,0] = c_i - a_i and
+    A[i, j] = a_i for j = coupling_row[i] >= 1, else A[i,0] = c_i."""
+    S = len(c)
+    A = np.zeros((S, S))
+    for i in range(1, S):
+        j = int(coupling_row[i])
+        if j >= 1:
+            A[i, j] = a_row[i]
+            A[i, 0] = c[i] - a_row[i]
+        else:
+            A[i, 0] = c[i]
+    return A
+
+
+@dataclass
+class PatternFamily:
+    """Second-order P-ERK family whose members evaluate their stages along chains of their own
+    (Sec. 3.2.4); c and b = e_S shared.  coupling[r][i] is the 0-based column j >= 1 of the one
+    coupling of row i (-1: none), a_val[r][i] the coefficient a_{i,j}."""
+    order: int
+    S: int
+    E: list
+    c: np.ndarray
+    b: np.ndarray
+    coupling: np.ndarray     # [R, S] int
+    a_val: np.ndarray        # [R, S]
+    chains: list = field(default_factory=list)
+
+    def dense(self, r):
+        return dense_A_coupled(self.c, self.coupling[r], self.a_val[r])
+
+
+def pattern_family(chains, S: int, alphas=None) -> PatternFamily:
+    """Members given by their chains of evaluated stages, each with the disk-optimal
+    second-order polynomial of its degree unless alphas[E] is given."""
+    chains = sorted((list(ch) for ch in chains), key=len)
+    c = perk2_abscissae(S)
+    b = perk2_weights(S)
+    cp, av, E = [], [], []
+    for ch in chains:
+        e = len(ch)
+        alpha = alphas[e] if alphas is not None and e in alphas else disk_optimal_alpha_p2(e)
+        j, a = chain_member(alpha, ch, S)
+        cp.append(j)
+        av.append(a)
+        E.append(e)
+    return PatternFamily(2, S, E, c, b, np.array(cp), np.array(av), chains)

@@ -86,9 +86,22 @@ typedef struct {
   int n_stages;             /* S = E[R-1] (the largest member uses every stage), S <= 32 */
   const int32_t* E;         /* host [R]: stage evaluations per member, strictly ascending */
   const double* c;          /* host [S]: shared abscissae */
-  const double* a_sub;      /* host [R][S]: a_{i,i-1} per member (0-based row i; rows 0 and 1
-                               are 0); a_{i,1} = c_i - a_{i,i-1} (internal consistency) */
+  const double* a_sub;      /* host [R][S]: per member and 0-based row i the one coefficient
+                               beside the first column: a_{i,i-1} (classic pattern) or a_{i,j}
+                               with j = coupling[r][i]; rows 0 and 1 are 0; a_{i,1} = c_i - a_sub
+                               (internal consistency) */
   const double* b;          /* host [S]: shared weights */
+  const int32_t* coupling;  /* host [R][S] or NULL.  NULL: the classic pattern of Sec. 3.1 (member
+                               r evaluates stages 1 and S-E_r+2 .. S, row i couples K_{i-1}).
+                               Otherwise an alternative stage-evaluation pattern (Sec. 3.2.4,
+                               eq. PERK_ButcherTableauAlternating and eq.
+                               PERK_ButcherTableauEarlyShared): the 0-based column j, 1 <= j < i, of
+                               row i's coupling, or -1 for a row that is U_n + dt c_i K_1.  Each
+                               K_j may feed at most one row per member; member r evaluates stage 1,
+                               the stages with b != 0 and the coupled ones, E_r in number, and the
+                               largest member all S.  The active elements of a stage are then a
+                               union of member ranges rather than a prefix.  Euler only; no adjoint
+                               and no batched runs with such patterns (PE_EUNSUPPORTED). */
 } pe_perk_coeffs;
 
 /* Create a context for the given physics.  No device work.  (Sec. 2, eq. ConservationLaw.) */

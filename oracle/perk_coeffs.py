@@ -404,6 +404,11 @@ class PatternFamily:
     def dense(self, r):
         return dense_A_coupled(self.c, self.coupling[r], self.a_val[r])
 
+    @property
+    def a_sub(self):
+        """The coefficient of every row's coupling (the per-row table a solver takes)."""
+        return self.a_val
+
 
 def pattern_family(chains, S: int, alphas=None) -> PatternFamily:
     """Members given by their chains of evaluated stages, each with the disk-optimal

@@ -28,7 +28,8 @@ class pe_mesh_desc(ctypes.Structure):
 class pe_perk_coeffs(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("n_members", ctypes.c_int), ("n_stages", ctypes.c_int),
                 ("E", ctypes.POINTER(ctypes.c_int32)), ("c", ctypes.POINTER(ctypes.c_double)),
-                ("a_sub", ctypes.POINTER(ctypes.c_double)), ("b", ctypes.POINTER(ctypes.c_double))]
+                ("a_sub", ctypes.POINTER(ctypes.c_double)), ("b", ctypes.POINTER(ctypes.c_double)),
+                ("coupling", ctypes.POINTER(ctypes.c_int32))]
 
 
 _lib = None

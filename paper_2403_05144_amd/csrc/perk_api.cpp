@@ -42,7 +42,17 @@ struct pe_ctx {
   bool have_coeffs = false;
   int order = 2, R = 1, S = 1;
   std::vector<int32_t> E;
-  std::vector<double> c, b, a_sub;      // a_sub [R][S]
+  std::vector<double> c, b, a_sub;      // a_sub [R][S]: a_{i,j} of row i's coupling column j
+  // stage-evaluation pattern (Sec. 3.2.4).  Classic families (no coupling table given) couple
+  // row i to column i-1 and keep two alternating stage buffers; a general pattern gives per
+  // member and row the coupling column cpl[r][i] (-1: none), uses[r][j] is the row coupling
+  // K_j (-1: none), and the stage values go to the buffers ybuf_of_stage assigns
+  bool general = false;
+  std::vector<int> cpl, uses;           // [R][S]
+  std::vector<int> ybuf_of_stage;       // [S] (general pattern)
+  int n_ybuf = 2;                       // stage buffers the coefficients need
+  int n_ybuf_bound = 0;                 // stage buffers carved at the last bind
+  std::vector<double*> ybuf;            // Ya, Yb, then the extra ones
   // level -> member rule applied when pe_partition / pe_amr_cycle get no explicit map
   bool have_rule = true;
   int rule = PE_LEVEL_RULE_PAPER;
@@ -70,6 +80,7 @@ struct pe_ctx {
   std::vector<int32_t> counts;          // [R] elements per member
   std::vector<int32_t> leaf_of_slot, slot_of_leaf, mem_of_slot;
   std::vector<int> n_act;               // [S]
+  std::vector<std::vector<std::pair<int, int>>> act_rng;   // [S] active slots as (first, count) ranges
   std::vector<int> halo_off, halo_cnt;  // [S] inactive face neighbours of the active prefix per stage
   bool halo_valid = false;              // built for Navier-Stokes at partition, on demand for the adjoint
   // adjoint workspace (caller-owned device memory): stage values Y_1..Y_{S-1}, stage cotangents
@@ -457,7 +468,8 @@ int64_t state_doubles(const pe_ctx* c) { return cap_of(c) * nvars(c) * nodes_per
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workspace layout: five state-sized fp64 arrays (K1, two stage buffers, the weighted stage
-// sum, a permutation temporary), BR1 gradients for Navier-Stokes, then int32 tables.
+// sum, a permutation temporary), the extra stage buffers of a general stage pattern, BR1
+// gradients for Navier-Stokes, then int32 tables.
 size_t carve(pe_ctx* c, char* base);
 
 size_t workspace_bytes(const pe_ctx* c) {
@@ -467,6 +479,7 @@ size_t workspace_bytes(const pe_ctx* c) {
   tmp.equations = c->equations;
   tmp.n_e = c->n_e;
   tmp.capacity = c->capacity;
+  tmp.n_ybuf = c->n_ybuf;
   return carve(&tmp, nullptr);
 }
 
@@ -484,6 +497,8 @@ size_t carve(pe_ctx* c, char* base) {
   c->Yb = (double*)take(sd);
   c->ACC = (double*)take(sd);
   c->Tmp = (double*)take(sd);
+  c->ybuf.assign({c->Ya, c->Yb});
+  for (int k = 2; k < c->n_ybuf; ++k) c->ybuf.push_back((double*)take(sd));
   c->Fv = c->equations == 1 ? (double*)take((size_t)c->dim * nvars(c) * n * nodes_per_elem(c) * sizeof(double))
                             : nullptr;
   c->d_fk_leaf = (int32_t*)take((size_t)n * nf * 4);
@@ -533,8 +548,20 @@ Mesh device_mesh(const pe_ctx* c) {
   return m;
 }
 
-// member r evaluates 0-based stage i iff i == 0 or i >= S - E_r + 1
-inline bool active(const pe_ctx* c, int r, int i) { return i == 0 || i >= c->S - c->E[r] + 1; }
+// member r evaluates 0-based stage i: classic pattern iff i == 0 or i >= S - E_r + 1; a general
+// pattern iff i == 0, b_i != 0 or some row couples K_i
+inline bool active(const pe_ctx* c, int r, int i) {
+  if (!c->general) return i == 0 || i >= c->S - c->E[r] + 1;
+  return i == 0 || c->b[i] != 0.0 || c->uses[(size_t)r * c->S + i] >= 0;
+}
+
+// where member r's stage value Y_i comes from at stage i: 0 U_n, 1 the stage buffer (computed at
+// an earlier stage), 2 U_n + dt c_i K_1 formed on the fly
+inline int src_code(const pe_ctx* c, int r, int i) {
+  if (i == 0) return 0;
+  if (!c->general) return (active(c, r, i) && active(c, r, i - 1)) ? 1 : 2;
+  return c->cpl[(size_t)r * c->S + i] >= 0 ? 1 : 2;
+}
 
 void fill_stage(const pe_ctx* c, int i, double dt, StageArgs& a) {
   std::memset(&a, 0, sizeof a);
@@ -557,14 +584,108 @@ void fill_stage(const pe_ctx* c, int i, double dt, StageArgs& a) {
     if (c->b[j] != 0.0) a.use_acc_last = 1;
   a.read_acc = (a.acc_mode == 2 || (a.last && a.use_acc_last)) ? 1 : 0;
   for (int r = 0; r < c->R; ++r) {
-    a.src[r] = i == 0 ? 0 : ((active(c, r, i) && active(c, r, i - 1)) ? 1 : 2);
+    a.src[r] = src_code(c, r, i);
     a.src_bits |= a.src[r] << (2 * r);
-    if (i + 1 < c->S) {
-      a.wr[r] = active(c, r, i + 1) ? 1 : 0;
-      a.a2[r] = c->a_sub[(size_t)r * c->S + i + 1];
-      a.a1[r] = c->c[i + 1] - a.a2[r];
+    if (!c->general) {
+      if (i + 1 < c->S) {
+        a.wr[r] = active(c, r, i + 1) ? 1 : 0;
+        a.a2[r] = c->a_sub[(size_t)r * c->S + i + 1];
+        a.a1[r] = c->c[i + 1] - a.a2[r];
+      }
+    } else {
+      // the one row k that couples K_i of this member gets Y_k = U_n + dt (a_{k,1} K_1 + a_{k,i} K_i)
+      const int k = c->uses[(size_t)r * c->S + i];
+      if (k >= 0) {
+        a.wr[r] = 1;
+        a.a2[r] = c->a_sub[(size_t)r * c->S + k];
+        a.a1[r] = c->c[k] - a.a2[r];
+      }
     }
   }
+  // the active elements as slot ranges
+  const auto& rg = c->act_rng[i];
+  a.n_rng = (int)rg.size();
+  for (int k = 0, cum = 0; k < (int)rg.size(); ++k) {
+    a.rng_start[k] = rg[k].first;
+    a.rng_cum[k] = cum;
+    cum += rg[k].second;
+  }
+}
+
+// Stage buffers of launch i: Yin holds Y_i (for members with src 1), Yw[r] receives the stage
+// value member r forms at this stage.  Classic: Y_i alternates between Ya and Yb.
+void set_stage_buffers(const pe_ctx* c, int i, StageArgs& a) {
+  if (!c->general) {
+    a.Yin = (i % 2 == 0) ? c->Ya : c->Yb;
+    a.Yout = (i % 2 == 0) ? c->Yb : c->Ya;
+    for (int r = 0; r < c->R; ++r) a.Yw[r] = a.wr[r] ? a.Yout : nullptr;
+    return;
+  }
+  a.Yin = c->ybuf_of_stage[i] >= 0 ? c->ybuf[c->ybuf_of_stage[i]] : c->Ya;
+  a.Yout = nullptr;
+  for (int r = 0; r < c->R; ++r) {
+    const int k = c->uses[(size_t)r * c->S + i];
+    a.Yw[r] = (a.wr[r] && k >= 0) ? c->ybuf[c->ybuf_of_stage[k]] : nullptr;
+  }
+}
+
+// Classic outputs into caller-chosen buffers: every member writing at this stage writes to a.Yout.
+void classic_outputs(StageArgs& a) {
+  for (int r = 0; r < kMaxMembers; ++r) a.Yw[r] = a.wr[r] ? a.Yout : nullptr;
+}
+
+// Active slot ranges per stage from the member counts: slots hold member R-1 first, then R-2, ...
+// Adjacent active members merge into one range (the classic pattern: one range [0, n_act)).
+void build_activity(pe_ctx* c) {
+  c->n_act.assign(c->S, 0);
+  c->act_rng.assign(c->S, {});
+  for (int i = 0; i < c->S; ++i) {
+    int start = 0;
+    for (int r = c->R - 1; r >= 0; --r) {
+      const int cnt = (int)c->counts.size() == c->R ? c->counts[r] : 0;
+      if (active(c, r, i) && cnt > 0) {
+        auto& rg = c->act_rng[i];
+        if (!rg.empty() && rg.back().first + rg.back().second == start) rg.back().second += cnt;
+        else rg.emplace_back(start, cnt);
+        c->n_act[i] += cnt;
+      }
+      start += cnt;
+    }
+  }
+}
+
+// Stage buffers of a general pattern: Y_k (rows with a coupling in some member) is written at the
+// stages of those couplings and read at stage k; two stage values share a buffer only if their
+// [first write, read] intervals are disjoint (greedy colouring by first write, reads inclusive:
+// a launch never reads and writes one buffer).
+void assign_stage_buffers(pe_ctx* c) {
+  const int S = c->S, R = c->R;
+  c->ybuf_of_stage.assign(S, -1);
+  if (!c->general) {
+    c->n_ybuf = 2;
+    return;
+  }
+  std::vector<int> first(S, S);
+  for (int r = 0; r < R; ++r)
+    for (int k = 0; k < S; ++k) {
+      const int j = c->cpl[(size_t)r * S + k];
+      if (j >= 0) first[k] = std::min(first[k], j);
+    }
+  std::vector<int> free_after;          // per buffer: the last stage that reads it
+  for (int w = 0; w < S; ++w)
+    for (int k = 0; k < S; ++k) {
+      if (first[k] != w) continue;
+      int buf = -1;
+      for (int q = 0; q < (int)free_after.size(); ++q)
+        if (free_after[q] < w) { buf = q; break; }
+      if (buf < 0) {
+        buf = (int)free_after.size();
+        free_after.push_back(-1);
+      }
+      free_after[buf] = k;
+      c->ybuf_of_stage[k] = buf;
+    }
+  c->n_ybuf = std::max(2, (int)free_after.size());
 }
 
 // Member of every level 0..n_levels-1 from the context's rule, the finest level being `finest`
@@ -599,9 +720,9 @@ void level_map(const pe_ctx* c, int finest, int n_levels, int32_t* out) {
 }
 
 bool last_stage_in_place_safe(const pe_ctx* c) {
-  // At the last stage a neighbour reads U_n only if its member is first activated there.
+  // At the last stage a neighbour reads U_n only if its stage value there is formed on the fly.
   for (int r = 0; r < c->R; ++r)
-    if (c->S > 1 && !active(c, r, c->S - 2)) return false;
+    if (c->S > 1 && src_code(c, r, c->S - 1) != 1) return false;
   return true;
 }
 
@@ -676,6 +797,43 @@ pe_status pe_set_perk_coefficients(pe_ctx* ctx, const pe_perk_coeffs* co) {
       return fail(ctx, PE_EINVAL, "coefficients: E must be strictly ascending in [1, S]");
   }
   if (co->E[R - 1] != S) return fail(ctx, PE_EINVAL, "coefficients: largest member must use all S stages");
+  // stage pattern: the classic chain, or one coupling column per row from the table
+  const bool general = co->coupling != nullptr;
+  std::vector<int> cpl((size_t)R * S, -1), uses((size_t)R * S, -1);
+  if (general) {
+    if (ctx->equations != 0)
+      return fail(ctx, PE_EUNSUPPORTED, "coefficients: alternative stage patterns are supported for Euler only");
+    for (int r = 0; r < R; ++r)
+      for (int i = 0; i < S; ++i) {
+        const int j = co->coupling[(size_t)r * S + i];
+        const double av = co->a_sub[(size_t)r * S + i];
+        if (j == -1) {
+          if (av != 0.0) return fail(ctx, PE_EINVAL, "member %d row %d: coefficient without a coupling", r, i + 1);
+          continue;
+        }
+        if (j < 1 || j >= i)
+          return fail(ctx, PE_EINVAL, "member %d row %d: coupling column %d outside [2, %d]", r, i + 1, j + 1, i);
+        if (uses[(size_t)r * S + j] >= 0)
+          return fail(ctx, PE_EINVAL, "member %d: K_%d feeds two stage values", r, j + 1);
+        cpl[(size_t)r * S + i] = j;
+        uses[(size_t)r * S + j] = i;
+      }
+    for (int r = 0; r < R; ++r) {
+      int ev = 0;
+      for (int i = 0; i < S; ++i)
+        if (i == 0 || co->b[i] != 0.0 || uses[(size_t)r * S + i] >= 0) ++ev;
+      if (ev != co->E[r])
+        return fail(ctx, PE_EINVAL, "member %d evaluates %d stages under its coupling table, E says %d", r, ev,
+                    co->E[r]);
+    }
+  } else {
+    for (int r = 0; r < R; ++r)
+      for (int i = S - co->E[r] + 2; i < S; ++i)
+        if (i >= 2) {
+          cpl[(size_t)r * S + i] = i - 1;
+          uses[(size_t)r * S + i - 1] = i;
+        }
+  }
   const double tol = 1e-12;
   double sb = 0.0, sbc = 0.0, sbc2 = 0.0;
   for (int i = 0; i < S; ++i) {
@@ -693,26 +851,47 @@ pe_status pe_set_perk_coefficients(pe_ctx* ctx, const pe_perk_coeffs* co) {
     const double* a = co->a_sub + (size_t)r * S;
     if ((S > 0 && a[0] != 0.0) || (S > 1 && a[1] != 0.0))
       return fail(ctx, PE_EINVAL, "member %d: a_sub rows 0 and 1 must be zero", r);
-    for (int i = 2; i < S; ++i)
-      if (i <= S - co->E[r] + 1 && a[i] != 0.0)
-        return fail(ctx, PE_EINVAL, "member %d (E=%d): a_{%d,%d} must be zero for a stage it skips", r, co->E[r],
-                    i + 1, i);
+    if (!general)
+      for (int i = 2; i < S; ++i)
+        if (i <= S - co->E[r] + 1 && a[i] != 0.0)
+          return fail(ctx, PE_EINVAL, "member %d (E=%d): a_{%d,%d} must be zero for a stage it skips", r, co->E[r],
+                      i + 1, i);
     if (co->order >= 3) {
-      // b^T A c = sum_i b_i (a_{i,1} c_1 + a_{i,i-1} c_{i-1}) with c_1 = 0
+      // b^T A c = sum_i b_i (a_{i,1} c_1 + a_{i,j} c_j) with c_1 = 0, j the coupling column of row i
       double s = 0.0;
-      for (int i = 2; i < S; ++i) s += co->b[i] * a[i] * co->c[i - 1];
+      for (int i = 2; i < S; ++i) {
+        const int j = cpl[(size_t)r * S + i];
+        if (j >= 0) s += co->b[i] * a[i] * co->c[j];
+      }
       if (S > 1) s += co->b[1] * co->c[1] * co->c[0];
       if (std::fabs(s - 1.0 / 6.0) > tol)
         return fail(ctx, PE_EINVAL, "member %d: order condition b^T A c = 1/6 violated (%g)", r, s);
     }
   }
   // every stage with b != 0 evaluated by every member (checked before anything is stored, so a
-  // rejected family leaves the context as it was)
-  for (int i = 0; i < S; ++i)
-    if (co->b[i] != 0.0)
-      for (int r = 0; r < R; ++r)
-        if (!(i == 0 || i >= S - co->E[r] + 1))
-          return fail(ctx, PE_EINVAL, "stage %d has b != 0 but member %d does not evaluate it", i + 1, r);
+  // rejected family leaves the context as it was); a general pattern evaluates such stages by
+  // definition
+  if (!general)
+    for (int i = 0; i < S; ++i)
+      if (co->b[i] != 0.0)
+        for (int r = 0; r < R; ++r)
+          if (!(i == 0 || i >= S - co->E[r] + 1))
+            return fail(ctx, PE_EINVAL, "stage %d has b != 0 but member %d does not evaluate it", i + 1, r);
+  // the largest member evaluates every stage
+  if (general)
+    for (int i = 1; i < S; ++i)
+      if (co->b[i] == 0.0 && uses[(size_t)(R - 1) * S + i] < 0)
+        return fail(ctx, PE_EINVAL, "coefficients: the largest member must evaluate every stage (stage %d)", i + 1);
+  // stage buffers the pattern needs; a bound workspace must already hold them
+  pe_ctx probe;
+  probe.general = general;
+  probe.R = R;
+  probe.S = S;
+  probe.cpl = cpl;
+  assign_stage_buffers(&probe);
+  if (ctx->bound && probe.n_ybuf > ctx->n_ybuf_bound)
+    return fail(ctx, PE_EINVAL, "coefficients: the pattern needs %d stage buffers, the bound workspace has %d "
+                "(query sizes and bind again)", probe.n_ybuf, ctx->n_ybuf_bound);
   if (ctx->have_rule && ctx->rule == PE_LEVEL_RULE_REQUIRED_STEP && (int)ctx->rule_dt_opt.size() != R)
     ctx->have_rule = false;   // the step sizes belonged to another family
   ctx->order = co->order;
@@ -722,6 +901,11 @@ pe_status pe_set_perk_coefficients(pe_ctx* ctx, const pe_perk_coeffs* co) {
   ctx->c.assign(co->c, co->c + S);
   ctx->b.assign(co->b, co->b + S);
   ctx->a_sub.assign(co->a_sub, co->a_sub + (size_t)R * S);
+  ctx->general = general;
+  ctx->cpl = cpl;
+  ctx->uses = uses;
+  ctx->ybuf_of_stage = probe.ybuf_of_stage;
+  ctx->n_ybuf = probe.n_ybuf;
   ctx->have_coeffs = true;
   ctx->partitioned = false;
   ctx->graph_valid = false;
@@ -784,6 +968,7 @@ pe_status pe_bind(pe_ctx* ctx, double* u_dev, void* ws, void* stream) {
   ctx->U = u_dev;
   ctx->ws = (char*)ws;
   carve(ctx, ctx->ws);
+  ctx->n_ybuf_bound = ctx->n_ybuf;
   const int n = ctx->n_e, nf = 2 * ctx->dim;
   HIPCHK(hipMemcpyAsync(ctx->d_fk_leaf, ctx->fk_leaf.data(), (size_t)n * nf * 4, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->d_fn_leaf, ctx->fn_leaf.data(), (size_t)n * nf * 16, hipMemcpyHostToDevice, s));
@@ -934,10 +1119,7 @@ pe_status pe_partition(pe_ctx* ctx, const int32_t* member_of_level, int n_levels
   ctx->counts.assign(ctx->R, 0);
   for (int e = 0; e < n; ++e) ctx->counts[member_of_level[ctx->lev_leaf[e]]] += 1;
   ctx->maps_on_host = false;
-  ctx->n_act.assign(ctx->S, 0);
-  for (int i = 0; i < ctx->S; ++i)
-    for (int r = 0; r < ctx->R; ++r)
-      if (active(ctx, r, i)) ctx->n_act[i] += ctx->counts[r];
+  build_activity(ctx);
   ctx->halo_valid = false;
   if (ctx->equations == 1) {
     pe_status st = build_halo(ctx, s);
@@ -1059,6 +1241,7 @@ namespace {
 pe_status adjoint_ready(pe_ctx* ctx, double dt, const char* who) {
   if (!ctx->partitioned) return fail(ctx, PE_ESTATE, "%s before partition", who);
   if (ctx->equations != 0) return fail(ctx, PE_EUNSUPPORTED, "%s: Euler only", who);
+  if (ctx->general) return fail(ctx, PE_EUNSUPPORTED, "%s: classic stage pattern only", who);
   if (!(dt > 0.0)) return fail(ctx, PE_EINVAL, "%s: dt must be > 0", who);
   if (!ctx->adj_ws || ctx->adj_S != ctx->S || ctx->adj_cap != cap_of(ctx))
     return fail(ctx, PE_ESTATE, "%s: adjoint workspace not bound for these coefficients and capacity", who);
@@ -1086,6 +1269,7 @@ pe_status record_step(pe_ctx* ctx, double dt, const double* u_n, double* K1, Sta
     a.K1 = K1;
     a.Yin = i >= 1 ? Y(i) : ctx->Ya;
     a.Yout = i + 1 < S ? Y(i + 1) : ctx->Yb;
+    classic_outputs(a);
     a.ACC = ctx->ACC;
     a.Uout = u_next;
     a.evals = nullptr;
@@ -1256,13 +1440,12 @@ pe_status enqueue_step(pe_ctx* ctx, double dt, hipStream_t s, bool timed) {
     fill_stage(ctx, i, dt, a);
     a.U = ctx->U;
     a.K1 = ctx->K1;
-    a.Yin = (i % 2 == 0) ? ctx->Ya : ctx->Yb;
-    a.Yout = (i % 2 == 0) ? ctx->Yb : ctx->Ya;
+    set_stage_buffers(ctx, i, a);
     a.ACC = ctx->ACC;
     a.Uout = in_place ? ctx->U : ctx->Tmp;
     a.evals = ctx->d_evals;
     a.Fv = ctx->Fv;
-    if (!a.U || !a.K1 || !a.Yin || !a.Yout || !a.ACC || !a.Uout || (ctx->equations == 1 && !a.Fv))
+    if (!a.U || !a.K1 || !a.Yin || !a.ACC || !a.Uout || (ctx->equations == 1 && !a.Fv))
       return fail(ctx, PE_ESTATE, "step: stage buffers not bound");
     if (ctx->equations == 1) {
       a.n_halo = ctx->halo_cnt[i];
@@ -1856,6 +2039,7 @@ pe_status pe_batch_create(pe_batch** out, pe_ctx* const* runs, int n_runs) {
     if (!c) return bfail(nullptr, PE_EINVAL, "batch: run %d is null", k);
     if (c->dim != 2 || c->equations != 0 || (c->N != 3 && c->N != 4))
       return bfail(nullptr, PE_EUNSUPPORTED, "batch: run %d is not 2D Euler with degree 2 or 3", k);
+    if (c->general) return bfail(nullptr, PE_EUNSUPPORTED, "batch: run %d has an alternative stage pattern", k);
     if (!c->partitioned || !c->state_valid || !c->bound)
       return bfail(nullptr, PE_ESTATE, "batch: run %d needs a bound state and a partition", k);
     if (!last_stage_in_place_safe(c))
@@ -1906,8 +2090,7 @@ pe_status pe_batch_set_steps(pe_batch* b, const double* dt, const int64_t* n_ste
       fill_stage(c, i, dt[k], a);
       a.U = c->U;
       a.K1 = c->K1;
-      a.Yin = (i % 2 == 0) ? c->Ya : c->Yb;
-      a.Yout = (i % 2 == 0) ? c->Yb : c->Ya;
+      set_stage_buffers(c, i, a);
       a.ACC = c->ACC;
       a.Uout = c->U;
       a.evals = c->d_evals;

@@ -72,14 +72,17 @@ struct StageArgs {
   const double* U;        // U_n (slot layout)
   double* K1;             // K_1 (written at stage 0)
   const double* Yin;      // Y_i of elements whose member was active at stages i-1 and i
-  double* Yout;           // Y_{i+1} of elements active at stage i+1
+  double* Yout;           // host side: the classic pattern's next-stage buffer (kernels use Yw)
   double* ACC;            // running sum of b_j K_j over the stages with b_j != 0 before the last
   double* Uout;           // U_{n+1} at the last stage (may alias U)
   double* Kout;           // if non-null: K_i is written here and nothing else (right-hand side)
   double* Fv;             // BR1 viscous flux [dim][n_v][slot][node] (Navier-Stokes; written by the
                           // gradient kernel, read by the stage kernel)
   int32_t* evals;         // [slot] right-hand-side evaluations of the slot's element, or null
-  int n_act;              // active slots: [0, n_act)
+  int n_act;              // active elements of the launch: n_act
+  int n_rng;              // they are the slots of n_rng ranges in order (0 or 1: [0, n_act)):
+  int rng_start[kMaxMembers];   // range k begins at slot rng_start[k] and holds the active
+  int rng_cum[kMaxMembers];     // indices [rng_cum[k], rng_cum[k + 1]) (rng_cum[0] = 0)
   int n_halo;             // Navier-Stokes gradient kernel only: extra slots listed in halo
   const int32_t* halo;
   double dt;
@@ -93,10 +96,21 @@ struct StageArgs {
   int src[kMaxMembers];   // where Y_i of a member comes from: 0 U_n, 1 Yin, 2 U_n + dt c_i K_1
   int src_bits;           // the same codes, two bits per member (member r at bits 2r, 2r+1)
   int read_acc;           // the epilogue reads ACC (acc_mode 2, or the last stage with use_acc_last)
-  int wr[kMaxMembers];    // member writes Y_{i+1}
-  double a1[kMaxMembers]; // a_{i+1,1}
-  double a2[kMaxMembers]; // a_{i+1,i}
+  int wr[kMaxMembers];    // member writes its next stage value Y_k (k = i+1 for the classic
+                          // pattern) into Yw[member]
+  double a1[kMaxMembers]; // a_{k,1}
+  double a2[kMaxMembers]; // a_{k,i}
+  double* Yw[kMaxMembers];
 };
+
+// Slot of the v-th active element of a launch (v < n_act): ranges are few (one per member at
+// most) and the same for every lane of a block, so this is scalar work.
+__host__ __device__ inline int active_slot(const StageArgs& a, int v) {
+  int k = 0;
+#pragma unroll
+  for (int j = 1; j < kMaxMembers; ++j) k += (j < a.n_rng && v >= a.rng_cum[j]) ? 1 : 0;
+  return a.rng_start[k] + (v - a.rng_cum[k]);
+}
 
 __host__ __device__ inline int src_of(const StageArgs& a, int member) { return (a.src_bits >> (2 * member)) & 3; }
 

@@ -261,8 +261,9 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
 
   const int le = threadIdx.x / T;
   const int lane = threadIdx.x - le * T;
-  const int e = blk * EPB + le;
-  const bool act = e < a.n_act;
+  const int v_act = blk * EPB + le;                 // index among the launch's active elements
+  const bool act = v_act < a.n_act;
+  const int e = act ? active_slot(a, v_act) : v_act;
   const int ld = m.ld;
   const double gamma = ph.gamma;
   const double inv_gm1 = 1.0 / (gamma - 1.0);
@@ -699,7 +700,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       const double inc = a.use_acc_last ? (a.acc_mode == 0 ? accv : a.ACC[idx]) + a.bS * du : a.bS * du;
       a.Uout[idx] = (HOLD_OPS ? un[it] : a.U[idx]) + a.dt * inc;
     } else if (a.wr[my_mem]) {
-      a.Yout[idx] = (HOLD_OPS ? un[it] : a.U[idx]) + a.dt * (a.a1[my_mem] * K1v + a.a2[my_mem] * du);
+      a.Yw[my_mem][idx] = (HOLD_OPS ? un[it] : a.U[idx]) + a.dt * (a.a1[my_mem] * K1v + a.a2[my_mem] * du);
     }
   }
 }
@@ -817,7 +818,7 @@ __global__ __launch_bounds__((GKc<DIM, N>::T), (GKc<DIM, N>::WPS)) void k_grad(S
   // would each be a slow memory round)
   __shared__ double s_op[5][N * N];
   const int b = blockIdx.x;
-  const int e = b < a.n_act ? b : a.halo[b - a.n_act];
+  const int e = b < a.n_act ? active_slot(a, b) : a.halo[b - a.n_act];
   const int lane = threadIdx.x;
   const int ld = m.ld;
   const double gamma = ph.gamma;

@@ -87,12 +87,16 @@ class PerkSolver:
         c = np.ascontiguousarray(np.asarray(fam.c, dtype=np.float64))
         b = np.ascontiguousarray(np.asarray(fam.b, dtype=np.float64))
         a = np.ascontiguousarray(np.asarray(fam.a_sub, dtype=np.float64).reshape(len(E), -1))
-        self._coef_keep = (E, c, b, a)
+        # an alternative stage pattern (Sec. 3.2.4) carries its coupling columns
+        cp = getattr(fam, "coupling", None)
+        cp = None if cp is None else np.ascontiguousarray(np.asarray(cp, dtype=np.int32).reshape(len(E), -1))
+        self._coef_keep = (E, c, b, a, cp)
         co = L.pe_perk_coeffs(int(fam.order), len(E), int(fam.S),
                               E.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                               c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                               a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                              b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                              b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              None if cp is None else cp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         self._check(self.lib.pe_set_perk_coefficients(self._ctx, ctypes.byref(co)),
                     "pe_set_perk_coefficients")
 

@@ -242,3 +242,45 @@ def test_mortar_operators_match_oracle(degree):
     np.testing.assert_allclose(P, np.asarray(Po), rtol=0, atol=2e-15)
     np.testing.assert_allclose(R, np.asarray(Ro), rtol=0, atol=2e-15)
     np.testing.assert_allclose(R[0] @ P[0] + R[1] @ P[1], np.eye(N), rtol=0, atol=2e-15)
+
+
+def _pattern_coeffs(L, fam, coupling=None):
+    co, keep = _coeffs(L, fam)
+    cp = np.ascontiguousarray(fam.coupling if coupling is None else coupling, dtype=np.int32)
+    co.coupling = cp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    return co, keep + (cp,)
+
+
+def test_stage_pattern_validation():
+    # alternative stage patterns (Sec. 3.2.4): the coupling table is checked before anything is
+    # stored
+    L, lib = _lib()
+    ctx = _ctx(L, lib)
+    fam = pc.pattern_family([[0, 3, 5, 7], [0, 1, 2, 3, 4, 7], list(range(8))], 8)
+    co, keep = _pattern_coeffs(L, fam)
+    assert lib.pe_set_perk_coefficients(ctx, ctypes.byref(co)) == 0
+    # a coupling to a later (or the same) column
+    bad = fam.coupling.copy(); bad[0, 5] = 5
+    co, keep = _pattern_coeffs(L, fam, bad)
+    assert lib.pe_set_perk_coefficients(ctx, ctypes.byref(co)) == -1
+    # K_4 feeding two rows of one member
+    bad = fam.coupling.copy(); bad[0, 7] = 3
+    co, keep = _pattern_coeffs(L, fam, bad)
+    assert lib.pe_set_perk_coefficients(ctx, ctypes.byref(co)) == -1
+    # a coefficient on a row without a coupling
+    fam2 = pc.pattern_family([[0, 3, 5, 7], [0, 1, 2, 3, 4, 7], list(range(8))], 8)
+    fam2.a_val = fam2.a_val.copy(); fam2.a_val[0, 4] = 0.1
+    co, keep = _pattern_coeffs(L, fam2)
+    assert lib.pe_set_perk_coefficients(ctx, ctypes.byref(co)) == -1
+    # E that does not match the evaluated stages
+    fam3 = pc.pattern_family([[0, 3, 5, 7], [0, 1, 2, 3, 4, 7], list(range(8))], 8)
+    fam3.E = [4, 5, 8]
+    co, keep = _pattern_coeffs(L, fam3)
+    assert lib.pe_set_perk_coefficients(ctx, ctypes.byref(co)) == -1
+    assert b"E says" in lib.pe_last_error(ctx)
+    lib.pe_destroy(ctx)
+    # Navier-Stokes contexts take the classic pattern only
+    ctx = _ctx(L, lib, eq=1)
+    co, keep = _pattern_coeffs(L, fam)
+    assert lib.pe_set_perk_coefficients(ctx, ctypes.byref(co)) == -6
+    lib.pe_destroy(ctx)

@@ -25,8 +25,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# files whose contents define the stage kernel (hashed into the counter summaries)
+# what defines the stage kernel (hashed into the counter summaries): its source, the device
+# helpers, and the data structures of the internal header (up to its launch declarations)
 STAGE_KERNEL_SOURCES = ("perk_stage.hip", "perk_device.h", "perk_internal.h")
+
+
+def stage_kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in STAGE_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2403_05144_amd", "csrc", name), "rb") as f:
+            data = f.read()
+        if name == "perk_internal.h":
+            cut = data.find(b"// Kernel launch wrappers")
+            data = data[:cut] if cut >= 0 else data
+        h.update(data)
+    return h.hexdigest()
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -71,6 +85,17 @@ def stable_dt(fam, mesh, mol, cfl):
         r = mol[int(l)]
         dts.append(fam.dt_opt[r] * h(l) / fam.h_ref)
     return cfl * min(dts)
+
+
+def make_solver(wl, mesh, fam, mol):
+    """The workload's solver: capacity, equations and refinement indicator as the workload says."""
+    from paper_2403_05144_amd import PerkSolver
+    amr = wl.get("amr")
+    s = PerkSolver(mesh, wl["degree"], fam, mol, capacity=amr["capacity"] if amr else None,
+                   equations=wl.get("equations", 0), mu=wl.get("mu", 0.0))
+    if amr and amr.get("indicator"):
+        s.set_indicator(*amr["indicator"])
+    return s
 
 
 def wl_vortex_2level():
@@ -120,6 +145,38 @@ def wl_kh_amr(n_root=8, level_max=3, name="kh_amr_l3-6"):
                      f"{int(np.log2(n_root)) + level_max} every 10 steps with re-partition after every "
                      f"adaptation, P-ERK3{{4,6,8,12,16}} with levels mapped to E={[fam.E[r] for r in mol]} "
                      f"(required-step rule, margin 2), CFL {cfl} of the finest member's optimised step")
+
+
+def wl_shear_layer():
+    """2D compressible Navier-Stokes doubly periodic shear layer (Sec. 7.1.1, eq. ShearLayerIC):
+    kappa 80, delta 0.05, c0 10 (Ma 0.1), Re 2.5e4, Pr 0.72 on [0,1]^2; 8x8 roots (level 3),
+    adaptation every 20 steps on Loehner's indicator of v_x (f_wave 0.2) up to six refinements
+    (level 9, 512 cells per direction); p = 3, BR1; P-ERK3{3,4,7} from the project's optimisation
+    on the spectrum of the 8x8 mesh, levels mapped by the paper's rule (finest E = 7, next E = 4,
+    the rest E = 3).  The timed run uses CFL 0.9 of the finest member's optimised step."""
+    import perk_inputs as pin
+    from paper_2403_05144_amd.partition_rule import LevelRule
+    mu = 1.0 / 2.5e4
+    mesh = pin.uniform_mesh(2, (8, 8), (0, 0), (1, 1), 0)
+    ic = lambda x: pin.shear_layer(x[0], x[1])
+    h_red = 1.0 / 8
+    fam = family_for("perk3_3_4_7_shear_p3", 3, [3, 4, 7], pin.uniform_mesh(2, (8, 8), (0, 0), (1, 1), 0), 3, ic,
+                     h_red, equations=1, mu=mu)
+    level_max = 6
+    rule = LevelRule.paper()
+    mol = rule_map(fam, rule, level_max)
+    cfl = 0.9
+    dt = cfl * fam.dt_opt[-1] * (h_red / 2 ** level_max) / fam.h_ref
+    return dict(name="shear_layer_ns_2d", mesh=mesh, degree=3, fam=fam, mol=mol, rule=rule, ic=ic, dt=dt, cfl=cfl,
+                t_final=1.2, eq_t_final=0.1, equations=1, mu=mu,
+                amr=dict(level_min=0, level_max=level_max, interval=20, refine_above=0.2, coarsen_below=0.05,
+                         capacity=1 << 17, indicator=("lohner", 1, 0.2)),
+                perk_maps=[("paper rule", mol)],
+                desc="2D compressible Navier-Stokes doubly periodic shear layer (kappa 80, delta 0.05, Ma 0.1, "
+                     "Re 2.5e4, Pr 0.72) on [0,1]^2, p=3, EC volume + HLL surface flux, BR1, quadtree AMR on "
+                     "Loehner's indicator of v_x between levels 3 and 9 every 20 steps with re-partition after "
+                     f"every adaptation, P-ERK3{{3,4,7}} with levels mapped to E={[fam.E[r] for r in mol]} "
+                     f"(paper rule), CFL {cfl} of the finest member's optimised step")
 
 
 def wl_tgv():
@@ -362,6 +419,154 @@ def run_adjoint(args):
     }
 
 
+PATTERN_CHAINS_S8_E4 = {
+    # 0-based evaluated stages of the E = 4 member in an S = 8 family: the classic chain (the last
+    # three stages), and the alternating and early-shared chains of Sec. 3.2.4 carried over from
+    # the printed S = 6 examples ({1,3,4,6} -> {1,5,6,8}, {1,2,3,6} -> {1,2,3,8}, 1-based)
+    "classic": [0, 5, 6, 7],
+    "alternating": [0, 4, 5, 7],
+    "early_shared": [0, 1, 2, 7],
+}
+
+
+def run_patterns(args):
+    """Alternative stage-evaluation patterns (Sec. 3.2.4) on the same kernels: the 2-level band
+    mesh (64^2 roots, band refined: 7168 elements, p = 3, Kelvin-Helmholtz state), P-ERK2{4,8}
+    from the product's optimisation, the E = 4 member (3072 coarse elements) on each chain of
+    PATTERN_CHAINS_S8_E4 in turn, the same polynomials.  Per pattern: DoF-updates/s over the
+    timed steps (graph replay) and the stage kernel's event-timed launches (roofline as for the
+    main workloads)."""
+    import torch
+    import perk_inputs as pin
+    from paper_2403_05144_amd import PerkSolver, coeffs
+    mesh = pin.mesh_band_2level(64)
+    ic = lambda x: pin.kelvin_helmholtz(x[0], x[1])
+    base = family_for("perk2_4_8_kh_p3_n8", 2, [4, 8], pin.uniform_mesh(2, (8, 8), (-1, -1), (1, 1), 0), 3, ic, 0.25)
+    mol = [0, 1]
+    dt = stable_dt(base, mesh, mol, 0.5)
+    rows = {}
+    for kind, chain in PATTERN_CHAINS_S8_E4.items():
+        fam = coeffs.with_chains(base, [chain, None])
+        s = PerkSolver(mesh, 3, fam, mol)
+        x = s.node_coords().cpu().numpy().transpose(1, 0, 2)
+        s.set_state(ic(x).transpose(1, 0, 2).copy())
+        s.step(dt, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(dt, args.steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if not np.all(np.isfinite(s.get_state().cpu().numpy())):
+            raise RuntimeError(f"patterns: non-finite state ({kind})")
+        s.set_profiling(True)
+        s.step(dt, min(args.steps, 20))
+        torch.cuda.synchronize()
+        ms, nl, es = s.profile_stats()
+        s.set_profiling(False)
+        esl = es / max(1, nl)
+        roof = roofline_of("k_stage", ms, nl, esl * bytes_per_element_stage(2, 4), esl * flops_per_element_stage(2, 4))
+        roof["element_stages_per_launch"] = esl
+        dofs = s.n_elements * s.nv * s.Nd
+        rows[kind] = {"chain_E4": chain, "dof_updates_per_s": dofs * args.steps / wall,
+                      "ms_per_step": wall / args.steps * 1e3, "roofline": roof}
+        _log(f"patterns {kind}: {rows[kind]['dof_updates_per_s']:.3e} DoF-updates/s, "
+             f"{roof['avg_launch_us']:.2f} us per launch, frac {roof['frac']:.3f}")
+        del s
+    c = rows["classic"]
+    return {
+        "metric": "DoF-updates/s & PID; P-ERK vs single-level RK wall time at equal error",
+        "value": c["dof_updates_per_s"], "unit": "DoF-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": c["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "patterns_band64", "elements": 7168, "degree": 3, "family_E": [4, 8], "dt": dt,
+                   "description": "2D Euler Kelvin-Helmholtz state on the 2-level band mesh (64^2 roots, 7168 "
+                                  "elements, p=3), P-ERK2{4,8} with the E=4 member on the classic, alternating "
+                                  "and early-shared stage chains (same polynomials); value: classic chain"},
+        "roofline": c["roofline"], "patterns": rows,
+    }
+
+
+def run_spectrum(args):
+    """Spectrum estimation at the real mesh (Sec. 4.1, steps 2-4) on the GPU: the hull points of the
+    reduced-mesh spectrum, scaled by h_reduced / h, as targets; one Arnoldi factorisation of m
+    steps of the Jacobian at the initial state (KH: exact products with J^T; TGV: central
+    differences); Ritz values plus the harmonic Ritz values nearest to every target; then the
+    P-ERK family optimised on those eigenvalues, next to the reduced-mesh family the benchmark
+    uses.  Timed: the Arnoldi factorisation (device) and the eigenvalue extraction (host)."""
+    import torch
+    import perk_inputs as pin
+    from paper_2403_05144_amd import coeffs
+    from paper_2403_05144_amd.amr import AmrDriver
+    out = {}
+    m = args.arnoldi_steps
+    for key, mk, op in (("kh_amr_l3-6", wl_kh_amr, "vjp"), ("tgv_ns_3d", wl_tgv, "fd")):
+        wl = mk()
+        fam = wl["fam"]
+        mesh = wl["mesh"]
+        m0 = pin.MeshDesc(mesh.dim, mesh.n_root, mesh.lo, mesh.hi, np.array(mesh.leaves, copy=True))
+        s = make_solver(wl, m0, fam, wl["mol"])
+        ic_leaf = lambda x: wl["ic"](x.transpose(1, 0, 2)).transpose(1, 0, 2).copy()
+        if wl.get("amr"):
+            a = wl["amr"]
+            AmrDriver(s, a["level_min"], a["level_max"], wl["mol"], a["refine_above"], a["coarsen_below"],
+                      a["interval"]).initial_mesh(ic_leaf, passes=3)
+        else:
+            s.set_state(ic_leaf(s.node_coords().cpu().numpy()))
+        # reduced spectrum of the family's own construction (its reduced mesh and element size)
+        red_mesh = (pin.uniform_mesh(2, (8, 8), (-1, -1), (1, 1), 0) if mesh.dim == 2 else
+                    pin.uniform_mesh(3, (2, 2, 2), (-np.pi,) * 3, (np.pi,) * 3, 0))
+        rs = make_solver(dict(wl, amr=None), red_mesh, fam, [0] * 8)
+        rs.set_state(ic_leaf(rs.node_coords().cpu().numpy()))
+        t0 = time.perf_counter()
+        lam_red = coeffs.fd_spectrum(rs, rs.get_state().cpu().numpy())
+        t_red = time.perf_counter() - t0
+        del rs
+        lv = s.leaves()[:, 0]
+        h_min = (mesh.hi[0] - mesh.lo[0]) / (mesh.n_root[0] << int(lv.max()))
+        u = s.u.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H = coeffs.arnoldi(s, u, m, op=op)
+        torch.cuda.synchronize()
+        t_arn = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        shifts = coeffs.hull_points(lam_red) * (fam.h_ref / h_min)
+        per = max(1, 1000 // max(1, len(shifts)))
+        ritz = np.linalg.eigvals(H[: H.shape[1], : H.shape[1]])
+        est = [ritz]
+        for sg in shifts:
+            th = coeffs.harmonic_ritz(H, sg)
+            est.append(th[np.argsort(np.abs(th - sg))[:per]])
+        lam = np.concatenate(est)
+        lam = lam[np.isfinite(lam) & (lam.imag >= 0)]
+        lam.real = np.minimum(lam.real, 0.0)
+        t_eig = time.perf_counter() - t0
+        full = coeffs.build_family(fam.order, fam.E, coeffs.hull_points(lam), h_ref=h_min)
+        scaled_red = [d * h_min / fam.h_ref for d in fam.dt_opt]
+        n = int(s.n_elements * s.nv * s.Nd)
+        out[key] = {"elements": int(s.n_elements), "unknowns": n, "arnoldi_steps": int(H.shape[1]),
+                    "products": "exact J^T (adjoint kernel)" if op == "vjp" else "central differences of F",
+                    "targets": int(len(shifts)), "eigenvalue_estimates": int(len(lam)),
+                    "spectral_radius_estimate": float(np.abs(lam).max()),
+                    "reduced_spectral_radius_scaled": float(np.abs(lam_red).max() * fam.h_ref / h_min),
+                    "arnoldi_s": t_arn, "eigen_s": t_eig, "reduced_spectrum_s": t_red,
+                    "dt_opt_full_mesh": [float(x) for x in full.dt_opt],
+                    "dt_opt_reduced_scaled": [float(x) for x in scaled_red],
+                    "E": list(fam.E)}
+        _log(f"spectrum {key}: {H.shape[1]} Arnoldi steps on {n} unknowns in {t_arn:.2f} s, "
+             f"{len(lam)} estimates; dt_opt full {np.round(full.dt_opt, 6)} vs reduced {np.round(scaled_red, 6)}")
+        del s
+        torch.cuda.empty_cache()
+    k = out["tgv_ns_3d"]
+    return {"metric": "DoF-updates/s & PID; P-ERK vs single-level RK wall time at equal error",
+            "value": k["unknowns"] * k["arnoldi_steps"] / k["arnoldi_s"], "unit": "DoF-updates/s",
+            "n_gpus": 1, "steps": k["arnoldi_steps"], "warmup": 0, "ms_per_step": k["arnoldi_s"] / k["arnoldi_steps"] * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "spectrum", "description": "Arnoldi spectrum estimation at the real meshes of the "
+                       "KH and TGV workloads (value: TGV unknowns x Arnoldi steps per second)"},
+            "spectra": out}
+
+
 def run_sweep(args):
     """Stage-kernel throughput on uniform single-level meshes, every element active at every
     stage: 2D p=3 Euler on 64^2 ... 1024^2 elements (isentropic vortex, P-ERK2;8 alone) and 3D
@@ -443,7 +648,8 @@ def run_sweep(args):
 
 
 WORKLOADS = {"vortex_2level": wl_vortex_2level, "kh_amr": wl_kh_amr, "tgv": wl_tgv, "batch_vortex64": None,
-             "adjoint_kh": None, "uniform_sweep": None,
+             "adjoint_kh": None, "uniform_sweep": None, "patterns": None, "shear_layer": wl_shear_layer,
+             "spectrum": None,
              "kh_amr_l4-7": lambda: wl_kh_amr(16, 3, "kh_amr_l4-7")}
 
 
@@ -539,12 +745,20 @@ def _steps_per_interval(spi, n_int):
     return np.diff(edges)
 
 
+def _kinetic_energy(u_leaf, w_leaf, dim):
+    """Discrete total kinetic energy sum_nodes w |rho v|^2 / (2 rho) of a leaf-layout state."""
+    mom2 = np.sum(u_leaf[:, 1:1 + dim] ** 2, axis=1)
+    return float(np.sum(w_leaf * 0.5 * mom2 / u_leaf[:, 0]))
+
+
 def _integrate(wl, fam1, mol1, start, T_int, n_int, spi, flags=None, record=False, reps=1):
-    """One run over [0, n_int T_int]: interval k takes its share of round(spi n_int) equal steps;
-    between intervals an adaptive workload adapts the mesh (recording the flags from the GPU
-    indicator, or replaying recorded ones).  Returns the wall time of the stepping and
-    adaptation (graph replay path; the smallest of `reps` runs, repeated on the same solver for
-    a static mesh and on a fresh one for an adaptive mesh), the final state and mesh, and the
+    """One run over [0, n_int T_int] with round(spi n_int) steps; the kinetic energy is sampled
+    at the end of every interval (its host time is left out of the wall time).  A static mesh
+    steps with one constant dt; an adaptive one gives interval k its share of the steps and
+    adapts between intervals (recording the flags from the GPU indicator, or replaying recorded
+    ones).  Returns the wall time of the stepping and adaptation (graph replay path; the
+    smallest of `reps` runs, repeated on the same solver for a static mesh and on a fresh one
+    for an adaptive mesh), the final state and mesh, the kinetic-energy history and the
     element-RHS count."""
     import torch
     import perk_inputs as pin
@@ -553,22 +767,31 @@ def _integrate(wl, fam1, mol1, start, T_int, n_int, spi, flags=None, record=Fals
     m0 = wl["mesh"]
     amr = wl.get("amr")
     steps = _steps_per_interval(spi, n_int)
-    s, walls, rec, ok = None, [], [], True
+    T = n_int * T_int
+    s, walls, rec, ok, ke = None, [], [], True, []
     for rep in range(reps):
         if s is None or amr:
             s = None
             mesh = pin.MeshDesc(m0.dim, m0.n_root, m0.lo, m0.hi, np.array(start["leaves"], copy=True))
-            s = PerkSolver(mesh, wl["degree"], fam1, mol1, capacity=amr["capacity"] if amr else None,
-                           equations=wl.get("equations", 0), mu=wl.get("mu", 0.0))
+            s = make_solver(wl, mesh, fam1, mol1)
         s.set_state(start["u"])
         drv = AmrDriver(s, amr["level_min"], amr["level_max"], mol1, amr["refine_above"], amr["coarsen_below"],
                         0) if (amr and record and rep == 0) else None
         s.counters(reset=True)
+        w_static = None if amr else s.node_weights()
+        ke_rep, excluded = [], 0.0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
             for k in range(n_int):
-                s.step(T_int / steps[k], int(steps[k]))
+                dt_k = T_int / steps[k] if amr else T / steps.sum()
+                s.step(dt_k, int(steps[k]))
+                if rep == 0:
+                    torch.cuda.synchronize()
+                    ts = time.perf_counter()
+                    w = s.node_weights() if amr else w_static
+                    ke_rep.append(_kinetic_energy(s.get_state().cpu().numpy(), w, m0.dim))
+                    excluded += time.perf_counter() - ts
                 if amr and k < n_int - 1:
                     if drv is not None:
                         rec.append(drv.adapt_once())
@@ -579,8 +802,11 @@ def _integrate(wl, fam1, mol1, start, T_int, n_int, spi, flags=None, record=Fals
             _log(f"run stopped: {e}")
             ok = False
             break
-        walls.append(time.perf_counter() - t0)
-    out = {"ok": ok, "wall": min(walls) if walls else float("nan"), "steps": int(steps.sum()), "flags": rec}
+        walls.append(time.perf_counter() - t0 - excluded)
+        if rep == 0:
+            ke = ke_rep
+    out = {"ok": ok, "wall": min(walls) if walls else float("nan"), "steps": int(steps.sum()), "flags": rec,
+           "ke": np.array(ke)}
     if ok:
         out["u"] = s.get_state().cpu().numpy()
         out["leaves"] = s.leaves()
@@ -597,15 +823,27 @@ def _stable(run, rho0_max):
     return bool(np.all(np.isfinite(run["u"])) and rho.min() > 0 and rho.max() < 2 * rho0_max)
 
 
-def _density_error(run, ref):
+NORMS = ("L1", "Linf", "KE")
+
+
+def _errors(run, ref):
+    """Errors of a run against the reference: density quadrature L1 (domain mean) and nodal max
+    of the final state, and the largest deviation of the kinetic-energy history (sampled at the
+    end of every interval) relative to the reference's first sample."""
     if ref.get("exact") is not None:
-        r_ref = ref["exact"](run)
+        r_ref, ke_ref = ref["exact"](run)
     else:
         if not np.array_equal(run["leaves"], ref["leaves"]):
             raise RuntimeError("compared runs ended on different meshes")
-        r_ref = ref["u"][:, 0]
+        r_ref, ke_ref = ref["u"][:, 0], ref["ke"]
     d = np.abs(run["u"][:, 0] - r_ref)
-    return float(np.sum(run["w"] * d) / np.sum(run["w"])), float(d.max())
+    ke = np.abs(run["ke"] - ke_ref) / abs(ke_ref[0])
+    return {"L1": float(np.sum(run["w"] * d) / np.sum(run["w"])), "Linf": float(d.max()), "KE": float(ke.max())}
+
+
+def _excess(err, target):
+    """Largest ratio of a run's errors to the target errors over the norms."""
+    return max(err[n] / target[n] for n in NORMS if target[n] > 0)
 
 
 CFL_SCAN = (1.0, 0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2, 0.15, 0.1)
@@ -614,16 +852,23 @@ CFL_SCAN = (1.0, 0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2, 0.15, 0.1)
 def compare_equal_error(wl, t_final=None, tol=0.05, ref_budget=6e8):
     """Wall time of the P-ERK family against (a) the standalone P-ERK_{p;E_max} on every element
     and (b) the order's classical scheme (explicit midpoint / SSPRK33), all on these kernels.
+
     Every scheme runs at the largest CFL of CFL_SCAN that keeps the density finite, positive and
-    below twice its initial maximum over the horizon; the density error (quadrature L1 over the
-    domain, and nodal max) is taken against the exact solution where one exists (isentropic
-    vortex) and otherwise against the standalone P-ERK_{p;E_max} at an eighth of the finest step
-    used, on the same mesh sequence (adaptive meshes replay the P-ERK run's flags).  Of each
-    pair, the step of the less accurate scheme is then shrunk (secant on log error vs log step
-    count, then bisection) until the L1 errors agree within tol, and both are timed again.
-    The P-ERK family is tried with every level -> member map the workload lists; the one with
-    the shortest wall time at its largest stable CFL is compared.  A comparator whose reference
-    run would exceed ref_budget element-stage evaluations is left out (reported as such)."""
+    below twice its initial maximum over the horizon.  Errors (three norms: density L1 over the
+    domain and nodal max of the final state, and the kinetic-energy history sampled ten times
+    over the horizon) are taken against the exact solution where one exists (isentropic vortex)
+    and otherwise against the standalone P-ERK_{p;E_max} at an eighth of the finest step used, on
+    the same mesh sequence (adaptive meshes replay the P-ERK run's flags).
+
+    Equal error: of each pair, the target in every norm is the smaller of the two errors at the
+    largest stable CFLs; each scheme whose error exceeds the target in some norm by more than
+    tol has its step shrunk (secant on the log of its largest error/target ratio against the
+    log of the step count, then bisection) until its largest ratio is within 1 + tol, so that
+    at the end both schemes are at least as accurate as the target in every norm.  Both are then
+    timed again.  The P-ERK family is tried with every level -> member map the workload lists;
+    the one with the shortest wall time at its largest stable CFL is compared.  A comparator
+    whose reference run would exceed ref_budget element-stage evaluations is left out (reported
+    as such)."""
     import perk_inputs as pin
     import torch
     from paper_2403_05144_amd import PerkSolver
@@ -633,8 +878,7 @@ def compare_equal_error(wl, t_final=None, tol=0.05, ref_budget=6e8):
     R = len(fam.E)
     # start state (adaptive workloads: the initial mesh built from the initial condition)
     mesh = pin.MeshDesc(m0.dim, m0.n_root, m0.lo, m0.hi, np.array(m0.leaves, copy=True))
-    s = PerkSolver(mesh, wl["degree"], fam, mol, capacity=amr["capacity"] if amr else None,
-                   equations=wl.get("equations", 0), mu=wl.get("mu", 0.0))
+    s = make_solver(wl, mesh, fam, mol)
     ic_leaf = lambda x: wl["ic"](x.transpose(1, 0, 2)).transpose(1, 0, 2).copy()
     if amr:
         AmrDriver(s, amr["level_min"], amr["level_max"], mol, amr["refine_above"], amr["coarsen_below"],
@@ -650,8 +894,8 @@ def compare_equal_error(wl, t_final=None, tol=0.05, ref_budget=6e8):
         T_int = amr["interval"] * wl["dt"]
         n_int = int(math.ceil((t_final or wl["t_final"]) / T_int))
     else:
-        n_int = 1
-        T_int = t_final or wl["t_final"] or 200 * wl["dt"]
+        n_int = 10                      # kinetic-energy samples; one constant step over the horizon
+        T_int = (t_final or wl["t_final"] or 200 * wl["dt"]) / n_int
     t_end = n_int * T_int
     Lmax = int(max(levels))
     schemes = {
@@ -707,7 +951,10 @@ def compare_equal_error(wl, t_final=None, tol=0.05, ref_budget=6e8):
                 mesh = pin.MeshDesc(m0.dim, m0.n_root, m0.lo, m0.hi, run["leaves"])
                 sx = PerkSolver(mesh, wl["degree"], fam, mol)
                 x = sx.node_coords().cpu().numpy().transpose(1, 0, 2)
-                x_cache[key] = pin.isentropic_vortex(x[0], x[1], t=t_end)[0].copy()
+                w = sx.node_weights()
+                kes = [_kinetic_energy(pin.isentropic_vortex(x[0], x[1], t=(k + 1) * T_int).transpose(1, 0, 2), w, 2)
+                       for k in range(n_int)]
+                x_cache[key] = (pin.isentropic_vortex(x[0], x[1], t=t_end)[0].copy(), np.array(kes))
                 del sx
             return x_cache[key]
         ref = {"exact": exact, "what": "exact solution"}
@@ -718,86 +965,99 @@ def compare_equal_error(wl, t_final=None, tol=0.05, ref_budget=6e8):
         rr = _integrate(wl, f1, m1, start, T_int, n_int, spi_ref, flags=flags)
         if not _stable(rr, rho0_max):
             raise RuntimeError("reference run unstable")
-        ref = {"u": rr["u"], "leaves": rr["leaves"], "what": f"{names['single_level']} with "
+        ref = {"u": rr["u"], "leaves": rr["leaves"], "ke": rr["ke"], "what": f"{names['single_level']} with "
                f"{rr['steps']} steps (1/8 of the finest step used), same mesh sequence"}
     for v in info.values():
-        v["run"]["err"] = _density_error(v["run"], ref)
+        v["run"]["err"] = _errors(v["run"], ref)
     for c in candidates:             # other maps: own mesh sequence under adaptation, no common reference
         if c is not best:
-            c["run"]["err"] = None if amr else _density_error(c["run"], ref)
+            c["run"]["err"] = None if amr else _errors(c["run"], ref)
 
     def run_at(key, spi):
         f1, m1 = schemes[key]
         r = _integrate(wl, f1, m1, start, T_int, n_int, spi, flags=flags)
-        r["err"] = _density_error(r, ref)
+        r["err"] = _errors(r, ref)
         return r
 
     def summary(key, spi, r):
         t2 = _integrate(wl, *schemes[key], start, T_int, n_int, spi, flags=flags, reps=2 if amr else 5)
         return {"scheme": names[key], "steps": r["steps"], "dt_mean": t_end / r["steps"],
-                "err_L1": r["err"][0], "err_Linf": r["err"][1], "wall_s": min(r["wall"], t2["wall"]),
-                "element_rhs": r["element_rhs"]}
+                "err": r["err"], "wall_s": min(r["wall"], t2["wall"]), "element_rhs": r["element_rhs"]}
 
-    pairs = []
-    for other in [k for k in ("single_level", "standard_rk") if k in info]:
-        a = {"p_erk": (info["p_erk"]["spi"], info["p_erk"]["run"]),
-             other: (info[other]["spi"], info[other]["run"])}
-        worse = max(a, key=lambda k: a[k][1]["err"][0])
-        better = other if worse == "p_erk" else "p_erk"
-        target = a[better][1]["err"][0]
-        spi_w, r_w = a[worse]
-        close = lambda e: abs(e - target) <= tol * max(e, target)
-        lo, hi = (spi_w, r_w), None          # too coarse / finer than needed
-        hist = [(spi_w, r_w["err"][0])]
-        it = 0
-        while not close(r_w["err"][0]) and it < 10:
+    def shrink(key, spi, run, target):
+        """Smallest step count found (up from spi) at which every error of `key` is within
+        1 + tol of the target; its (spi, run) and the search history."""
+        g = lambda r: _excess(r["err"], target)
+        lo, hi = (spi, run), None           # not accurate enough / accurate enough
+        hist = [(spi, g(run))]
+        if g(run) <= 1 + tol:
+            return spi, run, hist
+        for _ in range(12):
             if hi is None:
                 if len(hist) >= 2 and hist[-1][1] != hist[-2][1]:
                     (s1, e1), (s2, e2) = hist[-2], hist[-1]
                     slope = min(-0.5, (math.log(e2) - math.log(e1)) / (math.log(s2) - math.log(s1)))
                 else:
                     slope = -float(fam.order)
-                spi_new = lo[0] * (target / lo[1]["err"][0]) ** (1.0 / slope)
+                spi_new = lo[0] * (1.0 / g(lo[1])) ** (1.0 / slope)
                 spi_new = max(lo[0] + 1.0 / n_int, float(math.ceil(spi_new * n_int - 1e-9)) / n_int)
             else:
                 spi_new = float(round(0.5 * (lo[0] + hi[0]) * n_int)) / n_int
                 if spi_new <= lo[0] or spi_new >= hi[0]:
                     break
-            r_new = run_at(worse, spi_new)
-            hist.append((spi_new, r_new["err"][0]))
-            spi_w, r_w = spi_new, r_new
-            if r_new["err"][0] > target:
+            r_new = run_at(key, spi_new)
+            hist.append((spi_new, g(r_new)))
+            if g(r_new) > 1 + tol:
                 lo = (spi_new, r_new)
             else:
                 hi = (spi_new, r_new)
-            it += 1
-        if not close(r_w["err"][0]) and hi is not None:
-            spi_w, r_w = hi                   # nearest step count at which it is at least as accurate
-        a[worse] = (spi_w, r_w)
+                if g(r_new) >= 1 - tol:
+                    break
+        if hi is None:
+            raise RuntimeError(f"equal-error: {key} did not reach the target errors")
+        return hi[0], hi[1], hist
+
+    pairs = []
+    for other in [k for k in ("single_level", "standard_rk") if k in info]:
+        e_p, e_c = info["p_erk"]["run"]["err"], info[other]["run"]["err"]
+        target = {n: min(e_p[n], e_c[n]) for n in NORMS}
+        res = {}
+        for key in ("p_erk", other):
+            spi0, run0 = info[key]["spi"], info[key]["run"]
+            res[key] = shrink(key, spi0, run0, target)
+            _log(f"equal-error: {key} vs {other}: {res[key][1]['steps']} steps (from {run0['steps']}), largest "
+                 f"error/target {_excess(res[key][1]['err'], target):.3f}")
         t_c = _integrate(wl, *schemes[other], start, T_int, n_int, info[other]["spi"], flags=flags,
                          reps=2 if amr else 5)
         wall_c_max = min(info[other]["run"]["wall"], t_c["wall"])
         at_max = {"p_erk_steps": best["run"]["steps"], "comparator_steps": info[other]["run"]["steps"],
                   "p_erk_wall_s": best["wall"], "comparator_wall_s": wall_c_max,
-                  "p_erk_err_L1": best["run"]["err"][0], "comparator_err_L1": info[other]["run"]["err"][0],
+                  "p_erk_err": e_p, "comparator_err": e_c,
                   "wall_ratio_comparator_over_p_erk": wall_c_max / best["wall"]}
-        sp, sc = summary("p_erk", *a["p_erk"]), summary(other, *a[other])
-        rel = abs(sc["err_L1"] - sp["err_L1"]) / max(sp["err_L1"], sc["err_L1"])
-        pairs.append({"at_cfl_max": at_max, "comparator": sc, "p_erk": sp, "comparator_cfl_max": info[other]["cfl_max"],
-                      "shrunk": worse, "err_L1_rel_diff": rel, "equal_error": bool(rel <= tol),
+        sp, sc = summary("p_erk", res["p_erk"][0], res["p_erk"][1]), summary(other, res[other][0], res[other][1])
+        pairs.append({"at_cfl_max": at_max, "target_err": target, "comparator": sc, "p_erk": sp,
+                      "comparator_cfl_max": info[other]["cfl_max"],
+                      "shrunk": [k for k in ("p_erk", other) if res[k][1] is not info[k]["run"]],
+                      "search": {k: [(float(a), float(b)) for a, b in res[k][2]] for k in res},
+                      "largest_error_over_target": {"p_erk": _excess(sp["err"], target),
+                                                    "comparator": _excess(sc["err"], target)},
                       "wall_ratio_comparator_over_p_erk": sc["wall_s"] / sp["wall_s"],
                       "element_rhs_ratio": sc["element_rhs"] / sp["element_rhs"]})
-        _log(f"equal-error: {other}: wall ratio {sc['wall_s'] / sp['wall_s']:.3f} at L1 errors "
-             f"{sp['err_L1']:.3e} / {sc['err_L1']:.3e}")
+        _log(f"equal-error: {other}: wall ratio {sc['wall_s'] / sp['wall_s']:.3f} with every error within "
+             f"{1 + tol:.2f} of the target {target}")
     cand_out = [{"map": c["label"], "E_of_level": [int(fam.E[r]) for r in c["mol"]], "cfl_max": c["cfl_max"],
                  "steps": c["run"]["steps"], "wall_s_at_cfl_max": c["wall"], "element_rhs": c["run"]["element_rhs"],
-                 "err_L1": None if c["run"]["err"] is None else c["run"]["err"][0], "chosen": c is best}
+                 "err": c["run"]["err"], "chosen": c is best}
                 for c in candidates]
     return {"workload": wl["name"], "t_final": t_end, "p_erk_cfl_max": info["p_erk"]["cfl_max"],
             "p_erk_maps": cand_out,
             "cfl": "fraction of the scheme's own largest linearly stable step (optimised stability polynomial, "
                    "element sizes of every level); largest value of the scan without blow-up over the horizon",
-            "error": f"density, quadrature L1 (domain mean) and nodal max, against the {ref['what']}",
+            "error": f"density L1 (domain mean) and nodal max of the final state, and the largest deviation of the "
+                     f"kinetic-energy history ({n_int} samples) relative to its initial value, against the "
+                     f"{ref['what']}",
+            "equal_error": f"target per norm = the smaller error of the pair at the largest stable CFLs; each "
+                           f"scheme's step shrunk until all its errors are within {1 + tol:.2f} of the target",
             "adaptation": "flags of the P-ERK run replayed in every run" if amr else "static mesh",
             "pairs": pairs, "not_compared": skipped}
 
@@ -936,11 +1196,7 @@ def measured_traffic(workload, es_per_launch):
         for line in f:
             if line.startswith("TRAFFIC "):
                 rec = json.loads(line[len("TRAFFIC "):])
-    h = hashlib.sha256()
-    for name in STAGE_KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2403_05144_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    sha = h.hexdigest()
+    sha = stage_kernel_digest()
     if rec is None or rec.get("kernel_sha256") != sha:
         return None, f"{os.path.relpath(path, ROOT)} was taken on another kernel source"
     per_es = rec["fetch_bytes_per_element_stage"] + rec["write_bytes_per_element_stage"]
@@ -968,8 +1224,7 @@ def run(args):
         m0 = pin.MeshDesc(mesh.dim, mesh.n_root, mesh.lo, mesh.hi, np.array(leaves_init, copy=True))
         # the library applies the workload's level rule (at the finest level of the current mesh)
         rule = wl.get("rule", wl["mol"])
-        s = PerkSolver(m0, deg, fam, rule, capacity=amr["capacity"] if amr else None,
-                       equations=wl.get("equations", 0), mu=wl.get("mu", 0.0))
+        s = make_solver(wl, m0, fam, rule)
         drv = None
         if amr:
             drv = AmrDriver(s, amr["level_min"], amr["level_max"], rule, amr["refine_above"],
@@ -1141,7 +1396,7 @@ def run(args):
     }
     if not args.no_equal_error:
         _log("P-ERK against single-level schemes at equal error")
-        line["p_erk_vs_single_level"] = compare_equal_error(wl)
+        line["p_erk_vs_single_level"] = compare_equal_error(wl, t_final=wl.get("eq_t_final"))
     if not args.no_cpu_baseline:
         _log("timing the oracle on the host (cpu_baseline)")
         line["cpu_baseline"] = cpu_baseline(wl, u0, leaves0, budget_s=args.cpu_seconds)
@@ -1161,6 +1416,7 @@ def main():
                     help="skip the comparison with single-level schemes at equal error")
     ap.add_argument("--sweep-max", type=int, default=0,
                     help="uniform_sweep: largest element count to run (0: all sizes)")
+    ap.add_argument("--arnoldi-steps", type=int, default=200, help="spectrum: Arnoldi steps at the real mesh")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device once (calibration of HBM counters)")
     args = ap.parse_args()
@@ -1182,6 +1438,10 @@ def main():
         line = run_batch(args)
     elif args.workload == "adjoint_kh":
         line = run_adjoint(args)
+    elif args.workload == "spectrum":
+        line = run_spectrum(args)
+    elif args.workload == "patterns":
+        line = run_patterns(args)
     elif args.workload == "uniform_sweep":
         line = run_sweep(args)
     else:

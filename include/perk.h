@@ -289,11 +289,23 @@ pe_status pe_max_dt(pe_ctx* ctx, double cfl, double* dt_out, double* beta_of_lev
  * threads) race and must be ordered by the caller. */
 pe_status pe_max_dt_noalloc(pe_ctx* ctx, double cfl, double* dt_dev, double* beta_dev, void* stream);
 
-/* Refinement indicator per leaf (the adaptive Kelvin-Helmholtz workload's density-gradient
- * indicator): eta_e = h_e max_nodes |grad rho| / max_nodes rho, h_e the element size in x,
- * grad rho from the DGSEM derivative matrix.  Written to eta_leaf_host [n_elements] in leaf
- * order; synchronises `stream`.  (The paper's indicators are cited in Sec. 7; the mesh change
- * and re-flagging it triggers is Sec. 6.2.) */
+/* Which refinement indicator pe_amr_indicator and pe_amr_cycle compute (the paper's indicators
+ * are cited in Sec. 7):
+ *   PE_INDICATOR_DENSITY_GRADIENT (default; the adaptive Kelvin-Helmholtz workload):
+ *     eta_e = h_e max_nodes |grad rho| / max_nodes rho; variable and f_wave are ignored;
+ *   PE_INDICATOR_LOHNER (Loehner's indicator, the shear-layer workload of Sec. 7.1.1 on v_x):
+ *     the largest |q_{i+1} - 2 q_i + q_{i-1}| / (|q_{i+1} - q_i| + |q_i - q_{i-1}|
+ *     + f_wave (|q_{i+1}| + 2 |q_i| + |q_{i-1}|)) over the interior nodes of every coordinate line
+ *     of the element's LGL nodes (three consecutive nodal values as they are; 0 where the
+ *     denominator vanishes), q the primitive variable `variable` (0 rho, 1..dim the velocity
+ *     components, dim+1 the pressure).
+ * PE_EINVAL for another kind, a variable outside [0, dim+1] or f_wave < 0. */
+typedef enum { PE_INDICATOR_DENSITY_GRADIENT = 0, PE_INDICATOR_LOHNER = 1 } pe_indicator;
+pe_status pe_set_amr_indicator(pe_ctx* ctx, int kind, int variable, double f_wave);
+
+/* Refinement indicator per leaf (the one pe_set_amr_indicator selected; the density gradient by
+ * default).  Written to eta_leaf_host [n_elements] in leaf order; synchronises `stream`.  (The
+ * mesh change and re-flagging it triggers is Sec. 6.2.) */
 pe_status pe_amr_indicator(pe_ctx* ctx, double* eta_leaf_host, void* stream);
 
 /* Adapt the forest (Sec. 6.2: the mesh change after which the partition is rebuilt).
@@ -323,6 +335,32 @@ pe_status pe_amr_cycle(pe_ctx* ctx, double refine_above, double coarsen_below, i
 
 /* Current leaf list (host) [n][4] (level, i, j, k); leaves may be NULL to query n. */
 pe_status pe_get_leaves(const pe_ctx* ctx, int32_t* leaves, int64_t* n);
+
+/* ---------------------------------------------------------------- spectrum estimation
+ * Building blocks of the Arnoldi iteration on the Jacobian J = F'(u) of the right-hand side at
+ * the real mesh (Sec. 4.1, steps 3-4: outer eigenvalues near scaled hull points of a reduced
+ * spectrum).  Vectors are state arrays in slot layout (n = n_state_doubles of pe_query_sizes);
+ * the iteration itself (basis, Hessenberg matrix, Ritz values) is driven by the caller.  The
+ * product with J^T is pe_rhs_vjp (Euler; J^T has the eigenvalues of J). */
+
+/* Directional derivative F'(u) v by central differences,
+ * (F(u + h v) - F(u - h v)) / (2 h) with h = eps |u|_2 / |v|_2 (truncation O(h^2), any equations).
+ * u, v, out: device state arrays (out must not alias u or v); uses the stage buffers of the
+ * bound workspace as temporaries (they hold nothing between steps).  Synchronises `stream`
+ * once.  PE_ESTATE before pe_partition; PE_EINVAL for eps <= 0, a zero v or null pointers. */
+pe_status pe_rhs_jvp_fd(pe_ctx* ctx, const double* u, const double* v, double eps, double* out, void* stream);
+
+/* Device doubles of scratch pe_orthogonalize needs for k basis vectors. */
+pe_status pe_orthogonalize_scratch(int k, int64_t* doubles);
+
+/* One orthogonalisation of the Arnoldi iteration: w (device, n doubles) is orthogonalised
+ * against the k columns of V (device; column j at V + j ldv, assumed orthonormal) by two passes
+ * of classical Gram-Schmidt.  h_host [k + 1] receives the projections summed over both passes
+ * and, in h_host[k], the norm of what is left, by which w is then divided (unless it is 0).
+ * scratch: device, pe_orthogonalize_scratch(k) doubles.  Synchronises `stream`.  PE_EINVAL for
+ * k < 0, n <= 0, ldv < n or null pointers. */
+pe_status pe_orthogonalize(pe_ctx* ctx, const double* V, int k, int64_t ldv, double* w, int64_t n, double* scratch,
+                           double* h_host, void* stream);
 
 /* Self-check of the arithmetic routines the kernels use instead of library calls: the node
  * logarithms of the logarithmic means of the entropy-conserving flux (Sec. 6.1 volume flux),

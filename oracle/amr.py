@@ -7,7 +7,9 @@ re-flags the elements after every mesh change (Sec. 6.2, Sec. 7); it does not sp
 indicator of the adaptive Kelvin-Helmholtz workload, the balance rules or the projection.  The
 readings implemented here:
   * indicator eta_e = h_e max_nodes |grad rho| / max_nodes rho, grad rho from the LGL derivative
-    matrix, h_e the element size in x;
+    matrix, h_e the element size in x; or Loehner's indicator on a primitive variable (the
+    shear-layer workload, Sec. 7.1.1), the largest normalised second difference of three
+    consecutive nodal values along the element's coordinate lines;
   * flags: +1 if eta > refine threshold, -1 if eta < coarsen threshold, else 0;
   * adaptation: flagged leaves below level_max are refined once; then every pair of face
     neighbours whose target levels differ by two or more has the coarser one refined, until no
@@ -39,6 +41,47 @@ def indicator(o: Oracle, u):
             deriv = np.apply_along_axis(lambda line: D @ line, axis, r)
             g2 = g2 + (2.0 / h[e, d] * deriv) ** 2
         eta[e] = h[e, 0] * np.sqrt(g2).max() / r.max()
+    return eta
+
+
+def primitive_variable(u, var, dim, gamma=1.4):
+    """Node values of one primitive variable of a state [e, var, node]: 0 rho, 1..dim the velocity
+    components, dim+1 the pressure."""
+    rho = u[:, 0]
+    if var == 0:
+        return rho
+    if 1 <= var <= dim:
+        return u[:, var] / rho
+    ke = 0.5 * sum(u[:, 1 + k] ** 2 for k in range(dim)) / rho
+    return (gamma - 1.0) * (u[:, dim + 1] - ke)
+
+
+def lohner_estimate(um, u0, up, f_wave):
+    """Loehner's normalised second difference of three consecutive values (Sec. 7.1.1 cites
+    Loehner 1987 and the FLASH form): |up - 2 u0 + um| over |up - u0| + |u0 - um|
+    + f_wave (|up| + 2 |u0| + |um|); 0 where the denominator vanishes."""
+    num = abs(up - 2.0 * u0 + um)
+    den = abs(up - u0) + abs(u0 - um) + f_wave * (abs(up) + 2.0 * abs(u0) + abs(um))
+    return num / den if den > 0.0 else 0.0
+
+
+def lohner_indicator(o: Oracle, u, var=1, f_wave=0.2, gamma=1.4):
+    """Element indicator: the largest estimate over every interior node of every coordinate line
+    of the element's LGL nodes (three consecutive nodal values, as they are; the reading of the
+    indicator's adaptation to LGL elements), for the primitive variable `var`."""
+    N, dim = o.N, o.dim
+    q = primitive_variable(np.asarray(u, float), var, dim, gamma)
+    eta = np.zeros(o.n_elements)
+    for e in range(o.n_elements):
+        v = q[e].reshape((N,) * dim)                         # [(k,) j, i], i fastest
+        best = 0.0
+        for d in range(dim):
+            axis = dim - 1 - d
+            lines = np.moveaxis(v, axis, -1).reshape(-1, N)
+            for line in lines:
+                for i in range(1, N - 1):
+                    best = max(best, lohner_estimate(line[i - 1], line[i], line[i + 1], f_wave))
+        eta[e] = best
     return eta
 
 

@@ -16,6 +16,7 @@ Paper passages
 """
 from __future__ import annotations
 
+import ctypes
 import json
 import math
 from dataclasses import dataclass
@@ -30,20 +31,24 @@ class Family:
     E: list
     c: np.ndarray
     b: np.ndarray
-    a_sub: np.ndarray             # [R, S], a_{i,i-1}
+    a_sub: np.ndarray             # [R, S], a_{i,i-1} (or a_{i,j} of row i's coupling column j)
     dt_opt: list = None           # optimal step per member for the spectrum it was built on
     h_ref: float = None           # element size that spectrum belongs to
+    coupling: np.ndarray = None   # [R, S] coupling column per row (-1 none); None: classic pattern
 
     def to_dict(self):
         return {"order": self.order, "S": self.S, "E": [int(e) for e in self.E],
                 "c": self.c.tolist(), "b": self.b.tolist(), "a_sub": self.a_sub.tolist(),
                 "dt_opt": None if self.dt_opt is None else [float(x) for x in self.dt_opt],
-                "h_ref": self.h_ref}
+                "h_ref": self.h_ref,
+                "coupling": None if self.coupling is None else np.asarray(self.coupling).tolist()}
 
     @staticmethod
     def from_dict(d):
+        cp = d.get("coupling")
         return Family(d["order"], d["S"], list(d["E"]), np.asarray(d["c"], float), np.asarray(d["b"], float),
-                      np.asarray(d["a_sub"], float), d.get("dt_opt"), d.get("h_ref"))
+                      np.asarray(d["a_sub"], float), d.get("dt_opt"), d.get("h_ref"),
+                      None if cp is None else np.asarray(cp, np.int32))
 
     def save(self, path):
         with open(path, "w") as f:
@@ -207,6 +212,66 @@ def perk3_row(alpha, E, S, n_starts=200):
     raise RuntimeError(f"no positive third-order tableau for E={E}")
 
 
+def coupled_matrix(c, coupling_row, a_row):
+    """Full Butcher matrix of one member whose row i couples K_1 and K_j, j = coupling_row[i]."""
+    S = len(c)
+    A = np.zeros((S, S))
+    for i in range(1, S):
+        j = int(coupling_row[i])
+        A[i, 0] = c[i] - (a_row[i] if j >= 1 else 0.0)
+        if j >= 1:
+            A[i, j] = a_row[i]
+    return A
+
+
+def rechain(fam, r, chain):
+    """Member r of a second-order family moved onto another chain of evaluated stages (0-based,
+    from stage 0 to S-1; Sec. 3.2.4), keeping its stability polynomial.  The couplings are found
+    one at a time from the last row backwards: each new coefficient enters the polynomial
+    coefficient it fixes linearly, so two evaluations of the tableau's polynomial (coefficient 0
+    and 1) give it.  Returns (coupling row, coefficient row)."""
+    if fam.order != 2:
+        raise ValueError("stage patterns are built for second-order families")
+    S = fam.S
+    c, b = np.asarray(fam.c), np.asarray(fam.b)
+    cp0 = None if fam.coupling is None else fam.coupling[r]
+    A0 = member_matrix(c, fam.a_sub[r]) if cp0 is None else coupled_matrix(c, cp0, fam.a_sub[r])
+    target = poly_of(A0, b)
+    chain = [int(x) for x in chain]
+    E = len(chain)
+    if chain[0] != 0 or chain[-1] != S - 1 or any(q <= p for p, q in zip(chain, chain[1:])):
+        raise ValueError("chain must rise strictly from stage 0 to stage S-1")
+    coupling = -np.ones(S, dtype=np.int32)
+    a = np.zeros(S)
+    for m in range(E - 1, 1, -1):
+        row, col = chain[m], chain[m - 1]
+        coupling[row] = col
+        k = E + 2 - m                       # polynomial degree this coefficient fixes
+        vals = []
+        for trial in (0.0, 1.0):
+            a[row] = trial
+            vals.append(poly_of(coupled_matrix(c, coupling, a), b)[k])
+        a[row] = (target[k] - vals[0]) / (vals[1] - vals[0])
+    if np.max(np.abs(poly_of(coupled_matrix(c, coupling, a), b) - target)) > 1e-12 * np.max(np.abs(target)):
+        raise RuntimeError("rechain: polynomial not reproduced")
+    return coupling, a
+
+
+def with_chains(fam, chains):
+    """The family with member r moved onto chains[r] (None: keep its stages)."""
+    R, S = len(fam.E), fam.S
+    cp = np.array([[i - 1 if i >= S - fam.E[r] + 2 else -1 for i in range(S)] for r in range(R)], np.int32) \
+        if fam.coupling is None else np.array(fam.coupling, np.int32)
+    a = np.array(fam.a_sub, float)
+    for r, ch in enumerate(chains):
+        if ch is None:
+            continue
+        if len(ch) != fam.E[r]:
+            raise ValueError(f"member {r}: chain of {len(ch)} stages for E = {fam.E[r]}")
+        cp[r], a[r] = rechain(fam, r, ch)
+    return Family(fam.order, S, list(fam.E), np.asarray(fam.c), np.asarray(fam.b), a, fam.dt_opt, fam.h_ref, cp)
+
+
 def hull_points(lam):
     """Boundary of the spectrum in the closed upper half plane (Sec. 4.1, step 2): convex hull
     of the eigenvalues with non-negative imaginary part plus the origin, with extra points on
@@ -276,6 +341,78 @@ def fd_spectrum(solver, u_leaf, eps=1e-7):
     lam = lam[lam.imag >= 0]                  # spectrum is symmetric about the real axis
     lam.real = np.minimum(lam.real, 0.0)      # round-off positive real parts
     return lam
+
+
+def arnoldi(solver, u_slot, m, op="fd", eps=1e-7, seed=0):
+    """m steps of the Arnoldi iteration on J = F'(u) at the solver's mesh (Sec. 4.1 step 4):
+    products with J by central differences (op "fd", any equations) or exact products with J^T
+    (op "vjp", Euler; same eigenvalues), orthogonalisation by two passes of classical
+    Gram-Schmidt, all in libperk kernels on device vectors.  Returns the (j+1) x j Hessenberg
+    matrix of the j <= m steps taken (fewer if the Krylov space closes)."""
+    import torch
+    from . import _lib as L
+    n = u_slot.numel()
+    V = torch.zeros((m + 1, n), dtype=torch.float64, device=u_slot.device)
+    g = torch.Generator(device="cpu").manual_seed(int(seed))
+    v0 = torch.randn(n, generator=g, dtype=torch.float64)
+    # element slots only (the reserved capacity's padding stays zero)
+    v0 = v0.view(solver.nv, -1, solver.Nd)
+    v0[:, solver.n_elements:, :] = 0.0
+    V[0].copy_(v0.reshape(-1))
+    nd = ctypes.c_int64()
+    if solver.lib.pe_orthogonalize_scratch(m + 1, ctypes.byref(nd)) != 0:
+        raise RuntimeError("pe_orthogonalize_scratch failed")
+    scratch = torch.empty(nd.value, dtype=torch.float64, device=u_slot.device)
+    solver.orthogonalize(V, 0, V[0], scratch)
+    H = np.zeros((m + 1, m))
+    steps = 0
+    for j in range(m):
+        if op == "fd":
+            solver.jvp_fd_slot(u_slot, V[j], V[j + 1], eps)
+        else:
+            solver.vjp_into(u_slot, V[j], V[j + 1])
+        h = solver.orthogonalize(V, j + 1, V[j + 1], scratch)
+        H[: j + 2, j] = h
+        steps = j + 1
+        if h[j + 1] <= 1e-13 * max(1.0, np.abs(H[: j + 2, : j + 1]).max()):
+            break
+    torch.cuda.synchronize()
+    return H[: steps + 1, :steps]
+
+
+def harmonic_ritz(H, sigma):
+    """Harmonic Ritz values of an Arnoldi factorisation with respect to the target sigma: the
+    eigenvalue estimates from the Krylov space closest to sigma (the role the shifted Arnoldi runs
+    around hull points play in Sec. 4.1)."""
+    m = H.shape[1]
+    Hm = H[:m, :m].astype(complex)
+    A = Hm - sigma * np.eye(m)
+    beta = H[m, m - 1] if H.shape[0] > m else 0.0
+    em = np.zeros(m)
+    em[-1] = 1.0
+    f = np.linalg.solve(A.conj().T, em)
+    return sigma + np.linalg.eigvals(A + (abs(beta) ** 2) * np.outer(f, em))
+
+
+def full_mesh_spectrum(solver, u_slot, reduced_lam, h_reduced, h, m=240, per_shift=None, op="fd", eps=1e-7):
+    """Outer eigenvalues of the real mesh's Jacobian (Sec. 4.1 steps 2-4): the hull points of the
+    reduced spectrum scaled by h_reduced / h serve as targets; from one Arnoldi factorisation of m
+    steps, the Ritz values and, per target, the harmonic Ritz values nearest to it (per_shift of
+    them, 1000 / K by default) form the estimate."""
+    H = arnoldi(solver, u_slot, m, op=op, eps=eps)
+    shifts = hull_points(np.asarray(reduced_lam)) * (h_reduced / h)
+    K = len(shifts)
+    per = per_shift or max(1, 1000 // max(1, K))
+    ritz = np.linalg.eigvals(H[: H.shape[1], : H.shape[1]])
+    est = [ritz]
+    for sg in shifts:
+        th = harmonic_ritz(H, sg)
+        est.append(th[np.argsort(np.abs(th - sg))[:per]])
+    lam = np.concatenate(est)
+    lam = lam[np.isfinite(lam)]
+    lam = lam[lam.imag >= 0]
+    lam.real = np.minimum(lam.real, 0.0)
+    return lam, H
 
 
 def family_from_solver_spectrum(solver, u_leaf, order, E_list, h_ref):

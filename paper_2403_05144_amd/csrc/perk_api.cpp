@@ -58,6 +58,9 @@ struct pe_ctx {
   int rule = PE_LEVEL_RULE_PAPER;
   std::vector<double> rule_dt_opt;      // [R] optimal steps at a common element size (required-step rule)
   double rule_margin = 1.0;
+  // refinement indicator of pe_amr_indicator / pe_amr_cycle
+  int ind_kind = PE_INDICATOR_DENSITY_GRADIENT, ind_var = 1;
+  double ind_fwave = 0.2;
   // binding
   bool bound = false;
   double* U = nullptr;
@@ -1590,14 +1593,34 @@ pe_status pe_get_leaves(const pe_ctx* ctx, int32_t* leaves, int64_t* n) {
   return PE_OK;
 }
 
+pe_status pe_set_amr_indicator(pe_ctx* ctx, int kind, int variable, double f_wave) {
+  if (!ctx) return PE_EINVAL;
+  if (kind == PE_INDICATOR_DENSITY_GRADIENT) {
+    ctx->ind_kind = kind;
+    return PE_OK;
+  }
+  if (kind != PE_INDICATOR_LOHNER) return fail(ctx, PE_EINVAL, "indicator %d unknown", kind);
+  if (variable < 0 || variable > ctx->dim + 1)
+    return fail(ctx, PE_EINVAL, "indicator: variable %d outside [0, %d]", variable, ctx->dim + 1);
+  if (!(f_wave >= 0.0) || !std::isfinite(f_wave)) return fail(ctx, PE_EINVAL, "indicator: f_wave must be >= 0");
+  ctx->ind_kind = kind;
+  ctx->ind_var = variable;
+  ctx->ind_fwave = f_wave;
+  return PE_OK;
+}
+
 pe_status pe_amr_indicator(pe_ctx* ctx, double* eta_leaf, void* stream) {
   if (!ctx) return PE_EINVAL;
   if (!ctx->partitioned || !ctx->state_valid) return fail(ctx, PE_ESTATE, "indicator needs a partition and a state");
   if (!eta_leaf) return fail(ctx, PE_EINVAL, "indicator: null");
   hipStream_t s = (hipStream_t)stream;
   Mesh m = device_mesh(ctx);
-  HIPCHK(launch_indicator(ctx->dim, ctx->N, ctx->n_e, (int)cap_of(ctx), ctx->d_slot_of_leaf, ctx->d_lev_leaf, ctx->U,
-                          ctx->ops, m, ctx->d_eta, s));
+  if (ctx->ind_kind == PE_INDICATOR_LOHNER)
+    HIPCHK(launch_indicator_lohner(ctx->dim, ctx->N, ctx->n_e, (int)cap_of(ctx), ctx->d_slot_of_leaf, ctx->U,
+                                   ctx->ind_var, ctx->ind_fwave, ctx->ph.gamma, ctx->d_eta, s));
+  else
+    HIPCHK(launch_indicator(ctx->dim, ctx->N, ctx->n_e, (int)cap_of(ctx), ctx->d_slot_of_leaf, ctx->d_lev_leaf,
+                            ctx->U, ctx->ops, m, ctx->d_eta, s));
   const size_t bytes = (size_t)ctx->n_e * 8;
   pe_status st = stage_reserve(ctx, bytes);
   if (st != PE_OK) return st;
@@ -1864,6 +1887,71 @@ pe_status pe_amr_cycle(pe_ctx* ctx, double refine_above, double coarsen_below, i
     if (st != PE_OK) return st;
   }
   if (n_leaves) *n_leaves = ctx->n_e;
+  return PE_OK;
+}
+
+pe_status pe_orthogonalize_scratch(int k, int64_t* doubles) {
+  if (k < 0 || k > (1 << 20) || !doubles) return PE_EINVAL;
+  *doubles = multi_dot_scratch_doubles(k > 0 ? k : 1) + (k > 0 ? k : 1);
+  return PE_OK;
+}
+
+pe_status pe_orthogonalize(pe_ctx* ctx, const double* V, int k, int64_t ldv, double* w, int64_t n, double* scratch,
+                           double* h_host, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (k < 0 || n <= 0 || !w || !scratch || !h_host || (k > 0 && (!V || ldv < n)))
+    return fail(ctx, PE_EINVAL, "orthogonalize: bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const int kk = k > 0 ? k : 1;
+  double* hd = scratch + multi_dot_scratch_doubles(kk);    // [k] projections of one pass
+  std::vector<double> h(k, 0.0), hp(kk);
+  for (int pass = 0; pass < 2 && k > 0; ++pass) {
+    HIPCHK(launch_multi_dot(k, V, ldv, w, n, scratch, hd, s));
+    HIPCHK(launch_multi_axpy(k, V, ldv, hd, w, n, s));
+    HIPCHK(hipMemcpyAsync(hp.data(), hd, (size_t)k * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int j = 0; j < k; ++j) h[j] += hp[j];
+  }
+  double nn = 0.0;
+  HIPCHK(launch_multi_dot(1, w, n, w, n, scratch, hd, s));
+  HIPCHK(hipMemcpyAsync(&nn, hd, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double norm = std::sqrt(nn);
+  for (int j = 0; j < k; ++j) h_host[j] = h[j];
+  h_host[k] = norm;
+  if (norm > 0.0) HIPCHK(launch_scale(w, w, 1.0 / norm, n, s));
+  return PE_OK;
+}
+
+pe_status pe_rhs_jvp_fd(pe_ctx* ctx, const double* u, const double* v, double eps, double* out, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->partitioned) return fail(ctx, PE_ESTATE, "rhs_jvp_fd before partition");
+  if (!u || !v || !out) return fail(ctx, PE_EINVAL, "rhs_jvp_fd: null");
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(ctx, PE_EINVAL, "rhs_jvp_fd: eps must be positive");
+  const int64_t sd = state_doubles(ctx);
+  if (sd < multi_dot_scratch_doubles(1) + 2) return fail(ctx, PE_EINVAL, "rhs_jvp_fd: mesh too small");
+  hipStream_t s = (hipStream_t)stream;
+  // step h = eps |u|_2 / |v|_2 (relative perturbation eps), norms reduced on the device
+  double nrm[2];
+  HIPCHK(launch_multi_dot(1, u, sd, u, sd, ctx->Ya, ctx->Ya + sd - 2, s));
+  HIPCHK(launch_multi_dot(1, v, sd, v, sd, ctx->Ya, ctx->Ya + sd - 1, s));
+  HIPCHK(hipMemcpyAsync(nrm, ctx->Ya + sd - 2, 16, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (!(nrm[1] > 0.0)) return fail(ctx, PE_EINVAL, "rhs_jvp_fd: zero direction");
+  const double h = eps * std::sqrt(nrm[0] > 0.0 ? nrm[0] : 1.0) / std::sqrt(nrm[1]);
+  HIPCHK(launch_axpy_to(ctx->Ya, u, h, v, sd, s));
+  HIPCHK(launch_axpy_to(ctx->Tmp, u, -h, v, sd, s));
+  // the right-hand side writes the element slots only: the padding slots of the reserved
+  // capacity must read zero in the difference
+  if (cap_of(ctx) > ctx->n_e) {
+    HIPCHK(hipMemsetAsync(ctx->Yb, 0, (size_t)sd * 8, s));
+    HIPCHK(hipMemsetAsync(ctx->ACC, 0, (size_t)sd * 8, s));
+  }
+  pe_status st = pe_rhs(ctx, ctx->Ya, ctx->Yb, stream);
+  if (st != PE_OK) return st;
+  st = pe_rhs(ctx, ctx->Tmp, ctx->ACC, stream);
+  if (st != PE_OK) return st;
+  HIPCHK(launch_diff_scale(out, ctx->Yb, ctx->ACC, 0.5 / h, sd, s));
   return PE_OK;
 }
 

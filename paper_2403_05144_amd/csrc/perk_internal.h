@@ -191,6 +191,9 @@ hipError_t launch_slot_to_leaf(int n, int ld, int nv, int nd, const int32_t* slo
                                double* dst, hipStream_t s);
 
 // AMR indicator per leaf: eta = h max_nodes |grad rho| / max_nodes rho (h = element size in x).
+// Loehner's indicator per leaf on primitive variable var (0 rho, 1..dim velocity, dim+1 pressure)
+hipError_t launch_indicator_lohner(int dim, int N, int n, int ld, const int32_t* slot_of_leaf, const double* U,
+                                   int var, double f_wave, double gamma, double* eta, hipStream_t s);
 hipError_t launch_indicator(int dim, int N, int n, int ld, const int32_t* slot_of_leaf, const int32_t* lev_leaf,
                             const double* U, const Ops& op, const Mesh& m, double* eta_leaf, hipStream_t s);
 
@@ -206,6 +209,16 @@ hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s)
 // beta[l] = 1 / w_l or 0 (beta may be null).  n in [1, kNoAllocMaxElements].
 hipError_t launch_max_dt_noalloc(int dim, int N, int n, const double* U, const Physics& ph, const Mesh& m,
                                  double cfl, double* dt, double* beta, hipStream_t s);
+// Spectrum estimation (perk_spectrum.hip): out[j] = V_j . w for the k columns of V (stride ldv),
+// through a scratch of multi_dot_scratch_doubles(k) doubles; w -= sum_j h_j V_j (h on the
+// device); y = x + s v; y = (a - b) s.
+int64_t multi_dot_scratch_doubles(int k);
+hipError_t launch_multi_dot(int k, const double* V, int64_t ldv, const double* w, int64_t n, double* scratch,
+                            double* out, hipStream_t s);
+hipError_t launch_multi_axpy(int k, const double* V, int64_t ldv, const double* h, double* w, int64_t n,
+                             hipStream_t s);
+hipError_t launch_axpy_to(double* y, const double* x, double sc, const double* v, int64_t n, hipStream_t s);
+hipError_t launch_diff_scale(double* y, const double* a, const double* b, double sc, int64_t n, hipStream_t s);
 // out[0, n) = ln x, out[n, 2n) = sqrt x, out[2n, 3n) = 1/x with the kernels' own routines
 hipError_t launch_device_math(int64_t n, const double* x, double* out, hipStream_t s);
 // Add the per-slot evaluation counts into per-member totals (member from the partition

@@ -154,6 +154,53 @@ __global__ void k_indicator(int n, int ld, const int32_t* slot_of_leaf, const in
   eta[leaf] = h * gmax / rmax;
 }
 
+// Loehner's indicator on a primitive variable (0 rho, 1..DIM velocity, DIM+1 pressure): the
+// largest |q_{i+1} - 2 q_i + q_{i-1}| / (|q_{i+1} - q_i| + |q_i - q_{i-1}| + f_wave (|q_{i+1}| +
+// 2 |q_i| + |q_{i-1}|)) over the interior nodes of every coordinate line of the leaf's LGL nodes
+// (0 where the denominator vanishes); one lane per leaf.
+template <int DIM, int N>
+__global__ void k_indicator_lohner(int n, int ld, const int32_t* slot_of_leaf, const double* U, int var,
+                                   double f_wave, double gamma, double* eta) {
+  constexpr int ND = G<DIM, N>::ND, NV = DIM + 2;
+  const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
+  if (leaf >= n) return;
+  const int slot = slot_of_leaf[leaf];
+  double q[ND];
+#pragma unroll
+  for (int nd = 0; nd < ND; ++nd) {
+    const double rho = U[(int64_t)slot * ND + nd];
+    double val = rho;
+    if (var >= 1 && var <= DIM) {
+      val = U[((int64_t)var * ld + slot) * ND + nd] / rho;
+    } else if (var == DIM + 1) {
+      double ke = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double m = U[((int64_t)(1 + d) * ld + slot) * ND + nd];
+        ke += m * m;
+      }
+      val = (gamma - 1.0) * (U[((int64_t)(NV - 1) * ld + slot) * ND + nd] - 0.5 * ke / rho);
+    }
+    q[nd] = val;
+  }
+  double best = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const int st = stride_dir<DIM, N>(d);
+#pragma unroll
+    for (int nd = 0; nd < ND; ++nd) {
+      const int ia = node_index_dir<DIM, N>(nd, d);
+      if (ia == 0 || ia == N - 1) continue;
+      const double um = q[nd - st], u0 = q[nd], up = q[nd + st];
+      const double num = fabs(up - 2.0 * u0 + um);
+      const double den = fabs(up - u0) + fabs(u0 - um) + f_wave * (fabs(up) + 2.0 * fabs(u0) + fabs(um));
+      const double e = den > 0.0 ? num / den : 0.0;
+      best = e > best ? e : best;
+    }
+  }
+  eta[leaf] = best;
+}
+
 // Largest convective wave speed per slot, scaled to the step-size bound of eq. (CFL_DG):
 // w_e = max over nodes and directions of (k+1)(|v_d| + c) / h_d, one lane per slot.
 template <int DIM, int N>
@@ -330,6 +377,23 @@ hipError_t launch_slot_to_leaf(int n, int ld, int nv, int nd, const int32_t* slo
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_slot_to_leaf, dim3(grid_for(total, 256)), dim3(256), 0, s, total, ld, nv, nd, slot_of_leaf,
                      src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_indicator_lohner(int dim, int N, int n, int ld, const int32_t* slot_of_leaf, const double* U,
+                                   int var, double f_wave, double gamma, double* eta, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const dim3 g(grid_for(n, 128)), b(128);
+  if (dim == 2 && N == 4)
+    hipLaunchKernelGGL((k_indicator_lohner<2, 4>), g, b, 0, s, n, ld, slot_of_leaf, U, var, f_wave, gamma, eta);
+  else if (dim == 2 && N == 3)
+    hipLaunchKernelGGL((k_indicator_lohner<2, 3>), g, b, 0, s, n, ld, slot_of_leaf, U, var, f_wave, gamma, eta);
+  else if (dim == 3 && N == 4)
+    hipLaunchKernelGGL((k_indicator_lohner<3, 4>), g, b, 0, s, n, ld, slot_of_leaf, U, var, f_wave, gamma, eta);
+  else if (dim == 3 && N == 3)
+    hipLaunchKernelGGL((k_indicator_lohner<3, 3>), g, b, 0, s, n, ld, slot_of_leaf, U, var, f_wave, gamma, eta);
+  else
+    return hipErrorNotSupported;
   return hipGetLastError();
 }
 

@@ -117,16 +117,27 @@ __device__ __forceinline__ void ec_flux(const NodeQ<DIM>& L, const NodeQ<DIM>& R
                                         double* f) {
   const double rho_ln = log_mean(L.rho, R.rho, L.lrho, R.lrho);
   const double ibeta_ln = inv_log_mean(L.beta, R.beta, L.lbeta, R.lbeta);
-  double vd = 0.5 * (L.v[d] + R.v[d]);
+  // the direction differs from lane to lane: components along d by selects, not by indexing
+  // (an indexed register array goes to scratch memory)
+  double vdL = L.v[0], vdR = R.v[0];
+#pragma unroll
+  for (int k = 1; k < DIM; ++k) {
+    vdL = k == d ? L.v[k] : vdL;
+    vdR = k == d ? R.v[k] : vdR;
+  }
+  double vd = 0.5 * (vdL + vdR);
   double vv = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) vv += L.v[k] * R.v[k];
   const double fr = rho_ln * vd;
+  const double pm = 0.5 * (L.p + R.p);
   f[0] = fr;
 #pragma unroll
-  for (int k = 0; k < DIM; ++k) f[1 + k] = fr * 0.5 * (L.v[k] + R.v[k]);
-  f[1 + d] += 0.5 * (L.p + R.p);
-  f[DIM + 1] = fr * (0.5 * vv + ibeta_ln * inv_gm1) + 0.5 * (L.p * R.v[d] + R.p * L.v[d]);
+  for (int k = 0; k < DIM; ++k) {
+    const double fk = fr * 0.5 * (L.v[k] + R.v[k]);
+    f[1 + k] = k == d ? fk + pm : fk;
+  }
+  f[DIM + 1] = fr * (0.5 * vv + ibeta_ln * inv_gm1) + 0.5 * (L.p * vdR + R.p * vdL);
 }
 
 // HLL flux with Davis wave speeds, normal +e_d from L to R; uL, uR conservative.
@@ -135,21 +146,29 @@ __device__ __forceinline__ void hll_flux(const double* uL, const double* uR, int
   double rl, vl[DIM], pl, rr, vr[DIM], pr;
   cons_to_prim<DIM>(uL, gamma, rl, vl, pl);
   cons_to_prim<DIM>(uR, gamma, rr, vr, pr);
+  // normal components by selects (the direction differs from lane to lane)
+  double vnl = vl[0], vnr = vr[0], mnl = uL[1], mnr = uR[1];
+#pragma unroll
+  for (int k = 1; k < DIM; ++k) {
+    vnl = k == d ? vl[k] : vnl;
+    vnr = k == d ? vr[k] : vnr;
+    mnl = k == d ? uL[1 + k] : mnl;
+    mnr = k == d ? uR[1 + k] : mnr;
+  }
   const double cl = sqrt_pos(gamma * pl * rcp(rl)), cr = sqrt_pos(gamma * pr * rcp(rr));
-  const double sl = fmin(vl[d] - cl, vr[d] - cr);
-  const double sr = fmax(vl[d] + cl, vr[d] + cr);
+  const double sl = fmin(vnl - cl, vnr - cr);
+  const double sr = fmax(vnl + cl, vnr + cr);
   double fl[DIM + 2], fr[DIM + 2];
-  fl[0] = uL[1 + d];
-  fr[0] = uR[1 + d];
+  fl[0] = mnl;
+  fr[0] = mnr;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    fl[1 + k] = uL[1 + k] * vl[d];
-    fr[1 + k] = uR[1 + k] * vr[d];
+    const double al = uL[1 + k] * vnl, ar = uR[1 + k] * vnr;
+    fl[1 + k] = k == d ? al + pl : al;
+    fr[1 + k] = k == d ? ar + pr : ar;
   }
-  fl[1 + d] += pl;
-  fr[1 + d] += pr;
-  fl[DIM + 1] = (uL[DIM + 1] + pl) * vl[d];
-  fr[DIM + 1] = (uR[DIM + 1] + pr) * vr[d];
+  fl[DIM + 1] = (uL[DIM + 1] + pl) * vnl;
+  fr[DIM + 1] = (uR[DIM + 1] + pr) * vnr;
   if (sl >= 0.0) {
 #pragma unroll
     for (int v = 0; v < DIM + 2; ++v) f[v] = fl[v];
@@ -292,6 +311,9 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   double un[NITEM], k1[NITEM], acc[NITEM];
   if (act) {
     my_mem = member_of_slot(m, e);
+    // one element per block: the member is the same on every lane, so the epilogue's per-member
+    // argument reads (coefficients, output buffer) are scalar loads, not per-lane indexed ones
+    if (EPB == 1) my_mem = __builtin_amdgcn_readfirstlane(my_mem);
     my_src = src_of(a, my_mem);   // (a shift of one argument word, not an indexed argument load)
     int tr_nb[NTR], tr_pk[NTR];
 #pragma unroll
@@ -382,19 +404,45 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
     }
   }
   if (act) {
-    for (int w = lane; w < ND; w += T) {
-      double uu[NV];
+    // Node quantities.  When the element's nodes fill whole waves and the block has waves to
+    // spare (3D p=3: 64 nodes, 7 waves), the two logarithms of a node go to two waves: the first
+    // forms the primitives and ln rho, the second beta = rho/p and ln beta, side by side.
+    constexpr bool SPLITQ = ND % 64 == 0 && T >= 2 * ND;
+    if (SPLITQ) {
+      const int w = lane < ND ? lane : lane - ND;
+      if (lane < 2 * ND) {
+        double uu[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) uu[v] = s_u[le][v][w];
-      NodeQ<DIM> q;
-      cons_to_prim<DIM>(uu, gamma, q.rho, q.v, q.p);
-      q.lrho = log_pos(q.rho);
-      q.beta = q.rho * rcp(q.p);
-      q.lbeta = log_pos(q.beta);
-      s_q[le][w] = q;
+        for (int v = 0; v < NV; ++v) uu[v] = s_u[le][v][w];
+        double rho, vel[DIM], p;
+        cons_to_prim<DIM>(uu, gamma, rho, vel, p);
+        if (lane < ND) {
+          s_q[le][w].rho = rho;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) s_q[le][w].v[d] = vel[d];
+          s_q[le][w].p = p;
+          s_q[le][w].lrho = log_pos(rho);
+        } else {
+          const double beta = rho * rcp(p);
+          s_q[le][w].beta = beta;
+          s_q[le][w].lbeta = log_pos(beta);
+        }
+      }
+    } else {
+      for (int w = lane; w < ND; w += T) {
+        double uu[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) uu[v] = s_u[le][v][w];
+        NodeQ<DIM> q;
+        cons_to_prim<DIM>(uu, gamma, q.rho, q.v, q.p);
+        q.lrho = log_pos(q.rho);
+        q.beta = q.rho * rcp(q.p);
+        q.lbeta = log_pos(q.beta);
+        s_q[le][w] = q;
+      }
     }
-    // (interpolations start on the second wave, the node quantities sit on the first)
-    const int lane_c = (lane + 64) % T;
+    // (interpolations start on the wave after the node quantities)
+    const int lane_c = (lane + (SPLITQ ? 2 * ND : 64)) % T;
     for (int w = lane_c; w < NFC * NV * NF; w += T) {
       const int j = w % NF;
       const int v = (w / NF) % NV;

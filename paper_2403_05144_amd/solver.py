@@ -194,6 +194,31 @@ class PerkSolver:
                                         ctypes.c_void_p(out.data_ptr()), _stream_handle()), "pe_rhs_vjp")
         return out
 
+    def jvp_fd_slot(self, u_slot, v_slot, out, eps=1e-7):
+        """out = F'(u) v by central differences (pe_rhs_jvp_fd), all slot-layout device arrays."""
+        self._check(self.lib.pe_rhs_jvp_fd(self._ctx, ctypes.c_void_p(u_slot.data_ptr()),
+                                           ctypes.c_void_p(v_slot.data_ptr()), float(eps),
+                                           ctypes.c_void_p(out.data_ptr()), _stream_handle()), "pe_rhs_jvp_fd")
+        return out
+
+    def vjp_into(self, u_slot, w_slot, out):
+        """out = F'(u)^T w (pe_rhs_vjp), all slot-layout device arrays."""
+        self._check(self.lib.pe_rhs_vjp(self._ctx, ctypes.c_void_p(u_slot.data_ptr()), ctypes.c_void_p(w_slot.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), _stream_handle()), "pe_rhs_vjp")
+        return out
+
+    def orthogonalize(self, V, k, w, scratch):
+        """Orthogonalise device vector w against rows 0..k-1 of V (pe_orthogonalize); returns the
+        k + 1 coefficients (projections, then the norm w was divided by)."""
+        h = np.zeros(k + 1)
+        n = w.numel()
+        ldv = V.stride(0) if V.dim() == 2 else n
+        self._check(self.lib.pe_orthogonalize(self._ctx, ctypes.c_void_p(V.data_ptr()), int(k), int(ldv),
+                                              ctypes.c_void_p(w.data_ptr()), int(n), ctypes.c_void_p(scratch.data_ptr()),
+                                              h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream_handle()),
+                    "pe_orthogonalize")
+        return h
+
     def to_slot(self, x_leaf):
         """Leaf-layout array [n_leaves, n_vars, nodes] -> slot-layout tensor (uses the bound state)."""
         saved = self.u.clone()
@@ -278,6 +303,12 @@ class PerkSolver:
         self.n_elements = self._leaves.shape[0]
         self.mesh.leaves = self._leaves
         self.partition(member_of_level)
+
+    def set_indicator(self, kind, variable=1, f_wave=0.2):
+        """Refinement indicator of indicator() / amr_cycle(): "density_gradient" or "lohner" (on the
+        primitive variable `variable`: 0 rho, 1..dim velocity, dim+1 pressure)."""
+        k = {"density_gradient": 0, "lohner": 1}[kind]
+        self._check(self.lib.pe_set_amr_indicator(self._ctx, k, int(variable), float(f_wave)), "pe_set_amr_indicator")
 
     def amr_cycle(self, refine_above, coarsen_below, level_min, level_max, member_of_level):
         """indicator() + threshold flags + adapt() in one library call (the same flags, forest and

@@ -270,6 +270,17 @@ def kelvin_helmholtz(x, y, seed=MASTER_SEED + 1, gamma=1.4, amplitude=0.01, widt
     return prim2cons(rho, [vx, vy], p, gamma)
 
 
+def shear_layer(x, y, kappa=80.0, delta=0.05, c0=10.0, gamma=1.4):
+    """Doubly periodic double shear layer on [0,1]^2 (paper eq. ShearLayerIC): rho = 1,
+    v_x = tanh(kappa (y - 1/4)) for y <= 1/2 and tanh(kappa (3/4 - y)) above, v_y =
+    delta sin(2 pi (x + 1/4)), p = c0^2 rho / gamma; conservative variables."""
+    rho = np.ones_like(x)
+    vx = np.where(y <= 0.5, np.tanh(kappa * (y - 0.25)), np.tanh(kappa * (0.75 - y)))
+    vy = delta * np.sin(2.0 * np.pi * (x + 0.25))
+    p = c0 * c0 * rho / gamma
+    return prim2cons(rho, [vx, vy], p, gamma)
+
+
 def kh_density_perturbation(x, y, seed=MASTER_SEED + 4, amplitude=1e-3, n_modes=8):
     """Seeded smooth periodic density perturbation on [-1,1]^2 (the control of the
     differentiated workload): amplitude * sum_k a_k sin(pi (kx_k x + ky_k y) + phi_k), a_k in

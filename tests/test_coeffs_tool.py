@@ -37,3 +37,24 @@ def test_family_on_disk_spectrum(order, E_list):
         assert np.all(np.abs(coef[E + 1:]) < 1e-15)
     # steps grow with the number of stage evaluations (Sec. 3: dt_opt roughly linear in E)
     assert all(fam.dt_opt[i] < fam.dt_opt[i + 1] for i in range(len(fam.E) - 1))
+
+
+def test_rechained_members_match_the_oracle_patterns():
+    # the library's pattern construction (a linear solve per coefficient through the tableau's
+    # polynomial) against the oracle's closed-form chain recursion (Sec. 3.2.4)
+    import numpy as np
+    from oracle import perk_coeffs as pc
+    from paper_2403_05144_amd import coeffs
+    f = pc.perk2_family([4, 6])
+    fam = coeffs.Family(2, 6, [4, 6], f.c, f.b, f.a_sub)
+    for kind, chain in pc.PAPER_CHAINS_S6_E4.items():
+        got = coeffs.with_chains(fam, [chain, None])
+        ref = pc.pattern_family([chain, list(range(6))], 6)
+        np.testing.assert_array_equal(got.coupling, ref.coupling)
+        np.testing.assert_allclose(got.a_sub, ref.a_val, rtol=1e-13, atol=1e-16)
+    f8 = pc.perk2_family([4, 6, 8])
+    fam8 = coeffs.Family(2, 8, [4, 6, 8], f8.c, f8.b, f8.a_sub)
+    got = coeffs.with_chains(fam8, [[0, 3, 5, 7], [0, 1, 2, 3, 4, 7], None])
+    ref = pc.pattern_family([[0, 3, 5, 7], [0, 1, 2, 3, 4, 7], list(range(8))], 8)
+    np.testing.assert_array_equal(got.coupling, ref.coupling)
+    np.testing.assert_allclose(got.a_sub, ref.a_val, rtol=1e-13, atol=1e-16)

@@ -164,3 +164,49 @@ def test_amr_cycle_equals_separate_calls():
     for a, b in zip(runs[0], runs[1]):
         assert a.shape == b.shape
         np.testing.assert_array_equal(a, b)
+
+
+def test_lohner_indicator_and_ns_steps_on_the_shear_layer():
+    # Sec. 7.1.1: Loehner's indicator on v_x drives the adaptation of the doubly periodic shear
+    # layer; P-ERK3{3,4,7} Navier-Stokes steps (BR1, mu = 1/Re, Re = 2.5e4) on the adapted forest.
+    # The GPU indicator against the oracle's (1e-14: one division per estimate, contraction may
+    # differ), flags replayed from the oracle, leaf lists bit-exact, states 1e-12.
+    from paper_2403_05144_amd import PerkSolver
+    from parity_util import flux_scale, state_close, worst
+    th = np.linspace(0, 2 * np.pi, 200, endpoint=False)
+    eigs = -1.0 + np.exp(1j * th)
+    fam = pc.perk3_family([3, 4, 7], {E: pc.optimize_alpha(eigs, 3, E)[1] for E in (4, 7)})
+    mu = 1.0 / 2.5e4
+    mesh = pin.uniform_mesh(2, (8, 8), (0, 0), (1, 1), 0)
+    lmax = 3
+    s = PerkSolver(mesh, 3, fam, [0, 0, 1, 2], capacity=8192, equations=1, mu=mu)
+    s.set_indicator("lohner", 1, 0.2)
+    leaves = mesh.leaves
+    for cyc in range(3):
+        o = od.Oracle(pin.MeshDesc(2, (8, 8), (0, 0), (1, 1), leaves), 4, viscous=True, mu=mu)
+        x = o.node_coords().transpose(1, 0, 2)
+        u = pin.shear_layer(x[0], x[1]).transpose(1, 0, 2).copy()
+        s.set_state(u)
+        eta_o = amr.lohner_indicator(o, u, var=1, f_wave=0.2)
+        eta_g = s.indicator()
+        print(f"shear layer cycle {cyc}: {len(leaves)} leaves, max eta {eta_o.max():.3f}", flush=True)
+        assert np.max(np.abs(eta_g - eta_o)) <= 1e-14
+        flags = amr.flags_from_indicator(eta_o, 0.2, 0.05)
+        leaves, _ = amr.adapt(leaves, flags, 0, lmax, 2, (8, 8))
+        s.adapt(flags, 0, lmax, [0, 0, 1, 2])
+        np.testing.assert_array_equal(s.leaves(), leaves)
+    lv = np.asarray(leaves)[:, 0]
+    assert lv.max() == lmax and lv.min() == 0, np.bincount(lv)
+    o = od.Oracle(pin.MeshDesc(2, (8, 8), (0, 0), (1, 1), leaves), 4, viscous=True, mu=mu)
+    x = o.node_coords().transpose(1, 0, 2)
+    u0 = pin.shear_layer(x[0], x[1]).transpose(1, 0, 2).copy()
+    s.set_state(u0)
+    member = np.asarray([0, 0, 1, 2])[lv]
+    dt = 2e-5
+    u_ora = u0.copy()
+    for _ in range(2):
+        u_ora = o.prk_step(u_ora, dt, fam, member)
+    s.step(dt, 2)
+    u_gpu = s.get_state().cpu().numpy()
+    sig = flux_scale(o, u0)
+    assert state_close(u_gpu, u_ora, sig, 2, dt), worst(u_gpu, u_ora, sig, 2, dt)

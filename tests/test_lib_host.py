@@ -284,3 +284,15 @@ def test_stage_pattern_validation():
     co, keep = _pattern_coeffs(L, fam)
     assert lib.pe_set_perk_coefficients(ctx, ctypes.byref(co)) == -6
     lib.pe_destroy(ctx)
+
+
+def test_indicator_selection_errors():
+    L, lib = _lib()
+    ctx = _ctx(L, lib)
+    assert lib.pe_set_amr_indicator(ctx, 1, 1, 0.2) == 0            # Loehner on v_x
+    assert lib.pe_set_amr_indicator(ctx, 0, 0, 0.0) == 0            # density gradient
+    assert lib.pe_set_amr_indicator(ctx, 2, 1, 0.2) == -1           # unknown kind
+    assert lib.pe_set_amr_indicator(ctx, 1, 4, 0.2) == -1           # 2D: variables 0..3
+    assert lib.pe_set_amr_indicator(ctx, 1, 1, -0.1) == -1          # f_wave < 0
+    assert lib.pe_set_amr_indicator(ctx, 1, 1, float("nan")) == -1
+    lib.pe_destroy(ctx)

@@ -88,3 +88,45 @@ def test_indicator_of_linear_density():
     eta = amr.indicator(o, u)
     expect = 0.25 * 0.5 / np.max(u[:, 0], axis=1)
     np.testing.assert_allclose(eta, expect, rtol=1e-13)
+
+
+# ------------------------------------------------------------------ Loehner indicator (Sec. 7.1.1)
+def test_lohner_estimate_closed_forms():
+    from oracle.amr import lohner_estimate
+    # a peak (0, 1, 0): second difference 2 over 1 + 1 + f (0 + 2 + 0)
+    assert lohner_estimate(0.0, 1.0, 0.0, 0.2) == 2.0 / 2.4
+    # equal spacing of values (linear data) and constants give 0
+    assert lohner_estimate(1.0, 2.0, 3.0, 0.2) == 0.0
+    assert lohner_estimate(5.0, 5.0, 5.0, 0.2) == 0.0
+    assert lohner_estimate(0.0, 0.0, 0.0, 0.2) == 0.0           # vanishing denominator
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        um, u0, up = rng.standard_normal(3)
+        e = lohner_estimate(um, u0, up, 0.2)
+        assert 0.0 <= e <= 1.0                                   # |a - 2b + c| <= |a - b| + |b - c|
+        assert abs(lohner_estimate(up, u0, um, 0.2) - e) <= 1e-15                     # stencil reflection
+        assert abs(lohner_estimate(3.7 * um, 3.7 * u0, 3.7 * up, 0.2) - e) <= 1e-15   # degree-0 homogeneous
+        assert lohner_estimate(um, u0, up, 0.0) >= e             # f_wave only damps
+
+
+def test_lohner_indicator_on_the_shear_layer():
+    # element indicator = max over interior nodes of every coordinate line; elements far from the
+    # shear layers see a smooth v_x (small values), the layers (width 1/80) saturate it
+    import perk_inputs as pin
+    from oracle.amr import lohner_indicator, lohner_estimate, primitive_variable
+    mesh = pin.uniform_mesh(2, (8, 8), (0, 0), (1, 1), 0)
+    o = od.Oracle(mesh, 4)
+    x = o.node_coords().transpose(1, 0, 2)
+    u = pin.shear_layer(x[0], x[1]).transpose(1, 0, 2).copy()
+    eta = lohner_indicator(o, u, var=1, f_wave=0.2)
+    yc = np.array([(j + 0.5) / 8 for (_, i, j, _) in mesh.leaves.tolist()])
+    near = np.abs(np.abs(yc - 0.5) - 0.25) < 0.07
+    assert eta[near].min() > 3 * eta[~near].max()
+    # brute force on one element: every interior node of every line, both directions
+    e = int(np.argmax(eta))
+    v = primitive_variable(u, 1, 2)[e].reshape(4, 4)         # [j, i]
+    best = max(max(lohner_estimate(v[j, i - 1], v[j, i], v[j, i + 1], 0.2) for j in range(4) for i in (1, 2)),
+               max(lohner_estimate(v[j - 1, i], v[j, i], v[j + 1, i], 0.2) for j in (1, 2) for i in range(4)))
+    assert eta[e] == best
+    # primitive variables: velocity and pressure of the initial state
+    np.testing.assert_allclose(primitive_variable(u, 3, 2), 100.0 / 1.4, rtol=1e-14)

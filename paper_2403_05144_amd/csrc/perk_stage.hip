@@ -278,7 +278,8 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   auto Pm = [&](int mm, int idx) -> double { return OPS_A ? s_PR[mm][idx] : op.P[mm][idx]; };
   auto Rm = [&](int mm, int idx) -> double { return OPS_A ? s_PR[2 + mm][idx] : op.R[mm][idx]; };
 
-  const int le = threadIdx.x / T;
+  // one element per block: the element index is the same on every lane (scalar registers)
+  const int le = EPB == 1 ? 0 : (int)threadIdx.x / T;
   const int lane = threadIdx.x - le * T;
   const int v_act = blk * EPB + le;                 // index among the launch's active elements
   const bool act = v_act < a.n_act;

@@ -350,6 +350,15 @@ pe_status pe_get_leaves(const pe_ctx* ctx, int32_t* leaves, int64_t* n);
  * once.  PE_ESTATE before pe_partition; PE_EINVAL for eps <= 0, a zero v or null pointers. */
 pe_status pe_rhs_jvp_fd(pe_ctx* ctx, const double* u, const double* v, double eps, double* out, void* stream);
 
+/* Exact directional derivative t = F'(u) v of the Euler right-hand side (forward mode: every
+ * quantity of the operator of Sec. 6.1 carried with its derivative; flux branches -- HLL wave
+ * speeds and cases, the logarithmic-mean series -- as the values take them, a tie of the wave
+ * speeds' min / max taking the first argument).  Optionally also f = F(u) (f may be NULL).
+ * u, v, t, f: device state arrays in slot layout; t and f must not alias u or v.  Writes the
+ * element slots only.  Asynchronous on `stream`.  PE_ESTATE before pe_partition,
+ * PE_EUNSUPPORTED for Navier-Stokes, PE_EINVAL for null u, v or t. */
+pe_status pe_rhs_jvp(pe_ctx* ctx, const double* u, const double* v, double* t, double* f, void* stream);
+
 /* Device doubles of scratch pe_orthogonalize needs for k basis vectors. */
 pe_status pe_orthogonalize_scratch(int k, int64_t* doubles);
 

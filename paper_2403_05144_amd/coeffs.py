@@ -345,8 +345,8 @@ def fd_spectrum(solver, u_leaf, eps=1e-7):
 
 def arnoldi(solver, u_slot, m, op="fd", eps=1e-7, seed=0):
     """m steps of the Arnoldi iteration on J = F'(u) at the solver's mesh (Sec. 4.1 step 4):
-    products with J by central differences (op "fd", any equations) or exact products with J^T
-    (op "vjp", Euler; same eigenvalues), orthogonalisation by two passes of classical
+    products with J by central differences (op "fd", any equations), exact products with J
+    (op "jvp", forward mode, Euler) or with J^T (op "vjp", Euler; same eigenvalues), orthogonalisation by two passes of classical
     Gram-Schmidt, all in libperk kernels on device vectors.  Returns the (j+1) x j Hessenberg
     matrix of the j <= m steps taken (fewer if the Krylov space closes)."""
     import torch
@@ -369,6 +369,8 @@ def arnoldi(solver, u_slot, m, op="fd", eps=1e-7, seed=0):
     for j in range(m):
         if op == "fd":
             solver.jvp_fd_slot(u_slot, V[j], V[j + 1], eps)
+        elif op == "jvp":
+            solver.jvp_into(u_slot, V[j], V[j + 1])
         else:
             solver.vjp_into(u_slot, V[j], V[j + 1])
         h = solver.orthogonalize(V, j + 1, V[j + 1], scratch)

@@ -1955,6 +1955,16 @@ pe_status pe_rhs_jvp_fd(pe_ctx* ctx, const double* u, const double* v, double ep
   return PE_OK;
 }
 
+pe_status pe_rhs_jvp(pe_ctx* ctx, const double* u, const double* v, double* t, double* f, void* stream) {
+  if (!ctx) return PE_EINVAL;
+  if (!ctx->partitioned) return fail(ctx, PE_ESTATE, "rhs_jvp before partition");
+  if (ctx->equations != 0) return fail(ctx, PE_EUNSUPPORTED, "rhs_jvp: Euler only");
+  if (!u || !v || !t) return fail(ctx, PE_EINVAL, "rhs_jvp: null");
+  HIPCHK(launch_rhs_jvp(ctx->dim, ctx->N, (int)ctx->n_e, u, v, t, f, device_mesh(ctx), ctx->ops, ctx->ph,
+                        (hipStream_t)stream));
+  return PE_OK;
+}
+
 pe_status pe_device_math(pe_ctx* ctx, const double* x, int64_t n, double* out, void* stream) {
   if (!ctx) return PE_EINVAL;
   if (n < 0 || (n > 0 && (!x || !out))) return fail(ctx, PE_EINVAL, "device_math: bad arguments");

@@ -209,6 +209,10 @@ hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s)
 // beta[l] = 1 / w_l or 0 (beta may be null).  n in [1, kNoAllocMaxElements].
 hipError_t launch_max_dt_noalloc(int dim, int N, int n, const double* U, const Physics& ph, const Mesh& m,
                                  double cfl, double* dt, double* beta, hipStream_t s);
+// Tangent of the Euler right-hand side (perk_jvp.hip): T = F'(U) V, F = F(U) if F is not null,
+// for the n element slots.
+hipError_t launch_rhs_jvp(int dim, int N, int n, const double* U, const double* V, double* T, double* F,
+                          const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s);
 // Spectrum estimation (perk_spectrum.hip): out[j] = V_j . w for the k columns of V (stride ldv),
 // through a scratch of multi_dot_scratch_doubles(k) doubles; w -= sum_j h_j V_j (h on the
 // device); y = x + s v; y = (a - b) s.

@@ -201,6 +201,15 @@ class PerkSolver:
                                            ctypes.c_void_p(out.data_ptr()), _stream_handle()), "pe_rhs_jvp_fd")
         return out
 
+    def jvp_into(self, u_slot, v_slot, out, f=None):
+        """out = F'(u) v exactly (pe_rhs_jvp, Euler) and, if f is given, f = F(u); all
+        slot-layout device arrays."""
+        self._check(self.lib.pe_rhs_jvp(self._ctx, ctypes.c_void_p(u_slot.data_ptr()), ctypes.c_void_p(v_slot.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.c_void_p(f.data_ptr() if f is not None else 0), _stream_handle()),
+                    "pe_rhs_jvp")
+        return out
+
     def vjp_into(self, u_slot, w_slot, out):
         """out = F'(u)^T w (pe_rhs_vjp), all slot-layout device arrays."""
         self._check(self.lib.pe_rhs_vjp(self._ctx, ctypes.c_void_p(u_slot.data_ptr()), ctypes.c_void_p(w_slot.data_ptr()),

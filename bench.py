@@ -114,7 +114,7 @@ def wl_vortex_2level():
                      "surface flux, P-ERK2{4,8}")
 
 
-def wl_kh_amr(n_root=8, level_max=3, name="kh_amr_l3-6"):
+def wl_kh_amr(n_root=8, level_max=3, name="kh_amr_l3-6", fam=None):
     """Kelvin-Helmholtz shear layer, quadtree AMR between config levels 3 and 6 (forest levels
     0..3 on 8x8 roots), P-ERK3{4,6,8,12,16}, adaptation every 10 steps.
 
@@ -127,15 +127,19 @@ def wl_kh_amr(n_root=8, level_max=3, name="kh_amr_l3-6"):
     mesh = pin.uniform_mesh(2, (n_root, n_root), (-1, -1), (1, 1), 0)
     ic = lambda x: pin.kelvin_helmholtz(x[0], x[1])
     h_red = 2.0 / n_root
-    fam = family_for(f"perk3_4_6_8_12_16_kh_p3_n{n_root}", 3, [4, 6, 8, 12, 16],
-                     pin.uniform_mesh(2, (n_root, n_root), (-1, -1), (1, 1), 0), 3, ic, h_red)
+    fam_name = f"perk3_4_6_8_12_16_kh_p3_n{n_root}"
+    if fam is None:
+        fam = family_for(fam_name, 3, [4, 6, 8, 12, 16], pin.uniform_mesh(2, (n_root, n_root), (-1, -1), (1, 1), 0),
+                         3, ic, h_red)
     rule = LevelRule.required_step(fam.dt_opt, margin=2.0)
     mol = rule_map(fam, rule, level_max)
     mol1 = rule_map(fam, LevelRule.required_step(fam.dt_opt, margin=1.0), level_max)
     h_min = h_red / 2 ** level_max
     cfl = 0.9
     dt = cfl * fam.dt_opt[-1] * h_min / fam.h_ref
-    return dict(name=name, mesh=mesh, degree=3, fam=fam, mol=mol, rule=rule, ic=ic, dt=dt, cfl=cfl, t_final=3.0,
+    return dict(name=name, mesh=mesh, degree=3, fam=fam, fam_name=fam_name, mol=mol, rule=rule, ic=ic, dt=dt,
+                cfl=cfl, t_final=3.0, spectrum_op="jvp", h_reduced=h_red,
+                reduced_mesh=pin.uniform_mesh(2, (n_root, n_root), (-1, -1), (1, 1), 0),
                 perk_maps=[("required-step rule, margin 2", mol), ("required-step rule, margin 1", mol1)],
                 amr=dict(level_min=0, level_max=level_max, interval=10, refine_above=0.05, coarsen_below=0.01,
                          capacity=(n_root << level_max) ** 2),
@@ -179,7 +183,7 @@ def wl_shear_layer():
                      f"(paper rule), CFL {cfl} of the finest member's optimised step")
 
 
-def wl_tgv():
+def wl_tgv(fam=None):
     """3D compressible Navier-Stokes Taylor-Green vortex, Ma 0.1, Re 1600, Pr 0.72, 16^3 roots
     with a seeded 2-level refined region (7120 elements), p=3, BR1, P-ERK2{4,8,16}.
 
@@ -193,14 +197,16 @@ def wl_tgv():
     mu = 1.0 / 1600
     ic = lambda x: pin.taylor_green(x[0], x[1], x[2])
     red = pin.uniform_mesh(3, (2, 2, 2), (-np.pi,) * 3, (np.pi,) * 3, 0)
-    fam = family_for("perk2_4_8_16_tgv_p3", 2, [4, 8, 16], red, 3, ic, np.pi, equations=1, mu=mu)
+    fam_name = "perk2_4_8_16_tgv_p3"
+    if fam is None:
+        fam = family_for(fam_name, 2, [4, 8, 16], red, 3, ic, np.pi, equations=1, mu=mu)
     rule = LevelRule.required_step(fam.dt_opt, margin=1.0)
     mol = rule_map(fam, rule, 2)
     h_min = 2 * np.pi / 16 / 4
     cfl = 0.7
     dt = cfl * fam.dt_opt[-1] * h_min / fam.h_ref
-    return dict(name="tgv_ns_3d", mesh=mesh, degree=3, fam=fam, mol=mol, rule=rule, ic=ic, dt=dt, cfl=cfl,
-                t_final=200 * dt,
+    return dict(name="tgv_ns_3d", mesh=mesh, degree=3, fam=fam, fam_name=fam_name, mol=mol, rule=rule, ic=ic, dt=dt,
+                cfl=cfl, t_final=200 * dt, spectrum_op="fd", reduced_mesh=red, h_reduced=np.pi,
                 equations=1, mu=mu,
                 perk_maps=[("required-step rule", mol), ("one member per level", [0, 1, 2])],
                 desc="3D compressible Navier-Stokes Taylor-Green vortex (Ma 0.1, Re 1600, Pr 0.72) on "
@@ -486,77 +492,101 @@ def run_patterns(args):
     }
 
 
-def run_spectrum(args):
-    """Spectrum estimation at the real mesh (Sec. 4.1, steps 2-4) on the GPU: the hull points of the
-    reduced-mesh spectrum, scaled by h_reduced / h, as targets; one Arnoldi factorisation of m
-    steps of the Jacobian at the initial state (KH: exact products with J^T; TGV: central
-    differences); Ritz values plus the harmonic Ritz values nearest to every target; then the
-    P-ERK family optimised on those eigenvalues, next to the reduced-mesh family the benchmark
-    uses.  Timed: the Arnoldi factorisation (device) and the eigenvalue extraction (host)."""
+def spectrum_at_mesh(wl, m):
+    """Spectrum estimation at the workload's real mesh (Sec. 4.1, steps 2-4) on the GPU: the hull
+    points of the reduced-mesh spectrum, scaled by h_reduced / h, as targets; one Arnoldi
+    factorisation of m steps of the Jacobian at the initial state (Euler: exact products from the
+    forward-mode kernel; Navier-Stokes: central differences); Ritz values plus the harmonic Ritz
+    values nearest to every target; then the P-ERK family optimised on those eigenvalues (h_ref =
+    the smallest element size).  Returns (family, report)."""
     import torch
     import perk_inputs as pin
     from paper_2403_05144_amd import coeffs
     from paper_2403_05144_amd.amr import AmrDriver
+    fam, mesh, op = wl["fam"], wl["mesh"], wl["spectrum_op"]
+    m0 = pin.MeshDesc(mesh.dim, mesh.n_root, mesh.lo, mesh.hi, np.array(mesh.leaves, copy=True))
+    s = make_solver(wl, m0, fam, wl["mol"])
+    ic_leaf = lambda x: wl["ic"](x.transpose(1, 0, 2)).transpose(1, 0, 2).copy()
+    if wl.get("amr"):
+        a = wl["amr"]
+        AmrDriver(s, a["level_min"], a["level_max"], wl["mol"], a["refine_above"], a["coarsen_below"],
+                  a["interval"]).initial_mesh(ic_leaf, passes=3)
+    else:
+        s.set_state(ic_leaf(s.node_coords().cpu().numpy()))
+    # reduced spectrum of the family's own construction (its reduced mesh and element size)
+    rs = make_solver(dict(wl, amr=None), wl["reduced_mesh"], fam, [0] * 8)
+    rs.set_state(ic_leaf(rs.node_coords().cpu().numpy()))
+    t0 = time.perf_counter()
+    lam_red = coeffs.fd_spectrum(rs, rs.get_state().cpu().numpy())
+    t_red = time.perf_counter() - t0
+    del rs
+    lv = s.leaves()[:, 0]
+    h_min = (mesh.hi[0] - mesh.lo[0]) / (mesh.n_root[0] << int(lv.max()))
+    u = s.u.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = coeffs.arnoldi(s, u, m, op=op)
+    torch.cuda.synchronize()
+    t_arn = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    shifts = coeffs.hull_points(lam_red) * (fam.h_ref / h_min)
+    per = max(1, 1000 // max(1, len(shifts)))
+    ritz = np.linalg.eigvals(H[: H.shape[1], : H.shape[1]])
+    est = [ritz]
+    for sg in shifts:
+        th = coeffs.harmonic_ritz(H, sg)
+        est.append(th[np.argsort(np.abs(th - sg))[:per]])
+    lam = np.concatenate(est)
+    lam = lam[np.isfinite(lam) & (lam.imag >= 0)]
+    lam.real = np.minimum(lam.real, 0.0)
+    t_eig = time.perf_counter() - t0
+    full = coeffs.build_family(fam.order, fam.E, coeffs.hull_points(lam), h_ref=h_min)
+    scaled_red = [d * h_min / fam.h_ref for d in fam.dt_opt]
+    n = int(s.n_elements * s.nv * s.Nd)
+    rep = {"elements": int(s.n_elements), "unknowns": n, "arnoldi_steps": int(H.shape[1]),
+           "products": {"jvp": "exact J (forward-mode kernel)", "vjp": "exact J^T (adjoint kernel)",
+                        "fd": "central differences of F"}[op],
+           "targets": int(len(shifts)), "eigenvalue_estimates": int(len(lam)),
+           "spectral_radius_estimate": float(np.abs(lam).max()),
+           "reduced_spectral_radius_scaled": float(np.abs(lam_red).max() * fam.h_ref / h_min),
+           "arnoldi_s": t_arn, "eigen_s": t_eig, "reduced_spectrum_s": t_red,
+           "dt_opt_full_mesh": [float(x) for x in full.dt_opt],
+           "dt_opt_reduced_scaled": [float(x) for x in scaled_red],
+           "E": list(fam.E)}
+    _log(f"spectrum {wl['name']}: {H.shape[1]} Arnoldi steps on {n} unknowns in {t_arn:.2f} s, "
+         f"{len(lam)} estimates; dt_opt full {np.round(full.dt_opt, 6)} vs reduced {np.round(scaled_red, 6)}")
+    del s
+    torch.cuda.empty_cache()
+    return full, rep
+
+
+def full_mesh_family(wl, m=200):
+    """The workload's family optimised on the spectrum at its real mesh (spectrum_at_mesh), cached
+    as JSON next to the reduced-mesh one."""
+    from paper_2403_05144_amd import coeffs
+    path = os.path.join(ROOT, "paper_2403_05144_amd", "data", f"{wl['fam_name']}_fullmesh.json")
+    if os.path.exists(path):
+        return coeffs.Family.load(path), None
+    _log(f"building coefficient family {wl['fam_name']}_fullmesh (spectrum at the real mesh)")
+    fam, rep = spectrum_at_mesh(wl, m)
+    fam.save(path)
+    return fam, rep
+
+
+def run_spectrum(args):
+    """Spectrum estimation at the real meshes of the KH and TGV workloads (spectrum_at_mesh) and
+    the families optimised on them (stored next to the reduced-mesh families when missing).
+    Timed: the Arnoldi factorisation (device) and the eigenvalue extraction (host)."""
     out = {}
-    m = args.arnoldi_steps
-    for key, mk, op in (("kh_amr_l3-6", wl_kh_amr, "vjp"), ("tgv_ns_3d", wl_tgv, "fd")):
+    for key, mk in (("kh_amr_l3-6", wl_kh_amr), ("tgv_ns_3d", wl_tgv)):
         wl = mk()
-        fam = wl["fam"]
-        mesh = wl["mesh"]
-        m0 = pin.MeshDesc(mesh.dim, mesh.n_root, mesh.lo, mesh.hi, np.array(mesh.leaves, copy=True))
-        s = make_solver(wl, m0, fam, wl["mol"])
-        ic_leaf = lambda x: wl["ic"](x.transpose(1, 0, 2)).transpose(1, 0, 2).copy()
-        if wl.get("amr"):
-            a = wl["amr"]
-            AmrDriver(s, a["level_min"], a["level_max"], wl["mol"], a["refine_above"], a["coarsen_below"],
-                      a["interval"]).initial_mesh(ic_leaf, passes=3)
-        else:
-            s.set_state(ic_leaf(s.node_coords().cpu().numpy()))
-        # reduced spectrum of the family's own construction (its reduced mesh and element size)
-        red_mesh = (pin.uniform_mesh(2, (8, 8), (-1, -1), (1, 1), 0) if mesh.dim == 2 else
-                    pin.uniform_mesh(3, (2, 2, 2), (-np.pi,) * 3, (np.pi,) * 3, 0))
-        rs = make_solver(dict(wl, amr=None), red_mesh, fam, [0] * 8)
-        rs.set_state(ic_leaf(rs.node_coords().cpu().numpy()))
-        t0 = time.perf_counter()
-        lam_red = coeffs.fd_spectrum(rs, rs.get_state().cpu().numpy())
-        t_red = time.perf_counter() - t0
-        del rs
-        lv = s.leaves()[:, 0]
-        h_min = (mesh.hi[0] - mesh.lo[0]) / (mesh.n_root[0] << int(lv.max()))
-        u = s.u.clone()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        H = coeffs.arnoldi(s, u, m, op=op)
-        torch.cuda.synchronize()
-        t_arn = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        shifts = coeffs.hull_points(lam_red) * (fam.h_ref / h_min)
-        per = max(1, 1000 // max(1, len(shifts)))
-        ritz = np.linalg.eigvals(H[: H.shape[1], : H.shape[1]])
-        est = [ritz]
-        for sg in shifts:
-            th = coeffs.harmonic_ritz(H, sg)
-            est.append(th[np.argsort(np.abs(th - sg))[:per]])
-        lam = np.concatenate(est)
-        lam = lam[np.isfinite(lam) & (lam.imag >= 0)]
-        lam.real = np.minimum(lam.real, 0.0)
-        t_eig = time.perf_counter() - t0
-        full = coeffs.build_family(fam.order, fam.E, coeffs.hull_points(lam), h_ref=h_min)
-        scaled_red = [d * h_min / fam.h_ref for d in fam.dt_opt]
-        n = int(s.n_elements * s.nv * s.Nd)
-        out[key] = {"elements": int(s.n_elements), "unknowns": n, "arnoldi_steps": int(H.shape[1]),
-                    "products": "exact J^T (adjoint kernel)" if op == "vjp" else "central differences of F",
-                    "targets": int(len(shifts)), "eigenvalue_estimates": int(len(lam)),
-                    "spectral_radius_estimate": float(np.abs(lam).max()),
-                    "reduced_spectral_radius_scaled": float(np.abs(lam_red).max() * fam.h_ref / h_min),
-                    "arnoldi_s": t_arn, "eigen_s": t_eig, "reduced_spectrum_s": t_red,
-                    "dt_opt_full_mesh": [float(x) for x in full.dt_opt],
-                    "dt_opt_reduced_scaled": [float(x) for x in scaled_red],
-                    "E": list(fam.E)}
-        _log(f"spectrum {key}: {H.shape[1]} Arnoldi steps on {n} unknowns in {t_arn:.2f} s, "
-             f"{len(lam)} estimates; dt_opt full {np.round(full.dt_opt, 6)} vs reduced {np.round(scaled_red, 6)}")
-        del s
-        torch.cuda.empty_cache()
+        fam, rep = spectrum_at_mesh(wl, args.arnoldi_steps)
+        from paper_2403_05144_amd import coeffs
+        path = os.path.join(ROOT, "paper_2403_05144_amd", "data", f"{wl['fam_name']}_fullmesh.json")
+        if not os.path.exists(path):
+            fam.save(path)
+        rep["family_file"] = os.path.relpath(path, ROOT)
+        out[key] = rep
     k = out["tgv_ns_3d"]
     return {"metric": "DoF-updates/s & PID; P-ERK vs single-level RK wall time at equal error",
             "value": k["unknowns"] * k["arnoldi_steps"] / k["arnoldi_s"], "unit": "DoF-updates/s",
@@ -753,8 +783,11 @@ def _kinetic_energy(u_leaf, w_leaf, dim):
 
 def _integrate(wl, fam1, mol1, start, T_int, n_int, spi, flags=None, record=False, reps=1):
     """One run over [0, n_int T_int] with round(spi n_int) steps; the kinetic energy is sampled
-    at the end of every interval (its host time is left out of the wall time).  A static mesh
-    steps with one constant dt; an adaptive one gives interval k its share of the steps and
+    at the end of every interval (its host time is left out of the wall time).  Interval k takes
+    its share steps_k of the steps with dt = T_int / steps_k, so that every sample is taken at the
+    interval's end exactly (with one dt for the whole run and step counts that do not divide
+    evenly, the samples would sit up to a step away from the reference's, and the kinetic
+    energy's change over that offset would swamp the error being measured).  An adaptive mesh
     adapts between intervals (recording the flags from the GPU indicator, or replaying recorded
     ones).  Returns the wall time of the stepping and adaptation (graph replay path; the
     smallest of `reps` runs, repeated on the same solver for a static mesh and on a fresh one
@@ -767,7 +800,6 @@ def _integrate(wl, fam1, mol1, start, T_int, n_int, spi, flags=None, record=Fals
     m0 = wl["mesh"]
     amr = wl.get("amr")
     steps = _steps_per_interval(spi, n_int)
-    T = n_int * T_int
     s, walls, rec, ok, ke = None, [], [], True, []
     for rep in range(reps):
         if s is None or amr:
@@ -784,7 +816,7 @@ def _integrate(wl, fam1, mol1, start, T_int, n_int, spi, flags=None, record=Fals
         t0 = time.perf_counter()
         try:
             for k in range(n_int):
-                dt_k = T_int / steps[k] if amr else T / steps.sum()
+                dt_k = T_int / steps[k]
                 s.step(dt_k, int(steps[k]))
                 if rep == 0:
                     torch.cuda.synchronize()
@@ -986,7 +1018,10 @@ def compare_equal_error(wl, t_final=None, tol=0.05, ref_budget=6e8):
 
     def shrink(key, spi, run, target):
         """Smallest step count found (up from spi) at which every error of `key` is within
-        1 + tol of the target; its (spi, run) and the search history."""
+        1 + tol of the target; its (spi, run) and the search history.  The step count grows at
+        most 8-fold per try and to at most 64 times the start (an error that stalls against the
+        reference's own error would otherwise send it off); (None, None, history) if the target
+        is not reached."""
         g = lambda r: _excess(r["err"], target)
         lo, hi = (spi, run), None           # not accurate enough / accurate enough
         hist = [(spi, g(run))]
@@ -999,14 +1034,17 @@ def compare_equal_error(wl, t_final=None, tol=0.05, ref_budget=6e8):
                     slope = min(-0.5, (math.log(e2) - math.log(e1)) / (math.log(s2) - math.log(s1)))
                 else:
                     slope = -float(fam.order)
-                spi_new = lo[0] * (1.0 / g(lo[1])) ** (1.0 / slope)
+                spi_new = min(lo[0] * (1.0 / g(lo[1])) ** (1.0 / slope), 8.0 * lo[0])
                 spi_new = max(lo[0] + 1.0 / n_int, float(math.ceil(spi_new * n_int - 1e-9)) / n_int)
+                if spi_new > 64.0 * spi:
+                    break
             else:
                 spi_new = float(round(0.5 * (lo[0] + hi[0]) * n_int)) / n_int
                 if spi_new <= lo[0] or spi_new >= hi[0]:
                     break
             r_new = run_at(key, spi_new)
             hist.append((spi_new, g(r_new)))
+            _log(f"equal-error:   {key}: {r_new['steps']} steps, largest error/target {g(r_new):.3f}")
             if g(r_new) > 1 + tol:
                 lo = (spi_new, r_new)
             else:
@@ -1014,7 +1052,8 @@ def compare_equal_error(wl, t_final=None, tol=0.05, ref_budget=6e8):
                 if g(r_new) >= 1 - tol:
                     break
         if hi is None:
-            raise RuntimeError(f"equal-error: {key} did not reach the target errors")
+            _log(f"equal-error: {key} did not reach the target errors")
+            return None, None, hist
         return hi[0], hi[1], hist
 
     pairs = []
@@ -1025,8 +1064,16 @@ def compare_equal_error(wl, t_final=None, tol=0.05, ref_budget=6e8):
         for key in ("p_erk", other):
             spi0, run0 = info[key]["spi"], info[key]["run"]
             res[key] = shrink(key, spi0, run0, target)
+            if res[key][1] is None:
+                break
             _log(f"equal-error: {key} vs {other}: {res[key][1]['steps']} steps (from {run0['steps']}), largest "
                  f"error/target {_excess(res[key][1]['err'], target):.3f}")
+        if any(r[1] is None for r in res.values()):
+            miss = [k for k, r in res.items() if r[1] is None]
+            pairs.append({"comparator_scheme": names[other], "target_err": target, "p_erk_err": e_p,
+                          "comparator_err": e_c, "not_reached": miss,
+                          "search": {k: [(float(a), float(b)) for a, b in res[k][2]] for k in res}})
+            continue
         t_c = _integrate(wl, *schemes[other], start, T_int, n_int, info[other]["spi"], flags=flags,
                          reps=2 if amr else 5)
         wall_c_max = min(info[other]["run"]["wall"], t_c["wall"])
@@ -1210,6 +1257,12 @@ def run(args):
     from paper_2403_05144_amd.amr import AmrDriver
 
     wl = WORKLOADS[args.workload]()
+    if args.family == "full":
+        if "fam_name" not in wl:
+            raise SystemExit(f"--family full: workload {args.workload} has no full-mesh family")
+        fam_full, _ = full_mesh_family(wl)
+        wl = WORKLOADS[args.workload](fam=fam_full)
+        wl["family_source"] = "spectrum at the real mesh"
     mesh, deg, fam = wl["mesh"], wl["degree"], wl["fam"]
     leaves_init = np.array(mesh.leaves, copy=True)
     N = deg + 1
@@ -1373,7 +1426,10 @@ def run(args):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl["name"], "description": wl["desc"], "elements_start": int(leaves0.shape[0]),
                    "elements_end": int(n_elements_end), "degree": deg, "family_E": list(fam.E), "order": fam.order,
-                   "dt": dt, "cfl": wl.get("cfl"), "member_of_level": [int(m) for m in wl["mol"]],
+                   "dt": dt, "cfl": wl.get("cfl"), "family_dt_opt": [float(x) for x in fam.dt_opt],
+                   "family_h_ref": float(fam.h_ref),
+                   "family_spectrum": wl.get("family_source", "spectrum of the reduced mesh"),
+                   "member_of_level": [int(m) for m in wl["mol"]],
                    "E_of_level": [int(fam.E[m]) for m in wl["mol"]],
                    "adaptations_timed": n_adapt_timed, "episode_steps": episode,
                    "episode_restarts_timed": acc["episodes"], "restart_s_excluded": excluded},
@@ -1417,6 +1473,9 @@ def main():
     ap.add_argument("--sweep-max", type=int, default=0,
                     help="uniform_sweep: largest element count to run (0: all sizes)")
     ap.add_argument("--arnoldi-steps", type=int, default=200, help="spectrum: Arnoldi steps at the real mesh")
+    ap.add_argument("--family", default="reduced", choices=["reduced", "full"],
+                    help="tgv, kh_amr: coefficients optimised on the spectrum of the reduced mesh (default) or "
+                         "of the real mesh (Sec. 4.1 steps 3-4)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device once (calibration of HBM counters)")
     args = ap.parse_args()

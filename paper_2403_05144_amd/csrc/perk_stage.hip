@@ -251,12 +251,20 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   __shared__ NodeQ<DIM> s_q[EPB][ND];
   __shared__ double s_tr[EPB][NFC][NSUB][NV][NF];   // neighbour traces, later HLL fluxes in place
   __shared__ double s_tro[EO][LDS_OWN ? NFC : 1][NSO][LDS_OWN ? NV : 1][LDS_OWN ? NF : 1];  // coarse sides: own trace on every sub-face
-  __shared__ double s_pf[EPB][NP][NV];
+  // 3D Navier-Stokes: the neighbours' viscous traces on sub-faces 1.. of coarse sides are dead
+  // once phase C has formed the projected central face values, before phase D writes the pair
+  // fluxes: the two share storage (1440 doubles each at p=3), which brings the block from 50 KB
+  // of LDS to 38 KB, so that four blocks fit a CU instead of three
+  constexpr bool ALIAS = VISC && !LDS_OWN;
+  constexpr int NPF = NP * NV, NTV1 = NFC * (NSUB - 1) * NV * NF;
+  constexpr int NX = ALIAS && NTV1 > NPF ? NTV1 : NPF;
+  __shared__ double s_pf[EPB][NX];   // pair flux w, variable v at [w NV + v]
+  auto tv1 = [](int f, int sub, int v, int j) { return ((f * (NSUB - 1) + sub - 1) * NV + v) * NF + j; };
   __shared__ int s_fk[EPB][NFC];
   __shared__ int s_fn[EPB][NFC][4];
   // BR1: own viscous flux at every node (2D) and the neighbours' viscous face traces
   __shared__ double s_fv[FVL ? EPB : 1][FVL ? DIM : 1][FVL ? NV : 1][FVL ? ND : 1];
-  __shared__ double s_trv[VISC ? EPB : 1][VISC ? NFC : 1][VISC ? NSUB : 1][VISC ? NV : 1][VISC ? NF : 1];
+  __shared__ double s_trv[VISC ? EPB : 1][VISC ? NFC : 1][VISC && !ALIAS ? NSUB : 1][VISC ? NV : 1][VISC ? NF : 1];
   // the derivative matrix: the epilogue reads row `pos` of the lane's node, which from kernel
   // argument memory would be a gather with a memory round after the last barrier.  s_D2 holds
   // 2 D with a zero diagonal (the flux-differencing weights, no pair (i, i)), s_D plain D (BR1)
@@ -363,7 +371,11 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       const int src = src_of(a, member_of_slot(m, nb));
       const int nn = face_node<DIM, N>(d, 1 - side, j);
       s_tr[le][f][sub][v][j] = stage_value(a, src, ((int64_t)v * ld + nb) * ND + nn);
-      if (VISC) s_trv[le][f][sub][v][j] = a.Fv[(((int64_t)d * NV + v) * ld + nb) * ND + nn];
+      if (VISC) {
+        const double fvn = a.Fv[(((int64_t)d * NV + v) * ld + nb) * ND + nn];
+        if (ALIAS && sub > 0) s_pf[le][tv1(f, sub, v, j)] = fvn;
+        else s_trv[le][f][ALIAS ? 0 : sub][v][j] = fvn;
+      }
     }
     if (FVL) {
       for (int w = lane; w < DIM * NV * ND; w += T) {
@@ -404,6 +416,8 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       else if (VISC) s_D[t - N * N] = dv;
     }
   }
+  constexpr int NCV = ALIAS ? (NFC * NV * NF + T - 1) / T : 1;
+  double cv_hold[NCV];
   if (act) {
     // Node quantities.  When the element's nodes fill whole waves and the block has waves to
     // spare (3D p=3: 64 nodes, 7 waves), the two logarithms of a node go to two waves: the first
@@ -466,7 +480,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         }
       }
       s_tr[le][f][1][v][j] = val;
-      if (VISC) {
+      if (VISC && !ALIAS) {
         double vv = 0.0;
         if (DIM == 2) {
 #pragma unroll
@@ -487,7 +501,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
     // coarse sides: own trace interpolated to every sub-face (2D: one item per lane here
     // instead of a whole interpolation per flux lane in phase D) and, for BR1, the central
     // average of the interpolated own viscous flux with the fine neighbour's
-    for (int w = lane_c; (LDS_OWN || VISC) && w < NFC * NSUB * NV * NF; w += T) {
+    for (int w = lane_c; (LDS_OWN || (VISC && !ALIAS)) && w < NFC * NSUB * NV * NF; w += T) {
       const int j = w % NF;
       const int v = (w / NF) % NV;
       const int sub = (w / (NF * NV)) % NSUB;
@@ -524,11 +538,66 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       if (LDS_OWN) s_tro[le][f][sub][v][j] = x;
       if (VISC) s_trv[le][f][sub][v][j] = 0.5 * (xv + s_trv[le][f][sub][v][j]);
     }
+    if constexpr (ALIAS) {
+      // BR1 central viscous values on the element's own face nodes: conforming faces
+      // (own + neighbour)/2, fine sides with the coarse trace interpolated, coarse sides
+      // sum_m R_m (P_m own + nb_m)/2 = (own + sum_m R_m nb_m)/2 (sum_m R_m P_m = I)
+#pragma unroll
+      for (int q = 0; q < NCV; ++q) {
+        const int w = lane_c + q * T;
+        cv_hold[q] = 0.0;
+        if (w >= NFC * NV * NF) continue;
+        const int j = w % NF, v = (w / NF) % NV, f = w / (NF * NV);
+        const int32_t pk = s_fk[le][f];
+        const int kind = face_kind(pk);
+        const int d = f >> 1, side = f & 1;
+        const int ja = j % N, jb = j / N;
+        double nbv = 0.0;
+        if (kind == kConforming) {
+          nbv = s_trv[le][f][0][v][j];
+        } else if (kind == kFineSide) {
+          const int s0 = face_sub0(pk), s1 = face_sub1(pk);
+#pragma unroll
+          for (int kb = 0; kb < N; ++kb) {
+            double row = 0.0;
+#pragma unroll
+            for (int ka = 0; ka < N; ++ka) row += Pm(s0, ja * N + ka) * s_trv[le][f][0][v][ka + N * kb];
+            nbv += Pm(s1, jb * N + kb) * row;
+          }
+        } else {
+#pragma unroll 1
+          for (int ms = 0; ms < NSUB; ++ms) {
+            const int m0 = ms & 1, m1 = (ms >> 1) & 1;
+#pragma unroll
+            for (int kb = 0; kb < N; ++kb) {
+              double row = 0.0;
+#pragma unroll
+              for (int ka = 0; ka < N; ++ka) {
+                const int k = ka + N * kb;
+                row += Rm(m0, ja * N + ka) * (ms == 0 ? s_trv[le][f][0][v][k] : s_pf[le][tv1(f, ms, v, k)]);
+              }
+              nbv += Rm(m1, jb * N + kb) * row;
+            }
+          }
+        }
+        cv_hold[q] = 0.5 * (fv_own(d, v, face_node<DIM, N>(d, side, j)) + nbv);
+      }
+    }
   }
   __syncthreads();
 
   // ---- D: fluxes.  Pairs first, then face nodes sub-face-major (sub 0 of every face first).
   if (act) {
+    if constexpr (ALIAS) {
+      // the central viscous face values of phase C (the sub-face traces they replace are dead:
+      // their storage takes the pair fluxes now)
+      const int lane_c = (lane + (ND % 64 == 0 && T >= 2 * ND ? 2 * ND : 64)) % T;
+#pragma unroll
+      for (int q = 0; q < NCV; ++q) {
+        const int w = lane_c + q * T;
+        if (w < NFC * NV * NF) s_trv[le][w / (NF * NV)][0][(w / NF) % NV][w % NF] = cv_hold[q];
+      }
+    }
     // pair fluxes (w in [0, NP)) and face fluxes (r in [0, NFI)); with the split on, each on
     // lanes of its own ([0, PLN) and [PLN, T)), else one loop over both
     constexpr int NFI = NSUB * NFC * NF;
@@ -541,7 +610,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       ec_flux<DIM>(s_q[le][node_on_line<DIM, N>(d, line, pa)], s_q[le][node_on_line<DIM, N>(d, line, pb)], d,
                    inv_gm1, f);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) s_pf[le][w][v] = f[v];
+      for (int v = 0; v < NV; ++v) s_pf[le][w * NV + v] = f[v];
     };
     auto face_flux = [&](int r) {
       const int j = r % NF;
@@ -598,7 +667,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       hll_flux<DIM>(uL, uR, d, gamma, fl);
 #pragma unroll
       for (int v = 0; v < NV; ++v) s_tr[le][f][sub][v][j] = fl[v];
-      if (VISC && kind != kCoarseSide) {
+      if (VISC && !ALIAS && kind != kCoarseSide) {
         // BR1 central viscous flux on this face node: 1/2 (own + neighbour); coarse sides
         // were averaged in phase C
 #pragma unroll
@@ -667,11 +736,11 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
           for (int ka = 0; ka < N; ++ka) {
             const double r = Rm(m0, ia * N + ka);
             row += r * s_tr[le][f][ms][v][ka + N * kb];
-            if (VISC) rowv += r * s_trv[le][f][ms][v][ka + N * kb];
+            if (VISC && !ALIAS) rowv += r * s_trv[le][f][ms][v][ka + N * kb];
           }
           const double rb = Rm(m1, ib * N + kb);
           fs += rb * row;
-          if (VISC) fsv += rb * rowv;
+          if (VISC && !ALIAS) fsv += rb * rowv;
         }
       }
     }
@@ -692,7 +761,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       const int w = lane + k * T;
       const int i = w % NF, v = (w / NF) % NV, f = w / (NF * NV);
       s_tr[le][f][0][v][i] = e0_fs[k];
-      if (VISC) s_trv[le][f][0][v][i] = e0_fsv[k];
+      if (VISC && !ALIAS) s_trv[le][f][0][v][i] = e0_fsv[k];
     }
   }
   __syncthreads();
@@ -718,7 +787,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
 #pragma unroll
       for (int mm = 0; mm < N; ++mm) {
         const int pi = (int)((PairNodes<N>::kIndexOf >> (4 * (pos * N + mm))) & 15);
-        acc += s_D2[pos * N + mm] * s_pf[le][base + pi][v];
+        acc += s_D2[pos * N + mm] * s_pf[le][(base + pi) * NV + v];
       }
       const int f = 2 * d + (pos == N - 1 ? 1 : 0);
       const int fi = face_index<DIM, N>(nd, d);
@@ -862,7 +931,6 @@ __global__ __launch_bounds__((GKc<DIM, N>::T), (GKc<DIM, N>::WPS)) void k_grad(S
   auto s_tr = reinterpret_cast<double (*)[NSUB][NW][NF]>(s_trq);
   auto s_q = reinterpret_cast<double (*)[NW][ND]>(s_trq);
   __shared__ int s_fk[NFC];
-  __shared__ int s_fn[NFC][4];
   // D, P_0, P_1, R_0, R_1 from the device copy (lane-indexed reads from kernel-argument memory
   // would each be a slow memory round)
   __shared__ double s_op[5][N * N];
@@ -873,8 +941,37 @@ __global__ __launch_bounds__((GKc<DIM, N>::T), (GKc<DIM, N>::WPS)) void k_grad(S
   const double gamma = ph.gamma;
   const int my_src = src_of(a, member_of_slot(m, e));
   const int lev = m.lev[e];
+  // own values and neighbour traces in one memory round: each trace lane reads its face's kind
+  // and neighbour slot itself and issues the trace loads right behind them, before the own
+  // values are converted (through LDS they would wait for a barrier: a second round)
+  constexpr int NTRI = NSUB * NFC * NF, NTR = (NTRI + T - 1) / T;
+  int tr_nb[NTR], tr_pk[NTR];
+#pragma unroll
+  for (int q = 0; q < NTR; ++q) {
+    const int it = lane + q * T;
+    tr_pk[q] = -1;
+    tr_nb[q] = 0;
+    if (it < NTRI) {
+      const int f = (it / NF) % NFC, sub = it / (NF * NFC);
+      tr_pk[q] = m.fk[(int64_t)e * NFC + f];
+      tr_nb[q] = m.fn[((int64_t)e * NFC + f) * 4 + sub];
+    }
+  }
   if (lane < NFC) s_fk[lane] = m.fk[(int64_t)e * NFC + lane];
-  if (lane < NFC * 4) s_fn[lane / 4][lane % 4] = m.fn[(int64_t)e * NFC * 4 + lane];
+  double tu[NTR][NV];
+  bool tr_on[NTR];
+#pragma unroll
+  for (int q = 0; q < NTR; ++q) {
+    const int it = lane + q * T;
+    const int j = it % NF, f = (it / NF) % NFC, sub = it / (NF * NFC);
+    tr_on[q] = it < NTRI && (sub == 0 || face_kind(tr_pk[q]) == kCoarseSide);
+    if (!tr_on[q]) continue;
+    const int nb = tr_nb[q];
+    const int src = src_of(a, member_of_slot(m, nb));
+    const int nn = face_node<DIM, N>(f >> 1, 1 - (f & 1), j);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) tu[q][v] = stage_value(a, src, ((int64_t)v * ld + nb) * ND + nn);
+  }
   for (int nd = lane; nd < ND; nd += T) {
     double u[NV], w[NW];
 #pragma unroll
@@ -884,22 +981,14 @@ __global__ __launch_bounds__((GKc<DIM, N>::T), (GKc<DIM, N>::WPS)) void k_grad(S
     for (int k = 0; k < NW; ++k) s_w[k][nd] = w[k];
   }
   for (int t = lane; t < 5 * N * N; t += T) s_op[t / (N * N)][t % (N * N)] = op.dD[N * N + t];
-  __syncthreads();
   // neighbour traces, converted to w at the trace node
-  for (int it = lane; it < NSUB * NFC * NF; it += T) {
-    const int j = it % NF;
-    const int f = (it / NF) % NFC;
-    const int sub = it / (NF * NFC);
-    const int kind = face_kind(s_fk[f]);
-    if (sub > 0 && kind != kCoarseSide) continue;
-    const int nb = s_fn[f][sub];
-    const int d = f >> 1, side = f & 1;
-    const int src = src_of(a, member_of_slot(m, nb));
-    const int nn = face_node<DIM, N>(d, 1 - side, j);
-    double u[NV], w[NW];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) u[v] = stage_value(a, src, ((int64_t)v * ld + nb) * ND + nn);
-    grad_vars<DIM>(u, gamma, w);
+  for (int q = 0; q < NTR; ++q) {
+    if (!tr_on[q]) continue;
+    const int it = lane + q * T;
+    const int j = it % NF, f = (it / NF) % NFC, sub = it / (NF * NFC);
+    double w[NW];
+    grad_vars<DIM>(tu[q], gamma, w);
 #pragma unroll
     for (int k = 0; k < NW; ++k) s_tr[f][sub][k][j] = w[k];
   }
@@ -1016,27 +1105,26 @@ __global__ __launch_bounds__((GKc<DIM, N>::T), (GKc<DIM, N>::WPS)) void k_grad(S
     if (it < NQ) s_q[it / (NW * ND)][(it / ND) % NW][it % ND] = qv[q];
   }
   __syncthreads();
-  // viscous flux at every node, every direction
-  for (int nd = lane; nd < ND; nd += T) {
+  // viscous flux at every node, one direction per item (DIM ND items: 3D p=3 uses three of
+  // the four waves instead of one)
+  for (int it = lane; it < DIM * ND; it += T) {
+    const int nd = it % ND, d = it / ND;
     double divv = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) divv += s_q[k][k][nd];
+    double f[NV];
+    f[0] = 0.0;
+    double en = 0.0;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      double f[NV];
-      f[0] = 0.0;
-      double en = 0.0;
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) {
-        double tau = ph.mu * (s_q[d][k][nd] + s_q[k][d][nd]);
-        if (k == d) tau -= 2.0 / 3.0 * ph.mu * divv;
-        f[1 + k] = tau;
-        en += tau * s_w[k][nd];
-      }
-      f[DIM + 1] = en + ph.kappa * s_q[d][DIM][nd];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) a.Fv[(((int64_t)d * NV + v) * ld + e) * ND + nd] = f[v];
+    for (int k = 0; k < DIM; ++k) {
+      double tau = ph.mu * (s_q[d][k][nd] + s_q[k][d][nd]);
+      if (k == d) tau -= 2.0 / 3.0 * ph.mu * divv;
+      f[1 + k] = tau;
+      en += tau * s_w[k][nd];
     }
+    f[DIM + 1] = en + ph.kappa * s_q[d][DIM][nd];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a.Fv[(((int64_t)d * NV + v) * ld + e) * ND + nd] = f[v];
   }
 }
 

@@ -824,14 +824,14 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
 }
 
 // Waves per SIMD the register allocation must allow.  3D p=3 blocks (7 waves; 34 KB of LDS for
-// Euler, 50 KB for Navier-Stokes) at 80 VGPRs (6 waves per SIMD, a 20-byte spill) instead of
-// 86-87 leave room for a third block per CU: measured 10 % (Euler, uniform meshes) and 10 %
-// (Navier-Stokes, the Taylor-Green mesh) less time per element-stage.  The one-wave 2D p=3 body
+// Euler, 38 KB for Navier-Stokes) at 72 VGPRs (7 waves per SIMD, no spill since the element
+// index is uniform) fit four blocks per CU; the step from three to four blocks took the
+// Taylor-Green launch from 90 to 72.5 us (and from two to three, 105 to 90).  The one-wave 2D p=3 body
 // (large launches) at 96 VGPRs (5 waves, a 20-byte spill) instead of 102-106: 2-6 % less on
 // uniform 2D meshes of 128^2-1024^2 elements (6 waves spilled 72-88 bytes and ran slower).
 template <int DIM, int N, bool VISC, bool SPLIT>
 constexpr int stage_waves_per_simd() {
-  if (DIM == 3 && N == 4) return 6;
+  if (DIM == 3 && N == 4) return 7;
   if (DIM == 2 && N == 4 && !SPLIT) return 5;
   return SK<DIM, N, SPLIT>::MINW;
 }
@@ -903,9 +903,10 @@ struct GKc {
   using g = G<DIM, N>;
   static constexpr int ND = g::ND, NF = g::NF, NFC = g::NFC, NV = g::NV, NSUB = g::NSUB, NW = DIM + 1;
   static constexpr int T = DIM == 2 ? 64 : 256;
-  // 3D p=3: at most 72 VGPRs (7 waves per SIMD); with the 15 KB of LDS below, 37 -> 34.5 us per
-  // Taylor-Green launch against 20.7 KB (8 waves per SIMD measured the same, with a spill)
-  static constexpr int WPS = DIM == 3 && N == 4 ? 7 : 1;
+  // 3D p=3: 256 lanes, at most 64 VGPRs (8 waves per SIMD, without a spill since the trace
+  // loads issue together with the own values): eight 15 KB blocks per CU, 36.2 -> 34.7 us per
+  // Taylor-Green launch against seven at 72 VGPRs (128-lane blocks: 39 us)
+  static constexpr int WPS = DIM == 3 && N == 4 ? 8 : 1;
 };
 
 template <int DIM>

@@ -23,6 +23,14 @@
 //    truncation error at mortars.
 //  * BR1 viscous terms (Bassi-Rebay, cited in Sec. 7.1): gradients of w = (v, T) with central
 //    face values, viscous flux, divergence with the central average of the viscous flux.
+//  * Subcell shock capturing (Hennemann, Rueda-Ramirez, Hindenlang, Gassner 2021, which the
+//    paper uses for its inviscid runs: Sec. 4.1 and Sec. 7.2.1), optional, Euler: per element a
+//    blending factor alpha from the modal energy of the density in the L2-orthonormal Legendre
+//    basis (the share of the highest modes, E = max(E_1, E_2)), alpha = 1/(1 + exp(-s/T (E - T)))
+//    with T = a 10^(-c (p+1)^(1/4)), s = ln((1 - 1e-4)/1e-4), set to 0 below alpha_min and capped
+//    at alpha_max; the volume term becomes (1 - alpha) [flux differencing] + alpha [first-order
+//    finite volumes on the LGL subcells: (F_{i+1/2} - F_{i-1/2}) / w_i, F = the HLL flux of the
+//    neighbouring nodes, F = 0 at the element's own faces, whose flux the surface term brings].
 //  * Partitioned RK step (eq. PartitionedRKSystem): K_i^(r) = I^(r) F(U_n + dt sum_j sum_k
 //    a_ij^(k) K_j^(k)), U_{n+1} = U_n + dt sum_i b_i K_i.  Evaluated densely: F on the whole
 //    mesh at every stage, every element combined with its own member's Butcher row.
@@ -30,6 +38,7 @@
 // Layout of a state array: u[(e * nv + v) * Nd + node], node = i + N j (+ N^2 k), element
 // order = order of the leaf list passed in.  Variables: rho, rho v_1..rho v_d, E.
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdint>
@@ -355,6 +364,18 @@ struct Solver {
   // (B_m)_ij = int_{-1}^{1} l_i(xi^m(s)) l_j(s) ds
   std::vector<double> Rm[2];
 
+  // subcell shock capturing (see the header); off unless set
+  struct ShockCapturing {
+    bool on = false;
+    double alpha_max = 0.5, alpha_min = 0.001;
+    double a = 0.5, c = 1.8;
+    double alpha_fixed = -1.0;   // >= 0: every element takes this blending factor (checks)
+  } sc;
+  // [k*N + i]: coefficient of the k-th L2-orthonormal Legendre polynomial sqrt(k + 1/2) P_k of the
+  // interpolant of nodal values f_i: sum_i Vinv[k][i] f_i (the inverse of the Vandermonde matrix
+  // V[i][k] = sqrt(k + 1/2) P_k(x_i))
+  std::vector<double> Vinv;
+
   int ncell(int level, int d) const { return nroot[d] << level; }
   double h(int e, int d) const { return (hi[d] - lo[d]) / ncell(leaves[e][0], d); }
 
@@ -396,6 +417,18 @@ struct Solver {
             }
         Rm[m] = dense_solve(M, B, N, N);
       }
+    }
+    {
+      std::vector<double> V(N * N), I(N * N, 0.0);
+      for (int i = 0; i < N; ++i) {
+        for (int k = 0; k < N; ++k) {
+          double P, dP;
+          legendre_and_derivative(k, x[i], P, dP);
+          V[i * N + k] = std::sqrt(k + 0.5) * P;
+        }
+        I[i * N + i] = 1.0;
+      }
+      Vinv = dense_solve(V, I, N, N);
     }
     index.clear();
     for (size_t e = 0; e < leaves.size(); ++e) {
@@ -574,13 +607,58 @@ struct Solver {
     return dim == 2 ? ijk[0] + N * ijk[1] : ijk[0] + N * ijk[1] + N * N * ijk[2];
   }
 
+  // share of the highest modes in the density's modal energy on element e:
+  // E = max((total - clip_1) / total, (clip_1 - clip_2) / clip_1), clip_k the energy of the modes
+  // whose degree in every direction is at most p - k
+  double sc_energy(const double* u, size_t e) const {
+    const int p = N - 1;
+    const int nc = dim == 3 ? N : 1;
+    double total = 0.0, clip1 = 0.0, clip2 = 0.0;
+    for (int c3 = 0; c3 < nc; ++c3)
+      for (int b = 0; b < N; ++b)
+        for (int a = 0; a < N; ++a) {
+          double m = 0.0;
+          for (int k = 0; k < nc; ++k)
+            for (int j = 0; j < N; ++j)
+              for (int i = 0; i < N; ++i) {
+                const double vk = dim == 3 ? Vinv[c3 * N + k] : 1.0;
+                const int nd = dim == 3 ? i + N * j + N * N * k : i + N * j;
+                m += Vinv[a * N + i] * Vinv[b * N + j] * vk * u[(e * nv + 0) * Nd + nd];
+              }
+          const double m2 = m * m;
+          const int deg = std::max(a, std::max(b, c3));
+          total += m2;
+          if (deg <= p - 1) clip1 += m2;
+          if (deg <= p - 2) clip2 += m2;
+        }
+    const double e1 = total > 0.0 ? (total - clip1) / total : 0.0;
+    const double e2 = clip1 > 0.0 ? (clip1 - clip2) / clip1 : 0.0;
+    return std::max(e1, e2);
+  }
+
+  double sc_alpha_of_energy(double E) const {
+    const double T = sc.a * std::pow(10.0, -sc.c * std::pow((double)N, 0.25));
+    const double s = std::log((1.0 - 1e-4) / 1e-4);
+    double alpha = 1.0 / (1.0 + std::exp(-s / T * (E - T)));
+    if (alpha < sc.alpha_min) return 0.0;
+    return std::min(alpha, sc.alpha_max);
+  }
+
+  double sc_alpha(const double* u, size_t e) const {
+    if (!sc.on) return 0.0;
+    if (sc.alpha_fixed >= 0.0) return sc.alpha_fixed;
+    return sc_alpha_of_energy(sc_energy(u, e));
+  }
+
   // inviscid part of du = F(u): volume flux differencing and surface flux (scalar type T:
-  // double, or Dual for the tangent of the Euler operator)
+  // double, or Dual for the tangent of the Euler operator, which has no shock capturing)
   template <class T>
   void rhs_inviscid(const T* u, T* du) const {
     const size_t ne = leaves.size();
     for (size_t q = 0; q < ne * nv * Nd; ++q) du[q] = 0.0;
     for (size_t e = 0; e < ne; ++e) {
+      double alpha = 0.0;
+      if constexpr (std::is_same<T, double>::value) alpha = sc_alpha(u, e);
       for (int d = 0; d < dim; ++d) {
         double J = 2.0 / h((int)e, d);
         for (int nd = 0; nd < Nd; ++nd) {
@@ -596,7 +674,24 @@ struct Solver {
             int n2 = node_of(jk);
             for (int v = 0; v < nv; ++v) um[v] = u[(e * nv + v) * Nd + n2];
             ec_flux(ph, ui, um, d, f);
-            for (int v = 0; v < nv; ++v) du[(e * nv + v) * Nd + nd] -= J * 2.0 * D[a * N + m] * f[v];
+            for (int v = 0; v < nv; ++v) du[(e * nv + v) * Nd + nd] -= J * (1.0 - alpha) * 2.0 * D[a * N + m] * f[v];
+          }
+          if (alpha > 0.0) {
+            // first-order finite volumes on the LGL subcells: subcell interfaces between the
+            // node and its neighbours along d; none at the element's own faces
+            T fp[5], fm[5];
+            for (int v = 0; v < nv; ++v) fp[v] = fm[v] = 0.0;
+            for (int side = 0; side < 2; ++side) {
+              const int m = side ? a + 1 : a - 1;
+              if (m < 0 || m >= N) continue;
+              int jk[3] = {ijk[0], ijk[1], ijk[2]};
+              jk[d] = m;
+              const int n2 = node_of(jk);
+              for (int v = 0; v < nv; ++v) um[v] = u[(e * nv + v) * Nd + n2];
+              if (side) hll_flux(ph, ui, um, d, fp);
+              else hll_flux(ph, um, ui, d, fm);
+            }
+            for (int v = 0; v < nv; ++v) du[(e * nv + v) * Nd + nd] -= J * alpha * (fp[v] - fm[v]) / w[a];
           }
         }
         for (int s = 0; s < 2; ++s) {
@@ -949,12 +1044,45 @@ bool check_euler(const Solver* s) {
     g_err = "tangent and adjoint: Euler operator only";
     return false;
   }
+  if (s->sc.on) {
+    g_err = "tangent and adjoint: not with shock capturing";
+    return false;
+  }
   return true;
 }
 
 }  // namespace
 
 extern "C" {
+
+// Subcell shock capturing: on != 0 switches it on with the given parameters; alpha_fixed >= 0
+// gives every element that blending factor instead of the indicator's (checks).  Euler only.
+int orc_set_shock_capturing(void* h, int on, double alpha_max, double alpha_min, double alpha_fixed) {
+  Solver* s = static_cast<Solver*>(h);
+  if (on && s->ph.viscous) {
+    g_err = "shock capturing: Euler only";
+    return -1;
+  }
+  s->sc.on = on != 0;
+  s->sc.alpha_max = alpha_max;
+  s->sc.alpha_min = alpha_min;
+  s->sc.alpha_fixed = alpha_fixed;
+  return 0;
+}
+
+// Per element: the modal energy share E of the density and the blending factor alpha of the
+// current parameters (alpha regardless of whether shock capturing is on); Vinv [N*N] if not null.
+int orc_sc_indicator(void* h, const double* u, double* energy, double* alpha, double* vinv) {
+  Solver* s = static_cast<Solver*>(h);
+  for (size_t e = 0; e < s->leaves.size(); ++e) {
+    const double E = s->sc_energy(u, e);
+    if (energy) energy[e] = E;
+    if (alpha) alpha[e] = s->sc.alpha_fixed >= 0.0 ? s->sc.alpha_fixed : s->sc_alpha_of_energy(E);
+  }
+  if (vinv)
+    for (int i = 0; i < s->N * s->N; ++i) vinv[i] = s->Vinv[i];
+  return 0;
+}
 
 // f = F(u) and t = F'(u) du (Euler)
 int orc_rhs_jvp(void* h, const double* u, const double* du, double* f, double* t) {

@@ -67,6 +67,9 @@ def lib():
         L.orc_prk_step_vjp.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                        dp, dp, ip, dp]
         L.orc_hll_branch_counts.argtypes = [ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
+        L.orc_set_shock_capturing.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double]
+        L.orc_sc_indicator.argtypes = [ctypes.c_void_p, dp, dp, dp, dp]
         L.orc_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -158,6 +161,20 @@ class Oracle:
         lev = self.mesh.leaves[:, 0]
         return np.array([[(self.mesh.hi[d] - self.mesh.lo[d]) / (self.mesh.n_root[d] << int(l))
                           for d in range(self.dim)] for l in lev])
+
+    def set_shock_capturing(self, on=True, alpha_max=0.5, alpha_min=0.001, alpha_fixed=None):
+        """Subcell shock capturing (Hennemann et al., used by the paper for its inviscid runs) with
+        the blending factor of the density indicator, or alpha_fixed on every element."""
+        if lib().orc_set_shock_capturing(self._h, int(bool(on)), float(alpha_max), float(alpha_min),
+                                         -1.0 if alpha_fixed is None else float(alpha_fixed)) != 0:
+            raise ValueError(lib().orc_last_error().decode())
+
+    def sc_indicator(self, u):
+        """(E, alpha) per element for state u, and the modal transform Vinv [N, N]."""
+        u = np.ascontiguousarray(u, float).reshape(self.shape)
+        E, a, V = np.zeros(self.n_elements), np.zeros(self.n_elements), np.zeros(self.N * self.N)
+        lib().orc_sc_indicator(self._h, _dp(u), _dp(E), _dp(a), _dp(V))
+        return E, a, V.reshape(self.N, self.N)
 
     def rhs(self, u):
         u = np.ascontiguousarray(u, float).reshape(self.shape)

@@ -299,9 +299,35 @@ pe_status pe_max_dt_noalloc(pe_ctx* ctx, double cfl, double* dt_dev, double* bet
  *     of the element's LGL nodes (three consecutive nodal values as they are; 0 where the
  *     denominator vanishes), q the primitive variable `variable` (0 rho, 1..dim the velocity
  *     components, dim+1 the pressure).
- * PE_EINVAL for another kind, a variable outside [0, dim+1] or f_wave < 0. */
-typedef enum { PE_INDICATOR_DENSITY_GRADIENT = 0, PE_INDICATOR_LOHNER = 1 } pe_indicator;
+ *   PE_INDICATOR_HENNEMANN_GASSNER (the shock-capturing indicator, which the paper's
+ *     Kelvin-Helmholtz run of Sec. 7.2.1 also uses for refinement; 2D, variable 0 = density only):
+ *     1 / (1 + exp(-(s/T) (E - T))), E the energy share of the density's top modes as in
+ *     pe_set_shock_capturing, without the cut-off and the cap; f_wave is ignored.
+ * PE_EINVAL for another kind, a variable outside [0, dim+1] (HENNEMANN_GASSNER: not 0) or
+ * f_wave < 0; PE_EUNSUPPORTED for HENNEMANN_GASSNER in 3D. */
+typedef enum {
+  PE_INDICATOR_DENSITY_GRADIENT = 0,
+  PE_INDICATOR_LOHNER = 1,
+  PE_INDICATOR_HENNEMANN_GASSNER = 2
+} pe_indicator;
 pe_status pe_set_amr_indicator(pe_ctx* ctx, int kind, int variable, double f_wave);
+
+/* Subcell shock capturing (Hennemann, Rueda-Ramirez, Hindenlang and Gassner; the paper runs its
+ * inviscid Kelvin-Helmholtz case with it, Sec. 4.1 and 7.2.1), 2D Euler.  At every right-hand-side
+ * evaluation each element gets a blending factor alpha from its own stage value: with m_ab the
+ * density's coefficients in the L2-orthonormal Legendre basis (V^-1 of the Vandermonde matrix of
+ * sqrt(k + 1/2) P_k at the LGL nodes, applied per direction), all = sum m_ab^2, clip_k = the sum
+ * over max(a, b) <= p - k, E = max((all - clip_1)/all, (clip_1 - clip_2)/clip_1),
+ * T = 0.5 10^(-1.8 (p+1)^(1/4)), s = ln((1 - 1e-4)/1e-4): alpha = 1/(1 + exp(-(s/T)(E - T))),
+ * 0 below alpha_min, at most alpha_max.  The volume term becomes (1 - alpha) times the
+ * flux-differencing one plus alpha times first-order finite volumes on the LGL subcells:
+ * (F_{i+1/2} - F_{i-1/2}) / w_i along each coordinate line, F the HLL flux of the two
+ * neighbouring nodes, no subcell flux at the element's faces (the surface term is unchanged).
+ * on = 0 switches it off (parameters ignored).  The next pe_step captures its graph again.
+ * PE_EUNSUPPORTED for 3D, Navier-Stokes or an alternative stage pattern; PE_EINVAL unless
+ * 0 <= alpha_min <= alpha_max <= 1.  While on, the tangent, the adjoint and the batched form
+ * refuse the context (PE_EUNSUPPORTED). */
+pe_status pe_set_shock_capturing(pe_ctx* ctx, int on, double alpha_max, double alpha_min);
 
 /* Refinement indicator per leaf (the one pe_set_amr_indicator selected; the density gradient by
  * default).  Written to eta_leaf_host [n_elements] in leaf order; synchronises `stream`.  (The

@@ -60,6 +60,9 @@ struct pe_ctx {
   double rule_margin = 1.0;
   // refinement indicator of pe_amr_indicator / pe_amr_cycle
   int ind_kind = PE_INDICATOR_DENSITY_GRADIENT, ind_var = 1;
+  // subcell shock capturing (2D Euler)
+  bool sc_on = false;
+  double sc_amax = 0.5, sc_amin = 0.001;
   double ind_fwave = 0.2;
   // binding
   bool bound = false;
@@ -73,7 +76,7 @@ struct pe_ctx {
   int32_t* d_plan = nullptr;            // AMR projection plan [capacity][10]
   double* d_eta = nullptr;              // AMR indicator per leaf; wave-speed bound per slot
   double* d_beta = nullptr;             // [kMaxLevels] largest (p+1)(|v_d|+c)/h_d per level
-  double* d_dmat = nullptr;             // [6][N^2] operator tables (Ops::dD)
+  double* d_dmat = nullptr;             // [7][N^2] operator tables (Ops::dD)
   unsigned long long* d_counter = nullptr;   // [R] folded totals
   int32_t* d_evals = nullptr;               // [capacity] per-slot evaluations since the last fold
   // partition
@@ -214,6 +217,36 @@ void make_ops(int N, Ops& op) {
     op.w[j] = w[j];
     op.iw[j] = 1.0 / w[j];
     op.x[j] = x[j];
+  }
+  // modal transform for the shock-capturing indicator: Vinv = V^-1, V[i][k] = sqrt(k + 1/2)
+  // P_k(x_i) (L2-orthonormal Legendre polynomials at the nodes), by Gauss-Jordan elimination
+  {
+    double V[kMaxN][2 * kMaxN];
+    for (int i = 0; i < N; ++i)
+      for (int c = 0; c < 2 * N; ++c) {
+        if (c < N) {
+          double P, dP;
+          legendre(c, x[i], P, dP);
+          V[i][c] = std::sqrt(c + 0.5) * P;
+        } else {
+          V[i][c] = c - N == i ? 1.0 : 0.0;
+        }
+      }
+    for (int c = 0; c < N; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < N; ++r)
+        if (std::fabs(V[r][c]) > std::fabs(V[piv][c])) piv = r;
+      for (int k = 0; k < 2 * N; ++k) std::swap(V[c][k], V[piv][k]);
+      const double dg = V[c][c];
+      for (int k = 0; k < 2 * N; ++k) V[c][k] /= dg;
+      for (int r = 0; r < N; ++r)
+        if (r != c) {
+          const double f = V[r][c];
+          for (int k = 0; k < 2 * N; ++k) V[r][k] -= f * V[c][k];
+        }
+    }
+    for (int k = 0; k < N; ++k)
+      for (int i = 0; i < N; ++i) op.Vinv[k * N + i] = V[k][N + i];
   }
   // mortar interpolation: P_m[j][k] = l_k((x_j -/+ 1)/2)
   for (int m = 0; m < 2; ++m) {
@@ -522,7 +555,7 @@ size_t carve(pe_ctx* c, char* base) {
   c->d_plan = (int32_t*)take((size_t)n * 10 * 4);
   c->d_eta = (double*)take((size_t)n * 8);
   c->d_beta = (double*)take(kMaxLevels * 8);
-  c->d_dmat = (double*)take(6 * kMaxN * kMaxN * 8);
+  c->d_dmat = (double*)take(7 * kMaxN * kMaxN * 8);
   return off;
 }
 
@@ -566,8 +599,19 @@ inline int src_code(const pe_ctx* c, int r, int i) {
   return c->cpl[(size_t)r * c->S + i] >= 0 ? 1 : 2;
 }
 
+// blending-factor parameters of subcell shock capturing (Hennemann et al.): threshold
+// T = 0.5 10^(-1.8 (p+1)^(1/4)) and the sigmoid's slope s / T, s = ln((1 - 1e-4) / 1e-4)
+void set_shock_capturing_args(const pe_ctx* c, StageArgs& a) {
+  a.sc = c->sc_on ? 1 : 0;
+  a.sc_amax = c->sc_amax;
+  a.sc_amin = c->sc_amin;
+  a.sc_T = 0.5 * std::pow(10.0, -1.8 * std::pow((double)c->N, 0.25));
+  a.sc_slope = std::log((1.0 - 1e-4) / 1e-4) / a.sc_T;
+}
+
 void fill_stage(const pe_ctx* c, int i, double dt, StageArgs& a) {
   std::memset(&a, 0, sizeof a);
+  set_shock_capturing_args(c, a);
   a.dt = dt;
   a.ci = c->c[i];
   a.first = i == 0;
@@ -979,7 +1023,7 @@ pe_status pe_bind(pe_ctx* ctx, double* u_dev, void* ws, void* stream) {
   HIPCHK(hipMemsetAsync(ctx->d_counter, 0, kMaxMembers * 8, s));
   HIPCHK(hipMemsetAsync(ctx->d_evals, 0, (size_t)cap_of(ctx) * 4, s));
   const int N = ctx->N;
-  double dm[6 * kMaxN * kMaxN];
+  double dm[7 * kMaxN * kMaxN];
   for (int i = 0; i < N * N; ++i) {
     dm[i] = i / N == i % N ? 0.0 : 2.0 * ctx->ops.D[i];
     dm[N * N + i] = ctx->ops.D[i];
@@ -987,8 +1031,9 @@ pe_status pe_bind(pe_ctx* ctx, double* u_dev, void* ws, void* stream) {
       dm[(2 + mm) * N * N + i] = ctx->ops.P[mm][i];
       dm[(4 + mm) * N * N + i] = ctx->ops.R[mm][i];
     }
+    dm[6 * N * N + i] = ctx->ops.Vinv[i];
   }
-  HIPCHK(hipMemcpyAsync(ctx->d_dmat, dm, 6 * (size_t)N * N * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->d_dmat, dm, 7 * (size_t)N * N * 8, hipMemcpyHostToDevice, s));
   ctx->ops.dD = ctx->d_dmat;
   ctx->pending_leaf_state = false;
   HIPCHK(hipStreamSynchronize(s));
@@ -1198,6 +1243,7 @@ pe_status pe_rhs(pe_ctx* ctx, const double* u, double* du, void* stream) {
   a.Kout = du;
   a.first = 1;          // F(U): stage values are U itself (src 0 for every member)
   a.n_act = ctx->n_e;
+  set_shock_capturing_args(ctx, a);
   a.Fv = ctx->Fv;
   Mesh m = device_mesh(ctx);
   if (ctx->equations == 1)
@@ -1210,6 +1256,7 @@ pe_status pe_rhs_vjp(pe_ctx* ctx, const double* u, const double* w, double* out,
   if (!ctx) return PE_EINVAL;
   if (!ctx->partitioned) return fail(ctx, PE_ESTATE, "rhs_vjp before partition");
   if (ctx->equations != 0) return fail(ctx, PE_EUNSUPPORTED, "rhs_vjp: Euler only");
+  if (ctx->sc_on) return fail(ctx, PE_EUNSUPPORTED, "rhs_vjp: not with shock capturing");
   if (!u || !w || !out) return fail(ctx, PE_EINVAL, "rhs_vjp: null");
   VjpArgs a;
   std::memset(&a, 0, sizeof a);
@@ -1245,6 +1292,7 @@ pe_status adjoint_ready(pe_ctx* ctx, double dt, const char* who) {
   if (!ctx->partitioned) return fail(ctx, PE_ESTATE, "%s before partition", who);
   if (ctx->equations != 0) return fail(ctx, PE_EUNSUPPORTED, "%s: Euler only", who);
   if (ctx->general) return fail(ctx, PE_EUNSUPPORTED, "%s: classic stage pattern only", who);
+  if (ctx->sc_on) return fail(ctx, PE_EUNSUPPORTED, "%s: not with shock capturing", who);
   if (!(dt > 0.0)) return fail(ctx, PE_EINVAL, "%s: dt must be > 0", who);
   if (!ctx->adj_ws || ctx->adj_S != ctx->S || ctx->adj_cap != cap_of(ctx))
     return fail(ctx, PE_ESTATE, "%s: adjoint workspace not bound for these coefficients and capacity", who);
@@ -1500,7 +1548,7 @@ pe_status capture_step(pe_ctx* ctx, double dt) {
   // the point where the 2D p=3 launches change body changes that node's kernel and block size,
   // which an in-place update is not relied on to carry over: then the graph is instantiated anew
   std::vector<int> bodies(ctx->S);
-  for (int i = 0; i < ctx->S; ++i) bodies[i] = stage_body_id(ctx->dim, ctx->N, ctx->n_act[i]);
+  for (int i = 0; i < ctx->S; ++i) bodies[i] = stage_body_id(ctx->dim, ctx->N, ctx->n_act[i], ctx->sc_on);
   const bool same_bodies = bodies == ctx->graph_bodies;
   ctx->graph_bodies = bodies;
   if (ctx->gexec && same_bodies) {
@@ -1593,10 +1641,33 @@ pe_status pe_get_leaves(const pe_ctx* ctx, int32_t* leaves, int64_t* n) {
   return PE_OK;
 }
 
+pe_status pe_set_shock_capturing(pe_ctx* ctx, int on, double alpha_max, double alpha_min) {
+  if (!ctx) return PE_EINVAL;
+  if (on && (ctx->dim != 2 || ctx->equations != 0))
+    return fail(ctx, PE_EUNSUPPORTED, "shock capturing: 2D Euler only");
+  if (on && ctx->general) return fail(ctx, PE_EUNSUPPORTED, "shock capturing: classic stage pattern only");
+  if (on && !(alpha_min >= 0.0 && alpha_min <= alpha_max && alpha_max <= 1.0))
+    return fail(ctx, PE_EINVAL, "shock capturing: need 0 <= alpha_min <= alpha_max <= 1");
+  ctx->sc_on = on != 0;
+  if (on) {
+    ctx->sc_amax = alpha_max;
+    ctx->sc_amin = alpha_min;
+  }
+  ctx->graph_valid = false;
+  return PE_OK;
+}
+
 pe_status pe_set_amr_indicator(pe_ctx* ctx, int kind, int variable, double f_wave) {
   if (!ctx) return PE_EINVAL;
   if (kind == PE_INDICATOR_DENSITY_GRADIENT) {
     ctx->ind_kind = kind;
+    return PE_OK;
+  }
+  if (kind == PE_INDICATOR_HENNEMANN_GASSNER) {
+    if (variable != 0) return fail(ctx, PE_EINVAL, "indicator: Hennemann-Gassner on the density (variable 0) only");
+    if (ctx->dim != 2) return fail(ctx, PE_EUNSUPPORTED, "indicator: Hennemann-Gassner in 2D only");
+    ctx->ind_kind = kind;
+    ctx->ind_var = 0;
     return PE_OK;
   }
   if (kind != PE_INDICATOR_LOHNER) return fail(ctx, PE_EINVAL, "indicator %d unknown", kind);
@@ -1618,6 +1689,12 @@ pe_status pe_amr_indicator(pe_ctx* ctx, double* eta_leaf, void* stream) {
   if (ctx->ind_kind == PE_INDICATOR_LOHNER)
     HIPCHK(launch_indicator_lohner(ctx->dim, ctx->N, ctx->n_e, (int)cap_of(ctx), ctx->d_slot_of_leaf, ctx->U,
                                    ctx->ind_var, ctx->ind_fwave, ctx->ph.gamma, ctx->d_eta, s));
+  else if (ctx->ind_kind == PE_INDICATOR_HENNEMANN_GASSNER) {
+    StageArgs a;
+    set_shock_capturing_args(ctx, a);
+    HIPCHK(launch_indicator_hg(ctx->dim, ctx->N, ctx->n_e, (int)cap_of(ctx), ctx->d_slot_of_leaf, ctx->U,
+                               ctx->ops.dD, a.sc_T, a.sc_slope, ctx->d_eta, s));
+  }
   else
     HIPCHK(launch_indicator(ctx->dim, ctx->N, ctx->n_e, (int)cap_of(ctx), ctx->d_slot_of_leaf, ctx->d_lev_leaf,
                             ctx->U, ctx->ops, m, ctx->d_eta, s));
@@ -1959,6 +2036,7 @@ pe_status pe_rhs_jvp(pe_ctx* ctx, const double* u, const double* v, double* t, d
   if (!ctx) return PE_EINVAL;
   if (!ctx->partitioned) return fail(ctx, PE_ESTATE, "rhs_jvp before partition");
   if (ctx->equations != 0) return fail(ctx, PE_EUNSUPPORTED, "rhs_jvp: Euler only");
+  if (ctx->sc_on) return fail(ctx, PE_EUNSUPPORTED, "rhs_jvp: not with shock capturing");
   if (!u || !v || !t) return fail(ctx, PE_EINVAL, "rhs_jvp: null");
   HIPCHK(launch_rhs_jvp(ctx->dim, ctx->N, (int)ctx->n_e, u, v, t, f, device_mesh(ctx), ctx->ops, ctx->ph,
                         (hipStream_t)stream));
@@ -2138,6 +2216,7 @@ pe_status pe_batch_create(pe_batch** out, pe_ctx* const* runs, int n_runs) {
     if (c->dim != 2 || c->equations != 0 || (c->N != 3 && c->N != 4))
       return bfail(nullptr, PE_EUNSUPPORTED, "batch: run %d is not 2D Euler with degree 2 or 3", k);
     if (c->general) return bfail(nullptr, PE_EUNSUPPORTED, "batch: run %d has an alternative stage pattern", k);
+    if (c->sc_on) return bfail(nullptr, PE_EUNSUPPORTED, "batch: run %d has shock capturing", k);
     if (!c->partitioned || !c->state_valid || !c->bound)
       return bfail(nullptr, PE_ESTATE, "batch: run %d needs a bound state and a partition", k);
     if (!last_stage_in_place_safe(c))

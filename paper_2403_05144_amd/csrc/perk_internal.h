@@ -33,8 +33,9 @@ struct Ops {
   double P[2][kMaxN * kMaxN];       // mortar interpolation to the lower/upper half
   double R[2][kMaxN * kMaxN];       // mortar projection: exact L2 projection of the half faces (R_0 P_0 + R_1 P_1 = I)
   double x[kMaxN];                  // nodes on [-1, 1]
+  double Vinv[kMaxN * kMaxN];       // [k N + i]: coefficient of sqrt(k + 1/2) P_k in the interpolant of nodal values
   // device copy (caller's workspace, written at bind): [0, N^2) 2 D with a zero diagonal,
-  // [N^2, 2 N^2) D, then P[0], P[1], R[0], R[1] (N^2 each).  Lane-indexed reads of the tables
+  // [N^2, 2 N^2) D, then P[0], P[1], R[0], R[1], Vinv (N^2 each).  Lane-indexed reads of the tables
   // above come from kernel-argument memory, which is far slower than this L2-resident copy.
   const double* dD;
 };
@@ -101,6 +102,10 @@ struct StageArgs {
   double a1[kMaxMembers]; // a_{k,1}
   double a2[kMaxMembers]; // a_{k,i}
   double* Yw[kMaxMembers];
+  // subcell shock capturing (2D Euler; Hennemann et al.): on, cap and cut-off of the blending
+  // factor, threshold T and slope s / T of its sigmoid
+  int sc;
+  double sc_amax, sc_amin, sc_T, sc_slope;
 };
 
 // Slot of the v-th active element of a launch (v < n_act): ranges are few (one per member at
@@ -158,7 +163,7 @@ hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const 
                         const Physics& ph, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Which kernel body launch_stage picks for a stage with n_act active elements (0: the default
 // body; 1: the two-wave 2D p=3 body of small launches).
-int stage_body_id(int dim, int N, int n_act);
+int stage_body_id(int dim, int N, int n_act, bool sc);
 // BR1 gradient pass over slots [0, n_act) and the n_halo slots of `halo`: lifted gradients of
 // w = (v, T) with central face values, then the viscous flux F_v at every node into a.Fv.
 hipError_t launch_gradients(int dim, int N, const StageArgs& a, const Mesh& m, const Ops& op,
@@ -192,6 +197,9 @@ hipError_t launch_slot_to_leaf(int n, int ld, int nv, int nd, const int32_t* slo
 
 // AMR indicator per leaf: eta = h max_nodes |grad rho| / max_nodes rho (h = element size in x).
 // Loehner's indicator per leaf on primitive variable var (0 rho, 1..dim velocity, dim+1 pressure)
+// Hennemann-Gassner shock-capturing indicator as a refinement indicator (2D), per leaf.
+hipError_t launch_indicator_hg(int dim, int N, int n, int ld, const int32_t* slot_of_leaf, const double* U,
+                               const double* dD, double T, double slope, double* eta, hipStream_t s);
 hipError_t launch_indicator_lohner(int dim, int N, int n, int ld, const int32_t* slot_of_leaf, const double* U,
                                    int var, double f_wave, double gamma, double* eta, hipStream_t s);
 hipError_t launch_indicator(int dim, int N, int n, int ld, const int32_t* slot_of_leaf, const int32_t* lev_leaf,

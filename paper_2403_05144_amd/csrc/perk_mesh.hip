@@ -201,6 +201,52 @@ __global__ void k_indicator_lohner(int n, int ld, const int32_t* slot_of_leaf, c
   eta[leaf] = best;
 }
 
+// Shock-capturing indicator of Hennemann et al. used as a refinement indicator (the paper's
+// Kelvin-Helmholtz run, Sec. 7.2.1): the density's coefficients in the orthonormal Legendre
+// basis (Vinv, the seventh operator table, applied along each direction in turn), the energy
+// share of the top modes E = max((all - clip_1)/all, (clip_1 - clip_2)/clip_1) (clip_k: modes of
+// degree <= p - k in each direction) and the blending sigmoid 1/(1 + exp(-slope (E - T)))
+// without cut-off or cap; one lane per leaf.
+template <int N>
+__global__ void k_indicator_hg(int n, const int32_t* slot_of_leaf, const double* U, const double* dD, double T,
+                               double slope, double* eta) {
+  constexpr int ND = N * N;
+  const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
+  if (leaf >= n) return;
+  const int slot = slot_of_leaf[leaf];
+  const double* Vi = dD + 6 * N * N;
+  double q[ND], r[ND];
+#pragma unroll
+  for (int nd = 0; nd < ND; ++nd) q[nd] = U[(int64_t)slot * ND + nd];   // variable 0: the density
+#pragma unroll
+  for (int b = 0; b < N; ++b)
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc += Vi[a * N + i] * q[i + N * b];
+      r[a + N * b] = acc;
+    }
+  double tot = 0.0, c1 = 0.0, c2 = 0.0;
+#pragma unroll
+  for (int b = 0; b < N; ++b)
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      double m = 0.0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) m += Vi[b * N + j] * r[a + N * j];
+      const int deg = a > b ? a : b;
+      const double m2 = m * m;
+      tot += m2;
+      if (deg <= N - 2) c1 += m2;
+      if (deg <= N - 3) c2 += m2;
+    }
+  const double e1 = tot > 0.0 ? (tot - c1) / tot : 0.0;
+  const double e2 = c1 > 0.0 ? (c1 - c2) / c1 : 0.0;
+  const double E = e1 < e2 ? e2 : e1;
+  eta[leaf] = 1.0 / (1.0 + exp(-slope * (E - T)));
+}
+
 // Largest convective wave speed per slot, scaled to the step-size bound of eq. (CFL_DG):
 // w_e = max over nodes and directions of (k+1)(|v_d| + c) / h_d, one lane per slot.
 template <int DIM, int N>
@@ -392,6 +438,20 @@ hipError_t launch_indicator_lohner(int dim, int N, int n, int ld, const int32_t*
     hipLaunchKernelGGL((k_indicator_lohner<3, 4>), g, b, 0, s, n, ld, slot_of_leaf, U, var, f_wave, gamma, eta);
   else if (dim == 3 && N == 3)
     hipLaunchKernelGGL((k_indicator_lohner<3, 3>), g, b, 0, s, n, ld, slot_of_leaf, U, var, f_wave, gamma, eta);
+  else
+    return hipErrorNotSupported;
+  return hipGetLastError();
+}
+
+hipError_t launch_indicator_hg(int dim, int N, int n, int ld, const int32_t* slot_of_leaf, const double* U,
+                               const double* dD, double T, double slope, double* eta, hipStream_t s) {
+  (void)ld;   // the density is variable 0: slot-major within its slice
+  if (n == 0) return hipSuccess;
+  const dim3 g(grid_for(n, 128)), b(128);
+  if (dim == 2 && N == 4)
+    hipLaunchKernelGGL((k_indicator_hg<4>), g, b, 0, s, n, slot_of_leaf, U, dD, T, slope, eta);
+  else if (dim == 2 && N == 3)
+    hipLaunchKernelGGL((k_indicator_hg<3>), g, b, 0, s, n, slot_of_leaf, U, dD, T, slope, eta);
   else
     return hipErrorNotSupported;
   return hipGetLastError();

@@ -233,7 +233,7 @@ struct SK {
 // The stage work of one block of EPB elements: block `blk` of the launch covers the slots
 // [blk EPB, blk EPB + EPB).  Shared by the single-run kernel and the batched kernel, which
 // therefore compute bitwise identical stages.
-template <int DIM, int N, bool VISC, int EPB, bool SPLIT = false>
+template <int DIM, int N, bool VISC, int EPB, bool SPLIT = false, bool SC = false>
 __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph,
                                             int blk) {
   using K = SK<DIM, N, SPLIT>;
@@ -283,6 +283,13 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   constexpr bool HOLD_OPS = SPLIT || (DIM == 3 && !VISC);
   constexpr bool OPS_A = DIM == 3;
   __shared__ double s_PR[OPS_A ? 4 : 1][OPS_A ? N * N : 1];
+  // subcell shock capturing (2D Euler): the modal transform, the element's blending factor and
+  // the first-order fluxes between neighbouring nodes of every coordinate line (subcell faces)
+  static_assert(!SC || (DIM == 2 && !VISC && K::T >= 32 && K::ND <= 16), "shock capturing: 2D Euler bodies");
+  constexpr int NFVI = SC ? DIM * K::NLINE * (N - 1) : 1;
+  __shared__ double s_fvs[SC ? EPB : 1][NFVI][NV];
+  __shared__ double s_vinv[SC ? N * N : 1];
+  __shared__ double s_alpha[SC ? EPB : 1];
   auto Pm = [&](int mm, int idx) -> double { return OPS_A ? s_PR[mm][idx] : op.P[mm][idx]; };
   auto Rm = [&](int mm, int idx) -> double { return OPS_A ? s_PR[2 + mm][idx] : op.R[mm][idx]; };
 
@@ -403,6 +410,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       else s_PR[tb - 2][ti] = tab[k];
     }
   }
+  if (SC && threadIdx.x < N * N) s_vinv[threadIdx.x] = op.dD[6 * N * N + threadIdx.x];
   __syncthreads();
 
   // ---- C: node quantities; fine sides: coarse trace interpolated into sub-slot 1
@@ -583,10 +591,50 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         cv_hold[q] = 0.5 * (fv_own(d, v, face_node<DIM, N>(d, side, j)) + nbv);
       }
     }
+    if constexpr (SC) {
+      // blending factor of subcell shock capturing: the density's coefficients in the
+      // orthonormal Legendre basis, one per lane of [16, 16 + ND) (idle in this phase), the
+      // energies of all modes, of those of degree <= p - 1 and <= p - 2 in each direction summed
+      // over those 16 lanes, E = max((all - clip_1)/all, (clip_1 - clip_2)/clip_1), and the sigmoid
+      if (lane >= 16 && lane < 32) {
+        const int t = lane - 16;
+        double tot = 0.0, c1 = 0.0, c2 = 0.0;
+        if (t < ND) {
+          const int ia = t % N, ib = t / N;
+          double mo = 0.0;
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            double row = 0.0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) row += s_vinv[ia * N + i] * s_u[le][0][i + N * j];
+            mo += s_vinv[ib * N + j] * row;
+          }
+          const int deg = ia > ib ? ia : ib;
+          tot = mo * mo;
+          c1 = deg <= N - 2 ? tot : 0.0;
+          c2 = deg <= N - 3 ? tot : 0.0;
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+          tot += __shfl_xor(tot, o, 16);
+          c1 += __shfl_xor(c1, o, 16);
+          c2 += __shfl_xor(c2, o, 16);
+        }
+        if (t == 0) {
+          const double e1 = tot > 0.0 ? (tot - c1) / tot : 0.0;
+          const double e2 = c1 > 0.0 ? (c1 - c2) / c1 : 0.0;
+          const double E = e1 < e2 ? e2 : e1;
+          const double al = 1.0 / (1.0 + exp(-a.sc_slope * (E - a.sc_T)));
+          s_alpha[le] = al < a.sc_amin ? 0.0 : (al < a.sc_amax ? al : a.sc_amax);
+        }
+      }
+    }
   }
   __syncthreads();
 
   // ---- D: fluxes.  Pairs first, then face nodes sub-face-major (sub 0 of every face first).
+  double alpha = 0.0;
+  if (SC && act) alpha = s_alpha[le];
   if (act) {
     if constexpr (ALIAS) {
       // the central viscous face values of phase C (the sub-face traces they replace are dead:
@@ -694,6 +742,26 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         else face_flux(w - NP);
       }
     }
+    if constexpr (SC) {
+      if (alpha > 0.0) {
+        // HLL fluxes between neighbouring nodes of every coordinate line, on the lanes with the
+        // fewest flux items above (split body: after the face lanes; else after the last item)
+        constexpr int FVB = K::PLN ? K::PLN + NFI : (NP + NFI) % T;
+        for (int w = (lane + T - FVB) % T; w < NFVI; w += T) {
+          const int k = w % (N - 1), line = (w / (N - 1)) % K::NLINE, d = w / ((N - 1) * K::NLINE);
+          const int nl = node_on_line<DIM, N>(d, line, k), nr = node_on_line<DIM, N>(d, line, k + 1);
+          double uL[NV], uR[NV], fl[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            uL[v] = s_u[le][v][nl];
+            uR[v] = s_u[le][v][nr];
+          }
+          hll_flux<DIM>(uL, uR, d, gamma, fl);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) s_fvs[le][w][v] = fl[v];
+        }
+      }
+    }
   }
   __syncthreads();
 
@@ -768,7 +836,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   if (!act) return;
 
   // ---- E: sums, lifting, Jacobian, stage combination
-  const double iw0 = op.iw[0], iwN = op.iw[N - 1];
+  const double iw0 = op.iw[0], iwN = op.iw[N - 1], iw1 = op.iw[1];
 #pragma unroll
   for (int it = 0; it < NITEM; ++it) {
     const int w = lane + it * T;
@@ -788,6 +856,17 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       for (int mm = 0; mm < N; ++mm) {
         const int pi = (int)((PairNodes<N>::kIndexOf >> (4 * (pos * N + mm))) & 15);
         acc += s_D2[pos * N + mm] * s_pf[le][(base + pi) * NV + v];
+      }
+      if constexpr (SC) {
+        if (alpha > 0.0) {
+          // (1 - alpha) flux differencing + alpha finite volumes on the LGL subcells (no subcell
+          // flux at the element's faces: the surface term below brings the face flux)
+          const int fb = (d * K::NLINE + line) * (N - 1);
+          const double fr = pos < N - 1 ? s_fvs[le][fb + pos][v] : 0.0;
+          const double fl = pos > 0 ? s_fvs[le][fb + pos - 1][v] : 0.0;
+          const double iwp = pos == 0 || pos == N - 1 ? iw0 : iw1;
+          acc = (1.0 - alpha) * acc + alpha * iwp * (fr - fl);
+        }
       }
       const int f = 2 * d + (pos == N - 1 ? 1 : 0);
       const int fi = face_index<DIM, N>(nd, d);
@@ -836,7 +915,7 @@ constexpr int stage_waves_per_simd() {
   return SK<DIM, N, SPLIT>::MINW;
 }
 
-template <int DIM, int N, bool VISC, bool SPLIT>
+template <int DIM, int N, bool VISC, bool SPLIT, bool SC>
 __global__ __launch_bounds__((SK<DIM, N, SPLIT>::T * SK<DIM, N, SPLIT>::EPB),
                              (stage_waves_per_simd<DIM, N, VISC, SPLIT>())) void k_stage(StageArgs a, Mesh m, Ops op,
                                                                                        Physics ph) {
@@ -848,7 +927,7 @@ __global__ __launch_bounds__((SK<DIM, N, SPLIT>::T * SK<DIM, N, SPLIT>::EPB),
   // does not keep a slot's data.)
   const int g8 = (int)gridDim.x >> 3;
   const int b = (int)blockIdx.x;
-  stage_block<DIM, N, VISC, SK<DIM, N, SPLIT>::EPB, SPLIT>(a, m, op, ph, (b & 7) * g8 + (b >> 3));
+  stage_block<DIM, N, VISC, SK<DIM, N, SPLIT>::EPB, SPLIT, SC>(a, m, op, ph, (b & 7) * g8 + (b >> 3));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1141,16 +1220,16 @@ hipError_t launch_grad_t(const StageArgs& a, const Mesh& m, const Ops& op, const
   return hipGetLastError();
 }
 
-template <int DIM, int N, bool VISC, bool SPLIT>
+template <int DIM, int N, bool VISC, bool SPLIT, bool SC>
 hipError_t launch_stage_v(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1) {
   using K = SK<DIM, N, SPLIT>;
   const int blocks = ((a.n_act + K::EPB - 1) / K::EPB + 7) & ~7;   // a multiple of the 8 XCDs
   if (ev0)
-    hipExtLaunchKernelGGL((k_stage<DIM, N, VISC, SPLIT>), dim3(blocks), dim3(K::T * K::EPB), 0, s, ev0, ev1, 0, a, m,
-                          op, ph);
+    hipExtLaunchKernelGGL((k_stage<DIM, N, VISC, SPLIT, SC>), dim3(blocks), dim3(K::T * K::EPB), 0, s, ev0, ev1, 0,
+                          a, m, op, ph);
   else
-    hipLaunchKernelGGL((k_stage<DIM, N, VISC, SPLIT>), dim3(blocks), dim3(K::T * K::EPB), 0, s, a, m, op, ph);
+    hipLaunchKernelGGL((k_stage<DIM, N, VISC, SPLIT, SC>), dim3(blocks), dim3(K::T * K::EPB), 0, s, a, m, op, ph);
   return hipGetLastError();
 }
 
@@ -1160,14 +1239,14 @@ hipError_t launch_stage_v(const StageArgs& a, const Mesh& m, const Ops& op, cons
 // split faster up to 4096 elements (1024: 6.3 vs 7.2 us), single wave from 9216 on.
 constexpr int kSplitMaxElements = STAGE_SPLIT_MAX;
 
-template <int DIM, int N, bool VISC>
+template <int DIM, int N, bool VISC, bool SC = false>
 hipError_t launch_stage_t(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1) {
   if (a.n_act <= 0) return hipSuccess;
   if constexpr (DIM == 2 && N == 4) {
-    if (a.n_act <= kSplitMaxElements) return launch_stage_v<DIM, N, VISC, true>(a, m, op, ph, s, ev0, ev1);
+    if (a.n_act <= kSplitMaxElements) return launch_stage_v<DIM, N, VISC, true, SC>(a, m, op, ph, s, ev0, ev1);
   }
-  return launch_stage_v<DIM, N, VISC, false>(a, m, op, ph, s, ev0, ev1);
+  return launch_stage_v<DIM, N, VISC, false, SC>(a, m, op, ph, s, ev0, ev1);
 }
 
 }  // namespace
@@ -1196,12 +1275,17 @@ hipError_t launch_stage_batch(int N, int M, int grid, bool persistent, const Bat
   return hipErrorNotSupported;
 }
 
-int stage_body_id(int dim, int N, int n_act) {
-  return (dim == 2 && N == 4 && n_act > 0 && n_act <= kSplitMaxElements) ? 1 : 0;
+int stage_body_id(int dim, int N, int n_act, bool sc) {
+  return ((dim == 2 && N == 4 && n_act > 0 && n_act <= kSplitMaxElements) ? 1 : 0) + (sc ? 2 : 0);
 }
 
 hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,
                         const Physics& ph, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (!viscous && a.sc) {
+    if (dim == 2 && N == 4) return launch_stage_t<2, 4, false, true>(a, m, op, ph, s, e0, e1);
+    if (dim == 2 && N == 3) return launch_stage_t<2, 3, false, true>(a, m, op, ph, s, e0, e1);
+    return hipErrorNotSupported;
+  }
   if (!viscous) {
     if (dim == 2 && N == 4) return launch_stage_t<2, 4, false>(a, m, op, ph, s, e0, e1);
     if (dim == 2 && N == 3) return launch_stage_t<2, 3, false>(a, m, op, ph, s, e0, e1);

@@ -314,10 +314,16 @@ class PerkSolver:
         self.partition(member_of_level)
 
     def set_indicator(self, kind, variable=1, f_wave=0.2):
-        """Refinement indicator of indicator() / amr_cycle(): "density_gradient" or "lohner" (on the
-        primitive variable `variable`: 0 rho, 1..dim velocity, dim+1 pressure)."""
-        k = {"density_gradient": 0, "lohner": 1}[kind]
+        """Refinement indicator of indicator() / amr_cycle(): "density_gradient", "lohner" (on the
+        primitive variable `variable`: 0 rho, 1..dim velocity, dim+1 pressure) or
+        "hennemann_gassner" (the shock-capturing sigmoid of the density, variable 0)."""
+        k = {"density_gradient": 0, "lohner": 1, "hennemann_gassner": 2}[kind]
         self._check(self.lib.pe_set_amr_indicator(self._ctx, k, int(variable), float(f_wave)), "pe_set_amr_indicator")
+
+    def set_shock_capturing(self, on=True, alpha_max=0.5, alpha_min=0.001):
+        """Subcell shock capturing (pe_set_shock_capturing, 2D Euler)."""
+        self._check(self.lib.pe_set_shock_capturing(self._ctx, int(bool(on)), float(alpha_max), float(alpha_min)),
+                    "pe_set_shock_capturing")
 
     def amr_cycle(self, refine_above, coarsen_below, level_min, level_max, member_of_level):
         """indicator() + threshold flags + adapt() in one library call (the same flags, forest and

@@ -270,6 +270,17 @@ def kelvin_helmholtz(x, y, seed=MASTER_SEED + 1, gamma=1.4, amplitude=0.01, widt
     return prim2cons(rho, [vx, vy], p, gamma)
 
 
+def kelvin_helmholtz_paper(x, y, gamma=1.4):
+    """The Kelvin-Helmholtz instability of the paper's inviscid run (eq. KelvinHelmholtzIC) on
+    [-1,1]^2: B(y) = tanh(15 y + 7.5) - tanh(15 y - 7.5), rho = 0.5 + 0.75 B, v_x = (B - 1)/2,
+    v_y = 0.1 sin(2 pi x), p = 1; conservative variables."""
+    B = np.tanh(15.0 * y + 7.5) - np.tanh(15.0 * y - 7.5)
+    rho = 0.5 + 0.75 * B
+    vx = 0.5 * (B - 1.0)
+    vy = 0.1 * np.sin(2.0 * np.pi * x)
+    return prim2cons(rho, [vx, vy], np.ones_like(x), gamma)
+
+
 def shear_layer(x, y, kappa=80.0, delta=0.05, c0=10.0, gamma=1.4):
     """Doubly periodic double shear layer on [0,1]^2 (paper eq. ShearLayerIC): rho = 1,
     v_x = tanh(kappa (y - 1/4)) for y <= 1/2 and tanh(kappa (3/4 - y)) above, v_y =

@@ -291,8 +291,30 @@ def test_indicator_selection_errors():
     ctx = _ctx(L, lib)
     assert lib.pe_set_amr_indicator(ctx, 1, 1, 0.2) == 0            # Loehner on v_x
     assert lib.pe_set_amr_indicator(ctx, 0, 0, 0.0) == 0            # density gradient
-    assert lib.pe_set_amr_indicator(ctx, 2, 1, 0.2) == -1           # unknown kind
+    assert lib.pe_set_amr_indicator(ctx, 3, 1, 0.2) == -1           # unknown kind
     assert lib.pe_set_amr_indicator(ctx, 1, 4, 0.2) == -1           # 2D: variables 0..3
     assert lib.pe_set_amr_indicator(ctx, 1, 1, -0.1) == -1          # f_wave < 0
     assert lib.pe_set_amr_indicator(ctx, 1, 1, float("nan")) == -1
+    assert lib.pe_set_amr_indicator(ctx, 2, 0, 0.0) == 0            # Hennemann-Gassner on the density
+    assert lib.pe_set_amr_indicator(ctx, 2, 1, 0.0) == -1           # ... on the density only
     lib.pe_destroy(ctx)
+    ctx = _ctx(L, lib, dim=3)
+    assert lib.pe_set_amr_indicator(ctx, 2, 0, 0.0) == -6           # 2D only
+    lib.pe_destroy(ctx)
+
+
+def test_shock_capturing_selection_errors():
+    L, lib = _lib()
+    ctx = _ctx(L, lib)
+    assert lib.pe_set_shock_capturing(ctx, 1, 0.5, 0.001) == 0
+    assert lib.pe_set_shock_capturing(ctx, 1, 0.5, 0.6) == -1       # alpha_min > alpha_max
+    assert lib.pe_set_shock_capturing(ctx, 1, 1.5, 0.001) == -1     # alpha_max > 1
+    assert lib.pe_set_shock_capturing(ctx, 1, 0.5, -0.1) == -1
+    assert lib.pe_set_shock_capturing(ctx, 1, float("nan"), 0.0) == -1
+    assert lib.pe_set_shock_capturing(ctx, 0, 0.0, 0.0) == 0        # off: parameters ignored
+    lib.pe_destroy(ctx)
+    for dim, eq in ((3, 0), (2, 1)):                                 # 2D Euler only
+        ctx = _ctx(L, lib, dim=dim, eq=eq)
+        assert lib.pe_set_shock_capturing(ctx, 1, 0.5, 0.001) == -6
+        assert lib.pe_set_shock_capturing(ctx, 0, 0.5, 0.001) == 0
+        lib.pe_destroy(ctx)

@@ -51,9 +51,10 @@ def _log(msg):
 # ----------------------------------------------------------------------------------------
 # Workloads
 # ----------------------------------------------------------------------------------------
-def family_for(name, order, E_list, reduced_mesh, degree, ic_fn, h_red, equations=0, mu=0.0):
+def family_for(name, order, E_list, reduced_mesh, degree, ic_fn, h_red, equations=0, mu=0.0, shock_capturing=None):
     """Coefficients from the project's own optimisation on the spectrum of a reduced mesh
-    (cached as JSON next to the package)."""
+    (cached as JSON next to the package); shock_capturing = (alpha_max, alpha_min) takes the
+    spectrum of the blended operator."""
     from paper_2403_05144_amd import PerkSolver, coeffs
     path = os.path.join(ROOT, "paper_2403_05144_amd", "data", f"{name}.json")
     if os.path.exists(path):
@@ -62,6 +63,8 @@ def family_for(name, order, E_list, reduced_mesh, degree, ic_fn, h_red, equation
     tmp = coeffs.Family(2, 2, [2], np.array([0.0, 0.5]), np.array([0.0, 1.0]), np.zeros((1, 2)))
     s = PerkSolver(reduced_mesh, degree, tmp, [0] * (int(reduced_mesh.leaves[:, 0].max()) + 1),
                    equations=equations, mu=mu)
+    if shock_capturing:
+        s.set_shock_capturing(True, *shock_capturing)
     x = s.node_coords().cpu().numpy().transpose(1, 0, 2)
     u = ic_fn(x).transpose(1, 0, 2).copy()
     fam, lam = coeffs.family_from_solver_spectrum(s, u, order, E_list, h_red)
@@ -95,6 +98,8 @@ def make_solver(wl, mesh, fam, mol):
                    equations=wl.get("equations", 0), mu=wl.get("mu", 0.0))
     if amr and amr.get("indicator"):
         s.set_indicator(*amr["indicator"])
+    if wl.get("shock_capturing"):
+        s.set_shock_capturing(True, *wl["shock_capturing"])
     return s
 
 
@@ -677,9 +682,47 @@ def run_sweep(args):
     }
 
 
+def wl_kh_paper(fam=None, refine_above=0.01, coarsen_below=0.001):
+    """The paper's inviscid Kelvin-Helmholtz run (Sec. 7.2.1, eq. KelvinHelmholtzIC): Euler on
+    [-1,1]^2, 16x16 roots refined up to five times (finest h = 2^-8) where the shock-capturing
+    indicator of the density asks for it, subcell shock capturing (alpha_max 0.5, alpha_min 0.001),
+    p = 3, EC volume + HLL surface flux, P-ERK3{4,6,11} optimised on the spectrum of the 4x4 mesh
+    (1024 unknowns, with shock capturing), levels by the paper's rule (finest E = 11, next E = 6,
+    the rest E = 4), adaptation every 10 steps, t in [0, 3]."""
+    import perk_inputs as pin
+    from paper_2403_05144_amd.partition_rule import LevelRule
+    mesh = pin.uniform_mesh(2, (16, 16), (-1, -1), (1, 1), 0)
+    ic = lambda x: pin.kelvin_helmholtz_paper(x[0], x[1])
+    h_red = 0.5
+    red = pin.uniform_mesh(2, (4, 4), (-1, -1), (1, 1), 0)
+    sc = (0.5, 0.001)
+    fam_name = "perk3_4_6_11_khsc_p3"
+    if fam is None:
+        fam = family_for(fam_name, 3, [4, 6, 11], red, 3, ic, h_red, shock_capturing=sc)
+    level_max = 5
+    rule = LevelRule.paper()
+    mol = rule_map(fam, rule, level_max)
+    # the members' optimised steps on the reduced mesh overestimate what this flow tolerates: at
+    # CFL 0.5 of the standalone P-ERK3;11's bound a uniform 128^2 run blows up before t = 1.7, at
+    # 0.35 it reaches t = 3; the family on the adaptive mesh runs at 0.3 of its binding member
+    cfl = 0.3
+    levels = pin.MeshDesc(2, mesh.n_root, mesh.lo, mesh.hi, np.array([[l, 0, 0, 0] for l in range(level_max + 1)]))
+    dt = stable_dt(fam, levels, mol, cfl)
+    return dict(name="kh_paper_sc", mesh=mesh, degree=3, fam=fam, fam_name=fam_name, mol=mol, rule=rule, ic=ic,
+                dt=dt, cfl=cfl, t_final=3.0, shock_capturing=sc, spectrum_op="fd", reduced_mesh=red, h_reduced=h_red,
+                amr=dict(level_min=0, level_max=level_max, interval=10, refine_above=refine_above,
+                         coarsen_below=coarsen_below, capacity=1 << 18, indicator=("hennemann_gassner", 0, 0.0)),
+                perk_maps=[("paper rule", mol)],
+                desc="the paper's inviscid Kelvin-Helmholtz instability (eq. KelvinHelmholtzIC) on [-1,1]^2, p=3, EC "
+                     "volume + HLL surface flux, subcell shock capturing on the density (alpha_max 0.5), quadtree AMR "
+                     "on the same indicator between levels 4 and 9 every 10 steps with re-partition after every "
+                     f"adaptation, P-ERK3{{4,6,11}} with levels mapped to E={[fam.E[r] for r in mol]} (paper rule), "
+                     f"CFL {cfl} of the binding member's optimised step")
+
+
 WORKLOADS = {"vortex_2level": wl_vortex_2level, "kh_amr": wl_kh_amr, "tgv": wl_tgv, "batch_vortex64": None,
              "adjoint_kh": None, "uniform_sweep": None, "patterns": None, "shear_layer": wl_shear_layer,
-             "spectrum": None,
+             "spectrum": None, "kh_paper": wl_kh_paper,
              "kh_amr_l4-7": lambda: wl_kh_amr(16, 3, "kh_amr_l4-7")}
 
 
@@ -693,6 +736,8 @@ def cpu_baseline(wl, u0_leaf, leaves0, budget_s=15.0):
     m0 = wl["mesh"]
     mesh = pin.MeshDesc(m0.dim, m0.n_root, m0.lo, m0.hi, leaves0)
     o = od.Oracle(mesh, wl["degree"] + 1, viscous=wl.get("equations", 0) == 1, mu=wl.get("mu", 0.0))
+    if wl.get("shock_capturing"):
+        o.set_shock_capturing(True, *wl["shock_capturing"])
     fam = wl["fam"]
     ofam = pc.PerkFamily(fam.order, fam.S, list(fam.E), np.asarray(fam.c), np.asarray(fam.b),
                          np.asarray(fam.a_sub))

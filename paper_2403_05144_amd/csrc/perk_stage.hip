@@ -183,10 +183,11 @@ __device__ __forceinline__ void hll_flux(const double* uL, const double* uR, int
 }
 
 // Stage value of variable v at (slot, node) as seen at this stage (see StageArgs::src).
+// (one load from the source buffer the code selects, and K_1 only where it is needed: lanes of
+// one wave whose neighbours have different sources share that load instead of one per source)
 __device__ __forceinline__ double stage_value(const StageArgs& a, int src, int64_t idx) {
-  if (src == 0) return a.U[idx];
-  if (src == 1) return a.Yin[idx];
-  return a.U[idx] + a.dt * a.ci * a.K1[idx];
+  const double b = (src == 1 ? a.Yin : a.U)[idx];
+  return src == 2 ? b + a.dt * a.ci * a.K1[idx] : b;
 }
 
 // ------------------------------------------------------------------------------------------

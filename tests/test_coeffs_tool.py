@@ -58,3 +58,27 @@ def test_rechained_members_match_the_oracle_patterns():
     ref = pc.pattern_family([[0, 3, 5, 7], [0, 1, 2, 3, 4, 7], list(range(8))], 8)
     np.testing.assert_array_equal(got.coupling, ref.coupling)
     np.testing.assert_allclose(got.a_sub, ref.a_val, rtol=1e-13, atol=1e-16)
+
+
+# ---- the product's optimiser against closed forms (no oracle code involved)
+@pytest.mark.parametrize("E", [4, 8, 16])
+def test_optimiser_second_order_disk_closed_form(E):
+    # the largest disk {|z + r| <= r} inside the stability region of an E-stage second-order
+    # method has r = E - 1 (the shifted polynomial 1 - (E - 1) + ... of the circle), so on the
+    # unit disk centred at -1 the optimal step is E - 1
+    th = np.linspace(0, np.pi, 200)
+    lam = -1.0 + np.exp(1j * th)
+    dt, _ = pt.optimise(lam, 2, E)
+    assert abs(dt - (E - 1)) <= 2e-4 * (E - 1), dt   # polygon and bisection tolerances
+
+
+def test_optimiser_fixed_polynomials_on_the_real_axis():
+    # E = p leaves no free coefficient: the step is the real stability limit of the truncated
+    # exponential; on the spectrum [-1, 0] that is 2 for 1 + z + z^2/2 and the real root x of
+    # 1 - x + x^2/2 - x^3/6 = -1 (2.5127...) for the third-order one
+    lam = -np.linspace(1e-3, 1.0, 400).astype(complex)
+    dt2, _ = pt.optimise(lam, 2, 2)
+    assert abs(dt2 - 2.0) < 1e-6
+    x = [r.real for r in np.roots([-1 / 6, 1 / 2, -1, 2]) if abs(r.imag) < 1e-12 and r.real > 0][0]
+    dt3, _ = pt.optimise(lam, 3, 3)
+    assert abs(dt3 - x) < 1e-6 and abs(x - 2.5127453266183) < 1e-9

@@ -190,3 +190,51 @@ def test_tangent_and_adjoint_refused():
         s.vjp_into(us, us, torch.zeros_like(us))
     s.set_shock_capturing(False)
     s.jvp_into(us, us, torch.zeros_like(us))
+
+
+def test_kh_adaptation_on_the_indicator_and_blended_steps():
+    # the paper's KH run (Sec. 7.2.1, its layers compressed twice): the shock-capturing indicator
+    # of the density drives the
+    # adaptation; flags from the oracle's sigmoid (the GPU's checked against it), replayed on both
+    # sides, leaf lists bit-exact; then P-ERK3 steps with shock capturing on the adapted forest
+    from oracle import amr
+    from paper_2403_05144_amd import PerkSolver
+    mesh = pin.uniform_mesh(2, (16, 16), (-1, -1), (1, 1), 0)
+    lmax = 2
+    fam = _perk3_family([3, 6])
+    mol = [0, 0, 1]
+    s = PerkSolver(mesh, 3, fam, mol, capacity=8192)
+    s.set_indicator("hennemann_gassner", variable=0)
+    s.set_shock_capturing(True, alpha_max=AMAX, alpha_min=AMIN)
+    leaves = mesh.leaves
+    for cyc in range(3):
+        o = od.Oracle(pin.MeshDesc(2, (16, 16), (-1, -1), (1, 1), leaves), 4)
+        u = _kh_state(o, 2)
+        s.set_state(u)
+        o.set_shock_capturing(True, alpha_max=1.0, alpha_min=0.0)
+        _, eta_o, _ = o.sc_indicator(u)
+        eta_g = s.indicator()
+        assert np.max(np.abs(eta_g - eta_o)) <= 1e-11
+        for edge in (0.003, 0.0003):
+            assert np.all(np.abs(eta_o - edge) > 1e-9 * edge)
+        flags = amr.flags_from_indicator(eta_o, 0.003, 0.0003)
+        print(f"KH cycle {cyc}: {len(leaves)} leaves, refine {np.sum(flags > 0)}, coarsen {np.sum(flags < 0)}",
+              flush=True)
+        leaves, _ = amr.adapt(leaves, flags, 0, lmax, 2, (16, 16))
+        s.adapt(flags, 0, lmax, mol)
+        np.testing.assert_array_equal(s.leaves(), leaves)
+    lv = np.asarray(leaves)[:, 0]
+    assert lv.max() == lmax, np.bincount(lv)
+    o = od.Oracle(pin.MeshDesc(2, (16, 16), (-1, -1), (1, 1), leaves), 4)
+    u0 = _kh_state(o, 2)
+    assert np.count_nonzero(_alpha_checked(o, u0)) > 0
+    s.set_state(u0)
+    member = np.asarray(mol)[lv]
+    dt, n = 2e-4, 2
+    u_ora = u0.copy()
+    for _ in range(n):
+        u_ora = o.prk_step(u_ora, dt, fam, member)
+    s.step(dt, n)
+    g = s.get_state().cpu().numpy()
+    worst = max(np.max(np.abs(g[:, v] - u_ora[:, v])) / np.max(np.abs(u_ora[:, v])) for v in range(4))
+    assert worst <= TOL, worst

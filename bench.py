@@ -1477,7 +1477,13 @@ def run(args):
                    "member_of_level": [int(m) for m in wl["mol"]],
                    "E_of_level": [int(fam.E[m]) for m in wl["mol"]],
                    "adaptations_timed": n_adapt_timed, "episode_steps": episode,
-                   "episode_restarts_timed": acc["episodes"], "restart_s_excluded": excluded},
+                   "episode_restarts_timed": acc["episodes"], "restart_s_excluded": excluded,
+                   "adaptation": ({k: wl["amr"][k] for k in ("level_min", "level_max", "interval", "refine_above",
+                                                              "coarsen_below")}
+                                  | {"indicator": (wl["amr"].get("indicator") or ("density_gradient",))[0]})
+                   if wl.get("amr") else None,
+                   "shock_capturing": (dict(zip(("alpha_max", "alpha_min"), wl["shock_capturing"]))
+                                       if wl.get("shock_capturing") else None)},
         "pid_s": pid, "pid_per_node_s": pid * nv, "n_rhs_actual": n_rhs_actual,
         "n_rhs_opt": opt["n_rhs_opt"], "n_rhs_plus_hyp": opt["n_rhs_plus_hyp"], "kappa": opt["kappa"],
         "optimality": opt,

@@ -122,7 +122,8 @@ pe_status pe_mesh_build(pe_ctx* ctx, const pe_mesh_desc* mesh);
  * b^T c^2 = 1/3 and b^T A^(r) c = 1/6 for every member (order 3), eq. (PRKOrderCondsSimplified);
  * the zero pattern a_{i,i-1}^(r) = 0 for i < S - E^(r) + 2 (0-based) so that member r evaluates
  * exactly stages 1 and S-E^(r)+2..S; every stage with b_i != 0 evaluated by every member.
- * Returns PE_EINVAL on violation.  Invalidates the partition. */
+ * Returns PE_EINVAL on violation; PE_EUNSUPPORTED for a coupling table on a Navier-Stokes
+ * context or while shock capturing is on.  Invalidates the partition. */
 pe_status pe_set_perk_coefficients(pe_ctx* ctx, const pe_perk_coeffs* coeffs);
 
 /* Level -> member rules (which member of the family integrates the elements of each refinement
@@ -326,7 +327,7 @@ pe_status pe_set_amr_indicator(pe_ctx* ctx, int kind, int variable, double f_wav
  * on = 0 switches it off (parameters ignored).  The next pe_step captures its graph again.
  * PE_EUNSUPPORTED for 3D, Navier-Stokes or an alternative stage pattern; PE_EINVAL unless
  * 0 <= alpha_min <= alpha_max <= 1.  While on, the tangent, the adjoint and the batched form
- * refuse the context (PE_EUNSUPPORTED). */
+ * refuse the context, and pe_set_perk_coefficients a coupling table (PE_EUNSUPPORTED). */
 pe_status pe_set_shock_capturing(pe_ctx* ctx, int on, double alpha_max, double alpha_min);
 
 /* Refinement indicator per leaf (the one pe_set_amr_indicator selected; the density gradient by

@@ -850,6 +850,8 @@ pe_status pe_set_perk_coefficients(pe_ctx* ctx, const pe_perk_coeffs* co) {
   if (general) {
     if (ctx->equations != 0)
       return fail(ctx, PE_EUNSUPPORTED, "coefficients: alternative stage patterns are supported for Euler only");
+    if (ctx->sc_on)
+      return fail(ctx, PE_EUNSUPPORTED, "coefficients: alternative stage patterns are not supported with shock capturing");
     for (int r = 0; r < R; ++r)
       for (int i = 0; i < S; ++i) {
         const int j = co->coupling[(size_t)r * S + i];

@@ -318,3 +318,17 @@ def test_shock_capturing_selection_errors():
         assert lib.pe_set_shock_capturing(ctx, 1, 0.5, 0.001) == -6
         assert lib.pe_set_shock_capturing(ctx, 0, 0.5, 0.001) == 0
         lib.pe_destroy(ctx)
+    # the classic stage pattern only, whichever is set first
+    fam = pc.pattern_family([[0, 3, 5, 7], [0, 1, 2, 3, 4, 7], list(range(8))], 8)
+    co, keep = _pattern_coeffs(L, fam)
+    ctx = _ctx(L, lib)
+    assert lib.pe_set_perk_coefficients(ctx, ctypes.byref(co)) == 0
+    assert lib.pe_set_shock_capturing(ctx, 1, 0.5, 0.001) == -6
+    lib.pe_destroy(ctx)
+    ctx = _ctx(L, lib)
+    assert lib.pe_set_shock_capturing(ctx, 1, 0.5, 0.001) == 0
+    assert lib.pe_set_perk_coefficients(ctx, ctypes.byref(co)) == -6
+    assert b"shock capturing" in lib.pe_last_error(ctx)
+    assert lib.pe_set_shock_capturing(ctx, 0, 0.0, 0.0) == 0
+    assert lib.pe_set_perk_coefficients(ctx, ctypes.byref(co)) == 0
+    lib.pe_destroy(ctx)

@@ -27,7 +27,10 @@
 #include "perk_device.h"
 
 #ifndef STAGE_SPLIT_MAX
-#define STAGE_SPLIT_MAX 6144
+#define STAGE_SPLIT_MAX 2048
+#endif
+#ifndef STAGE_SPLIT_MAX_SC
+#define STAGE_SPLIT_MAX_SC 6144
 #endif
 
 namespace perk {
@@ -224,6 +227,9 @@ struct SK {
   // (0: one mixed loop over both)
   static constexpr int PLN = SPLIT ? T / 2 : (DIM == 3 && N == 4 ? 320 : 0);
   static constexpr int EPB = T >= 64 ? 1 : 64 / T;
+  // elements per block of the single-run kernel: the one-wave 2D p=3 body without shock
+  // capturing runs four (their flux phase mapped across the block, see stage_block)
+  static constexpr int epb(bool sc) { return DIM == 2 && N == 4 && !SPLIT && !sc ? 4 : EPB; }
   static constexpr int NITEM = (NV * ND + T - 1) / T;         // (variable, node) items per lane
   // waves per SIMD the register allocation must allow.  A second 6-wave block fits on a CU
   // only when every SIMD can hold 4 waves (at most 128 VGPRs) and the LDS allows it (measured:
@@ -265,6 +271,12 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   // same order was 1.5 % (KH, ~1400 elements) and 6 % (two-level vortex) slower, so the plain
   // bodies keep the original order.
   constexpr bool EARLYF = SPLIT && !VISC && SC;
+  // four one-wave 2D p=3 elements per block (large launches and batch tiles, throughput-bound
+  // on the VALU): the node quantities of all four on the first wave, and in the flux phase the
+  // 4 x 48 pair fluxes on the first three waves and the 4 x 16 face fluxes on the fourth, so
+  // that no wave issues both flux paths (one wave per element ran pairs and faces one after
+  // the other, divergent, in every element)
+  constexpr bool XM = DIM == 2 && N == 4 && T == 64 && EPB == 4 && !SPLIT && !SC;
   constexpr int NPF = NP * NV, NTV1 = NFC * (NSUB - 1) * NV * NF;
   constexpr int NX = ALIAS && NTV1 > NPF ? NTV1 : NPF;
   __shared__ double s_pf[EPB][NX];   // pair flux w, variable v at [w NV + v]
@@ -312,10 +324,14 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   const double gamma = ph.gamma;
   const double inv_gm1 = 1.0 / (gamma - 1.0);
   // own viscous flux, direction d, variable v, node nd
-  auto fv_own = [&](int d, int v, int nd) -> double {
-    if (FVL) return s_fv[le][d][v][nd];
+  // (the device array is addressed through the block's own slot e: only the 3D bodies read
+  // it, whose flux phase works on the lane's own element, q == le)
+  auto fv_own_q = [&](int q, int d, int v, int nd) -> double {
+    if (FVL) return s_fv[q][d][v][nd];
     return a.Fv[(((int64_t)d * NV + v) * ld + e) * ND + nd];
   };
+  auto fv_own = [&](int d, int v, int nd) -> double { return fv_own_q(le, d, v, nd); };
+  static_assert(!XM || !VISC || FVL, "cross-element flux mapping reads the viscous flux from LDS");
 
   // ---- A+B: connectivity, own values and epilogue operands, neighbour traces, all in flight
   //      together; one barrier before the node quantities
@@ -461,16 +477,21 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         }
       }
     } else {
-      for (int w = lane; w < ND; w += T) {
+      // XM: the first wave (its own element active, so every active element of the block is
+      // one of the four) forms the nodes of all four, node w of element qe on lane qe ND + w
+      const int qe = XM ? (int)threadIdx.x / ND : le;
+      const int w0 = XM ? (int)threadIdx.x - qe * ND : lane;
+      const bool qact = XM ? (qe < EPB && blk * EPB + qe < a.n_act) : true;
+      for (int w = w0; qact && w < ND; w += XM ? ND : T) {
         double uu[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) uu[v] = s_u[le][v][w];
+        for (int v = 0; v < NV; ++v) uu[v] = s_u[qe][v][w];
         NodeQ<DIM> q;
         cons_to_prim<DIM>(uu, gamma, q.rho, q.v, q.p);
         q.lrho = log_pos(q.rho);
         q.beta = q.rho * rcp(q.p);
         q.lbeta = log_pos(q.beta);
-        s_q[le][w] = q;
+        s_q[qe][w] = q;
       }
     }
     // (interpolations start on the wave after the node quantities)
@@ -694,7 +715,8 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   // ---- D: fluxes.  Pairs first, then face nodes sub-face-major (sub 0 of every face first).
   double alpha = 0.0;
   if (SC && act) alpha = s_alpha[le];
-  if (act) {
+  // (XM: a lane's flux item may belong to another element of the block; activity per item)
+  if (act || XM) {
     if constexpr (ALIAS) {
       // the central viscous face values of phase C (the sub-face traces they replace are dead:
       // their storage takes the pair fluxes now)
@@ -708,22 +730,23 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
     // pair fluxes (w in [0, NP)) and face fluxes (r in [0, NFI)); with the split on, each on
     // lanes of its own ([0, PLN) and [PLN, T)), else one loop over both
     constexpr int NFI = NSUB * NFC * NF;
-    auto pair_flux = [&](int w) {
+    // pair flux w and face flux r of element q of the block
+    auto pair_flux = [&](int q, int w) {
       const int pl = w % NPL;
       const int line = (w / NPL) % K::NLINE;
       const int d = w / (NPL * K::NLINE);
       const int pa = (PairNodes<N>::kFirst >> (4 * pl)) & 15, pb = (PairNodes<N>::kSecond >> (4 * pl)) & 15;
       double f[NV];
-      ec_flux<DIM>(s_q[le][node_on_line<DIM, N>(d, line, pa)], s_q[le][node_on_line<DIM, N>(d, line, pb)], d,
+      ec_flux<DIM>(s_q[q][node_on_line<DIM, N>(d, line, pa)], s_q[q][node_on_line<DIM, N>(d, line, pb)], d,
                    inv_gm1, f);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) s_pf[le][w * NV + v] = f[v];
+      for (int v = 0; v < NV; ++v) s_pf[q][w * NV + v] = f[v];
     };
-    auto face_flux = [&](int r) {
+    auto face_flux = [&](int q, int r) {
       const int j = r % NF;
       const int f = (r / NF) % NFC;
       const int sub = r / (NF * NFC);
-      const int32_t pk = s_fk[le][f];
+      const int32_t pk = s_fk[q][f];
       const int kind = face_kind(pk);
       if (sub > 0 && kind != kCoarseSide) return;
       const int d = f >> 1, side = f & 1;
@@ -732,8 +755,8 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         // own trace interpolated to sub-face `sub` (phase C)
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          mine[v] = s_tro[le][f][sub][v][j];
-          oth[v] = s_tr[le][f][sub][v][j];
+          mine[v] = s_tro[q][f][sub][v][j];
+          oth[v] = s_tr[q][f][sub][v][j];
         }
       } else if (kind == kCoarseSide) {
         // own trace interpolated to sub-face `sub` here: P_{m1} (x) P_{m0} on the face, one
@@ -742,14 +765,14 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         const int ja = j % N, jb = j / N;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          oth[v] = s_tr[le][f][sub][v][j];
+          oth[v] = s_tr[q][f][sub][v][j];
           double x = 0.0;
 #pragma unroll 1
           for (int kb = 0; kb < N; ++kb) {
             double row = 0.0;
 #pragma unroll
             for (int ka = 0; ka < N; ++ka)
-              row += Pm(m0, ja * N + ka) * s_u[le][v][face_node<DIM, N>(d, side, ka + N * kb)];
+              row += Pm(m0, ja * N + ka) * s_u[q][v][face_node<DIM, N>(d, side, ka + N * kb)];
             x += Pm(m1, jb * N + kb) * row;
           }
           mine[v] = x;
@@ -759,8 +782,8 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         const int ts = kind == kFineSide ? 1 : 0;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          mine[v] = s_u[le][v][on];
-          oth[v] = s_tr[le][f][ts][v][j];
+          mine[v] = s_u[q][v][on];
+          oth[v] = s_tr[q][f][ts][v][j];
         }
       }
       // one flux call with the states ordered along +e_d (two calls, one per side, would run
@@ -773,21 +796,21 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       }
       hll_flux<DIM>(uL, uR, d, gamma, fl);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) s_tr[le][f][sub][v][j] = fl[v];
+      for (int v = 0; v < NV; ++v) s_tr[q][f][sub][v][j] = fl[v];
       if (VISC && !ALIAS && kind != kCoarseSide) {
         // BR1 central viscous flux on this face node: 1/2 (own + neighbour); coarse sides
         // were averaged in phase C
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          const double ownv = fv_own(d, v, face_node<DIM, N>(d, side, j));
+          const double ownv = fv_own_q(q, d, v, face_node<DIM, N>(d, side, j));
           const int ts = kind == kFineSide ? 1 : 0;
-          s_trv[le][f][sub][v][j] = 0.5 * (ownv + s_trv[le][f][ts][v][j]);
+          s_trv[q][f][sub][v][j] = 0.5 * (ownv + s_trv[q][f][ts][v][j]);
         }
       }
     };
     if (EARLYF) {
       if (lane < K::PLN) {
-        for (int w = lane; w < NP; w += K::PLN) pair_flux(w);
+        for (int w = lane; w < NP; w += K::PLN) pair_flux(le, w);
       } else {
         // coarse sides: the sub-face fluxes projected back with R_m into s_tr (sub-face 0)
         for (int w = lane - K::PLN; w < NFC * NV * NF; w += T - K::PLN) {
@@ -801,20 +824,37 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
           s_tr[le][f][0][v][i] = fs;
         }
       }
+    } else if constexpr (XM) {
+      // pairs of element t / NP on lanes [0, EPB NP), sub-face-0 face items of element
+      // (t - EPB NP) / NF0 on the rest; the items of other sub-faces (coarse sides only) after
+      constexpr int NF0 = NFC * NF, NFX = NFI - NF0;
+      static_assert(EPB * (NP + NF0) == T * EPB, "cross-element flux mapping fills the block");
+      const int t = threadIdx.x;
+      if (t < EPB * NP) {
+        const int q = t / NP;
+        if (blk * EPB + q < a.n_act) pair_flux(q, t - q * NP);
+      } else {
+        const int r = t - EPB * NP, q = r / NF0;
+        if (blk * EPB + q < a.n_act) face_flux(q, r - q * NF0);
+      }
+      for (int x = t; x < EPB * NFX; x += T * EPB) {
+        const int q = x / NFX;
+        if (blk * EPB + q < a.n_act) face_flux(q, NF0 + x - q * NFX);
+      }
     } else if (K::PLN) {
       constexpr int NFL = T - K::PLN;   // face lanes
       if (lane < K::PLN) {
-        for (int w = lane; w < NP; w += K::PLN) pair_flux(w);
+        for (int w = lane; w < NP; w += K::PLN) pair_flux(le, w);
       } else if (lane - K::PLN < NFI) {
-        face_flux(lane - K::PLN);
+        face_flux(le, lane - K::PLN);
       }
       // face items beyond the face lanes exist only on the sub-faces of coarse sides; every lane
       // takes part (on other blocks each returns at once)
-      for (int r = NFL + lane; r < NFI; r += T) face_flux(r);
+      for (int r = NFL + lane; r < NFI; r += T) face_flux(le, r);
     } else {
       for (int w = lane; w < NP + NFI; w += T) {
-        if (w < NP) pair_flux(w);
-        else face_flux(w - NP);
+        if (w < NP) pair_flux(le, w);
+        else face_flux(le, w - NP);
       }
     }
     if constexpr (SC) {
@@ -992,7 +1032,7 @@ constexpr int stage_waves_per_simd() {
 }
 
 template <int DIM, int N, bool VISC, bool SPLIT, bool SC>
-__global__ __launch_bounds__((SK<DIM, N, SPLIT>::T * SK<DIM, N, SPLIT>::EPB),
+__global__ __launch_bounds__((SK<DIM, N, SPLIT>::T * SK<DIM, N, SPLIT>::epb(SC)),
                              (stage_waves_per_simd<DIM, N, VISC, SPLIT>())) void k_stage(StageArgs a, Mesh m, Ops op,
                                                                                        Physics ph) {
   // Workgroups go to the 8 XCDs round-robin (block b to XCD b mod 8); give XCD x the
@@ -1003,7 +1043,7 @@ __global__ __launch_bounds__((SK<DIM, N, SPLIT>::T * SK<DIM, N, SPLIT>::EPB),
   // does not keep a slot's data.)
   const int g8 = (int)gridDim.x >> 3;
   const int b = (int)blockIdx.x;
-  stage_block<DIM, N, VISC, SK<DIM, N, SPLIT>::EPB, SPLIT, SC>(a, m, op, ph, (b & 7) * g8 + (b >> 3));
+  stage_block<DIM, N, VISC, SK<DIM, N, SPLIT>::epb(SC), SPLIT, SC>(a, m, op, ph, (b & 7) * g8 + (b >> 3));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1300,27 +1340,33 @@ template <int DIM, int N, bool VISC, bool SPLIT, bool SC>
 hipError_t launch_stage_v(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1) {
   using K = SK<DIM, N, SPLIT>;
-  const int blocks = ((a.n_act + K::EPB - 1) / K::EPB + 7) & ~7;   // a multiple of the 8 XCDs
+  constexpr int EPB = K::epb(SC);
+  const int blocks = ((a.n_act + EPB - 1) / EPB + 7) & ~7;   // a multiple of the 8 XCDs
   if (ev0)
-    hipExtLaunchKernelGGL((k_stage<DIM, N, VISC, SPLIT, SC>), dim3(blocks), dim3(K::T * K::EPB), 0, s, ev0, ev1, 0,
+    hipExtLaunchKernelGGL((k_stage<DIM, N, VISC, SPLIT, SC>), dim3(blocks), dim3(K::T * EPB), 0, s, ev0, ev1, 0,
                           a, m, op, ph);
   else
-    hipLaunchKernelGGL((k_stage<DIM, N, VISC, SPLIT, SC>), dim3(blocks), dim3(K::T * K::EPB), 0, s, a, m, op, ph);
+    hipLaunchKernelGGL((k_stage<DIM, N, VISC, SPLIT, SC>), dim3(blocks), dim3(K::T * EPB), 0, s, a, m, op, ph);
   return hipGetLastError();
 }
 
 // 2D p=3 launches with few active elements are latency-bound: two waves per element (pair and
 // face fluxes side by side) finish sooner; with many elements the launch is throughput-bound
-// and one wave per element issues fewer instructions per element.  Measured on uniform meshes:
-// split faster up to 4096 elements (1024: 6.3 vs 7.2 us), single wave from 9216 on.
+// and the one-wave body issues fewer instructions per element.  Measured on uniform meshes:
+// without shock capturing (four elements per block, flux phase across the block) the split
+// body is faster up to 1024 elements (5.8 vs 6.5 us per launch) and on the adaptive KH
+// launches (~1400: 7.4 vs 7.8 us), the one-wave body from 2304 on (7.1 vs 7.9 us); with shock
+// capturing (one element per block) the split is faster up to 4096 elements.
 constexpr int kSplitMaxElements = STAGE_SPLIT_MAX;
+constexpr int kSplitMaxElementsSC = STAGE_SPLIT_MAX_SC;
 
 template <int DIM, int N, bool VISC, bool SC = false>
 hipError_t launch_stage_t(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1) {
   if (a.n_act <= 0) return hipSuccess;
   if constexpr (DIM == 2 && N == 4) {
-    if (a.n_act <= kSplitMaxElements) return launch_stage_v<DIM, N, VISC, true, SC>(a, m, op, ph, s, ev0, ev1);
+    if (a.n_act <= (SC ? kSplitMaxElementsSC : kSplitMaxElements))
+      return launch_stage_v<DIM, N, VISC, true, SC>(a, m, op, ph, s, ev0, ev1);
   }
   return launch_stage_v<DIM, N, VISC, false, SC>(a, m, op, ph, s, ev0, ev1);
 }
@@ -1352,7 +1398,8 @@ hipError_t launch_stage_batch(int N, int M, int grid, bool persistent, const Bat
 }
 
 int stage_body_id(int dim, int N, int n_act, bool sc) {
-  return ((dim == 2 && N == 4 && n_act > 0 && n_act <= kSplitMaxElements) ? 1 : 0) + (sc ? 2 : 0);
+  const int split_max = sc ? kSplitMaxElementsSC : kSplitMaxElements;
+  return ((dim == 2 && N == 4 && n_act > 0 && n_act <= split_max) ? 1 : 0) + (sc ? 2 : 0);
 }
 
 hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,

@@ -74,7 +74,7 @@ CASES = {
     "random_forest_p2": (lambda: pin.random_forest_2d(5, n_root=3, max_level=3), 3, lambda o: _random_state(o, 8)),
     "uniform_p3": (lambda: pin.uniform_mesh(2, (5, 3), (-5, -5), (5, 5), 0), 4, lambda o: _random_state(o, 9)),
     # above the element count where 2D p=3 launches switch from two waves per element to one
-    # (6144): 11092 elements with 2:1 mortars
+    # (2048; four elements per block): 11092 elements with 2:1 mortars
     "large_forest_p3": (lambda: pin.random_forest_2d(3, n_root=40, max_level=2, p_refine=0.5), 4,
                         lambda o: _random_state(o, 10)),
 }
@@ -152,10 +152,11 @@ def test_step_parity_three_members_random_forest():
 
 
 def test_step_parity_large_forest_both_launch_shapes():
-    # 11553 elements on three levels, three members: the stages with more than 6144 active
-    # elements take the one-wave body, the finest member's stages (4640 elements) the two-wave one
-    mesh = pin.random_forest_2d(3, n_root=48, max_level=2, p_refine=0.35)
-    assert len(mesh.leaves) > 6144 and np.bincount(mesh.leaves[:, 0])[-1] < 6144
+    # 3511 elements on three levels, three members: the stages with more than 2048 active
+    # elements take the one-wave body (four elements per block, the last block ragged), the
+    # finest member's stages (1248 elements) the two-wave one
+    mesh = pin.random_forest_2d(3, n_root=28, max_level=2, p_refine=0.3)
+    assert len(mesh.leaves) > 2048 and len(mesh.leaves) % 4 != 0 and np.bincount(mesh.leaves[:, 0])[-1] < 2048
     err, *_ = _stepping_case(2, [2, 4, 8], mesh, 4, lambda o: _random_state(o, 11), 0.002, 2)
     assert err <= TOL
 

@@ -46,7 +46,7 @@ CASES = {
     "2d_forest_p2": (lambda: pin.random_forest_2d(5, n_root=3, max_level=3), 3, lambda o: _random2d(o, 8), 2e-2),
     "3d_mortar_p3": (_mesh3d_small, 4, _tgv, 1.0 / 1600),
     "3d_mortar_p2": (_mesh3d_small, 3, _tgv, 1.0 / 1600),
-    # above 6144 elements: the one-wave 2D p=3 body with its viscous terms
+    # above 2048 elements: the one-wave 2D p=3 body (four elements per block) with its viscous terms
     "2d_large_forest_p3": (lambda: pin.random_forest_2d(3, n_root=40, max_level=2, p_refine=0.5), 4,
                            lambda o: _random2d(o, 9), 2e-2),
 }

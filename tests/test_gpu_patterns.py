@@ -127,8 +127,10 @@ def test_nonnested_family_p2_blocks_of_two_elements():
 
 def test_nonnested_family_large_forest_both_launch_shapes():
     fam = pc.pattern_family(NONNESTED, 8)
-    mesh = pin.random_forest_2d(3, n_root=48, max_level=2, p_refine=0.35)
-    assert len(mesh.leaves) > 6144
+    # 3511 elements, levels of 187, 2076 and 1248: stages above 2048 active elements on the
+    # one-wave body, the others on the two-wave one
+    mesh = pin.random_forest_2d(3, n_root=28, max_level=2, p_refine=0.3)
+    assert len(mesh.leaves) > 2048 and np.bincount(mesh.leaves[:, 0]).min() < 2048
     print(f"large forest, {len(mesh.leaves)} elements", flush=True)
     u_gpu, u_ora, sig, _, _ = _run(mesh, 4, fam, [0, 1, 2], _random2d(11), 0.002, 2)
     assert state_close(u_gpu, u_ora, sig, 2, 0.002), worst(u_gpu, u_ora, sig, 2, 0.002)

@@ -121,17 +121,18 @@ def test_rejected_coefficients_keep_the_context_stepping():
 
 
 def test_graph_replay_equals_eager_across_body_switch():
-    # 64x64 = 4096 elements (two-wave body of 2D p=3 stage launches), refined to more than 6144
-    # (one-wave body) and coarsened back: the captured step must be rebuilt, not updated in
-    # place, when a stage's kernel body changes; graph replay and eager launches stay bitwise equal
+    # 32x32 = 1024 elements (two-wave body of 2D p=3 stage launches), refined to more than 2048
+    # (one-wave body, four elements per block) and coarsened back: the captured step must be
+    # rebuilt, not updated in place, when a stage's kernel body changes; graph replay and eager
+    # launches stay bitwise equal
     from paper_2403_05144_amd import PerkSolver
     fam = pc.perk2_family([4, 8])
-    mesh0 = pin.uniform_mesh(2, (64, 64), (-1, -1), (1, 1), 0)
-    flags_up = np.zeros(4096, np.int8)
-    flags_up[:720] = 1                      # +3 elements each: 4096 + 2160 = 6256 > 6144
+    mesh0 = pin.uniform_mesh(2, (32, 32), (-1, -1), (1, 1), 0)
+    flags_up = np.zeros(1024, np.int8)
+    flags_up[:400] = 1                      # +3 elements each: 1024 + 1200 = 2224 > 2048
     runs = []
     for graphs in (True, False):
-        s = PerkSolver(pin.MeshDesc(2, (64, 64), (-1, -1), (1, 1), np.array(mesh0.leaves, copy=True)), 3, fam,
+        s = PerkSolver(pin.MeshDesc(2, (32, 32), (-1, -1), (1, 1), np.array(mesh0.leaves, copy=True)), 3, fam,
                        [1, 1], capacity=8192)
         s.set_graph_replay(graphs)
         s.set_state(kh_leaf(s.node_coords().cpu().numpy()))
@@ -139,11 +140,11 @@ def test_graph_replay_equals_eager_across_body_switch():
         s.step(1e-4, 3)
         rec.append(s.get_state().cpu().numpy())
         s.adapt(flags_up, 0, 1, [1, 1])
-        assert s.n_elements > 6144
+        assert s.n_elements > 2048
         s.step(1e-4, 3)
         rec.append(s.get_state().cpu().numpy())
         s.adapt(-np.ones(s.n_elements, np.int8), 0, 1, [1, 1])
-        assert s.n_elements == 4096
+        assert s.n_elements == 1024
         s.step(1e-4, 3)
         rec.append(s.get_state().cpu().numpy())
         runs.append(rec)

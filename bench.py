@@ -31,15 +31,20 @@ STAGE_KERNEL_SOURCES = ("perk_stage.hip", "perk_device.h", "perk_internal.h")
 
 
 def stage_kernel_digest():
-    import hashlib
+    """sha256 of the stage kernel's code (the kernel file, the device helpers, the data
+    structures of the internal header) with comments and blank lines left out, so that a
+    comment edit does not make recorded counter summaries stale."""
+    import hashlib, re
     h = hashlib.sha256()
     for name in STAGE_KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2403_05144_amd", "csrc", name), "rb") as f:
+        with open(os.path.join(ROOT, "paper_2403_05144_amd", "csrc", name), encoding="utf-8") as f:
             data = f.read()
         if name == "perk_internal.h":
-            cut = data.find(b"// Kernel launch wrappers")
+            cut = data.find("// Kernel launch wrappers")
             data = data[:cut] if cut >= 0 else data
-        h.update(data)
+        data = re.sub(r"/\*.*?\*/", "", data, flags=re.S)
+        data = re.sub(r"//[^\n]*", "", data)
+        h.update("\n".join(l.rstrip() for l in data.splitlines() if l.strip()).encode())
     return h.hexdigest()
 FP64_PEAK_TFLOPS = 78.6
 

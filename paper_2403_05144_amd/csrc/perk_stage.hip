@@ -1021,9 +1021,12 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
 // Waves per SIMD the register allocation must allow.  3D p=3 blocks (7 waves; 34 KB of LDS for
 // Euler, 38 KB for Navier-Stokes) at 72 VGPRs (7 waves per SIMD, no spill since the element
 // index is uniform) fit four blocks per CU; the step from three to four blocks took the
-// Taylor-Green launch from 90 to 72.5 us (and from two to three, 105 to 90).  The one-wave 2D p=3 body
-// (large launches) at 96 VGPRs (5 waves, a 20-byte spill) instead of 102-106: 2-6 % less on
-// uniform 2D meshes of 128^2-1024^2 elements (6 waves spilled 72-88 bytes and ran slower).
+// Taylor-Green launch from 90 to 72.5 us (and from two to three, 105 to 90).  The one-wave 2D p=3
+// bodies (large launches) are held to 5 waves per SIMD (at most 102 VGPRs): with one element per
+// wave and block that meant 96 VGPRs and a 20-byte spill instead of 102-106, 2-6 % less on uniform
+// meshes of 128^2-1024^2 elements (6 waves spilled 72-88 bytes and ran slower); the four-element
+// body stays below that by itself (62 VGPRs for Euler, 81 for Navier-Stokes), the one-element
+// body with shock capturing takes 94.
 template <int DIM, int N, bool VISC, bool SPLIT>
 constexpr int stage_waves_per_simd() {
   if (DIM == 3 && N == 4) return 7;

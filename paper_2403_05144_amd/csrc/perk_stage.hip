@@ -477,8 +477,9 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         }
       }
     } else {
-      // XM: the first wave (its own element active, so every active element of the block is
-      // one of the four) forms the nodes of all four, node w of element qe on lane qe ND + w
+      // XM: the block's first wave forms the nodes of all four elements, node w of element qe
+      // on lane qe ND + w (it gets here whenever any element of the block is active: the
+      // active elements of a block come first)
       const int qe = XM ? (int)threadIdx.x / ND : le;
       const int w0 = XM ? (int)threadIdx.x - qe * ND : lane;
       const bool qact = XM ? (qe < EPB && blk * EPB + qe < a.n_act) : true;

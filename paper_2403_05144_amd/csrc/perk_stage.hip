@@ -29,9 +29,6 @@
 #ifndef STAGE_SPLIT_MAX
 #define STAGE_SPLIT_MAX 2048
 #endif
-#ifndef STAGE_SPLIT_MAX_SC
-#define STAGE_SPLIT_MAX_SC 6144
-#endif
 
 namespace perk {
 namespace {
@@ -227,9 +224,9 @@ struct SK {
   // (0: one mixed loop over both)
   static constexpr int PLN = SPLIT ? T / 2 : (DIM == 3 && N == 4 ? 320 : 0);
   static constexpr int EPB = T >= 64 ? 1 : 64 / T;
-  // elements per block of the single-run kernel: the one-wave 2D p=3 body without shock
-  // capturing runs four (their flux phase mapped across the block, see stage_block)
-  static constexpr int epb(bool sc) { return DIM == 2 && N == 4 && !SPLIT && !sc ? 4 : EPB; }
+  // elements per block of the single-run kernel: the one-wave 2D p=3 body runs four (their
+  // flux phase mapped across the block, see stage_block)
+  static constexpr int epb() { return DIM == 2 && N == 4 && !SPLIT ? 4 : EPB; }
   static constexpr int NITEM = (NV * ND + T - 1) / T;         // (variable, node) items per lane
   // waves per SIMD the register allocation must allow.  A second 6-wave block fits on a CU
   // only when every SIMD can hold 4 waves (at most 128 VGPRs) and the LDS allows it (measured:
@@ -275,8 +272,10 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
   // on the VALU): the node quantities of all four on the first wave, and in the flux phase the
   // 4 x 48 pair fluxes on the first three waves and the 4 x 16 face fluxes on the fourth, so
   // that no wave issues both flux paths (one wave per element ran pairs and faces one after
-  // the other, divergent, in every element)
-  constexpr bool XM = DIM == 2 && N == 4 && T == 64 && EPB == 4 && !SPLIT && !SC;
+  // the other, divergent, in every element).  With shock capturing the blending factors of
+  // the four come from the second wave and their subcell fluxes (HLL, like the face fluxes)
+  // from the fourth.
+  constexpr bool XM = DIM == 2 && N == 4 && T == 64 && EPB == 4 && !SPLIT;
   constexpr int NPF = NP * NV, NTV1 = NFC * (NSUB - 1) * NV * NF;
   constexpr int NX = ALIAS && NTV1 > NPF ? NTV1 : NPF;
   __shared__ double s_pf[EPB][NX];   // pair flux w, variable v at [w NV + v]
@@ -672,42 +671,46 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
         }
       }
     }
-    if constexpr (SC) {
-      // blending factor of subcell shock capturing: the density's coefficients in the
-      // orthonormal Legendre basis, one per lane of [16, 16 + ND) (idle in this phase), the
-      // energies of all modes, of those of degree <= p - 1 and <= p - 2 in each direction summed
-      // over those 16 lanes, E = max((all - clip_1)/all, (clip_1 - clip_2)/clip_1), and the sigmoid
-      if (lane >= 16 && lane < 32) {
-        const int t = lane - 16;
-        double tot = 0.0, c1 = 0.0, c2 = 0.0;
-        if (t < ND) {
-          const int ia = t % N, ib = t / N;
-          double mo = 0.0;
+  }
+  if constexpr (SC) {
+    // blending factor of subcell shock capturing: the density's coefficients in the
+    // orthonormal Legendre basis, one per lane of a 16-lane group (lanes [16, 32) of the
+    // element's wave, idle in this phase; XM: the second wave, a group per element), the
+    // energies of all modes, of those of degree <= p - 1 and <= p - 2 in each direction summed
+    // over the group, E = max((all - clip_1)/all, (clip_1 - clip_2)/clip_1), and the sigmoid
+    const int tq = XM ? (int)threadIdx.x - T : lane - 16;
+    const int qa = XM ? (tq >= 0 ? tq / 16 : EPB) : le;
+    const bool on = XM ? (tq >= 0 && qa < EPB && blk * EPB + qa < a.n_act) : (act && lane >= 16 && lane < 32);
+    if (on) {
+      const int t = XM ? tq - qa * 16 : tq;
+      double tot = 0.0, c1 = 0.0, c2 = 0.0;
+      if (t < ND) {
+        const int ia = t % N, ib = t / N;
+        double mo = 0.0;
 #pragma unroll
-          for (int j = 0; j < N; ++j) {
-            double row = 0.0;
+        for (int j = 0; j < N; ++j) {
+          double row = 0.0;
 #pragma unroll
-            for (int i = 0; i < N; ++i) row += s_vinv[ia * N + i] * s_u[le][0][i + N * j];
-            mo += s_vinv[ib * N + j] * row;
-          }
-          const int deg = ia > ib ? ia : ib;
-          tot = mo * mo;
-          c1 = deg <= N - 2 ? tot : 0.0;
-          c2 = deg <= N - 3 ? tot : 0.0;
+          for (int i = 0; i < N; ++i) row += s_vinv[ia * N + i] * s_u[qa][0][i + N * j];
+          mo += s_vinv[ib * N + j] * row;
         }
+        const int deg = ia > ib ? ia : ib;
+        tot = mo * mo;
+        c1 = deg <= N - 2 ? tot : 0.0;
+        c2 = deg <= N - 3 ? tot : 0.0;
+      }
 #pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-          tot += __shfl_xor(tot, o, 16);
-          c1 += __shfl_xor(c1, o, 16);
-          c2 += __shfl_xor(c2, o, 16);
-        }
-        if (t == 0) {
-          const double e1 = tot > 0.0 ? (tot - c1) / tot : 0.0;
-          const double e2 = c1 > 0.0 ? (c1 - c2) / c1 : 0.0;
-          const double E = e1 < e2 ? e2 : e1;
-          const double al = 1.0 / (1.0 + exp(-a.sc_slope * (E - a.sc_T)));
-          s_alpha[le] = al < a.sc_amin ? 0.0 : (al < a.sc_amax ? al : a.sc_amax);
-        }
+      for (int o = 8; o > 0; o >>= 1) {
+        tot += __shfl_xor(tot, o, 16);
+        c1 += __shfl_xor(c1, o, 16);
+        c2 += __shfl_xor(c2, o, 16);
+      }
+      if (t == 0) {
+        const double e1 = tot > 0.0 ? (tot - c1) / tot : 0.0;
+        const double e2 = c1 > 0.0 ? (c1 - c2) / c1 : 0.0;
+        const double E = e1 < e2 ? e2 : e1;
+        const double al = 1.0 / (1.0 + exp(-a.sc_slope * (E - a.sc_T)));
+        s_alpha[qa] = al < a.sc_amin ? 0.0 : (al < a.sc_amax ? al : a.sc_amax);
       }
     }
   }
@@ -859,23 +862,32 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
       }
     }
     if constexpr (SC) {
-      if (alpha > 0.0) {
-        // HLL fluxes between neighbouring nodes of every coordinate line, on the lanes with the
-        // fewest flux items above (split body: after the face lanes; else after the last item)
-        constexpr int FVB = K::PLN ? K::PLN + NFI : (NP + NFI) % T;
-        for (int w = (lane + T - FVB) % T; w < NFVI; w += T) {
-          const int k = w % (N - 1), line = (w / (N - 1)) % K::NLINE, d = w / ((N - 1) * K::NLINE);
-          const int nl = node_on_line<DIM, N>(d, line, k), nr = node_on_line<DIM, N>(d, line, k + 1);
-          double uL[NV], uR[NV], fl[NV];
+      // HLL fluxes between neighbouring nodes of every coordinate line (subcell faces) of
+      // elements with alpha > 0: on the lanes with the fewest flux items above (split body:
+      // after the face lanes; one element per wave: after the last item; XM: the face wave,
+      // after the face fluxes, whose code path they share)
+      auto subcell_flux = [&](int q, int w) {
+        const int k = w % (N - 1), line = (w / (N - 1)) % K::NLINE, d = w / ((N - 1) * K::NLINE);
+        const int nl = node_on_line<DIM, N>(d, line, k), nr = node_on_line<DIM, N>(d, line, k + 1);
+        double uL[NV], uR[NV], fl[NV];
 #pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            uL[v] = s_u[le][v][nl];
-            uR[v] = s_u[le][v][nr];
-          }
-          hll_flux<DIM>(uL, uR, d, gamma, fl);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) s_fvs[le][w][v] = fl[v];
+        for (int v = 0; v < NV; ++v) {
+          uL[v] = s_u[q][v][nl];
+          uR[v] = s_u[q][v][nr];
         }
+        hll_flux<DIM>(uL, uR, d, gamma, fl);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s_fvs[q][w][v] = fl[v];
+      };
+      if constexpr (XM) {
+        constexpr int NFW = NFC * NF * EPB;   // lanes of the face wave
+        for (int x = (int)threadIdx.x - EPB * NP; x >= 0 && x < EPB * NFVI; x += NFW) {
+          const int q = x / NFVI;
+          if (blk * EPB + q < a.n_act && s_alpha[q] > 0.0) subcell_flux(q, x - q * NFVI);
+        }
+      } else if (alpha > 0.0) {
+        constexpr int FVB = K::PLN ? K::PLN + NFI : (NP + NFI) % T;
+        for (int w = (lane + T - FVB) % T; w < NFVI; w += T) subcell_flux(le, w);
       }
     }
   }
@@ -1036,7 +1048,7 @@ constexpr int stage_waves_per_simd() {
 }
 
 template <int DIM, int N, bool VISC, bool SPLIT, bool SC>
-__global__ __launch_bounds__((SK<DIM, N, SPLIT>::T * SK<DIM, N, SPLIT>::epb(SC)),
+__global__ __launch_bounds__((SK<DIM, N, SPLIT>::T * SK<DIM, N, SPLIT>::epb()),
                              (stage_waves_per_simd<DIM, N, VISC, SPLIT>())) void k_stage(StageArgs a, Mesh m, Ops op,
                                                                                        Physics ph) {
   // Workgroups go to the 8 XCDs round-robin (block b to XCD b mod 8); give XCD x the
@@ -1047,7 +1059,7 @@ __global__ __launch_bounds__((SK<DIM, N, SPLIT>::T * SK<DIM, N, SPLIT>::epb(SC))
   // does not keep a slot's data.)
   const int g8 = (int)gridDim.x >> 3;
   const int b = (int)blockIdx.x;
-  stage_block<DIM, N, VISC, SK<DIM, N, SPLIT>::epb(SC), SPLIT, SC>(a, m, op, ph, (b & 7) * g8 + (b >> 3));
+  stage_block<DIM, N, VISC, SK<DIM, N, SPLIT>::epb(), SPLIT, SC>(a, m, op, ph, (b & 7) * g8 + (b >> 3));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1344,7 +1356,7 @@ template <int DIM, int N, bool VISC, bool SPLIT, bool SC>
 hipError_t launch_stage_v(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1) {
   using K = SK<DIM, N, SPLIT>;
-  constexpr int EPB = K::epb(SC);
+  constexpr int EPB = K::epb();
   const int blocks = ((a.n_act + EPB - 1) / EPB + 7) & ~7;   // a multiple of the 8 XCDs
   if (ev0)
     hipExtLaunchKernelGGL((k_stage<DIM, N, VISC, SPLIT, SC>), dim3(blocks), dim3(K::T * EPB), 0, s, ev0, ev1, 0,
@@ -1356,20 +1368,19 @@ hipError_t launch_stage_v(const StageArgs& a, const Mesh& m, const Ops& op, cons
 
 // 2D p=3 launches with few active elements are latency-bound: two waves per element (pair and
 // face fluxes side by side) finish sooner; with many elements the launch is throughput-bound
-// and the one-wave body issues fewer instructions per element.  Measured on uniform meshes:
-// without shock capturing (four elements per block, flux phase across the block) the split
-// body is faster up to 1024 elements (5.8 vs 6.5 us per launch) and on the adaptive KH
-// launches (~1400: 7.4 vs 7.8 us), the one-wave body from 2304 on (7.1 vs 7.9 us); with shock
-// capturing (one element per block) the split is faster up to 4096 elements.
+// and the one-wave body (four elements per block, flux phase across the block) issues fewer
+// instructions per element.  Measured on uniform meshes: the split body is faster up to 1024
+// elements (5.8 vs 6.5 us per launch) and on the adaptive KH launches (~1400: 7.4 vs 7.8 us),
+// the one-wave body from 2304 on (7.1 vs 7.9 us); with shock capturing (the paper's KH state)
+// likewise, 1024: 7.8 vs 8.4 us, 2304: 8.6 vs 7.7 us, 4096: 12.0 vs 8.8 us.
 constexpr int kSplitMaxElements = STAGE_SPLIT_MAX;
-constexpr int kSplitMaxElementsSC = STAGE_SPLIT_MAX_SC;
 
 template <int DIM, int N, bool VISC, bool SC = false>
 hipError_t launch_stage_t(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1) {
   if (a.n_act <= 0) return hipSuccess;
   if constexpr (DIM == 2 && N == 4) {
-    if (a.n_act <= (SC ? kSplitMaxElementsSC : kSplitMaxElements))
+    if (a.n_act <= kSplitMaxElements)
       return launch_stage_v<DIM, N, VISC, true, SC>(a, m, op, ph, s, ev0, ev1);
   }
   return launch_stage_v<DIM, N, VISC, false, SC>(a, m, op, ph, s, ev0, ev1);
@@ -1402,8 +1413,7 @@ hipError_t launch_stage_batch(int N, int M, int grid, bool persistent, const Bat
 }
 
 int stage_body_id(int dim, int N, int n_act, bool sc) {
-  const int split_max = sc ? kSplitMaxElementsSC : kSplitMaxElements;
-  return ((dim == 2 && N == 4 && n_act > 0 && n_act <= split_max) ? 1 : 0) + (sc ? 2 : 0);
+  return ((dim == 2 && N == 4 && n_act > 0 && n_act <= kSplitMaxElements) ? 1 : 0) + (sc ? 2 : 0);
 }
 
 hipError_t launch_stage(int dim, int N, bool viscous, const StageArgs& a, const Mesh& m, const Ops& op,

@@ -73,7 +73,9 @@ CASES = {
     "kh_16x16_p3": (lambda: pin.uniform_mesh(2, (16, 16), (-1, -1), (1, 1), 0), 4, 1),
     "kh_forest_p3": (lambda: pin.random_forest_2d(4, n_root=8, max_level=2), 4, 1),
     "kh_forest_p2": (lambda: pin.random_forest_2d(6, n_root=8, max_level=2), 3, 1),
-    # above 6144 elements: the one-wave 2D p=3 body (layers compressed 8 times to stay sharp)
+    # above 2048 elements: the one-wave 2D p=3 body, four elements per block (layers compressed
+    # 8 times to stay sharp); 3511 elements leave the last block ragged
+    "kh_mid_forest_p3": (lambda: pin.random_forest_2d(3, n_root=28, max_level=2, p_refine=0.3), 4, 8),
     "kh_large_forest_p3": (lambda: pin.random_forest_2d(3, n_root=48, max_level=2, p_refine=0.35), 4, 8),
 }
 

@@ -1561,6 +1561,9 @@ def main():
         line = run_sweep(args)
     else:
         line = run(args)
+    if "library" not in line:
+        lib_path, lib_sha = _lib_fingerprint()
+        line["library"] = {"path": os.path.relpath(lib_path, ROOT), "sha256": lib_sha}
     print(json.dumps(line), flush=True)
 
 

@@ -1038,8 +1038,8 @@ __device__ __forceinline__ void stage_block(const StageArgs& a, const Mesh& m, c
 // bodies (large launches) are held to 5 waves per SIMD (at most 102 VGPRs): with one element per
 // wave and block that meant 96 VGPRs and a 20-byte spill instead of 102-106, 2-6 % less on uniform
 // meshes of 128^2-1024^2 elements (6 waves spilled 72-88 bytes and ran slower); the four-element
-// body stays below that by itself (62 VGPRs for Euler, 81 for Navier-Stokes), the one-element
-// body with shock capturing takes 94.
+// body stays below that by itself (62 VGPRs for Euler, 65 with shock capturing, 81 for
+// Navier-Stokes).
 template <int DIM, int N, bool VISC, bool SPLIT>
 constexpr int stage_waves_per_simd() {
   if (DIM == 3 && N == 4) return 7;

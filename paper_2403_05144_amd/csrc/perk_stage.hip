@@ -1146,7 +1146,13 @@ __global__ __launch_bounds__((GKc<DIM, N>::T), (GKc<DIM, N>::WPS)) void k_grad(S
   // D, P_0, P_1, R_0, R_1 from the device copy (lane-indexed reads from kernel-argument memory
   // would each be a slow memory round)
   __shared__ double s_op[5][N * N];
-  const int b = blockIdx.x;
+  // XCD-aware as the stage kernel: XCD x takes the contiguous range [x G, (x+1) G) of the
+  // elements (G = gridDim / 8; the grid is padded to a multiple of the 8 XCDs), so that the
+  // neighbours whose traces a block reads are mostly on its own XCD's L2 (Taylor-Green: 34.3 ->
+  // 33.5 us per launch against block b on element b)
+  const int g8 = (int)gridDim.x >> 3;
+  const int b = ((int)blockIdx.x & 7) * g8 + ((int)blockIdx.x >> 3);
+  if (b >= a.n_act + a.n_halo) return;
   const int e = b < a.n_act ? active_slot(a, b) : a.halo[b - a.n_act];
   const int lane = threadIdx.x;
   const int ld = m.ld;
@@ -1343,8 +1349,9 @@ __global__ __launch_bounds__((GKc<DIM, N>::T), (GKc<DIM, N>::WPS)) void k_grad(S
 template <int DIM, int N>
 hipError_t launch_grad_t(const StageArgs& a, const Mesh& m, const Ops& op, const Physics& ph, hipStream_t s,
                          hipEvent_t ev0, hipEvent_t ev1) {
-  const int blocks = a.n_act + a.n_halo;
-  if (blocks <= 0) return hipSuccess;
+  const int nb = a.n_act + a.n_halo;
+  if (nb <= 0) return hipSuccess;
+  const int blocks = (nb + 7) & ~7;   // a multiple of the 8 XCDs
   if (ev0)
     hipExtLaunchKernelGGL((k_grad<DIM, N>), dim3(blocks), dim3(GKc<DIM, N>::T), 0, s, ev0, ev1, 0, a, m, op, ph);
   else

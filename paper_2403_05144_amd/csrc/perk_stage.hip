@@ -1085,13 +1085,21 @@ __device__ __forceinline__ void batch_tile(const BatchRun* __restrict__ runs, co
   stage_block<2, N, false, EPB>(a, r.m, r.op, r.ph, t - tile_off[k]);
 }
 
-// one block per tile, no loop: the register allocation of the single-run kernel
+// one block per tile (the grid padded to a multiple of 8), no loop: the register allocation of the
+// single-run kernel
 template <int N, int EPB>
 __global__ __launch_bounds__((SK<2, N>::T * EPB)) void k_stage_batch_flat(const BatchRun* __restrict__ runs,
                                                                           const StageArgs* __restrict__ sargs,
                                                                           const int32_t* __restrict__ tile_off,
                                                                           int k0, int k1, int64_t tick) {
-  batch_tile<N, EPB>(runs, sargs, tile_off, k0, k1, tick, tile_off[k0] + (int)blockIdx.x);
+  // XCD-aware as the single-run kernel: XCD x takes the contiguous tile range [x G, (x+1) G)
+  // (G = gridDim / 8, the grid padded to a multiple of the 8 XCDs), so that the neighbouring
+  // tiles of a run share an L2 (64 runs of the C4 batch: 108.8 -> 106.1 us per tick)
+  const int n_tiles = tile_off[k1] - tile_off[k0];
+  const int g8 = (int)gridDim.x >> 3;
+  const int bb = ((int)blockIdx.x & 7) * g8 + ((int)blockIdx.x >> 3);
+  if (bb >= n_tiles) return;
+  batch_tile<N, EPB>(runs, sargs, tile_off, k0, k1, tick, tile_off[k0] + bb);
 }
 
 // persistent: a fixed grid loops over the tiles (values hoisted out of the loop raise the
@@ -1402,7 +1410,8 @@ hipError_t launch_batch_t(bool persistent, int grid, const BatchRun* runs, const
   if (persistent)
     hipLaunchKernelGGL((k_stage_batch<N, EPB>), dim3(grid), b, 0, s, runs, sargs, tile_off, k0, k1, tick);
   else
-    hipLaunchKernelGGL((k_stage_batch_flat<N, EPB>), dim3(grid), b, 0, s, runs, sargs, tile_off, k0, k1, tick);
+    hipLaunchKernelGGL((k_stage_batch_flat<N, EPB>), dim3((grid + 7) & ~7), b, 0, s, runs, sargs, tile_off, k0, k1,
+                       tick);
   return hipGetLastError();
 }
 
